@@ -1,0 +1,199 @@
+/*
+ * kur.h -- C ABI of the MI355X (gfx950) library for the Kuramoto model on graphs.
+ *
+ * Problem (Boehle, Kuehn, Thalhammer, arXiv 2102.07167, Sec. 3, eq. KuramotoGraph):
+ *     theta_m'(t) = omega_m + K / Mscale_m * sum_l A_ml sin(theta_l(t) - theta_m(t)),  A_ml in {0,1}
+ * with uniform scaling Mscale_m = N (default) or non-uniform scaling Mscale_m = sum_l A_ml
+ * (option "scaling" = 1; a zero row then gives theta_m' = omega_m). Row m receives from column l.
+ *
+ * Method (Sec. 3, eq. KuramotoGraphApproach and the remark after it): after the nodes are
+ * regrouped so that every community is contiguous (Sec. 3, community detection: the
+ * permutation P A P^T), every diagonal block is evaluated either
+ *   - "dense": with the localised order parameters S_b = sum_{l in b} sin theta_l and
+ *     C_b = sum_{l in b} cos theta_l, minus the few entries with A_ml = 0 (list of zeros), or
+ *   - "sparse": by straightforward summation over the entries with A_ml = 1 (list of ones),
+ * and all edges between communities by straightforward summation over a CSR list. The sine of a
+ * difference is expanded by the addition theorem (Sec. 2, eq. KuramotoReformulation), so every
+ * list entry costs one gather of (sin theta_l, cos theta_l).
+ * Time integration: classical fourth-order Runge-Kutta with a fixed step. Order parameter:
+ * r e^{i psi} = (1/N) sum_m e^{i theta_m} (Sec. 2, eq. OrderParameter).
+ *
+ * Conventions
+ *   - Every call returns kur_status; nothing throws or aborts across the ABI. On failure,
+ *     kur_last_error(ctx) describes the problem (valid until the next call on ctx).
+ *   - Host arrays passed in are borrowed for the duration of the call and copied; the library
+ *     owns every device buffer it allocates. Host arrays are double precision for both
+ *     dtypes; a KUR_F32 context rounds them to float on upload.
+ *   - Arrays in "user order" are indexed by the caller's node numbering; the library keeps its
+ *     own block order internally and applies the permutation on the way in and out.
+ *   - Argument validation (shapes, ranges, finiteness, graph consistency) happens on the host
+ *     before any device work, and a rejected call leaves the context unchanged.
+ *   - A context drives one device and one stream; it is not thread safe.
+ *   - *_dev variants take device pointers, enqueue on the context stream and do not
+ *     synchronise; the pointers must stay valid until that stream work completes.
+ */
+#ifndef KUR_H
+#define KUR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kur_ctx kur_ctx;
+
+typedef enum {
+    KUR_OK = 0,
+    KUR_EINVAL = 1,     /* invalid argument; nothing was changed */
+    KUR_ENOMEM = 2,     /* host or device allocation failed */
+    KUR_EDEVICE = 3,    /* HIP runtime error, or no device (host-only context) */
+    KUR_ESTATE = 4,     /* call out of order (e.g. stepping before a graph was set) */
+    KUR_ENONFINITE = 5  /* a non-finite phase was detected */
+} kur_status;
+
+typedef enum { KUR_F32 = 1, KUR_F64 = 2 } kur_dtype;
+
+/* Library version as 10000*major + 100*minor + patch. */
+int kur_version(void);
+
+/*
+ * Create a context computing in dtype on HIP device `device`. hip_stream is a hipStream_t to
+ * enqueue on (NULL: the context creates its own stream at default priority).
+ * device = -1 creates a host-only context: graph preprocessing and validation work, every
+ * call that needs the GPU returns KUR_EDEVICE.
+ */
+kur_status kur_create(kur_ctx **out, kur_dtype dtype, int device, void *hip_stream);
+
+/* Release every resource of ctx (NULL is accepted). Waits for the context stream. */
+void kur_destroy(kur_ctx *ctx);
+
+/* Human-readable description of the last failure on ctx ("" if none; ctx may be NULL). */
+const char *kur_last_error(const kur_ctx *ctx);
+
+/*
+ * Set a tuning or model option; takes effect at the next kur_set_graph* call unless noted.
+ *   "tau"         density threshold: a diagonal block whose realised density is >= tau is
+ *                 evaluated with localised order parameters (list of zeros), otherwise with its
+ *                 list of ones. Default 0.5 (Sec. 3: precompute when ones outnumber zeros).
+ *   "chunk"       columns of a diagonal block staged in LDS at a time (64..32768, multiple of
+ *                 64). Default 8192 (FP32), 4096 (FP64).
+ *   "tile_rows"   maximal rows per work tile (64..4096). Default 1024 (FP32), 512 (FP64).
+ *   "tiles"       target number of work tiles (>= 1). Default 4096.
+ *   "scaling"     0: K/N (uniform, default); 1: K/deg_m (non-uniform). Immediate.
+ *   "compensate"  1: compensated phase update with winding (default); 0: plain update. Immediate.
+ *   "timing"      1: time every launch of the row kernel with HIP events (see kur_kernel_time).
+ *                 Immediate.
+ * Unknown keys and out-of-range values return KUR_EINVAL.
+ */
+kur_status kur_set_option(kur_ctx *ctx, const char *key, double value);
+
+/*
+ * Set the graph from a CSR adjacency in user order plus a community label per node; the
+ * library does the host preprocessing: a stable counting sort of the nodes by label (the
+ * permutation to block structure), the per-block dense/sparse choice at "tau", the list
+ * build and the work decomposition.
+ *   n           number of oscillators (1 <= n < 2^31)
+ *   row_ptr     n+1 offsets, row_ptr[0] = 0, non-decreasing
+ *   col         row_ptr[n] column indices in [0, n); row m lists the l with A_ml = 1, in any
+ *               order, without duplicates. Diagonal entries are ignored (sin 0 = 0).
+ *   labels      n community labels >= 0 (any values; communities are ordered by label)
+ * The adjacency may be asymmetric.
+ */
+kur_status kur_set_graph_csr(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                             const int32_t *labels);
+
+/*
+ * Set the graph already in block form (the expert path; no community search is done).
+ *   n, nb        nodes and diagonal blocks; block b owns block-order rows
+ *                [block_ptr[b], block_ptr[b+1]), block sizes 1..65535
+ *   block_ptr    nb+1 offsets, block_ptr[0] = 0, strictly increasing, block_ptr[nb] = n
+ *   mode         nb flags: 1 = the block list holds the ZERO entries (l != m) of the block,
+ *                0 = it holds the ONE entries
+ *   list_ptr     n+1 offsets into list_col (block order)
+ *   list_col     block-local column indices (0 <= c < block size, c != row's own local index),
+ *                no duplicates
+ *   inter_ptr    n+1 offsets into inter_col (block order)
+ *   inter_col    block-order column indices outside the row's own block, no duplicates
+ *   perm         n entries: perm[u] = block-order index of user node u (NULL = identity);
+ *                must be a permutation
+ */
+kur_status kur_set_graph(kur_ctx *ctx, int64_t n, int32_t nb, const int64_t *block_ptr,
+                         const uint8_t *mode, const int64_t *list_ptr, const uint16_t *list_col,
+                         const int64_t *inter_ptr, const int32_t *inter_col, const int32_t *perm);
+
+/* Graph statistics after kur_set_graph*: out[0..7] = n, nb, dense blocks, list entries
+ * (unpadded), list entries (padded, as stored), inter entries, tiles, chunk width. */
+kur_status kur_graph_info(const kur_ctx *ctx, int64_t out[8]);
+
+/* Permutation in use: perm[u] = block-order index of user node u (n entries). */
+kur_status kur_get_perm(const kur_ctx *ctx, int32_t *perm);
+
+/*
+ * Introspection of the host preprocessing, for host-only contexts (device = -1), which keep
+ * the built layout in host memory. kur_get_blocks: block_ptr (nb+1) and mode (nb; 1 = list of
+ * zeros). kur_get_row_lists: for block-order row `row`, the block-local columns stored in its
+ * list (ascending; zeros for a dense block, ones for a sparse one) and its inter-block columns
+ * (block order, ascending). Pass NULL arrays to query the counts; otherwise the arrays must
+ * hold *nlist and *ninter entries (the counts are written back). Device contexts return
+ * KUR_ESTATE.
+ */
+kur_status kur_get_blocks(const kur_ctx *ctx, int64_t *block_ptr, uint8_t *mode);
+kur_status kur_get_row_lists(const kur_ctx *ctx, int64_t row, int32_t *list, int64_t *nlist, int32_t *inter,
+                             int64_t *ninter);
+
+/* Intrinsic frequencies omega (n, user order, finite) and coupling constant K (finite). */
+kur_status kur_set_params(kur_ctx *ctx, const double *omega, double K);
+
+/* Phases theta (n, user order, finite, any real value; stored wrapped plus a winding count). */
+kur_status kur_set_phases(kur_ctx *ctx, const double *theta);
+
+/*
+ * Evaluate the right-hand side F(theta) (n, user order) at theta (n, user order; NULL = the
+ * current phases). Synchronous.
+ */
+kur_status kur_eval_rhs(kur_ctx *ctx, const double *theta, double *dtheta);
+
+/*
+ * Advance the current phases by nsteps classical RK4 steps of size dt (finite, nonzero).
+ * If r_every > 0 the order parameter is sampled at steps 0, r_every, 2 r_every, ...,
+ * floor(nsteps/r_every) r_every, i.e. nsteps/r_every + 1 values, written to r_out and psi_out
+ * (either may be NULL). With r_out == psi_out == NULL the call only enqueues work.
+ * Returns KUR_ENONFINITE if a sampled order parameter is not finite.
+ */
+kur_status kur_step_rk4(kur_ctx *ctx, double dt, int64_t nsteps, int64_t r_every, double *r_out,
+                        double *psi_out);
+
+/* Current phases (n, user order): wrapped != 0 gives values in [-pi, pi), wrapped == 0 the
+ * unwrapped phases (wrapped value plus 2 pi times the winding count). Synchronous. */
+kur_status kur_get_phases(kur_ctx *ctx, double *theta, int wrapped);
+
+/* Order parameter r and angle psi of the current phases. Synchronous. */
+kur_status kur_order_parameter(kur_ctx *ctx, double *r, double *psi);
+
+/*
+ * Save / restore the phase state (wrapped phases, compensation terms and winding counts, block
+ * order) so that a run can be resumed bit for bit. With blob == NULL, *bytes receives the size.
+ */
+kur_status kur_get_state(kur_ctx *ctx, void *blob, size_t *bytes);
+kur_status kur_set_state(kur_ctx *ctx, const void *blob, size_t bytes);
+
+/* Wait for all work enqueued on the context stream. */
+kur_status kur_sync(kur_ctx *ctx);
+
+/*
+ * Row-kernel timing (option "timing" = 1): number of timed launches and their total duration
+ * in milliseconds since the option was last enabled. Synchronises the stream.
+ */
+kur_status kur_kernel_time(kur_ctx *ctx, int64_t *launches, double *total_ms);
+
+/* Device-pointer variants. Arrays are in BLOCK order and of the context dtype
+ * (float or double); they enqueue on the context stream. */
+kur_status kur_eval_rhs_dev(kur_ctx *ctx, const void *theta_dev, void *dtheta_dev);
+kur_status kur_get_phases_dev(kur_ctx *ctx, void *theta_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KUR_H */

@@ -1,0 +1,471 @@
+// graph_build.cpp -- host preprocessing of the graph (untimed set-up work).
+//
+// 1. Regroup the nodes so that every community is contiguous: a stable counting sort by label,
+//    i.e. the permutation P with A~ = P A P^T of the paper (Sec. 3, community detection), done
+//    here on given (planted) labels.
+// 2. For every diagonal block choose the evaluation: localised order parameters with the list
+//    of zero entries when the realised density is at least tau, straightforward summation over
+//    the list of one entries otherwise (Sec. 3, eq. KuramotoGraphApproach and the density rule
+//    of the introduction).
+// 3. Store the lists as 16-bit column offsets relative to a chunk of W columns, chunk-major
+//    inside a block, every (row, chunk) segment padded to a multiple of 8 entries with the
+//    index W (an all-zero slot), so that a kernel reads them with aligned 16-byte loads while
+//    the chunk's (sin, cos) values sit in LDS.
+// 4. All edges between blocks go to a CSR list with block-order columns.
+// 5. Cut every block into work tiles of similar cost and choose the lanes per row.
+#include <algorithm>
+#include <atomic>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <thread>
+
+#include "kur_internal.hpp"
+
+namespace kur {
+
+static int host_threads()
+{
+    const char *e = std::getenv("KUR_THREADS");
+    if (!e) e = std::getenv("OMP_NUM_THREADS");
+    int t = e ? std::atoi(e) : 0;
+    if (t <= 0) t = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
+    return std::max(1, std::min(t, 256));
+}
+
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &f)
+{
+    if (n <= 0) return;
+    int nt = host_threads();
+    int64_t per = std::max<int64_t>(1, (n + nt * 8 - 1) / (nt * 8));  // 8 ranges per thread
+    std::atomic<int64_t> next{0};
+    auto work = [&]() {
+        for (;;) {
+            int64_t b = next.fetch_add(per);
+            if (b >= n) break;
+            f(b, std::min(n, b + per));
+        }
+    };
+    if (nt == 1 || n <= per) { work(); return; }
+    std::vector<std::thread> th;
+    for (int i = 0; i < nt; ++i) th.emplace_back(work);
+    for (auto &t : th) t.join();
+}
+
+namespace {
+
+struct ErrFlag {
+    std::atomic<bool> bad{false};
+    std::mutex mu;
+    std::string msg;
+    void set(const std::string &m)
+    {
+        std::lock_guard<std::mutex> g(mu);
+        if (!bad.load()) { msg = m; bad.store(true); }
+    }
+};
+
+inline int64_t round8(int64_t x) { return (x + 7) & ~int64_t(7); }
+
+// Common second half: given the block layout and, for every block-order row, a way to mark
+// the row's "listed" block-local columns in a bitmap (for a dense block the ones, which are
+// complemented on output; for a sparse block the ones themselves) plus the row's inter
+// columns, produce segments, the inter CSR and the tiles.
+struct RowSource {
+    // mark(m, bits, s): set bit lc for every one entry of row m inside its block (local col);
+    // returns the count; must report duplicates through err.
+    std::function<int64_t(int64_t, uint64_t *, ErrFlag &)> mark_ones;
+    // clear(m, bits): clear what mark_ones set
+    std::function<void(int64_t, uint64_t *)> clear;
+    // inter(m, out): append block-order inter columns of row m
+    std::function<void(int64_t, std::vector<int32_t> &)> inter;
+    // number of inter columns of row m
+    std::function<int64_t(int64_t)> inter_count;
+};
+
+std::string finish(BlockGraph &g, const std::vector<int32_t> &block_of_row, const RowSource &src,
+                   const std::vector<uint8_t> *given_mode, const BuildOptions &opt)
+{
+    const int64_t n = g.n;
+    const int32_t W = opt.W;
+    g.W = W;
+    g.tile_rows = opt.tile_rows;
+    int32_t smax = 0;
+    for (auto &b : g.blk) smax = std::max(smax, b.size);
+    const int64_t words = (smax + 63) / 64 + 1;
+    ErrFlag err;
+
+    // per block segment base (chunk-major)
+    int64_t tot_segs = 0;
+    for (auto &b : g.blk) {
+        b.nchunk = (b.size + W - 1) / W;
+        b.segbase = tot_segs;
+        tot_segs += (int64_t)b.nchunk * b.size;
+    }
+    std::vector<int32_t> ones_seg(tot_segs, 0);   // one entries per (chunk, row)
+    std::vector<int64_t> ones_row(n, 0), inter_row(n, 0);
+
+    // pass A: count ones per chunk
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        std::vector<uint64_t> bits(words, 0);
+        for (int64_t m = lo; m < hi && !err.bad.load(); ++m) {
+            const BlkInfo &b = g.blk[block_of_row[m]];
+            int64_t cnt = src.mark_ones(m, bits.data(), err);
+            int64_t r = m - b.row0;
+            for (int32_t c = 0; c < b.nchunk; ++c) {
+                int64_t c0 = (int64_t)c * W, c1 = std::min<int64_t>(b.size, c0 + W);
+                int64_t k = 0;
+                for (int64_t w = c0 / 64; w * 64 < c1; ++w) {
+                    uint64_t x = bits[w];
+                    int64_t wb = w * 64;
+                    if (wb < c0) x &= ~uint64_t(0) << (c0 - wb);
+                    if (wb + 64 > c1) x &= (c1 - wb >= 64) ? ~uint64_t(0) : ((uint64_t(1) << (c1 - wb)) - 1);
+                    k += __builtin_popcountll(x);
+                }
+                ones_seg[b.segbase + (int64_t)c * b.size + r] = (int32_t)k;
+            }
+            ones_row[m] = cnt;
+            inter_row[m] = src.inter_count(m);
+            src.clear(m, bits.data());
+        }
+    });
+    if (err.bad) return err.msg;
+
+    // density rule per block
+    g.n_dense = 0;
+    for (int32_t bi = 0; bi < g.nb; ++bi) {
+        BlkInfo &b = g.blk[bi];
+        if (given_mode) {
+            b.mode = (*given_mode)[bi] ? 1 : 0;
+        } else {
+            int64_t ones = 0;
+            for (int64_t m = b.row0; m < b.row0 + b.size; ++m) ones += ones_row[m];
+            double pairs = (double)b.size * (double)(b.size - 1);
+            double rho = pairs > 0 ? (double)ones / pairs : 0.0;
+            b.mode = (b.size >= 2 && rho >= opt.tau) ? 1 : 0;
+        }
+        g.n_dense += b.mode;
+    }
+
+    // segment lengths and offsets
+    g.seg_ptr.assign(tot_segs + 1, 0);
+    g.list_unpadded = 0;
+    for (auto &b : g.blk) {
+        for (int32_t c = 0; c < b.nchunk; ++c) {
+            int64_t c0 = (int64_t)c * W, cw = std::min<int64_t>(b.size, c0 + W) - c0;
+            for (int32_t r = 0; r < b.size; ++r) {
+                int64_t idx = b.segbase + (int64_t)c * b.size + r;
+                int64_t ones = ones_seg[idx];
+                int64_t len = ones;
+                if (b.mode) {
+                    int64_t diag = (r >= c0 && r < c0 + cw) ? 1 : 0;
+                    len = cw - ones - diag;
+                }
+                g.list_unpadded += len;
+                g.seg_ptr[idx + 1] = round8(len);
+            }
+        }
+    }
+    for (int64_t i = 0; i < tot_segs; ++i) g.seg_ptr[i + 1] += g.seg_ptr[i];
+    g.list.assign((size_t)g.seg_ptr[tot_segs], (uint16_t)0);
+
+    g.inter_ptr.assign(n + 1, 0);
+    for (int64_t m = 0; m < n; ++m) g.inter_ptr[m + 1] = g.inter_ptr[m] + inter_row[m];
+    g.inter_col.assign((size_t)g.inter_ptr[n], 0);
+    g.deg.assign(n, 0);
+
+    // pass B: emit the lists and the inter CSR
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        std::vector<uint64_t> bits(words, 0);
+        std::vector<int32_t> tmp;
+        for (int64_t m = lo; m < hi && !err.bad.load(); ++m) {
+            const BlkInfo &b = g.blk[block_of_row[m]];
+            int64_t r = m - b.row0;
+            int64_t cnt = src.mark_ones(m, bits.data(), err);
+            for (int32_t c = 0; c < b.nchunk; ++c) {
+                int64_t c0 = (int64_t)c * W, c1 = std::min<int64_t>(b.size, c0 + W);
+                int64_t idx = b.segbase + (int64_t)c * b.size + r;
+                uint16_t *out = g.list.data() + g.seg_ptr[idx];
+                int64_t k = 0;
+                for (int64_t w = c0 / 64; w * 64 < c1; ++w) {
+                    uint64_t x = bits[w];
+                    if (b.mode) x = ~x;
+                    int64_t wb = w * 64;
+                    if (wb < c0) x &= ~uint64_t(0) << (c0 - wb);
+                    if (wb + 64 > c1) x &= (c1 - wb >= 64) ? ~uint64_t(0) : ((uint64_t(1) << (c1 - wb)) - 1);
+                    if (b.mode && r >= wb && r < wb + 64) x &= ~(uint64_t(1) << (r - wb));
+                    while (x) {
+                        int t = __builtin_ctzll(x);
+                        x &= x - 1;
+                        out[k++] = (uint16_t)(wb + t - c0);
+                    }
+                }
+                int64_t padded = g.seg_ptr[idx + 1] - g.seg_ptr[idx];
+                for (; k < padded; ++k) out[k] = (uint16_t)W;
+            }
+            src.clear(m, bits.data());
+            tmp.clear();
+            src.inter(m, tmp);
+            std::sort(tmp.begin(), tmp.end());
+            for (size_t i = 1; i < tmp.size(); ++i)
+                if (tmp[i] == tmp[i - 1]) { err.set("duplicate column in a row (inter-block entry)"); break; }
+            std::copy(tmp.begin(), tmp.end(), g.inter_col.begin() + g.inter_ptr[m]);
+            g.deg[m] = (int32_t)std::min<int64_t>(cnt + (int64_t)tmp.size(), INT32_MAX);
+        }
+    });
+    if (err.bad) return err.msg;
+
+    // work tiles: consecutive rows of one block with similar cost
+    std::vector<int64_t> rowcost(n);
+    int64_t total = 0;
+    for (auto &b : g.blk) {
+        for (int32_t r = 0; r < b.size; ++r) {
+            int64_t c = 32 + 4 * inter_row[b.row0 + r];
+            for (int32_t ch = 0; ch < b.nchunk; ++ch) {
+                int64_t idx = b.segbase + (int64_t)ch * b.size + r;
+                c += g.seg_ptr[idx + 1] - g.seg_ptr[idx];
+            }
+            rowcost[b.row0 + r] = c;
+            total += c;
+        }
+    }
+    const int64_t target = std::max<int64_t>(2048, total / std::max<int64_t>(1, opt.tiles_target));
+    g.tiles.clear();
+    std::vector<int64_t> tcost;
+    for (int32_t bi = 0; bi < g.nb; ++bi) {
+        BlkInfo &b = g.blk[bi];
+        b.tile0 = (int32_t)g.tiles.size();
+        int32_t r = 0;
+        while (r < b.size) {
+            int32_t r1 = r;
+            int64_t c = 0;
+            while (r1 < b.size && r1 - r < opt.tile_rows && (r1 == r || c + rowcost[b.row0 + r1] <= target)) {
+                c += rowcost[b.row0 + r1];
+                ++r1;
+            }
+            // lanes per row: about two 8-entry vectors per lane in a non-empty chunk
+            int64_t vec = 0, nonempty = 0;
+            for (int32_t ch = 0; ch < b.nchunk; ++ch) {
+                int64_t s0 = g.seg_ptr[b.segbase + (int64_t)ch * b.size + r];
+                int64_t s1 = g.seg_ptr[b.segbase + (int64_t)ch * b.size + r1];
+                vec += (s1 - s0) / 8;
+                nonempty += (s1 > s0);
+            }
+            double avg = nonempty ? (double)vec / ((double)(r1 - r) * (double)nonempty) : 0.0;
+            int32_t G = 2;
+            while (G < 64 && G * 2 < avg) G *= 2;
+            g.tiles.push_back(Tile{bi, r, r1, G});
+            tcost.push_back(c + (int64_t)b.size * nonempty / 4);
+            r = r1;
+        }
+        b.ntiles = (int32_t)g.tiles.size() - b.tile0;
+    }
+    g.order.resize(g.tiles.size());
+    std::iota(g.order.begin(), g.order.end(), 0);
+    std::stable_sort(g.order.begin(), g.order.end(), [&](int32_t a, int32_t b) { return tcost[a] > tcost[b]; });
+    return "";
+}
+
+}  // namespace
+
+std::string build_from_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *labels,
+                           const BuildOptions &opt, BlockGraph &g)
+{
+    if (n < 1 || n > INT32_MAX - 1) return "n must be in [1, 2^31-2]";
+    if (!row_ptr || !labels) return "row_ptr and labels must not be NULL";
+    if (row_ptr[0] != 0) return "row_ptr[0] must be 0";
+    for (int64_t m = 0; m < n; ++m)
+        if (row_ptr[m + 1] < row_ptr[m]) return "row_ptr must be non-decreasing";
+    const int64_t nnz = row_ptr[n];
+    if (nnz > 0 && !col) return "col must not be NULL";
+    {
+        std::atomic<bool> bad{false};
+        parallel_for(nnz, [&](int64_t lo, int64_t hi) {
+            for (int64_t e = lo; e < hi; ++e)
+                if (col[e] < 0 || col[e] >= n) { bad = true; return; }
+        });
+        if (bad) return "column index out of range";
+    }
+    for (int64_t u = 0; u < n; ++u)
+        if (labels[u] < 0) return "labels must be >= 0";
+
+    // communities ordered by label value; stable counting sort of the nodes
+    std::vector<int32_t> uniq(labels, labels + n);
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    const int32_t nb = (int32_t)uniq.size();
+    std::vector<int32_t> comm(n);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t u = lo; u < hi; ++u)
+            comm[u] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), labels[u]) - uniq.begin());
+    });
+    std::vector<int64_t> cnt(nb + 1, 0);
+    for (int64_t u = 0; u < n; ++u) cnt[comm[u] + 1]++;
+    for (int32_t b = 0; b < nb; ++b) cnt[b + 1] += cnt[b];
+    g = BlockGraph();
+    g.n = n;
+    g.nb = nb;
+    g.perm.resize(n);
+    std::vector<int32_t> node_at(n), block_of_row(n);
+    {
+        std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+        for (int64_t u = 0; u < n; ++u) {
+            int64_t m = fill[comm[u]]++;
+            g.perm[u] = (int32_t)m;
+            node_at[m] = (int32_t)u;
+            block_of_row[m] = comm[u];
+        }
+    }
+    g.blk.resize(nb);
+    for (int32_t b = 0; b < nb; ++b) {
+        g.blk[b] = BlkInfo{};
+        g.blk[b].row0 = (int32_t)cnt[b];
+        g.blk[b].size = (int32_t)(cnt[b + 1] - cnt[b]);
+    }
+    const int32_t *perm = g.perm.data();
+    RowSource src;
+    src.mark_ones = [&](int64_t m, uint64_t *bits, ErrFlag &err) -> int64_t {
+        int64_t u = node_at[m];
+        const BlkInfo &b = g.blk[block_of_row[m]];
+        int64_t k = 0;
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            int64_t pv = perm[col[e]];
+            if (pv == m || pv < b.row0 || pv >= b.row0 + b.size) continue;
+            int64_t lc = pv - b.row0;
+            uint64_t bit = uint64_t(1) << (lc & 63);
+            if (bits[lc >> 6] & bit) { err.set("duplicate column in a row"); continue; }
+            bits[lc >> 6] |= bit;
+            ++k;
+        }
+        return k;
+    };
+    src.clear = [&](int64_t m, uint64_t *bits) {
+        int64_t u = node_at[m];
+        const BlkInfo &b = g.blk[block_of_row[m]];
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            int64_t pv = perm[col[e]];
+            if (pv < b.row0 || pv >= b.row0 + b.size) continue;
+            int64_t lc = pv - b.row0;
+            bits[lc >> 6] = 0;
+        }
+    };
+    src.inter_count = [&](int64_t m) -> int64_t {
+        int64_t u = node_at[m];
+        const BlkInfo &b = g.blk[block_of_row[m]];
+        int64_t k = 0;
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            int64_t pv = perm[col[e]];
+            k += (pv < b.row0 || pv >= b.row0 + b.size);
+        }
+        return k;
+    };
+    src.inter = [&](int64_t m, std::vector<int32_t> &out) {
+        int64_t u = node_at[m];
+        const BlkInfo &b = g.blk[block_of_row[m]];
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            int64_t pv = perm[col[e]];
+            if (pv < b.row0 || pv >= b.row0 + b.size) out.push_back((int32_t)pv);
+        }
+    };
+    return finish(g, block_of_row, src, nullptr, opt);
+}
+
+std::string build_from_blocks(int64_t n, int32_t nb, const int64_t *block_ptr, const uint8_t *mode,
+                              const int64_t *list_ptr, const uint16_t *list_col, const int64_t *inter_ptr,
+                              const int32_t *inter_col, const int32_t *perm, const BuildOptions &opt,
+                              BlockGraph &g)
+{
+    if (n < 1 || n > INT32_MAX - 1) return "n must be in [1, 2^31-2]";
+    if (nb < 1 || nb > n) return "nb must be in [1, n]";
+    if (!block_ptr || !mode || !list_ptr || !inter_ptr) return "block_ptr, mode, list_ptr, inter_ptr must not be NULL";
+    if (block_ptr[0] != 0 || block_ptr[nb] != n) return "block_ptr must start at 0 and end at n";
+    for (int32_t b = 0; b < nb; ++b) {
+        if (block_ptr[b + 1] <= block_ptr[b]) return "block_ptr must be strictly increasing";
+        if (block_ptr[b + 1] - block_ptr[b] > 65535) return "block sizes must be <= 65535";
+    }
+    if (list_ptr[0] != 0 || inter_ptr[0] != 0) return "list_ptr[0] and inter_ptr[0] must be 0";
+    for (int64_t m = 0; m < n; ++m)
+        if (list_ptr[m + 1] < list_ptr[m] || inter_ptr[m + 1] < inter_ptr[m])
+            return "list_ptr and inter_ptr must be non-decreasing";
+    if (list_ptr[n] > 0 && !list_col) return "list_col must not be NULL";
+    if (inter_ptr[n] > 0 && !inter_col) return "inter_col must not be NULL";
+    g = BlockGraph();
+    g.n = n;
+    g.nb = nb;
+    std::vector<int32_t> block_of_row(n);
+    g.blk.resize(nb);
+    for (int32_t b = 0; b < nb; ++b) {
+        g.blk[b] = BlkInfo{};
+        g.blk[b].row0 = (int32_t)block_ptr[b];
+        g.blk[b].size = (int32_t)(block_ptr[b + 1] - block_ptr[b]);
+        for (int64_t m = block_ptr[b]; m < block_ptr[b + 1]; ++m) block_of_row[m] = b;
+    }
+    for (int64_t m = 0; m < n; ++m) {
+        const BlkInfo &b = g.blk[block_of_row[m]];
+        int64_t r = m - b.row0;
+        for (int64_t e = list_ptr[m]; e < list_ptr[m + 1]; ++e)
+            if (list_col[e] >= b.size || list_col[e] == r) return "list_col out of range or on the diagonal";
+        for (int64_t e = inter_ptr[m]; e < inter_ptr[m + 1]; ++e)
+            if (inter_col[e] < 0 || inter_col[e] >= n || (inter_col[e] >= b.row0 && inter_col[e] < b.row0 + b.size))
+                return "inter_col out of range or inside the row's own block";
+    }
+    g.perm.resize(n);
+    if (perm) {
+        std::vector<uint8_t> seen(n, 0);
+        for (int64_t u = 0; u < n; ++u) {
+            if (perm[u] < 0 || perm[u] >= n || seen[perm[u]]) return "perm is not a permutation";
+            seen[perm[u]] = 1;
+            g.perm[u] = perm[u];
+        }
+    } else {
+        std::iota(g.perm.begin(), g.perm.end(), 0);
+    }
+    std::vector<uint8_t> modes(mode, mode + nb);
+    for (int32_t b = 0; b < nb; ++b) g.blk[b].mode = modes[b] ? 1 : 0;
+    // finish() marks the one entries of a row and complements them for a dense block; a dense
+    // block's given list holds the zeros, so its ones are everything else except the diagonal.
+    RowSource src;
+    src.mark_ones = [&](int64_t m, uint64_t *bits, ErrFlag &err) -> int64_t {
+        const BlkInfo &b = g.blk[block_of_row[m]];
+        const int64_t r = m - b.row0, s = b.size;
+        if (!b.mode) {
+            int64_t k = 0;
+            for (int64_t e = list_ptr[m]; e < list_ptr[m + 1]; ++e) {
+                int64_t lc = list_col[e];
+                uint64_t bit = uint64_t(1) << (lc & 63);
+                if (bits[lc >> 6] & bit) { err.set("duplicate column in a row"); continue; }
+                bits[lc >> 6] |= bit;
+                ++k;
+            }
+            return k;
+        }
+        for (int64_t w = 0; w * 64 < s; ++w)
+            bits[w] = (s - w * 64 >= 64) ? ~uint64_t(0) : ((uint64_t(1) << (s - w * 64)) - 1);
+        bits[r >> 6] &= ~(uint64_t(1) << (r & 63));
+        int64_t k = s - 1;
+        for (int64_t e = list_ptr[m]; e < list_ptr[m + 1]; ++e) {
+            int64_t lc = list_col[e];
+            uint64_t bit = uint64_t(1) << (lc & 63);
+            if (!(bits[lc >> 6] & bit)) { err.set("duplicate column in a row"); continue; }
+            bits[lc >> 6] &= ~bit;
+            --k;
+        }
+        return k;
+    };
+    src.clear = [&](int64_t m, uint64_t *bits) {
+        const BlkInfo &b = g.blk[block_of_row[m]];
+        if (!b.mode) {
+            for (int64_t e = list_ptr[m]; e < list_ptr[m + 1]; ++e) bits[list_col[e] >> 6] = 0;
+        } else {
+            std::memset(bits, 0, sizeof(uint64_t) * (size_t)((b.size + 63) / 64));
+        }
+    };
+    src.inter_count = [&](int64_t m) -> int64_t { return inter_ptr[m + 1] - inter_ptr[m]; };
+    src.inter = [&](int64_t m, std::vector<int32_t> &out) {
+        for (int64_t e = inter_ptr[m]; e < inter_ptr[m + 1]; ++e) out.push_back(inter_col[e]);
+    };
+    return finish(g, block_of_row, src, &modes, opt);
+}
+
+}  // namespace kur

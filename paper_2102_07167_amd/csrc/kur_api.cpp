@@ -1,0 +1,923 @@
+// kur_api.cpp -- the C ABI declared in include/kur.h: context, validation, device buffers,
+// permutation handling and the RK4 driver loop. Every numerical step runs in the HIP kernels
+// of kur_kernels.hip; this file only moves data and sequences launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/kur.h"
+#include "kur_internal.hpp"
+#include "kur_kernels.hpp"
+
+using namespace kur;
+
+static constexpr double kPi = 3.14159265358979323846;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct kur_ctx {
+    kur_dtype dtype = KUR_F32;
+    int esz = 4;  // bytes per real
+    int device = -1;
+    bool host_only = true;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    BuildOptions bopt;
+    int threads = 512;
+    int scaling = 0;
+    int compensate = 1;
+    int timing = 0;
+
+    // graph (host metadata)
+    bool has_graph = false;
+    int64_t n = 0;
+    int32_t nb = 0;
+    int32_t ntiles = 0;
+    int32_t W = 0, tile_rows = 0;
+    std::vector<int32_t> perm;
+    std::vector<int32_t> deg;
+    int64_t info[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    BlockGraph host_graph;  // full layout, kept by host-only contexts for introspection
+
+    // device graph
+    DevBuf d_blk, d_tiles, d_order, d_seg, d_list, d_iptr, d_icol;
+    // device state
+    DevBuf d_omega, d_rowscale, d_hi, d_lo, d_wind, d_ksum, d_sc[2], d_part[2], d_sce, d_parte, d_kout, d_y;
+    DevBuf d_r, d_psi;
+    int cur = 0;
+    bool sc_valid = false;
+    bool has_params = false, has_phases = false;
+    double K = 0.0;
+
+    // timing of the row kernel
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    int64_t t_launches = 0;
+    double t_ms = 0.0;
+};
+
+namespace {
+
+kur_status fail(kur_ctx *c, kur_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+kur_status hip_fail(kur_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, e == hipErrorOutOfMemory ? KUR_ENOMEM : KUR_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, expr, what)                          \
+    do {                                                 \
+        hipError_t _e = (expr);                          \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
+    } while (0)
+
+void dfree(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+hipError_t dalloc(DevBuf &b, size_t bytes)
+{
+    if (b.p && b.bytes >= bytes && bytes > 0) return hipSuccess;
+    dfree(b);
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return e;
+    }
+    b.bytes = bytes;
+    return hipSuccess;
+}
+
+hipError_t upload(DevBuf &b, const void *src, size_t bytes, hipStream_t st)
+{
+    hipError_t e = dalloc(b, bytes);
+    if (e != hipSuccess || bytes == 0) return e;
+    e = hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
+void free_all(kur_ctx *c)
+{
+    DevBuf *bufs[] = {&c->d_blk, &c->d_tiles, &c->d_order, &c->d_seg, &c->d_list, &c->d_iptr, &c->d_icol,
+                      &c->d_omega, &c->d_rowscale, &c->d_hi, &c->d_lo, &c->d_wind, &c->d_ksum, &c->d_sc[0],
+                      &c->d_sc[1], &c->d_part[0], &c->d_part[1], &c->d_sce, &c->d_parte, &c->d_kout, &c->d_y,
+                      &c->d_r, &c->d_psi};
+    for (DevBuf *b : bufs) dfree(*b);
+}
+
+bool finite_arr(const double *a, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+DevGraph devgraph(const kur_ctx *c)
+{
+    DevGraph g;
+    g.blk = (const BlkInfo *)c->d_blk.p;
+    g.tiles = (const Tile *)c->d_tiles.p;
+    g.order = (const int32_t *)c->d_order.p;
+    g.seg_ptr = (const int64_t *)c->d_seg.p;
+    g.list = (const uint16_t *)c->d_list.p;
+    g.inter_ptr = (const int64_t *)c->d_iptr.p;
+    g.inter_col = (const int32_t *)c->d_icol.p;
+    g.W = c->W;
+    g.tile_rows = c->tile_rows;
+    return g;
+}
+
+// host double array (user order) -> device T array (block order)
+hipError_t upload_perm(kur_ctx *c, DevBuf &b, const double *src)
+{
+    const int64_t n = c->n;
+    hipError_t e;
+    if (c->esz == 4) {
+        std::vector<float> t(n);
+        for (int64_t u = 0; u < n; ++u) t[c->perm[u]] = (float)src[u];
+        e = upload(b, t.data(), sizeof(float) * n, c->stream);
+    } else {
+        std::vector<double> t(n);
+        for (int64_t u = 0; u < n; ++u) t[c->perm[u]] = src[u];
+        e = upload(b, t.data(), sizeof(double) * n, c->stream);
+    }
+    return e;
+}
+
+// device T array (block order) -> host double (user order)
+hipError_t download_perm(kur_ctx *c, const void *dsrc, double *dst)
+{
+    const int64_t n = c->n;
+    if (c->esz == 4) {
+        std::vector<float> t(n);
+        hipError_t e = hipMemcpyAsync(t.data(), dsrc, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return e;
+        for (int64_t u = 0; u < n; ++u) dst[u] = (double)t[c->perm[u]];
+    } else {
+        std::vector<double> t(n);
+        hipError_t e = hipMemcpyAsync(t.data(), dsrc, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return e;
+        for (int64_t u = 0; u < n; ++u) dst[u] = t[c->perm[u]];
+    }
+    return hipSuccess;
+}
+
+kur_status need_device(kur_ctx *c)
+{
+    if (!c) return KUR_EINVAL;
+    if (c->host_only) return fail(c, KUR_EDEVICE, "host-only context (device = -1)");
+    HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    return KUR_OK;
+}
+
+kur_status need_ready(kur_ctx *c, bool params, bool phases)
+{
+    kur_status s = need_device(c);
+    if (s != KUR_OK) return s;
+    if (!c->has_graph) return fail(c, KUR_ESTATE, "no graph set");
+    if (params && !c->has_params) return fail(c, KUR_ESTATE, "omega and K not set");
+    if (phases && !c->has_phases) return fail(c, KUR_ESTATE, "phases not set");
+    return KUR_OK;
+}
+
+kur_status set_rowscale(kur_ctx *c)
+{
+    if (c->scaling == 0) {
+        dfree(c->d_rowscale);
+        return KUR_OK;
+    }
+    const int64_t n = c->n;
+    hipError_t e;
+    if (c->esz == 4) {
+        std::vector<float> t(n);
+        for (int64_t m = 0; m < n; ++m) t[m] = c->deg[m] > 0 ? (float)(c->K / (double)c->deg[m]) : 0.0f;
+        e = upload(c->d_rowscale, t.data(), sizeof(float) * n, c->stream);
+    } else {
+        std::vector<double> t(n);
+        for (int64_t m = 0; m < n; ++m) t[m] = c->deg[m] > 0 ? c->K / (double)c->deg[m] : 0.0;
+        e = upload(c->d_rowscale, t.data(), sizeof(double) * n, c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "row scale upload");
+    return KUR_OK;
+}
+
+template <typename T>
+RowArgs<T> row_args(kur_ctx *c, int stage, double dt)
+{
+    RowArgs<T> a;
+    a.stage = stage;
+    a.compensate = c->compensate;
+    a.dt = (T)dt;
+    a.half_dt = (T)(0.5 * dt);
+    a.dt6 = (T)(dt / 6.0);
+    a.kscale = (T)(c->K / (double)c->n);
+    a.rowscale = (const T *)c->d_rowscale.p;
+    a.omega = (const T *)c->d_omega.p;
+    a.hi = (T *)c->d_hi.p;
+    a.lo = (T *)c->d_lo.p;
+    a.wind = (int32_t *)c->d_wind.p;
+    a.ksum = (T *)c->d_ksum.p;
+    a.kout = (T *)c->d_kout.p;
+    a.sc_in = c->d_sc[c->cur].p;
+    a.part_in = c->d_part[c->cur].p;
+    a.sc_out = c->d_sc[c->cur ^ 1].p;
+    a.part_out = c->d_part[c->cur ^ 1].p;
+    return a;
+}
+
+hipError_t timed_rows(kur_ctx *c, const DevGraph &g, const void *args)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        if (c->ev_used + 2 > c->ev.size()) {
+            for (int i = 0; i < 64; ++i) {
+                hipEvent_t e;
+                hipError_t r = hipEventCreate(&e);
+                if (r != hipSuccess) return r;
+                c->ev.push_back(e);
+            }
+        }
+        e0 = c->ev[c->ev_used];
+        e1 = c->ev[c->ev_used + 1];
+        c->ev_used += 2;
+        hipError_t r = hipEventRecord(e0, c->stream);
+        if (r != hipSuccess) return r;
+    }
+    hipError_t r;
+    if (c->esz == 4)
+        r = launch_rows<float>(g, c->ntiles, *(const RowArgs<float> *)args, c->threads, c->stream);
+    else
+        r = launch_rows<double>(g, c->ntiles, *(const RowArgs<double> *)args, c->threads, c->stream);
+    if (r != hipSuccess) return r;
+    if (c->timing) {
+        r = hipEventRecord(e1, c->stream);
+        if (r != hipSuccess) return r;
+        c->t_launches += 1;
+    }
+    return hipSuccess;
+}
+
+// fold recorded event pairs into the totals (synchronises)
+hipError_t harvest_events(kur_ctx *c)
+{
+    if (c->ev_used == 0) return hipSuccess;
+    hipError_t r = hipStreamSynchronize(c->stream);
+    if (r != hipSuccess) return r;
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0.f;
+        r = hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
+        if (r != hipSuccess) return r;
+        c->t_ms += ms;
+    }
+    c->ev_used = 0;
+    return hipSuccess;
+}
+
+kur_status sc_init(kur_ctx *c, const void *y, DevBuf &sc, DevBuf &part)
+{
+    DevGraph g = devgraph(c);
+    hipError_t e;
+    if (c->esz == 4)
+        e = launch_sc_init<float>(g, c->ntiles, (const float *)y, sc.p, part.p, c->threads, c->stream);
+    else
+        e = launch_sc_init<double>(g, c->ntiles, (const double *)y, sc.p, part.p, c->threads, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "sc_init launch");
+    return KUR_OK;
+}
+
+kur_status install_graph(kur_ctx *c, BlockGraph &g)
+{
+    const size_t lds = rows_lds_bytes(c->esz, g.W, g.tile_rows, c->threads);
+    if (lds > 160 * 1024) return fail(c, KUR_EINVAL, "chunk/tile_rows/threads exceed the 160 KiB LDS of a workgroup");
+    if (g.tiles.size() > (size_t)INT32_MAX) return fail(c, KUR_EINVAL, "too many tiles");
+    if (!c->host_only) {
+        HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+        free_all(c);
+        hipError_t e;
+        const int64_t n = g.n;
+        const size_t T = (size_t)c->esz;
+        if ((e = upload(c->d_blk, g.blk.data(), sizeof(BlkInfo) * g.blk.size(), c->stream)) != hipSuccess ||
+            (e = upload(c->d_tiles, g.tiles.data(), sizeof(Tile) * g.tiles.size(), c->stream)) != hipSuccess ||
+            (e = upload(c->d_order, g.order.data(), sizeof(int32_t) * g.order.size(), c->stream)) != hipSuccess ||
+            (e = upload(c->d_seg, g.seg_ptr.data(), sizeof(int64_t) * g.seg_ptr.size(), c->stream)) != hipSuccess ||
+            (e = upload(c->d_list, g.list.data(), sizeof(uint16_t) * g.list.size(), c->stream)) != hipSuccess ||
+            (e = upload(c->d_iptr, g.inter_ptr.data(), sizeof(int64_t) * g.inter_ptr.size(), c->stream)) != hipSuccess ||
+            (e = upload(c->d_icol, g.inter_col.data(), sizeof(int32_t) * g.inter_col.size(), c->stream)) != hipSuccess ||
+            (e = dalloc(c->d_omega, T * n)) != hipSuccess || (e = dalloc(c->d_hi, T * n)) != hipSuccess ||
+            (e = dalloc(c->d_lo, T * n)) != hipSuccess || (e = dalloc(c->d_wind, 4 * n)) != hipSuccess ||
+            (e = dalloc(c->d_ksum, T * n)) != hipSuccess || (e = dalloc(c->d_sc[0], 2 * T * n)) != hipSuccess ||
+            (e = dalloc(c->d_sc[1], 2 * T * n)) != hipSuccess || (e = dalloc(c->d_sce, 2 * T * n)) != hipSuccess ||
+            (e = dalloc(c->d_part[0], 2 * T * g.tiles.size())) != hipSuccess ||
+            (e = dalloc(c->d_part[1], 2 * T * g.tiles.size())) != hipSuccess ||
+            (e = dalloc(c->d_parte, 2 * T * g.tiles.size())) != hipSuccess ||
+            (e = dalloc(c->d_kout, T * n)) != hipSuccess || (e = dalloc(c->d_y, T * n)) != hipSuccess) {
+            free_all(c);
+            c->has_graph = false;
+            return hip_fail(c, e, "graph upload");
+        }
+    }
+    c->n = g.n;
+    c->nb = g.nb;
+    c->ntiles = (int32_t)g.tiles.size();
+    c->W = g.W;
+    c->tile_rows = g.tile_rows;
+    c->perm.swap(g.perm);
+    c->deg.swap(g.deg);
+    c->info[0] = g.n;
+    c->info[1] = g.nb;
+    c->info[2] = g.n_dense;
+    c->info[3] = g.list_unpadded;
+    c->info[4] = (int64_t)g.list.size();
+    c->info[5] = (int64_t)g.inter_col.size();
+    c->info[6] = (int64_t)g.tiles.size();
+    c->info[7] = g.W;
+    if (c->host_only) c->host_graph = std::move(g);
+    c->has_graph = true;
+    c->has_params = false;
+    c->has_phases = false;
+    c->sc_valid = false;
+    c->cur = 0;
+    return KUR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kur_version(void) { return 100; }
+
+kur_status kur_create(kur_ctx **out, kur_dtype dtype, int device, void *hip_stream)
+{
+    if (!out) return KUR_EINVAL;
+    *out = nullptr;
+    if (dtype != KUR_F32 && dtype != KUR_F64) return KUR_EINVAL;
+    if (device < -1) return KUR_EINVAL;
+    kur_ctx *c = new (std::nothrow) kur_ctx();
+    if (!c) return KUR_ENOMEM;
+    c->dtype = dtype;
+    c->esz = dtype == KUR_F32 ? 4 : 8;
+    if (dtype == KUR_F64) {
+        c->bopt.W = 4096;
+        c->bopt.tile_rows = 512;
+    }
+    c->device = device;
+    c->host_only = device < 0;
+    if (!c->host_only) {
+        int cnt = 0;
+        if (hipGetDeviceCount(&cnt) != hipSuccess || device >= cnt) {
+            (void)hipGetLastError();
+            delete c;
+            return KUR_EDEVICE;
+        }
+        if (hipSetDevice(device) != hipSuccess) {
+            delete c;
+            return KUR_EDEVICE;
+        }
+        if (hip_stream) {
+            c->stream = (hipStream_t)hip_stream;
+        } else {
+            if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+                delete c;
+                return KUR_EDEVICE;
+            }
+            c->own_stream = true;
+        }
+    }
+    *out = c;
+    return KUR_OK;
+}
+
+void kur_destroy(kur_ctx *c)
+{
+    if (!c) return;
+    if (!c->host_only) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        free_all(c);
+        for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    }
+    delete c;
+}
+
+const char *kur_last_error(const kur_ctx *c) { return c ? c->err.c_str() : ""; }
+
+kur_status kur_set_option(kur_ctx *c, const char *key, double v)
+{
+    if (!c || !key) return KUR_EINVAL;
+    c->err.clear();
+    std::string k(key);
+    if (!std::isfinite(v)) return fail(c, KUR_EINVAL, "option value must be finite");
+    if (k == "tau") {
+        if (v < 0.0 || v > 1.0 + 1e-12) return fail(c, KUR_EINVAL, "tau must be in [0, 1]");
+        c->bopt.tau = v;
+    } else if (k == "chunk") {
+        int64_t w = (int64_t)v;
+        if ((double)w != v || w < 64 || w > 32768 || w % 64) return fail(c, KUR_EINVAL, "chunk must be a multiple of 64 in [64, 32768]");
+        c->bopt.W = (int32_t)w;
+    } else if (k == "tile_rows") {
+        int64_t t = (int64_t)v;
+        if ((double)t != v || t < 64 || t > 4096) return fail(c, KUR_EINVAL, "tile_rows must be an integer in [64, 4096]");
+        c->bopt.tile_rows = (int32_t)t;
+    } else if (k == "tiles") {
+        int64_t t = (int64_t)v;
+        if ((double)t != v || t < 1 || t > (int64_t)1 << 24) return fail(c, KUR_EINVAL, "tiles must be an integer in [1, 2^24]");
+        c->bopt.tiles_target = t;
+    } else if (k == "threads") {
+        if (v != 256 && v != 512 && v != 1024) return fail(c, KUR_EINVAL, "threads must be 256, 512 or 1024");
+        if (c->has_graph && rows_lds_bytes(c->esz, c->W, c->tile_rows, (int)v) > 160 * 1024)
+            return fail(c, KUR_EINVAL, "threads exceed the LDS budget of the current graph layout");
+        c->threads = (int)v;
+    } else if (k == "scaling") {
+        if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "scaling must be 0 or 1");
+        c->scaling = (int)v;
+        if (c->has_graph && c->has_params && !c->host_only) return set_rowscale(c);
+    } else if (k == "compensate") {
+        if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "compensate must be 0 or 1");
+        c->compensate = (int)v;
+    } else if (k == "timing") {
+        if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "timing must be 0 or 1");
+        if (!c->host_only) {
+            hipError_t e = harvest_events(c);
+            if (e != hipSuccess) return hip_fail(c, e, "timing");
+        }
+        c->timing = (int)v;
+        c->t_launches = 0;
+        c->t_ms = 0.0;
+    } else {
+        return fail(c, KUR_EINVAL, "unknown option '" + k + "'");
+    }
+    return KUR_OK;
+}
+
+kur_status kur_set_graph_csr(kur_ctx *c, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                             const int32_t *labels)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    BlockGraph g;
+    std::string msg;
+    try {
+        msg = build_from_csr(n, row_ptr, col, labels, c->bopt, g);
+    } catch (const std::bad_alloc &) {
+        return fail(c, KUR_ENOMEM, "host allocation failed in graph preprocessing");
+    }
+    if (!msg.empty()) return fail(c, KUR_EINVAL, msg);
+    return install_graph(c, g);
+}
+
+kur_status kur_set_graph(kur_ctx *c, int64_t n, int32_t nb, const int64_t *block_ptr, const uint8_t *mode,
+                         const int64_t *list_ptr, const uint16_t *list_col, const int64_t *inter_ptr,
+                         const int32_t *inter_col, const int32_t *perm)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    BlockGraph g;
+    std::string msg;
+    try {
+        msg = build_from_blocks(n, nb, block_ptr, mode, list_ptr, list_col, inter_ptr, inter_col, perm, c->bopt, g);
+    } catch (const std::bad_alloc &) {
+        return fail(c, KUR_ENOMEM, "host allocation failed in graph preprocessing");
+    }
+    if (!msg.empty()) return fail(c, KUR_EINVAL, msg);
+    return install_graph(c, g);
+}
+
+kur_status kur_graph_info(const kur_ctx *c, int64_t out[8])
+{
+    if (!c || !out) return KUR_EINVAL;
+    if (!c->has_graph) return KUR_ESTATE;
+    std::memcpy(out, c->info, sizeof(c->info));
+    return KUR_OK;
+}
+
+kur_status kur_get_perm(const kur_ctx *c, int32_t *perm)
+{
+    if (!c || !perm) return KUR_EINVAL;
+    if (!c->has_graph) return KUR_ESTATE;
+    std::memcpy(perm, c->perm.data(), sizeof(int32_t) * c->n);
+    return KUR_OK;
+}
+
+kur_status kur_get_blocks(const kur_ctx *c, int64_t *block_ptr, uint8_t *mode)
+{
+    if (!c || !block_ptr || !mode) return KUR_EINVAL;
+    if (!c->has_graph || !c->host_only) return KUR_ESTATE;
+    const BlockGraph &g = c->host_graph;
+    for (int32_t b = 0; b < g.nb; ++b) {
+        block_ptr[b] = g.blk[b].row0;
+        mode[b] = (uint8_t)g.blk[b].mode;
+    }
+    block_ptr[g.nb] = g.n;
+    return KUR_OK;
+}
+
+kur_status kur_get_row_lists(const kur_ctx *c, int64_t row, int32_t *list, int64_t *nlist, int32_t *inter,
+                             int64_t *ninter)
+{
+    if (!c || !nlist || !ninter) return KUR_EINVAL;
+    if (!c->has_graph || !c->host_only) return KUR_ESTATE;
+    const BlockGraph &g = c->host_graph;
+    if (row < 0 || row >= g.n) return KUR_EINVAL;
+    int32_t b = (int32_t)(std::upper_bound(g.blk.begin(), g.blk.end(), (int32_t)row,
+                                           [](int32_t r, const BlkInfo &x) { return r < x.row0; }) - g.blk.begin()) - 1;
+    const BlkInfo &bi = g.blk[b];
+    const int64_t r = row - bi.row0;
+    int64_t k = 0;
+    for (int32_t ch = 0; ch < bi.nchunk; ++ch) {
+        const int64_t idx = bi.segbase + (int64_t)ch * bi.size + r;
+        for (int64_t e = g.seg_ptr[idx]; e < g.seg_ptr[idx + 1]; ++e) {
+            if (g.list[e] == (uint16_t)g.W) continue;  // padding
+            if (list) {
+                if (k >= *nlist) return KUR_EINVAL;
+                list[k] = (int32_t)ch * g.W + g.list[e];
+            }
+            ++k;
+        }
+    }
+    const int64_t ni = g.inter_ptr[row + 1] - g.inter_ptr[row];
+    if (inter) {
+        if (ni > *ninter) return KUR_EINVAL;
+        std::memcpy(inter, g.inter_col.data() + g.inter_ptr[row], sizeof(int32_t) * ni);
+    }
+    *nlist = k;
+    *ninter = ni;
+    return KUR_OK;
+}
+
+kur_status kur_set_params(kur_ctx *c, const double *omega, double K)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!c->has_graph) return fail(c, KUR_ESTATE, "no graph set");
+    if (!omega) return fail(c, KUR_EINVAL, "omega must not be NULL");
+    if (!std::isfinite(K)) return fail(c, KUR_EINVAL, "K must be finite");
+    if (!finite_arr(omega, c->n)) return fail(c, KUR_EINVAL, "omega must be finite");
+    kur_status s = need_device(c);
+    if (s != KUR_OK) return s;
+    hipError_t e = upload_perm(c, c->d_omega, omega);
+    if (e != hipSuccess) return hip_fail(c, e, "omega upload");
+    c->K = K;
+    c->has_params = true;
+    return set_rowscale(c);
+}
+
+kur_status kur_set_phases(kur_ctx *c, const double *theta)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!c->has_graph) return fail(c, KUR_ESTATE, "no graph set");
+    if (!theta) return fail(c, KUR_EINVAL, "theta must not be NULL");
+    for (int64_t u = 0; u < c->n; ++u)
+        if (!std::isfinite(theta[u]) || std::fabs(theta[u]) > 1e9)
+            return fail(c, KUR_EINVAL, "theta must be finite with |theta| <= 1e9");
+    kur_status s = need_device(c);
+    if (s != KUR_OK) return s;
+    const int64_t n = c->n;
+    const double P1 = two_pi_p1(c->esz), P2 = two_pi_p2(c->esz);
+    std::vector<int32_t> wind(n);
+    std::vector<double> red(n);
+    for (int64_t u = 0; u < n; ++u) {
+        double q = std::nearbyint(theta[u] / (2.0 * kPi));
+        wind[c->perm[u]] = (int32_t)q;
+        red[c->perm[u]] = (theta[u] - q * P1) - q * P2;
+    }
+    hipError_t e;
+    if (c->esz == 4) {
+        std::vector<float> hi(n), lo(n);
+        for (int64_t m = 0; m < n; ++m) {
+            hi[m] = (float)red[m];
+            lo[m] = (float)(red[m] - (double)hi[m]);
+        }
+        if ((e = upload(c->d_hi, hi.data(), 4 * n, c->stream)) != hipSuccess ||
+            (e = upload(c->d_lo, lo.data(), 4 * n, c->stream)) != hipSuccess)
+            return hip_fail(c, e, "phase upload");
+    } else {
+        std::vector<double> lo(n, 0.0);
+        if ((e = upload(c->d_hi, red.data(), 8 * n, c->stream)) != hipSuccess ||
+            (e = upload(c->d_lo, lo.data(), 8 * n, c->stream)) != hipSuccess)
+            return hip_fail(c, e, "phase upload");
+    }
+    if ((e = upload(c->d_wind, wind.data(), 4 * n, c->stream)) != hipSuccess) return hip_fail(c, e, "phase upload");
+    c->has_phases = true;
+    c->sc_valid = false;
+    return KUR_OK;
+}
+
+static kur_status eval_common(kur_ctx *c, const void *y_dev, void *out_dev)
+{
+    kur_status s = sc_init(c, y_dev, c->d_sce, c->d_parte);
+    if (s != KUR_OK) return s;
+    DevGraph g = devgraph(c);
+    hipError_t e;
+    if (c->esz == 4) {
+        RowArgs<float> a = row_args<float>(c, 0, 0.0);
+        a.sc_in = c->d_sce.p;
+        a.part_in = c->d_parte.p;
+        a.kout = (float *)out_dev;
+        e = timed_rows(c, g, &a);
+    } else {
+        RowArgs<double> a = row_args<double>(c, 0, 0.0);
+        a.sc_in = c->d_sce.p;
+        a.part_in = c->d_parte.p;
+        a.kout = (double *)out_dev;
+        e = timed_rows(c, g, &a);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "rhs launch");
+    return KUR_OK;
+}
+
+kur_status kur_eval_rhs(kur_ctx *c, const double *theta, double *dtheta)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!dtheta) return fail(c, KUR_EINVAL, "dtheta must not be NULL");
+    kur_status s = need_ready(c, true, theta == nullptr);
+    if (s != KUR_OK) return s;
+    const void *y;
+    if (theta) {
+        for (int64_t u = 0; u < c->n; ++u)
+            if (!std::isfinite(theta[u])) return fail(c, KUR_EINVAL, "theta must be finite");
+        // reduce to [-pi, pi] in double before rounding to the context type
+        std::vector<double> red(c->n);
+        for (int64_t u = 0; u < c->n; ++u) red[u] = std::remainder(theta[u], 2.0 * kPi);
+        hipError_t e = upload_perm(c, c->d_y, red.data());
+        if (e != hipSuccess) return hip_fail(c, e, "theta upload");
+        y = c->d_y.p;
+    } else {
+        y = c->d_hi.p;
+    }
+    s = eval_common(c, y, c->d_kout.p);
+    if (s != KUR_OK) return s;
+    hipError_t e = download_perm(c, c->d_kout.p, dtheta);
+    if (e != hipSuccess) return hip_fail(c, e, "rhs download");
+    return KUR_OK;
+}
+
+kur_status kur_eval_rhs_dev(kur_ctx *c, const void *theta_dev, void *dtheta_dev)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!theta_dev || !dtheta_dev) return fail(c, KUR_EINVAL, "device pointers must not be NULL");
+    kur_status s = need_ready(c, true, false);
+    if (s != KUR_OK) return s;
+    return eval_common(c, theta_dev, dtheta_dev);
+}
+
+kur_status kur_step_rk4(kur_ctx *c, double dt, int64_t nsteps, int64_t r_every, double *r_out, double *psi_out)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!std::isfinite(dt) || dt == 0.0) return fail(c, KUR_EINVAL, "dt must be finite and nonzero");
+    if (nsteps < 0 || r_every < 0) return fail(c, KUR_EINVAL, "nsteps and r_every must be >= 0");
+    kur_status s = need_ready(c, true, true);
+    if (s != KUR_OK) return s;
+    const int64_t nsamp = r_every > 0 ? nsteps / r_every + 1 : 0;
+    if (nsamp > 0) {
+        hipError_t e;
+        if ((e = dalloc(c->d_r, sizeof(double) * nsamp)) != hipSuccess ||
+            (e = dalloc(c->d_psi, sizeof(double) * nsamp)) != hipSuccess)
+            return hip_fail(c, e, "r buffer");
+    }
+    if (!c->sc_valid) {
+        s = sc_init(c, c->d_hi.p, c->d_sc[c->cur], c->d_part[c->cur]);
+        if (s != KUR_OK) return s;
+        c->sc_valid = true;
+    }
+    DevGraph g = devgraph(c);
+    int64_t k = 0;
+    for (int64_t step = 0; step <= nsteps; ++step) {
+        if (r_every > 0 && step % r_every == 0) {
+            hipError_t e = c->esz == 4
+                               ? launch_order<float>(c->d_part[c->cur].p, c->ntiles, c->n, (double *)c->d_r.p, (double *)c->d_psi.p, k, c->stream)
+                               : launch_order<double>(c->d_part[c->cur].p, c->ntiles, c->n, (double *)c->d_r.p, (double *)c->d_psi.p, k, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "order parameter launch");
+            ++k;
+        }
+        if (step == nsteps) break;
+        for (int stage = 1; stage <= 4; ++stage) {
+            hipError_t e;
+            if (c->esz == 4) {
+                RowArgs<float> a = row_args<float>(c, stage, dt);
+                e = timed_rows(c, g, &a);
+            } else {
+                RowArgs<double> a = row_args<double>(c, stage, dt);
+                e = timed_rows(c, g, &a);
+            }
+            if (e != hipSuccess) return hip_fail(c, e, "rk4 stage launch");
+            c->cur ^= 1;
+        }
+        if (c->timing && c->ev_used + 16 > 4096) {
+            hipError_t e = harvest_events(c);
+            if (e != hipSuccess) return hip_fail(c, e, "timing");
+        }
+    }
+    if (nsamp > 0 && (r_out || psi_out)) {
+        std::vector<double> r(nsamp), p(nsamp);
+        hipError_t e = hipMemcpyAsync(r.data(), c->d_r.p, sizeof(double) * nsamp, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(p.data(), c->d_psi.p, sizeof(double) * nsamp, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "r download");
+        if (r_out) std::memcpy(r_out, r.data(), sizeof(double) * nsamp);
+        if (psi_out) std::memcpy(psi_out, p.data(), sizeof(double) * nsamp);
+        for (int64_t i = 0; i < nsamp; ++i)
+            if (!std::isfinite(r[i])) return fail(c, KUR_ENONFINITE, "non-finite order parameter (phases are not finite)");
+    }
+    return KUR_OK;
+}
+
+kur_status kur_get_phases(kur_ctx *c, double *theta, int wrapped)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!theta) return fail(c, KUR_EINVAL, "theta must not be NULL");
+    kur_status s = need_ready(c, false, true);
+    if (s != KUR_OK) return s;
+    const int64_t n = c->n;
+    std::vector<int32_t> wind(n);
+    std::vector<double> hi(n), lo(n);
+    hipError_t e;
+    if (c->esz == 4) {
+        std::vector<float> h(n), l(n);
+        e = hipMemcpyAsync(h.data(), c->d_hi.p, 4 * n, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(l.data(), c->d_lo.p, 4 * n, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(wind.data(), c->d_wind.p, 4 * n, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        for (int64_t m = 0; m < n; ++m) {
+            hi[m] = h[m];
+            lo[m] = l[m];
+        }
+    } else {
+        e = hipMemcpyAsync(hi.data(), c->d_hi.p, 8 * n, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(lo.data(), c->d_lo.p, 8 * n, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(wind.data(), c->d_wind.p, 4 * n, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "phase download");
+    const double P1 = two_pi_p1(c->esz), P2 = two_pi_p2(c->esz);
+    for (int64_t u = 0; u < n; ++u) {
+        const int64_t m = c->perm[u];
+        double x = hi[m] + lo[m];
+        if (wrapped) {
+            x = std::remainder(x, 2.0 * kPi);
+            if (x >= kPi) x -= 2.0 * kPi;
+        } else {
+            x += (double)wind[m] * P1 + (double)wind[m] * P2;
+        }
+        theta[u] = x;
+    }
+    return KUR_OK;
+}
+
+kur_status kur_get_phases_dev(kur_ctx *c, void *theta_dev)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!theta_dev) return fail(c, KUR_EINVAL, "theta_dev must not be NULL");
+    kur_status s = need_ready(c, false, true);
+    if (s != KUR_OK) return s;
+    hipError_t e = c->esz == 4 ? launch_phase_out<float>(c->n, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, 0, theta_dev, c->stream)
+                               : launch_phase_out<double>(c->n, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, 0, theta_dev, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "phase launch");
+    return KUR_OK;
+}
+
+kur_status kur_order_parameter(kur_ctx *c, double *r, double *psi)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!r || !psi) return fail(c, KUR_EINVAL, "r and psi must not be NULL");
+    kur_status s = need_ready(c, false, true);
+    if (s != KUR_OK) return s;
+    hipError_t e;
+    if (!c->sc_valid) {
+        s = sc_init(c, c->d_hi.p, c->d_sc[c->cur], c->d_part[c->cur]);
+        if (s != KUR_OK) return s;
+        c->sc_valid = true;
+    }
+    if ((e = dalloc(c->d_r, sizeof(double) * std::max<size_t>(1, c->d_r.bytes / sizeof(double)))) != hipSuccess ||
+        (e = dalloc(c->d_psi, sizeof(double) * std::max<size_t>(1, c->d_psi.bytes / sizeof(double)))) != hipSuccess)
+        return hip_fail(c, e, "r buffer");
+    e = c->esz == 4 ? launch_order<float>(c->d_part[c->cur].p, c->ntiles, c->n, (double *)c->d_r.p, (double *)c->d_psi.p, 0, c->stream)
+                    : launch_order<double>(c->d_part[c->cur].p, c->ntiles, c->n, (double *)c->d_r.p, (double *)c->d_psi.p, 0, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "order parameter launch");
+    double rv = 0, pv = 0;
+    e = hipMemcpyAsync(&rv, c->d_r.p, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&pv, c->d_psi.p, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "r download");
+    *r = rv;
+    *psi = pv;
+    if (!std::isfinite(rv)) return fail(c, KUR_ENONFINITE, "non-finite order parameter");
+    return KUR_OK;
+}
+
+struct StateHeader {
+    char magic[4];
+    int32_t version;
+    int32_t esz;
+    int32_t pad;
+    int64_t n;
+};
+
+kur_status kur_get_state(kur_ctx *c, void *blob, size_t *bytes)
+{
+    if (!c || !bytes) return KUR_EINVAL;
+    c->err.clear();
+    if (!c->has_graph) return fail(c, KUR_ESTATE, "no graph set");
+    const size_t need = sizeof(StateHeader) + (size_t)c->n * (2 * c->esz + 4);
+    if (!blob) {
+        *bytes = need;
+        return KUR_OK;
+    }
+    if (*bytes < need) return fail(c, KUR_EINVAL, "state buffer too small");
+    kur_status s = need_ready(c, false, true);
+    if (s != KUR_OK) return s;
+    StateHeader h = {{'K', 'U', 'R', 'S'}, 1, c->esz, 0, c->n};
+    char *p = (char *)blob;
+    std::memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    hipError_t e = hipMemcpyAsync(p, c->d_hi.p, (size_t)c->n * c->esz, hipMemcpyDeviceToHost, c->stream);
+    p += (size_t)c->n * c->esz;
+    if (e == hipSuccess) e = hipMemcpyAsync(p, c->d_lo.p, (size_t)c->n * c->esz, hipMemcpyDeviceToHost, c->stream);
+    p += (size_t)c->n * c->esz;
+    if (e == hipSuccess) e = hipMemcpyAsync(p, c->d_wind.p, (size_t)c->n * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "state download");
+    *bytes = need;
+    return KUR_OK;
+}
+
+kur_status kur_set_state(kur_ctx *c, const void *blob, size_t bytes)
+{
+    if (!c || !blob) return KUR_EINVAL;
+    c->err.clear();
+    if (!c->has_graph) return fail(c, KUR_ESTATE, "no graph set");
+    const size_t need = sizeof(StateHeader) + (size_t)c->n * (2 * c->esz + 4);
+    StateHeader h;
+    if (bytes < sizeof(h)) return fail(c, KUR_EINVAL, "state blob too small");
+    std::memcpy(&h, blob, sizeof(h));
+    if (std::memcmp(h.magic, "KURS", 4) != 0 || h.version != 1 || h.esz != c->esz || h.n != c->n || bytes != need)
+        return fail(c, KUR_EINVAL, "state blob does not match this context (dtype, n or format)");
+    kur_status s = need_device(c);
+    if (s != KUR_OK) return s;
+    const char *p = (const char *)blob + sizeof(h);
+    hipError_t e;
+    if ((e = upload(c->d_hi, p, (size_t)c->n * c->esz, c->stream)) != hipSuccess ||
+        (e = upload(c->d_lo, p + (size_t)c->n * c->esz, (size_t)c->n * c->esz, c->stream)) != hipSuccess ||
+        (e = upload(c->d_wind, p + (size_t)2 * c->n * c->esz, (size_t)c->n * 4, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "state upload");
+    c->has_phases = true;
+    c->sc_valid = false;
+    return KUR_OK;
+}
+
+kur_status kur_sync(kur_ctx *c)
+{
+    kur_status s = need_device(c);
+    if (s != KUR_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    return KUR_OK;
+}
+
+kur_status kur_kernel_time(kur_ctx *c, int64_t *launches, double *total_ms)
+{
+    if (!c || !launches || !total_ms) return KUR_EINVAL;
+    kur_status s = need_device(c);
+    if (s != KUR_OK) return s;
+    hipError_t e = harvest_events(c);
+    if (e != hipSuccess) return hip_fail(c, e, "timing");
+    *launches = c->t_launches;
+    *total_ms = c->t_ms;
+    return KUR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// kur_internal.hpp -- internal data layout shared by the host preprocessing and the HIP code.
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+namespace kur {
+
+// One diagonal block (a community after regrouping) as the kernels see it.
+struct BlkInfo {
+    int32_t row0;     // first block-order row
+    int32_t size;     // rows (= columns) of the block
+    int32_t nchunk;   // column chunks of width W
+    int32_t mode;     // 1: list of zeros (localised order parameters), 0: list of ones
+    int64_t segbase;  // index into seg_ptr of (chunk 0, local row 0); chunk c, row r at
+                      // segbase + c * size + r
+    int32_t tile0;    // first tile of this block (tiles of a block are contiguous)
+    int32_t ntiles;
+};
+
+// One unit of work: rows [r0, r1) (block-local) of one block, G lanes per row.
+struct Tile {
+    int32_t block;
+    int32_t r0;
+    int32_t r1;
+    int32_t G;
+};
+
+struct BuildOptions {
+    double tau = 0.5;        // dense if realised density >= tau
+    int32_t W = 8192;        // chunk width (columns staged in LDS at a time)
+    int32_t tile_rows = 1024;
+    int64_t tiles_target = 4096;
+};
+
+// The graph in block order, ready for upload.
+struct BlockGraph {
+    int64_t n = 0;
+    int32_t nb = 0;
+    int32_t W = 0;
+    int32_t tile_rows = 0;
+    std::vector<int32_t> perm;        // user node -> block-order row
+    std::vector<BlkInfo> blk;
+    std::vector<int64_t> seg_ptr;     // total segments + 1 (chunk-major inside every block)
+    std::vector<uint16_t> list;       // chunk-relative column, segments padded to 8 entries
+    std::vector<int64_t> inter_ptr;   // n + 1, block order
+    std::vector<int32_t> inter_col;   // block-order columns
+    std::vector<Tile> tiles;
+    std::vector<int32_t> order;       // launch order of tiles (largest first)
+    std::vector<int32_t> deg;         // row degree (ones of the row), block order
+    int64_t list_unpadded = 0;
+    int64_t n_dense = 0;
+};
+
+// Host preprocessing entry points; return "" on success or an error message.
+std::string build_from_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *labels,
+                           const BuildOptions &opt, BlockGraph &out);
+std::string build_from_blocks(int64_t n, int32_t nb, const int64_t *block_ptr, const uint8_t *mode,
+                              const int64_t *list_ptr, const uint16_t *list_col, const int64_t *inter_ptr,
+                              const int32_t *inter_col, const int32_t *perm, const BuildOptions &opt,
+                              BlockGraph &out);
+
+// Runs f(i) for i in [0, n) on the host threads (static contiguous ranges).
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &f);
+
+}  // namespace kur

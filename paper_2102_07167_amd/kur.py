@@ -1,0 +1,247 @@
+"""Thin ctypes binding of the C ABI in include/kur.h (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``libkur.so``; this module converts numpy arrays
+and torch device tensors into pointers and status codes into exceptions. If the shared library
+is missing it raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .buildlib import SO
+
+KUR_OK, KUR_EINVAL, KUR_ENOMEM, KUR_EDEVICE, KUR_ESTATE, KUR_ENONFINITE = range(6)
+KUR_F32, KUR_F64 = 1, 2
+STATUS_NAMES = {0: "KUR_OK", 1: "KUR_EINVAL", 2: "KUR_ENOMEM", 3: "KUR_EDEVICE", 4: "KUR_ESTATE",
+                5: "KUR_ENONFINITE"}
+
+_lib = None
+
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+I32 = ctypes.c_int32
+F64 = ctypes.c_double
+ST = ctypes.c_int
+
+# name -> (restype, argtypes); the full exported surface of include/kur.h
+SIGNATURES = {
+    "kur_version": (ctypes.c_int, []),
+    "kur_create": (ST, [ctypes.POINTER(P), ctypes.c_int, ctypes.c_int, P]),
+    "kur_destroy": (None, [P]),
+    "kur_last_error": (ctypes.c_char_p, [P]),
+    "kur_set_option": (ST, [P, ctypes.c_char_p, F64]),
+    "kur_set_graph_csr": (ST, [P, I64, P, P, P]),
+    "kur_set_graph": (ST, [P, I64, I32, P, P, P, P, P, P, P]),
+    "kur_graph_info": (ST, [P, P]),
+    "kur_get_perm": (ST, [P, P]),
+    "kur_get_blocks": (ST, [P, P, P]),
+    "kur_get_row_lists": (ST, [P, I64, P, P, P, P]),
+    "kur_set_params": (ST, [P, P, F64]),
+    "kur_set_phases": (ST, [P, P]),
+    "kur_eval_rhs": (ST, [P, P, P]),
+    "kur_step_rk4": (ST, [P, F64, I64, I64, P, P]),
+    "kur_get_phases": (ST, [P, P, ctypes.c_int]),
+    "kur_order_parameter": (ST, [P, P, P]),
+    "kur_get_state": (ST, [P, P, ctypes.POINTER(ctypes.c_size_t)]),
+    "kur_set_state": (ST, [P, P, ctypes.c_size_t]),
+    "kur_sync": (ST, [P]),
+    "kur_kernel_time": (ST, [P, P, P]),
+    "kur_eval_rhs_dev": (ST, [P, P, P]),
+    "kur_get_phases_dev": (ST, [P, P]),
+}
+
+
+class KurError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+def lib():
+    """Load libkur.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO):
+            raise RuntimeError("libkur.so is not built (run paper_2102_07167_amd.build.build())")
+        L = ctypes.CDLL(SO)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(P)
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.shape != (n,):
+        raise ValueError("expected shape (%d,), got %s" % (n, a.shape))
+    return a
+
+
+class Kuramoto:
+    """One library context: a graph, omega, K, the phase state, one device and one stream."""
+
+    def __init__(self, dtype: str = "f32", device: int = 0, stream=None):
+        self._L = lib()
+        self.dtype = dtype
+        h = P()
+        code = KUR_F32 if dtype in ("f32", "float32") else KUR_F64
+        st = None
+        if stream is not None:
+            st = P(int(getattr(stream, "cuda_stream", stream)))
+        rc = self._L.kur_create(ctypes.byref(h), code, int(device), st)
+        if rc != KUR_OK:
+            raise KurError(rc, "kur_create(dtype=%s, device=%d) failed" % (dtype, device))
+        self._h = h
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.kur_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _chk(self, rc):
+        if rc != KUR_OK:
+            raise KurError(rc, self._L.kur_last_error(self._h).decode())
+
+    # -- configuration ----------------------------------------------------------------------
+    def set_option(self, key: str, value: float):
+        self._chk(self._L.kur_set_option(self._h, key.encode(), float(value)))
+
+    def set_graph_csr(self, n, row_ptr, col, labels):
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        labels = np.ascontiguousarray(labels, dtype=np.int32)
+        self._chk(self._L.kur_set_graph_csr(self._h, int(n), _ptr(row_ptr), _ptr(col), _ptr(labels)))
+        self.n = int(n)
+
+    def set_graph_blocks(self, n, block_ptr, mode, list_ptr, list_col, inter_ptr, inter_col, perm=None):
+        block_ptr = np.ascontiguousarray(block_ptr, dtype=np.int64)
+        mode = np.ascontiguousarray(mode, dtype=np.uint8)
+        list_ptr = np.ascontiguousarray(list_ptr, dtype=np.int64)
+        list_col = np.ascontiguousarray(list_col, dtype=np.uint16)
+        inter_ptr = np.ascontiguousarray(inter_ptr, dtype=np.int64)
+        inter_col = np.ascontiguousarray(inter_col, dtype=np.int32)
+        perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+        self._chk(self._L.kur_set_graph(self._h, int(n), len(block_ptr) - 1, _ptr(block_ptr), _ptr(mode),
+                                        _ptr(list_ptr), _ptr(list_col), _ptr(inter_ptr), _ptr(inter_col),
+                                        _ptr(perm)))
+        self.n = int(n)
+
+    def set_graph_complete(self, n):
+        """All-to-all coupling: one dense block whose list of zeros is empty."""
+        z = np.zeros(n + 1, dtype=np.int64)
+        self.set_graph_blocks(n, np.array([0, n], dtype=np.int64), np.array([1], dtype=np.uint8), z,
+                              np.zeros(1, np.uint16), z, np.zeros(1, np.int32))
+
+    def set_graph(self, graph):
+        """Any object with n, labels, row_ptr, col, complete (e.g. a generated graph)."""
+        if getattr(graph, "complete", False):
+            self.set_graph_complete(graph.n)
+        else:
+            self.set_graph_csr(graph.n, graph.row_ptr, graph.col, graph.labels)
+
+    def graph_info(self) -> dict:
+        out = np.zeros(8, dtype=np.int64)
+        self._chk(self._L.kur_graph_info(self._h, _ptr(out)))
+        keys = ["n", "blocks", "dense_blocks", "list_entries", "list_padded", "inter_entries", "tiles", "chunk"]
+        return {k: int(v) for k, v in zip(keys, out)}
+
+    def perm(self) -> np.ndarray:
+        p = np.empty(self.n, dtype=np.int32)
+        self._chk(self._L.kur_get_perm(self._h, _ptr(p)))
+        return p
+
+    def blocks(self):
+        nb = self.graph_info()["blocks"]
+        bp = np.empty(nb + 1, dtype=np.int64)
+        md = np.empty(nb, dtype=np.uint8)
+        self._chk(self._L.kur_get_blocks(self._h, _ptr(bp), _ptr(md)))
+        return bp, md
+
+    def row_lists(self, row: int):
+        nl, ni = I64(0), I64(0)
+        self._chk(self._L.kur_get_row_lists(self._h, int(row), None, ctypes.byref(nl), None, ctypes.byref(ni)))
+        lst = np.empty(max(nl.value, 1), dtype=np.int32)
+        itr = np.empty(max(ni.value, 1), dtype=np.int32)
+        self._chk(self._L.kur_get_row_lists(self._h, int(row), _ptr(lst), ctypes.byref(nl), _ptr(itr),
+                                            ctypes.byref(ni)))
+        return lst[: nl.value], itr[: ni.value]
+
+    def set_params(self, omega, K: float):
+        omega = _f64(omega, self.n)
+        self._chk(self._L.kur_set_params(self._h, _ptr(omega), float(K)))
+
+    def set_phases(self, theta):
+        theta = _f64(theta, self.n)
+        self._chk(self._L.kur_set_phases(self._h, _ptr(theta)))
+
+    # -- computation --------------------------------------------------------------------------
+    def eval_rhs(self, theta=None) -> np.ndarray:
+        out = np.empty(self.n)
+        th = None if theta is None else _f64(theta, self.n)
+        self._chk(self._L.kur_eval_rhs(self._h, _ptr(th), _ptr(out)))
+        return out
+
+    def step_rk4(self, dt: float, nsteps: int, r_every: int = 0, want_r: bool = True):
+        ns = nsteps // r_every + 1 if r_every > 0 else 0
+        r = np.empty(ns) if (ns and want_r) else None
+        psi = np.empty(ns) if (ns and want_r) else None
+        self._chk(self._L.kur_step_rk4(self._h, float(dt), int(nsteps), int(r_every), _ptr(r), _ptr(psi)))
+        return r, psi
+
+    def get_phases(self, wrapped: bool = False) -> np.ndarray:
+        out = np.empty(self.n)
+        self._chk(self._L.kur_get_phases(self._h, _ptr(out), 1 if wrapped else 0))
+        return out
+
+    def order_parameter(self):
+        r, psi = F64(), F64()
+        self._chk(self._L.kur_order_parameter(self._h, ctypes.byref(r), ctypes.byref(psi)))
+        return r.value, psi.value
+
+    def get_state(self) -> bytes:
+        nb = ctypes.c_size_t(0)
+        self._chk(self._L.kur_get_state(self._h, None, ctypes.byref(nb)))
+        buf = ctypes.create_string_buffer(nb.value)
+        self._chk(self._L.kur_get_state(self._h, buf, ctypes.byref(nb)))
+        return buf.raw[: nb.value]
+
+    def set_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._chk(self._L.kur_set_state(self._h, buf, len(blob)))
+
+    def sync(self):
+        self._chk(self._L.kur_sync(self._h))
+
+    def kernel_time(self):
+        n, ms = I64(0), F64(0)
+        self._chk(self._L.kur_kernel_time(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+    # -- device tensors (block order, context dtype) ----------------------------------------
+    def eval_rhs_dev(self, theta_t, out_t):
+        self._chk(self._L.kur_eval_rhs_dev(self._h, P(theta_t.data_ptr()), P(out_t.data_ptr())))
+
+    def get_phases_dev(self, out_t):
+        self._chk(self._L.kur_get_phases_dev(self._h, P(out_t.data_ptr())))

@@ -1,0 +1,192 @@
+"""CPU tests of the C ABI: the library loads and exports every declared symbol, and the host
+preprocessing (regroup by label, dense/sparse choice, chunked lists, inter CSR) is checked on
+host-only contexts against the dense adjacency. No GPU call is made."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gen
+from paper_2102_07167_amd import kur as K
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "kur.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(kur_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = K.lib()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert set(names) == set(K.SIGNATURES), set(names) ^ set(K.SIGNATURES)
+    assert L.kur_version() >= 100
+
+
+def host_ctx(dtype="f32", **opts):
+    k = K.Kuramoto(dtype, device=-1)
+    for key, v in opts.items():
+        k.set_option(key, v)
+    return k
+
+
+def check_layout(k, g, tau):
+    """Compare the stored layout with the dense adjacency of g (user order)."""
+    A = g.dense()
+    perm = k.perm()
+    n = g.n
+    # stable counting sort by label: block order sorted by (label, user index)
+    order = np.lexsort((np.arange(n), g.labels))
+    assert np.array_equal(perm[order], np.arange(n))
+    bp, mode = k.blocks()
+    labs = g.labels[order]
+    starts = np.flatnonzero(np.r_[True, labs[1:] != labs[:-1]])
+    assert np.array_equal(bp[:-1], starts) and bp[-1] == n
+    B = A[np.ix_(order, order)]  # block-order adjacency P A P^T
+    for b in range(len(mode)):
+        s0, s1 = bp[b], bp[b + 1]
+        sub = B[s0:s1, s0:s1]
+        s = s1 - s0
+        rho = sub.sum() / (s * (s - 1)) if s > 1 else 0.0
+        assert mode[b] == (1 if (s >= 2 and rho >= tau) else 0)
+        for m in range(s0, s1):
+            lst, itr = k.row_lists(m)
+            r = m - s0
+            if mode[b]:
+                want = [c for c in range(s) if c != r and sub[r, c] == 0]
+            else:
+                want = list(np.flatnonzero(sub[r]))
+            assert list(lst) == want, (b, m)
+            cross = [c for c in np.flatnonzero(B[m]) if not (s0 <= c < s1)]
+            assert list(itr) == cross
+
+
+@pytest.mark.parametrize("chunk", [64, 8192])
+@pytest.mark.parametrize("tau", [0.0, 0.5, 1.0])
+def test_preprocessing_matches_dense_adjacency(chunk, tau):
+    rng = np.random.default_rng(3)
+    sizes = np.array([130, 1, 64, 200, 7])
+    rho = np.array([0.9, 0.5, 0.3, 0.7, 1.0])
+    g = gen.sbm(sizes, rho, 0.02, key=12345, uperm=rng.permutation(sizes.sum()).astype(np.int32))
+    with host_ctx(chunk=chunk, tau=tau, tile_rows=64) as k:
+        k.set_graph(g)
+        info = k.graph_info()
+        assert info["n"] == g.n and info["blocks"] == 5 and info["chunk"] == chunk
+        assert info["inter_entries"] == sum(
+            int(np.sum(g.labels[g.col[g.row_ptr[u]:g.row_ptr[u + 1]]] != g.labels[u])) for u in range(g.n))
+        check_layout(k, g, tau)
+
+
+def test_preprocessing_asymmetric_and_labels_unordered():
+    rng = np.random.default_rng(9)
+    n = 150
+    A = (rng.random((n, n)) < 0.3).astype(np.uint8)
+    np.fill_diagonal(A, 0)
+    labels = rng.choice([7, 3, 100, 42], size=n).astype(np.int32)
+    # make the blocks denser than the rest
+    for i in range(n):
+        for j in range(n):
+            if i != j and labels[i] == labels[j] and rng.random() < 0.7:
+                A[i, j] = 1
+    g = gen.from_dense(A, labels)
+    with host_ctx(chunk=64) as k:
+        k.set_graph(g)
+        check_layout(k, g, 0.5)
+
+
+def test_block_form_roundtrip():
+    """kur_set_graph with the lists exported from a CSR-built layout rebuilds the same layout."""
+    rng = np.random.default_rng(5)
+    sizes = np.array([100, 60, 90])
+    g = gen.sbm(sizes, np.array([0.95, 0.2, 0.6]), 0.05, key=99, uperm=rng.permutation(250).astype(np.int32))
+    with host_ctx(chunk=64) as k1:
+        k1.set_graph(g)
+        bp, mode = k1.blocks()
+        perm = k1.perm()
+        lp, lc, ip, ic = [0], [], [0], []
+        for m in range(g.n):
+            lst, itr = k1.row_lists(m)
+            lc += list(lst)
+            ic += list(itr)
+            lp.append(len(lc))
+            ip.append(len(ic))
+        with host_ctx(chunk=128) as k2:
+            k2.set_graph_blocks(g.n, bp, mode, np.array(lp), np.array(lc), np.array(ip), np.array(ic), perm)
+            assert np.array_equal(k2.perm(), perm)
+            bp2, mode2 = k2.blocks()
+            assert np.array_equal(bp2, bp) and np.array_equal(mode2, mode)
+            for m in range(g.n):
+                a1, b1 = k1.row_lists(m)
+                a2, b2 = k2.row_lists(m)
+                assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+            assert k2.graph_info()["list_entries"] == k1.graph_info()["list_entries"]
+
+
+def test_complete_graph_has_empty_lists():
+    with host_ctx() as k:
+        k.set_graph_complete(1000)
+        info = k.graph_info()
+        assert info["blocks"] == 1 and info["dense_blocks"] == 1 and info["list_entries"] == 0
+
+
+def _expect(status, fn, *a):
+    with pytest.raises(K.KurError) as ei:
+        fn(*a)
+    assert ei.value.status == status, str(ei.value)
+
+
+def test_validation_errors_before_device_work():
+    with host_ctx() as k:
+        rp = np.array([0, 1, 2], dtype=np.int64)
+        _expect(K.KUR_EINVAL, k.set_graph_csr, 2, np.array([0, 2, 1]), np.array([1, 0]), np.zeros(2))
+        _expect(K.KUR_EINVAL, k.set_graph_csr, 2, rp, np.array([1, 2]), np.zeros(2))       # col out of range
+        _expect(K.KUR_EINVAL, k.set_graph_csr, 2, rp, np.array([1, 0]), np.array([0, -1]))  # negative label
+        _expect(K.KUR_EINVAL, k.set_graph_csr, 2, np.array([0, 2, 2]), np.array([1, 1]), np.zeros(2))  # dup
+        _expect(K.KUR_EINVAL, k.set_graph_csr, 0, np.array([0]), np.zeros(0), np.zeros(0))
+        for key, v in [("tau", -0.1), ("chunk", 100), ("chunk", 65536), ("tile_rows", 10), ("threads", 128),
+                       ("scaling", 2), ("nonsense", 1.0), ("tau", float("nan"))]:
+            _expect(K.KUR_EINVAL, k.set_option, key, v)
+        # LDS budget: 32768 columns of FP32 (sin, cos) do not fit next to 4096-row accumulators
+        k.set_option("chunk", 32768)
+        k.set_option("tile_rows", 4096)
+        _expect(K.KUR_EINVAL, k.set_graph_complete, 10)
+        k.set_option("chunk", 8192)
+        k.set_option("tile_rows", 1024)
+        # calls out of order
+        _expect(K.KUR_ESTATE, k.graph_info)
+        k.set_graph_complete(4)
+        # no device on a host-only context
+        _expect(K.KUR_EDEVICE, k.set_params, np.zeros(4), 1.0)
+        _expect(K.KUR_EINVAL, k.set_params, np.array([0, np.nan, 0, 0]), 1.0)
+        _expect(K.KUR_EINVAL, k.set_params, np.zeros(4), float("inf"))
+        _expect(K.KUR_EINVAL, k.set_phases, np.array([0, 0, np.inf, 0]))
+        _expect(K.KUR_EDEVICE, k.step_rk4, 0.01, 1)
+        _expect(K.KUR_EINVAL, k.step_rk4, 0.0, 1)
+        _expect(K.KUR_EINVAL, k.step_rk4, 0.01, -1)
+
+
+def test_block_form_validation():
+    with host_ctx() as k:
+        z = np.zeros(5, dtype=np.int64)
+        ok = dict(n=4, block_ptr=np.array([0, 2, 4]), mode=np.array([1, 0]), list_ptr=z, list_col=np.zeros(1),
+                  inter_ptr=z, inter_col=np.zeros(1))
+        k.set_graph_blocks(**ok)
+        bad = [dict(block_ptr=np.array([0, 2, 5])), dict(block_ptr=np.array([0, 2, 2, 4]), mode=np.array([1, 0, 1])),
+               dict(list_ptr=np.array([0, 1, 1, 1, 1]), list_col=np.array([0])),        # diagonal
+               dict(list_ptr=np.array([0, 1, 1, 1, 1]), list_col=np.array([2])),        # out of block
+               dict(inter_ptr=np.array([0, 1, 1, 1, 1]), inter_col=np.array([1])),      # own block
+               dict(inter_ptr=np.array([0, 2, 2, 2, 2]), inter_col=np.array([2, 2])),   # duplicate
+               dict(perm=np.array([0, 1, 1, 3]))]
+        for b in bad:
+            args = dict(ok)
+            args.update(b)
+            _expect(K.KUR_EINVAL, k.set_graph_blocks, *[args[x] for x in
+                                                        ["n", "block_ptr", "mode", "list_ptr", "list_col",
+                                                         "inter_ptr", "inter_col"]], args.get("perm"))

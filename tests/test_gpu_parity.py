@@ -1,0 +1,270 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the same seeded inputs.
+
+Tolerances (from the arithmetic and the stated targets):
+  FP64 right-hand side   max |dF| <= 1e-12 * max |F_oracle|
+  FP64 phases            max |wrap(dtheta)| <= 1e-12 * max(1, max |theta_oracle|)  (unwrapped scale)
+  FP32 phases            max |wrap(dtheta)| <= 1e-5 after 1000 RK4 steps; the oracle integrates in FP64
+                         from the FP32-rounded theta0, omega, K and dt
+  FP32 right-hand side   |dG_m| <= 1e-5 * scale_m * (deg_m + 2 s_b [dense]) where G = F - omega
+                         (rounding scale of the complement form: u * (|S_b| + |C_b| + sum |terms|))
+"""
+import math
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from paper_2102_07167_amd import Kuramoto
+
+pytestmark = pytest.mark.gpu
+
+TWO_PI = 2 * np.pi
+
+
+def wrap(x):
+    return np.remainder(x + np.pi, TWO_PI) - np.pi
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def make(w, dtype, **opts):
+    k = Kuramoto(dtype, device=0)
+    for key, v in opts.items():
+        k.set_option(key, v)
+    k.set_graph(w.graph)
+    k.set_params(w.omega, w.K)
+    k.set_phases(w.theta0)
+    return k
+
+
+def rel_err(a, b):
+    return np.abs(a - b).max() / max(1.0, np.abs(b).max())
+
+
+def fp32_rhs_bound(k, w, theta):
+    """Per-row rounding scale for an FP32 evaluation (see module docstring)."""
+    g = w.graph
+    deg = np.diff(g.row_ptr) if not g.complete else np.full(g.n, g.n - 1)
+    bp, mode = None, None
+    perm = k.perm()
+    info = k.graph_info()
+    # block size of every user node: size of its label's community
+    if g.complete:
+        sb = np.full(g.n, g.n)
+    else:
+        _, inv, cnt = np.unique(g.labels, return_inverse=True, return_counts=True)
+        sb = cnt[inv]
+    return 1e-5 * (w.K / g.n) * (deg + 2 * sb) + 1e-6 * np.abs(w.omega) + 1e-7
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_all_to_all_n512(need_gpu, dtype):
+    """Classical model as one dense block with an empty list (Sec. 2, eq. KuramotoReformulation)."""
+    w = gen.all_to_all()
+    if dtype == "f32":
+        w.omega, w.theta0, w.K, w.dt = f32(w.omega), f32(w.theta0), float(np.float32(w.K)), float(np.float32(w.dt))
+    with make(w, dtype) as k:
+        F = k.eval_rhs()
+        Fo = oracle.rhs(w.graph, w.omega, w.K, w.theta0)
+        tol = 1e-12 if dtype == "f64" else 1e-5
+        assert rel_err(F, Fo) < tol
+        r, psi = k.step_rk4(w.dt, w.steps, r_every=1)
+        th = k.get_phases()
+        tho, ro, psio = oracle.rk4(w.graph, w.omega, w.K, w.theta0, w.dt, w.steps, r_every=1)
+        ptol = 1e-12 * max(1.0, np.abs(tho).max()) if dtype == "f64" else 1e-5
+        assert np.abs(wrap(th - tho)).max() < ptol
+        assert np.abs(r - ro).max() < (1e-12 if dtype == "f64" else 1e-5)
+        assert len(r) == w.steps + 1
+
+
+def small_sbm(seed=21, n_comm=8, comm_size=512, steps=1000, **kw):
+    return gen.sbm_equal(n_comm=n_comm, comm_size=comm_size, rho_in=0.97, p_out=2e-3, K=4.0, dt=0.01,
+                         steps=steps, seed=seed, **kw)
+
+
+def test_sbm_fp64_rhs_and_trajectory(need_gpu):
+    w = small_sbm()
+    with make(w, "f64") as k:
+        F = k.eval_rhs()
+        Fo = oracle.rhs(w.graph, w.omega, w.K, w.theta0)
+        assert rel_err(F, Fo) < 1e-12
+        k.step_rk4(w.dt, w.steps)
+        th = k.get_phases()
+    tho, _, _ = oracle.rk4(w.graph, w.omega, w.K, w.theta0, w.dt, w.steps)
+    assert np.abs(wrap(th - tho)).max() < 1e-12 * max(1.0, np.abs(tho).max())
+
+
+def test_sbm_fp32_trajectory_1000_steps(need_gpu):
+    w = small_sbm()
+    om, th0, Kf, dtf = f32(w.omega), f32(w.theta0), float(np.float32(w.K)), float(np.float32(w.dt))
+    w.omega, w.theta0, w.K = om, th0, Kf
+    with make(w, "f32") as k:
+        k.step_rk4(dtf, w.steps)
+        th = k.get_phases()
+        thw = k.get_phases(wrapped=True)
+    tho, _, _ = oracle.rk4(w.graph, om, Kf, th0, dtf, w.steps)
+    err = np.abs(wrap(th - tho)).max()
+    assert err < 1e-5, err
+    assert np.abs(wrap(thw - tho)).max() < 1e-5
+    assert np.all(thw >= -np.pi) and np.all(thw < np.pi)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("opts", [dict(chunk=64, tile_rows=64), dict(tau=0.0, chunk=128), dict(tau=1.0),
+                                  dict(threads=256, tile_rows=128), dict(threads=1024)])
+def test_ragged_layouts(need_gpu, dtype, opts):
+    """Odd block sizes, several chunks per block, several tiles per block, all-dense and
+    all-sparse evaluation, a size-1 block and a complete block."""
+    rng = np.random.default_rng(77)
+    sizes = np.array([333, 1, 129, 700, 64, 2, 515])
+    rho = np.array([0.95, 0.5, 0.3, 0.75, 1.0, 1.0, 0.55])
+    n = int(sizes.sum())
+    g = gen.sbm(sizes, rho, 0.01, key=2024, uperm=rng.permutation(n).astype(np.int32))
+    w = gen.Workload("ragged", g, rng.standard_normal(n), rng.uniform(0, TWO_PI, n), 3.0, 0.01, 50)
+    if dtype == "f32":
+        w.omega, w.theta0 = f32(w.omega), f32(w.theta0)
+    with make(w, dtype, **opts) as k:
+        F = k.eval_rhs()
+        Fo = oracle.rhs(g, w.omega, w.K, w.theta0)
+        if dtype == "f64":
+            assert rel_err(F, Fo) < 1e-12
+        else:
+            assert np.all(np.abs(F - Fo) <= fp32_rhs_bound(k, w, w.theta0))
+        k.step_rk4(w.dt, w.steps)
+        th = k.get_phases()
+    tho, _, _ = oracle.rk4(g, w.omega, w.K, w.theta0, w.dt, w.steps)
+    tol = 1e-12 * max(1.0, np.abs(tho).max()) if dtype == "f64" else 1e-5
+    assert np.abs(wrap(th - tho)).max() < tol
+
+
+def test_asymmetric_and_degree_scaling(need_gpu):
+    rng = np.random.default_rng(8)
+    n = 600
+    labels = rng.integers(0, 5, n).astype(np.int32)
+    A = (rng.random((n, n)) < 0.02).astype(np.uint8)
+    same = labels[:, None] == labels[None, :]
+    A |= (same & (rng.random((n, n)) < 0.8)).astype(np.uint8)
+    A[:7, :] = 0  # zero rows: theta' = omega under degree scaling
+    np.fill_diagonal(A, 0)
+    g = gen.from_dense(A, labels)
+    omega, th0 = rng.standard_normal(n), rng.uniform(0, TWO_PI, n)
+    for scaling in (0, 1):
+        with Kuramoto("f64", device=0) as k:
+            k.set_option("scaling", scaling)
+            k.set_graph(g)
+            k.set_params(omega, 2.5)
+            k.set_phases(th0)
+            F = k.eval_rhs()
+            assert rel_err(F, oracle.rhs(g, omega, 2.5, th0, scaling=scaling)) < 1e-12
+            k.step_rk4(0.02, 100)
+            th = k.get_phases()
+        tho, _, _ = oracle.rk4(g, omega, 2.5, th0, 0.02, 100, scaling=scaling)
+        assert np.abs(wrap(th - tho)).max() < 1e-12 * max(1, np.abs(tho).max())
+
+
+def test_empty_graph_and_single_node(need_gpu):
+    rng = np.random.default_rng(1)
+    n = 50
+    g = gen.Graph(n=n, labels=rng.integers(0, 3, n).astype(np.int32), row_ptr=np.zeros(n + 1, np.int64),
+                  col=np.zeros(0, np.int32))
+    om, th0 = rng.standard_normal(n), rng.uniform(0, TWO_PI, n)
+    with Kuramoto("f64", device=0) as k:
+        k.set_graph(g)
+        k.set_params(om, 5.0)
+        k.set_phases(th0)
+        assert np.array_equal(k.eval_rhs(), om)
+        k.step_rk4(0.1, 10)
+        assert np.abs(k.get_phases() - (th0 + om)).max() < 1e-13
+    with Kuramoto("f32", device=0) as k:
+        k.set_graph(gen.Graph(n=1, labels=np.zeros(1, np.int32), row_ptr=np.zeros(2, np.int64),
+                              col=np.zeros(0, np.int32)))
+        k.set_params(np.array([0.5]), 1.0)
+        k.set_phases(np.array([3.0]))
+        k.step_rk4(0.5, 4)
+        assert abs(k.get_phases()[0] - 4.0) < 1e-6
+        r, _ = k.order_parameter()
+        assert abs(r - 1.0) < 1e-6
+
+
+def test_state_roundtrip_bitwise_and_determinism(need_gpu):
+    w = small_sbm(n_comm=4, comm_size=300, steps=40)
+    for dtype in ("f32", "f64"):
+        with make(w, dtype) as k1:
+            k1.step_rk4(w.dt, 40)
+            a = k1.get_state()
+        with make(w, dtype) as k2:
+            k2.step_rk4(w.dt, 20)
+            blob = k2.get_state()
+        with make(w, dtype) as k3:
+            k3.set_state(blob)
+            k3.step_rk4(w.dt, 20)
+            b = k3.get_state()
+        assert a == b  # bitwise: resume and rerun agree exactly
+
+
+def test_conservation_and_fixed_point(need_gpu):
+    """Symmetric A, uniform scaling: the mean of theta - theta0 - t omega stays 0 (Sec. 3, eq.
+    KuramotoGraphConservation); omega = 0 with equal phases is a fixed point."""
+    w = small_sbm(n_comm=8, comm_size=256, steps=200)
+    with make(w, "f64") as k:
+        k.step_rk4(w.dt, 200)
+        th = k.get_phases()
+        dev = math.fsum(th - w.theta0 - 200 * w.dt * w.omega) / w.graph.n
+        assert abs(dev) < 1e-11
+        k.set_params(np.zeros(w.graph.n), w.K)
+        k.set_phases(np.full(w.graph.n, 0.3))
+        F = k.eval_rhs()
+        assert np.abs(F).max() < 1e-12
+        k.step_rk4(w.dt, 50)
+        assert np.abs(k.get_phases() - 0.3).max() < 1e-12
+
+
+def test_order_parameter_samples(need_gpu):
+    w = small_sbm(n_comm=4, comm_size=256, steps=100)
+    with make(w, "f64") as k:
+        r, psi = k.step_rk4(w.dt, 100, r_every=10)
+        r1, psi1 = k.order_parameter()
+    tho, ro, psio = oracle.rk4(w.graph, w.omega, w.K, w.theta0, w.dt, 100, r_every=10)
+    assert len(r) == 11
+    assert np.abs(r - ro).max() < 1e-12
+    assert np.abs(wrap(psi - psio)).max() < 1e-10
+    assert abs(r1 - ro[-1]) < 1e-12
+
+
+def test_eval_at_given_theta(need_gpu):
+    w = small_sbm(n_comm=4, comm_size=256, steps=1)
+    rng = np.random.default_rng(4)
+    th = rng.uniform(-50, 50, w.graph.n)
+    with make(w, "f64") as k:
+        F = k.eval_rhs(th)
+    assert rel_err(F, oracle.rhs(w.graph, w.omega, w.K, th)) < 1e-12
+
+
+def test_config2_full_size_sampled_rows(need_gpu):
+    """N = 65536 = 64 x 1024, rho 0.97, p_out 2e-4: FP64 and FP32 right-hand side on a seeded
+    1/64 subsample of rows at theta0 and at a partially synchronised state; conservation over
+    100 steps."""
+    w = gen.sbm_equal()
+    g = w.graph
+    rows = np.sort(np.random.default_rng(0).choice(g.n, g.n // 64, replace=False))
+    rng = np.random.default_rng(5)
+    th_sync = (g.labels * 0.7 + 0.1 * rng.standard_normal(g.n))
+    for dtype in ("f64", "f32"):
+        with make(w, dtype) as k:
+            for th in (w.theta0, th_sync):
+                thx = th if dtype == "f64" else f32(th)
+                F = k.eval_rhs(thx)
+                Fo = oracle.rhs_rows(g, w.omega, w.K, thx, rows)
+                if dtype == "f64":
+                    assert np.abs(F[rows] - Fo).max() < 1e-12 * np.abs(Fo).max()
+                else:
+                    bound = fp32_rhs_bound(k, w, thx)[rows]
+                    assert np.all(np.abs(F[rows] - Fo) <= bound)
+            if dtype == "f64":
+                k.step_rk4(w.dt, 100)
+                th = k.get_phases()
+                dev = math.fsum(th - w.theta0 - 100 * w.dt * w.omega) / g.n
+                assert abs(dev) < 1e-10
