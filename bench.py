@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the graph-Kuramoto hot path on one MI355X.
+
+A step is one classical RK4 step (four right-hand-side evaluations with localised order
+parameters, list and inter-community gathers, the fused stage updates and the compensated phase
+update) over the whole graph, with every input resident in HBM before the timed region.
+
+Default workload: heterogeneous stochastic block model, N = 2^20, power-law community sizes in
+[256, 16384], intra densities U[0.3, 1], cross-community Erdos-Renyi edges of mean degree 8,
+omega ~ Cauchy(0, 0.5), K = 3, dt = 0.005, FP32 (seeded synthetic input).
+
+Prints one JSON line with the throughput, the roofline of the dominant kernel (the row kernel,
+timed live with HIP events on its own stream) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RK4 steps/s and RHS evals/s at N=2^20 (fraction of HBM roofline); adjoint/fwd ratio"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2102_07167_amd", "csrc", "kur_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rows_kernel_traffic.json")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes_per_eval(info: dict, elem: int) -> int:
+    """Bytes one right-hand-side evaluation must move: the stored index lists (2 B per entry,
+    unpadded), the inter-block columns (4 B), the list and inter row offsets (2 x 8 (N+1)),
+    four per-node vectors (theta, the previous stage, omega read; the stage result written) and
+    the block sums."""
+    n, nb = info["n"], info["blocks"]
+    return (2 * info["list_entries"] + 4 * info["inter_entries"] + 16 * (n + 1) + 4 * n * elem
+            + 2 * nb * elem * 4)
+
+
+def make_workload(name: str):
+    import gen
+    if name == "het":
+        return gen.sbm_heterogeneous()
+    if name == "sbm":
+        return gen.sbm_equal()
+    if name == "a2a":
+        return gen.all_to_all()
+    raise SystemExit("unknown workload %s" % name)
+
+
+def workload_desc(name: str, w, info) -> dict:
+    d = {"n": info["n"], "blocks": info["blocks"], "dense_blocks": info["dense_blocks"],
+         "list_entries": info["list_entries"], "inter_entries": info["inter_entries"],
+         "K": w.K, "dt": w.dt, "tau": 0.5}
+    if name == "het":
+        d["workload"] = ("heterogeneous SBM N=2^20: power-law(2) community sizes clipped to [256,16384], "
+                         "intra density U[0.3,1], inter ER mean degree 8, omega~Cauchy(0,0.5), K=3, dt=0.005, "
+                         "seed 1003")
+    elif name == "sbm":
+        d["workload"] = "SBM N=65536 = 64x1024, rho_in 0.97, p_out 2e-4, omega~N(0,1), K=4, dt=0.01, seed 1002"
+    else:
+        d["workload"] = "all-to-all N=512, omega~N(0,1), K=2, dt=0.01, seed 1001"
+    return d
+
+
+def cpu_baseline(w, seconds: float) -> dict:
+    """The FP64 oracle (direct summation) on a seeded 1/64 row sample, extrapolated."""
+    import numpy as np
+    import oracle
+    g = w.graph
+    rows = np.sort(np.random.default_rng(64).choice(g.n, max(1, g.n // 64), replace=False))
+    oracle.rhs_rows(g, w.omega, w.K, w.theta0, rows[:8])  # load and warm
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.rhs_rows(g, w.omega, w.K, w.theta0, rows)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or reps >= 1000:
+            break
+    t_eval = el / reps * (g.n / len(rows))  # extrapolated full evaluation
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / (4.0 * t_eval), "unit": "RK4 steps/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 direct-summation RHS on a seeded 1/64 row sample (%d rows) x%d repeats in %.1f s, "
+                      "extrapolated x%d per RHS and x4 RHS per RK4 step" % (len(rows), reps, el, g.n // len(rows)),
+            "rhs_evals_per_s": 1.0 / t_eval}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="het", choices=["het", "sbm", "a2a"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--option", action="append", default=[], help="library option key=value")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2102_07167_amd import Kuramoto
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    if args.copy_calibration:
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
+    t0 = time.perf_counter()
+    w = make_workload(args.workload)
+    log("workload %s generated in %.1f s (nnz %d)" % (w.name, time.perf_counter() - t0, w.graph.nnz))
+    dtype = "f64" if args.workload == "a2a" else "f32"
+    elem = 8 if dtype == "f64" else 4
+    k = Kuramoto(dtype, device=0)
+    for kv in args.option:
+        key, v = kv.split("=")
+        k.set_option(key, float(v))
+    t0 = time.perf_counter()
+    k.set_graph(w.graph)
+    k.set_params(w.omega, w.K)
+    k.set_phases(w.theta0)
+    info = k.graph_info()
+    log("graph set in %.1f s: %s" % (time.perf_counter() - t0, info))
+
+    k.step_rk4(w.dt, args.warmup)
+    k.sync()
+    torch.cuda.synchronize()
+    log("warmup %d steps done" % args.warmup)
+
+    k.set_option("timing", 1)
+    torch.cuda.synchronize()
+    k.sync()
+    t0 = time.perf_counter()
+    k.step_rk4(w.dt, args.steps)
+    k.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    launches, kms = k.kernel_time()
+    k.set_option("timing", 0)
+    log("timed %d steps in %.3f s; row kernel %d launches, %.3f ms total" % (args.steps, el, launches, kms))
+    r, psi = k.order_parameter()
+    theta = k.get_phases(wrapped=True)
+    assert all(math.isfinite(x) for x in (r, psi)) and bool((abs(theta) <= math.pi + 1e-6).all())
+
+    steps_per_s = args.steps / el
+    avg_ms = kms / max(1, launches)
+    b_eval = algorithmic_bytes_per_eval(info, elem)
+    achieved = b_eval / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            tr = json.load(open(TRAFFIC_FILE))
+            if tr.get("kernel_sha") == kernel_hash() and tr.get("workload") == args.workload:
+                traffic = tr.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    out = {
+        "metric": METRIC,
+        "value": steps_per_s,
+        "unit": "RK4 steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": workload_desc(args.workload, w, info),
+        "rhs_evals_per_s": 4 * steps_per_s,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_rows", "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": b_eval},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, %.0f s budget)" % args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    k.close()
+
+
+if __name__ == "__main__":
+    main()

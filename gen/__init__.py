@@ -54,7 +54,7 @@ def _load():
         lib.kg_sbm_degrees.restype = None
         lib.kg_sbm_degrees.argtypes = [i64, P, i64, P, u64, P, P, P, P, P]
         lib.kg_sbm_fill.restype = None
-        lib.kg_sbm_fill.argtypes = [i64, P, i64, P, u64, P, P, P, P, P, P, P]
+        lib.kg_sbm_fill.argtypes = [i64, P, i64, P, u64, P, P, P, P, P, P, P, P]
         lib.kg_intra_edge.restype = ctypes.c_int
         lib.kg_intra_edge.argtypes = [u64, i64, ctypes.c_uint32, ctypes.c_uint32, f64]
         _lib = lib
@@ -149,8 +149,10 @@ def sbm(sizes, rho, p_out: float, key: int, uperm: np.ndarray | None = None) -> 
     col = np.empty(max(int(row_ptr[-1]), 1), dtype=np.int32)
     soff = np.zeros(n + 1, dtype=np.int64)
     snbr = np.zeros(max(2 * ne, 1), dtype=np.int64)
-    lib.kg_sbm_fill(n, _p(cptr), nc, _p(rho), key, _p(ioff), _p(iq), _p(uperm), _p(row_ptr),
-                    _p(col), _p(soff), _p(snbr))
+    by_user = np.concatenate([np.argsort(uperm[cptr[c]:cptr[c + 1]], kind="stable").astype(np.int32)
+                              for c in range(nc)])
+    lib.kg_sbm_fill(n, _p(cptr), nc, _p(rho), key, _p(ioff), _p(iq), _p(uperm), _p(by_user),
+                    _p(row_ptr), _p(col), _p(soff), _p(snbr))
     labels = np.empty(n, dtype=np.int32)
     labels[uperm] = np.repeat(np.arange(nc, dtype=np.int32), sizes)
     return Graph(n=n, labels=labels, row_ptr=row_ptr, col=col[: int(row_ptr[-1])], sizes=sizes,

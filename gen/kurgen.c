@@ -145,11 +145,14 @@ void kg_sbm_degrees(int64_t n, const int64_t *cptr, int64_t nc, const double *rh
 /*
  * Fill the USER-order CSR: row_ptr (n+1, prefix of deg_user, computed by the caller) and col
  * (user indices, ascending per row). sym_off (n+1) and sym_nbr (2*E) are caller scratch that
- * receive the inter edges in symmetric planted CSR form.
+ * receive the inter edges in symmetric planted CSR form. by_user (n) holds, for every
+ * community, its local indices ordered by user index, so intra neighbours come out sorted and
+ * only the few inter neighbours need sorting and a merge.
  */
 void kg_sbm_fill(int64_t n, const int64_t *cptr, int64_t nc, const double *rho, uint64_t seed,
                  const int64_t *inter_off, const int64_t *inter_q, const int32_t *uperm,
-                 const int64_t *row_ptr, int32_t *col, int64_t *sym_off, int64_t *sym_nbr)
+                 const int32_t *by_user, const int64_t *row_ptr, int32_t *col, int64_t *sym_off,
+                 int64_t *sym_nbr)
 {
     /* symmetric planted CSR of the inter edges */
     memset(sym_off, 0, sizeof(int64_t) * (size_t)(n + 1));
@@ -170,19 +173,35 @@ void kg_sbm_fill(int64_t n, const int64_t *cptr, int64_t nc, const double *rho, 
             }
         free(fill);
     }
-#pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t p = 0; p < n; ++p) {
-        int64_t c = comm_of(cptr, nc, p);
-        uint64_t kc = comm_key(seed, c);
-        int64_t s = cptr[c + 1] - cptr[c], i = p - cptr[c];
-        int32_t u = uperm[p];
-        int32_t *out = col + row_ptr[u];
-        int64_t k = 0;
-        if (rho[c] > 0.0)
-            for (int64_t j = 0; j < s; ++j)
-                if (j != i && (rho[c] >= 1.0 || intra_edge(kc, (uint32_t)i, (uint32_t)j, rho[c])))
-                    out[k++] = uperm[cptr[c] + j];
-        for (int64_t e = sym_off[p]; e < sym_off[p + 1]; ++e) out[k++] = uperm[sym_nbr[e]];
-        qsort(out, (size_t)k, sizeof(int32_t), cmp_i32);
+#pragma omp parallel
+    {
+        int32_t *ibuf = NULL;
+        int64_t icap = 0;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t p = 0; p < n; ++p) {
+            int64_t c = comm_of(cptr, nc, p);
+            uint64_t kc = comm_key(seed, c);
+            int64_t s = cptr[c + 1] - cptr[c], i = p - cptr[c];
+            int64_t ni = sym_off[p + 1] - sym_off[p];
+            if (ni > icap) {
+                icap = 2 * ni + 16;
+                ibuf = (int32_t *)realloc(ibuf, sizeof(int32_t) * (size_t)icap);
+            }
+            for (int64_t e = 0; e < ni; ++e) ibuf[e] = uperm[sym_nbr[sym_off[p] + e]];
+            qsort(ibuf, (size_t)ni, sizeof(int32_t), cmp_i32);
+            int32_t *out = col + row_ptr[uperm[p]];
+            const int32_t *ord = by_user + cptr[c];
+            int64_t k = 0, e = 0;
+            if (rho[c] > 0.0)
+                for (int64_t t = 0; t < s; ++t) {
+                    int64_t j = ord[t];
+                    if (j == i || !(rho[c] >= 1.0 || intra_edge(kc, (uint32_t)i, (uint32_t)j, rho[c]))) continue;
+                    int32_t v = uperm[cptr[c] + j];
+                    while (e < ni && ibuf[e] < v) out[k++] = ibuf[e++];
+                    out[k++] = v;
+                }
+            while (e < ni) out[k++] = ibuf[e++];
+        }
+        free(ibuf);
     }
 }

@@ -81,6 +81,9 @@ const char *kur_last_error(const kur_ctx *ctx);
  *                 64). Default 8192 (FP32), 4096 (FP64).
  *   "tile_rows"   maximal rows per work tile (64..4096). Default 1024 (FP32), 512 (FP64).
  *   "tiles"       target number of work tiles (>= 1). Default 4096.
+ *   "flat_min_vec" rows of a tile averaging at least this many 8-entry list vectors per chunk
+ *                 are streamed one contiguous run per wavefront; shorter rows get a group of
+ *                 lanes each. 0 disables streaming. Default 8.
  *   "scaling"     0: K/N (uniform, default); 1: K/deg_m (non-uniform). Immediate.
  *   "compensate"  1: compensated phase update with winding (default); 0: plain update. Immediate.
  *   "timing"      1: time every launch of the row kernel with HIP events (see kur_kernel_time).

@@ -255,6 +255,7 @@ std::string finish(BlockGraph &g, const std::vector<int32_t> &block_of_row, cons
             double avg = nonempty ? (double)vec / ((double)(r1 - r) * (double)nonempty) : 0.0;
             int32_t G = 2;
             while (G < 64 && G * 2 < avg) G *= 2;
+            if (opt.flat_min_vec > 0 && avg >= opt.flat_min_vec) G = 0;  // wave-streaming mode
             g.tiles.push_back(Tile{bi, r, r1, G});
             tcost.push_back(c + (int64_t)b.size * nonempty / 4);
             r = r1;

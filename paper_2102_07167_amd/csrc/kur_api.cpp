@@ -451,6 +451,9 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
         int64_t t = (int64_t)v;
         if ((double)t != v || t < 1 || t > (int64_t)1 << 24) return fail(c, KUR_EINVAL, "tiles must be an integer in [1, 2^24]");
         c->bopt.tiles_target = t;
+    } else if (k == "flat_min_vec") {
+        if (v < 0.0 || v > 1e6) return fail(c, KUR_EINVAL, "flat_min_vec must be in [0, 1e6]");
+        c->bopt.flat_min_vec = v;
     } else if (k == "threads") {
         if (v != 256 && v != 512 && v != 1024) return fail(c, KUR_EINVAL, "threads must be 256, 512 or 1024");
         if (c->has_graph && rows_lds_bytes(c->esz, c->W, c->tile_rows, (int)v) > 160 * 1024)

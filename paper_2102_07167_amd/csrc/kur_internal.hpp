@@ -20,7 +20,8 @@ struct BlkInfo {
     int32_t ntiles;
 };
 
-// One unit of work: rows [r0, r1) (block-local) of one block, G lanes per row.
+// One unit of work: rows [r0, r1) (block-local) of one block, G lanes per row (G == 0: each
+// wave streams a contiguous run of the tile's rows).
 struct Tile {
     int32_t block;
     int32_t r0;
@@ -33,6 +34,7 @@ struct BuildOptions {
     int32_t W = 8192;        // chunk width (columns staged in LDS at a time)
     int32_t tile_rows = 1024;
     int64_t tiles_target = 4096;
+    double flat_min_vec = 8.0;  // rows averaging at least this many 8-entry vectors: wave streaming
 };
 
 // The graph in block order, ready for upload.

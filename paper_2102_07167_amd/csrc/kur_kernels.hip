@@ -172,11 +172,17 @@ __global__ __launch_bounds__(NT) void k_rows(DevGraph g, RowArgs<T> a)
     }
     __syncthreads();  // accumulators, pad slot and block sums visible to every wave
 
-    const int G = tl.G;
+    // G > 0: G lanes per row (short rows); G == 0: every wave streams a contiguous run of rows
+    const bool flat = tl.G == 0;
+    const int G = flat ? 8 : tl.G;
     const int lane = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int ngrp = NT / G;
     const T sign = bi.mode ? T(-1) : T(1);
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int ra = (int)(((int64_t)nrows * wv) / (NT / 64));
+    const int rb = (int)(((int64_t)nrows * (wv + 1)) / (NT / 64));
+    const uint32_t padw = (uint32_t)W | ((uint32_t)W << 16);
 
     for (int c = 0; c < bi.nchunk; ++c) {
         const int64_t sb = bi.segbase + (int64_t)c * bi.size;
@@ -187,49 +193,115 @@ __global__ __launch_bounds__(NT) void k_rows(DevGraph g, RowArgs<T> a)
         __syncthreads();  // previous chunk's gathers are done
         for (int j = threadIdx.x; j < cw; j += NT) lds_sc[j] = sc_in[bi.row0 + c0 + j];
         __syncthreads();
-        for (int r = grp; r < nrows; r += ngrp) {
-            const int64_t s0 = g.seg_ptr[sb + tl.r0 + r], s1 = g.seg_ptr[sb + tl.r0 + r + 1];
-            const u32x4 *__restrict__ p = reinterpret_cast<const u32x4 *>(g.list + s0);
-            const int nv = (int)((s1 - s0) >> 3);
-            T xs = T(0), xc = T(0);
-            int v = lane;
-            for (; v + G < nv; v += 2 * G) {
-                const u32x4 q0 = __builtin_nontemporal_load(p + v);
-                const u32x4 q1 = __builtin_nontemporal_load(p + v + G);
-                const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        if (flat) {
+            // rows [ra, rb) of this wave occupy the contiguous vectors [va, vb) of the chunk
+            const int64_t *__restrict__ sp = g.seg_ptr + sb + tl.r0;
+            const int64_t va = sp[ra] >> 3, vb = sp[rb] >> 3;
+            if (va < vb) {
+                const u32x4 *__restrict__ L = reinterpret_cast<const u32x4 *>(g.list);
+                int r = ra;
+                int64_t nbnd = sp[r + 1] >> 3;  // first vector after row r
+                T as = T(0), ac = T(0);
+                constexpr int U = 4;
+                u32x4 q[U];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const T2 t0 = lds_sc[w[k] & 0xffffu];
-                    const T2 t1 = lds_sc[w[k] >> 16];
-                    xs += t0.x;
-                    xc += t0.y;
-                    xs += t1.x;
-                    xc += t1.y;
+                for (int j = 0; j < U; ++j) {
+                    const int64_t vi = va + 64 * j + ln;
+                    q[j] = vi < vb ? __builtin_nontemporal_load(L + vi) : u32x4{padw, padw, padw, padw};
+                }
+                for (int64_t base = va; base < vb; base += 64 * U) {
+                    u32x4 qn[U];
+#pragma unroll
+                    for (int j = 0; j < U; ++j) {
+                        const int64_t vi = base + 64 * (U + j) + ln;
+                        qn[j] = vi < vb ? __builtin_nontemporal_load(L + vi) : u32x4{padw, padw, padw, padw};
+                    }
+#pragma unroll
+                    for (int j = 0; j < U; ++j) {
+                        const uint32_t w4[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
+                        T ps = T(0), pc = T(0);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const T2 t0 = lds_sc[w4[k] & 0xffffu];
+                            const T2 t1 = lds_sc[w4[k] >> 16];
+                            ps += t0.x;
+                            pc += t0.y;
+                            ps += t1.x;
+                            pc += t1.y;
+                        }
+                        const int64_t s0 = base + 64 * j;
+                        const int64_t vi = s0 + ln;
+                        // rows ending inside (or right at the end of) this 64-vector span
+                        while (nbnd <= s0 + 64 && r < rb) {
+                            if (vi < nbnd) {
+                                as += ps;
+                                ac += pc;
+                                ps = T(0);
+                                pc = T(0);
+                            }
+                            const T ts = wave_sum(as), tc = wave_sum(ac);
+                            if (ln == 0) {
+                                acc_s[r] += sign * ts;
+                                acc_c[r] += sign * tc;
+                            }
+                            as = T(0);
+                            ac = T(0);
+                            ++r;
+                            nbnd = r < rb ? (sp[r + 1] >> 3) : INT64_MAX;
+                        }
+                        as += ps;
+                        ac += pc;
+                        q[j] = qn[j];
+                    }
                 }
             }
-            if (v < nv) {
-                const u32x4 q0 = __builtin_nontemporal_load(p + v);
-                const uint32_t w[4] = {q0.x, q0.y, q0.z, q0.w};
+        } else {
+            for (int r = grp; r < nrows; r += ngrp) {
+                const int64_t s0 = g.seg_ptr[sb + tl.r0 + r], s1 = g.seg_ptr[sb + tl.r0 + r + 1];
+                const u32x4 *__restrict__ p = reinterpret_cast<const u32x4 *>(g.list + s0);
+                const int nv = (int)((s1 - s0) >> 3);
+                T xs = T(0), xc = T(0);
+                int v = lane;
+                for (; v + G < nv; v += 2 * G) {
+                    const u32x4 q0 = __builtin_nontemporal_load(p + v);
+                    const u32x4 q1 = __builtin_nontemporal_load(p + v + G);
+                    const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const T2 t0 = lds_sc[w[k] & 0xffffu];
-                    const T2 t1 = lds_sc[w[k] >> 16];
-                    xs += t0.x;
-                    xc += t0.y;
-                    xs += t1.x;
-                    xc += t1.y;
+                    for (int k = 0; k < 8; ++k) {
+                        const T2 t0 = lds_sc[w[k] & 0xffffu];
+                        const T2 t1 = lds_sc[w[k] >> 16];
+                        xs += t0.x;
+                        xc += t0.y;
+                        xs += t1.x;
+                        xc += t1.y;
+                    }
                 }
-            }
-            xs = group_sum(xs, G);
-            xc = group_sum(xc, G);
-            if (lane == 0) {
-                acc_s[r] += sign * xs;
-                acc_c[r] += sign * xc;
+                if (v < nv) {
+                    const u32x4 q0 = __builtin_nontemporal_load(p + v);
+                    const uint32_t w[4] = {q0.x, q0.y, q0.z, q0.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const T2 t0 = lds_sc[w[k] & 0xffffu];
+                        const T2 t1 = lds_sc[w[k] >> 16];
+                        xs += t0.x;
+                        xc += t0.y;
+                        xs += t1.x;
+                        xc += t1.y;
+                    }
+                }
+                xs = group_sum(xs, G);
+                xc = group_sum(xc, G);
+                if (lane == 0) {
+                    acc_s[r] += sign * xs;
+                    acc_c[r] += sign * xc;
+                }
             }
         }
     }
 
-    // edges between blocks: straightforward summation from the global table
+    // edges between blocks: straightforward summation from the global table. In streaming mode
+    // another wave owns the row's accumulator above, so wait for those updates first.
+    if (flat) __syncthreads();
     for (int r = grp; r < nrows; r += ngrp) {
         const int m = rowbase + r;
         const int64_t e0 = g.inter_ptr[m], e1 = g.inter_ptr[m + 1];

@@ -85,9 +85,10 @@ def small_sbm(seed=21, n_comm=8, comm_size=512, steps=1000, **kw):
                          steps=steps, seed=seed, **kw)
 
 
-def test_sbm_fp64_rhs_and_trajectory(need_gpu):
+@pytest.mark.parametrize("flat", [0.1, 8.0])
+def test_sbm_fp64_rhs_and_trajectory(need_gpu, flat):
     w = small_sbm()
-    with make(w, "f64") as k:
+    with make(w, "f64", flat_min_vec=flat) as k:
         F = k.eval_rhs()
         Fo = oracle.rhs(w.graph, w.omega, w.K, w.theta0)
         assert rel_err(F, Fo) < 1e-12
@@ -97,11 +98,12 @@ def test_sbm_fp64_rhs_and_trajectory(need_gpu):
     assert np.abs(wrap(th - tho)).max() < 1e-12 * max(1.0, np.abs(tho).max())
 
 
-def test_sbm_fp32_trajectory_1000_steps(need_gpu):
+@pytest.mark.parametrize("flat", [0.1, 8.0])
+def test_sbm_fp32_trajectory_1000_steps(need_gpu, flat):
     w = small_sbm()
     om, th0, Kf, dtf = f32(w.omega), f32(w.theta0), float(np.float32(w.K)), float(np.float32(w.dt))
     w.omega, w.theta0, w.K = om, th0, Kf
-    with make(w, "f32") as k:
+    with make(w, "f32", flat_min_vec=flat) as k:
         k.step_rk4(dtf, w.steps)
         th = k.get_phases()
         thw = k.get_phases(wrapped=True)
@@ -114,7 +116,9 @@ def test_sbm_fp32_trajectory_1000_steps(need_gpu):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("opts", [dict(chunk=64, tile_rows=64), dict(tau=0.0, chunk=128), dict(tau=1.0),
-                                  dict(threads=256, tile_rows=128), dict(threads=1024)])
+                                  dict(threads=256, tile_rows=128), dict(threads=1024),
+                                  dict(flat_min_vec=0.1, chunk=128, tile_rows=64), dict(flat_min_vec=0.1, tau=0.0),
+                                  dict(flat_min_vec=0)])
 def test_ragged_layouts(need_gpu, dtype, opts):
     """Odd block sizes, several chunks per block, several tiles per block, all-dense and
     all-sparse evaluation, a size-1 block and a complete block."""
