@@ -77,9 +77,9 @@ const char *kur_last_error(const kur_ctx *ctx);
  *   "tau"         density threshold: a diagonal block whose realised density is >= tau is
  *                 evaluated with localised order parameters (list of zeros), otherwise with its
  *                 list of ones. Default 0.5 (Sec. 3: precompute when ones outnumber zeros).
- *   "chunk"       columns of a diagonal block staged in LDS at a time (64..32768, multiple of
- *                 64). Default 8192 (FP32), 4096 (FP64).
- *   "tile_rows"   maximal rows per work tile (64..4096). Default 1024 (FP32), 512 (FP64).
+ *   "chunk"       columns of a diagonal block staged in LDS at a time: a multiple of 64, at
+ *                 most 8128 (FP32) or 4032 (FP64). Default 4096 (FP32), 2048 (FP64).
+ *   "tile_rows"   maximal rows per work tile (64..4096). Default 256.
  *   "tiles"       target number of work tiles (>= 1). Default 4096.
  *   "flat_min_vec" rows of a tile averaging at least this many 8-entry list vectors per chunk
  *                 are streamed one contiguous run per wavefront; shorter rows get a group of

@@ -7,10 +7,10 @@
 //    of zero entries when the realised density is at least tau, straightforward summation over
 //    the list of one entries otherwise (Sec. 3, eq. KuramotoGraphApproach and the density rule
 //    of the introduction).
-// 3. Store the lists as 16-bit column offsets relative to a chunk of W columns, chunk-major
-//    inside a block, every (row, chunk) segment padded to a multiple of 8 entries with the
-//    index W (an all-zero slot), so that a kernel reads them with aligned 16-byte loads while
-//    the chunk's (sin, cos) values sit in LDS.
+// 3. Store the lists as 16-bit LDS byte offsets (column relative to a chunk of W columns, times
+//    the size of a staged (sin, cos) pair), chunk-major inside a block, every (row, chunk)
+//    segment padded to a multiple of 8 entries with the offset of slot W (all zero), so that a
+//    kernel reads them with aligned 16-byte loads while the chunk's values sit in LDS.
 // 4. All edges between blocks go to a CSR list with block-order columns.
 // 5. Cut every block into work tiles of similar cost and choose the lanes per row.
 #include <algorithm>
@@ -91,6 +91,8 @@ std::string finish(BlockGraph &g, const std::vector<int32_t> &block_of_row, cons
     const int32_t W = opt.W;
     g.W = W;
     g.tile_rows = opt.tile_rows;
+    g.esz2 = opt.esz2;
+    if ((int64_t)W * opt.esz2 > 65535) return "chunk too wide for 16-bit LDS byte offsets";
     int32_t smax = 0;
     for (auto &b : g.blk) smax = std::max(smax, b.size);
     const int64_t words = (smax + 63) / 64 + 1;
@@ -198,11 +200,11 @@ std::string finish(BlockGraph &g, const std::vector<int32_t> &block_of_row, cons
                     while (x) {
                         int t = __builtin_ctzll(x);
                         x &= x - 1;
-                        out[k++] = (uint16_t)(wb + t - c0);
+                        out[k++] = (uint16_t)((wb + t - c0) * opt.esz2);
                     }
                 }
                 int64_t padded = g.seg_ptr[idx + 1] - g.seg_ptr[idx];
-                for (; k < padded; ++k) out[k] = (uint16_t)W;
+                for (; k < padded; ++k) out[k] = (uint16_t)(W * opt.esz2);
             }
             src.clear(m, bits.data());
             tmp.clear();

@@ -384,9 +384,12 @@ kur_status kur_create(kur_ctx **out, kur_dtype dtype, int device, void *hip_stre
     if (!c) return KUR_ENOMEM;
     c->dtype = dtype;
     c->esz = dtype == KUR_F32 ? 4 : 8;
+    c->bopt.W = 4096;
+    c->bopt.tile_rows = 256;
+    c->bopt.esz2 = 8;
     if (dtype == KUR_F64) {
-        c->bopt.W = 4096;
-        c->bopt.tile_rows = 512;
+        c->bopt.W = 2048;
+        c->bopt.esz2 = 16;
     }
     c->device = device;
     c->host_only = device < 0;
@@ -441,7 +444,8 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
         c->bopt.tau = v;
     } else if (k == "chunk") {
         int64_t w = (int64_t)v;
-        if ((double)w != v || w < 64 || w > 32768 || w % 64) return fail(c, KUR_EINVAL, "chunk must be a multiple of 64 in [64, 32768]");
+        if ((double)w != v || w < 64 || w % 64 || w * c->bopt.esz2 > 65535)
+            return fail(c, KUR_EINVAL, "chunk must be a multiple of 64 in [64, 65535 / pair bytes] (8128 FP32, 4032 FP64)");
         c->bopt.W = (int32_t)w;
     } else if (k == "tile_rows") {
         int64_t t = (int64_t)v;
@@ -558,10 +562,10 @@ kur_status kur_get_row_lists(const kur_ctx *c, int64_t row, int32_t *list, int64
     for (int32_t ch = 0; ch < bi.nchunk; ++ch) {
         const int64_t idx = bi.segbase + (int64_t)ch * bi.size + r;
         for (int64_t e = g.seg_ptr[idx]; e < g.seg_ptr[idx + 1]; ++e) {
-            if (g.list[e] == (uint16_t)g.W) continue;  // padding
+            if (g.list[e] == (uint16_t)(g.W * g.esz2)) continue;  // padding
             if (list) {
                 if (k >= *nlist) return KUR_EINVAL;
-                list[k] = (int32_t)ch * g.W + g.list[e];
+                list[k] = (int32_t)ch * g.W + g.list[e] / g.esz2;
             }
             ++k;
         }

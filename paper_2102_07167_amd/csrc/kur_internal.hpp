@@ -35,6 +35,8 @@ struct BuildOptions {
     int32_t tile_rows = 1024;
     int64_t tiles_target = 4096;
     double flat_min_vec = 8.0;  // rows averaging at least this many 8-entry vectors: wave streaming
+    int32_t esz2 = 8;           // bytes of one staged (sin, cos) pair; list entries are LDS byte
+                                // offsets col * esz2, so W * esz2 must stay below 65536
 };
 
 // The graph in block order, ready for upload.
@@ -43,10 +45,12 @@ struct BlockGraph {
     int32_t nb = 0;
     int32_t W = 0;
     int32_t tile_rows = 0;
+    int32_t esz2 = 8;
     std::vector<int32_t> perm;        // user node -> block-order row
     std::vector<BlkInfo> blk;
     std::vector<int64_t> seg_ptr;     // total segments + 1 (chunk-major inside every block)
-    std::vector<uint16_t> list;       // chunk-relative column, segments padded to 8 entries
+    std::vector<uint16_t> list;       // chunk-relative LDS byte offset (col * esz2), segments
+                                      // padded to 8 entries with W * esz2 (the zero slot)
     std::vector<int64_t> inter_ptr;   // n + 1, block order
     std::vector<int32_t> inter_col;   // block-order columns
     std::vector<Tile> tiles;

@@ -46,10 +46,80 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
-template <typename T> __device__ __forceinline__ T group_sum(T v, int G)
+// Cross-lane moves with DPP (VALU only, no LDS traffic). Rows are the 16-lane DPP rows of a
+// wave64; lanes of disabled rows receive 0.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp_mov(float x)
 {
-    for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_mov(double x)
+{
+    const int2 v = __builtin_bit_cast(int2, x);
+    int2 o;
+    o.x = __builtin_amdgcn_update_dpp(0, v.x, CTRL, ROWS, 0xf, false);
+    o.y = __builtin_amdgcn_update_dpp(0, v.y, CTRL, ROWS, 0xf, false);
+    return __builtin_bit_cast(double, o);
+}
+
+enum : int {
+    DPP_XOR1 = 0xB1,        // quad_perm [1,0,3,2]
+    DPP_XOR2 = 0x4E,        // quad_perm [2,3,0,1]
+    DPP_HALF_MIRROR = 0x141,
+    DPP_MIRROR = 0x140,
+    DPP_BCAST15 = 0x142,
+    DPP_BCAST31 = 0x143,
+};
+
+// Sum over aligned groups of G lanes (G a power of two, 2..64) in a fixed order; the result is
+// valid in the last lane of every group (for G <= 16 in every lane of the group).
+template <typename T>
+__device__ __forceinline__ T group_sum_dpp(T v, int G)
+{
+    v += dpp_mov<DPP_XOR1>(v);
+    if (G >= 4) v += dpp_mov<DPP_XOR2>(v);
+    if (G >= 8) v += dpp_mov<DPP_HALF_MIRROR>(v);
+    if (G >= 16) v += dpp_mov<DPP_MIRROR>(v);
+    if (G >= 32) v += dpp_mov<DPP_BCAST15, 0xa>(v);
+    if (G >= 64) v += dpp_mov<DPP_BCAST31, 0xc>(v);
     return v;
+}
+
+// Sum over the whole wave; valid in lane 63.
+template <typename T>
+__device__ __forceinline__ T wave_sum_dpp(T v)
+{
+    v += dpp_mov<DPP_XOR1>(v);
+    v += dpp_mov<DPP_XOR2>(v);
+    v += dpp_mov<DPP_HALF_MIRROR>(v);
+    v += dpp_mov<DPP_MIRROR>(v);
+    v += dpp_mov<DPP_BCAST15, 0xa>(v);
+    v += dpp_mov<DPP_BCAST31, 0xc>(v);
+    return v;
+}
+
+// LDS gather of the (sin, cos) pair at a byte offset into the staged chunk
+template <typename T2>
+__device__ __forceinline__ T2 lds_at(const T2 *base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const T2 *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+// Accumulate the 8 list entries of one 16-byte vector (two 16-bit byte offsets per dword).
+template <typename T, typename T2>
+__device__ __forceinline__ void gather8(const T2 *lds, const u32x4 q, T &xs, T &xc)
+{
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const T2 t0 = lds_at(lds, w[k] & 0xffffu);
+        const T2 t1 = lds_at(lds, w[k] >> 16);
+        xs += t0.x;
+        xc += t0.y;
+        xs += t1.x;
+        xc += t1.y;
+    }
 }
 
 // Sum v over the workgroup in a fixed order and store it to *out (thread 0).
@@ -125,7 +195,7 @@ template <typename T> __device__ __forceinline__ void two_sum(T a, T b, T &s, T 
 }
 
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_rows(DevGraph g, RowArgs<T> a)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_rows(DevGraph g, RowArgs<T> a)
 {
     using T2 = typename V2<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -134,6 +204,7 @@ __global__ __launch_bounds__(NT) void k_rows(DevGraph g, RowArgs<T> a)
     T *acc_s = reinterpret_cast<T *>(lds_sc + W + 1);          // tile_rows
     T *acc_c = acc_s + g.tile_rows;                            // tile_rows
     T2 *red = reinterpret_cast<T2 *>(acc_c + g.tile_rows);     // NT/64 + 1
+    int *bnd = reinterpret_cast<int *>(red + NT / 64 + 1);     // tile_rows + 1 row starts (vectors)
 
     const int tile_id = g.order[blockIdx.x];
     const Tile tl = g.tiles[tile_id];
@@ -179,10 +250,11 @@ __global__ __launch_bounds__(NT) void k_rows(DevGraph g, RowArgs<T> a)
     const int grp = threadIdx.x / G;
     const int ngrp = NT / G;
     const T sign = bi.mode ? T(-1) : T(1);
-    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int ln = threadIdx.x & 63;
+    // this wave's rows [ra, rb) in streaming mode (wave-uniform, kept in scalar registers)
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ra = (int)(((int64_t)nrows * wv) / (NT / 64));
     const int rb = (int)(((int64_t)nrows * (wv + 1)) / (NT / 64));
-    const uint32_t padw = (uint32_t)W | ((uint32_t)W << 16);
 
     for (int c = 0; c < bi.nchunk; ++c) {
         const int64_t sb = bi.segbase + (int64_t)c * bi.size;
@@ -192,106 +264,83 @@ __global__ __launch_bounds__(NT) void k_rows(DevGraph g, RowArgs<T> a)
         const int cw = min(W, bi.size - c0);
         __syncthreads();  // previous chunk's gathers are done
         for (int j = threadIdx.x; j < cw; j += NT) lds_sc[j] = sc_in[bi.row0 + c0 + j];
+        // row starts of this chunk, in 8-entry vectors relative to the tile's first one
+        for (int r = threadIdx.x; r <= nrows; r += NT) bnd[r] = (int)((g.seg_ptr[sb + tl.r0 + r] - e0) >> 3);
         __syncthreads();
+        const u32x4 *__restrict__ Lt = reinterpret_cast<const u32x4 *>(g.list + e0);
         if (flat) {
-            // rows [ra, rb) of this wave occupy the contiguous vectors [va, vb) of the chunk
-            const int64_t *__restrict__ sp = g.seg_ptr + sb + tl.r0;
-            const int64_t va = sp[ra] >> 3, vb = sp[rb] >> 3;
-            if (va < vb) {
-                const u32x4 *__restrict__ L = reinterpret_cast<const u32x4 *>(g.list);
+            // rows [ra, rb) occupy the contiguous 8-entry vectors [va, va + nvec) of this chunk
+            const int va = __builtin_amdgcn_readfirstlane(bnd[ra]);
+            const int nvec = __builtin_amdgcn_readfirstlane(bnd[rb]) - va;
+            if (nvec > 0) {
+                const u32x4 *__restrict__ L = Lt + va;
                 int r = ra;
-                int64_t nbnd = sp[r + 1] >> 3;  // first vector after row r
+                int nbnd = __builtin_amdgcn_readfirstlane(bnd[r + 1]) - va;  // first vector after row r
                 T as = T(0), ac = T(0);
-                constexpr int U = 4;
-                u32x4 q[U];
-#pragma unroll
-                for (int j = 0; j < U; ++j) {
-                    const int64_t vi = va + 64 * j + ln;
-                    q[j] = vi < vb ? __builtin_nontemporal_load(L + vi) : u32x4{padw, padw, padw, padw};
-                }
-                for (int64_t base = va; base < vb; base += 64 * U) {
-                    u32x4 qn[U];
-#pragma unroll
-                    for (int j = 0; j < U; ++j) {
-                        const int64_t vi = base + 64 * (U + j) + ln;
-                        qn[j] = vi < vb ? __builtin_nontemporal_load(L + vi) : u32x4{padw, padw, padw, padw};
+                // rolling prefetch: four 64-vector spans in flight per wave; loads are issued
+                // unconditionally (index clamped) so the in-order wait counts stay exact, and
+                // lanes past the end are masked after the gather
+                const uint32_t last = (uint32_t)(nvec - 1);
+                u32x4 q0 = __builtin_nontemporal_load(L + min((uint32_t)ln, last));
+                u32x4 q1 = __builtin_nontemporal_load(L + min((uint32_t)(64 + ln), last));
+                u32x4 q2 = __builtin_nontemporal_load(L + min((uint32_t)(128 + ln), last));
+                u32x4 q3 = __builtin_nontemporal_load(L + min((uint32_t)(192 + ln), last));
+                auto span = [&](const u32x4 q, const int s0) {
+                    T ps = T(0), pc = T(0);
+                    gather8<T, T2>(lds_sc, q, ps, pc);
+                    if (s0 + ln >= nvec) {
+                        ps = T(0);
+                        pc = T(0);
                     }
-#pragma unroll
-                    for (int j = 0; j < U; ++j) {
-                        const uint32_t w4[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
-                        T ps = T(0), pc = T(0);
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const T2 t0 = lds_sc[w4[k] & 0xffffu];
-                            const T2 t1 = lds_sc[w4[k] >> 16];
-                            ps += t0.x;
-                            pc += t0.y;
-                            ps += t1.x;
-                            pc += t1.y;
+                    // rows that end inside (or right at the end of) this span
+                    while (nbnd <= s0 + 64 && r < rb) {
+                        if (s0 + ln < nbnd) {
+                            as += ps;
+                            ac += pc;
+                            ps = T(0);
+                            pc = T(0);
                         }
-                        const int64_t s0 = base + 64 * j;
-                        const int64_t vi = s0 + ln;
-                        // rows ending inside (or right at the end of) this 64-vector span
-                        while (nbnd <= s0 + 64 && r < rb) {
-                            if (vi < nbnd) {
-                                as += ps;
-                                ac += pc;
-                                ps = T(0);
-                                pc = T(0);
-                            }
-                            const T ts = wave_sum(as), tc = wave_sum(ac);
-                            if (ln == 0) {
-                                acc_s[r] += sign * ts;
-                                acc_c[r] += sign * tc;
-                            }
-                            as = T(0);
-                            ac = T(0);
-                            ++r;
-                            nbnd = r < rb ? (sp[r + 1] >> 3) : INT64_MAX;
+                        const T ts = wave_sum_dpp(as), tc = wave_sum_dpp(ac);
+                        if (ln == 63) {
+                            acc_s[r] += sign * ts;
+                            acc_c[r] += sign * tc;
                         }
-                        as += ps;
-                        ac += pc;
-                        q[j] = qn[j];
+                        as = T(0);
+                        ac = T(0);
+                        ++r;
+                        nbnd = r < rb ? __builtin_amdgcn_readfirstlane(bnd[r + 1]) - va : INT32_MAX;
                     }
+                    as += ps;
+                    ac += pc;
+                };
+                for (int s0 = 0; s0 < nvec; s0 += 256) {
+                    span(q0, s0);
+                    q0 = __builtin_nontemporal_load(L + min((uint32_t)(s0 + 256 + ln), last));
+                    span(q1, s0 + 64);
+                    q1 = __builtin_nontemporal_load(L + min((uint32_t)(s0 + 320 + ln), last));
+                    span(q2, s0 + 128);
+                    q2 = __builtin_nontemporal_load(L + min((uint32_t)(s0 + 384 + ln), last));
+                    span(q3, s0 + 192);
+                    q3 = __builtin_nontemporal_load(L + min((uint32_t)(s0 + 448 + ln), last));
                 }
             }
         } else {
             for (int r = grp; r < nrows; r += ngrp) {
-                const int64_t s0 = g.seg_ptr[sb + tl.r0 + r], s1 = g.seg_ptr[sb + tl.r0 + r + 1];
-                const u32x4 *__restrict__ p = reinterpret_cast<const u32x4 *>(g.list + s0);
-                const int nv = (int)((s1 - s0) >> 3);
+                const int v0 = bnd[r];
+                const u32x4 *__restrict__ p = Lt + v0;
+                const int nv = bnd[r + 1] - v0;
                 T xs = T(0), xc = T(0);
                 int v = lane;
                 for (; v + G < nv; v += 2 * G) {
-                    const u32x4 q0 = __builtin_nontemporal_load(p + v);
-                    const u32x4 q1 = __builtin_nontemporal_load(p + v + G);
-                    const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const T2 t0 = lds_sc[w[k] & 0xffffu];
-                        const T2 t1 = lds_sc[w[k] >> 16];
-                        xs += t0.x;
-                        xc += t0.y;
-                        xs += t1.x;
-                        xc += t1.y;
-                    }
+                    const u32x4 qa = __builtin_nontemporal_load(p + v);
+                    const u32x4 qb = __builtin_nontemporal_load(p + v + G);
+                    gather8<T, T2>(lds_sc, qa, xs, xc);
+                    gather8<T, T2>(lds_sc, qb, xs, xc);
                 }
-                if (v < nv) {
-                    const u32x4 q0 = __builtin_nontemporal_load(p + v);
-                    const uint32_t w[4] = {q0.x, q0.y, q0.z, q0.w};
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const T2 t0 = lds_sc[w[k] & 0xffffu];
-                        const T2 t1 = lds_sc[w[k] >> 16];
-                        xs += t0.x;
-                        xc += t0.y;
-                        xs += t1.x;
-                        xc += t1.y;
-                    }
-                }
-                xs = group_sum(xs, G);
-                xc = group_sum(xc, G);
-                if (lane == 0) {
+                if (v < nv) gather8<T, T2>(lds_sc, __builtin_nontemporal_load(p + v), xs, xc);
+                xs = group_sum_dpp(xs, G);
+                xc = group_sum_dpp(xc, G);
+                if (lane == G - 1) {
                     acc_s[r] += sign * xs;
                     acc_c[r] += sign * xc;
                 }
@@ -312,9 +361,9 @@ __global__ __launch_bounds__(NT) void k_rows(DevGraph g, RowArgs<T> a)
             xs += t.x;
             xc += t.y;
         }
-        xs = group_sum(xs, G);
-        xc = group_sum(xc, G);
-        if (lane == 0) {
+        xs = group_sum_dpp(xs, G);
+        xc = group_sum_dpp(xc, G);
+        if (lane == G - 1) {
             acc_s[r] += xs;
             acc_c[r] += xc;
         }
@@ -454,7 +503,7 @@ hipError_t launch_sc_init(const DevGraph &g, int ntiles, const T *y, void *sc, v
 size_t rows_lds_bytes(int elem_bytes, int W, int tile_rows, int threads)
 {
     size_t b = (size_t)(W + 1) * 2 * elem_bytes + (size_t)2 * tile_rows * elem_bytes +
-               (size_t)(threads / 64 + 1) * 2 * elem_bytes;
+               (size_t)(threads / 64 + 1) * 2 * elem_bytes + (size_t)(tile_rows + 1) * 4;
     return (b + 15) & ~size_t(15);
 }
 

@@ -68,7 +68,7 @@ def check_layout(k, g, tau):
             assert list(itr) == cross
 
 
-@pytest.mark.parametrize("chunk", [64, 8192])
+@pytest.mark.parametrize("chunk", [64, 8128])
 @pytest.mark.parametrize("tau", [0.0, 0.5, 1.0])
 def test_preprocessing_matches_dense_adjacency(chunk, tau):
     rng = np.random.default_rng(3)
@@ -150,15 +150,12 @@ def test_validation_errors_before_device_work():
         _expect(K.KUR_EINVAL, k.set_graph_csr, 2, rp, np.array([1, 0]), np.array([0, -1]))  # negative label
         _expect(K.KUR_EINVAL, k.set_graph_csr, 2, np.array([0, 2, 2]), np.array([1, 1]), np.zeros(2))  # dup
         _expect(K.KUR_EINVAL, k.set_graph_csr, 0, np.array([0]), np.zeros(0), np.zeros(0))
-        for key, v in [("tau", -0.1), ("chunk", 100), ("chunk", 65536), ("tile_rows", 10), ("threads", 128),
-                       ("scaling", 2), ("nonsense", 1.0), ("tau", float("nan"))]:
+        for key, v in [("tau", -0.1), ("chunk", 100), ("chunk", 8192), ("tile_rows", 10), ("threads", 128),
+                       ("scaling", 2), ("nonsense", 1.0), ("tau", float("nan")), ("flat_min_vec", -1)]:
             _expect(K.KUR_EINVAL, k.set_option, key, v)
-        # LDS budget: 32768 columns of FP32 (sin, cos) do not fit next to 4096-row accumulators
-        k.set_option("chunk", 32768)
-        k.set_option("tile_rows", 4096)
-        _expect(K.KUR_EINVAL, k.set_graph_complete, 10)
-        k.set_option("chunk", 8192)
-        k.set_option("tile_rows", 1024)
+        with host_ctx("f64") as k64:
+            _expect(K.KUR_EINVAL, k64.set_option, "chunk", 4096)
+            k64.set_option("chunk", 4032)
         # calls out of order
         _expect(K.KUR_ESTATE, k.graph_info)
         k.set_graph_complete(4)
