@@ -126,9 +126,10 @@ kur_status kur_set_graph(kur_ctx *ctx, int64_t n, int32_t nb, const int64_t *blo
                          const uint8_t *mode, const int64_t *list_ptr, const uint16_t *list_col,
                          const int64_t *inter_ptr, const int32_t *inter_col, const int32_t *perm);
 
-/* Graph statistics after kur_set_graph*: out[0..7] = n, nb, dense blocks, list entries
- * (unpadded), list entries (padded, as stored), inter entries, tiles, chunk width. */
-kur_status kur_graph_info(const kur_ctx *ctx, int64_t out[8]);
+/* Graph statistics after kur_set_graph*: out[0..9] = n, nb, dense blocks, list entries
+ * (unpadded), list entries (padded, as stored), inter entries, tiles, chunk width, 1 if the
+ * adjacency is symmetric, largest block size. */
+kur_status kur_graph_info(const kur_ctx *ctx, int64_t out[10]);
 
 /* Permutation in use: perm[u] = block-order index of user node u (n entries). */
 kur_status kur_get_perm(const kur_ctx *ctx, int32_t *perm);
@@ -181,6 +182,24 @@ kur_status kur_order_parameter(kur_ctx *ctx, double *r, double *psi);
  */
 kur_status kur_get_state(kur_ctx *ctx, void *blob, size_t *bytes);
 kur_status kur_set_state(kur_ctx *ctx, const void *blob, size_t bytes);
+
+/*
+ * Gradients of a loss L(theta(T)) through nsteps classical RK4 steps of size dt started at
+ * theta0: the discrete adjoint of exactly the computed RK4 trajectory (not the continuous
+ * adjoint equation). With l_i = dL/dk_i and lam = dL/dtheta at the end of a step, one step
+ * back reads l4 = dt/6 lam, l3 = dt/3 lam + dt J(Y4)^T l4, l2 = dt/3 lam + dt/2 J(Y3)^T l3,
+ * l1 = dt/6 lam + dt/2 J(Y2)^T l2, lam <- lam + sum_i J(Y_i)^T l_i, dL/domega += sum_i l_i,
+ * dL/dK += sum_i <l_i, dF/dK(Y_i)>, where J is the Jacobian of eq. KuramotoGraph.
+ * The forward pass keeps the phases every ckpt_every steps and each segment is recomputed
+ * before its reverse sweep. The context's own phase state is not touched.
+ *   theta0      n, user order (NULL: the current phases)
+ *   dl_dthetaT  n, user order: dL/dtheta(T)
+ *   g_theta0, g_omega (n, user order) and g_K (scalar) receive the gradients (any may be NULL)
+ * Requires a symmetric adjacency (KUR_EINVAL otherwise). Uses device memory of about
+ * (4 ckpt_every + 15) n reals plus 2 n reals per checkpoint. Synchronous.
+ */
+kur_status kur_adjoint_rk4(kur_ctx *ctx, const double *theta0, double dt, int64_t nsteps, int64_t ckpt_every,
+                           const double *dl_dthetaT, double *g_theta0, double *g_omega, double *g_K);
 
 /* Wait for all work enqueued on the context stream. */
 kur_status kur_sync(kur_ctx *ctx);

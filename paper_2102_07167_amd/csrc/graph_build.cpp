@@ -68,6 +68,27 @@ struct ErrFlag {
 
 inline int64_t round8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
+inline uint64_t mix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Order-dependent hash of a directed pair: the adjacency is symmetric iff the multiset of
+// (row, col) pairs equals that of (col, row), which is checked by comparing wrap-around sums.
+inline uint64_t pair_hash(uint64_t a, uint64_t b) { return mix64(mix64(a) ^ (b * 0xD6E8FEB86659FD93ull)); }
+
+struct SymHash {
+    std::atomic<uint64_t> fwd{0}, bwd{0};
+    void add(uint64_t f, uint64_t b)
+    {
+        fwd.fetch_add(f, std::memory_order_relaxed);
+        bwd.fetch_add(b, std::memory_order_relaxed);
+    }
+};
+
 // Common second half: given the block layout and, for every block-order row, a way to mark
 // the row's "listed" block-local columns in a bitmap (for a dense block the ones, which are
 // complemented on output; for a sparse block the ones themselves) plus the row's inter
@@ -293,6 +314,19 @@ std::string build_from_csr(int64_t n, const int64_t *row_ptr, const int32_t *col
     for (int64_t u = 0; u < n; ++u)
         if (labels[u] < 0) return "labels must be >= 0";
 
+    // symmetry of A (diagonal entries ignored)
+    SymHash sym;
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        uint64_t f = 0, b = 0;
+        for (int64_t u = lo; u < hi; ++u)
+            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                if (col[e] == u) continue;
+                f += pair_hash((uint64_t)u, (uint64_t)col[e]);
+                b += pair_hash((uint64_t)col[e], (uint64_t)u);
+            }
+        sym.add(f, b);
+    });
+
     // communities ordered by label value; stable counting sort of the nodes
     std::vector<int32_t> uniq(labels, labels + n);
     std::sort(uniq.begin(), uniq.end());
@@ -371,7 +405,9 @@ std::string build_from_csr(int64_t n, const int64_t *row_ptr, const int32_t *col
             if (pv < b.row0 || pv >= b.row0 + b.size) out.push_back((int32_t)pv);
         }
     };
-    return finish(g, block_of_row, src, nullptr, opt);
+    std::string msg = finish(g, block_of_row, src, nullptr, opt);
+    g.symmetric = sym.fwd.load() == sym.bwd.load();
+    return msg;
 }
 
 std::string build_from_blocks(int64_t n, int32_t nb, const int64_t *block_ptr, const uint8_t *mode,
@@ -426,6 +462,26 @@ std::string build_from_blocks(int64_t n, int32_t nb, const int64_t *block_ptr, c
     }
     std::vector<uint8_t> modes(mode, mode + nb);
     for (int32_t b = 0; b < nb; ++b) g.blk[b].mode = modes[b] ? 1 : 0;
+    // symmetry: the list of a block (zeros or ones, in block-order coordinates) and the inter
+    // entries must each be symmetric
+    SymHash sym;
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        uint64_t f = 0, b = 0;
+        for (int64_t m = lo; m < hi; ++m) {
+            const int64_t r0 = g.blk[block_of_row[m]].row0;
+            for (int64_t e = list_ptr[m]; e < list_ptr[m + 1]; ++e) {
+                const uint64_t v = (uint64_t)(r0 + list_col[e]);
+                f += pair_hash((uint64_t)m, v);
+                b += pair_hash(v, (uint64_t)m);
+            }
+            for (int64_t e = inter_ptr[m]; e < inter_ptr[m + 1]; ++e) {
+                const uint64_t v = (uint64_t)inter_col[e];
+                f += pair_hash((uint64_t)m, v);
+                b += pair_hash(v, (uint64_t)m);
+            }
+        }
+        sym.add(f, b);
+    });
     // finish() marks the one entries of a row and complements them for a dense block; a dense
     // block's given list holds the zeros, so its ones are everything else except the diagonal.
     RowSource src;
@@ -468,7 +524,9 @@ std::string build_from_blocks(int64_t n, int32_t nb, const int64_t *block_ptr, c
     src.inter = [&](int64_t m, std::vector<int32_t> &out) {
         for (int64_t e = inter_ptr[m]; e < inter_ptr[m + 1]; ++e) out.push_back(inter_col[e]);
     };
-    return finish(g, block_of_row, src, &modes, opt);
+    std::string msg = finish(g, block_of_row, src, &modes, opt);
+    g.symmetric = sym.fwd.load() == sym.bwd.load();
+    return msg;
 }
 
 }  // namespace kur

@@ -51,13 +51,14 @@ struct kur_ctx {
     int32_t W = 0, tile_rows = 0;
     std::vector<int32_t> perm;
     std::vector<int32_t> deg;
-    int64_t info[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t info[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    bool symmetric = false;
     BlockGraph host_graph;  // full layout, kept by host-only contexts for introspection
 
     // device graph
     DevBuf d_blk, d_tiles, d_order, d_seg, d_list, d_iptr, d_icol;
     // device state
-    DevBuf d_omega, d_rowscale, d_hi, d_lo, d_wind, d_ksum, d_sc[2], d_part[2], d_sce, d_parte, d_kout, d_y;
+    DevBuf d_omega, d_unit, d_hi, d_lo, d_wind, d_ksum, d_sc[2], d_part[2], d_sce, d_parte, d_kout, d_y;
     DevBuf d_r, d_psi;
     int cur = 0;
     bool sc_valid = false;
@@ -125,7 +126,7 @@ hipError_t upload(DevBuf &b, const void *src, size_t bytes, hipStream_t st)
 void free_all(kur_ctx *c)
 {
     DevBuf *bufs[] = {&c->d_blk, &c->d_tiles, &c->d_order, &c->d_seg, &c->d_list, &c->d_iptr, &c->d_icol,
-                      &c->d_omega, &c->d_rowscale, &c->d_hi, &c->d_lo, &c->d_wind, &c->d_ksum, &c->d_sc[0],
+                      &c->d_omega, &c->d_unit, &c->d_hi, &c->d_lo, &c->d_wind, &c->d_ksum, &c->d_sc[0],
                       &c->d_sc[1], &c->d_part[0], &c->d_part[1], &c->d_sce, &c->d_parte, &c->d_kout, &c->d_y,
                       &c->d_r, &c->d_psi};
     for (DevBuf *b : bufs) dfree(*b);
@@ -208,22 +209,23 @@ kur_status need_ready(kur_ctx *c, bool params, bool phases)
     return KUR_OK;
 }
 
-kur_status set_rowscale(kur_ctx *c)
+// per-row unit scale 1/deg_m for non-uniform scaling (zero rows: 0, so theta' = omega)
+kur_status set_unit(kur_ctx *c)
 {
     if (c->scaling == 0) {
-        dfree(c->d_rowscale);
+        dfree(c->d_unit);
         return KUR_OK;
     }
     const int64_t n = c->n;
     hipError_t e;
     if (c->esz == 4) {
         std::vector<float> t(n);
-        for (int64_t m = 0; m < n; ++m) t[m] = c->deg[m] > 0 ? (float)(c->K / (double)c->deg[m]) : 0.0f;
-        e = upload(c->d_rowscale, t.data(), sizeof(float) * n, c->stream);
+        for (int64_t m = 0; m < n; ++m) t[m] = c->deg[m] > 0 ? (float)(1.0 / (double)c->deg[m]) : 0.0f;
+        e = upload(c->d_unit, t.data(), sizeof(float) * n, c->stream);
     } else {
         std::vector<double> t(n);
-        for (int64_t m = 0; m < n; ++m) t[m] = c->deg[m] > 0 ? c->K / (double)c->deg[m] : 0.0;
-        e = upload(c->d_rowscale, t.data(), sizeof(double) * n, c->stream);
+        for (int64_t m = 0; m < n; ++m) t[m] = c->deg[m] > 0 ? 1.0 / (double)c->deg[m] : 0.0;
+        e = upload(c->d_unit, t.data(), sizeof(double) * n, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "row scale upload");
     return KUR_OK;
@@ -238,8 +240,9 @@ RowArgs<T> row_args(kur_ctx *c, int stage, double dt)
     a.dt = (T)dt;
     a.half_dt = (T)(0.5 * dt);
     a.dt6 = (T)(dt / 6.0);
-    a.kscale = (T)(c->K / (double)c->n);
-    a.rowscale = (const T *)c->d_rowscale.p;
+    a.K = (T)c->K;
+    a.inv_n = (T)(1.0 / (double)c->n);
+    a.unit = (const T *)c->d_unit.p;
     a.omega = (const T *)c->d_omega.p;
     a.hi = (T *)c->d_hi.p;
     a.lo = (T *)c->d_lo.p;
@@ -315,8 +318,8 @@ kur_status sc_init(kur_ctx *c, const void *y, DevBuf &sc, DevBuf &part)
 
 kur_status install_graph(kur_ctx *c, BlockGraph &g)
 {
-    const size_t lds = rows_lds_bytes(c->esz, g.W, g.tile_rows, c->threads);
-    if (lds > 160 * 1024) return fail(c, KUR_EINVAL, "chunk/tile_rows/threads exceed the 160 KiB LDS of a workgroup");
+    const size_t lds = rows_lds_bytes(c->esz, g.W, g.tile_rows, c->threads, 1);
+    if (lds > 156 * 1024) return fail(c, KUR_EINVAL, "chunk/tile_rows/threads exceed the LDS of a workgroup");
     if (g.tiles.size() > (size_t)INT32_MAX) return fail(c, KUR_EINVAL, "too many tiles");
     if (!c->host_only) {
         HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
@@ -359,12 +362,18 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
     c->info[5] = (int64_t)g.inter_col.size();
     c->info[6] = (int64_t)g.tiles.size();
     c->info[7] = g.W;
+    c->info[8] = g.symmetric ? 1 : 0;
+    int64_t smax = 0;
+    for (const BlkInfo &b : g.blk) smax = std::max<int64_t>(smax, b.size);
+    c->info[9] = smax;
+    c->symmetric = g.symmetric;
     if (c->host_only) c->host_graph = std::move(g);
     c->has_graph = true;
     c->has_params = false;
     c->has_phases = false;
     c->sc_valid = false;
     c->cur = 0;
+    if (!c->host_only) return set_unit(c);
     return KUR_OK;
 }
 
@@ -460,13 +469,13 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
         c->bopt.flat_min_vec = v;
     } else if (k == "threads") {
         if (v != 256 && v != 512 && v != 1024) return fail(c, KUR_EINVAL, "threads must be 256, 512 or 1024");
-        if (c->has_graph && rows_lds_bytes(c->esz, c->W, c->tile_rows, (int)v) > 160 * 1024)
+        if (c->has_graph && rows_lds_bytes(c->esz, c->W, c->tile_rows, (int)v, 1) > 156 * 1024)
             return fail(c, KUR_EINVAL, "threads exceed the LDS budget of the current graph layout");
         c->threads = (int)v;
     } else if (k == "scaling") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "scaling must be 0 or 1");
         c->scaling = (int)v;
-        if (c->has_graph && c->has_params && !c->host_only) return set_rowscale(c);
+        if (c->has_graph && !c->host_only) return set_unit(c);
     } else if (k == "compensate") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "compensate must be 0 or 1");
         c->compensate = (int)v;
@@ -518,7 +527,7 @@ kur_status kur_set_graph(kur_ctx *c, int64_t n, int32_t nb, const int64_t *block
     return install_graph(c, g);
 }
 
-kur_status kur_graph_info(const kur_ctx *c, int64_t out[8])
+kur_status kur_graph_info(const kur_ctx *c, int64_t out[10])
 {
     if (!c || !out) return KUR_EINVAL;
     if (!c->has_graph) return KUR_ESTATE;
@@ -594,7 +603,7 @@ kur_status kur_set_params(kur_ctx *c, const double *omega, double K)
     if (e != hipSuccess) return hip_fail(c, e, "omega upload");
     c->K = K;
     c->has_params = true;
-    return set_rowscale(c);
+    return KUR_OK;
 }
 
 kur_status kur_set_phases(kur_ctx *c, const double *theta)
@@ -928,3 +937,212 @@ kur_status kur_kernel_time(kur_ctx *c, int64_t *launches, double *total_ms)
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// Discrete adjoint of kur_step_rk4 with checkpointing
+// ------------------------------------------------------------------------------------------------
+
+namespace {
+
+struct AdjBufs {
+    DevBuf hi, lo, wind, ksum, ck, slots, fpart[2], x[2], xpart[2], lam, lam_acc, lbuf, gom, gk;
+    ~AdjBufs()
+    {
+        DevBuf *b[] = {&hi, &lo, &wind, &ksum, &ck, &slots, &fpart[0], &fpart[1], &x[0], &x[1],
+                       &xpart[0], &xpart[1], &lam, &lam_acc, &lbuf, &gom, &gk};
+        for (DevBuf *p : b) dfree(*p);
+    }
+};
+
+template <typename T>
+kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, double dt, int64_t nsteps, int64_t C,
+                        const double *seed_user, double *g_theta0, double *g_omega, double *g_K)
+{
+    using std::vector;
+    const int64_t n = c->n;
+    const int nt = c->ntiles;
+    const size_t TN = sizeof(T) * (size_t)n;
+    hipStream_t st = c->stream;
+    const int64_t nseg = nsteps > 0 ? (nsteps + C - 1) / C : 0;
+    const int64_t nslot = 4 * std::min<int64_t>(C, std::max<int64_t>(nsteps, 1)) + 1;
+    AdjBufs B;
+    hipError_t e;
+    if ((e = dalloc(B.hi, TN)) != hipSuccess || (e = dalloc(B.lo, TN)) != hipSuccess ||
+        (e = dalloc(B.wind, 4 * (size_t)n)) != hipSuccess || (e = dalloc(B.ksum, TN)) != hipSuccess ||
+        (e = dalloc(B.ck, 2 * TN * (size_t)std::max<int64_t>(nseg, 1))) != hipSuccess ||
+        (e = dalloc(B.slots, 2 * TN * (size_t)nslot)) != hipSuccess ||
+        (e = dalloc(B.fpart[0], 2 * sizeof(T) * nt)) != hipSuccess || (e = dalloc(B.fpart[1], 2 * sizeof(T) * nt)) != hipSuccess ||
+        (e = dalloc(B.x[0], 4 * TN)) != hipSuccess || (e = dalloc(B.x[1], 4 * TN)) != hipSuccess ||
+        (e = dalloc(B.xpart[0], 4 * sizeof(T) * nt)) != hipSuccess || (e = dalloc(B.xpart[1], 4 * sizeof(T) * nt)) != hipSuccess ||
+        (e = dalloc(B.lam, TN)) != hipSuccess || (e = dalloc(B.lam_acc, TN)) != hipSuccess ||
+        (e = dalloc(B.lbuf, TN)) != hipSuccess || (e = dalloc(B.gom, 8 * (size_t)n)) != hipSuccess ||
+        (e = dalloc(B.gk, 8 * (size_t)nt)) != hipSuccess)
+        return hip_fail(c, e, "adjoint buffers");
+
+    // initial phases (block order), split as in kur_set_phases; the seed dL/dtheta(T)
+    {
+        const double P1 = two_pi_p1(c->esz), P2 = two_pi_p2(c->esz);
+        vector<T> hi(n), lo(n), lam(n);
+        vector<int32_t> wind(n);
+        for (int64_t u = 0; u < n; ++u) {
+            const int64_t m = c->perm[u];
+            const double q = std::nearbyint(theta0_user[u] / (2.0 * kPi));
+            const double red = (theta0_user[u] - q * P1) - q * P2;
+            hi[m] = (T)red;
+            lo[m] = (T)(red - (double)hi[m]);
+            wind[m] = (int32_t)q;
+            lam[m] = (T)seed_user[u];
+        }
+        if ((e = hipMemcpyAsync(B.hi.p, hi.data(), TN, hipMemcpyHostToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(B.lo.p, lo.data(), TN, hipMemcpyHostToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(B.wind.p, wind.data(), 4 * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(B.lam.p, lam.data(), TN, hipMemcpyHostToDevice, st)) != hipSuccess ||
+            (e = hipMemsetAsync(B.gom.p, 0, 8 * (size_t)n, st)) != hipSuccess ||
+            (e = hipMemsetAsync(B.gk.p, 0, 8 * (size_t)nt, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(c, e, "adjoint upload");
+    }
+    const DevGraph g = devgraph(c);
+    auto rows = [&](int stage, const void *sc_in, const void *p_in, void *sc_out, void *p_out) -> hipError_t {
+        RowArgs<T> a = row_args<T>(c, stage, dt);
+        a.hi = (T *)B.hi.p;
+        a.lo = (T *)B.lo.p;
+        a.wind = (int32_t *)B.wind.p;
+        a.ksum = (T *)B.ksum.p;
+        a.sc_in = sc_in;
+        a.part_in = p_in;
+        a.sc_out = sc_out;
+        a.part_out = p_out;
+        return launch_rows<T>(g, nt, a, c->threads, st);
+    };
+    auto slot = [&](int64_t i) -> void * { return (char *)B.slots.p + (size_t)i * 2 * TN; };
+
+    // forward pass, keeping (hi, lo) every C steps
+    if (nsteps > 0) {
+        int cur = 0;
+        if ((e = launch_sc_init<T>(g, nt, (const T *)B.hi.p, slot(0), B.fpart[0].p, c->threads, st)) != hipSuccess)
+            return hip_fail(c, e, "adjoint forward");
+        void *fsc[2] = {slot(0), slot(1)};
+        for (int64_t step = 0; step < nsteps; ++step) {
+            if (step % C == 0) {
+                char *ck = (char *)B.ck.p + (size_t)(step / C) * 2 * TN;
+                if ((e = hipMemcpyAsync(ck, B.hi.p, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+                    (e = hipMemcpyAsync(ck + TN, B.lo.p, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+                    return hip_fail(c, e, "adjoint checkpoint");
+            }
+            for (int stage = 1; stage <= 4; ++stage) {
+                if ((e = rows(stage, fsc[cur], B.fpart[cur].p, fsc[cur ^ 1], B.fpart[cur ^ 1].p)) != hipSuccess)
+                    return hip_fail(c, e, "adjoint forward");
+                cur ^= 1;
+            }
+        }
+    }
+
+    // reverse sweep, segment by segment
+    const T tdt = (T)dt;
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t s0 = seg * C, len = std::min<int64_t>(C, nsteps - s0);
+        const char *ck = (const char *)B.ck.p + (size_t)seg * 2 * TN;
+        if ((e = hipMemcpyAsync(B.hi.p, ck, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(B.lo.p, ck + TN, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+            return hip_fail(c, e, "adjoint restore");
+        // recompute the segment, keeping (sin, cos) of every stage state: Y_i of step k at slot 4k+i-1
+        int cur = 0;
+        if ((e = launch_sc_init<T>(g, nt, (const T *)B.hi.p, slot(0), B.fpart[0].p, c->threads, st)) != hipSuccess)
+            return hip_fail(c, e, "adjoint recompute");
+        for (int64_t k = 0; k < len; ++k)
+            for (int stage = 1; stage <= 4; ++stage) {
+                const int64_t i = 4 * k + stage;
+                if ((e = rows(stage, slot(i - 1), B.fpart[cur].p, slot(i), B.fpart[cur ^ 1].p)) != hipSuccess)
+                    return hip_fail(c, e, "adjoint recompute");
+                cur ^= 1;
+            }
+        for (int64_t k = len - 1; k >= 0; --k) {
+            VjpArgs<T> v;
+            v.K = (T)c->K;
+            v.inv_n = (T)(1.0 / (double)n);
+            v.unit = (const T *)c->d_unit.p;
+            v.lam = (T *)B.lam.p;
+            v.lam_acc = (T *)B.lam_acc.p;
+            v.lbuf = (T *)B.lbuf.p;
+            v.g_omega = (double *)B.gom.p;
+            v.gk_part = (double *)B.gk.p;
+            int xc = 0;
+            v.stage = 4;
+            v.cl = (T)(dt / 6.0);
+            v.cm = T(0);
+            v.sc_next = slot(4 * k + 3);
+            v.x_in = nullptr;
+            v.part_in = nullptr;
+            v.x_out = B.x[0].p;
+            v.part_out = B.xpart[0].p;
+            if ((e = launch_vjp_init<T>(g, nt, v, c->threads, st)) != hipSuccess) return hip_fail(c, e, "adjoint init");
+            for (int i = 4; i >= 1; --i) {
+                v.stage = i;
+                // l_{i-1} = cl lam + cm mu_i: (dt/3, dt), (dt/3, dt/2), (dt/6, dt/2)
+                v.cl = i == 4 ? (T)(dt / 3.0) : i == 3 ? (T)(dt / 3.0) : (T)(dt / 6.0);
+                v.cm = i == 4 ? tdt : (T)(0.5 * dt);
+                v.sc_next = i > 1 ? slot(4 * k + i - 2) : nullptr;
+                v.x_in = B.x[xc].p;
+                v.part_in = B.xpart[xc].p;
+                v.x_out = B.x[xc ^ 1].p;
+                v.part_out = B.xpart[xc ^ 1].p;
+                if ((e = launch_vjp<T>(g, nt, v, c->threads, st)) != hipSuccess) return hip_fail(c, e, "adjoint stage");
+                xc ^= 1;
+            }
+        }
+    }
+
+    // results
+    vector<T> lam(n);
+    vector<double> gom(n), gk(nt);
+    if ((e = hipMemcpyAsync(lam.data(), B.lam.p, TN, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(gom.data(), B.gom.p, 8 * (size_t)n, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(gk.data(), B.gk.p, 8 * (size_t)nt, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(c, e, "adjoint download");
+    for (int64_t u = 0; u < n; ++u) {
+        if (g_theta0) g_theta0[u] = (double)lam[c->perm[u]];
+        if (g_omega) g_omega[u] = gom[c->perm[u]];
+    }
+    if (g_K) {
+        double t = 0.0;
+        for (int i = 0; i < nt; ++i) t += gk[i];
+        *g_K = t;
+    }
+    return KUR_OK;
+}
+
+}  // namespace
+
+extern "C" kur_status kur_adjoint_rk4(kur_ctx *c, const double *theta0, double dt, int64_t nsteps, int64_t ckpt_every,
+                                      const double *dl_dthetaT, double *g_theta0, double *g_omega, double *g_K)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!std::isfinite(dt) || dt == 0.0) return fail(c, KUR_EINVAL, "dt must be finite and nonzero");
+    if (nsteps < 0 || ckpt_every < 1) return fail(c, KUR_EINVAL, "nsteps must be >= 0 and ckpt_every >= 1");
+    if (!dl_dthetaT) return fail(c, KUR_EINVAL, "dl_dthetaT must not be NULL");
+    kur_status s = need_ready(c, true, theta0 == nullptr);
+    if (s != KUR_OK) return s;
+    if (!c->symmetric) return fail(c, KUR_EINVAL, "the adjoint needs a symmetric adjacency");
+    if (rows_lds_bytes(c->esz, c->W, c->tile_rows, c->threads, 2) > 156 * 1024)
+        return fail(c, KUR_EINVAL, "chunk/tile_rows too large for the adjoint's LDS (4 values per node)");
+    std::vector<double> th0;
+    if (!theta0) {
+        th0.resize(c->n);
+        s = kur_get_phases(c, th0.data(), 0);
+        if (s != KUR_OK) return s;
+        theta0 = th0.data();
+    }
+    for (int64_t u = 0; u < c->n; ++u)
+        if (!std::isfinite(theta0[u]) || std::fabs(theta0[u]) > 1e9 || !std::isfinite(dl_dthetaT[u]))
+            return fail(c, KUR_EINVAL, "theta0 and dl_dthetaT must be finite (|theta0| <= 1e9)");
+    const int64_t C = std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1));
+    try {
+        return c->esz == 4 ? adjoint_impl<float>(c, theta0, dt, nsteps, C, dl_dthetaT, g_theta0, g_omega, g_K)
+                           : adjoint_impl<double>(c, theta0, dt, nsteps, C, dl_dthetaT, g_theta0, g_omega, g_K);
+    } catch (const std::bad_alloc &) {
+        return fail(c, KUR_ENOMEM, "host allocation failed in the adjoint");
+    }
+}

@@ -58,6 +58,7 @@ struct BlockGraph {
     std::vector<int32_t> deg;         // row degree (ones of the row), block order
     int64_t list_unpadded = 0;
     int64_t n_dense = 0;
+    bool symmetric = false;           // A equals its transpose (checked by a 64-bit hash)
 };
 
 // Host preprocessing entry points; return "" on success or an error message.

@@ -99,43 +99,29 @@ __device__ __forceinline__ T wave_sum_dpp(T v)
     return v;
 }
 
-// LDS gather of the (sin, cos) pair at a byte offset into the staged chunk
-template <typename T2>
-__device__ __forceinline__ T2 lds_at(const T2 *base, uint32_t byte_off)
-{
-    return *reinterpret_cast<const T2 *>(reinterpret_cast<const char *>(base) + byte_off);
-}
-
-// Accumulate the 8 list entries of one 16-byte vector (two 16-bit byte offsets per dword).
-template <typename T, typename T2>
-__device__ __forceinline__ void gather8(const T2 *lds, const u32x4 q, T &xs, T &xc)
-{
-    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const T2 t0 = lds_at(lds, w[k] & 0xffffu);
-        const T2 t1 = lds_at(lds, w[k] >> 16);
-        xs += t0.x;
-        xc += t0.y;
-        xs += t1.x;
-        xc += t1.y;
-    }
-}
-
 // Sum v over the workgroup in a fixed order and store it to *out (thread 0).
-template <typename T2, int NT>
-__device__ __forceinline__ void block_sum_store(T2 v, T2 *red, T2 *out)
+template <typename VT, int NT>
+__device__ __forceinline__ void block_sum_store(VT v, VT *red, VT *out)
 {
     v.x = wave_sum(v.x);
     v.y = wave_sum(v.y);
+    if constexpr (sizeof(VT) / sizeof(v.x) == 4) {
+        v.z = wave_sum(v.z);
+        v.w = wave_sum(v.w);
+    }
     const int w = threadIdx.x >> 6;
+    __syncthreads();  // red may still be read by other waves
     if ((threadIdx.x & 63) == 0) red[w] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
-        T2 s = red[0];
+        VT s = red[0];
         for (int i = 1; i < NT / 64; ++i) {
             s.x += red[i].x;
             s.y += red[i].y;
+            if constexpr (sizeof(VT) / sizeof(v.x) == 4) {
+                s.z += red[i].z;
+                s.w += red[i].w;
+            }
         }
         *out = s;
     }
@@ -194,52 +180,141 @@ template <typename T> __device__ __forceinline__ void two_sum(T a, T b, T &s, T 
     e = (a - (s - bb)) + (b - bb);
 }
 
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_rows(DevGraph g, RowArgs<T> a)
-{
-    using T2 = typename V2<T>::type;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int W = g.W;
-    T2 *lds_sc = reinterpret_cast<T2 *>(smem);                 // W + 1 slots, slot W is zero
-    T *acc_s = reinterpret_cast<T *>(lds_sc + W + 1);          // tile_rows
-    T *acc_c = acc_s + g.tile_rows;                            // tile_rows
-    T2 *red = reinterpret_cast<T2 *>(acc_c + g.tile_rows);     // NT/64 + 1
-    int *bnd = reinterpret_cast<int *>(red + NT / 64 + 1);     // tile_rows + 1 row starts (vectors)
+// ------------------------------------------------------------------------------------------------
+// Gather core shared by the right-hand side (NV = 1: per node (sin, cos)) and the Jacobian-
+// transpose product (NV = 2: per node (sin, cos, w sin, w cos)).
+// ------------------------------------------------------------------------------------------------
 
-    const int tile_id = g.order[blockIdx.x];
-    const Tile tl = g.tiles[tile_id];
-    const BlkInfo bi = g.blk[tl.block];
+template <typename T, int NV> struct VecT;
+template <> struct VecT<float, 1> { using type = float2; };
+template <> struct VecT<double, 1> { using type = double2; };
+template <> struct VecT<float, 2> { using type = float4; };
+template <> struct VecT<double, 2> { using type = double4; };
+
+template <typename VT> __device__ __forceinline__ VT vzero()
+{
+    VT v;
+    v.x = 0;
+    v.y = 0;
+    if constexpr (sizeof(VT) / sizeof(v.x) == 4) {
+        v.z = 0;
+        v.w = 0;
+    }
+    return v;
+}
+
+template <typename VT> __device__ __forceinline__ void vacc(VT &a, const VT &b)
+{
+    a.x += b.x;
+    a.y += b.y;
+    if constexpr (sizeof(VT) / sizeof(a.x) == 4) {
+        a.z += b.z;
+        a.w += b.w;
+    }
+}
+
+template <typename VT, typename S> __device__ __forceinline__ VT vscale(const VT &a, S s)
+{
+    VT r = a;
+    r.x *= s;
+    r.y *= s;
+    if constexpr (sizeof(VT) / sizeof(a.x) == 4) {
+        r.z *= s;
+        r.w *= s;
+    }
+    return r;
+}
+
+template <typename VT> __device__ __forceinline__ VT vwave_sum_dpp(VT v)
+{
+    v.x = wave_sum_dpp(v.x);
+    v.y = wave_sum_dpp(v.y);
+    if constexpr (sizeof(VT) / sizeof(v.x) == 4) {
+        v.z = wave_sum_dpp(v.z);
+        v.w = wave_sum_dpp(v.w);
+    }
+    return v;
+}
+
+template <typename VT> __device__ __forceinline__ VT vgroup_sum_dpp(VT v, int G)
+{
+    v.x = group_sum_dpp(v.x, G);
+    v.y = group_sum_dpp(v.y, G);
+    if constexpr (sizeof(VT) / sizeof(v.x) == 4) {
+        v.z = group_sum_dpp(v.z, G);
+        v.w = group_sum_dpp(v.w, G);
+    }
+    return v;
+}
+
+template <typename VT> __device__ __forceinline__ VT vwave_sum(VT v)
+{
+    v.x = wave_sum(v.x);
+    v.y = wave_sum(v.y);
+    if constexpr (sizeof(VT) / sizeof(v.x) == 4) {
+        v.z = wave_sum(v.z);
+        v.w = wave_sum(v.w);
+    }
+    return v;
+}
+
+// Accumulate the 8 list entries of one 16-byte vector. Entries are LDS byte offsets of a
+// (sin, cos) pair; with NV = 2 every node occupies twice that, hence the shift.
+template <int SHIFT, typename VT>
+__device__ __forceinline__ void gather8(const VT *lds, const u32x4 q, VT &acc)
+{
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+    const char *base = reinterpret_cast<const char *>(lds);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const VT t0 = *reinterpret_cast<const VT *>(base + ((w[k] & 0xffffu) << SHIFT));
+        const VT t1 = *reinterpret_cast<const VT *>(base + ((w[k] >> 16) << SHIFT));
+        vacc(acc, t0);
+        vacc(acc, t1);
+    }
+}
+
+// LDS layout of a tile workgroup (bytes are computed by rows_lds_bytes):
+//   xs[W + 1] staged chunk values (slot W all zero) | acc[tile_rows] | red[NT/64 + 1] | bnd[tile_rows + 1]
+template <typename VT, int NT>
+struct TileLds {
+    VT *xs;
+    VT *acc;
+    VT *red;
+    int *bnd;
+    __device__ TileLds(unsigned char *smem, int W, int tile_rows)
+    {
+        xs = reinterpret_cast<VT *>(smem);
+        acc = xs + W + 1;
+        red = acc + tile_rows;
+        bnd = reinterpret_cast<int *>(red + NT / 64 + 1);
+    }
+};
+
+// For the rows of one tile, accumulate in L.acc[r] the sum over the row's stored list of x
+// (added for a sparse block, subtracted for a dense block) plus the sum over its inter-block
+// columns, and fold the block sum of x from the tile partials into L.red[NT/64] (dense blocks).
+// Ends with a barrier; the complete row sum is then (dense ? block sum : 0) + acc[r].
+template <typename T, int NT, int NV>
+__device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, const BlkInfo &bi,
+                                            const typename VecT<T, NV>::type *__restrict__ x_in,
+                                            const typename VecT<T, NV>::type *__restrict__ part_in,
+                                            TileLds<typename VecT<T, NV>::type, NT> &L)
+{
+    using VT = typename VecT<T, NV>::type;
+    constexpr int SHIFT = NV == 2 ? 1 : 0;
+    const int W = g.W;
     const int nrows = tl.r1 - tl.r0;
     const int rowbase = bi.row0 + tl.r0;
-    const T2 *__restrict__ sc_in = reinterpret_cast<const T2 *>(a.sc_in);
-    const T2 *__restrict__ part_in = reinterpret_cast<const T2 *>(a.part_in);
 
-    for (int r = threadIdx.x; r < nrows; r += NT) {
-        acc_s[r] = T(0);
-        acc_c[r] = T(0);
-    }
-    if (threadIdx.x == 0) {
-        T2 z;
-        z.x = T(0);
-        z.y = T(0);
-        lds_sc[W] = z;
-    }
+    for (int r = threadIdx.x; r < nrows; r += NT) L.acc[r] = vzero<VT>();
+    if (threadIdx.x == 0) L.xs[W] = vzero<VT>();
     // localised order parameters of the block: fixed-order sum of its tile partials
     if (bi.mode && threadIdx.x < 64) {
-        T sx = T(0), sy = T(0);
-        for (int i = threadIdx.x; i < bi.ntiles; i += 64) {
-            T2 p = part_in[bi.tile0 + i];
-            sx += p.x;
-            sy += p.y;
-        }
-        sx = wave_sum(sx);
-        sy = wave_sum(sy);
-        if (threadIdx.x == 0) {
-            T2 s;
-            s.x = sx;
-            s.y = sy;
-            red[NT / 64] = s;
-        }
+        VT sx = vzero<VT>();
+        for (int i = threadIdx.x; i < bi.ntiles; i += 64) vacc(sx, part_in[bi.tile0 + i]);
+        sx = vwave_sum(sx);
+        if (threadIdx.x == 0) L.red[NT / 64] = sx;
     }
     __syncthreads();  // accumulators, pad slot and block sums visible to every wave
 
@@ -263,87 +338,73 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         const int c0 = c * W;
         const int cw = min(W, bi.size - c0);
         __syncthreads();  // previous chunk's gathers are done
-        for (int j = threadIdx.x; j < cw; j += NT) lds_sc[j] = sc_in[bi.row0 + c0 + j];
+        for (int j = threadIdx.x; j < cw; j += NT) L.xs[j] = x_in[bi.row0 + c0 + j];
         // row starts of this chunk, in 8-entry vectors relative to the tile's first one
-        for (int r = threadIdx.x; r <= nrows; r += NT) bnd[r] = (int)((g.seg_ptr[sb + tl.r0 + r] - e0) >> 3);
+        for (int r = threadIdx.x; r <= nrows; r += NT) L.bnd[r] = (int)((g.seg_ptr[sb + tl.r0 + r] - e0) >> 3);
         __syncthreads();
         const u32x4 *__restrict__ Lt = reinterpret_cast<const u32x4 *>(g.list + e0);
         if (flat) {
             // rows [ra, rb) occupy the contiguous 8-entry vectors [va, va + nvec) of this chunk
-            const int va = __builtin_amdgcn_readfirstlane(bnd[ra]);
-            const int nvec = __builtin_amdgcn_readfirstlane(bnd[rb]) - va;
+            const int va = __builtin_amdgcn_readfirstlane(L.bnd[ra]);
+            const int nvec = __builtin_amdgcn_readfirstlane(L.bnd[rb]) - va;
             if (nvec > 0) {
-                const u32x4 *__restrict__ L = Lt + va;
+                const u32x4 *__restrict__ Lv = Lt + va;
                 int r = ra;
-                int nbnd = __builtin_amdgcn_readfirstlane(bnd[r + 1]) - va;  // first vector after row r
-                T as = T(0), ac = T(0);
+                int nbnd = __builtin_amdgcn_readfirstlane(L.bnd[r + 1]) - va;  // first vector after row r
+                VT acc = vzero<VT>();
                 // rolling prefetch: four 64-vector spans in flight per wave; loads are issued
                 // unconditionally (index clamped) so the in-order wait counts stay exact, and
                 // lanes past the end are masked after the gather
                 const uint32_t last = (uint32_t)(nvec - 1);
-                u32x4 q0 = __builtin_nontemporal_load(L + min((uint32_t)ln, last));
-                u32x4 q1 = __builtin_nontemporal_load(L + min((uint32_t)(64 + ln), last));
-                u32x4 q2 = __builtin_nontemporal_load(L + min((uint32_t)(128 + ln), last));
-                u32x4 q3 = __builtin_nontemporal_load(L + min((uint32_t)(192 + ln), last));
+                u32x4 q0 = __builtin_nontemporal_load(Lv + min((uint32_t)ln, last));
+                u32x4 q1 = __builtin_nontemporal_load(Lv + min((uint32_t)(64 + ln), last));
+                u32x4 q2 = __builtin_nontemporal_load(Lv + min((uint32_t)(128 + ln), last));
+                u32x4 q3 = __builtin_nontemporal_load(Lv + min((uint32_t)(192 + ln), last));
                 auto span = [&](const u32x4 q, const int s0) {
-                    T ps = T(0), pc = T(0);
-                    gather8<T, T2>(lds_sc, q, ps, pc);
-                    if (s0 + ln >= nvec) {
-                        ps = T(0);
-                        pc = T(0);
-                    }
+                    VT p = vzero<VT>();
+                    gather8<SHIFT>(L.xs, q, p);
+                    if (s0 + ln >= nvec) p = vzero<VT>();
                     // rows that end inside (or right at the end of) this span
                     while (nbnd <= s0 + 64 && r < rb) {
                         if (s0 + ln < nbnd) {
-                            as += ps;
-                            ac += pc;
-                            ps = T(0);
-                            pc = T(0);
+                            vacc(acc, p);
+                            p = vzero<VT>();
                         }
-                        const T ts = wave_sum_dpp(as), tc = wave_sum_dpp(ac);
-                        if (ln == 63) {
-                            acc_s[r] += sign * ts;
-                            acc_c[r] += sign * tc;
-                        }
-                        as = T(0);
-                        ac = T(0);
+                        const VT t = vwave_sum_dpp(acc);
+                        if (ln == 63) vacc(L.acc[r], vscale(t, sign));
+                        acc = vzero<VT>();
                         ++r;
-                        nbnd = r < rb ? __builtin_amdgcn_readfirstlane(bnd[r + 1]) - va : INT32_MAX;
+                        nbnd = r < rb ? __builtin_amdgcn_readfirstlane(L.bnd[r + 1]) - va : INT32_MAX;
                     }
-                    as += ps;
-                    ac += pc;
+                    vacc(acc, p);
                 };
                 for (int s0 = 0; s0 < nvec; s0 += 256) {
                     span(q0, s0);
-                    q0 = __builtin_nontemporal_load(L + min((uint32_t)(s0 + 256 + ln), last));
+                    q0 = __builtin_nontemporal_load(Lv + min((uint32_t)(s0 + 256 + ln), last));
                     span(q1, s0 + 64);
-                    q1 = __builtin_nontemporal_load(L + min((uint32_t)(s0 + 320 + ln), last));
+                    q1 = __builtin_nontemporal_load(Lv + min((uint32_t)(s0 + 320 + ln), last));
                     span(q2, s0 + 128);
-                    q2 = __builtin_nontemporal_load(L + min((uint32_t)(s0 + 384 + ln), last));
+                    q2 = __builtin_nontemporal_load(Lv + min((uint32_t)(s0 + 384 + ln), last));
                     span(q3, s0 + 192);
-                    q3 = __builtin_nontemporal_load(L + min((uint32_t)(s0 + 448 + ln), last));
+                    q3 = __builtin_nontemporal_load(Lv + min((uint32_t)(s0 + 448 + ln), last));
                 }
             }
         } else {
             for (int r = grp; r < nrows; r += ngrp) {
-                const int v0 = bnd[r];
+                const int v0 = L.bnd[r];
                 const u32x4 *__restrict__ p = Lt + v0;
-                const int nv = bnd[r + 1] - v0;
-                T xs = T(0), xc = T(0);
+                const int nv = L.bnd[r + 1] - v0;
+                VT acc = vzero<VT>();
                 int v = lane;
                 for (; v + G < nv; v += 2 * G) {
                     const u32x4 qa = __builtin_nontemporal_load(p + v);
                     const u32x4 qb = __builtin_nontemporal_load(p + v + G);
-                    gather8<T, T2>(lds_sc, qa, xs, xc);
-                    gather8<T, T2>(lds_sc, qb, xs, xc);
+                    gather8<SHIFT>(L.xs, qa, acc);
+                    gather8<SHIFT>(L.xs, qb, acc);
                 }
-                if (v < nv) gather8<T, T2>(lds_sc, __builtin_nontemporal_load(p + v), xs, xc);
-                xs = group_sum_dpp(xs, G);
-                xc = group_sum_dpp(xc, G);
-                if (lane == G - 1) {
-                    acc_s[r] += sign * xs;
-                    acc_c[r] += sign * xc;
-                }
+                if (v < nv) gather8<SHIFT>(L.xs, __builtin_nontemporal_load(p + v), acc);
+                acc = vgroup_sum_dpp(acc, G);
+                if (lane == G - 1) vacc(L.acc[r], vscale(acc, sign));
             }
         }
     }
@@ -355,35 +416,39 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         const int m = rowbase + r;
         const int64_t e0 = g.inter_ptr[m], e1 = g.inter_ptr[m + 1];
         if (e0 == e1) continue;  // uniform over the group
-        T xs = T(0), xc = T(0);
-        for (int64_t e = e0 + lane; e < e1; e += G) {
-            const T2 t = sc_in[g.inter_col[e]];
-            xs += t.x;
-            xc += t.y;
-        }
-        xs = group_sum_dpp(xs, G);
-        xc = group_sum_dpp(xc, G);
-        if (lane == G - 1) {
-            acc_s[r] += xs;
-            acc_c[r] += xc;
-        }
+        VT acc = vzero<VT>();
+        for (int64_t e = e0 + lane; e < e1; e += G) vacc(acc, x_in[g.inter_col[e]]);
+        acc = vgroup_sum_dpp(acc, G);
+        if (lane == G - 1) vacc(L.acc[r], acc);
     }
     __syncthreads();
+}
 
-    T Sb = T(0), Cb = T(0);
-    if (bi.mode) {
-        Sb = red[NT / 64].x;
-        Cb = red[NT / 64].y;
-    }
-    T2 part;
-    part.x = T(0);
-    part.y = T(0);
+// Right-hand side and classical RK4 stage bookkeeping, one tile per workgroup.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_rows(DevGraph g, RowArgs<T> a)
+{
+    using T2 = typename V2<T>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    TileLds<T2, NT> L(smem, g.W, g.tile_rows);
+    const int tile_id = g.order[blockIdx.x];
+    const Tile tl = g.tiles[tile_id];
+    const BlkInfo bi = g.blk[tl.block];
+    const int nrows = tl.r1 - tl.r0;
+    const int rowbase = bi.row0 + tl.r0;
+    const T2 *__restrict__ sc_in = reinterpret_cast<const T2 *>(a.sc_in);
+
+    tile_gather<T, NT, 1>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L);
+
+    T2 base = vzero<T2>();
+    if (bi.mode) base = L.red[NT / 64];
+    T2 part = vzero<T2>();
     for (int r = threadIdx.x; r < nrows; r += NT) {
         const int m = rowbase + r;
         const T2 scm = sc_in[m];
-        const T As = Sb + acc_s[r];
-        const T Ac = Cb + acc_c[r];
-        const T scale = a.rowscale ? a.rowscale[m] : a.kscale;
+        const T As = base.x + L.acc[r].x;
+        const T Ac = base.y + L.acc[r].y;
+        const T scale = a.K * (a.unit ? a.unit[m] : a.inv_n);
         const T k = a.omega[m] + scale * (As * scm.y - Ac * scm.x);
         if (a.stage == 0) {
             a.kout[m] = k;
@@ -438,7 +503,112 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         part.x += s;
         part.y += c;
     }
-    if (a.stage != 0) block_sum_store<T2, NT>(part, red, reinterpret_cast<T2 *>(a.part_out) + tile_id);
+    if (a.stage != 0) block_sum_store<T2, NT>(part, L.red, reinterpret_cast<T2 *>(a.part_out) + tile_id);
+}
+
+// Discrete adjoint of one classical RK4 stage (reverse order 4, 3, 2, 1). With x_in holding
+// (s, c, w s, w c) at the stage state Y_i, w = K scale_m l_i, the gathers give (A s, A c, A ws,
+// A wc) and, for symmetric A,
+//   (J^T l_i)_m = c_m (A wc)_m + s_m (A ws)_m - w_m (c_m (A c)_m + s_m (A s)_m)      (= mu_i)
+//   dF_m/dK     = scale_m ((A s)_m c_m - (A c)_m s_m),
+// obtained by differentiating eq. KuramotoGraph term by term. The epilogue accumulates
+// lam_acc += mu_i, g_omega += l_i, dK += l_i dF/dK, and forms l_{i-1} = a dt lam + b dt mu_i
+// and the next stage's x; at stage 1 it stores the new lam = lam_acc.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_vjp(DevGraph g, VjpArgs<T> a)
+{
+    using T2 = typename V2<T>::type;
+    using T4 = typename VecT<T, 2>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    TileLds<T4, NT> L(smem, g.W, g.tile_rows);
+    const int tile_id = g.order[blockIdx.x];
+    const Tile tl = g.tiles[tile_id];
+    const BlkInfo bi = g.blk[tl.block];
+    const int nrows = tl.r1 - tl.r0;
+    const int rowbase = bi.row0 + tl.r0;
+    const T4 *__restrict__ x_in = reinterpret_cast<const T4 *>(a.x_in);
+
+    tile_gather<T, NT, 2>(g, tl, bi, x_in, reinterpret_cast<const T4 *>(a.part_in), L);
+
+    T4 base = vzero<T4>();
+    if (bi.mode) base = L.red[NT / 64];
+    T4 part = vzero<T4>();
+    double gk = 0.0;
+    for (int r = threadIdx.x; r < nrows; r += NT) {
+        const int m = rowbase + r;
+        const T4 xm = x_in[m];
+        const T s = xm.x, c = xm.y;
+        const T As = base.x + L.acc[r].x, Ac = base.y + L.acc[r].y;
+        const T Aws = base.z + L.acc[r].z, Awc = base.w + L.acc[r].w;
+        const T unit = a.unit ? a.unit[m] : a.inv_n;
+        const T l = a.lbuf[m];
+        const T w = a.K * unit * l;
+        const T mu = c * Awc + s * Aws - w * (c * Ac + s * As);
+        const T dfdk = unit * (As * c - Ac * s);
+        a.g_omega[m] += (double)l;
+        gk += (double)l * (double)dfdk;
+        const T la = a.lam_acc[m] + mu;
+        if (a.stage > 1) {
+            a.lam_acc[m] = la;
+            const T ln = a.cl * a.lam[m] + a.cm * mu;
+            a.lbuf[m] = ln;
+            const T wn = a.K * unit * ln;
+            const T2 scn = reinterpret_cast<const T2 *>(a.sc_next)[m];
+            T4 xn;
+            xn.x = scn.x;
+            xn.y = scn.y;
+            xn.z = wn * scn.x;
+            xn.w = wn * scn.y;
+            reinterpret_cast<T4 *>(a.x_out)[m] = xn;
+            vacc(part, xn);
+        } else {
+            a.lam[m] = la;
+        }
+    }
+    if (a.stage > 1) block_sum_store<T4, NT>(part, L.red, reinterpret_cast<T4 *>(a.part_out) + tile_id);
+    // the tile's dK contribution, accumulated over all launches in a fixed order
+    __shared__ double gks[NT / 64];
+    gk = wave_sum(gk);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) gks[threadIdx.x >> 6] = gk;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = gks[0];
+        for (int i = 1; i < NT / 64; ++i) t += gks[i];
+        a.gk_part[tile_id] += t;
+    }
+}
+
+// Start of a reverse RK4 step: l_4 = dt/6 lam, lam_acc = lam, x = (s, c, w s, w c) at Y_4.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_vjp_init(const Tile *__restrict__ tiles, const BlkInfo *__restrict__ blk,
+                                                 VjpArgs<T> a)
+{
+    using T2 = typename V2<T>::type;
+    using T4 = typename VecT<T, 2>::type;
+    __shared__ T4 red[NT / 64];
+    const int t = blockIdx.x;
+    const Tile tl = tiles[t];
+    const int row0 = blk[tl.block].row0 + tl.r0;
+    const int nrows = tl.r1 - tl.r0;
+    T4 part = vzero<T4>();
+    for (int r = threadIdx.x; r < nrows; r += NT) {
+        const int m = row0 + r;
+        const T lam = a.lam[m];
+        const T l4 = a.cl * lam;
+        a.lbuf[m] = l4;
+        a.lam_acc[m] = lam;
+        const T w = a.K * (a.unit ? a.unit[m] : a.inv_n) * l4;
+        const T2 sc = reinterpret_cast<const T2 *>(a.sc_next)[m];
+        T4 x;
+        x.x = sc.x;
+        x.y = sc.y;
+        x.z = w * sc.x;
+        x.w = w * sc.y;
+        reinterpret_cast<T4 *>(a.x_out)[m] = x;
+        vacc(part, x);
+    }
+    block_sum_store<T4, NT>(part, red, reinterpret_cast<T4 *>(a.part_out) + t);
 }
 
 // r e^{i psi} = (1/N) sum_m e^{i theta_m} from the tile partials (Sec. 2, eq. OrderParameter).
@@ -500,10 +670,14 @@ hipError_t launch_sc_init(const DevGraph &g, int ntiles, const T *y, void *sc, v
     return hipGetLastError();
 }
 
-size_t rows_lds_bytes(int elem_bytes, int W, int tile_rows, int threads)
+// dynamic LDS limit requested for the tile kernels (the rest of the 160 KiB stays for static use)
+constexpr int kMaxDynLds = 156 * 1024;
+
+size_t rows_lds_bytes(int elem_bytes, int W, int tile_rows, int threads, int nv)
 {
-    size_t b = (size_t)(W + 1) * 2 * elem_bytes + (size_t)2 * tile_rows * elem_bytes +
-               (size_t)(threads / 64 + 1) * 2 * elem_bytes + (size_t)(tile_rows + 1) * 4;
+    const size_t vt = (size_t)2 * nv * elem_bytes;
+    size_t b = (size_t)(W + 1) * vt + (size_t)tile_rows * vt + (size_t)(threads / 64 + 1) * vt +
+               (size_t)(tile_rows + 1) * 4;
     return (b + 15) & ~size_t(15);
 }
 
@@ -518,7 +692,7 @@ hipError_t launch_rows(const DevGraph &g, int ntiles, const RowArgs<T> &a, int t
         const void *fn = threads == 256 ? reinterpret_cast<const void *>(&k_rows<T, 256>)
                          : threads == 1024 ? reinterpret_cast<const void *>(&k_rows<T, 1024>)
                                            : reinterpret_cast<const void *>(&k_rows<T, 512>);
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         if (e != hipSuccess) return e;
         attr_done[slot] = true;
     }
@@ -526,6 +700,41 @@ hipError_t launch_rows(const DevGraph &g, int ntiles, const RowArgs<T> &a, int t
     case 256: hipLaunchKernelGGL((k_rows<T, 256>), dim3(ntiles), dim3(256), lds, st, g, a); break;
     case 1024: hipLaunchKernelGGL((k_rows<T, 1024>), dim3(ntiles), dim3(1024), lds, st, g, a); break;
     default: hipLaunchKernelGGL((k_rows<T, 512>), dim3(ntiles), dim3(512), lds, st, g, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_vjp(const DevGraph &g, int ntiles, const VjpArgs<T> &a, int threads, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const size_t lds = rows_lds_bytes(sizeof(T), g.W, g.tile_rows, threads, 2);
+    static bool attr_done[3] = {false, false, false};
+    const int slot = threads == 256 ? 0 : threads == 1024 ? 2 : 1;
+    if (!attr_done[slot]) {
+        const void *fn = threads == 256 ? reinterpret_cast<const void *>(&k_vjp<T, 256>)
+                         : threads == 1024 ? reinterpret_cast<const void *>(&k_vjp<T, 1024>)
+                                           : reinterpret_cast<const void *>(&k_vjp<T, 512>);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+        if (e != hipSuccess) return e;
+        attr_done[slot] = true;
+    }
+    switch (threads) {
+    case 256: hipLaunchKernelGGL((k_vjp<T, 256>), dim3(ntiles), dim3(256), lds, st, g, a); break;
+    case 1024: hipLaunchKernelGGL((k_vjp<T, 1024>), dim3(ntiles), dim3(1024), lds, st, g, a); break;
+    default: hipLaunchKernelGGL((k_vjp<T, 512>), dim3(ntiles), dim3(512), lds, st, g, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_vjp_init(const DevGraph &g, int ntiles, const VjpArgs<T> &a, int threads, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    switch (threads) {
+    case 256: hipLaunchKernelGGL((k_vjp_init<T, 256>), dim3(ntiles), dim3(256), 0, st, g.tiles, g.blk, a); break;
+    case 1024: hipLaunchKernelGGL((k_vjp_init<T, 1024>), dim3(ntiles), dim3(1024), 0, st, g.tiles, g.blk, a); break;
+    default: hipLaunchKernelGGL((k_vjp_init<T, 512>), dim3(ntiles), dim3(512), 0, st, g.tiles, g.blk, a); break;
     }
     return hipGetLastError();
 }
@@ -552,6 +761,10 @@ template hipError_t launch_sc_init<float>(const DevGraph &, int, const float *, 
 template hipError_t launch_sc_init<double>(const DevGraph &, int, const double *, void *, void *, int, hipStream_t);
 template hipError_t launch_rows<float>(const DevGraph &, int, const RowArgs<float> &, int, hipStream_t);
 template hipError_t launch_rows<double>(const DevGraph &, int, const RowArgs<double> &, int, hipStream_t);
+template hipError_t launch_vjp<float>(const DevGraph &, int, const VjpArgs<float> &, int, hipStream_t);
+template hipError_t launch_vjp<double>(const DevGraph &, int, const VjpArgs<double> &, int, hipStream_t);
+template hipError_t launch_vjp_init<float>(const DevGraph &, int, const VjpArgs<float> &, int, hipStream_t);
+template hipError_t launch_vjp_init<double>(const DevGraph &, int, const VjpArgs<double> &, int, hipStream_t);
 template hipError_t launch_order<float>(const void *, int, int64_t, double *, double *, int64_t, hipStream_t);
 template hipError_t launch_order<double>(const void *, int, int64_t, double *, double *, int64_t, hipStream_t);
 template hipError_t launch_phase_out<float>(int64_t, const void *, const void *, const int32_t *, int, void *, hipStream_t);

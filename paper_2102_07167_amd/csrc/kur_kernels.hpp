@@ -23,13 +23,14 @@ struct DevGraph {
 };
 
 // Arguments of one row-kernel launch (one RK stage, or a plain evaluation when stage == 0).
+// The coupling factor of row m is K * unit[m] (unit = 1/deg_m) or K * inv_n when unit is null.
 template <typename T>
 struct RowArgs {
     int stage;          // 0: write F to kout; 1..4: classical RK4 stage
     int compensate;     // compensated phase update in stage 4
     T dt, half_dt, dt6; // dt, dt/2, dt/6
-    T kscale;           // K/N when rowscale == nullptr
-    const T *rowscale;  // per-row coupling factor (K/deg_m), or nullptr
+    T K, inv_n;
+    const T *unit;
     const T *omega;
     T *hi;              // wrapped phase
     T *lo;              // compensation term
@@ -42,6 +43,24 @@ struct RowArgs {
     void *part_out;
 };
 
+// Arguments of one reverse RK4 stage (Jacobian-transpose product and adjoint bookkeeping).
+template <typename T>
+struct VjpArgs {
+    int stage;          // 4, 3, 2, 1 (k_vjp); unused by k_vjp_init
+    T K, inv_n;
+    const T *unit;
+    T cl, cm;           // l_{i-1} = cl * lam + cm * mu_i (k_vjp); l_4 = cl * lam (k_vjp_init)
+    const void *x_in;   // (s, c, w s, w c) at Y_i
+    const void *part_in;
+    void *x_out;        // the same for the next stage
+    void *part_out;
+    const void *sc_next;// (sin, cos) of the next stage's state
+    T *lam;             // dL/dtheta at the end of the step; the start of the step after stage 1
+    T *lam_acc;         // lam + sum of mu_i
+    T *lbuf;            // l_i
+    double *g_omega;    // dL/domega, accumulated
+    double *gk_part;    // per tile dL/dK, accumulated
+};
 template <typename T>
 hipError_t launch_sc_init(const DevGraph &g, int ntiles, const T *y, void *sc, void *part, int threads, hipStream_t st);
 template <typename T>
@@ -52,7 +71,13 @@ template <typename T>
 hipError_t launch_phase_out(int64_t n, const void *hi, const void *lo, const int32_t *wind, int unwrapped, void *out,
                             hipStream_t st);
 
-size_t rows_lds_bytes(int elem_bytes, int W, int tile_rows, int threads);
+template <typename T>
+hipError_t launch_vjp(const DevGraph &g, int ntiles, const VjpArgs<T> &a, int threads, hipStream_t st);
+template <typename T>
+hipError_t launch_vjp_init(const DevGraph &g, int ntiles, const VjpArgs<T> &a, int threads, hipStream_t st);
+
+// Dynamic LDS bytes of a tile workgroup gathering nv (sin, cos)-sized pairs per node.
+size_t rows_lds_bytes(int elem_bytes, int W, int tile_rows, int threads, int nv = 1);
 double two_pi_p1(int elem_bytes);
 double two_pi_p2(int elem_bytes);
 

@@ -49,6 +49,7 @@ SIGNATURES = {
     "kur_set_state": (ST, [P, P, ctypes.c_size_t]),
     "kur_sync": (ST, [P]),
     "kur_kernel_time": (ST, [P, P, P]),
+    "kur_adjoint_rk4": (ST, [P, P, F64, I64, I64, P, P, P, P]),
     "kur_eval_rhs_dev": (ST, [P, P, P]),
     "kur_get_phases_dev": (ST, [P, P]),
 }
@@ -162,9 +163,10 @@ class Kuramoto:
             self.set_graph_csr(graph.n, graph.row_ptr, graph.col, graph.labels)
 
     def graph_info(self) -> dict:
-        out = np.zeros(8, dtype=np.int64)
+        out = np.zeros(10, dtype=np.int64)
         self._chk(self._L.kur_graph_info(self._h, _ptr(out)))
-        keys = ["n", "blocks", "dense_blocks", "list_entries", "list_padded", "inter_entries", "tiles", "chunk"]
+        keys = ["n", "blocks", "dense_blocks", "list_entries", "list_padded", "inter_entries", "tiles", "chunk",
+                "symmetric", "max_block"]
         return {k: int(v) for k, v in zip(keys, out)}
 
     def perm(self) -> np.ndarray:
@@ -230,6 +232,17 @@ class Kuramoto:
     def set_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         self._chk(self._L.kur_set_state(self._h, buf, len(blob)))
+
+    def adjoint_rk4(self, dt: float, nsteps: int, dl_dthetaT, theta0=None, ckpt_every: int = 32):
+        """(dL/dtheta0, dL/domega, dL/dK) of a loss on theta(T) after nsteps RK4 steps from theta0."""
+        seed = _f64(dl_dthetaT, self.n)
+        th0 = None if theta0 is None else _f64(theta0, self.n)
+        gt = np.empty(self.n)
+        gw = np.empty(self.n)
+        gk = F64()
+        self._chk(self._L.kur_adjoint_rk4(self._h, _ptr(th0), float(dt), int(nsteps), int(ckpt_every), _ptr(seed),
+                                          _ptr(gt), _ptr(gw), ctypes.byref(gk)))
+        return gt, gw, gk.value
 
     def sync(self):
         self._chk(self._L.kur_sync(self._h))

@@ -1,0 +1,146 @@
+"""GPU adjoint: the discrete adjoint of the RK4 trajectory against the oracle's discrete adjoint,
+exact cases, central differences of the GPU FP64 forward, and the autograd wrapper.
+
+Tolerances: FP64 vs oracle adjoint max |dg| <= 1e-10 max |g| (both are the same discrete
+adjoint; the difference is rounding); FP32 vs oracle <= 1e-3 max |g|. Central differences with
+h = 1e-6 on the FP64 forward carry an error of about eps |L| / h + O(h^2), so they are compared
+to 1e-4 of max(|g_fd|, 1e-2 max |g|) plus 50 eps |L| / h.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from paper_2102_07167_amd import Kuramoto
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+def ctx(w, dtype, **opts):
+    k = Kuramoto(dtype, device=0)
+    for key, v in opts.items():
+        k.set_option(key, v)
+    k.set_graph(w.graph)
+    k.set_params(w.omega, w.K)
+    k.set_phases(w.theta0)
+    return k
+
+
+def ragged_sbm(seed=3):
+    rng = np.random.default_rng(seed)
+    sizes = np.array([150, 1, 97, 260, 33])
+    rho = np.array([0.9, 0.5, 0.35, 0.7, 1.0])
+    n = int(sizes.sum())
+    g = gen.sbm(sizes, rho, 0.02, key=777, uperm=rng.permutation(n).astype(np.int32))
+    return gen.Workload("ragged", g, rng.standard_normal(n), rng.uniform(0, 2 * np.pi, n), 2.5, 0.02, 30,
+                        target=rng.uniform(0, 2 * np.pi, n))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ckpt", [1, 7, 100])
+@pytest.mark.parametrize("opts", [dict(), dict(chunk=64, tile_rows=64, flat_min_vec=0.5), dict(scaling=1)])
+def test_adjoint_matches_oracle(need_gpu, dtype, ckpt, opts):
+    w = ragged_sbm()
+    scaling = opts.get("scaling", 0)
+    if dtype == "f32":
+        w.omega = w.omega.astype(np.float32).astype(np.float64)
+        w.theta0 = w.theta0.astype(np.float32).astype(np.float64)
+    thT, _, _ = oracle.rk4(w.graph, w.omega, w.K, w.theta0, w.dt, w.steps, scaling=scaling)
+    _, seed = oracle.loss_and_seed(thT, w.target)
+    gt_o, gw_o, gk_o = oracle.adjoint_rk4(w.graph, w.omega, w.K, w.theta0, w.dt, w.steps, seed, scaling=scaling)
+    with ctx(w, dtype, **opts) as k:
+        assert k.graph_info()["symmetric"] == 1
+        gt, gw, gk = k.adjoint_rk4(w.dt, w.steps, seed, theta0=w.theta0, ckpt_every=ckpt)
+    tol = 1e-10 if dtype == "f64" else 1e-3
+    for a, b in ((gt, gt_o), (gw, gw_o)):
+        assert np.abs(a - b).max() <= tol * np.abs(b).max(), (np.abs(a - b).max(), np.abs(b).max())
+    assert abs(gk - gk_o) <= tol * max(abs(gk_o), np.abs(gw_o).max())
+
+
+def test_adjoint_exact_cases(need_gpu):
+    """L = sum theta(T): dL/dtheta0 = 1, dL/domega = T, dL/dK = 0 (linear invariant, symmetric A,
+    uniform scaling); K = 0: dL/dtheta0 = seed, dL/domega = T seed."""
+    w = ragged_sbm(5)
+    n, steps, dt = w.graph.n, 40, 0.02
+    with ctx(w, "f64") as k:
+        gt, gw, gk = k.adjoint_rk4(dt, steps, np.ones(n), theta0=w.theta0, ckpt_every=9)
+        assert np.abs(gt - 1).max() < 1e-12 and np.abs(gw - steps * dt).max() < 1e-12 and abs(gk) < 1e-11
+        seed = np.random.default_rng(1).standard_normal(n)
+        k.set_params(w.omega, 0.0)
+        gt, gw, gk = k.adjoint_rk4(dt, steps, seed, theta0=w.theta0, ckpt_every=40)
+        assert np.abs(gt - seed).max() < 1e-13 and np.abs(gw - steps * dt * seed).max() < 1e-12
+        # no steps: the seed comes back unchanged
+        gt, gw, gk = k.adjoint_rk4(dt, 0, seed, theta0=w.theta0)
+        assert np.array_equal(gt, seed) and not gw.any() and gk == 0.0
+
+
+def test_adjoint_rejects_asymmetric(need_gpu):
+    from paper_2102_07167_amd.kur import KurError, KUR_EINVAL
+    rng = np.random.default_rng(2)
+    g = gen.random_dense(40, 0.3, rng, symmetric=False)
+    with Kuramoto("f64", device=0) as k:
+        k.set_graph(g)
+        k.set_params(np.zeros(40), 1.0)
+        k.set_phases(np.zeros(40))
+        assert k.graph_info()["symmetric"] == 0
+        with pytest.raises(KurError) as ei:
+            k.adjoint_rk4(0.1, 3, np.ones(40))
+        assert ei.value.status == KUR_EINVAL
+
+
+def _loss(k, w, th0, om, K, steps):
+    k.set_params(om, K)
+    k.set_phases(th0)
+    k.step_rk4(w.dt, steps)
+    return oracle.loss_and_seed(k.get_phases(), w.target)
+
+
+def test_adjoint_config5_central_differences(need_gpu):
+    """Equal-community SBM N = 65536 (64 x 1024), 2000 steps of dt 0.01, checkpoint every 32,
+    loss (1 - r(T))^2 + mean chordal distance to seeded targets: 16 theta0, 15 omega coordinates
+    and K against central differences (h = 1e-6) of the GPU FP64 forward."""
+    w = gen.sbm_equal(steps=2000, seed=1005)
+    steps = w.steps
+    with ctx(w, "f64") as k:
+        L0, seed = _loss(k, w, w.theta0, w.omega, w.K, steps)
+        gt, gw, gk = k.adjoint_rk4(w.dt, steps, seed, theta0=w.theta0, ckpt_every=32)
+        rng = np.random.default_rng(55)
+        h = 1e-6
+        gmax = max(np.abs(gt).max(), np.abs(gw).max())
+        noise = 50 * EPS * abs(L0) / h
+        for j in rng.choice(w.graph.n, 16, replace=False):
+            e = np.zeros(w.graph.n)
+            e[j] = h
+            fd = (_loss(k, w, w.theta0 + e, w.omega, w.K, steps)[0] - _loss(k, w, w.theta0 - e, w.omega, w.K, steps)[0]) / (2 * h)
+            assert abs(gt[j] - fd) <= 1e-4 * max(abs(fd), 1e-2 * gmax) + noise, (j, gt[j], fd)
+        for j in rng.choice(w.graph.n, 15, replace=False):
+            e = np.zeros(w.graph.n)
+            e[j] = h
+            fd = (_loss(k, w, w.theta0, w.omega + e, w.K, steps)[0] - _loss(k, w, w.theta0, w.omega - e, w.K, steps)[0]) / (2 * h)
+            assert abs(gw[j] - fd) <= 1e-4 * max(abs(fd), 1e-2 * gmax) + noise, (j, gw[j], fd)
+        fd = (_loss(k, w, w.theta0, w.omega, w.K + h, steps)[0] - _loss(k, w, w.theta0, w.omega, w.K - h, steps)[0]) / (2 * h)
+        assert abs(gk - fd) <= 1e-4 * max(abs(fd), 1e-2 * gmax) + noise, (gk, fd)
+
+
+def test_autograd_function(need_gpu):
+    import torch
+    from paper_2102_07167_amd.autograd import integrate, order_parameter
+    w = ragged_sbm(9)
+    with ctx(w, "f64") as k:
+        th0 = torch.tensor(w.theta0, requires_grad=True)
+        om = torch.tensor(w.omega, requires_grad=True)
+        K = torch.tensor(w.K, dtype=torch.float64, requires_grad=True)
+        thT = integrate(k, th0, om, K, w.dt, w.steps, ckpt_every=8)
+        tgt = torch.tensor(w.target)
+        loss = (1 - order_parameter(thT)) ** 2 + (2 * (1 - torch.cos(thT - tgt))).mean()
+        loss.backward()
+        thT_o, _, _ = oracle.rk4(w.graph, w.omega, w.K, w.theta0, w.dt, w.steps)
+        L_o, seed = oracle.loss_and_seed(thT_o, w.target)
+        assert abs(loss.item() - L_o) < 1e-12
+        gt_o, gw_o, gk_o = oracle.adjoint_rk4(w.graph, w.omega, w.K, w.theta0, w.dt, w.steps, seed)
+        assert np.abs(th0.grad.numpy() - gt_o).max() <= 1e-10 * np.abs(gt_o).max()
+        assert np.abs(om.grad.numpy() - gw_o).max() <= 1e-10 * np.abs(gw_o).max()
+        assert abs(K.grad.item() - gk_o) <= 1e-10 * max(abs(gk_o), 1e-3)
