@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--option", action="append", default=[], help="library option key=value")
+    ap.add_argument("--adjoint-steps", type=int, default=64,
+                    help="steps of the timed adjoint leg (0 skips it); checkpoints every 32 steps")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -197,6 +199,25 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_rows", "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": b_eval},
     }
+    if args.adjoint_steps > 0:
+        import numpy as np
+        na, ck = args.adjoint_steps, 32
+        seed = np.random.default_rng(7).standard_normal(w.graph.n) / w.graph.n
+        k.adjoint_rk4(w.dt, min(na, 4), seed, theta0=w.theta0, ckpt_every=ck)  # warm-up
+        k.set_phases(w.theta0)
+        k.sync()
+        t0 = time.perf_counter()
+        k.step_rk4(w.dt, na)
+        k.sync()
+        t_fwd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        gt, gw, gk = k.adjoint_rk4(w.dt, na, seed, theta0=w.theta0, ckpt_every=ck)
+        t_adj = time.perf_counter() - t0
+        assert np.isfinite(gt).all() and np.isfinite(gw).all() and math.isfinite(gk)
+        out["adjoint"] = {"steps": na, "ckpt_every": ck, "fwd_ms": 1e3 * t_fwd, "adjoint_ms": 1e3 * t_adj,
+                          "ratio": t_adj / t_fwd,
+                          "note": "adjoint = forward with checkpoints + per-segment recompute + 4 VJP stages per step"}
+        log("adjoint %d steps: %.1f ms vs forward %.1f ms (ratio %.2f)" % (na, 1e3 * t_adj, 1e3 * t_fwd, t_adj / t_fwd))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, %.0f s budget)" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

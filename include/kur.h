@@ -87,7 +87,10 @@ const char *kur_last_error(const kur_ctx *ctx);
  *   "scaling"     0: K/N (uniform, default); 1: K/deg_m (non-uniform). Immediate.
  *   "compensate"  1: compensated phase update with winding (default); 0: plain update. Immediate.
  *   "timing"      1: time every launch of the row kernel with HIP events (see kur_kernel_time).
- *                 Immediate.
+ *                 Immediate; disables graph replay while on.
+ *   "graph"       1 (default): kur_step_rk4 captures one sampling period (r_every steps, else
+ *                 "graph_steps" steps) into a HIP graph and replays it; 0: plain launches.
+ *   "graph_steps" steps per replayed graph when no order parameter is sampled (default 16).
  * Unknown keys and out-of-range values return KUR_EINVAL.
  */
 kur_status kur_set_option(kur_ctx *ctx, const char *key, double value);
@@ -125,6 +128,34 @@ kur_status kur_set_graph_csr(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, co
 kur_status kur_set_graph(kur_ctx *ctx, int64_t n, int32_t nb, const int64_t *block_ptr,
                          const uint8_t *mode, const int64_t *list_ptr, const uint16_t *list_col,
                          const int64_t *inter_ptr, const int32_t *inter_col, const int32_t *perm);
+
+/* The complete graph on n nodes (the classical all-to-all model of Sec. 2, eq. Kuramoto): one
+ * dense block with an empty list of zeros, so F = omega + K (S cos theta - C sin theta) with the
+ * global order parameters (Sec. 2, eq. KuramotoReformulation). */
+kur_status kur_set_graph_complete(kur_ctx *ctx, int64_t n);
+
+/*
+ * Batches of independent instances integrated together (ensembles, K sweeps): the instances
+ * form one block-diagonal graph, every row carries its instance's factor K_i / N_i, and the
+ * order parameter is sampled per instance.
+ *   kur_batch_begin   starts a new batch (drops instances added earlier)
+ *   kur_batch_add     appends one instance: n oscillators, complete != 0 for all-to-all
+ *                     (row_ptr, col, labels ignored) or a CSR in the instance's own numbering with
+ *                     labels as for kur_set_graph_csr; its K, omega (n) and theta0 (n). The
+ *                     instance's preprocessing runs here, so the caller may free its arrays.
+ *   kur_batch_commit  installs the union as the context's graph, with the instances' omega and
+ *                     theta0 in user order (instance 0 first) and K = 1 as a global factor.
+ *   kur_batch_info    number of instances and their first user node (n_inst + 1 entries).
+ *   kur_batch_step    like kur_step_rk4; r_out/psi_out receive (nsteps/r_every + 1) x n_inst
+ *                     values, sample-major.
+ * The adjoint is not available for a batch.
+ */
+kur_status kur_batch_begin(kur_ctx *ctx);
+kur_status kur_batch_add(kur_ctx *ctx, int64_t n, int complete, const int64_t *row_ptr, const int32_t *col,
+                         const int32_t *labels, double K, const double *omega, const double *theta0);
+kur_status kur_batch_commit(kur_ctx *ctx);
+kur_status kur_batch_info(const kur_ctx *ctx, int32_t *n_inst, int64_t *row_first);
+kur_status kur_batch_step(kur_ctx *ctx, double dt, int64_t nsteps, int64_t r_every, double *r_out, double *psi_out);
 
 /* Graph statistics after kur_set_graph*: out[0..9] = n, nb, dense blocks, list entries
  * (unpadded), list entries (padded, as stored), inter entries, tiles, chunk width, 1 if the

@@ -285,13 +285,135 @@ std::string finish(BlockGraph &g, const std::vector<int32_t> &block_of_row, cons
         }
         b.ntiles = (int32_t)g.tiles.size() - b.tile0;
     }
-    g.order.resize(g.tiles.size());
-    std::iota(g.order.begin(), g.order.end(), 0);
-    std::stable_sort(g.order.begin(), g.order.end(), [&](int32_t a, int32_t b) { return tcost[a] > tcost[b]; });
+    (void)tcost;
+    order_tiles(g);
     return "";
 }
 
 }  // namespace
+
+void order_tiles(BlockGraph &g)
+{
+    std::vector<int64_t> cost(g.tiles.size());
+    for (size_t t = 0; t < g.tiles.size(); ++t) {
+        const Tile &tl = g.tiles[t];
+        const BlkInfo &b = g.blk[tl.block];
+        int64_t c = 32 * (int64_t)(tl.r1 - tl.r0);
+        int64_t nonempty = 0;
+        for (int32_t ch = 0; ch < b.nchunk; ++ch) {
+            const int64_t s0 = g.seg_ptr[b.segbase + (int64_t)ch * b.size + tl.r0];
+            const int64_t s1 = g.seg_ptr[b.segbase + (int64_t)ch * b.size + tl.r1];
+            c += s1 - s0;
+            nonempty += (s1 > s0);
+        }
+        c += 4 * (g.inter_ptr[b.row0 + tl.r1] - g.inter_ptr[b.row0 + tl.r0]);
+        cost[t] = c + (int64_t)b.size * nonempty / 4;
+    }
+    g.order.resize(g.tiles.size());
+    std::iota(g.order.begin(), g.order.end(), 0);
+    std::stable_sort(g.order.begin(), g.order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+}
+
+std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &g)
+{
+    if (n < 1 || n > INT32_MAX - 1) return "n must be in [1, 2^31-2]";
+    if ((int64_t)opt.W * opt.esz2 > 65535) return "chunk too wide for 16-bit LDS byte offsets";
+    g = BlockGraph();
+    g.n = n;
+    g.nb = 1;
+    g.W = opt.W;
+    g.tile_rows = opt.tile_rows;
+    g.esz2 = opt.esz2;
+    g.perm.resize(n);
+    std::iota(g.perm.begin(), g.perm.end(), 0);
+    BlkInfo b{};
+    b.row0 = 0;
+    b.size = (int32_t)n;
+    b.nchunk = (int32_t)((n + opt.W - 1) / opt.W);
+    b.mode = n >= 2 ? 1 : 0;
+    b.segbase = 0;
+    g.blk.push_back(b);
+    g.seg_ptr.assign((size_t)b.nchunk * n + 1, 0);
+    g.inter_ptr.assign(n + 1, 0);
+    g.deg.assign(n, (int32_t)std::min<int64_t>(n - 1, INT32_MAX));
+    g.n_dense = b.mode;
+    g.symmetric = true;
+    // tiles: only the epilogue works per row, so use full-size tiles
+    g.blk[0].tile0 = 0;
+    for (int64_t r = 0; r < n; r += opt.tile_rows)
+        g.tiles.push_back(Tile{0, (int32_t)r, (int32_t)std::min<int64_t>(n, r + opt.tile_rows), 2});
+    g.blk[0].ntiles = (int32_t)g.tiles.size();
+    order_tiles(g);
+    return "";
+}
+
+std::string merge_graphs(std::vector<BlockGraph> &parts, BlockGraph &g, std::vector<int64_t> &row_first,
+                         std::vector<int64_t> &tile_first)
+{
+    if (parts.empty()) return "no instances";
+    g = BlockGraph();
+    g.W = parts[0].W;
+    g.tile_rows = parts[0].tile_rows;
+    g.esz2 = parts[0].esz2;
+    g.symmetric = true;
+    int64_t n = 0, nb = 0, segs = 0, entries = 0, inter = 0, tiles = 0;
+    for (const BlockGraph &p : parts) {
+        if (p.W != g.W || p.tile_rows != g.tile_rows || p.esz2 != g.esz2) return "instances built with different layouts";
+        n += p.n;
+        nb += p.nb;
+        segs += (int64_t)p.seg_ptr.size() - 1;
+        entries += (int64_t)p.list.size();
+        inter += (int64_t)p.inter_col.size();
+        tiles += (int64_t)p.tiles.size();
+    }
+    if (n > INT32_MAX - 1 || nb > INT32_MAX || tiles > INT32_MAX) return "batch too large";
+    g.n = n;
+    g.nb = (int32_t)nb;
+    g.perm.reserve(n);
+    g.blk.reserve(nb);
+    g.seg_ptr.reserve(segs + 1);
+    g.list.reserve(entries);
+    g.inter_ptr.reserve(n + 1);
+    g.inter_col.reserve(inter);
+    g.tiles.reserve(tiles);
+    g.deg.reserve(n);
+    row_first.assign(1, 0);
+    tile_first.assign(1, 0);
+    g.inter_ptr.push_back(0);
+    int64_t roff = 0, segoff = 0, loff = 0, toff = 0, boff = 0;
+    for (BlockGraph &p : parts) {
+        for (int32_t v : p.perm) g.perm.push_back((int32_t)(v + roff));
+        for (BlkInfo b : p.blk) {
+            b.row0 += (int32_t)roff;
+            b.segbase += segoff;
+            b.tile0 += (int32_t)toff;
+            g.blk.push_back(b);
+        }
+        for (size_t i = 0; i + 1 < p.seg_ptr.size(); ++i) g.seg_ptr.push_back(p.seg_ptr[i] + loff);
+        g.list.insert(g.list.end(), p.list.begin(), p.list.end());
+        for (int64_t m = 0; m < p.n; ++m) g.inter_ptr.push_back(p.inter_ptr[m + 1] + (g.inter_ptr.size() > 0 ? g.inter_ptr[roff] : 0));
+        for (int32_t v : p.inter_col) g.inter_col.push_back((int32_t)(v + roff));
+        for (Tile t : p.tiles) {
+            t.block += (int32_t)boff;
+            g.tiles.push_back(t);
+        }
+        g.deg.insert(g.deg.end(), p.deg.begin(), p.deg.end());
+        g.list_unpadded += p.list_unpadded;
+        g.n_dense += p.n_dense;
+        g.symmetric = g.symmetric && p.symmetric;
+        roff += p.n;
+        segoff += (int64_t)p.seg_ptr.size() - 1;
+        loff += (int64_t)p.list.size();
+        toff += (int64_t)p.tiles.size();
+        boff += p.nb;
+        row_first.push_back(roff);
+        tile_first.push_back(toff);
+        p = BlockGraph();  // release the part
+    }
+    g.seg_ptr.push_back(loff);
+    order_tiles(g);
+    return "";
+}
 
 std::string build_from_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *labels,
                            const BuildOptions &opt, BlockGraph &g)

@@ -65,6 +65,34 @@ struct kur_ctx {
     bool has_params = false, has_phases = false;
     double K = 0.0;
 
+    // instances: a single graph is one instance; a batch is a block-diagonal union
+    int32_t n_inst = 0;
+    bool batch = false;
+    std::vector<int64_t> inst_row_first, inst_tile_first;
+    DevBuf d_tile_first, d_inv_n, d_ctr;
+    // batch under construction
+    std::vector<BlockGraph> pend_graph;
+    std::vector<double> pend_omega, pend_theta, pend_unit;
+    std::vector<double> pend_K;
+    bool pend_open = false;
+
+    // replayed step graph
+    int use_graph = 1;
+    int64_t graph_steps = 16;
+    hipGraphExec_t gexec = nullptr;
+    struct GraphKey {
+        uint64_t gen;
+        double dt;
+        int64_t period;
+        int sample;
+        int cur;
+        bool operator==(const GraphKey &o) const
+        {
+            return gen == o.gen && dt == o.dt && period == o.period && sample == o.sample && cur == o.cur;
+        }
+    } gkey{0, 0.0, 0, 0, 0};
+    uint64_t gen = 1;  // bumped whenever launch arguments may change
+
     // timing of the row kernel
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
@@ -128,8 +156,10 @@ void free_all(kur_ctx *c)
     DevBuf *bufs[] = {&c->d_blk, &c->d_tiles, &c->d_order, &c->d_seg, &c->d_list, &c->d_iptr, &c->d_icol,
                       &c->d_omega, &c->d_unit, &c->d_hi, &c->d_lo, &c->d_wind, &c->d_ksum, &c->d_sc[0],
                       &c->d_sc[1], &c->d_part[0], &c->d_part[1], &c->d_sce, &c->d_parte, &c->d_kout, &c->d_y,
-                      &c->d_r, &c->d_psi};
+                      &c->d_r, &c->d_psi, &c->d_tile_first, &c->d_inv_n, &c->d_ctr};
     for (DevBuf *b : bufs) dfree(*b);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
 }
 
 bool finite_arr(const double *a, int64_t n)
@@ -212,6 +242,8 @@ kur_status need_ready(kur_ctx *c, bool params, bool phases)
 // per-row unit scale 1/deg_m for non-uniform scaling (zero rows: 0, so theta' = omega)
 kur_status set_unit(kur_ctx *c)
 {
+    c->gen++;
+    if (c->batch) return KUR_OK;  // a batch carries its own per-row factors K_i / N_i
     if (c->scaling == 0) {
         dfree(c->d_unit);
         return KUR_OK;
@@ -316,6 +348,18 @@ kur_status sc_init(kur_ctx *c, const void *y, DevBuf &sc, DevBuf &part)
     return KUR_OK;
 }
 
+kur_status upload_instances(kur_ctx *c)
+{
+    std::vector<double> inv(c->n_inst);
+    for (int32_t i = 0; i < c->n_inst; ++i) inv[i] = 1.0 / (double)(c->inst_row_first[i + 1] - c->inst_row_first[i]);
+    hipError_t e;
+    if ((e = upload(c->d_tile_first, c->inst_tile_first.data(), 8 * c->inst_tile_first.size(), c->stream)) != hipSuccess ||
+        (e = upload(c->d_inv_n, inv.data(), 8 * inv.size(), c->stream)) != hipSuccess ||
+        (e = dalloc(c->d_ctr, 64)) != hipSuccess)
+        return hip_fail(c, e, "instance tables");
+    return KUR_OK;
+}
+
 kur_status install_graph(kur_ctx *c, BlockGraph &g)
 {
     const size_t lds = rows_lds_bytes(c->esz, g.W, g.tile_rows, c->threads, 1);
@@ -373,7 +417,16 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
     c->has_phases = false;
     c->sc_valid = false;
     c->cur = 0;
-    if (!c->host_only) return set_unit(c);
+    c->gen++;
+    c->batch = false;
+    c->n_inst = 1;
+    c->inst_row_first = {0, c->n};
+    c->inst_tile_first = {0, (int64_t)c->ntiles};
+    if (!c->host_only) {
+        kur_status s = upload_instances(c);
+        if (s != KUR_OK) return s;
+        return set_unit(c);
+    }
     return KUR_OK;
 }
 
@@ -472,6 +525,7 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
         if (c->has_graph && rows_lds_bytes(c->esz, c->W, c->tile_rows, (int)v, 1) > 156 * 1024)
             return fail(c, KUR_EINVAL, "threads exceed the LDS budget of the current graph layout");
         c->threads = (int)v;
+        c->gen++;
     } else if (k == "scaling") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "scaling must be 0 or 1");
         c->scaling = (int)v;
@@ -479,6 +533,13 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
     } else if (k == "compensate") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "compensate must be 0 or 1");
         c->compensate = (int)v;
+        c->gen++;
+    } else if (k == "graph") {
+        if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "graph must be 0 or 1");
+        c->use_graph = (int)v;
+    } else if (k == "graph_steps") {
+        if (v != (int64_t)v || v < 1 || v > 4096) return fail(c, KUR_EINVAL, "graph_steps must be an integer in [1, 4096]");
+        c->graph_steps = (int64_t)v;
     } else if (k == "timing") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "timing must be 0 or 1");
         if (!c->host_only) {
@@ -603,6 +664,7 @@ kur_status kur_set_params(kur_ctx *c, const double *omega, double K)
     if (e != hipSuccess) return hip_fail(c, e, "omega upload");
     c->K = K;
     c->has_params = true;
+    c->gen++;
     return KUR_OK;
 }
 
@@ -708,6 +770,127 @@ kur_status kur_eval_rhs_dev(kur_ctx *c, const void *theta_dev, void *dtheta_dev)
     return eval_common(c, theta_dev, dtheta_dev);
 }
 
+static hipError_t launch_sample(kur_ctx *c, const int64_t *idx_dev, int64_t idx)
+{
+    return c->esz == 4
+               ? launch_order<float>(c->d_part[c->cur].p, (const int64_t *)c->d_tile_first.p, (const double *)c->d_inv_n.p,
+                                     c->n_inst, (double *)c->d_r.p, (double *)c->d_psi.p, idx_dev, idx, c->stream)
+               : launch_order<double>(c->d_part[c->cur].p, (const int64_t *)c->d_tile_first.p, (const double *)c->d_inv_n.p,
+                                      c->n_inst, (double *)c->d_r.p, (double *)c->d_psi.p, idx_dev, idx, c->stream);
+}
+
+static hipError_t launch_step(kur_ctx *c, const DevGraph &g, double dt)
+{
+    for (int stage = 1; stage <= 4; ++stage) {
+        hipError_t e;
+        if (c->esz == 4) {
+            RowArgs<float> a = row_args<float>(c, stage, dt);
+            e = timed_rows(c, g, &a);
+        } else {
+            RowArgs<double> a = row_args<double>(c, stage, dt);
+            e = timed_rows(c, g, &a);
+        }
+        if (e != hipSuccess) return e;
+        c->cur ^= 1;
+    }
+    if (c->timing && c->ev_used + 16 > 4096) return harvest_events(c);
+    return hipSuccess;
+}
+
+// Capture `period` steps (and, when sampling, the order-parameter kernel with a device-side
+// sample index) into one executable graph, reusing the cached one when nothing changed.
+static hipError_t step_graph(kur_ctx *c, const DevGraph &g, double dt, int64_t period, bool sample)
+{
+    kur_ctx::GraphKey key{c->gen, dt, period, sample ? 1 : 0, c->cur};
+    if (c->gexec && c->gkey == key) return hipSuccess;
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const int cur0 = c->cur;
+    hipError_t le = hipSuccess;
+    for (int64_t s = 0; s < period && le == hipSuccess; ++s) le = launch_step(c, g, dt);
+    if (le == hipSuccess && sample) {
+        le = launch_sample(c, (const int64_t *)c->d_ctr.p, 0);
+        if (le == hipSuccess) le = launch_bump((int64_t *)c->d_ctr.p, c->stream);
+    }
+    c->cur = cur0;  // the capture did not run anything
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(c->stream, &graph);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        c->gexec = nullptr;
+        return e;
+    }
+    c->gkey = key;
+    return hipSuccess;
+}
+
+// Enqueue nsteps RK4 steps with order-parameter samples every r_every steps (all instances).
+static kur_status run_steps(kur_ctx *c, double dt, int64_t nsteps, int64_t r_every)
+{
+    const int64_t nsamp = r_every > 0 ? nsteps / r_every + 1 : 0;
+    hipError_t e;
+    if (nsamp > 0) {
+        if ((e = dalloc(c->d_r, sizeof(double) * nsamp * c->n_inst)) != hipSuccess ||
+            (e = dalloc(c->d_psi, sizeof(double) * nsamp * c->n_inst)) != hipSuccess)
+            return hip_fail(c, e, "r buffer");
+    }
+    if (!c->sc_valid) {
+        kur_status s = sc_init(c, c->d_hi.p, c->d_sc[c->cur], c->d_part[c->cur]);
+        if (s != KUR_OK) return s;
+        c->sc_valid = true;
+    }
+    const DevGraph g = devgraph(c);
+    int64_t done = 0, k = 0;
+    if (r_every > 0) {
+        if ((e = launch_sample(c, nullptr, 0)) != hipSuccess) return hip_fail(c, e, "order parameter launch");
+        k = 1;
+    }
+    const int64_t period = r_every > 0 ? r_every : std::max<int64_t>(1, c->graph_steps);
+    const int64_t reps = nsteps / period;
+    if (c->use_graph && !c->timing && reps >= 2) {
+        if (r_every > 0) {
+            const int64_t one = 1;
+            if ((e = hipMemcpyAsync(c->d_ctr.p, &one, sizeof(one), hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+                (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+                return hip_fail(c, e, "sample counter");
+        }
+        if ((e = step_graph(c, g, dt, period, r_every > 0)) != hipSuccess) return hip_fail(c, e, "step graph");
+        for (int64_t i = 0; i < reps; ++i)
+            if ((e = hipGraphLaunch(c->gexec, c->stream)) != hipSuccess) return hip_fail(c, e, "step graph launch");
+        done = reps * period;  // four stage swaps per step: c->cur is unchanged
+        if (r_every > 0) k += reps;
+    }
+    for (int64_t step = done; step < nsteps; ++step) {
+        if ((e = launch_step(c, g, dt)) != hipSuccess) return hip_fail(c, e, "rk4 stage launch");
+        if (r_every > 0 && (step + 1) % r_every == 0) {
+            if ((e = launch_sample(c, nullptr, k)) != hipSuccess) return hip_fail(c, e, "order parameter launch");
+            ++k;
+        }
+    }
+    return KUR_OK;
+}
+
+static kur_status fetch_samples(kur_ctx *c, int64_t count, double *r_out, double *psi_out)
+{
+    if (count <= 0 || (!r_out && !psi_out)) return KUR_OK;
+    std::vector<double> r(count), p(count);
+    hipError_t e = hipMemcpyAsync(r.data(), c->d_r.p, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p.data(), c->d_psi.p, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "r download");
+    if (r_out) std::memcpy(r_out, r.data(), sizeof(double) * count);
+    if (psi_out) std::memcpy(psi_out, p.data(), sizeof(double) * count);
+    for (int64_t i = 0; i < count; ++i)
+        if (!std::isfinite(r[i])) return fail(c, KUR_ENONFINITE, "non-finite order parameter (phases are not finite)");
+    return KUR_OK;
+}
+
 kur_status kur_step_rk4(kur_ctx *c, double dt, int64_t nsteps, int64_t r_every, double *r_out, double *psi_out)
 {
     if (!c) return KUR_EINVAL;
@@ -716,58 +899,11 @@ kur_status kur_step_rk4(kur_ctx *c, double dt, int64_t nsteps, int64_t r_every, 
     if (nsteps < 0 || r_every < 0) return fail(c, KUR_EINVAL, "nsteps and r_every must be >= 0");
     kur_status s = need_ready(c, true, true);
     if (s != KUR_OK) return s;
-    const int64_t nsamp = r_every > 0 ? nsteps / r_every + 1 : 0;
-    if (nsamp > 0) {
-        hipError_t e;
-        if ((e = dalloc(c->d_r, sizeof(double) * nsamp)) != hipSuccess ||
-            (e = dalloc(c->d_psi, sizeof(double) * nsamp)) != hipSuccess)
-            return hip_fail(c, e, "r buffer");
-    }
-    if (!c->sc_valid) {
-        s = sc_init(c, c->d_hi.p, c->d_sc[c->cur], c->d_part[c->cur]);
-        if (s != KUR_OK) return s;
-        c->sc_valid = true;
-    }
-    DevGraph g = devgraph(c);
-    int64_t k = 0;
-    for (int64_t step = 0; step <= nsteps; ++step) {
-        if (r_every > 0 && step % r_every == 0) {
-            hipError_t e = c->esz == 4
-                               ? launch_order<float>(c->d_part[c->cur].p, c->ntiles, c->n, (double *)c->d_r.p, (double *)c->d_psi.p, k, c->stream)
-                               : launch_order<double>(c->d_part[c->cur].p, c->ntiles, c->n, (double *)c->d_r.p, (double *)c->d_psi.p, k, c->stream);
-            if (e != hipSuccess) return hip_fail(c, e, "order parameter launch");
-            ++k;
-        }
-        if (step == nsteps) break;
-        for (int stage = 1; stage <= 4; ++stage) {
-            hipError_t e;
-            if (c->esz == 4) {
-                RowArgs<float> a = row_args<float>(c, stage, dt);
-                e = timed_rows(c, g, &a);
-            } else {
-                RowArgs<double> a = row_args<double>(c, stage, dt);
-                e = timed_rows(c, g, &a);
-            }
-            if (e != hipSuccess) return hip_fail(c, e, "rk4 stage launch");
-            c->cur ^= 1;
-        }
-        if (c->timing && c->ev_used + 16 > 4096) {
-            hipError_t e = harvest_events(c);
-            if (e != hipSuccess) return hip_fail(c, e, "timing");
-        }
-    }
-    if (nsamp > 0 && (r_out || psi_out)) {
-        std::vector<double> r(nsamp), p(nsamp);
-        hipError_t e = hipMemcpyAsync(r.data(), c->d_r.p, sizeof(double) * nsamp, hipMemcpyDeviceToHost, c->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(p.data(), c->d_psi.p, sizeof(double) * nsamp, hipMemcpyDeviceToHost, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        if (e != hipSuccess) return hip_fail(c, e, "r download");
-        if (r_out) std::memcpy(r_out, r.data(), sizeof(double) * nsamp);
-        if (psi_out) std::memcpy(psi_out, p.data(), sizeof(double) * nsamp);
-        for (int64_t i = 0; i < nsamp; ++i)
-            if (!std::isfinite(r[i])) return fail(c, KUR_ENONFINITE, "non-finite order parameter (phases are not finite)");
-    }
-    return KUR_OK;
+    if (c->batch && r_every > 0 && (r_out || psi_out))
+        return fail(c, KUR_EINVAL, "a batch samples per instance: use kur_batch_step");
+    s = run_steps(c, dt, nsteps, r_every);
+    if (s != KUR_OK) return s;
+    return fetch_samples(c, r_every > 0 ? nsteps / r_every + 1 : 0, r_out, psi_out);
 }
 
 kur_status kur_get_phases(kur_ctx *c, double *theta, int wrapped)
@@ -833,27 +969,22 @@ kur_status kur_order_parameter(kur_ctx *c, double *r, double *psi)
     if (!r || !psi) return fail(c, KUR_EINVAL, "r and psi must not be NULL");
     kur_status s = need_ready(c, false, true);
     if (s != KUR_OK) return s;
-    hipError_t e;
     if (!c->sc_valid) {
         s = sc_init(c, c->d_hi.p, c->d_sc[c->cur], c->d_part[c->cur]);
         if (s != KUR_OK) return s;
         c->sc_valid = true;
     }
-    if ((e = dalloc(c->d_r, sizeof(double) * std::max<size_t>(1, c->d_r.bytes / sizeof(double)))) != hipSuccess ||
-        (e = dalloc(c->d_psi, sizeof(double) * std::max<size_t>(1, c->d_psi.bytes / sizeof(double)))) != hipSuccess)
+    hipError_t e;
+    const size_t need = sizeof(double) * (size_t)c->n_inst;
+    if ((e = dalloc(c->d_r, std::max(need, c->d_r.bytes))) != hipSuccess ||
+        (e = dalloc(c->d_psi, std::max(need, c->d_psi.bytes))) != hipSuccess)
         return hip_fail(c, e, "r buffer");
-    e = c->esz == 4 ? launch_order<float>(c->d_part[c->cur].p, c->ntiles, c->n, (double *)c->d_r.p, (double *)c->d_psi.p, 0, c->stream)
-                    : launch_order<double>(c->d_part[c->cur].p, c->ntiles, c->n, (double *)c->d_r.p, (double *)c->d_psi.p, 0, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "order parameter launch");
-    double rv = 0, pv = 0;
-    e = hipMemcpyAsync(&rv, c->d_r.p, sizeof(double), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(&pv, c->d_psi.p, sizeof(double), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "r download");
-    *r = rv;
-    *psi = pv;
-    if (!std::isfinite(rv)) return fail(c, KUR_ENONFINITE, "non-finite order parameter");
-    return KUR_OK;
+    if ((e = launch_sample(c, nullptr, 0)) != hipSuccess) return hip_fail(c, e, "order parameter launch");
+    std::vector<double> rv(c->n_inst), pv(c->n_inst);
+    s = fetch_samples(c, c->n_inst, rv.data(), pv.data());
+    *r = rv[0];
+    *psi = pv[0];
+    return s;
 }
 
 struct StateHeader {
@@ -1126,6 +1257,7 @@ extern "C" kur_status kur_adjoint_rk4(kur_ctx *c, const double *theta0, double d
     kur_status s = need_ready(c, true, theta0 == nullptr);
     if (s != KUR_OK) return s;
     if (!c->symmetric) return fail(c, KUR_EINVAL, "the adjoint needs a symmetric adjacency");
+    if (c->batch) return fail(c, KUR_EINVAL, "the adjoint of a batch is not supported");
     if (rows_lds_bytes(c->esz, c->W, c->tile_rows, c->threads, 2) > 156 * 1024)
         return fail(c, KUR_EINVAL, "chunk/tile_rows too large for the adjoint's LDS (4 values per node)");
     std::vector<double> th0;
@@ -1145,4 +1277,136 @@ extern "C" kur_status kur_adjoint_rk4(kur_ctx *c, const double *theta0, double d
     } catch (const std::bad_alloc &) {
         return fail(c, KUR_ENOMEM, "host allocation failed in the adjoint");
     }
+}
+
+// ------------------------------------------------------------------------------------------------
+// complete graph and batches of independent instances
+// ------------------------------------------------------------------------------------------------
+
+extern "C" kur_status kur_set_graph_complete(kur_ctx *c, int64_t n)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    BlockGraph g;
+    std::string msg;
+    try {
+        msg = build_complete(n, c->bopt, g);
+    } catch (const std::bad_alloc &) {
+        return fail(c, KUR_ENOMEM, "host allocation failed in graph preprocessing");
+    }
+    if (!msg.empty()) return fail(c, KUR_EINVAL, msg);
+    return install_graph(c, g);
+}
+
+extern "C" kur_status kur_batch_begin(kur_ctx *c)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    c->pend_graph.clear();
+    c->pend_omega.clear();
+    c->pend_theta.clear();
+    c->pend_K.clear();
+    c->pend_open = true;
+    return KUR_OK;
+}
+
+extern "C" kur_status kur_batch_add(kur_ctx *c, int64_t n, int complete, const int64_t *row_ptr, const int32_t *col,
+                                    const int32_t *labels, double K, const double *omega, const double *theta0)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!c->pend_open) return fail(c, KUR_ESTATE, "kur_batch_begin was not called");
+    if (n < 1) return fail(c, KUR_EINVAL, "n must be >= 1");
+    if (!omega || !theta0) return fail(c, KUR_EINVAL, "omega and theta0 must not be NULL");
+    if (!std::isfinite(K)) return fail(c, KUR_EINVAL, "K must be finite");
+    for (int64_t u = 0; u < n; ++u)
+        if (!std::isfinite(omega[u]) || !std::isfinite(theta0[u]) || std::fabs(theta0[u]) > 1e9)
+            return fail(c, KUR_EINVAL, "omega and theta0 must be finite (|theta0| <= 1e9)");
+    BlockGraph g;
+    std::string msg;
+    try {
+        msg = complete ? build_complete(n, c->bopt, g) : build_from_csr(n, row_ptr, col, labels, c->bopt, g);
+    } catch (const std::bad_alloc &) {
+        return fail(c, KUR_ENOMEM, "host allocation failed in graph preprocessing");
+    }
+    if (!msg.empty()) return fail(c, KUR_EINVAL, msg);
+    c->pend_graph.push_back(std::move(g));
+    c->pend_omega.insert(c->pend_omega.end(), omega, omega + n);
+    c->pend_theta.insert(c->pend_theta.end(), theta0, theta0 + n);
+    c->pend_K.push_back(K);
+    return KUR_OK;
+}
+
+extern "C" kur_status kur_batch_commit(kur_ctx *c)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!c->pend_open || c->pend_graph.empty()) return fail(c, KUR_ESTATE, "no instances added");
+    const int64_t ninst = (int64_t)c->pend_graph.size();
+    if (ninst > 65535) return fail(c, KUR_EINVAL, "at most 65535 instances");
+    std::vector<int64_t> nrow(ninst);
+    for (int64_t i = 0; i < ninst; ++i) nrow[i] = c->pend_graph[i].n;
+    BlockGraph g;
+    std::vector<int64_t> row_first, tile_first;
+    std::string msg;
+    try {
+        msg = merge_graphs(c->pend_graph, g, row_first, tile_first);
+    } catch (const std::bad_alloc &) {
+        return fail(c, KUR_ENOMEM, "host allocation failed while merging the batch");
+    }
+    if (!msg.empty()) return fail(c, KUR_EINVAL, msg);
+    std::vector<double> omega, theta, K;
+    omega.swap(c->pend_omega);
+    theta.swap(c->pend_theta);
+    K.swap(c->pend_K);
+    c->pend_graph.clear();
+    c->pend_open = false;
+    kur_status s = install_graph(c, g);
+    if (s != KUR_OK) return s;
+    c->batch = true;
+    c->n_inst = (int32_t)ninst;
+    c->inst_row_first = row_first;
+    c->inst_tile_first = tile_first;
+    if (c->host_only) return KUR_OK;
+    if ((s = upload_instances(c)) != KUR_OK) return s;
+    // per-row coupling K_i / N_i with a global factor K = 1 (block order = user order per instance)
+    std::vector<double> unit(c->n);
+    for (int64_t i = 0; i < ninst; ++i)
+        for (int64_t m = row_first[i]; m < row_first[i + 1]; ++m) unit[m] = K[i] / (double)nrow[i];
+    hipError_t e;
+    if (c->esz == 4) {
+        std::vector<float> tb(c->n);
+        for (int64_t u = 0; u < c->n; ++u) tb[c->perm[u]] = (float)unit[u];
+        e = upload(c->d_unit, tb.data(), 4 * c->n, c->stream);
+    } else {
+        std::vector<double> tb(c->n);
+        for (int64_t u = 0; u < c->n; ++u) tb[c->perm[u]] = unit[u];
+        e = upload(c->d_unit, tb.data(), 8 * c->n, c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "batch coupling upload");
+    if ((s = kur_set_params(c, omega.data(), 1.0)) != KUR_OK) return s;
+    return kur_set_phases(c, theta.data());
+}
+
+extern "C" kur_status kur_batch_info(const kur_ctx *c, int32_t *n_inst, int64_t *row_first)
+{
+    if (!c || !n_inst) return KUR_EINVAL;
+    if (!c->has_graph) return KUR_ESTATE;
+    *n_inst = c->n_inst;
+    if (row_first) std::memcpy(row_first, c->inst_row_first.data(), sizeof(int64_t) * (c->n_inst + 1));
+    return KUR_OK;
+}
+
+extern "C" kur_status kur_batch_step(kur_ctx *c, double dt, int64_t nsteps, int64_t r_every, double *r_out,
+                                     double *psi_out)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!std::isfinite(dt) || dt == 0.0) return fail(c, KUR_EINVAL, "dt must be finite and nonzero");
+    if (nsteps < 0 || r_every < 0) return fail(c, KUR_EINVAL, "nsteps and r_every must be >= 0");
+    kur_status s = need_ready(c, true, true);
+    if (s != KUR_OK) return s;
+    s = run_steps(c, dt, nsteps, r_every);
+    if (s != KUR_OK) return s;
+    return fetch_samples(c, r_every > 0 ? (nsteps / r_every + 1) * c->n_inst : 0, r_out, psi_out);
 }

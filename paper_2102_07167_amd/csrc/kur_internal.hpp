@@ -69,6 +69,18 @@ std::string build_from_blocks(int64_t n, int32_t nb, const int64_t *block_ptr, c
                               const int32_t *inter_col, const int32_t *perm, const BuildOptions &opt,
                               BlockGraph &out);
 
+// The complete graph on n nodes: one dense block whose list of zeros is empty.
+std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &out);
+
+// Block-diagonal union of independent graphs (no edges between parts), part i occupying the
+// user nodes and block-order rows that follow those of parts 0..i-1. row_first[i] and
+// tile_first[i] (size parts+1) receive the row and tile ranges of every part.
+std::string merge_graphs(std::vector<BlockGraph> &parts, BlockGraph &out, std::vector<int64_t> &row_first,
+                         std::vector<int64_t> &tile_first);
+
+// Launch order of tiles: largest estimated cost first (stable).
+void order_tiles(BlockGraph &g);
+
 // Runs f(i) for i in [0, n) on the host threads (static contiguous ranges).
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &f);
 

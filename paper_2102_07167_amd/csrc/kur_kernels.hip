@@ -611,15 +611,20 @@ __global__ __launch_bounds__(NT) void k_vjp_init(const Tile *__restrict__ tiles,
     block_sum_store<T4, NT>(part, red, reinterpret_cast<T4 *>(a.part_out) + t);
 }
 
-// r e^{i psi} = (1/N) sum_m e^{i theta_m} from the tile partials (Sec. 2, eq. OrderParameter).
+// r e^{i psi} = (1/N) sum_m e^{i theta_m} (Sec. 2, eq. OrderParameter) for every instance of a
+// batch (one workgroup each; a single graph is one instance), from the partials of the
+// instance's tiles, accumulated in FP64 in a fixed order. The sample index comes from *idx_dev
+// when given (graph replay), else from idx.
 template <typename T>
-__global__ __launch_bounds__(256) void k_order(const typename V2<T>::type *__restrict__ part, int ntiles, double inv_n,
-                                               double *__restrict__ r_out, double *__restrict__ psi_out,
-                                               int64_t idx)
+__global__ __launch_bounds__(256) void k_order(const typename V2<T>::type *__restrict__ part,
+                                               const int64_t *__restrict__ tile_first, const double *__restrict__ inv_n,
+                                               int n_inst, double *__restrict__ r_out, double *__restrict__ psi_out,
+                                               const int64_t *__restrict__ idx_dev, int64_t idx)
 {
     __shared__ double rs[4], rc[4];
+    const int inst = blockIdx.x;
     double s = 0.0, c = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += 256) {
+    for (int64_t t = tile_first[inst] + threadIdx.x; t < tile_first[inst + 1]; t += 256) {
         s += (double)part[t].x;
         c += (double)part[t].y;
     }
@@ -631,14 +636,16 @@ __global__ __launch_bounds__(256) void k_order(const typename V2<T>::type *__res
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        s = rs[0] + rs[1] + rs[2] + rs[3];
-        c = rc[0] + rc[1] + rc[2] + rc[3];
-        s *= inv_n;
-        c *= inv_n;
-        r_out[idx] = sqrt(s * s + c * c);
-        psi_out[idx] = atan2(s, c);
+        s = (rs[0] + rs[1] + rs[2] + rs[3]) * inv_n[inst];
+        c = (rc[0] + rc[1] + rc[2] + rc[3]) * inv_n[inst];
+        const int64_t k = (idx_dev ? *idx_dev : idx) * n_inst + inst;
+        r_out[k] = sqrt(s * s + c * c);
+        psi_out[k] = atan2(s, c);
     }
 }
+
+// advance the replayed sample counter
+__global__ void k_bump(int64_t *ctr) { *ctr += 1; }
 
 // out[m] = hi + lo (+ 2 pi wind)
 template <typename T>
@@ -740,10 +747,18 @@ hipError_t launch_vjp_init(const DevGraph &g, int ntiles, const VjpArgs<T> &a, i
 }
 
 template <typename T>
-hipError_t launch_order(const void *part, int ntiles, int64_t n, double *r, double *psi, int64_t idx, hipStream_t st)
+hipError_t launch_order(const void *part, const int64_t *tile_first, const double *inv_n, int n_inst, double *r,
+                        double *psi, const int64_t *idx_dev, int64_t idx, hipStream_t st)
 {
     using T2 = typename V2<T>::type;
-    hipLaunchKernelGGL((k_order<T>), dim3(1), dim3(256), 0, st, (const T2 *)part, ntiles, 1.0 / (double)n, r, psi, idx);
+    hipLaunchKernelGGL((k_order<T>), dim3(n_inst), dim3(256), 0, st, (const T2 *)part, tile_first, inv_n, n_inst, r,
+                       psi, idx_dev, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_bump(int64_t *ctr, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bump, dim3(1), dim3(1), 0, st, ctr);
     return hipGetLastError();
 }
 
@@ -765,8 +780,10 @@ template hipError_t launch_vjp<float>(const DevGraph &, int, const VjpArgs<float
 template hipError_t launch_vjp<double>(const DevGraph &, int, const VjpArgs<double> &, int, hipStream_t);
 template hipError_t launch_vjp_init<float>(const DevGraph &, int, const VjpArgs<float> &, int, hipStream_t);
 template hipError_t launch_vjp_init<double>(const DevGraph &, int, const VjpArgs<double> &, int, hipStream_t);
-template hipError_t launch_order<float>(const void *, int, int64_t, double *, double *, int64_t, hipStream_t);
-template hipError_t launch_order<double>(const void *, int, int64_t, double *, double *, int64_t, hipStream_t);
+template hipError_t launch_order<float>(const void *, const int64_t *, const double *, int, double *, double *,
+                                       const int64_t *, int64_t, hipStream_t);
+template hipError_t launch_order<double>(const void *, const int64_t *, const double *, int, double *, double *,
+                                        const int64_t *, int64_t, hipStream_t);
 template hipError_t launch_phase_out<float>(int64_t, const void *, const void *, const int32_t *, int, void *, hipStream_t);
 template hipError_t launch_phase_out<double>(int64_t, const void *, const void *, const int32_t *, int, void *, hipStream_t);
 

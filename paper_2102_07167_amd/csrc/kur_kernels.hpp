@@ -66,7 +66,9 @@ hipError_t launch_sc_init(const DevGraph &g, int ntiles, const T *y, void *sc, v
 template <typename T>
 hipError_t launch_rows(const DevGraph &g, int ntiles, const RowArgs<T> &a, int threads, hipStream_t st);
 template <typename T>
-hipError_t launch_order(const void *part, int ntiles, int64_t n, double *r, double *psi, int64_t idx, hipStream_t st);
+hipError_t launch_order(const void *part, const int64_t *tile_first, const double *inv_n, int n_inst, double *r,
+                        double *psi, const int64_t *idx_dev, int64_t idx, hipStream_t st);
+hipError_t launch_bump(int64_t *ctr, hipStream_t st);
 template <typename T>
 hipError_t launch_phase_out(int64_t n, const void *hi, const void *lo, const int32_t *wind, int unwrapped, void *out,
                             hipStream_t st);

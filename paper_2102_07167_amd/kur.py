@@ -50,6 +50,12 @@ SIGNATURES = {
     "kur_sync": (ST, [P]),
     "kur_kernel_time": (ST, [P, P, P]),
     "kur_adjoint_rk4": (ST, [P, P, F64, I64, I64, P, P, P, P]),
+    "kur_set_graph_complete": (ST, [P, I64]),
+    "kur_batch_begin": (ST, [P]),
+    "kur_batch_add": (ST, [P, I64, ctypes.c_int, P, P, P, F64, P, P]),
+    "kur_batch_commit": (ST, [P]),
+    "kur_batch_info": (ST, [P, P, P]),
+    "kur_batch_step": (ST, [P, F64, I64, I64, P, P]),
     "kur_eval_rhs_dev": (ST, [P, P, P]),
     "kur_get_phases_dev": (ST, [P, P]),
 }
@@ -151,9 +157,8 @@ class Kuramoto:
 
     def set_graph_complete(self, n):
         """All-to-all coupling: one dense block whose list of zeros is empty."""
-        z = np.zeros(n + 1, dtype=np.int64)
-        self.set_graph_blocks(n, np.array([0, n], dtype=np.int64), np.array([1], dtype=np.uint8), z,
-                              np.zeros(1, np.uint16), z, np.zeros(1, np.int32))
+        self._chk(self._L.kur_set_graph_complete(self._h, int(n)))
+        self.n = int(n)
 
     def set_graph(self, graph):
         """Any object with n, labels, row_ptr, col, complete (e.g. a generated graph)."""
@@ -161,6 +166,41 @@ class Kuramoto:
             self.set_graph_complete(graph.n)
         else:
             self.set_graph_csr(graph.n, graph.row_ptr, graph.col, graph.labels)
+
+    def set_batch(self, instances):
+        """instances: iterable of (graph, K, omega, theta0); graph as for set_graph."""
+        self._chk(self._L.kur_batch_begin(self._h))
+        total = 0
+        for graph, K, omega, theta0 in instances:
+            n = int(graph.n)
+            om, th = _f64(omega, n), _f64(theta0, n)
+            if getattr(graph, "complete", False):
+                self._chk(self._L.kur_batch_add(self._h, n, 1, None, None, None, float(K), _ptr(om), _ptr(th)))
+            else:
+                rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int64)
+                cl = np.ascontiguousarray(graph.col, dtype=np.int32)
+                lb = np.ascontiguousarray(graph.labels, dtype=np.int32)
+                self._chk(self._L.kur_batch_add(self._h, n, 0, _ptr(rp), _ptr(cl), _ptr(lb), float(K), _ptr(om),
+                                                _ptr(th)))
+            total += n
+        self._chk(self._L.kur_batch_commit(self._h))
+        self.n = total
+
+    def batch_info(self):
+        ni = ctypes.c_int32(0)
+        self._chk(self._L.kur_batch_info(self._h, ctypes.byref(ni), None))
+        rf = np.empty(ni.value + 1, dtype=np.int64)
+        self._chk(self._L.kur_batch_info(self._h, ctypes.byref(ni), _ptr(rf)))
+        return rf
+
+    def batch_step(self, dt: float, nsteps: int, r_every: int = 0):
+        """Advance every instance; returns r and psi as (samples, instances) arrays (or None)."""
+        ni = len(self.batch_info()) - 1
+        ns = nsteps // r_every + 1 if r_every > 0 else 0
+        r = np.empty((ns, ni)) if ns else None
+        psi = np.empty((ns, ni)) if ns else None
+        self._chk(self._L.kur_batch_step(self._h, float(dt), int(nsteps), int(r_every), _ptr(r), _ptr(psi)))
+        return r, psi
 
     def graph_info(self) -> dict:
         out = np.zeros(10, dtype=np.int64)

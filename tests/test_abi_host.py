@@ -187,3 +187,42 @@ def test_block_form_validation():
             _expect(K.KUR_EINVAL, k.set_graph_blocks, *[args[x] for x in
                                                         ["n", "block_ptr", "mode", "list_ptr", "list_col",
                                                          "inter_ptr", "inter_col"]], args.get("perm"))
+
+
+def test_batch_layout_is_block_diagonal():
+    """A batch is the block-diagonal union of its instances: every instance keeps its own lists
+    and inter-block columns, shifted to its rows; complete instances store no list."""
+    rng = np.random.default_rng(12)
+    parts = []
+    g1 = gen.sbm(np.array([40, 25]), np.array([0.9, 0.3]), 0.05, key=1, uperm=rng.permutation(65).astype(np.int32))
+    parts.append((g1, 1.0, np.zeros(65), np.zeros(65)))
+    parts.append((gen.complete_graph(30), 2.0, np.zeros(30), np.zeros(30)))
+    g3 = gen.sbm(np.array([50]), np.array([0.6]), 0.0, key=3)
+    parts.append((g3, 3.0, np.zeros(50), np.zeros(50)))
+    with host_ctx(chunk=64) as k:
+        k.set_batch(parts)
+        rf = k.batch_info()
+        assert list(rf) == [0, 65, 95, 145]
+        perm = k.perm()
+        for i, (g, *_rest) in enumerate(parts):
+            lo, hi = rf[i], rf[i + 1]
+            assert set(perm[lo:hi]) == set(range(lo, hi))
+            with host_ctx(chunk=64) as k1:
+                if g.complete:
+                    k1.set_graph_complete(g.n)
+                else:
+                    k1.set_graph(g)
+                assert np.array_equal(k1.perm() + lo, perm[lo:hi])
+                for m in range(g.n):
+                    a1, b1 = k1.row_lists(m)
+                    a2, b2 = k.row_lists(m + lo)
+                    assert np.array_equal(a1, a2) and np.array_equal(b1 + lo, b2)
+        info = k.graph_info()
+        assert info["blocks"] == 4 and info["symmetric"] == 1
+
+
+def test_complete_graph_beyond_u16_block():
+    with host_ctx() as k:
+        k.set_graph_complete(70000)
+        info = k.graph_info()
+        assert info["blocks"] == 1 and info["list_entries"] == 0 and info["max_block"] == 70000
