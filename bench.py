@@ -99,12 +99,57 @@ def cpu_baseline(w, seconds: float) -> dict:
             "rhs_evals_per_s": 1.0 / t_eval}
 
 
+def bench_batch(args):
+    """256 independent instances (N log-uniform in [1024, 65536], all-to-all or SBM, K swept
+    over [0, 6]) integrated as one batch, r sampled per instance every 10 steps."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2102_07167_amd import Kuramoto
+    t0 = time.perf_counter()
+    k = Kuramoto("f32", device=0)
+    for kv in args.option:
+        key, v = kv.split("=")
+        k.set_option(key, float(v))
+    insts = []
+
+    def feed():
+        for w in gen.batch_instances_iter():
+            insts.append((w.graph.n, w.meta["kind"], w.K))
+            yield w.graph, w.K, w.omega, w.theta0
+    k.set_batch(feed())
+    info = k.graph_info()
+    ntot = info["n"]
+    log("batch of %d instances, %d nodes, set in %.1f s: %s" % (len(insts), ntot, time.perf_counter() - t0, info))
+    dt = 0.01
+    k.batch_step(dt, args.warmup, 10)
+    k.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, psi = k.batch_step(dt, args.steps, 10)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    assert np.isfinite(r).all()
+    out = {"metric": "aggregate node-steps/s of a batched ensemble (RK4)", "value": ntot * args.steps / el,
+           "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "256 instances, N log-uniform in [1024,65536], all-to-all or SBM(1024-node "
+                                  "communities, rho 0.97, p_out 2e-4) by a coin, K=linspace(0,6,256), dt=0.01, "
+                                  "r every 10 steps, seed 1004", "nodes": ntot, "list_entries": info["list_entries"],
+                      "inter_entries": info["inter_entries"], "tiles": info["tiles"]},
+           "r_final_K0": float(r[-1, 0]), "r_final_K6": float(r[-1, -1])}
+    print(json.dumps(out), flush=True)
+    k.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="het", choices=["het", "sbm", "a2a"])
+    ap.add_argument("--workload", default="het", choices=["het", "sbm", "a2a", "batch"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -132,6 +177,8 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
+    if args.workload == "batch":
+        return bench_batch(args)
     t0 = time.perf_counter()
     w = make_workload(args.workload)
     log("workload %s generated in %.1f s (nnz %d)" % (w.name, time.perf_counter() - t0, w.graph.nnz))

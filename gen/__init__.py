@@ -309,19 +309,20 @@ def four_blocks_flip(M: int, p: float, seed: int = 1007) -> Graph:
     return sbm(sizes, np.full(4, 1.0 - p), p, key, _perm(p_rng, M))
 
 
-def batch_instances(n_inst: int = 256, nmin: int = 1024, nmax: int = 65536, Kmax: float = 6.0,
-                    dt: float = 0.01, steps: int = 2000, seed: int = 1004):
-    """Ensemble of independent instances: N log-uniform in [nmin, nmax], all-to-all or
-    equal-community SBM (communities of about 1024, rho 0.97, p_out 2e-4) by a fair coin,
-    K swept uniformly over [0, Kmax], omega ~ N(0,1), theta0 ~ U[0, 2 pi)."""
+def batch_instances_iter(n_inst: int = 256, nmin: int = 1024, nmax: int = 65536, Kmax: float = 6.0,
+                         dt: float = 0.01, steps: int = 2000, seed: int = 1004):
+    """Ensemble of independent instances, generated lazily: N log-uniform in [nmin, nmax],
+    all-to-all or equal-community SBM (communities of about 1024, rho 0.97, p_out 2e-4) by a fair
+    coin, K swept uniformly over [0, Kmax], omega ~ N(0,1), theta0 ~ U[0, 2 pi)."""
     ss = np.random.SeedSequence(seed)
     top = np.random.Generator(np.random.PCG64(ss.spawn(1)[0]))
     Ks = np.linspace(0.0, Kmax, n_inst)
-    out = []
+    plan = []
     for i in range(n_inst):
         n = int(round(math.exp(top.uniform(math.log(nmin), math.log(nmax)))))
         kind = "a2a" if top.random() < 0.5 else "sbm"
-        s_i = int(top.integers(0, 2**31))
+        plan.append((n, kind, int(top.integers(0, 2**31))))
+    for i, (n, kind, s_i) in enumerate(plan):
         g_rng, p_rng, w_rng, t_rng, x_rng = streams(s_i)
         if kind == "a2a":
             g = complete_graph(n)
@@ -331,7 +332,11 @@ def batch_instances(n_inst: int = 256, nmin: int = 1024, nmax: int = 65536, Kmax
             sizes[: n - sizes.sum()] += 1
             key = int(g_rng.integers(0, 2**63))
             g = sbm(sizes, np.full(nb, 0.97), 2e-4, key, _perm(p_rng, n))
-        out.append(Workload(name="inst%d_%s_n%d" % (i, kind, n), graph=g, omega=w_rng.standard_normal(n),
-                            theta0=uniform_theta(t_rng, n), K=float(Ks[i]), dt=dt, steps=steps, r_every=10,
-                            meta={"kind": kind}))
-    return out
+        yield Workload(name="inst%d_%s_n%d" % (i, kind, n), graph=g, omega=w_rng.standard_normal(n),
+                       theta0=uniform_theta(t_rng, n), K=float(Ks[i]), dt=dt, steps=steps, r_every=10,
+                       meta={"kind": kind})
+
+
+def batch_instances(*args, **kw):
+    """The ensemble of batch_instances_iter as a list."""
+    return list(batch_instances_iter(*args, **kw))

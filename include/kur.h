@@ -81,6 +81,8 @@ const char *kur_last_error(const kur_ctx *ctx);
  *                 most 8128 (FP32) or 4032 (FP64). Default 4096 (FP32), 2048 (FP64).
  *   "tile_rows"   maximal rows per work tile (64..4096). Default 256.
  *   "tiles"       target number of work tiles (>= 1). Default 4096.
+ *   "tile_min_cost" least work per tile in list-entry equivalents (a row costs its stored list
+ *                 entries + 4 per inter-block entry + 32). Default 16384.
  *   "flat_min_vec" rows of a tile averaging at least this many 8-entry list vectors per chunk
  *                 are streamed one contiguous run per wavefront; shorter rows get a group of
  *                 lanes each. 0 disables streaming. Default 8.

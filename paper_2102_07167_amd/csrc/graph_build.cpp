@@ -253,7 +253,8 @@ std::string finish(BlockGraph &g, const std::vector<int32_t> &block_of_row, cons
             total += c;
         }
     }
-    const int64_t target = std::max<int64_t>(2048, total / std::max<int64_t>(1, opt.tiles_target));
+    // a tile's list work should amortise its fixed cost (block-sum fold, staging, launch)
+    const int64_t target = std::max<int64_t>(opt.tile_min_cost, total / std::max<int64_t>(1, opt.tiles_target));
     g.tiles.clear();
     std::vector<int64_t> tcost;
     for (int32_t bi = 0; bi < g.nb; ++bi) {
@@ -279,6 +280,7 @@ std::string finish(BlockGraph &g, const std::vector<int32_t> &block_of_row, cons
             int32_t G = 2;
             while (G < 64 && G * 2 < avg) G *= 2;
             if (opt.flat_min_vec > 0 && avg >= opt.flat_min_vec) G = 0;  // wave-streaming mode
+            if (nonempty == 0) G = -1;                                    // no list entries at all
             g.tiles.push_back(Tile{bi, r, r1, G});
             tcost.push_back(c + (int64_t)b.size * nonempty / 4);
             r = r1;
@@ -338,10 +340,10 @@ std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &g)
     g.deg.assign(n, (int32_t)std::min<int64_t>(n - 1, INT32_MAX));
     g.n_dense = b.mode;
     g.symmetric = true;
-    // tiles: only the epilogue works per row, so use full-size tiles
+    // tiles: only the epilogue works per row (no list entries), so use full-size tiles
     g.blk[0].tile0 = 0;
     for (int64_t r = 0; r < n; r += opt.tile_rows)
-        g.tiles.push_back(Tile{0, (int32_t)r, (int32_t)std::min<int64_t>(n, r + opt.tile_rows), 2});
+        g.tiles.push_back(Tile{0, (int32_t)r, (int32_t)std::min<int64_t>(n, r + opt.tile_rows), -1});
     g.blk[0].ntiles = (int32_t)g.tiles.size();
     order_tiles(g);
     return "";

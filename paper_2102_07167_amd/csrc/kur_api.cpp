@@ -80,17 +80,22 @@ struct kur_ctx {
     int use_graph = 1;
     int64_t graph_steps = 16;
     hipGraphExec_t gexec = nullptr;
+    // every value baked into a captured graph: a change of any forces a new capture
     struct GraphKey {
         uint64_t gen;
         double dt;
         int64_t period;
         int sample;
         int cur;
+        const void *r;    // sample buffers written by the captured order-parameter kernel
+        const void *psi;
+        const void *ctr;
         bool operator==(const GraphKey &o) const
         {
-            return gen == o.gen && dt == o.dt && period == o.period && sample == o.sample && cur == o.cur;
+            return gen == o.gen && dt == o.dt && period == o.period && sample == o.sample && cur == o.cur &&
+                   r == o.r && psi == o.psi && ctr == o.ctr;
         }
-    } gkey{0, 0.0, 0, 0, 0};
+    } gkey{0, 0.0, 0, 0, 0, nullptr, nullptr, nullptr};
     uint64_t gen = 1;  // bumped whenever launch arguments may change
 
     // timing of the row kernel
@@ -517,6 +522,9 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
         int64_t t = (int64_t)v;
         if ((double)t != v || t < 1 || t > (int64_t)1 << 24) return fail(c, KUR_EINVAL, "tiles must be an integer in [1, 2^24]");
         c->bopt.tiles_target = t;
+    } else if (k == "tile_min_cost") {
+        if (v != (int64_t)v || v < 1 || v > 1e9) return fail(c, KUR_EINVAL, "tile_min_cost must be an integer in [1, 1e9]");
+        c->bopt.tile_min_cost = (int64_t)v;
     } else if (k == "flat_min_vec") {
         if (v < 0.0 || v > 1e6) return fail(c, KUR_EINVAL, "flat_min_vec must be in [0, 1e6]");
         c->bopt.flat_min_vec = v;
@@ -801,7 +809,7 @@ static hipError_t launch_step(kur_ctx *c, const DevGraph &g, double dt)
 // sample index) into one executable graph, reusing the cached one when nothing changed.
 static hipError_t step_graph(kur_ctx *c, const DevGraph &g, double dt, int64_t period, bool sample)
 {
-    kur_ctx::GraphKey key{c->gen, dt, period, sample ? 1 : 0, c->cur};
+    kur_ctx::GraphKey key{c->gen, dt, period, sample ? 1 : 0, c->cur, c->d_r.p, c->d_psi.p, c->d_ctr.p};
     if (c->gexec && c->gkey == key) return hipSuccess;
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);

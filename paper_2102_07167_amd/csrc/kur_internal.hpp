@@ -21,7 +21,7 @@ struct BlkInfo {
 };
 
 // One unit of work: rows [r0, r1) (block-local) of one block, G lanes per row (G == 0: each
-// wave streams a contiguous run of the tile's rows).
+// wave streams a contiguous run of the tile's rows; G == -1: the rows store no list entries).
 struct Tile {
     int32_t block;
     int32_t r0;
@@ -34,6 +34,7 @@ struct BuildOptions {
     int32_t W = 8192;        // chunk width (columns staged in LDS at a time)
     int32_t tile_rows = 1024;
     int64_t tiles_target = 4096;
+    int64_t tile_min_cost = 16384;  // least work per tile, in list-entry equivalents
     double flat_min_vec = 8.0;  // rows averaging at least this many 8-entry vectors: wave streaming
     int32_t esz2 = 8;           // bytes of one staged (sin, cos) pair; list entries are LDS byte
                                 // offsets col * esz2, so W * esz2 must stay below 65536

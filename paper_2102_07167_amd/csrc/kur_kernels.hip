@@ -318,9 +318,11 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
     }
     __syncthreads();  // accumulators, pad slot and block sums visible to every wave
 
-    // G > 0: G lanes per row (short rows); G == 0: every wave streams a contiguous run of rows
+    // G > 0: G lanes per row (short rows); G == 0: every wave streams a contiguous run of rows;
+    // G < 0: no list entries in any chunk (only inter-block entries)
     const bool flat = tl.G == 0;
-    const int G = flat ? 8 : tl.G;
+    const int G = tl.G > 0 ? tl.G : 8;
+    const int nchunk = tl.G < 0 ? 0 : bi.nchunk;
     const int lane = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int ngrp = NT / G;
@@ -331,7 +333,7 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
     const int ra = (int)(((int64_t)nrows * wv) / (NT / 64));
     const int rb = (int)(((int64_t)nrows * (wv + 1)) / (NT / 64));
 
-    for (int c = 0; c < bi.nchunk; ++c) {
+    for (int c = 0; c < nchunk; ++c) {
         const int64_t sb = bi.segbase + (int64_t)c * bi.size;
         const int64_t e0 = g.seg_ptr[sb + tl.r0], e1 = g.seg_ptr[sb + tl.r1];
         if (e0 == e1) continue;  // uniform over the workgroup

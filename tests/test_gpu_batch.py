@@ -63,6 +63,8 @@ def test_batch_matches_oracle_per_instance(need_gpu, dtype, graph):
 
 
 def test_graph_replay_is_bitwise_equal_to_plain_launches(need_gpu):
+    """Regression: a cached step graph once kept the order-parameter buffers of an earlier call
+    after they had been reallocated for more samples."""
     w = gen.sbm_equal(n_comm=8, comm_size=300, rho_in=0.9, p_out=0.01, steps=10, seed=9)
     out = {}
     for graph in (0, 1):
@@ -74,7 +76,9 @@ def test_graph_replay_is_bitwise_equal_to_plain_launches(need_gpu):
             k.set_phases(w.theta0)
             rs = []
             # several calls: replays of a cached graph with eager work and host reads in between
-            for nsteps, r_every in [(17, 0), (40, 5), (12, 0), (30, 10), (9, 3)]:
+            # (60, 2) needs a larger sample buffer than the earlier captures used: the replayed
+            # graph must be captured again with the new buffer
+            for nsteps, r_every in [(17, 0), (40, 5), (12, 0), (30, 10), (9, 3), (60, 2), (20, 4)]:
                 r, _ = k.step_rk4(w.dt, nsteps, r_every=r_every)
                 rs.append(r)
                 rs.append(np.array([k.order_parameter()[0]]))
@@ -100,3 +104,46 @@ def test_complete_graph_70000(need_gpu):
         F = k.eval_rhs()
     Fo = oracle.rhs_rows(g, om, 2.0, th, rows)
     assert np.abs(F[rows] - Fo).max() < 1e-12 * np.abs(Fo).max()
+
+
+def test_batch_ensemble_full_size(need_gpu):
+    """The full ensemble: 256 instances, N log-uniform in [1024, 65536], all-to-all or SBM,
+    K = linspace(0, 6, 256), 2000 RK4 steps of dt 0.01 in FP32, r every 10 steps. Checked by
+    properties that hold at any size (per-instance conservation, free rotation at K = 0, r(0)
+    of every instance) and by the oracle trajectory of the smallest all-to-all instance (FP32
+    bound 2e-5 after 2000 steps: the 1e-5 bound stated for 1000 steps, doubled)."""
+    keep = []
+
+    def feed():
+        for w in gen.batch_instances_iter():
+            om = w.omega.astype(np.float32).astype(np.float64)
+            th = w.theta0.astype(np.float32).astype(np.float64)
+            keep.append((w.graph.n, w.meta["kind"], w.K, om, th))
+            yield w.graph, w.K, om, th
+    dt, steps = 0.01, 2000
+    with Kuramoto("f32", device=0) as k:
+        k.set_batch(feed())
+        rf = k.batch_info()
+        r, _ = k.batch_step(dt, steps, 10)
+        th_all = k.get_phases()
+    T = steps * dt
+    assert r.shape == (steps // 10 + 1, 256) and np.isfinite(r).all()
+    for i, (n, kind, K, om, th0) in enumerate(keep):
+        thT = th_all[rf[i]:rf[i + 1]]
+        # mean of theta - theta0 - T omega is conserved (symmetric A, uniform scaling)
+        assert abs(np.mean(thT - th0 - T * om)) < 2e-4, i
+        r0, _ = oracle.order_parameter(th0)
+        assert abs(r[0, i] - r0) < 1e-5, i
+        if K == 0.0:
+            assert np.abs(wrap(thT - (th0 + T * om))).max() < 1e-4
+    # all-to-all instances: strong coupling synchronises (mean-field K_c ~ 1.6 for N(0,1)
+    # frequencies), weak coupling does not
+    a2a = np.array([kind == "a2a" for _, kind, *_ in keep])
+    Ks = np.array([K for _, _, K, *_ in keep])
+    assert r[-1, a2a & (Ks > 4.5)].min() > 0.8
+    assert r[-1, a2a & (Ks < 0.5)].max() < 0.3
+    small = min((x for x in enumerate(keep) if x[1][1] == "a2a"), key=lambda x: x[1][0])
+    i, (n, kind, K, om, th0) = small
+    Kf = float(np.float32(K))
+    tho, _, _ = oracle.rk4(gen.complete_graph(n), om, Kf, th0, float(np.float32(dt)), steps)
+    assert np.abs(wrap(th_all[rf[i]:rf[i + 1]] - tho)).max() < 2e-5

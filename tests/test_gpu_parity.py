@@ -118,7 +118,7 @@ def test_sbm_fp32_trajectory_1000_steps(need_gpu, flat):
 @pytest.mark.parametrize("opts", [dict(chunk=64, tile_rows=64), dict(tau=0.0, chunk=128), dict(tau=1.0),
                                   dict(threads=256, tile_rows=128), dict(threads=1024),
                                   dict(flat_min_vec=0.1, chunk=128, tile_rows=64), dict(flat_min_vec=0.1, tau=0.0),
-                                  dict(flat_min_vec=0)])
+                                  dict(flat_min_vec=0), dict(tile_min_cost=1), dict(tile_min_cost=1, tiles=100000)])
 def test_ragged_layouts(need_gpu, dtype, opts):
     """Odd block sizes, several chunks per block, several tiles per block, all-dense and
     all-sparse evaluation, a size-1 block and a complete block."""
