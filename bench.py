@@ -246,6 +246,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_rows", "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": b_eval},
     }
+    stream_gbs = k.read_bandwidth(4 << 30, 5)
+    out["roofline"]["stream_read_gbs"] = stream_gbs
+    out["roofline"]["frac_of_stream_read"] = achieved / stream_gbs
+    log("plain streaming read on this GPU: %.0f GB/s" % stream_gbs)
     if args.adjoint_steps > 0:
         import numpy as np
         na, ck = args.adjoint_steps, 32

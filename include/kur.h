@@ -243,6 +243,11 @@ kur_status kur_sync(kur_ctx *ctx);
  */
 kur_status kur_kernel_time(kur_ctx *ctx, int64_t *launches, double *total_ms);
 
+/* Reference for the roofline: achieved bandwidth (GB/s) of a plain streaming read of `bytes`
+ * (1 MiB .. 64 GiB, temporary device buffer) with 16-byte non-temporal loads, repeated
+ * `repeats` times. Synchronous. */
+kur_status kur_read_bandwidth(kur_ctx *ctx, int64_t bytes, int32_t repeats, double *gbps);
+
 /* Device-pointer variants. Arrays are in BLOCK order and of the context dtype
  * (float or double); they enqueue on the context stream. */
 kur_status kur_eval_rhs_dev(kur_ctx *ctx, const void *theta_dev, void *dtheta_dev);

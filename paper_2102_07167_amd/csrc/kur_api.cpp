@@ -1418,3 +1418,35 @@ extern "C" kur_status kur_batch_step(kur_ctx *c, double dt, int64_t nsteps, int6
     if (s != KUR_OK) return s;
     return fetch_samples(c, r_every > 0 ? (nsteps / r_every + 1) * c->n_inst : 0, r_out, psi_out);
 }
+
+extern "C" kur_status kur_read_bandwidth(kur_ctx *c, int64_t bytes, int32_t repeats, double *gbps)
+{
+    if (!c || !gbps) return KUR_EINVAL;
+    c->err.clear();
+    if (bytes < (1 << 20) || bytes > ((int64_t)64 << 30) || repeats < 1 || repeats > 1000)
+        return fail(c, KUR_EINVAL, "bytes must be in [1 MiB, 64 GiB] and repeats in [1, 1000]");
+    kur_status s = need_device(c);
+    if (s != KUR_OK) return s;
+    const int64_t words = bytes / 16;
+    DevBuf buf, out;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    float ms = 0.f;
+    if ((e = dalloc(buf, (size_t)words * 16)) != hipSuccess || (e = dalloc(out, 64)) != hipSuccess ||
+        (e = hipMemsetAsync(buf.p, 1, (size_t)words * 16, c->stream)) != hipSuccess ||
+        (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess ||
+        (e = launch_stream_read(buf.p, words, (uint32_t *)out.p, c->stream)) != hipSuccess ||
+        (e = hipEventRecord(e0, c->stream)) != hipSuccess)
+        goto done;
+    for (int32_t r = 0; r < repeats && e == hipSuccess; ++r) e = launch_stream_read(buf.p, words, (uint32_t *)out.p, c->stream);
+    if (e == hipSuccess && (e = hipEventRecord(e1, c->stream)) == hipSuccess && (e = hipEventSynchronize(e1)) == hipSuccess)
+        e = hipEventElapsedTime(&ms, e0, e1);
+done:
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dfree(buf);
+    dfree(out);
+    if (e != hipSuccess) return hip_fail(c, e, "read bandwidth");
+    *gbps = (double)words * 16.0 * repeats / ((double)ms * 1e-3) / 1e9;
+    return KUR_OK;
+}

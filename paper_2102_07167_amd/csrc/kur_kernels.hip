@@ -411,17 +411,40 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
         }
     }
 
-    // edges between blocks: straightforward summation from the global table. In streaming mode
-    // another wave owns the row's accumulator above, so wait for those updates first.
-    if (flat) __syncthreads();
-    for (int r = grp; r < nrows; r += ngrp) {
-        const int m = rowbase + r;
-        const int64_t e0 = g.inter_ptr[m], e1 = g.inter_ptr[m + 1];
-        if (e0 == e1) continue;  // uniform over the group
-        VT acc = vzero<VT>();
-        for (int64_t e = e0 + lane; e < e1; e += G) vacc(acc, x_in[g.inter_col[e]]);
-        acc = vgroup_sum_dpp(acc, G);
-        if (lane == G - 1) vacc(L.acc[r], acc);
+    // edges between blocks: straightforward summation from the global table. The tile's rows
+    // own the contiguous entries [i0, i1) of the inter CSR; they are gathered in rounds of
+    // 4 NT entries (all loads of a round in flight together) into the staging area, which is
+    // free now, and each row then adds its entries in order.
+    const int64_t i0 = g.inter_ptr[rowbase], i1 = g.inter_ptr[rowbase + nrows];
+    if (i1 > i0) {  // uniform over the workgroup
+        const int total = (int)(i1 - i0);
+        constexpr int U = 4;
+        const int round = min(U * NT, W);  // entries per round: at most the staging area
+        __syncthreads();  // the staging area and bnd are no longer read by the list pass
+        for (int r = threadIdx.x; r <= nrows; r += NT) L.bnd[r] = (int)(g.inter_ptr[rowbase + r] - i0);
+        for (int base = 0; base < total; base += round) {
+            if (base > 0) __syncthreads();  // the previous round's values are consumed
+            const int end = min(total, base + round);
+            int col[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) col[u] = g.inter_col[i0 + min(base + u * NT + (int)threadIdx.x, end - 1)];
+            VT v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = x_in[col[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = base + u * NT + (int)threadIdx.x;
+                if (j < end) L.xs[j - base] = v[u];
+            }
+            __syncthreads();
+            for (int r = threadIdx.x; r < nrows; r += NT) {
+                const int lo = max(L.bnd[r], base), hi = min(L.bnd[r + 1], end);
+                if (lo >= hi) continue;
+                VT a = L.xs[lo - base];
+                for (int j = lo + 1; j < hi; ++j) vacc(a, L.xs[j - base]);
+                vacc(L.acc[r], a);
+            }
+        }
     }
     __syncthreads();
 }
@@ -644,6 +667,26 @@ __global__ __launch_bounds__(256) void k_order(const typename V2<T>::type *__res
         r_out[k] = sqrt(s * s + c * c);
         psi_out[k] = atan2(s, c);
     }
+}
+
+// Streaming read of n 16-byte words (a bandwidth reference for the roofline): every lane
+// reads a grid-strided sequence with non-temporal loads and folds it into one word.
+__global__ __launch_bounds__(512) void k_stream_read(const u32x4 *__restrict__ p, int64_t n, uint32_t *__restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    uint32_t acc = 0;
+    for (; i < n; i += st) {
+        const u32x4 v = __builtin_nontemporal_load(p + i);
+        acc ^= v.x + v.y + v.z + v.w;
+    }
+    if (acc == 0x9E3779B9u) out[0] = acc;  // keeps the loads; practically never taken
+}
+
+hipError_t launch_stream_read(const void *p, int64_t words, uint32_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stream_read, dim3(2048), dim3(512), 0, st, (const u32x4 *)p, words, out);
+    return hipGetLastError();
 }
 
 // advance the replayed sample counter

@@ -69,6 +69,7 @@ template <typename T>
 hipError_t launch_order(const void *part, const int64_t *tile_first, const double *inv_n, int n_inst, double *r,
                         double *psi, const int64_t *idx_dev, int64_t idx, hipStream_t st);
 hipError_t launch_bump(int64_t *ctr, hipStream_t st);
+hipError_t launch_stream_read(const void *p, int64_t words, uint32_t *out, hipStream_t st);
 template <typename T>
 hipError_t launch_phase_out(int64_t n, const void *hi, const void *lo, const int32_t *wind, int unwrapped, void *out,
                             hipStream_t st);

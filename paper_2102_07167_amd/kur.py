@@ -56,6 +56,7 @@ SIGNATURES = {
     "kur_batch_commit": (ST, [P]),
     "kur_batch_info": (ST, [P, P, P]),
     "kur_batch_step": (ST, [P, F64, I64, I64, P, P]),
+    "kur_read_bandwidth": (ST, [P, I64, I32, P]),
     "kur_eval_rhs_dev": (ST, [P, P, P]),
     "kur_get_phases_dev": (ST, [P, P]),
 }
@@ -283,6 +284,12 @@ class Kuramoto:
         self._chk(self._L.kur_adjoint_rk4(self._h, _ptr(th0), float(dt), int(nsteps), int(ckpt_every), _ptr(seed),
                                           _ptr(gt), _ptr(gw), ctypes.byref(gk)))
         return gt, gw, gk.value
+
+    def read_bandwidth(self, nbytes: int = 4 << 30, repeats: int = 5) -> float:
+        """GB/s of a plain streaming read on this context's device (roofline reference)."""
+        g = F64()
+        self._chk(self._L.kur_read_bandwidth(self._h, int(nbytes), int(repeats), ctypes.byref(g)))
+        return g.value
 
     def sync(self):
         self._chk(self._L.kur_sync(self._h))
