@@ -255,20 +255,30 @@ def main():
         na, ck = args.adjoint_steps, 32
         seed = np.random.default_rng(7).standard_normal(w.graph.n) / w.graph.n
         k.adjoint_rk4(w.dt, min(na, 4), seed, theta0=w.theta0, ckpt_every=ck)  # warm-up
+
+        def timed(fn):
+            k.sync()
+            t0 = time.perf_counter()
+            res = fn()
+            k.sync()
+            return time.perf_counter() - t0, res
         k.set_phases(w.theta0)
-        k.sync()
-        t0 = time.perf_counter()
-        k.step_rk4(w.dt, na)
-        k.sync()
-        t_fwd = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        gt, gw, gk = k.adjoint_rk4(w.dt, na, seed, theta0=w.theta0, ckpt_every=ck)
-        t_adj = time.perf_counter() - t0
+        t_fwd, _ = timed(lambda: k.step_rk4(w.dt, na))
+        k.set_phases(w.theta0)
+        k.set_option("checkpoint_every", ck)
+        t_fwd_ck, _ = timed(lambda: k.step_rk4(w.dt, na))
+        k.set_option("checkpoint_every", 0)
+        t_bwd, (gt, gw, gk) = timed(lambda: k.adjoint_recorded(seed))
+        t_full, (gt2, gw2, gk2) = timed(lambda: k.adjoint_rk4(w.dt, na, seed, theta0=w.theta0, ckpt_every=ck))
         assert np.isfinite(gt).all() and np.isfinite(gw).all() and math.isfinite(gk)
-        out["adjoint"] = {"steps": na, "ckpt_every": ck, "fwd_ms": 1e3 * t_fwd, "adjoint_ms": 1e3 * t_adj,
-                          "ratio": t_adj / t_fwd,
-                          "note": "adjoint = forward with checkpoints + per-segment recompute + 4 VJP stages per step"}
-        log("adjoint %d steps: %.1f ms vs forward %.1f ms (ratio %.2f)" % (na, 1e3 * t_adj, 1e3 * t_fwd, t_adj / t_fwd))
+        assert np.array_equal(gt, gt2) and np.array_equal(gw, gw2) and gk == gk2
+        out["adjoint"] = {"steps": na, "ckpt_every": ck, "fwd_ms": 1e3 * t_fwd, "fwd_checkpointed_ms": 1e3 * t_fwd_ck,
+                          "backward_ms": 1e3 * t_bwd, "ratio": t_bwd / t_fwd,
+                          "adjoint_with_forward_ms": 1e3 * t_full, "ratio_with_forward": t_full / t_fwd,
+                          "note": "ratio = backward (recompute per segment + 4 VJP stages per step, using the "
+                                  "forward run's checkpoints) / plain forward; ratio_with_forward also repeats the forward"}
+        log("adjoint %d steps: backward %.1f ms, with forward %.1f ms, forward %.1f ms (ratio %.2f / %.2f)" % (
+            na, 1e3 * t_bwd, 1e3 * t_full, 1e3 * t_fwd, t_bwd / t_fwd, t_full / t_fwd))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, %.0f s budget)" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

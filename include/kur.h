@@ -90,6 +90,9 @@ const char *kur_last_error(const kur_ctx *ctx);
  *   "compensate"  1: compensated phase update with winding (default); 0: plain update. Immediate.
  *   "timing"      1: time every launch of the row kernel with HIP events (see kur_kernel_time).
  *                 Immediate; disables graph replay while on.
+ *   "checkpoint_every" C > 0: kur_step_rk4 keeps the phases every C steps for
+ *                 kur_adjoint_rk4_recorded (and launches without graph replay); 0 (default) off.
+ *                 Immediate.
  *   "graph"       1 (default): kur_step_rk4 captures one sampling period (r_every steps, else
  *                 "graph_steps" steps) into a HIP graph and replays it; 0: plain launches.
  *   "graph_steps" steps per replayed graph when no order parameter is sampled (default 16).
@@ -233,6 +236,19 @@ kur_status kur_set_state(kur_ctx *ctx, const void *blob, size_t bytes);
  */
 kur_status kur_adjoint_rk4(kur_ctx *ctx, const double *theta0, double dt, int64_t nsteps, int64_t ckpt_every,
                            const double *dl_dthetaT, double *g_theta0, double *g_omega, double *g_K);
+
+/*
+ * The same gradients for the run of the last kur_step_rk4 call made with the option
+ * "checkpoint_every" = C > 0, which kept the phases every C steps: the forward pass is not
+ * repeated. Returns KUR_ESTATE if no such run is recorded or the graph, omega, K or an option
+ * changed since. Synchronous.
+ */
+kur_status kur_adjoint_rk4_recorded(kur_ctx *ctx, const double *dl_dthetaT, double *g_theta0, double *g_omega,
+                                    double *g_K);
+
+/* The recorded run kur_adjoint_rk4_recorded would use: a serial number that grows with every
+ * recording (0 if none is usable), its dt and its number of steps (either may be NULL). */
+kur_status kur_recorded_run(const kur_ctx *ctx, int64_t *serial, double *dt, int64_t *nsteps);
 
 /* Wait for all work enqueued on the context stream. */
 kur_status kur_sync(kur_ctx *ctx);

@@ -26,7 +26,10 @@ class KuramotoRK4(torch.autograd.Function):
         k = float(K)
         model.set_params(om, k)
         model.set_phases(th0)
+        model.set_option("checkpoint_every", ckpt_every)  # keep checkpoints for the backward pass
         model.step_rk4(dt, nsteps)
+        model.set_option("checkpoint_every", 0)
+        ctx.rec = model.recorded_run()[0]
         thT = model.get_phases(wrapped=False)
         ctx.model, ctx.dt, ctx.nsteps, ctx.ckpt = model, dt, nsteps, ckpt_every
         ctx.th0, ctx.om, ctx.k = th0, om, k
@@ -37,8 +40,12 @@ class KuramotoRK4(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_thetaT):
         m = ctx.model
-        m.set_params(ctx.om, ctx.k)
-        gt, gw, gk = m.adjoint_rk4(ctx.dt, ctx.nsteps, _host(grad_thetaT), theta0=ctx.th0, ckpt_every=ctx.ckpt)
+        seed = _host(grad_thetaT)
+        if ctx.rec and m.recorded_run()[0] == ctx.rec:  # this forward run's own checkpoints
+            gt, gw, gk = m.adjoint_recorded(seed)
+        else:  # the model ran or changed since: repeat the forward pass inside the adjoint
+            m.set_params(ctx.om, ctx.k)
+            gt, gw, gk = m.adjoint_rk4(ctx.dt, ctx.nsteps, seed, theta0=ctx.th0, ckpt_every=ctx.ckpt)
         to = dict(device=ctx.dev, dtype=ctx.dtype)
         g_k = torch.tensor(gk, **to) if ctx.k_is_tensor else None
         return torch.from_numpy(gt).to(**to), torch.from_numpy(gw).to(**to), g_k, None, None, None, None

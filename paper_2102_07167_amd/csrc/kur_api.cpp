@@ -76,6 +76,15 @@ struct kur_ctx {
     std::vector<double> pend_K;
     bool pend_open = false;
 
+    // checkpoints recorded by kur_step_rk4 (option "checkpoint_every") for the adjoint
+    int64_t ckpt_every = 0;
+    DevBuf d_ck;
+    bool rec_valid = false;
+    double rec_dt = 0.0;
+    int64_t rec_nsteps = 0, rec_C = 0;
+    uint64_t rec_gen = 0;
+    int64_t rec_serial = 0;
+
     // replayed step graph
     int use_graph = 1;
     int64_t graph_steps = 16;
@@ -161,7 +170,7 @@ void free_all(kur_ctx *c)
     DevBuf *bufs[] = {&c->d_blk, &c->d_tiles, &c->d_order, &c->d_seg, &c->d_list, &c->d_iptr, &c->d_icol,
                       &c->d_omega, &c->d_unit, &c->d_hi, &c->d_lo, &c->d_wind, &c->d_ksum, &c->d_sc[0],
                       &c->d_sc[1], &c->d_part[0], &c->d_part[1], &c->d_sce, &c->d_parte, &c->d_kout, &c->d_y,
-                      &c->d_r, &c->d_psi, &c->d_tile_first, &c->d_inv_n, &c->d_ctr};
+                      &c->d_r, &c->d_psi, &c->d_tile_first, &c->d_inv_n, &c->d_ctr, &c->d_ck};
     for (DevBuf *b : bufs) dfree(*b);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
@@ -542,6 +551,9 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "compensate must be 0 or 1");
         c->compensate = (int)v;
         c->gen++;
+    } else if (k == "checkpoint_every") {
+        if (v != (int64_t)v || v < 0 || v > 1e9) return fail(c, KUR_EINVAL, "checkpoint_every must be an integer >= 0");
+        c->ckpt_every = (int64_t)v;
     } else if (k == "graph") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "graph must be 0 or 1");
         c->use_graph = (int)v;
@@ -861,7 +873,14 @@ static kur_status run_steps(kur_ctx *c, double dt, int64_t nsteps, int64_t r_eve
     }
     const int64_t period = r_every > 0 ? r_every : std::max<int64_t>(1, c->graph_steps);
     const int64_t reps = nsteps / period;
-    if (c->use_graph && !c->timing && reps >= 2) {
+    const int64_t C = c->batch ? 0 : c->ckpt_every;  // record checkpoints: plain launches
+    if (C > 0) {
+        const size_t TN = (size_t)c->esz * (size_t)c->n;
+        const int64_t nseg = nsteps > 0 ? (nsteps + C - 1) / C : 0;
+        c->rec_valid = false;
+        if ((e = dalloc(c->d_ck, 2 * TN * (size_t)std::max<int64_t>(nseg, 1))) != hipSuccess) return hip_fail(c, e, "checkpoints");
+    }
+    if (C == 0 && c->use_graph && !c->timing && reps >= 2) {
         if (r_every > 0) {
             const int64_t one = 1;
             if ((e = hipMemcpyAsync(c->d_ctr.p, &one, sizeof(one), hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
@@ -875,11 +894,26 @@ static kur_status run_steps(kur_ctx *c, double dt, int64_t nsteps, int64_t r_eve
         if (r_every > 0) k += reps;
     }
     for (int64_t step = done; step < nsteps; ++step) {
+        if (C > 0 && step % C == 0) {
+            const size_t TN = (size_t)c->esz * (size_t)c->n;
+            char *ck = (char *)c->d_ck.p + (size_t)(step / C) * 2 * TN;
+            if ((e = hipMemcpyAsync(ck, c->d_hi.p, TN, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
+                (e = hipMemcpyAsync(ck + TN, c->d_lo.p, TN, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+                return hip_fail(c, e, "checkpoint copy");
+        }
         if ((e = launch_step(c, g, dt)) != hipSuccess) return hip_fail(c, e, "rk4 stage launch");
         if (r_every > 0 && (step + 1) % r_every == 0) {
             if ((e = launch_sample(c, nullptr, k)) != hipSuccess) return hip_fail(c, e, "order parameter launch");
             ++k;
         }
+    }
+    if (C > 0) {
+        c->rec_valid = true;
+        c->rec_dt = dt;
+        c->rec_nsteps = nsteps;
+        c->rec_C = C;
+        c->rec_gen = c->gen;
+        c->rec_serial++;
     }
     return KUR_OK;
 }
@@ -1093,9 +1127,11 @@ struct AdjBufs {
     }
 };
 
+// theta0_user: start of the forward run (then the forward pass runs here); ck_ext: device
+// checkpoints recorded by kur_step_rk4 instead (then theta0_user is unused).
 template <typename T>
-kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, double dt, int64_t nsteps, int64_t C,
-                        const double *seed_user, double *g_theta0, double *g_omega, double *g_K)
+kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ext, double dt, int64_t nsteps,
+                        int64_t C, const double *seed_user, double *g_theta0, double *g_omega, double *g_K)
 {
     using std::vector;
     const int64_t n = c->n;
@@ -1108,7 +1144,7 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, double dt, int64_
     hipError_t e;
     if ((e = dalloc(B.hi, TN)) != hipSuccess || (e = dalloc(B.lo, TN)) != hipSuccess ||
         (e = dalloc(B.wind, 4 * (size_t)n)) != hipSuccess || (e = dalloc(B.ksum, TN)) != hipSuccess ||
-        (e = dalloc(B.ck, 2 * TN * (size_t)std::max<int64_t>(nseg, 1))) != hipSuccess ||
+        (!ck_ext && (e = dalloc(B.ck, 2 * TN * (size_t)std::max<int64_t>(nseg, 1))) != hipSuccess) ||
         (e = dalloc(B.slots, 2 * TN * (size_t)nslot)) != hipSuccess ||
         (e = dalloc(B.fpart[0], 2 * sizeof(T) * nt)) != hipSuccess || (e = dalloc(B.fpart[1], 2 * sizeof(T) * nt)) != hipSuccess ||
         (e = dalloc(B.x[0], 4 * TN)) != hipSuccess || (e = dalloc(B.x[1], 4 * TN)) != hipSuccess ||
@@ -1125,12 +1161,13 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, double dt, int64_
         vector<int32_t> wind(n);
         for (int64_t u = 0; u < n; ++u) {
             const int64_t m = c->perm[u];
+            lam[m] = (T)seed_user[u];
+            if (ck_ext) continue;
             const double q = std::nearbyint(theta0_user[u] / (2.0 * kPi));
             const double red = (theta0_user[u] - q * P1) - q * P2;
             hi[m] = (T)red;
             lo[m] = (T)(red - (double)hi[m]);
             wind[m] = (int32_t)q;
-            lam[m] = (T)seed_user[u];
         }
         if ((e = hipMemcpyAsync(B.hi.p, hi.data(), TN, hipMemcpyHostToDevice, st)) != hipSuccess ||
             (e = hipMemcpyAsync(B.lo.p, lo.data(), TN, hipMemcpyHostToDevice, st)) != hipSuccess ||
@@ -1156,8 +1193,9 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, double dt, int64_
     };
     auto slot = [&](int64_t i) -> void * { return (char *)B.slots.p + (size_t)i * 2 * TN; };
 
-    // forward pass, keeping (hi, lo) every C steps
-    if (nsteps > 0) {
+    const char *ckbase = ck_ext ? (const char *)ck_ext : (const char *)B.ck.p;
+    // forward pass, keeping (hi, lo) every C steps (unless recorded by the caller's run)
+    if (nsteps > 0 && !ck_ext) {
         int cur = 0;
         if ((e = launch_sc_init<T>(g, nt, (const T *)B.hi.p, slot(0), B.fpart[0].p, c->threads, st)) != hipSuccess)
             return hip_fail(c, e, "adjoint forward");
@@ -1181,7 +1219,7 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, double dt, int64_
     const T tdt = (T)dt;
     for (int64_t seg = nseg - 1; seg >= 0; --seg) {
         const int64_t s0 = seg * C, len = std::min<int64_t>(C, nsteps - s0);
-        const char *ck = (const char *)B.ck.p + (size_t)seg * 2 * TN;
+        const char *ck = ckbase + (size_t)seg * 2 * TN;
         if ((e = hipMemcpyAsync(B.hi.p, ck, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
             (e = hipMemcpyAsync(B.lo.p, ck + TN, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess)
             return hip_fail(c, e, "adjoint restore");
@@ -1280,8 +1318,8 @@ extern "C" kur_status kur_adjoint_rk4(kur_ctx *c, const double *theta0, double d
             return fail(c, KUR_EINVAL, "theta0 and dl_dthetaT must be finite (|theta0| <= 1e9)");
     const int64_t C = std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1));
     try {
-        return c->esz == 4 ? adjoint_impl<float>(c, theta0, dt, nsteps, C, dl_dthetaT, g_theta0, g_omega, g_K)
-                           : adjoint_impl<double>(c, theta0, dt, nsteps, C, dl_dthetaT, g_theta0, g_omega, g_K);
+        return c->esz == 4 ? adjoint_impl<float>(c, theta0, nullptr, dt, nsteps, C, dl_dthetaT, g_theta0, g_omega, g_K)
+                           : adjoint_impl<double>(c, theta0, nullptr, dt, nsteps, C, dl_dthetaT, g_theta0, g_omega, g_K);
     } catch (const std::bad_alloc &) {
         return fail(c, KUR_ENOMEM, "host allocation failed in the adjoint");
     }
@@ -1448,5 +1486,41 @@ done:
     dfree(out);
     if (e != hipSuccess) return hip_fail(c, e, "read bandwidth");
     *gbps = (double)words * 16.0 * repeats / ((double)ms * 1e-3) / 1e9;
+    return KUR_OK;
+}
+
+extern "C" kur_status kur_adjoint_rk4_recorded(kur_ctx *c, const double *dl_dthetaT, double *g_theta0, double *g_omega,
+                                               double *g_K)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!dl_dthetaT) return fail(c, KUR_EINVAL, "dl_dthetaT must not be NULL");
+    kur_status s = need_ready(c, true, true);
+    if (s != KUR_OK) return s;
+    if (!c->rec_valid || c->rec_gen != c->gen)
+        return fail(c, KUR_ESTATE, "no checkpoints recorded by kur_step_rk4 for the current graph, omega and K");
+    if (!c->symmetric) return fail(c, KUR_EINVAL, "the adjoint needs a symmetric adjacency");
+    if (c->batch) return fail(c, KUR_EINVAL, "the adjoint of a batch is not supported");
+    if (rows_lds_bytes(c->esz, c->W, c->tile_rows, c->threads, 2) > 156 * 1024)
+        return fail(c, KUR_EINVAL, "chunk/tile_rows too large for the adjoint's LDS (4 values per node)");
+    for (int64_t u = 0; u < c->n; ++u)
+        if (!std::isfinite(dl_dthetaT[u])) return fail(c, KUR_EINVAL, "dl_dthetaT must be finite");
+    try {
+        return c->esz == 4 ? adjoint_impl<float>(c, nullptr, c->d_ck.p, c->rec_dt, c->rec_nsteps, c->rec_C, dl_dthetaT,
+                                                 g_theta0, g_omega, g_K)
+                           : adjoint_impl<double>(c, nullptr, c->d_ck.p, c->rec_dt, c->rec_nsteps, c->rec_C, dl_dthetaT,
+                                                  g_theta0, g_omega, g_K);
+    } catch (const std::bad_alloc &) {
+        return fail(c, KUR_ENOMEM, "host allocation failed in the adjoint");
+    }
+}
+
+extern "C" kur_status kur_recorded_run(const kur_ctx *c, int64_t *serial, double *dt, int64_t *nsteps)
+{
+    if (!c || !serial) return KUR_EINVAL;
+    const bool ok = c->rec_valid && c->rec_gen == c->gen;
+    *serial = ok ? c->rec_serial : 0;
+    if (dt) *dt = ok ? c->rec_dt : 0.0;
+    if (nsteps) *nsteps = ok ? c->rec_nsteps : 0;
     return KUR_OK;
 }

@@ -57,6 +57,8 @@ SIGNATURES = {
     "kur_batch_info": (ST, [P, P, P]),
     "kur_batch_step": (ST, [P, F64, I64, I64, P, P]),
     "kur_read_bandwidth": (ST, [P, I64, I32, P]),
+    "kur_adjoint_rk4_recorded": (ST, [P, P, P, P, P]),
+    "kur_recorded_run": (ST, [P, P, P, P]),
     "kur_eval_rhs_dev": (ST, [P, P, P]),
     "kur_get_phases_dev": (ST, [P, P]),
 }
@@ -284,6 +286,21 @@ class Kuramoto:
         self._chk(self._L.kur_adjoint_rk4(self._h, _ptr(th0), float(dt), int(nsteps), int(ckpt_every), _ptr(seed),
                                           _ptr(gt), _ptr(gw), ctypes.byref(gk)))
         return gt, gw, gk.value
+
+    def adjoint_recorded(self, dl_dthetaT):
+        """Gradients for the last kur_step_rk4 run recorded with option checkpoint_every > 0."""
+        seed = _f64(dl_dthetaT, self.n)
+        gt = np.empty(self.n)
+        gw = np.empty(self.n)
+        gk = F64()
+        self._chk(self._L.kur_adjoint_rk4_recorded(self._h, _ptr(seed), _ptr(gt), _ptr(gw), ctypes.byref(gk)))
+        return gt, gw, gk.value
+
+    def recorded_run(self):
+        """(serial, dt, nsteps) of the run kept for adjoint_recorded (serial 0: none)."""
+        sr, dt, ns = I64(0), F64(0), I64(0)
+        self._chk(self._L.kur_recorded_run(self._h, ctypes.byref(sr), ctypes.byref(dt), ctypes.byref(ns)))
+        return sr.value, dt.value, ns.value
 
     def read_bandwidth(self, nbytes: int = 4 << 30, repeats: int = 5) -> float:
         """GB/s of a plain streaming read on this context's device (roofline reference)."""

@@ -144,3 +144,47 @@ def test_autograd_function(need_gpu):
         assert np.abs(th0.grad.numpy() - gt_o).max() <= 1e-10 * np.abs(gt_o).max()
         assert np.abs(om.grad.numpy() - gw_o).max() <= 1e-10 * np.abs(gw_o).max()
         assert abs(K.grad.item() - gk_o) <= 1e-10 * max(abs(gk_o), 1e-3)
+
+
+def test_recorded_adjoint_matches_full_adjoint(need_gpu):
+    """Checkpoints kept by kur_step_rk4 give bit for bit the gradients of the full adjoint, which
+    repeats the forward pass; a change of omega or K invalidates the recording."""
+    from paper_2102_07167_amd.kur import KurError, KUR_ESTATE
+    w = ragged_sbm(7)
+    seed = np.random.default_rng(3).standard_normal(w.graph.n)
+    for dtype in ("f64", "f32"):
+        with ctx(w, dtype) as k:
+            with pytest.raises(KurError) as ei:
+                k.adjoint_recorded(seed)
+            assert ei.value.status == KUR_ESTATE
+            k.set_option("checkpoint_every", 7)
+            k.step_rk4(w.dt, 30)
+            k.set_option("checkpoint_every", 0)
+            serial, dt, ns = k.recorded_run()
+            assert serial > 0 and dt == w.dt and ns == 30
+            a = k.adjoint_recorded(seed)
+            b = k.adjoint_rk4(w.dt, 30, seed, theta0=w.theta0, ckpt_every=7)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+            k.set_params(w.omega, w.K * 1.5)
+            assert k.recorded_run()[0] == 0
+            with pytest.raises(KurError):
+                k.adjoint_recorded(seed)
+
+
+def test_autograd_two_forwards(need_gpu):
+    """Backward of an earlier forward after a later one on the same model still gets its own
+    gradients (the recording belongs to the later run, so the adjoint repeats the forward)."""
+    import torch
+    from paper_2102_07167_amd.autograd import integrate
+    w = ragged_sbm(11)
+    with ctx(w, "f64") as k:
+        th_a = torch.tensor(w.theta0, requires_grad=True)
+        th_b = torch.tensor(w.theta0[::-1].copy(), requires_grad=True)
+        om = torch.tensor(w.omega)
+        K = torch.tensor(w.K, dtype=torch.float64)
+        out_a = integrate(k, th_a, om, K, w.dt, 20, 8)
+        out_b = integrate(k, th_b, om, K, w.dt, 20, 8)
+        out_a.sum().backward()
+        out_b.sum().backward()
+    # L = sum theta(T): dL/dtheta0 = 1 (symmetric A, uniform scaling)
+    assert np.abs(th_a.grad.numpy() - 1).max() < 1e-12 and np.abs(th_b.grad.numpy() - 1).max() < 1e-12
