@@ -29,6 +29,7 @@ METRIC = "RK4 steps/s and RHS evals/s at N=2^20 (fraction of HBM roofline); adjo
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2102_07167_amd", "csrc", "kur_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rows_kernel_traffic.json")
+TUNE_CACHE = os.path.join(ROOT, "paper_2102_07167_amd", "tuned_layouts.tsv")
 
 
 def log(msg):
@@ -38,6 +39,11 @@ def log(msg):
 def kernel_hash() -> str:
     with open(KERNEL_SOURCE, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def layout_of(info: dict) -> dict:
+    """The layout figures a stored traffic measurement must share with this run."""
+    return {k: int(info[k]) for k in ("chunk", "tiles", "list_padded", "dense_blocks")}
 
 
 def algorithmic_bytes_per_eval(info: dict, elem: int) -> int:
@@ -122,6 +128,12 @@ def bench_batch(args):
     info = k.graph_info()
     ntot = info["n"]
     log("batch of %d instances, %d nodes, set in %.1f s: %s" % (len(insts), ntot, time.perf_counter() - t0, info))
+    tuning = None
+    if args.tune_effort >= 0:
+        t0 = time.perf_counter()
+        tuning = k.tune_tiles(args.tune_effort)
+        info = k.graph_info()
+        log("tiles tuned in %.1f s: %s" % (time.perf_counter() - t0, tuning))
     dt = 0.01
     k.batch_step(dt, args.warmup, 10)
     k.sync()
@@ -139,6 +151,7 @@ def bench_batch(args):
                                   "communities, rho 0.97, p_out 2e-4) by a coin, K=linspace(0,6,256), dt=0.01, "
                                   "r every 10 steps, seed 1004", "nodes": ntot, "list_entries": info["list_entries"],
                       "inter_entries": info["inter_entries"], "tiles": info["tiles"]},
+           "layout": {"tuning": tuning},
            "r_final_K0": float(r[-1, 0]), "r_final_K6": float(r[-1, -1])}
     print(json.dumps(out), flush=True)
     k.close()
@@ -155,6 +168,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--option", action="append", default=[], help="library option key=value")
+    ap.add_argument("--tune-effort", type=int, default=1, choices=[-1, 0, 1, 2],
+                    help="layout autotuning effort (-1: defaults and --option values only)")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="tuning cache file (a matching entry skips the timing)")
     ap.add_argument("--adjoint-steps", type=int, default=64,
                     help="steps of the timed adjoint leg (0 skips it); checkpoints every 32 steps")
     args = ap.parse_args()
@@ -189,7 +206,13 @@ def main():
         key, v = kv.split("=")
         k.set_option(key, float(v))
     t0 = time.perf_counter()
-    k.set_graph(w.graph)
+    tuning = None
+    if args.tune_effort >= 0 and not getattr(w.graph, "complete", False):
+        tuning = k.autotune(w.graph, effort=args.tune_effort, cache=args.tune_cache)
+        log("layout %s in %.1f s: %s" % ("from the tuning cache" if tuning["cache"] == 1 else "tuned",
+                                         time.perf_counter() - t0, tuning))
+    else:
+        k.set_graph(w.graph)
     k.set_params(w.omega, w.K)
     k.set_phases(w.theta0)
     info = k.graph_info()
@@ -223,7 +246,8 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         try:
             tr = json.load(open(TRAFFIC_FILE))
-            if tr.get("kernel_sha") == kernel_hash() and tr.get("workload") == args.workload:
+            if (tr.get("kernel_sha") == kernel_hash() and tr.get("workload") == args.workload
+                    and tr.get("layout") == layout_of(info)):
                 traffic = tr.get("bytes_per_launch")
         except Exception:
             traffic = None
@@ -242,6 +266,8 @@ def main():
         "data": "synthetic",
         "config": workload_desc(args.workload, w, info),
         "rhs_evals_per_s": 4 * steps_per_s,
+        "layout": {"tuning": tuning, "chunk": info["chunk"], "tiles": info["tiles"],
+                   "dense_blocks": info["dense_blocks"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_rows", "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": b_eval},

@@ -264,6 +264,41 @@ kur_status kur_kernel_time(kur_ctx *ctx, int64_t *launches, double *total_ms);
  * `repeats` times. Synchronous. */
 kur_status kur_read_bandwidth(kur_ctx *ctx, int64_t bytes, int32_t repeats, double *gbps);
 
+/*
+ * Layout autotuning. The density threshold tau that decides whether a block stores its zeros
+ * (localised order parameters) or its ones (straightforward summation) follows the
+ * Introduction and Sec. 3: precomputed sums pay off once ones outnumber zeros, so tau = 1/2
+ * minimises the stored bytes. The tuner times whole RK4 steps of the row kernel with HIP events
+ * for candidate values of tau, the chunk width ("chunk") and the tile options ("tile_rows",
+ * "tile_min_cost", "flat_min_vec", "threads"), by coordinate descent from the options in
+ * force; a candidate wins only when it is at least 1 % faster. Results do not change with the
+ * layout beyond rounding order.
+ *
+ * report (may be NULL) receives 12 doubles: tau, chunk, threads, tile_rows, tile_min_cost,
+ * flat_min_vec, ms per RK4 step of the chosen layout, ms per step of the starting layout (NaN
+ * when taken from the cache), candidates timed, cache status (1: loaded from the cache, 0:
+ * tuned and stored or no cache given, -1: tuned but the cache file could not be written), list
+ * builds, seconds spent. Synchronous; effort 0, 1 or 2 widens the candidate sets.
+ *
+ * kur_autotune_csr: takes the arguments of kur_set_graph_csr and ends with that graph installed
+ * in the chosen layout, as kur_set_graph_csr would (omega, K and phases unset); the options
+ * chosen stay in force for later builds. cache_path (NULL: none) is a text file with one line
+ * per graph signature (dtype, device, n, edge count and a sampled hash of row offsets and
+ * labels); a matching line skips the timing, also on a host-only context. Without a match a
+ * host-only context returns KUR_EDEVICE. The lists are rebuilt once per timed tau or chunk.
+ *
+ * kur_tune_tiles: tile options only, on the installed graph or batch (no list rebuild; the
+ * lists, omega, K and phases stay as they are). Device contexts only.
+ *
+ * kur_tune_key: the cache signature of a graph for this context (NUL-terminated, at most 255
+ * characters) in buf of len bytes.
+ */
+kur_status kur_autotune_csr(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                            const int32_t *labels, int32_t effort, const char *cache_path, double *report);
+kur_status kur_tune_tiles(kur_ctx *ctx, int32_t effort, double *report);
+kur_status kur_tune_key(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *labels, char *buf,
+                        size_t len);
+
 /* Device-pointer variants. Arrays are in BLOCK order and of the context dtype
  * (float or double); they enqueue on the context stream. */
 kur_status kur_eval_rhs_dev(kur_ctx *ctx, const void *theta_dev, void *dtheta_dev);

@@ -239,24 +239,34 @@ std::string finish(BlockGraph &g, const std::vector<int32_t> &block_of_row, cons
     });
     if (err.bad) return err.msg;
 
+    make_tiles(g, opt);
+    return "";
+}
+
+}  // namespace
+
+void make_tiles(BlockGraph &g, const BuildOptions &opt)
+{
+    const int64_t n = g.n;
+    g.tile_rows = opt.tile_rows;
     // work tiles: consecutive rows of one block with similar cost
     std::vector<int64_t> rowcost(n);
     int64_t total = 0;
     for (auto &b : g.blk) {
         for (int32_t r = 0; r < b.size; ++r) {
-            int64_t c = 32 + 4 * inter_row[b.row0 + r];
+            const int64_t m = b.row0 + r;
+            int64_t c = 32 + 4 * (g.inter_ptr[m + 1] - g.inter_ptr[m]);
             for (int32_t ch = 0; ch < b.nchunk; ++ch) {
                 int64_t idx = b.segbase + (int64_t)ch * b.size + r;
                 c += g.seg_ptr[idx + 1] - g.seg_ptr[idx];
             }
-            rowcost[b.row0 + r] = c;
+            rowcost[m] = c;
             total += c;
         }
     }
     // a tile's list work should amortise its fixed cost (block-sum fold, staging, launch)
     const int64_t target = std::max<int64_t>(opt.tile_min_cost, total / std::max<int64_t>(1, opt.tiles_target));
     g.tiles.clear();
-    std::vector<int64_t> tcost;
     for (int32_t bi = 0; bi < g.nb; ++bi) {
         BlkInfo &b = g.blk[bi];
         b.tile0 = (int32_t)g.tiles.size();
@@ -282,17 +292,12 @@ std::string finish(BlockGraph &g, const std::vector<int32_t> &block_of_row, cons
             if (opt.flat_min_vec > 0 && avg >= opt.flat_min_vec) G = 0;  // wave-streaming mode
             if (nonempty == 0) G = -1;                                    // no list entries at all
             g.tiles.push_back(Tile{bi, r, r1, G});
-            tcost.push_back(c + (int64_t)b.size * nonempty / 4);
             r = r1;
         }
         b.ntiles = (int32_t)g.tiles.size() - b.tile0;
     }
-    (void)tcost;
     order_tiles(g);
-    return "";
 }
-
-}  // namespace
 
 void order_tiles(BlockGraph &g)
 {

@@ -14,6 +14,7 @@
 #include "../../include/kur.h"
 #include "kur_internal.hpp"
 #include "kur_kernels.hpp"
+#include "kur_tune.hpp"
 
 using namespace kur;
 
@@ -54,6 +55,8 @@ struct kur_ctx {
     int64_t info[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     bool symmetric = false;
     BlockGraph host_graph;  // full layout, kept by host-only contexts for introspection
+    BlockGraph skel;        // device contexts: blocks, segment and inter offsets (no lists), for re-tiling
+    TileParams tiles_installed;  // tile options of the installed layout
 
     // device graph
     DevBuf d_blk, d_tiles, d_order, d_seg, d_list, d_iptr, d_icol;
@@ -425,7 +428,23 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
     for (const BlkInfo &b : g.blk) smax = std::max<int64_t>(smax, b.size);
     c->info[9] = smax;
     c->symmetric = g.symmetric;
-    if (c->host_only) c->host_graph = std::move(g);
+    c->tiles_installed.threads = c->threads;
+    c->tiles_installed.tile_rows = g.tile_rows;
+    c->tiles_installed.tile_min_cost = c->bopt.tile_min_cost;
+    c->tiles_installed.flat_min_vec = c->bopt.flat_min_vec;
+    if (c->host_only) {
+        c->host_graph = std::move(g);
+    } else {
+        c->skel = BlockGraph();
+        c->skel.n = g.n;
+        c->skel.nb = g.nb;
+        c->skel.W = g.W;
+        c->skel.tile_rows = g.tile_rows;
+        c->skel.esz2 = g.esz2;
+        c->skel.blk.swap(g.blk);
+        c->skel.seg_ptr.swap(g.seg_ptr);
+        c->skel.inter_ptr.swap(g.inter_ptr);
+    }
     c->has_graph = true;
     c->has_params = false;
     c->has_phases = false;
@@ -1524,3 +1543,214 @@ extern "C" kur_status kur_recorded_run(const kur_ctx *c, int64_t *serial, double
     if (nsteps) *nsteps = ok ? c->rec_nsteps : 0;
     return KUR_OK;
 }
+
+// ---------------------------------------------------------------------------------------------
+// Hooks of the layout autotuner (kur_tune.hpp).
+
+namespace kur {
+
+bool ctx_is_device(const kur_ctx *c) { return c && !c->host_only; }
+bool ctx_has_graph(const kur_ctx *c) { return c && c->has_graph; }
+int ctx_esz(const kur_ctx *c) { return c->esz; }
+kur_status ctx_fail(kur_ctx *c, kur_status s, const std::string &msg) { return fail(c, s, msg); }
+int32_t ctx_max_chunk(const kur_ctx *c) { return (int32_t)((65535 / c->bopt.esz2) / 64 * 64); }
+
+std::string ctx_arch(const kur_ctx *c)
+{
+    if (c->host_only) return "host";
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return "unknown";
+    std::string arch(prop.gcnArchName);
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    return arch + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+}
+
+TileParams ctx_tile_params(const kur_ctx *c) { return c->tiles_installed; }
+
+bool ctx_layout_fits(const kur_ctx *c, int32_t chunk, const TileParams &t)
+{
+    // the row kernel, and for a symmetric graph also the adjoint kernel (twice the staged width)
+    const int nv = c->has_graph && c->symmetric ? 2 : 1;
+    return rows_lds_bytes(c->esz, chunk > 0 ? chunk : c->W, t.tile_rows, t.threads, nv) <= 156 * 1024;
+}
+
+LayoutParams ctx_layout_params(const kur_ctx *c)
+{
+    LayoutParams l;
+    l.tau = c->bopt.tau;
+    l.chunk = c->bopt.W;
+    return l;
+}
+
+kur_status ctx_set_build_options(kur_ctx *c, const LayoutParams &l, const TileParams &t)
+{
+    if (!(l.tau >= 0.0 && l.tau <= 1.0) || l.chunk < 64 || l.chunk % 64 || l.chunk > ctx_max_chunk(c) ||
+        t.tile_rows < 64 || t.tile_rows > 4096 || t.tile_min_cost < 1 || !(t.flat_min_vec >= 0.0) ||
+        (t.threads != 256 && t.threads != 512 && t.threads != 1024))
+        return fail(c, KUR_EINVAL, "layout options out of range");
+    c->bopt.tau = l.tau;
+    c->bopt.W = l.chunk;
+    c->bopt.tile_rows = t.tile_rows;
+    c->bopt.tile_min_cost = t.tile_min_cost;
+    c->bopt.flat_min_vec = t.flat_min_vec;
+    c->threads = t.threads;
+    c->gen++;
+    return KUR_OK;
+}
+
+kur_status ctx_retile(kur_ctx *c, const TileParams &t)
+{
+    if (!c->has_graph) return fail(c, KUR_ESTATE, "no graph set");
+    if (t.tile_rows < 64 || t.tile_rows > 4096 || t.tile_min_cost < 1 || !(t.flat_min_vec >= 0.0) ||
+        (t.threads != 256 && t.threads != 512 && t.threads != 1024))
+        return fail(c, KUR_EINVAL, "tile options out of range");
+    if (!ctx_layout_fits(c, c->W, t)) return fail(c, KUR_EINVAL, "chunk/tile_rows/threads exceed the LDS of a workgroup");
+    BlockGraph &L = c->host_only ? c->host_graph : c->skel;
+    BuildOptions o = c->bopt;
+    o.tile_rows = t.tile_rows;
+    o.tile_min_cost = t.tile_min_cost;
+    o.flat_min_vec = t.flat_min_vec;
+    try {
+        make_tiles(L, o);
+    } catch (const std::bad_alloc &) {
+        return fail(c, KUR_ENOMEM, "host allocation failed while re-tiling");
+    }
+    if (L.tiles.size() > (size_t)INT32_MAX) return fail(c, KUR_EINVAL, "too many tiles");
+    c->ntiles = (int32_t)L.tiles.size();
+    c->tile_rows = t.tile_rows;
+    c->threads = t.threads;
+    c->info[6] = c->ntiles;
+    c->bopt.tile_rows = t.tile_rows;
+    c->bopt.tile_min_cost = t.tile_min_cost;
+    c->bopt.flat_min_vec = t.flat_min_vec;
+    c->tiles_installed = t;
+    // tiles never span blocks and an instance is a run of whole blocks: its first tile is the
+    // first tile of the first block at or after its first row
+    c->inst_tile_first.assign(c->n_inst + 1, (int64_t)c->ntiles);
+    for (int32_t i = 0; i < c->n_inst; ++i) {
+        const int64_t r = c->inst_row_first[i];
+        auto it = std::lower_bound(L.blk.begin(), L.blk.end(), r,
+                                   [](const BlkInfo &b, int64_t row) { return (int64_t)b.row0 < row; });
+        if (it != L.blk.end()) c->inst_tile_first[i] = it->tile0;
+    }
+    c->sc_valid = false;
+    c->gen++;
+    if (c->host_only) return KUR_OK;
+    HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    hipError_t e;
+    const size_t T = (size_t)c->esz;
+    if ((e = upload(c->d_blk, L.blk.data(), sizeof(BlkInfo) * L.blk.size(), c->stream)) != hipSuccess ||
+        (e = upload(c->d_tiles, L.tiles.data(), sizeof(Tile) * L.tiles.size(), c->stream)) != hipSuccess ||
+        (e = upload(c->d_order, L.order.data(), sizeof(int32_t) * L.order.size(), c->stream)) != hipSuccess ||
+        (e = dalloc(c->d_part[0], 2 * T * L.tiles.size())) != hipSuccess ||
+        (e = dalloc(c->d_part[1], 2 * T * L.tiles.size())) != hipSuccess ||
+        (e = dalloc(c->d_parte, 2 * T * L.tiles.size())) != hipSuccess) {
+        c->has_graph = false;  // partially replaced device layout: unusable until the next set_graph
+        return hip_fail(c, e, "re-tiled layout upload");
+    }
+    L.tiles.clear();
+    L.tiles.shrink_to_fit();
+    L.order.clear();
+    L.order.shrink_to_fit();
+    return upload_instances(c);
+}
+
+kur_status ctx_time_steps(kur_ctx *c, int trials, double *ms_per_step)
+{
+    kur_status s = need_ready(c, false, false);
+    if (s != KUR_OK) return s;
+    const bool synth = !(c->has_params && c->has_phases);
+    const int64_t n = c->n;
+    const size_t TN = (size_t)c->esz * (size_t)n;
+    DevBuf sv_hi, sv_lo, sv_wind;
+    hipError_t e = hipSuccess;
+    struct Release {
+        DevBuf *b[3];
+        ~Release()
+        {
+            for (DevBuf *x : b) dfree(*x);
+        }
+    } rel{{&sv_hi, &sv_lo, &sv_wind}};
+    if (synth) {
+        // omega = 0, K = 1 and phases spread by the golden ratio: the timed work does not
+        // depend on the values
+        std::vector<double> om(n, 0.0), th(n);
+        for (int64_t u = 0; u < n; ++u) th[u] = 2.0 * kPi * std::fmod(0.6180339887498949 * (double)u, 1.0);
+        if ((s = kur_set_params(c, om.data(), 1.0)) != KUR_OK || (s = kur_set_phases(c, th.data())) != KUR_OK)
+            return s;
+    } else {
+        if ((e = dalloc(sv_hi, TN)) != hipSuccess || (e = dalloc(sv_lo, TN)) != hipSuccess ||
+            (e = dalloc(sv_wind, 4 * (size_t)n)) != hipSuccess ||
+            (e = hipMemcpyAsync(sv_hi.p, c->d_hi.p, TN, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(sv_lo.p, c->d_lo.p, TN, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(sv_wind.p, c->d_wind.p, 4 * (size_t)n, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+            return hip_fail(c, e, "state save");
+    }
+    const int cur0 = c->cur;
+    const int timing0 = c->timing;
+    c->timing = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double best = 1e300;
+    if ((e = hipEventCreate(&e0)) == hipSuccess && (e = hipEventCreate(&e1)) == hipSuccess) {
+        if (!c->sc_valid) {
+            s = sc_init(c, c->d_hi.p, c->d_sc[c->cur], c->d_part[c->cur]);
+            c->sc_valid = s == KUR_OK;
+        }
+        const DevGraph g = devgraph(c);
+        const double dt = 1e-3;
+        int64_t steps = 1;
+        for (int t = -1; t < trials && s == KUR_OK && e == hipSuccess; ++t) {
+            // t = -1: warm-up step, then one step to size the trials to about 4 ms each
+            if (t == -1 && (e = launch_step(c, g, dt)) != hipSuccess) break;
+            if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) break;
+            for (int64_t k = 0; k < steps && e == hipSuccess; ++k) e = launch_step(c, g, dt);
+            if (e != hipSuccess || (e = hipEventRecord(e1, c->stream)) != hipSuccess ||
+                (e = hipEventSynchronize(e1)) != hipSuccess)
+                break;
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            if (t == -1)
+                steps = std::min<int64_t>(256, std::max<int64_t>(2, (int64_t)std::ceil(4.0 / std::max(1e-3, (double)ms))));
+            else
+                best = std::min(best, (double)ms / (double)steps);
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    c->timing = timing0;
+    c->cur = cur0;
+    c->sc_valid = false;
+    if (s != KUR_OK) return s;
+    if (e != hipSuccess) return hip_fail(c, e, "timed steps");
+    if (synth) {
+        c->has_params = false;
+        c->has_phases = false;
+    } else {
+        if ((e = hipMemcpyAsync(c->d_hi.p, sv_hi.p, TN, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(c->d_lo.p, sv_lo.p, TN, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(c->d_wind.p, sv_wind.p, 4 * (size_t)n, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+            return hip_fail(c, e, "state restore");
+    }
+    *ms_per_step = best;
+    return KUR_OK;
+}
+
+void ctx_block_stats(const kur_ctx *c, std::vector<double> &density, std::vector<int32_t> &size)
+{
+    const BlockGraph &L = c->host_only ? c->host_graph : c->skel;
+    density.assign(L.blk.size(), 0.0);
+    size.assign(L.blk.size(), 0);
+    for (size_t b = 0; b < L.blk.size(); ++b) {
+        const BlkInfo &bi = L.blk[b];
+        double ones = 0.0;
+        for (int64_t m = bi.row0; m < (int64_t)bi.row0 + bi.size; ++m)
+            ones += (double)c->deg[m] - (double)(L.inter_ptr[m + 1] - L.inter_ptr[m]);
+        const double pairs = (double)bi.size * (double)(bi.size - 1);
+        density[b] = pairs > 0 ? ones / pairs : 0.0;
+        size[b] = bi.size;
+    }
+}
+
+}  // namespace kur

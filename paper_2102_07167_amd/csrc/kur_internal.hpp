@@ -79,6 +79,11 @@ std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &out);
 std::string merge_graphs(std::vector<BlockGraph> &parts, BlockGraph &out, std::vector<int64_t> &row_first,
                          std::vector<int64_t> &tile_first);
 
+// Work tiles from the segment and inter-block offsets alone (the lists are not read): rows of one
+// block grouped until a tile carries max(tile_min_cost, total / tiles_target) of estimated work
+// or tile_rows rows; sets blk[].tile0/ntiles, tiles, tile_rows and the launch order.
+void make_tiles(BlockGraph &g, const BuildOptions &opt);
+
 // Launch order of tiles: largest estimated cost first (stable).
 void order_tiles(BlockGraph &g);
 

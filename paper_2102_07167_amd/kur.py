@@ -59,6 +59,9 @@ SIGNATURES = {
     "kur_read_bandwidth": (ST, [P, I64, I32, P]),
     "kur_adjoint_rk4_recorded": (ST, [P, P, P, P, P]),
     "kur_recorded_run": (ST, [P, P, P, P]),
+    "kur_autotune_csr": (ST, [P, I64, P, P, P, I32, ctypes.c_char_p, P]),
+    "kur_tune_tiles": (ST, [P, I32, P]),
+    "kur_tune_key": (ST, [P, I64, P, P, ctypes.c_char_p, ctypes.c_size_t]),
     "kur_eval_rhs_dev": (ST, [P, P, P]),
     "kur_get_phases_dev": (ST, [P, P]),
 }
@@ -301,6 +304,42 @@ class Kuramoto:
         sr, dt, ns = I64(0), F64(0), I64(0)
         self._chk(self._L.kur_recorded_run(self._h, ctypes.byref(sr), ctypes.byref(dt), ctypes.byref(ns)))
         return sr.value, dt.value, ns.value
+
+    # -- layout autotuning -------------------------------------------------------------------
+    _TUNE_FIELDS = ("tau", "chunk", "threads", "tile_rows", "tile_min_cost", "flat_min_vec", "ms_per_step",
+                    "ms_per_step_start", "timed", "cache", "builds", "seconds")
+
+    def _tune_report(self, rep):
+        d = dict(zip(self._TUNE_FIELDS, (float(x) for x in rep)))
+        for k in ("chunk", "threads", "tile_rows", "tile_min_cost", "timed", "cache", "builds"):
+            d[k] = int(d[k])
+        return d
+
+    def autotune(self, graph, effort: int = 1, cache: str | None = None) -> dict:
+        """Install `graph` (CSR with planted labels) in the layout that runs fastest on this device;
+        see kur_autotune_csr. Returns the chosen options and timings."""
+        rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(graph.col, dtype=np.int32)
+        lb = np.ascontiguousarray(graph.labels, dtype=np.int32)
+        rep = np.zeros(12)
+        self._chk(self._L.kur_autotune_csr(self._h, int(graph.n), _ptr(rp), _ptr(cl), _ptr(lb), int(effort),
+                                           None if cache is None else os.fsencode(cache), _ptr(rep)))
+        self.n = int(graph.n)
+        return self._tune_report(rep)
+
+    def tune_tiles(self, effort: int = 1) -> dict:
+        """Re-tile the installed graph or batch with the fastest tile options (kur_tune_tiles)."""
+        rep = np.zeros(12)
+        self._chk(self._L.kur_tune_tiles(self._h, int(effort), _ptr(rep)))
+        return self._tune_report(rep)
+
+    def tune_key(self, graph) -> str:
+        """The tuning-cache signature of `graph` for this context."""
+        rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int64)
+        lb = np.ascontiguousarray(graph.labels, dtype=np.int32)
+        buf = ctypes.create_string_buffer(256)
+        self._chk(self._L.kur_tune_key(self._h, int(graph.n), _ptr(rp), _ptr(lb), buf, 256))
+        return buf.value.decode()
 
     def read_bandwidth(self, nbytes: int = 4 << 30, repeats: int = 5) -> float:
         """GB/s of a plain streaming read on this context's device (roofline reference)."""
