@@ -157,12 +157,86 @@ def bench_batch(args):
     k.close()
 
 
+def bench_ensemble(args):
+    """B replicas of one graph (the equal-community SBM, 64 x 1024, rho 0.97, p_out 2e-4) with
+    K swept over [0, 6], omega ~ N(0, 1) and theta0 ~ U[0, 2 pi) per replica; r of every replica
+    every 10 steps. Dense blocks form A_b [sin, cos] on the matrix cores when the tuner says so."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2102_07167_amd import Kuramoto
+    B = args.replicas
+    w = gen.sbm_equal(seed=1002)
+    g = w.graph
+    rng = np.random.default_rng(1006)
+    K = np.linspace(0.0, 6.0, B)
+    om = rng.standard_normal((B, g.n))
+    th = rng.uniform(0.0, 2 * np.pi, (B, g.n))
+    k = Kuramoto("f32", device=0)
+    for kv in args.option:
+        key, v = kv.split("=")
+        k.set_option(key, float(v))
+    t0 = time.perf_counter()
+    tuning = None
+    if args.tune_effort >= 0:
+        tuning = k.ens_autotune(g, B, args.tune_effort)
+        log("ensemble threshold tuned in %.1f s: %s" % (time.perf_counter() - t0, tuning))
+    else:
+        k.ens_set_graph(g)
+    k.ens_set_params(K, om)
+    k.ens_set_phases(th)
+    info = k.ens_info()
+    log("ensemble layout: %s" % info)
+    dt, r_every = 0.01, 10
+    k.ens_step(dt, args.warmup, r_every)
+    k.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, _ = k.ens_step(dt, args.steps, r_every)
+    k.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    assert np.isfinite(r).all()
+    # per-kernel split from HIP events on a separate short run
+    k.set_option("timing", 1)
+    k.ens_kernel_time()
+    k.ens_step(dt, 50, 0)
+    kt = k.ens_kernel_time()
+    k.set_option("timing", 0)
+    out = {"metric": "aggregate node-steps/s of a shared-graph ensemble (RK4)", "value": g.n * B * args.steps / el,
+           "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "%d replicas of the equal-community SBM N=65536 (64 x 1024, rho 0.97, p_out 2e-4), "
+                                  "K=linspace(0,6,%d), omega~N(0,1), theta0~U[0,2pi) per replica, dt=0.01, r every 10 "
+                                  "steps, seed 1006" % (B, B), "layout": info, "tuning": tuning}}
+    if kt["gemm_launches"] > 0:
+        # issued matrix-core work per launch: every 128 x 128 output tile of a block runs over
+        # the block's width padded to 32, with three bf16 terms and 2 flops per multiply-add
+        modes, _ = k.ens_block_modes()
+        sizes = np.bincount(np.unique(g.labels, return_inverse=True)[1])
+        J = 2 * info["Bp"]
+        issued = sum(2.0 * 3 * 128 * 128 * (-(-s // 32) * 32) * (-(-s // 128)) * (J // 128)
+                     for s, m in zip(sizes, modes) if m)
+        useful = 2.0 * info["gemm_pairs"] * 2 * B
+        gms = kt["gemm_ms"] / kt["gemm_launches"]
+        out["roofline"] = {"bound": "mfma", "achieved": issued / (gms * 1e-3) / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                           "frac": issued / (gms * 1e-3) / 1e12 / 2500.0, "traffic": None, "kernel": "k_ens_gemm",
+                           "avg_launch_ms": gms, "issued_bf16_flops_per_launch": issued,
+                           "useful_fp32_flops_per_launch": useful,
+                           "rows_kernel_avg_ms": kt["rows_ms"] / max(1, kt["rows_launches"])}
+    print(json.dumps(out), flush=True)
+    k.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="het", choices=["het", "sbm", "a2a", "batch"])
+    ap.add_argument("--workload", default="het", choices=["het", "sbm", "a2a", "batch", "ens"])
+    ap.add_argument("--replicas", type=int, default=128, help="replicas of the ensemble workload (1..256)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -196,6 +270,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "ens":
+        return bench_ensemble(args)
     t0 = time.perf_counter()
     w = make_workload(args.workload)
     log("workload %s generated in %.1f s (nnz %d)" % (w.name, time.perf_counter() - t0, w.graph.nnz))

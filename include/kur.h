@@ -96,6 +96,9 @@ const char *kur_last_error(const kur_ctx *ctx);
  *   "graph"       1 (default): kur_step_rk4 captures one sampling period (r_every steps, else
  *                 "graph_steps" steps) into a HIP graph and replays it; 0: plain launches.
  *   "graph_steps" steps per replayed graph when no order parameter is sampled (default 16).
+ *   "ens_tau"     shared-graph ensembles: blocks at least this dense form their products on the
+ *                 matrix cores (0..2, above 1: none). Default 0.5. Takes effect at the next
+ *                 kur_ens_set_graph_csr.
  * Unknown keys and out-of-range values return KUR_EINVAL.
  */
 kur_status kur_set_option(kur_ctx *ctx, const char *key, double value);
@@ -298,6 +301,60 @@ kur_status kur_autotune_csr(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, con
 kur_status kur_tune_tiles(kur_ctx *ctx, int32_t effort, double *report);
 kur_status kur_tune_key(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *labels, char *buf,
                         size_t len);
+
+/*
+ * Shared-graph ensembles: B replicas (1..256) of one graph, each with its own omega, K and
+ * phases, integrated together with classical RK4. The replicas' coupling sums of a row are the
+ * row of A X with X = [sin Theta, cos Theta] (n x 2B), the sums of eq.
+ * KuramotoGraphReformulation for all replicas at once. For every community block whose realised
+ * density is at least the option "ens_tau" (default 0.5; above 1: none) this is a dense matrix
+ * product A_b X_b, run on the matrix cores (0/1 pattern stored as a bitmask, X split exactly into
+ * three bf16 terms, FP32 accumulation); the remaining blocks' edges and all inter-block edges are
+ * summed as CSR rows (Sec. 3: block structure with dense and sparse parts). Replica e follows
+ * d theta_m / dt = omega_{e,m} + (K_e / N) sum_l A_ml sin(theta_l - theta_m).
+ * FP32 contexts only (KUR_EINVAL otherwise). Independent of the single-system graph and state.
+ *
+ * kur_ens_set_graph_csr  CSR with planted labels, as kur_set_graph_csr; host-only contexts keep
+ *                        the layout for inspection (kur_ens_row_pattern); params and phases unset
+ * kur_ens_set_params     K (B) and omega (B x n, replica-major, user order); copied
+ * kur_ens_set_phases     theta (B x n, replica-major, user order, |theta| <= 1e9)
+ * kur_ens_eval_rhs       dtheta (B x n) at the current phases
+ * kur_ens_step           nsteps RK4 steps of size dt; with r_every > 0, r_out and psi_out (each
+ *                        (nsteps / r_every + 1) x B, sample-major, may be NULL) receive the order
+ *                        parameter of every replica at step 0 and every r_every steps
+ * kur_ens_get_phases     theta (B x n), wrapped to [-pi, pi) or unwrapped (winding counts)
+ * kur_ens_info           out[10]: n, blocks, matrix-core blocks, their rows, sum of their
+ *                        squared sizes, CSR entries, B, B padded to 64, matrix-product work
+ *                        items, symmetric
+ * kur_ens_block_modes    per block (either may be NULL): 1 if on the matrix cores, realised density
+ * kur_ens_get_perm       user node -> block-order row (n)
+ * kur_ens_row_pattern    host-only contexts: block-order row m's CSR columns (block order) into
+ *                        csr_cols, which holds *ncsr entries on entry (NULL: count only; too few:
+ *                        KUR_EINVAL); *ncsr receives the count. If the row's block is on the
+ *                        matrix cores, dense (block size bytes, may be NULL) receives its 0/1
+ *                        pattern over the block
+ * kur_ens_kernel_time    with option "timing" = 1: out[4] = matrix-product launches, their total
+ *                        ms, row-kernel launches, their total ms, since the previous call
+ * kur_ens_autotune_csr   times RK4 steps of B replicas (synthetic values) for candidate
+ *                        thresholds, installs the graph with the fastest, sets "ens_tau";
+ *                        report (may be NULL) receives 6 doubles: threshold, ms per step, ms with
+ *                        every block on the matrix cores, ms with none (NaN if not timed),
+ *                        candidates timed, seconds
+ */
+kur_status kur_ens_set_graph_csr(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                                 const int32_t *labels);
+kur_status kur_ens_set_params(kur_ctx *ctx, int32_t B, const double *K, const double *omega);
+kur_status kur_ens_set_phases(kur_ctx *ctx, const double *theta);
+kur_status kur_ens_eval_rhs(kur_ctx *ctx, double *dtheta);
+kur_status kur_ens_step(kur_ctx *ctx, double dt, int64_t nsteps, int64_t r_every, double *r_out, double *psi_out);
+kur_status kur_ens_get_phases(kur_ctx *ctx, double *theta, int wrapped);
+kur_status kur_ens_info(kur_ctx *ctx, int64_t *out);
+kur_status kur_ens_block_modes(kur_ctx *ctx, uint8_t *gemm, double *density);
+kur_status kur_ens_get_perm(kur_ctx *ctx, int32_t *perm);
+kur_status kur_ens_row_pattern(kur_ctx *ctx, int64_t m, int32_t *csr_cols, int64_t *ncsr, uint8_t *dense);
+kur_status kur_ens_kernel_time(kur_ctx *ctx, double *out);
+kur_status kur_ens_autotune_csr(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                                const int32_t *labels, int32_t B, int32_t effort, double *report);
 
 /* Device-pointer variants. Arrays are in BLOCK order and of the context dtype
  * (float or double); they enqueue on the context stream. */

@@ -1,0 +1,68 @@
+// ens.hpp -- layout and launchers of the shared-graph ensemble path: B replicas of one graph,
+// state stored node-major ([n][Bp] per quantity, Bp = B rounded up to 64) so that one row's
+// replicas are contiguous.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kur {
+
+// A diagonal block whose product A_b X_b runs on the matrix cores.
+struct EnsBlk {
+    int64_t bits_off;  // first 32-bit word of the block's 0/1 pattern (row-major)
+    int32_t row0;      // first block-order row
+    int32_t size;      // rows = columns
+    int32_t words;     // words per pattern row = ceil(size / 32); bit (k & 31) of word k / 32 is A(row, k)
+    int32_t pad;
+};
+
+// One workgroup of the dense product: rows [r0, r0 + 128) of block `blk` (block-local) and
+// columns [c0, c0 + 128) of X.
+struct EnsItem {
+    int32_t blk, r0, c0, pad;
+};
+
+constexpr int kEnsTileRows = 128;
+constexpr int kEnsTileCols = 128;
+
+struct EnsGemmArgs {
+    const EnsBlk *blk;
+    const EnsItem *items;
+    const uint32_t *bits;
+    const float *x;  // [n][J]: sin of every replica, then cos (J = 2 Bp)
+    float *y;        // [n][J]: (A sin, A cos) for the rows of matrix-core blocks
+    int64_t J;
+};
+
+struct EnsRowArgs {
+    int64_t n;
+    int32_t Bp;
+    int32_t stage;  // 0: derivative only (kout); 1..4: RK4 stage
+    int32_t compensate;
+    float dt, half_dt, dt6;
+    const int64_t *csr_ptr;  // n + 1, block order
+    const int32_t *csr_col;  // block-order columns
+    const uint8_t *row_gemm; // 1 where y holds the row's dense-block product
+    const float *x;          // [n][J] stage input (sin | cos)
+    const float *y;
+    float *x_out;            // [n][J] next stage input (sin | cos)
+    const float *omega;      // [n][Bp]
+    const float *unit;       // [Bp]: K_e / N
+    float *hi, *lo;          // [n][Bp] phase and its compensation term
+    int32_t *wind;           // [n][Bp]
+    float *ksum;             // [n][Bp]
+    float *kout;             // [n][Bp], stage 0
+};
+
+hipError_t launch_ens_gemm(const EnsGemmArgs &a, int64_t nitems, hipStream_t st);
+hipError_t launch_ens_rows(const EnsRowArgs &a, hipStream_t st);
+hipError_t launch_ens_sincos(int64_t n, int32_t Bp, const float *hi, float *x, hipStream_t st);
+// partial column sums of x over chunks of 256 rows: part [ceil(n / 256)][J]
+hipError_t launch_ens_colsum(int64_t n, int64_t J, const float *x, float *part, hipStream_t st);
+// r and psi of replicas [0, B) from the partials, written to r[0..B) and psi[0..B)
+hipError_t launch_ens_order(int64_t n, int32_t Bp, int32_t B, const float *part, double *r, double *psi,
+                            hipStream_t st);
+
+}  // namespace kur

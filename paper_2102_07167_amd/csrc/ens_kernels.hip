@@ -1,0 +1,272 @@
+// ens_kernels.hip -- gfx950 kernels of the shared-graph ensemble path.
+//
+// With B replicas of one graph, the coupling sums of a row for all replicas at once are the row
+// of A X with X = [sin Theta, cos Theta] (n x 2B). For a dense community block this is a real
+// matrix product A_b X_b (Sec. 3: the block structure; eq. KuramotoGraphReformulation: the sine
+// difference expanded into sums of sin and cos), which k_ens_gemm runs on the matrix cores:
+//   * A_b is 0/1 and stored as a bitmask; each lane expands one byte into eight bf16 ones and
+//     zeros, which are exact;
+//   * X is split exactly into three bf16 terms x = t0 + t1 + t2 (each the truncated upper half
+//     of the remainder: 8 + 8 + 8 significant bits cover the 24 of FP32), so every product is
+//     exact and only the FP32 accumulation of the matrix core rounds;
+//   * v_mfma_f32_32x32x16_bf16, a 128 x 128 output tile per workgroup (four waves of 32 rows,
+//     four 32-column tiles each), X staged in LDS per 32 columns of A.
+// k_ens_rows then adds the CSR edges (sparse blocks and inter-block edges) by gathering whole
+// X rows (all replicas contiguous), and runs the stage epilogue of every replica:
+// F = omega + K_e / N ((sum A sin) cos y - (sum A cos) sin y), the RK4 bookkeeping and the next
+// stage's (sin, cos).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ens.hpp"
+#include "kur_device.hpp"
+
+namespace kur {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4_e __attribute__((ext_vector_type(4)));
+
+// bits 0..7 of b as eight bf16 values (bit v -> element v): 1.0 = 0x3F80, 0.0 = 0
+__device__ __forceinline__ bf16x8 expand_bits(uint32_t b)
+{
+    u32x4_e v;
+    v.x = ((b >> 0) & 1u) * 0x3F80u | ((b >> 1) & 1u) * 0x3F800000u;
+    v.y = ((b >> 2) & 1u) * 0x3F80u | ((b >> 3) & 1u) * 0x3F800000u;
+    v.z = ((b >> 4) & 1u) * 0x3F80u | ((b >> 5) & 1u) * 0x3F800000u;
+    v.w = ((b >> 6) & 1u) * 0x3F80u | ((b >> 7) & 1u) * 0x3F800000u;
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// x = t0 + t1 + t2 exactly, each term a bf16 bit pattern in the low 16 bits: t0 keeps the upper
+// half of x (8 significant bits), the remainder x - t0 is exact and has at most 16 significant
+// bits, of which t1 keeps the upper 8; the last remainder has at most 8 and is t2 itself.
+__device__ __forceinline__ void split3(float x, uint32_t &t0, uint32_t &t1, uint32_t &t2)
+{
+    const uint32_t h0 = __float_as_uint(x) & 0xFFFF0000u;
+    const float r1 = x - __uint_as_float(h0);
+    const uint32_t h1 = __float_as_uint(r1) & 0xFFFF0000u;
+    const float r2 = r1 - __uint_as_float(h1);
+    t0 = h0 >> 16;
+    t1 = h1 >> 16;
+    t2 = __float_as_uint(r2) >> 16;
+}
+
+__global__ __launch_bounds__(256) void k_ens_gemm(EnsGemmArgs a)
+{
+    // [term][group of 8 k][column]: 8 bf16 of one column, the layout of the B operand
+    __shared__ u32x4_e xs[3][4][kEnsTileCols];
+    const EnsItem it = a.items[blockIdx.x];
+    const EnsBlk b = a.blk[it.blk];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, half = lane >> 5, l32 = lane & 31;
+    // A operand: lane holds row (l32) and k = 8 half + v of each 16-wide k step
+    const int arow = it.r0 + wave * 32 + l32;
+    const bool arow_ok = arow < b.size;
+    const uint32_t *abits = a.bits + b.bits_off + (int64_t)(arow_ok ? arow : 0) * b.words;
+    // staging: thread -> one column, k groups sg and sg + 2 of each 32-wide step
+    const int sc = tid & (kEnsTileCols - 1), sg = tid >> 7;
+    const float *xcol = a.x + (int64_t)b.row0 * a.J + it.c0 + sc;
+    f32x16 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[c][r] = 0.f;
+
+    const int kend = b.words * 32;
+    for (int k0 = 0; k0 < kend; k0 += 32) {
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi) {
+            const int g = sg + 2 * gi;
+            uint32_t t0[8], t1[8], t2[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = k0 + 8 * g + i;
+                const float v = k < b.size ? xcol[(int64_t)k * a.J] : 0.f;
+                split3(v, t0[i], t1[i], t2[i]);
+            }
+            u32x4_e p0, p1, p2;
+            p0.x = t0[0] | (t0[1] << 16); p0.y = t0[2] | (t0[3] << 16); p0.z = t0[4] | (t0[5] << 16); p0.w = t0[6] | (t0[7] << 16);
+            p1.x = t1[0] | (t1[1] << 16); p1.y = t1[2] | (t1[3] << 16); p1.z = t1[4] | (t1[5] << 16); p1.w = t1[6] | (t1[7] << 16);
+            p2.x = t2[0] | (t2[1] << 16); p2.y = t2[2] | (t2[3] << 16); p2.z = t2[4] | (t2[5] << 16); p2.w = t2[6] | (t2[7] << 16);
+            xs[0][g][sc] = p0;
+            xs[1][g][sc] = p1;
+            xs[2][g][sc] = p2;
+        }
+        const uint32_t word = arow_ok ? abits[k0 >> 5] : 0u;
+        __syncthreads();
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+            const int g = 2 * sub + half;
+            const bf16x8 av = expand_bits(word >> (8 * g));
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const bf16x8 bv = __builtin_bit_cast(bf16x8, xs[t][g][ct * 32 + l32]);
+                    acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[ct], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    // result: lane column l32, register r -> row 8 (r / 4) + 4 half + (r % 4) of the wave's 32
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = it.r0 + wave * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+            if (row < b.size) a.y[(int64_t)(b.row0 + row) * a.J + it.c0 + ct * 32 + l32] = acc[ct][r];
+        }
+}
+
+// One wave per row; lane l handles replicas l + 64 q, q < NE.
+template <int NE>
+__global__ __launch_bounds__(256) void k_ens_rows(EnsRowArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t m = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (m >= a.n) return;
+    const int64_t Bp = a.Bp;
+    const int64_t J = 2 * Bp;
+    float as[NE], ac[NE];
+    const bool dense = a.row_gemm[m] != 0;
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        as[q] = dense ? a.y[m * J + lane + 64 * q] : 0.f;
+        ac[q] = dense ? a.y[m * J + Bp + lane + 64 * q] : 0.f;
+    }
+    const int64_t p0 = a.csr_ptr[m], p1 = a.csr_ptr[m + 1];
+    int64_t p = p0;
+    for (; p + 4 <= p1; p += 4) {
+        int64_t col[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) col[i] = a.csr_col[p + i];
+        float vs[4][NE], vc[4][NE];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < NE; ++q) {
+                vs[i][q] = a.x[col[i] * J + lane + 64 * q];
+                vc[i][q] = a.x[col[i] * J + Bp + lane + 64 * q];
+            }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < NE; ++q) {
+                as[q] += vs[i][q];
+                ac[q] += vc[i][q];
+            }
+    }
+    for (; p < p1; ++p) {
+        const int64_t col = a.csr_col[p];
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            as[q] += a.x[col * J + lane + 64 * q];
+            ac[q] += a.x[col * J + Bp + lane + 64 * q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int64_t e = lane + 64 * q;
+        const int64_t ix = m * Bp + e;
+        const float s = a.x[m * J + e], c = a.x[m * J + Bp + e];
+        const float k = a.omega[ix] + a.unit[e] * (as[q] * c - ac[q] * s);
+        if (a.stage == 0) {
+            a.kout[ix] = k;
+            continue;
+        }
+        const float y = rk4_stage<float>(a.stage, k, a.dt, a.half_dt, a.dt6, a.compensate, a.ksum + ix, a.hi + ix,
+                                         a.lo + ix, a.wind + ix);
+        float sy, cy;
+        dev_sincos<float>(y, &sy, &cy);
+        a.x_out[m * J + e] = sy;
+        a.x_out[m * J + Bp + e] = cy;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ens_sincos(int64_t n, int32_t Bp, const float *__restrict__ hi, float *__restrict__ x)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n * Bp) return;
+    const int64_t m = i / Bp, e = i - m * Bp;
+    float s, c;
+    dev_sincos<float>(hi[i], &s, &c);
+    x[m * 2 * Bp + e] = s;
+    x[m * 2 * Bp + Bp + e] = c;
+}
+
+__global__ __launch_bounds__(256) void k_ens_colsum(int64_t n, int64_t J, const float *__restrict__ x, float *__restrict__ part)
+{
+    const int64_t r0 = (int64_t)blockIdx.x * 256;
+    const int64_t r1 = r0 + 256 < n ? r0 + 256 : n;
+    for (int64_t j = threadIdx.x; j < J; j += 256) {
+        float s = 0.f;
+        for (int64_t m = r0; m < r1; ++m) s += x[m * J + j];
+        part[(int64_t)blockIdx.x * J + j] = s;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_ens_order(int64_t nchunk, int32_t Bp, int32_t B, double inv_n,
+                                                  const float *__restrict__ part, double *__restrict__ r,
+                                                  double *__restrict__ psi)
+{
+    const int e = blockIdx.x * 64 + threadIdx.x;
+    if (e >= B) return;
+    double S = 0.0, C = 0.0;
+    for (int64_t c = 0; c < nchunk; ++c) {
+        S += (double)part[c * 2 * Bp + e];
+        C += (double)part[c * 2 * Bp + Bp + e];
+    }
+    S *= inv_n;
+    C *= inv_n;
+    r[e] = sqrt(S * S + C * C);
+    psi[e] = atan2(S, C);
+}
+
+hipError_t launch_ens_gemm(const EnsGemmArgs &a, int64_t nitems, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ens_gemm, dim3((unsigned)nitems), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ens_rows(const EnsRowArgs &a, hipStream_t st)
+{
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n + 3) / 4)), block(256);
+    switch (a.Bp / 64) {
+    case 1: hipLaunchKernelGGL(k_ens_rows<1>, grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_ens_rows<2>, grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_ens_rows<3>, grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(k_ens_rows<4>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ens_sincos(int64_t n, int32_t Bp, const float *hi, float *x, hipStream_t st)
+{
+    const int64_t tot = n * Bp;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ens_sincos, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, Bp, hi, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_ens_colsum(int64_t n, int64_t J, const float *x, float *part, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ens_colsum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, J, x, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_ens_order(int64_t n, int32_t Bp, int32_t B, const float *part, double *r, double *psi, hipStream_t st)
+{
+    if (B <= 0) return hipSuccess;
+    const int64_t nchunk = (n + 255) / 256;
+    hipLaunchKernelGGL(k_ens_order, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, nchunk, Bp, B, 1.0 / (double)n,
+                       part, r, psi);
+    return hipGetLastError();
+}
+
+}  // namespace kur

@@ -422,8 +422,7 @@ std::string merge_graphs(std::vector<BlockGraph> &parts, BlockGraph &g, std::vec
     return "";
 }
 
-std::string build_from_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *labels,
-                           const BuildOptions &opt, BlockGraph &g)
+std::string validate_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *labels)
 {
     if (n < 1 || n > INT32_MAX - 1) return "n must be in [1, 2^31-2]";
     if (!row_ptr || !labels) return "row_ptr and labels must not be NULL";
@@ -442,8 +441,13 @@ std::string build_from_csr(int64_t n, const int64_t *row_ptr, const int32_t *col
     }
     for (int64_t u = 0; u < n; ++u)
         if (labels[u] < 0) return "labels must be >= 0";
+    return "";
+}
 
-    // symmetry of A (diagonal entries ignored)
+bool csr_symmetric(int64_t n, const int64_t *row_ptr, const int32_t *col)
+{
+    // the sums of a 64-bit hash over the (row, col) pairs and over the (col, row) pairs agree
+    // for a symmetric pattern (diagonal entries ignored)
     SymHash sym;
     parallel_for(n, [&](int64_t lo, int64_t hi) {
         uint64_t f = 0, b = 0;
@@ -455,7 +459,12 @@ std::string build_from_csr(int64_t n, const int64_t *row_ptr, const int32_t *col
             }
         sym.add(f, b);
     });
+    return sym.fwd.load() == sym.bwd.load();
+}
 
+int32_t regroup_by_labels(int64_t n, const int32_t *labels, std::vector<int32_t> &perm, std::vector<int32_t> &node_at,
+                          std::vector<int32_t> &block_of_row, std::vector<int64_t> &block_ptr)
+{
     // communities ordered by label value; stable counting sort of the nodes
     std::vector<int32_t> uniq(labels, labels + n);
     std::sort(uniq.begin(), uniq.end());
@@ -466,28 +475,39 @@ std::string build_from_csr(int64_t n, const int64_t *row_ptr, const int32_t *col
         for (int64_t u = lo; u < hi; ++u)
             comm[u] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), labels[u]) - uniq.begin());
     });
-    std::vector<int64_t> cnt(nb + 1, 0);
-    for (int64_t u = 0; u < n; ++u) cnt[comm[u] + 1]++;
-    for (int32_t b = 0; b < nb; ++b) cnt[b + 1] += cnt[b];
+    block_ptr.assign(nb + 1, 0);
+    for (int64_t u = 0; u < n; ++u) block_ptr[comm[u] + 1]++;
+    for (int32_t b = 0; b < nb; ++b) block_ptr[b + 1] += block_ptr[b];
+    perm.resize(n);
+    node_at.resize(n);
+    block_of_row.resize(n);
+    std::vector<int64_t> fill(block_ptr.begin(), block_ptr.end() - 1);
+    for (int64_t u = 0; u < n; ++u) {
+        const int64_t m = fill[comm[u]]++;
+        perm[u] = (int32_t)m;
+        node_at[m] = (int32_t)u;
+        block_of_row[m] = comm[u];
+    }
+    return nb;
+}
+
+std::string build_from_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *labels,
+                           const BuildOptions &opt, BlockGraph &g)
+{
+    std::string msg = validate_csr(n, row_ptr, col, labels);
+    if (!msg.empty()) return msg;
+    const bool symmetric = csr_symmetric(n, row_ptr, col);
     g = BlockGraph();
     g.n = n;
-    g.nb = nb;
-    g.perm.resize(n);
-    std::vector<int32_t> node_at(n), block_of_row(n);
-    {
-        std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-        for (int64_t u = 0; u < n; ++u) {
-            int64_t m = fill[comm[u]]++;
-            g.perm[u] = (int32_t)m;
-            node_at[m] = (int32_t)u;
-            block_of_row[m] = comm[u];
-        }
-    }
+    std::vector<int32_t> node_at, block_of_row;
+    std::vector<int64_t> bptr;
+    g.nb = regroup_by_labels(n, labels, g.perm, node_at, block_of_row, bptr);
+    const int32_t nb = g.nb;
     g.blk.resize(nb);
     for (int32_t b = 0; b < nb; ++b) {
         g.blk[b] = BlkInfo{};
-        g.blk[b].row0 = (int32_t)cnt[b];
-        g.blk[b].size = (int32_t)(cnt[b + 1] - cnt[b]);
+        g.blk[b].row0 = (int32_t)bptr[b];
+        g.blk[b].size = (int32_t)(bptr[b + 1] - bptr[b]);
     }
     const int32_t *perm = g.perm.data();
     RowSource src;
@@ -534,8 +554,8 @@ std::string build_from_csr(int64_t n, const int64_t *row_ptr, const int32_t *col
             if (pv < b.row0 || pv >= b.row0 + b.size) out.push_back((int32_t)pv);
         }
     };
-    std::string msg = finish(g, block_of_row, src, nullptr, opt);
-    g.symmetric = sym.fwd.load() == sym.bwd.load();
+    msg = finish(g, block_of_row, src, nullptr, opt);
+    g.symmetric = symmetric;
     return msg;
 }
 

@@ -57,6 +57,8 @@ struct kur_ctx {
     BlockGraph host_graph;  // full layout, kept by host-only contexts for introspection
     BlockGraph skel;        // device contexts: blocks, segment and inter offsets (no lists), for re-tiling
     TileParams tiles_installed;  // tile options of the installed layout
+    EnsState *ens = nullptr;     // shared-graph ensembles (ensemble.cpp)
+    double ens_tau = 0.5;        // ensembles: blocks at least this dense use the matrix cores
 
     // device graph
     DevBuf d_blk, d_tiles, d_order, d_seg, d_list, d_iptr, d_icol;
@@ -520,9 +522,12 @@ void kur_destroy(kur_ctx *c)
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
         free_all(c);
+        ens_free(c->ens);
+        c->ens = nullptr;
         for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
     }
+    ens_free(c->ens);
     delete c;
 }
 
@@ -576,6 +581,9 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
     } else if (k == "graph") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "graph must be 0 or 1");
         c->use_graph = (int)v;
+    } else if (k == "ens_tau") {
+        if (v < 0.0 || v > 2.0) return fail(c, KUR_EINVAL, "ens_tau must be in [0, 2] (above 1: no block on the matrix cores)");
+        c->ens_tau = v;
     } else if (k == "graph_steps") {
         if (v != (int64_t)v || v < 1 || v > 4096) return fail(c, KUR_EINVAL, "graph_steps must be an integer in [1, 4096]");
         c->graph_steps = (int64_t)v;
@@ -1548,6 +1556,14 @@ extern "C" kur_status kur_recorded_run(const kur_ctx *c, int64_t *serial, double
 // Hooks of the layout autotuner (kur_tune.hpp).
 
 namespace kur {
+
+EnsState *&ctx_ens_slot(kur_ctx *c) { return c->ens; }
+int ctx_device(const kur_ctx *c) { return c->device; }
+hipStream_t ctx_stream(const kur_ctx *c) { return c->stream; }
+int ctx_timing(const kur_ctx *c) { return c->timing; }
+int ctx_compensate(const kur_ctx *c) { return c->compensate; }
+double ctx_ens_tau(const kur_ctx *c) { return c->ens_tau; }
+void ctx_set_ens_tau(kur_ctx *c, double tau) { c->ens_tau = tau; }
 
 bool ctx_is_device(const kur_ctx *c) { return c && !c->host_only; }
 bool ctx_has_graph(const kur_ctx *c) { return c && c->has_graph; }

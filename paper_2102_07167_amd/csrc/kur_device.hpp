@@ -1,0 +1,98 @@
+// kur_device.hpp -- device helpers shared by the kernel files: (sin, cos), rounding, the two-part
+// split of 2 pi used to wrap phases, the error-free sum, and the per-oscillator bookkeeping of
+// one classical RK4 stage.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kur {
+
+template <typename T> struct V2;
+template <> struct V2<float> { using type = float2; };
+template <> struct V2<double> { using type = double2; };
+
+template <typename T> __device__ __forceinline__ void dev_sincos(T x, T *s, T *c);
+template <> __device__ __forceinline__ void dev_sincos<float>(float x, float *s, float *c) { sincosf(x, s, c); }
+template <> __device__ __forceinline__ void dev_sincos<double>(double x, double *s, double *c) { sincos(x, s, c); }
+
+template <typename T> __device__ __forceinline__ T dev_rint(T x);
+template <> __device__ __forceinline__ float dev_rint<float>(float x) { return rintf(x); }
+template <> __device__ __forceinline__ double dev_rint<double>(double x) { return rint(x); }
+
+template <typename T>
+struct TwoPi;
+template <> struct TwoPi<float> {
+    // 2 pi = P1 + P2 + O(1e-10); P1 has 8 significant bits so q * P1 is exact for |q| < 2^16
+    static constexpr float P1 = 6.28125f;
+    static constexpr float P2 = 1.93530717958647692528676655900576839e-3f;
+    static constexpr float INV = 0.159154943091895335768883763372514362f;
+    static constexpr float PI = 3.14159265358979323846264338327950288f;
+};
+template <> struct TwoPi<double> {
+    // P1 has 26 significant bits so q * P1 is exact for |q| < 2^27
+    static constexpr double P1 = 6.283185362815857;  // 52707179 / 2^23
+    static constexpr double P2 = -5.5636270456668466e-08;
+    static constexpr double INV = 0.159154943091895335768883763372514362;
+    static constexpr double PI = 3.14159265358979323846264338327950288;
+};
+
+// error-free sum a + b = s + e
+template <typename T> __device__ __forceinline__ void two_sum(T a, T b, T &s, T &e)
+{
+    s = a + b;
+    T bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Bookkeeping of one oscillator in classical RK4 (y_{n+1} = y_n + dt/6 (k1 + 2 k2 + 2 k3 + k4))
+// given its stage derivative k. Stages 1-3 accumulate k1 + 2 k2 + 2 k3 in *ksum and return the
+// next stage input (theta + dt/2 k1, theta + dt/2 k2, theta + dt k3). Stage 4 adds
+// dt/6 (ksum + k4) to the phase hi + lo with error-free sums when `compensate`, wraps the result
+// to [-pi, pi) (the whole turns go to *wind), stores it and returns the new phase.
+template <typename T>
+__device__ __forceinline__ T rk4_stage(int stage, T k, T dt, T half_dt, T dt6, int compensate, T *ksum, T *hi_p,
+                                       T *lo_p, int32_t *wind_p)
+{
+    const T th = *hi_p;
+    if (stage == 1) {
+        *ksum = k;
+        return th + half_dt * k;
+    }
+    if (stage == 2) {
+        *ksum += T(2) * k;
+        return th + half_dt * k;
+    }
+    if (stage == 3) {
+        *ksum += T(2) * k;
+        return th + dt * k;
+    }
+    const T delta = dt6 * (*ksum + k);
+    T hi, lo;
+    int wd = *wind_p;
+    if (compensate) {
+        T d1, e1, s, e2;
+        two_sum(delta, *lo_p, d1, e1);
+        two_sum(th, d1, s, e2);
+        hi = s;
+        lo = e1 + e2;
+    } else {
+        hi = th + delta;
+        lo = T(0);
+    }
+    if (!(hi >= -TwoPi<T>::PI && hi < TwoPi<T>::PI)) {
+        const T q = dev_rint<T>(hi * TwoPi<T>::INV);
+        hi = hi - q * TwoPi<T>::P1;  // exact (Sterbenz)
+        lo = lo - q * TwoPi<T>::P2;
+        wd += (int)q;
+    }
+    T s2, e3;
+    two_sum(hi, lo, s2, e3);
+    *hi_p = s2;
+    *lo_p = e3;
+    *wind_p = wd;
+    return s2;
+}
+
+}  // namespace kur

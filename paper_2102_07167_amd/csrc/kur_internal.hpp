@@ -70,6 +70,15 @@ std::string build_from_blocks(int64_t n, int32_t nb, const int64_t *block_ptr, c
                               const int32_t *inter_col, const int32_t *perm, const BuildOptions &opt,
                               BlockGraph &out);
 
+// Pieces of build_from_csr shared with the ensemble builder: argument validation ("" if valid),
+// the symmetry test of the pattern (diagonal ignored), and the regroup of the nodes by label
+// value (stable counting sort; perm: user -> block order, node_at: block order -> user,
+// block_ptr: nb + 1 block boundaries). Returns the number of blocks.
+std::string validate_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *labels);
+bool csr_symmetric(int64_t n, const int64_t *row_ptr, const int32_t *col);
+int32_t regroup_by_labels(int64_t n, const int32_t *labels, std::vector<int32_t> &perm, std::vector<int32_t> &node_at,
+                          std::vector<int32_t> &block_of_row, std::vector<int64_t> &block_ptr);
+
 // The complete graph on n nodes: one dense block whose list of zeros is empty.
 std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &out);
 

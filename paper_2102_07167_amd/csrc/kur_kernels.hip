@@ -20,24 +20,13 @@
 
 #include <cstdint>
 
+#include "kur_device.hpp"
 #include "kur_internal.hpp"
 #include "kur_kernels.hpp"
 
 namespace kur {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct V2;
-template <> struct V2<float> { using type = float2; };
-template <> struct V2<double> { using type = double2; };
-
-template <typename T> __device__ __forceinline__ void dev_sincos(T x, T *s, T *c);
-template <> __device__ __forceinline__ void dev_sincos<float>(float x, float *s, float *c) { sincosf(x, s, c); }
-template <> __device__ __forceinline__ void dev_sincos<double>(double x, double *s, double *c) { sincos(x, s, c); }
-
-template <typename T> __device__ __forceinline__ T dev_rint(T x);
-template <> __device__ __forceinline__ float dev_rint<float>(float x) { return rintf(x); }
-template <> __device__ __forceinline__ double dev_rint<double>(double x) { return rint(x); }
 
 template <typename T> __device__ __forceinline__ T wave_sum(T v)
 {
@@ -153,31 +142,6 @@ __global__ __launch_bounds__(NT) void k_sc_init(const Tile *__restrict__ tiles, 
         acc.y += c;
     }
     block_sum_store<T2, NT>(acc, red, part + t);
-}
-
-template <typename T>
-struct TwoPi;
-template <> struct TwoPi<float> {
-    // 2 pi = P1 + P2 + O(1e-10); P1 has 8 significant bits so q * P1 is exact for |q| < 2^16
-    static constexpr float P1 = 6.28125f;
-    static constexpr float P2 = 1.93530717958647692528676655900576839e-3f;
-    static constexpr float INV = 0.159154943091895335768883763372514362f;
-    static constexpr float PI = 3.14159265358979323846264338327950288f;
-};
-template <> struct TwoPi<double> {
-    // P1 has 26 significant bits so q * P1 is exact for |q| < 2^27
-    static constexpr double P1 = 6.283185362815857;  // 52707179 / 2^23
-    static constexpr double P2 = -5.5636270456668466e-08;
-    static constexpr double INV = 0.159154943091895335768883763372514362;
-    static constexpr double PI = 3.14159265358979323846264338327950288;
-};
-
-// error-free sum a + b = s + e
-template <typename T> __device__ __forceinline__ void two_sum(T a, T b, T &s, T &e)
-{
-    s = a + b;
-    T bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -479,46 +443,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
             a.kout[m] = k;
             continue;
         }
-        const T th = a.hi[m];
-        T y;
-        if (a.stage == 1) {
-            a.ksum[m] = k;
-            y = th + a.half_dt * k;
-        } else if (a.stage == 2) {
-            a.ksum[m] += T(2) * k;
-            y = th + a.half_dt * k;
-        } else if (a.stage == 3) {
-            a.ksum[m] += T(2) * k;
-            y = th + a.dt * k;
-        } else {
-            const T delta = a.dt6 * (a.ksum[m] + k);
-            T hi, lo;
-            int wd = a.wind[m];
-            if (a.compensate) {
-                T d1, e1, s, e2;
-                two_sum(delta, a.lo[m], d1, e1);
-                two_sum(th, d1, s, e2);
-                hi = s;
-                lo = e1 + e2;
-            } else {
-                hi = th + delta;
-                lo = T(0);
-            }
-            if (!(hi >= -TwoPi<T>::PI && hi < TwoPi<T>::PI)) {
-                const T q = dev_rint<T>(hi * TwoPi<T>::INV);
-                hi = hi - q * TwoPi<T>::P1;  // exact (Sterbenz)
-                lo = lo - q * TwoPi<T>::P2;
-                wd += (int)q;
-            }
-            T s2, e3;
-            two_sum(hi, lo, s2, e3);
-            hi = s2;
-            lo = e3;
-            a.hi[m] = hi;
-            a.lo[m] = lo;
-            a.wind[m] = wd;
-            y = hi;
-        }
+        const T y = rk4_stage<T>(a.stage, k, a.dt, a.half_dt, a.dt6, a.compensate, a.ksum + m, a.hi + m, a.lo + m,
+                                 a.wind + m);
         T s, c;
         dev_sincos<T>(y, &s, &c);
         T2 v;

@@ -1,10 +1,13 @@
-// kur_tune.hpp -- the hooks the layout autotuner (autotune.cpp) uses to re-tile an installed
-// graph, time RK4 steps and read the block densities; implemented in kur_api.cpp.
+// kur_tune.hpp -- hooks into the context for the layout autotuner (autotune.cpp) and the
+// shared-graph ensemble path (ensemble.cpp): re-tiling, timing, block densities, the device,
+// stream and options of a context; implemented in kur_api.cpp.
 #pragma once
 
 #include <cstdint>
 #include <string>
 #include <vector>
+
+#include <hip/hip_runtime.h>
 
 #include "../../include/kur.h"
 
@@ -31,6 +34,16 @@ struct LayoutParams {
     bool operator==(const LayoutParams &o) const { return tau == o.tau && chunk == o.chunk; }
     bool operator!=(const LayoutParams &o) const { return !(*this == o); }
 };
+
+struct EnsState;                    // ensemble.cpp
+void ens_free(EnsState *s);         // ensemble.cpp
+EnsState *&ctx_ens_slot(kur_ctx *c);
+int ctx_device(const kur_ctx *c);
+hipStream_t ctx_stream(const kur_ctx *c);
+int ctx_timing(const kur_ctx *c);
+int ctx_compensate(const kur_ctx *c);
+double ctx_ens_tau(const kur_ctx *c);
+void ctx_set_ens_tau(kur_ctx *c, double tau);
 
 bool ctx_is_device(const kur_ctx *c);
 bool ctx_has_graph(const kur_ctx *c);

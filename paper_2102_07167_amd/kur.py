@@ -62,6 +62,18 @@ SIGNATURES = {
     "kur_autotune_csr": (ST, [P, I64, P, P, P, I32, ctypes.c_char_p, P]),
     "kur_tune_tiles": (ST, [P, I32, P]),
     "kur_tune_key": (ST, [P, I64, P, P, ctypes.c_char_p, ctypes.c_size_t]),
+    "kur_ens_set_graph_csr": (ST, [P, I64, P, P, P]),
+    "kur_ens_set_params": (ST, [P, I32, P, P]),
+    "kur_ens_set_phases": (ST, [P, P]),
+    "kur_ens_eval_rhs": (ST, [P, P]),
+    "kur_ens_step": (ST, [P, F64, I64, I64, P, P]),
+    "kur_ens_get_phases": (ST, [P, P, ctypes.c_int]),
+    "kur_ens_info": (ST, [P, P]),
+    "kur_ens_block_modes": (ST, [P, P, P]),
+    "kur_ens_get_perm": (ST, [P, P]),
+    "kur_ens_row_pattern": (ST, [P, I64, P, P, P]),
+    "kur_ens_kernel_time": (ST, [P, P]),
+    "kur_ens_autotune_csr": (ST, [P, I64, P, P, P, I32, I32, P]),
     "kur_eval_rhs_dev": (ST, [P, P, P]),
     "kur_get_phases_dev": (ST, [P, P]),
 }
@@ -340,6 +352,93 @@ class Kuramoto:
         buf = ctypes.create_string_buffer(256)
         self._chk(self._L.kur_tune_key(self._h, int(graph.n), _ptr(rp), _ptr(lb), buf, 256))
         return buf.value.decode()
+
+    # -- shared-graph ensembles (FP32) ------------------------------------------------------
+    _ENS_INFO = ("n", "blocks", "gemm_blocks", "gemm_rows", "gemm_pairs", "csr_entries", "B", "Bp", "gemm_items",
+                 "symmetric")
+
+    def ens_set_graph(self, graph):
+        """Install `graph` (CSR with planted labels) for replicas; see kur_ens_set_graph_csr."""
+        rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(graph.col, dtype=np.int32)
+        lb = np.ascontiguousarray(graph.labels, dtype=np.int32)
+        self._chk(self._L.kur_ens_set_graph_csr(self._h, int(graph.n), _ptr(rp), _ptr(cl), _ptr(lb)))
+        self.ens_n = int(graph.n)
+
+    def ens_set_params(self, K, omega):
+        """K: (B,), omega: (B, n) per replica (user order)."""
+        K = np.ascontiguousarray(np.atleast_1d(K), dtype=np.float64)
+        om = np.ascontiguousarray(omega, dtype=np.float64).reshape(len(K), self.ens_n)
+        self._chk(self._L.kur_ens_set_params(self._h, len(K), _ptr(K), _ptr(om)))
+        self.ens_B = len(K)
+
+    def ens_set_phases(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(self.ens_B, self.ens_n)
+        self._chk(self._L.kur_ens_set_phases(self._h, _ptr(th)))
+
+    def ens_eval_rhs(self):
+        out = np.empty((self.ens_B, self.ens_n))
+        self._chk(self._L.kur_ens_eval_rhs(self._h, _ptr(out)))
+        return out
+
+    def ens_step(self, dt: float, nsteps: int, r_every: int = 0):
+        """Advance every replica; returns r and psi as (samples, B) arrays (or None)."""
+        if r_every > 0:
+            ns = nsteps // r_every + 1
+            r = np.empty((ns, self.ens_B))
+            psi = np.empty((ns, self.ens_B))
+            self._chk(self._L.kur_ens_step(self._h, float(dt), int(nsteps), int(r_every), _ptr(r), _ptr(psi)))
+            return r, psi
+        self._chk(self._L.kur_ens_step(self._h, float(dt), int(nsteps), 0, None, None))
+        return None, None
+
+    def ens_get_phases(self, wrapped: bool = True):
+        out = np.empty((self.ens_B, self.ens_n))
+        self._chk(self._L.kur_ens_get_phases(self._h, _ptr(out), 1 if wrapped else 0))
+        return out
+
+    def ens_info(self) -> dict:
+        out = np.zeros(10, dtype=np.int64)
+        self._chk(self._L.kur_ens_info(self._h, _ptr(out)))
+        return dict(zip(self._ENS_INFO, (int(x) for x in out)))
+
+    def ens_block_modes(self):
+        nb = self.ens_info()["blocks"]
+        g = np.zeros(nb, dtype=np.uint8)
+        d = np.zeros(nb)
+        self._chk(self._L.kur_ens_block_modes(self._h, _ptr(g), _ptr(d)))
+        return g, d
+
+    def ens_perm(self):
+        p = np.empty(self.ens_n, dtype=np.int32)
+        self._chk(self._L.kur_ens_get_perm(self._h, _ptr(p)))
+        return p
+
+    def ens_row_pattern(self, m: int):
+        """(CSR columns, dense 0/1 row or None) of block-order row m (host-only contexts)."""
+        cnt = I64(0)
+        self._chk(self._L.kur_ens_row_pattern(self._h, int(m), None, ctypes.byref(cnt), None))
+        cols = np.empty(cnt.value, dtype=np.int32)
+        cap = I64(cnt.value)
+        dense = np.full(self.ens_n, 255, dtype=np.uint8)
+        self._chk(self._L.kur_ens_row_pattern(self._h, int(m), _ptr(cols), ctypes.byref(cap), _ptr(dense)))
+        return cols, dense
+
+    def ens_kernel_time(self) -> dict:
+        out = np.zeros(4)
+        self._chk(self._L.kur_ens_kernel_time(self._h, _ptr(out)))
+        return {"gemm_launches": int(out[0]), "gemm_ms": out[1], "rows_launches": int(out[2]), "rows_ms": out[3]}
+
+    def ens_autotune(self, graph, B: int, effort: int = 1) -> dict:
+        rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(graph.col, dtype=np.int32)
+        lb = np.ascontiguousarray(graph.labels, dtype=np.int32)
+        rep = np.zeros(6)
+        self._chk(self._L.kur_ens_autotune_csr(self._h, int(graph.n), _ptr(rp), _ptr(cl), _ptr(lb), int(B), int(effort),
+                                               _ptr(rep)))
+        self.ens_n = int(graph.n)
+        return dict(zip(("ens_tau", "ms_per_step", "ms_all_gemm", "ms_no_gemm", "timed", "seconds"),
+                        (float(x) for x in rep)))
 
     def read_bandwidth(self, nbytes: int = 4 << 30, repeats: int = 5) -> float:
         """GB/s of a plain streaming read on this context's device (roofline reference)."""
