@@ -212,12 +212,12 @@ def bench_ensemble(args):
                                   "K=linspace(0,6,%d), omega~N(0,1), theta0~U[0,2pi) per replica, dt=0.01, r every 10 "
                                   "steps, seed 1006" % (B, B), "layout": info, "tuning": tuning}}
     if kt["gemm_launches"] > 0:
-        # issued matrix-core work per launch: every 128 x 128 output tile of a block runs over
+        # issued matrix-core work per launch: every 256 x 128 output tile of a block runs over
         # the block's width padded to 32, with three bf16 terms and 2 flops per multiply-add
         modes, _ = k.ens_block_modes()
         sizes = np.bincount(np.unique(g.labels, return_inverse=True)[1])
         J = 2 * info["Bp"]
-        issued = sum(2.0 * 3 * 128 * 128 * (-(-s // 32) * 32) * (-(-s // 128)) * (J // 128)
+        issued = sum(2.0 * 3 * 256 * 128 * (-(-s // 32) * 32) * (-(-s // 256)) * (J // 128)
                      for s, m in zip(sizes, modes) if m)
         useful = 2.0 * info["gemm_pairs"] * 2 * B
         gms = kt["gemm_ms"] / kt["gemm_launches"]

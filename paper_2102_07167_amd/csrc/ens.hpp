@@ -18,13 +18,13 @@ struct EnsBlk {
     int32_t pad;
 };
 
-// One workgroup of the dense product: rows [r0, r0 + 128) of block `blk` (block-local) and
+// One workgroup of the dense product: rows [r0, r0 + 256) of block `blk` (block-local) and
 // columns [c0, c0 + 128) of X.
 struct EnsItem {
     int32_t blk, r0, c0, pad;
 };
 
-constexpr int kEnsTileRows = 128;
+constexpr int kEnsTileRows = 256;
 constexpr int kEnsTileCols = 128;
 
 struct EnsGemmArgs {

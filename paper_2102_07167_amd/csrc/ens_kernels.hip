@@ -9,8 +9,9 @@
 //   * X is split exactly into three bf16 terms x = t0 + t1 + t2 (each the truncated upper half
 //     of the remainder: 8 + 8 + 8 significant bits cover the 24 of FP32), so every product is
 //     exact and only the FP32 accumulation of the matrix core rounds;
-//   * v_mfma_f32_32x32x16_bf16, a 128 x 128 output tile per workgroup (four waves of 32 rows,
-//     four 32-column tiles each), X staged in LDS per 32 columns of A.
+//   * v_mfma_f32_32x32x16_bf16, a 256 x 128 output tile per workgroup (four waves of 64 rows,
+//     two 32-row by four 32-column tiles each, so every LDS read of X feeds two products); X is staged in LDS per 32 columns of A, double-buffered, with
+//     the next step's X and pattern words loaded into registers while the matrix cores run.
 // k_ens_rows then adds the CSR edges (sparse blocks and inter-block edges) by gathering whole
 // X rows (all replicas contiguous), and runs the stage epilogue of every replica:
 // F = omega + K_e / N ((sum A sin) cos y - (sum A cos) sin y), the RK4 bookkeeping and the next
@@ -55,103 +56,159 @@ __device__ __forceinline__ void split3(float x, uint32_t &t0, uint32_t &t1, uint
 
 __global__ __launch_bounds__(256) void k_ens_gemm(EnsGemmArgs a)
 {
-    // [term][group of 8 k][column]: 8 bf16 of one column, the layout of the B operand
-    __shared__ u32x4_e xs[3][4][kEnsTileCols];
+    // double buffer of [term][group of 8 k][column]: 8 bf16 of one column, the layout of the B
+    // operand; step i is staged into buffer i & 1 while the matrix cores work on the other
+    __shared__ u32x4_e xs[2][3][4][kEnsTileCols];
     const EnsItem it = a.items[blockIdx.x];
     const EnsBlk b = a.blk[it.blk];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, half = lane >> 5, l32 = lane & 31;
-    // A operand: lane holds row (l32) and k = 8 half + v of each 16-wide k step
-    const int arow = it.r0 + wave * 32 + l32;
-    const bool arow_ok = arow < b.size;
-    const uint32_t *abits = a.bits + b.bits_off + (int64_t)(arow_ok ? arow : 0) * b.words;
+    // A operand: each wave owns 64 rows as two 32-row tiles; lane holds row l32 of each tile and
+    // k = 8 half + v of each 16-wide k step
+    const int arow0 = it.r0 + wave * 64 + l32, arow1 = arow0 + 32;
+    const bool ok0 = arow0 < b.size, ok1 = arow1 < b.size;
+    const uint32_t *ab0 = a.bits + b.bits_off + (int64_t)(ok0 ? arow0 : 0) * b.words;
+    const uint32_t *ab1 = a.bits + b.bits_off + (int64_t)(ok1 ? arow1 : 0) * b.words;
     // staging: thread -> one column, k groups sg and sg + 2 of each 32-wide step
     const int sc = tid & (kEnsTileCols - 1), sg = tid >> 7;
     const float *xcol = a.x + (int64_t)b.row0 * a.J + it.c0 + sc;
-    f32x16 acc[4];
+    f32x16 acc[2][4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[c][r] = 0.f;
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[rt][c][r] = 0.f;
 
     const int kend = b.words * 32;
+    float v[2][8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                // unconditional load of a clamped row (no branch per load), then the mask
+                const int k = k0 + 8 * (sg + 2 * gi) + i;
+                const float t = xcol[(int64_t)(k < b.size ? k : b.size - 1) * a.J];
+                v[gi][i] = k < b.size ? t : 0.f;
+            }
+    };
+    load(0);
+    uint32_t w0 = ab0[0], w1 = ab1[0];
+    w0 = ok0 ? w0 : 0u;
+    w1 = ok1 ? w1 : 0u;
+    int buf = 0;
     for (int k0 = 0; k0 < kend; k0 += 32) {
 #pragma unroll
         for (int gi = 0; gi < 2; ++gi) {
-            const int g = sg + 2 * gi;
             uint32_t t0[8], t1[8], t2[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int k = k0 + 8 * g + i;
-                const float v = k < b.size ? xcol[(int64_t)k * a.J] : 0.f;
-                split3(v, t0[i], t1[i], t2[i]);
-            }
+            for (int i = 0; i < 8; ++i) split3(v[gi][i], t0[i], t1[i], t2[i]);
             u32x4_e p0, p1, p2;
             p0.x = t0[0] | (t0[1] << 16); p0.y = t0[2] | (t0[3] << 16); p0.z = t0[4] | (t0[5] << 16); p0.w = t0[6] | (t0[7] << 16);
             p1.x = t1[0] | (t1[1] << 16); p1.y = t1[2] | (t1[3] << 16); p1.z = t1[4] | (t1[5] << 16); p1.w = t1[6] | (t1[7] << 16);
             p2.x = t2[0] | (t2[1] << 16); p2.y = t2[2] | (t2[3] << 16); p2.z = t2[4] | (t2[5] << 16); p2.w = t2[6] | (t2[7] << 16);
-            xs[0][g][sc] = p0;
-            xs[1][g][sc] = p1;
-            xs[2][g][sc] = p2;
+            const int g = sg + 2 * gi;
+            xs[buf][0][g][sc] = p0;
+            xs[buf][1][g][sc] = p1;
+            xs[buf][2][g][sc] = p2;
         }
-        const uint32_t word = arow_ok ? abits[k0 >> 5] : 0u;
+        // one barrier per step: a wave past it has finished its reads of the other buffer
+        // (step - 1), which the next step overwrites
         __syncthreads();
+        const uint32_t c0 = w0, c1 = w1;
+        if (k0 + 32 < kend) {
+            load(k0 + 32);
+            const uint32_t n0 = ab0[(k0 >> 5) + 1], n1 = ab1[(k0 >> 5) + 1];
+            w0 = ok0 ? n0 : 0u;
+            w1 = ok1 ? n1 : 0u;
+        }
 #pragma unroll
         for (int sub = 0; sub < 2; ++sub) {
             const int g = 2 * sub + half;
-            const bf16x8 av = expand_bits(word >> (8 * g));
+            const bf16x8 av0 = expand_bits(c0 >> (8 * g));
+            const bf16x8 av1 = expand_bits(c1 >> (8 * g));
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
                 for (int t = 0; t < 3; ++t) {
-                    const bf16x8 bv = __builtin_bit_cast(bf16x8, xs[t][g][ct * 32 + l32]);
-                    acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[ct], 0, 0, 0);
+                    // one LDS read feeds both row tiles
+                    const bf16x8 bv = __builtin_bit_cast(bf16x8, xs[buf][t][g][ct * 32 + l32]);
+                    acc[0][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av0, bv, acc[0][ct], 0, 0, 0);
+                    acc[1][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av1, bv, acc[1][ct], 0, 0, 0);
                 }
         }
-        __syncthreads();
+        buf ^= 1;
     }
-    // result: lane column l32, register r -> row 8 (r / 4) + 4 half + (r % 4) of the wave's 32
+    // result: lane column l32, register r -> row 8 (r / 4) + 4 half + (r % 4) of the 32-row tile
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = it.r0 + wave * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-            if (row < b.size) a.y[(int64_t)(b.row0 + row) * a.J + it.c0 + ct * 32 + l32] = acc[ct][r];
-        }
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = it.r0 + wave * 64 + rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (row < b.size) a.y[(int64_t)(b.row0 + row) * a.J + it.c0 + ct * 32 + l32] = acc[rt][ct][r];
+            }
 }
 
-// One wave per row; lane l handles replicas l + 64 q, q < NE.
+// One wave per row; lane l handles replicas l + 64 q, q < NE. Every load of the row's own data
+// (dense-block sums, stage input, omega and the RK4 state) is issued before the CSR gathers, so
+// a wave waits on memory about as often as it has groups of CSR entries.
 template <int NE>
 __global__ __launch_bounds__(256) void k_ens_rows(EnsRowArgs a)
 {
+    constexpr int GRP = NE <= 2 ? 8 : 4;  // CSR entries gathered per round
     const int lane = threadIdx.x & 63;
     const int64_t m = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (m >= a.n) return;
     const int64_t Bp = a.Bp;
     const int64_t J = 2 * Bp;
-    float as[NE], ac[NE];
-    const bool dense = a.row_gemm[m] != 0;
+    const int stage = a.stage;
+    // y holds rows of matrix-core blocks only: the branch is uniform over the wave
+    const bool dense = __builtin_amdgcn_readfirstlane((int)a.row_gemm[m]) != 0;
+    float as[NE], ac[NE], sm[NE], cm[NE], om[NE], th[NE], ks[NE], lo[NE];
+    int32_t wd[NE];
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
-        as[q] = dense ? a.y[m * J + lane + 64 * q] : 0.f;
-        ac[q] = dense ? a.y[m * J + Bp + lane + 64 * q] : 0.f;
+        as[q] = 0.f;
+        ac[q] = 0.f;
+    }
+    if (dense) {
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            as[q] = a.y[m * J + lane + 64 * q];
+            ac[q] = a.y[m * J + Bp + lane + 64 * q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int64_t e = lane + 64 * q;
+        const int64_t ix = m * Bp + e;
+        sm[q] = a.x[m * J + e];
+        cm[q] = a.x[m * J + Bp + e];
+        om[q] = a.omega[ix];
+        th[q] = a.hi[ix];
+        ks[q] = stage >= 2 ? a.ksum[ix] : 0.f;
+        lo[q] = stage == 4 ? a.lo[ix] : 0.f;
+        wd[q] = stage == 4 ? a.wind[ix] : 0;
     }
     const int64_t p0 = a.csr_ptr[m], p1 = a.csr_ptr[m + 1];
     int64_t p = p0;
-    for (; p + 4 <= p1; p += 4) {
-        int64_t col[4];
+    for (; p + GRP <= p1; p += GRP) {
+        int64_t col[GRP];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) col[i] = a.csr_col[p + i];
-        float vs[4][NE], vc[4][NE];
+        for (int i = 0; i < GRP; ++i) col[i] = a.csr_col[p + i];
+        float vs[GRP][NE], vc[GRP][NE];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < GRP; ++i)
 #pragma unroll
             for (int q = 0; q < NE; ++q) {
                 vs[i][q] = a.x[col[i] * J + lane + 64 * q];
                 vc[i][q] = a.x[col[i] * J + Bp + lane + 64 * q];
             }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < GRP; ++i)
 #pragma unroll
             for (int q = 0; q < NE; ++q) {
                 as[q] += vs[i][q];
@@ -170,14 +227,18 @@ __global__ __launch_bounds__(256) void k_ens_rows(EnsRowArgs a)
     for (int q = 0; q < NE; ++q) {
         const int64_t e = lane + 64 * q;
         const int64_t ix = m * Bp + e;
-        const float s = a.x[m * J + e], c = a.x[m * J + Bp + e];
-        const float k = a.omega[ix] + a.unit[e] * (as[q] * c - ac[q] * s);
-        if (a.stage == 0) {
+        const float k = om[q] + a.unit[e] * (as[q] * cm[q] - ac[q] * sm[q]);
+        if (stage == 0) {
             a.kout[ix] = k;
             continue;
         }
-        const float y = rk4_stage<float>(a.stage, k, a.dt, a.half_dt, a.dt6, a.compensate, a.ksum + ix, a.hi + ix,
-                                         a.lo + ix, a.wind + ix);
+        const float y = rk4_stage<float>(stage, k, a.dt, a.half_dt, a.dt6, a.compensate, &ks[q], &th[q], &lo[q], &wd[q]);
+        a.ksum[ix] = ks[q];
+        if (stage == 4) {
+            a.hi[ix] = th[q];
+            a.lo[ix] = lo[q];
+            a.wind[ix] = wd[q];
+        }
         float sy, cy;
         dev_sincos<float>(y, &sy, &cy);
         a.x_out[m * J + e] = sy;

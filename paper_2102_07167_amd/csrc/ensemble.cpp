@@ -447,7 +447,7 @@ kur_status set_params_impl(kur_ctx *c, EnsState &S, int32_t B, const double *K, 
         (err = S.d_hi.ensure(4 * NB)) != hipSuccess || (err = S.d_lo.ensure(4 * NB)) != hipSuccess ||
         (err = S.d_wind.ensure(4 * NB)) != hipSuccess || (err = S.d_ksum.ensure(4 * NB)) != hipSuccess ||
         (err = S.d_x[0].ensure(8 * NB)) != hipSuccess || (err = S.d_x[1].ensure(8 * NB)) != hipSuccess ||
-        (err = S.d_y.ensure(S.L.gemm_rows > 0 ? 8 * NB : 256)) != hipSuccess || (err = S.d_kout.ensure(4 * NB)) != hipSuccess ||
+        (err = S.d_y.ensure(8 * NB)) != hipSuccess || (err = S.d_kout.ensure(4 * NB)) != hipSuccess ||
         (err = S.d_part.ensure(8 * (size_t)nchunk * Bp)) != hipSuccess)
         return hipfail(c, err, "ensemble buffers");
     if (Bp != S.Bp) S.has_phases = false;
