@@ -83,6 +83,10 @@ const char *kur_last_error(const kur_ctx *ctx);
  *   "tiles"       target number of work tiles (>= 1). Default 4096.
  *   "tile_min_cost" least work per tile in list-entry equivalents (a row costs its stored list
  *                 entries + 4 per inter-block entry + 32). Default 16384.
+ *   "xcds"        launch order of the tiles for this many XCDs dispatched round-robin: the tiles
+ *                 of a block all run on one XCD, whose L2 then serves the block's re-staged
+ *                 (sin, cos) chunks; 1: plain largest-first order (default; the tuner tries
+ *                 8, the XCD count of MI355X).
  *   "flat_min_vec" rows of a tile averaging at least this many 8-entry list vectors per chunk
  *                 are streamed one contiguous run per wavefront; shorter rows get a group of
  *                 lanes each. 0 disables streaming. Default 8.
@@ -273,15 +277,15 @@ kur_status kur_read_bandwidth(kur_ctx *ctx, int64_t bytes, int32_t repeats, doub
  * Introduction and Sec. 3: precomputed sums pay off once ones outnumber zeros, so tau = 1/2
  * minimises the stored bytes. The tuner times whole RK4 steps of the row kernel with HIP events
  * for candidate values of tau, the chunk width ("chunk") and the tile options ("tile_rows",
- * "tile_min_cost", "flat_min_vec", "threads"), by coordinate descent from the options in
+ * "tile_min_cost", "flat_min_vec", "threads", "xcds"), by coordinate descent from the options in
  * force; a candidate wins only when it is at least 1 % faster. Results do not change with the
  * layout beyond rounding order.
  *
- * report (may be NULL) receives 12 doubles: tau, chunk, threads, tile_rows, tile_min_cost,
+ * report (may be NULL) receives 13 doubles: tau, chunk, threads, tile_rows, tile_min_cost,
  * flat_min_vec, ms per RK4 step of the chosen layout, ms per step of the starting layout (NaN
  * when taken from the cache), candidates timed, cache status (1: loaded from the cache, 0:
  * tuned and stored or no cache given, -1: tuned but the cache file could not be written), list
- * builds, seconds spent. Synchronous; effort 0, 1 or 2 widens the candidate sets.
+ * builds, seconds spent, xcds. Synchronous; effort 0, 1 or 2 widens the candidate sets.
  *
  * kur_autotune_csr: takes the arguments of kur_set_graph_csr and ends with that graph installed
  * in the chosen layout, as kur_set_graph_csr would (omega, K and phases unset); the options

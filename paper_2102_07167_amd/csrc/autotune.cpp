@@ -49,7 +49,7 @@ std::string graph_key(const kur_ctx *c, int64_t n, const int64_t *row_ptr, const
         h = mix(h ^ (uint64_t)(uint32_t)labels[i]);
     }
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "kur1 %s %s n=%lld nnz=%lld h=%016llx", ctx_esz(c) == 4 ? "f32" : "f64",
+    std::snprintf(buf, sizeof(buf), "kur2 %s %s n=%lld nnz=%lld h=%016llx", ctx_esz(c) == 4 ? "f32" : "f64",
                   ctx_arch(c).c_str(), (long long)n, (long long)row_ptr[n], (unsigned long long)h);
     return buf;
 }
@@ -60,7 +60,7 @@ struct Choice {
     double ms = 1e300;
 };
 
-// Cache lines: "<key>\t<tau> <chunk> <threads> <tile_rows> <tile_min_cost> <flat_min_vec> <ms>".
+// Cache lines: "<key>\t<tau> <chunk> <threads> <tile_rows> <tile_min_cost> <flat_min_vec> <xcds> <ms>".
 // The last line with a matching key wins; malformed lines are skipped.
 bool cache_lookup(const char *path, const std::string &key, Choice &out)
 {
@@ -73,11 +73,12 @@ bool cache_lookup(const char *path, const std::string &key, Choice &out)
         char *tab = std::strchr(line, '\t');
         if (!tab || (size_t)(tab - line) != key.size() || std::strncmp(line, key.c_str(), key.size()) != 0) continue;
         Choice ch;
-        int chunk = 0, threads = 0, rows = 0;
+        int chunk = 0, threads = 0, rows = 0, xcds = 0;
         long long cost = 0;
-        if (std::sscanf(tab + 1, "%lf %d %d %d %lld %lf %lf", &ch.l.tau, &chunk, &threads, &rows, &cost,
-                        &ch.t.flat_min_vec, &ch.ms) != 7)
+        if (std::sscanf(tab + 1, "%lf %d %d %d %lld %lf %d %lf", &ch.l.tau, &chunk, &threads, &rows, &cost,
+                        &ch.t.flat_min_vec, &xcds, &ch.ms) != 8)
             continue;
+        ch.t.xcds = xcds;
         ch.l.chunk = chunk;
         ch.t.threads = threads;
         ch.t.tile_rows = rows;
@@ -94,8 +95,9 @@ bool cache_store(const char *path, const std::string &key, const Choice &ch)
     if (!path) return true;
     FILE *f = std::fopen(path, "a");
     if (!f) return false;
-    const int r = std::fprintf(f, "%s\t%.17g %d %d %d %lld %.17g %.6g\n", key.c_str(), ch.l.tau, ch.l.chunk,
-                               ch.t.threads, ch.t.tile_rows, (long long)ch.t.tile_min_cost, ch.t.flat_min_vec, ch.ms);
+    const int r = std::fprintf(f, "%s\t%.17g %d %d %d %lld %.17g %d %.6g\n", key.c_str(), ch.l.tau, ch.l.chunk,
+                               ch.t.threads, ch.t.tile_rows, (long long)ch.t.tile_min_cost, ch.t.flat_min_vec,
+                               ch.t.xcds, ch.ms);
     return std::fclose(f) == 0 && r > 0;
 }
 
@@ -134,7 +136,7 @@ kur_status search_tiles(Search &S, Choice &best)
 {
     const int sweeps = S.effort >= 2 ? 2 : 1;
     for (int sweep = 0; sweep < sweeps; ++sweep) {
-        for (int dim = 0; dim < 4; ++dim) {
+        for (int dim = 0; dim < 5; ++dim) {
             std::vector<TileParams> cands;
             if (dim == 0)
                 for (int64_t v : cost_values(S.effort)) { TileParams t = best.t; t.tile_min_cost = v; cands.push_back(t); }
@@ -144,6 +146,8 @@ kur_status search_tiles(Search &S, Choice &best)
                 for (int32_t v : row_values(S.effort)) { TileParams t = best.t; t.tile_rows = v; cands.push_back(t); }
             if (dim == 3)
                 for (double v : flat_values(S.effort)) { TileParams t = best.t; t.flat_min_vec = v; cands.push_back(t); }
+            if (dim == 4)  // XCD-aware launch order on or off
+                for (int32_t v : {1, 8}) { TileParams t = best.t; t.xcds = v; cands.push_back(t); }
             const TileParams incumbent = best.t;
             for (const TileParams &t : cands) {
                 if (t == incumbent || t == best.t || !ctx_layout_fits(S.c, 0, t)) continue;
@@ -187,6 +191,7 @@ void fill_report(double *report, const Choice &best, double ms_default, const Se
     report[9] = from_cache;
     report[10] = S.builds;
     report[11] = seconds;
+    report[12] = best.t.xcds;
 }
 
 }  // namespace

@@ -249,6 +249,7 @@ void make_tiles(BlockGraph &g, const BuildOptions &opt)
 {
     const int64_t n = g.n;
     g.tile_rows = opt.tile_rows;
+    g.xcds = opt.xcds;
     // work tiles: consecutive rows of one block with similar cost
     std::vector<int64_t> rowcost(n);
     int64_t total = 0;
@@ -301,8 +302,9 @@ void make_tiles(BlockGraph &g, const BuildOptions &opt)
 
 void order_tiles(BlockGraph &g)
 {
-    std::vector<int64_t> cost(g.tiles.size());
-    for (size_t t = 0; t < g.tiles.size(); ++t) {
+    const size_t nt = g.tiles.size();
+    std::vector<int64_t> cost(nt);
+    for (size_t t = 0; t < nt; ++t) {
         const Tile &tl = g.tiles[t];
         const BlkInfo &b = g.blk[tl.block];
         int64_t c = 32 * (int64_t)(tl.r1 - tl.r0);
@@ -316,9 +318,51 @@ void order_tiles(BlockGraph &g)
         c += 4 * (g.inter_ptr[b.row0 + tl.r1] - g.inter_ptr[b.row0 + tl.r0]);
         cost[t] = c + (int64_t)b.size * nonempty / 4;
     }
-    g.order.resize(g.tiles.size());
-    std::iota(g.order.begin(), g.order.end(), 0);
-    std::stable_sort(g.order.begin(), g.order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    const int X = std::max(1, g.xcds);
+    // units of placement: a block, or for a block costing more than total / (2 X) runs of its
+    // consecutive tiles of about that cost each, so that few or uneven blocks still spread over
+    // every XCD
+    int64_t total = 0;
+    for (int64_t c : cost) total += c;
+    const int64_t cap = std::max<int64_t>(1, total / (2 * X));
+    struct Unit {
+        int32_t t0, t1;
+        int64_t cost;
+    };
+    std::vector<Unit> units;
+    for (int32_t b = 0; b < g.nb; ++b) {
+        const BlkInfo &bi = g.blk[b];
+        int32_t t = bi.tile0;
+        const int32_t tend = bi.tile0 + bi.ntiles;
+        while (t < tend) {
+            Unit u{t, t, 0};
+            while (u.t1 < tend && (u.t1 == u.t0 || u.cost + cost[u.t1] <= cap)) u.cost += cost[u.t1++];
+            units.push_back(u);
+            t = u.t1;
+        }
+    }
+    // units to XCDs: largest first, each to the least loaded XCD
+    std::stable_sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) { return a.cost > b.cost; });
+    std::vector<int64_t> load(X, 0);
+    std::vector<int32_t> xcd_of_tile(nt, 0);
+    for (const Unit &u : units) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        for (int32_t t = u.t0; t < u.t1; ++t) xcd_of_tile[t] = x;
+        load[x] += u.cost;
+    }
+    // per XCD, its tiles largest first; then interleave
+    std::vector<std::vector<int32_t>> lists(X);
+    for (size_t t = 0; t < nt; ++t) lists[xcd_of_tile[t]].push_back((int32_t)t);
+    size_t longest = 0;
+    for (auto &l : lists) {
+        std::stable_sort(l.begin(), l.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+        longest = std::max(longest, l.size());
+    }
+    g.order.assign(longest * X, -1);
+    for (int x = 0; x < X; ++x)
+        for (size_t j = 0; j < lists[x].size(); ++j) g.order[j * X + x] = lists[x][j];
+    // drop empty slots after the last tile
+    while (!g.order.empty() && g.order.back() < 0) g.order.pop_back();
 }
 
 std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &g)
@@ -350,6 +394,7 @@ std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &g)
     for (int64_t r = 0; r < n; r += opt.tile_rows)
         g.tiles.push_back(Tile{0, (int32_t)r, (int32_t)std::min<int64_t>(n, r + opt.tile_rows), -1});
     g.blk[0].ntiles = (int32_t)g.tiles.size();
+    g.xcds = opt.xcds;
     order_tiles(g);
     return "";
 }
@@ -362,6 +407,7 @@ std::string merge_graphs(std::vector<BlockGraph> &parts, BlockGraph &g, std::vec
     g.W = parts[0].W;
     g.tile_rows = parts[0].tile_rows;
     g.esz2 = parts[0].esz2;
+    g.xcds = parts[0].xcds;
     g.symmetric = true;
     int64_t n = 0, nb = 0, segs = 0, entries = 0, inter = 0, tiles = 0;
     for (const BlockGraph &p : parts) {

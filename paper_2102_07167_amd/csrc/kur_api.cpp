@@ -49,6 +49,7 @@ struct kur_ctx {
     int64_t n = 0;
     int32_t nb = 0;
     int32_t ntiles = 0;
+    int32_t nlaunch = 0;  // workgroups of a tile launch (tiles plus empty slots of the launch order)
     int32_t W = 0, tile_rows = 0;
     std::vector<int32_t> perm;
     std::vector<int32_t> deg;
@@ -200,6 +201,7 @@ DevGraph devgraph(const kur_ctx *c)
     g.inter_col = (const int32_t *)c->d_icol.p;
     g.W = c->W;
     g.tile_rows = c->tile_rows;
+    g.nlaunch = c->nlaunch;
     return g;
 }
 
@@ -413,6 +415,7 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
     c->n = g.n;
     c->nb = g.nb;
     c->ntiles = (int32_t)g.tiles.size();
+    c->nlaunch = (int32_t)g.order.size();
     c->W = g.W;
     c->tile_rows = g.tile_rows;
     c->perm.swap(g.perm);
@@ -434,6 +437,7 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
     c->tiles_installed.tile_rows = g.tile_rows;
     c->tiles_installed.tile_min_cost = c->bopt.tile_min_cost;
     c->tiles_installed.flat_min_vec = c->bopt.flat_min_vec;
+    c->tiles_installed.xcds = c->bopt.xcds;
     if (c->host_only) {
         c->host_graph = std::move(g);
     } else {
@@ -561,6 +565,9 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
     } else if (k == "flat_min_vec") {
         if (v < 0.0 || v > 1e6) return fail(c, KUR_EINVAL, "flat_min_vec must be in [0, 1e6]");
         c->bopt.flat_min_vec = v;
+    } else if (k == "xcds") {
+        if (v != (int64_t)v || v < 1 || v > 64) return fail(c, KUR_EINVAL, "xcds must be an integer in [1, 64]");
+        c->bopt.xcds = (int32_t)v;
     } else if (k == "threads") {
         if (v != 256 && v != 512 && v != 1024) return fail(c, KUR_EINVAL, "threads must be 256, 512 or 1024");
         if (c->has_graph && rows_lds_bytes(c->esz, c->W, c->tile_rows, (int)v, 1) > 156 * 1024)
@@ -1603,13 +1610,14 @@ kur_status ctx_set_build_options(kur_ctx *c, const LayoutParams &l, const TilePa
 {
     if (!(l.tau >= 0.0 && l.tau <= 1.0) || l.chunk < 64 || l.chunk % 64 || l.chunk > ctx_max_chunk(c) ||
         t.tile_rows < 64 || t.tile_rows > 4096 || t.tile_min_cost < 1 || !(t.flat_min_vec >= 0.0) ||
-        (t.threads != 256 && t.threads != 512 && t.threads != 1024))
+        (t.threads != 256 && t.threads != 512 && t.threads != 1024) || t.xcds < 1 || t.xcds > 64)
         return fail(c, KUR_EINVAL, "layout options out of range");
     c->bopt.tau = l.tau;
     c->bopt.W = l.chunk;
     c->bopt.tile_rows = t.tile_rows;
     c->bopt.tile_min_cost = t.tile_min_cost;
     c->bopt.flat_min_vec = t.flat_min_vec;
+    c->bopt.xcds = t.xcds;
     c->threads = t.threads;
     c->gen++;
     return KUR_OK;
@@ -1619,7 +1627,7 @@ kur_status ctx_retile(kur_ctx *c, const TileParams &t)
 {
     if (!c->has_graph) return fail(c, KUR_ESTATE, "no graph set");
     if (t.tile_rows < 64 || t.tile_rows > 4096 || t.tile_min_cost < 1 || !(t.flat_min_vec >= 0.0) ||
-        (t.threads != 256 && t.threads != 512 && t.threads != 1024))
+        (t.threads != 256 && t.threads != 512 && t.threads != 1024) || t.xcds < 1 || t.xcds > 64)
         return fail(c, KUR_EINVAL, "tile options out of range");
     if (!ctx_layout_fits(c, c->W, t)) return fail(c, KUR_EINVAL, "chunk/tile_rows/threads exceed the LDS of a workgroup");
     BlockGraph &L = c->host_only ? c->host_graph : c->skel;
@@ -1627,19 +1635,22 @@ kur_status ctx_retile(kur_ctx *c, const TileParams &t)
     o.tile_rows = t.tile_rows;
     o.tile_min_cost = t.tile_min_cost;
     o.flat_min_vec = t.flat_min_vec;
+    o.xcds = t.xcds;
     try {
         make_tiles(L, o);
     } catch (const std::bad_alloc &) {
         return fail(c, KUR_ENOMEM, "host allocation failed while re-tiling");
     }
-    if (L.tiles.size() > (size_t)INT32_MAX) return fail(c, KUR_EINVAL, "too many tiles");
+    if (L.order.size() > (size_t)INT32_MAX) return fail(c, KUR_EINVAL, "too many tiles");
     c->ntiles = (int32_t)L.tiles.size();
+    c->nlaunch = (int32_t)L.order.size();
     c->tile_rows = t.tile_rows;
     c->threads = t.threads;
     c->info[6] = c->ntiles;
     c->bopt.tile_rows = t.tile_rows;
     c->bopt.tile_min_cost = t.tile_min_cost;
     c->bopt.flat_min_vec = t.flat_min_vec;
+    c->bopt.xcds = t.xcds;
     c->tiles_installed = t;
     // tiles never span blocks and an instance is a run of whole blocks: its first tile is the
     // first tile of the first block at or after its first row

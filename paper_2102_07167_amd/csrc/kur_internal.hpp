@@ -38,6 +38,7 @@ struct BuildOptions {
     double flat_min_vec = 8.0;  // rows averaging at least this many 8-entry vectors: wave streaming
     int32_t esz2 = 8;           // bytes of one staged (sin, cos) pair; list entries are LDS byte
                                 // offsets col * esz2, so W * esz2 must stay below 65536
+    int32_t xcds = 1;           // launch order for this many round-robin XCDs (1: plain largest first)
 };
 
 // The graph in block order, ready for upload.
@@ -55,7 +56,8 @@ struct BlockGraph {
     std::vector<int64_t> inter_ptr;   // n + 1, block order
     std::vector<int32_t> inter_col;   // block-order columns
     std::vector<Tile> tiles;
-    std::vector<int32_t> order;       // launch order of tiles (largest first)
+    std::vector<int32_t> order;       // launch order of tiles; -1 marks an empty slot (see order_tiles)
+    int32_t xcds = 1;
     std::vector<int32_t> deg;         // row degree (ones of the row), block order
     int64_t list_unpadded = 0;
     int64_t n_dense = 0;
@@ -93,7 +95,14 @@ std::string merge_graphs(std::vector<BlockGraph> &parts, BlockGraph &out, std::v
 // or tile_rows rows; sets blk[].tile0/ntiles, tiles, tile_rows and the launch order.
 void make_tiles(BlockGraph &g, const BuildOptions &opt);
 
-// Launch order of tiles: largest estimated cost first (stable).
+// Launch order of tiles. Workgroup i of a launch runs on XCD i mod g.xcds (round-robin
+// dispatch) and every XCD has its own L2, so the blocks are first spread over the XCDs by
+// estimated cost (largest to the least loaded XCD), and all tiles of a block run on its XCD:
+// the block's staged (sin, cos) chunks are then read from HBM once and hit that L2 for the
+// other tiles. A block costing more than total / (2 xcds) is placed as runs of consecutive
+// tiles of about that cost, so that few or uneven blocks still use every XCD. Within an XCD the
+// tiles run largest first; slot j * xcds + x holds the j-th tile of XCD x, and -1 where XCD x
+// has fewer tiles. xcds = 1 gives the plain largest-first order.
 void order_tiles(BlockGraph &g);
 
 // Runs f(i) for i in [0, n) on the host threads (static contiguous ranges).

@@ -421,6 +421,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     extern __shared__ __align__(16) unsigned char smem[];
     TileLds<T2, NT> L(smem, g.W, g.tile_rows);
     const int tile_id = g.order[blockIdx.x];
+    if (tile_id < 0) return;  // empty slot of the XCD-aware launch order
     const Tile tl = g.tiles[tile_id];
     const BlkInfo bi = g.blk[tl.block];
     const int nrows = tl.r1 - tl.r0;
@@ -473,6 +474,7 @@ __global__ __launch_bounds__(NT) void k_vjp(DevGraph g, VjpArgs<T> a)
     extern __shared__ __align__(16) unsigned char smem[];
     TileLds<T4, NT> L(smem, g.W, g.tile_rows);
     const int tile_id = g.order[blockIdx.x];
+    if (tile_id < 0) return;  // empty slot of the XCD-aware launch order
     const Tile tl = g.tiles[tile_id];
     const BlkInfo bi = g.blk[tl.block];
     const int nrows = tl.r1 - tl.r0;
@@ -675,9 +677,9 @@ hipError_t launch_rows(const DevGraph &g, int ntiles, const RowArgs<T> &a, int t
         attr_done[slot] = true;
     }
     switch (threads) {
-    case 256: hipLaunchKernelGGL((k_rows<T, 256>), dim3(ntiles), dim3(256), lds, st, g, a); break;
-    case 1024: hipLaunchKernelGGL((k_rows<T, 1024>), dim3(ntiles), dim3(1024), lds, st, g, a); break;
-    default: hipLaunchKernelGGL((k_rows<T, 512>), dim3(ntiles), dim3(512), lds, st, g, a); break;
+    case 256: hipLaunchKernelGGL((k_rows<T, 256>), dim3(g.nlaunch), dim3(256), lds, st, g, a); break;
+    case 1024: hipLaunchKernelGGL((k_rows<T, 1024>), dim3(g.nlaunch), dim3(1024), lds, st, g, a); break;
+    default: hipLaunchKernelGGL((k_rows<T, 512>), dim3(g.nlaunch), dim3(512), lds, st, g, a); break;
     }
     return hipGetLastError();
 }
@@ -698,9 +700,9 @@ hipError_t launch_vjp(const DevGraph &g, int ntiles, const VjpArgs<T> &a, int th
         attr_done[slot] = true;
     }
     switch (threads) {
-    case 256: hipLaunchKernelGGL((k_vjp<T, 256>), dim3(ntiles), dim3(256), lds, st, g, a); break;
-    case 1024: hipLaunchKernelGGL((k_vjp<T, 1024>), dim3(ntiles), dim3(1024), lds, st, g, a); break;
-    default: hipLaunchKernelGGL((k_vjp<T, 512>), dim3(ntiles), dim3(512), lds, st, g, a); break;
+    case 256: hipLaunchKernelGGL((k_vjp<T, 256>), dim3(g.nlaunch), dim3(256), lds, st, g, a); break;
+    case 1024: hipLaunchKernelGGL((k_vjp<T, 1024>), dim3(g.nlaunch), dim3(1024), lds, st, g, a); break;
+    default: hipLaunchKernelGGL((k_vjp<T, 512>), dim3(g.nlaunch), dim3(512), lds, st, g, a); break;
     }
     return hipGetLastError();
 }

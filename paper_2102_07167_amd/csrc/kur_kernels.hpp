@@ -20,6 +20,7 @@ struct DevGraph {
     const int32_t *inter_col;
     int32_t W;
     int32_t tile_rows;
+    int32_t nlaunch;  // entries of order (workgroups of a tile launch); -1 entries are empty slots
 };
 
 // Arguments of one row-kernel launch (one RK stage, or a plain evaluation when stage == 0).

@@ -19,10 +19,11 @@ struct TileParams {
     int32_t tile_rows = 256;
     int64_t tile_min_cost = 16384;
     double flat_min_vec = 8.0;
+    int32_t xcds = 1;
     bool operator==(const TileParams &o) const
     {
         return threads == o.threads && tile_rows == o.tile_rows && tile_min_cost == o.tile_min_cost &&
-               flat_min_vec == o.flat_min_vec;
+               flat_min_vec == o.flat_min_vec && xcds == o.xcds;
     }
     bool operator!=(const TileParams &o) const { return !(*this == o); }
 };

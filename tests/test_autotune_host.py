@@ -24,8 +24,8 @@ def test_tune_key_identifies_graph_and_dtype():
                  uperm=np.arange(402, dtype=np.int32))
     with host_ctx("f32") as a, host_ctx("f64") as b:
         k1 = a.tune_key(g1)
-        assert k1 == a.tune_key(g1) and " host " in k1 and k1.startswith("kur1 f32")
-        assert b.tune_key(g1).startswith("kur1 f64") and b.tune_key(g1) != k1
+        assert k1 == a.tune_key(g1) and " host " in k1 and k1.startswith("kur2 f32")
+        assert b.tune_key(g1).startswith("kur2 f64") and b.tune_key(g1) != k1
         assert a.tune_key(g2) != k1  # same sizes, other labels order
         assert a.tune_key(g3) != k1  # other edges
 
@@ -59,15 +59,15 @@ def test_cached_choice_installs_its_layout(tmp_path):
     with host_ctx() as k:
         key = k.tune_key(g)
         path.write_text(
-            "kur1 f32 host n=1 nnz=0 h=0000000000000000\t0.9 64 256 64 1 1 1\n"
-            + key + "\t0.6 128 256 64 4096 2 1.5\n"
+            "kur2 f32 host n=1 nnz=0 h=0000000000000000\t0.9 64 256 64 1 1 8 1\n"
+            + key + "\t0.6 128 256 64 4096 2 8 1.5\n"
             + key + "\tgarbage\n"
-            + key + "\t0.4 192 512 128 8192 4 1.25\n"
+            + key + "\t0.4 192 512 128 8192 4 1 1.25\n"
             + "no tab here\n")
         rep = k.autotune(g, effort=1, cache=str(path))
         assert rep["cache"] == 1 and rep["builds"] == 1 and rep["timed"] == 0
         assert (rep["tau"], rep["chunk"], rep["threads"], rep["tile_rows"], rep["tile_min_cost"],
-                rep["flat_min_vec"], rep["ms_per_step"]) == (0.4, 192, 512, 128, 8192, 4.0, 1.25)
+                rep["flat_min_vec"], rep["xcds"], rep["ms_per_step"]) == (0.4, 192, 512, 128, 8192, 4.0, 1, 1.25)
         assert np.isnan(rep["ms_per_step_start"])
         info = k.graph_info()
         assert info["chunk"] == 192
@@ -82,7 +82,7 @@ def test_cached_choice_out_of_range_is_rejected(tmp_path):
     g = small_sbm()
     path = tmp_path / "tune.tsv"
     with host_ctx() as k:
-        path.write_text(k.tune_key(g) + "\t0.5 100 512 256 16384 8 1\n")
+        path.write_text(k.tune_key(g) + "\t0.5 100 512 256 16384 8 8 1\n")
         with pytest.raises(K.KurError) as ei:
             k.autotune(g, cache=str(path))
         assert ei.value.status == K.KUR_EINVAL

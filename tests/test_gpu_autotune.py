@@ -99,7 +99,7 @@ def test_autotune_stores_and_reloads(need_gpu, tmp_path):
     with Kuramoto("f32", device=0) as k2:
         rep2 = k2.autotune(g, effort=1, cache=path)
         assert rep2["cache"] == 1 and rep2["timed"] == 0
-        for key in ("tau", "chunk", "threads", "tile_rows", "tile_min_cost", "flat_min_vec"):
+        for key in ("tau", "chunk", "threads", "tile_rows", "tile_min_cost", "flat_min_vec", "xcds"):
             assert rep2[key] == rep[key], key
         assert k2.graph_info() == info
         k2.set_params(om32, 3.0)
