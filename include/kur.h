@@ -257,6 +257,35 @@ kur_status kur_adjoint_rk4_recorded(kur_ctx *ctx, const double *dl_dthetaT, doub
  * recording (0 if none is usable), its dt and its number of steps (either may be NULL). */
 kur_status kur_recorded_run(const kur_ctx *ctx, int64_t *serial, double *dt, int64_t *nsteps);
 
+/*
+ * Advance nsteps steps of size dt with the implicit midpoint rule, the second-order symmetric
+ * (geometric) integrator theta_{n+1} = theta_n + dt F((theta_n + theta_{n+1}) / 2) (Sec. 2,
+ * numerical integration: a second-order geometric integrator beside the explicit RK4). The
+ * implicit equation is solved by `iters` fixed-point iterations on the midpoint Y, each one
+ * evaluation of F: Y_0 = theta_n, Y_i = theta_n + dt/2 F(Y_{i-1}) (i < iters), and
+ * theta_{n+1} = theta_n + dt F(Y_{iters-1}). iters = 1 is explicit Euler, iters = 2 the explicit
+ * midpoint rule; the error of the fixed point shrinks by about dt/2 |dF| per iteration. The
+ * phase update is compensated and wrapped as for kur_step_rk4; r_every, r_out and psi_out as
+ * there. Plain launches (no graph replay, no checkpoint recording). iters in [1, 64].
+ */
+kur_status kur_step_midpoint(kur_ctx *ctx, double dt, int64_t nsteps, int32_t iters, int64_t r_every, double *r_out,
+                             double *psi_out);
+
+/*
+ * Diagnostics of the current state (single systems; a batch returns KUR_ESTATE), computed on
+ * the device with FP64 sums in a fixed order:
+ *   out[0]  the potential V(theta) = -omega^T theta + K/2 sum_{m,l} At_ml (1 - cos(theta_l -
+ *           theta_m)), At_ml = A_ml / Mscale_m (Sec. 3, eq. ExtendedPotentialConservation; Sec. 2,
+ *           eq. Potential for the complete graph), with theta the unwrapped phases. For a
+ *           symmetric A with uniform scaling the dynamics is its gradient flow, so V does not
+ *           increase along a trajectory;
+ *   out[1]  the mean of the unwrapped phases, (1/N) sum_m theta_m;
+ *   out[2]  the mean of omega.
+ * The mean deviation of eq. Means is out[1](t) - out[1](0) - t out[2]; it vanishes for a
+ * symmetric A with uniform scaling (eq. KuramotoGraphConservation). Synchronous.
+ */
+kur_status kur_diagnostics(kur_ctx *ctx, double *out);
+
 /* Wait for all work enqueued on the context stream. */
 kur_status kur_sync(kur_ctx *ctx);
 

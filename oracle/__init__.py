@@ -10,6 +10,7 @@ Functions (all FP64; graphs are ``gen.Graph`` objects in user order):
   rhs(graph, omega, K, theta)            Sec. 3 eq. KuramotoGraph, straightforward summation
   rhs_rows(graph, omega, K, theta, rows) the same on a subset of rows
   rk4(graph, omega, K, theta0, dt, n)    classical RK4, unwrapped phases, r(t) sampling
+  midpoint(graph, omega, K, theta0, dt, n, iters)  implicit midpoint rule, fixed-point iterations
   order_parameter(theta)                 Sec. 2 eq. OrderParameter
   vjp(graph, K, theta, lam)              J(theta)^T lam
   adjoint_rk4(...)                       discrete adjoint of ``rk4``
@@ -56,6 +57,8 @@ def _load():
         lib.orc_order_parameter.argtypes = [i64, P, P, P]
         lib.orc_rk4.restype = ci
         lib.orc_rk4.argtypes = [i64, ci, P, P, ci, P, f64, f64, i64, i64, P, P, P]
+        lib.orc_midpoint.restype = ci
+        lib.orc_midpoint.argtypes = [i64, ci, P, P, ci, P, f64, f64, i64, ctypes.c_int32, i64, P, P, P]
         lib.orc_vjp.restype = None
         lib.orc_vjp.argtypes = [i64, ci, P, P, ci, f64, P, P, P]
         lib.orc_adjoint_rk4.restype = ci
@@ -117,6 +120,21 @@ def rk4(graph, omega, K, theta0, dt, nsteps, r_every: int = 0, scaling: int = 0)
                          _p(theta), _p(r) if nr else None, _p(psi) if nr else None)
     if rc != 0:
         raise MemoryError("oracle rk4")
+    return theta, r, psi
+
+
+def midpoint(graph, omega, K, theta0, dt, nsteps, iters, r_every: int = 0, scaling: int = 0):
+    """Implicit midpoint rule by `iters` fixed-point iterations per step on unwrapped phases;
+    returns (theta(T), r, psi) as rk4."""
+    omega = _f64(omega)
+    theta = _f64(theta0).copy()
+    nr = nsteps // r_every + 1 if r_every > 0 else 0
+    r = np.empty(nr)
+    psi = np.empty(nr)
+    rc = _load().orc_midpoint(*_g(graph), scaling, _p(omega), float(K), float(dt), int(nsteps), int(iters),
+                              int(r_every), _p(theta), _p(r) if nr else None, _p(psi) if nr else None)
+    if rc != 0:
+        raise MemoryError("oracle midpoint")
     return theta, r, psi
 
 

@@ -764,20 +764,20 @@ kur_status kur_set_phases(kur_ctx *c, const double *theta)
     return KUR_OK;
 }
 
-static kur_status eval_common(kur_ctx *c, const void *y_dev, void *out_dev)
+static kur_status eval_common(kur_ctx *c, const void *y_dev, void *out_dev, int stage = 0)
 {
     kur_status s = sc_init(c, y_dev, c->d_sce, c->d_parte);
     if (s != KUR_OK) return s;
     DevGraph g = devgraph(c);
     hipError_t e;
     if (c->esz == 4) {
-        RowArgs<float> a = row_args<float>(c, 0, 0.0);
+        RowArgs<float> a = row_args<float>(c, stage, 0.0);
         a.sc_in = c->d_sce.p;
         a.part_in = c->d_parte.p;
         a.kout = (float *)out_dev;
         e = timed_rows(c, g, &a);
     } else {
-        RowArgs<double> a = row_args<double>(c, 0, 0.0);
+        RowArgs<double> a = row_args<double>(c, stage, 0.0);
         a.sc_in = c->d_sce.p;
         a.part_in = c->d_parte.p;
         a.kout = (double *)out_dev;
@@ -822,6 +822,47 @@ kur_status kur_eval_rhs_dev(kur_ctx *c, const void *theta_dev, void *dtheta_dev)
     kur_status s = need_ready(c, true, false);
     if (s != KUR_OK) return s;
     return eval_common(c, theta_dev, dtheta_dev);
+}
+
+kur_status kur_diagnostics(kur_ctx *c, double *out)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!out) return fail(c, KUR_EINVAL, "out must not be NULL");
+    kur_status s = need_ready(c, true, true);
+    if (s != KUR_OK) return s;
+    if (c->batch) return fail(c, KUR_ESTATE, "diagnostics are defined per system, not for a batch");
+    DevBuf part, res;
+    hipError_t e;
+    const int64_t n = c->n;
+    const int64_t nchunk = (n + 255) / 256;
+    if ((e = dalloc(part, 24 * (size_t)nchunk)) != hipSuccess || (e = dalloc(res, 24)) != hipSuccess)
+        return hip_fail(c, e, "diagnostics buffers");
+    struct Release {
+        DevBuf *a, *b;
+        ~Release()
+        {
+            dfree(*a);
+            dfree(*b);
+        }
+    } rel{&part, &res};
+    if ((s = eval_common(c, c->d_hi.p, c->d_kout.p, -1)) != KUR_OK) return s;
+    e = c->esz == 4 ? launch_diag<float>(n, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, c->d_omega.p, c->d_unit.p,
+                                         c->d_kout.p, c->K, (double *)part.p, (double *)res.p, c->stream)
+                    : launch_diag<double>(n, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, c->d_omega.p,
+                                          c->d_unit.p, c->d_kout.p, c->K, (double *)part.p, (double *)res.p, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
+    double h[3];
+    if ((e = hipMemcpyAsync(h, res.p, 24, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+        return hip_fail(c, e, "diagnostics download");
+    // the constant of the potential, K/2 sum_m scale_m deg_m, from the host degrees
+    double cst = 0.0;
+    for (int64_t m = 0; m < n; ++m) cst += c->scaling ? (c->deg[m] > 0 ? 1.0 : 0.0) : (double)c->deg[m] / (double)n;
+    out[0] = h[2] + 0.5 * c->K * cst;
+    out[1] = h[0] / (double)n;
+    out[2] = h[1] / (double)n;
+    return KUR_OK;
 }
 
 static hipError_t launch_sample(kur_ctx *c, const int64_t *idx_dev, int64_t idx)
@@ -978,6 +1019,64 @@ kur_status kur_step_rk4(kur_ctx *c, double dt, int64_t nsteps, int64_t r_every, 
     if (c->batch && r_every > 0 && (r_out || psi_out))
         return fail(c, KUR_EINVAL, "a batch samples per instance: use kur_batch_step");
     s = run_steps(c, dt, nsteps, r_every);
+    if (s != KUR_OK) return s;
+    return fetch_samples(c, r_every > 0 ? nsteps / r_every + 1 : 0, r_out, psi_out);
+}
+
+// Implicit midpoint rule by fixed-point iteration on the midpoint Y: Y_0 = theta_n,
+// Y_i = theta_n + dt/2 F(Y_{i-1}) for i < iters, theta_{n+1} = theta_n + dt F(Y_{iters-1}).
+// One row-kernel launch per iteration (stage 5, the last one stage 6).
+static kur_status run_midpoint(kur_ctx *c, double dt, int64_t nsteps, int32_t iters, int64_t r_every)
+{
+    const int64_t nsamp = r_every > 0 ? nsteps / r_every + 1 : 0;
+    hipError_t e;
+    if (nsamp > 0) {
+        if ((e = dalloc(c->d_r, sizeof(double) * nsamp * c->n_inst)) != hipSuccess ||
+            (e = dalloc(c->d_psi, sizeof(double) * nsamp * c->n_inst)) != hipSuccess)
+            return hip_fail(c, e, "r buffer");
+    }
+    if (!c->sc_valid) {
+        kur_status s = sc_init(c, c->d_hi.p, c->d_sc[c->cur], c->d_part[c->cur]);
+        if (s != KUR_OK) return s;
+        c->sc_valid = true;
+    }
+    const DevGraph g = devgraph(c);
+    int64_t k = 0;
+    if (r_every > 0 && (e = launch_sample(c, nullptr, k++)) != hipSuccess) return hip_fail(c, e, "order parameter launch");
+    for (int64_t step = 0; step < nsteps; ++step) {
+        for (int32_t it = 1; it <= iters; ++it) {
+            const int stage = it < iters ? 5 : 6;
+            if (c->esz == 4) {
+                RowArgs<float> a = row_args<float>(c, stage, dt);
+                e = timed_rows(c, g, &a);
+            } else {
+                RowArgs<double> a = row_args<double>(c, stage, dt);
+                e = timed_rows(c, g, &a);
+            }
+            if (e != hipSuccess) return hip_fail(c, e, "midpoint launch");
+            c->cur ^= 1;
+        }
+        if (c->timing && c->ev_used + 2 * (size_t)iters > 4096 && (e = harvest_events(c)) != hipSuccess)
+            return hip_fail(c, e, "timing");
+        if (r_every > 0 && (step + 1) % r_every == 0 && (e = launch_sample(c, nullptr, k++)) != hipSuccess)
+            return hip_fail(c, e, "order parameter launch");
+    }
+    return KUR_OK;
+}
+
+kur_status kur_step_midpoint(kur_ctx *c, double dt, int64_t nsteps, int32_t iters, int64_t r_every, double *r_out,
+                             double *psi_out)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!std::isfinite(dt) || dt == 0.0) return fail(c, KUR_EINVAL, "dt must be finite and nonzero");
+    if (nsteps < 0 || r_every < 0) return fail(c, KUR_EINVAL, "nsteps and r_every must be >= 0");
+    if (iters < 1 || iters > 64) return fail(c, KUR_EINVAL, "iters must be in [1, 64]");
+    kur_status s = need_ready(c, true, true);
+    if (s != KUR_OK) return s;
+    if (c->batch && r_every > 0 && (r_out || psi_out))
+        return fail(c, KUR_EINVAL, "a batch samples per instance: use kur_batch_step");
+    s = run_midpoint(c, dt, nsteps, iters, r_every);
     if (s != KUR_OK) return s;
     return fetch_samples(c, r_every > 0 ? nsteps / r_every + 1 : 0, r_out, psi_out);
 }

@@ -46,11 +46,16 @@ template <typename T> __device__ __forceinline__ void two_sum(T a, T b, T &s, T 
     e = (a - (s - bb)) + (b - bb);
 }
 
-// Bookkeeping of one oscillator in classical RK4 (y_{n+1} = y_n + dt/6 (k1 + 2 k2 + 2 k3 + k4))
-// given its stage derivative k. Stages 1-3 accumulate k1 + 2 k2 + 2 k3 in *ksum and return the
-// next stage input (theta + dt/2 k1, theta + dt/2 k2, theta + dt k3). Stage 4 adds
-// dt/6 (ksum + k4) to the phase hi + lo with error-free sums when `compensate`, wraps the result
-// to [-pi, pi) (the whole turns go to *wind), stores it and returns the new phase.
+// Bookkeeping of one oscillator given its stage derivative k, for classical RK4
+// (y_{n+1} = y_n + dt/6 (k1 + 2 k2 + 2 k3 + k4)) and for the implicit midpoint rule
+// (y_{n+1} = y_n + dt F((y_n + y_{n+1}) / 2), solved by fixed-point iteration on the midpoint).
+//   stages 1-3   RK4: accumulate k1 + 2 k2 + 2 k3 in *ksum and return the next stage input
+//                (theta + dt/2 k1, theta + dt/2 k2, theta + dt k3);
+//   stage 4      RK4: advance the phase by dt/6 (ksum + k4);
+//   stage 5      midpoint iterate: return theta + dt/2 k (the phase is not changed);
+//   stage 6      midpoint final: advance the phase by dt k.
+// The advance adds to hi + lo with error-free sums when `compensate`, wraps the result to
+// [-pi, pi) (the whole turns go to *wind), stores it and returns the new phase.
 template <typename T>
 __device__ __forceinline__ T rk4_stage(int stage, T k, T dt, T half_dt, T dt6, int compensate, T *ksum, T *hi_p,
                                        T *lo_p, int32_t *wind_p)
@@ -68,7 +73,8 @@ __device__ __forceinline__ T rk4_stage(int stage, T k, T dt, T half_dt, T dt6, i
         *ksum += T(2) * k;
         return th + dt * k;
     }
-    const T delta = dt6 * (*ksum + k);
+    if (stage == 5) return th + half_dt * k;
+    const T delta = stage == 6 ? dt * k : dt6 * (*ksum + k);
     T hi, lo;
     int wd = *wind_p;
     if (compensate) {

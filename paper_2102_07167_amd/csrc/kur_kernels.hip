@@ -440,8 +440,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         const T Ac = base.y + L.acc[r].y;
         const T scale = a.K * (a.unit ? a.unit[m] : a.inv_n);
         const T k = a.omega[m] + scale * (As * scm.y - Ac * scm.x);
-        if (a.stage == 0) {
-            a.kout[m] = k;
+        if (a.stage <= 0) {
+            // 0: the derivative; -1: the row's coupling energy cos y (A cos y) + sin y (A sin y).
+            // The localised order parameters of a dense block include the row's own node, whose
+            // term cancels in the derivative but adds cos^2 y + sin^2 y here: it is removed.
+            T en = scm.y * Ac + scm.x * As;
+            if (bi.mode) en -= scm.y * scm.y + scm.x * scm.x;
+            a.kout[m] = a.stage == 0 ? k : en;
             continue;
         }
         const T y = rk4_stage<T>(a.stage, k, a.dt, a.half_dt, a.dt6, a.compensate, a.ksum + m, a.hi + m, a.lo + m,
@@ -455,7 +460,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         part.x += s;
         part.y += c;
     }
-    if (a.stage != 0) block_sum_store<T2, NT>(part, L.red, reinterpret_cast<T2 *>(a.part_out) + tile_id);
+    if (a.stage > 0) block_sum_store<T2, NT>(part, L.red, reinterpret_cast<T2 *>(a.part_out) + tile_id);
 }
 
 // Discrete adjoint of one classical RK4 stage (reverse order 4, 3, 2, 1). With x_in holding
@@ -620,6 +625,57 @@ hipError_t launch_stream_read(const void *p, int64_t words, uint32_t *out, hipSt
 // advance the replayed sample counter
 __global__ void k_bump(int64_t *ctr) { *ctr += 1; }
 
+// Partial sums for the diagnostics, one chunk of 256 rows per workgroup, in FP64 and a fixed
+// order: the unwrapped phases theta = hi + lo + 2 pi wind, omega, and the potential's row terms
+// -omega_m theta_m - K/2 scale_m e_m with e_m the row's coupling energy (Sec. 3, eq.
+// ExtendedPotentialConservation; the constant K/2 sum_m scale_m deg_m is added on the host).
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag(int64_t n, const T *__restrict__ hi, const T *__restrict__ lo,
+                                              const int32_t *__restrict__ wind, const T *__restrict__ omega,
+                                              const T *__restrict__ unit, const T *__restrict__ e, double K, double inv_n,
+                                              double *__restrict__ part)
+{
+    __shared__ double red[3][256];
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double st = 0.0, so = 0.0, sv = 0.0;
+    if (m < n) {
+        const double th = (double)hi[m] + (double)lo[m] +
+                          (double)wind[m] * ((double)TwoPi<T>::P1 + (double)TwoPi<T>::P2);
+        const double om = (double)omega[m];
+        const double sc = unit ? (double)unit[m] : inv_n;
+        st = th;
+        so = om;
+        sv = -om * th - 0.5 * K * sc * (double)e[m];
+    }
+    red[0][threadIdx.x] = st;
+    red[1][threadIdx.x] = so;
+    red[2][threadIdx.x] = sv;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[3 * (int64_t)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Fixed-order fold of the k_diag partials into out[0..3): one workgroup.
+__global__ __launch_bounds__(256) void k_diag_fold(int64_t nchunk, const double *__restrict__ part, double *__restrict__ out)
+{
+    __shared__ double red[3][256];
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int64_t c = threadIdx.x; c < nchunk; c += 256)
+        for (int q = 0; q < 3; ++q) a[q] += part[3 * c + q];
+    for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = a[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
 // out[m] = hi + lo (+ 2 pi wind)
 template <typename T>
 __global__ void k_phase_out(int64_t n, const T *__restrict__ hi, const T *__restrict__ lo, const int32_t *__restrict__ wind,
@@ -720,6 +776,20 @@ hipError_t launch_vjp_init(const DevGraph &g, int ntiles, const VjpArgs<T> &a, i
 }
 
 template <typename T>
+hipError_t launch_diag(int64_t n, const void *hi, const void *lo, const int32_t *wind, const void *omega,
+                       const void *unit, const void *e, double K, double *part, double *out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t nchunk = (n + 255) / 256;
+    hipLaunchKernelGGL((k_diag<T>), dim3((unsigned)nchunk), dim3(256), 0, st, n, (const T *)hi, (const T *)lo, wind,
+                       (const T *)omega, (const T *)unit, (const T *)e, K, 1.0 / (double)n, part);
+    hipError_t r = hipGetLastError();
+    if (r != hipSuccess) return r;
+    hipLaunchKernelGGL(k_diag_fold, dim3(1), dim3(256), 0, st, nchunk, (const double *)part, out);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_order(const void *part, const int64_t *tile_first, const double *inv_n, int n_inst, double *r,
                         double *psi, const int64_t *idx_dev, int64_t idx, hipStream_t st)
 {
@@ -753,6 +823,10 @@ template hipError_t launch_vjp<float>(const DevGraph &, int, const VjpArgs<float
 template hipError_t launch_vjp<double>(const DevGraph &, int, const VjpArgs<double> &, int, hipStream_t);
 template hipError_t launch_vjp_init<float>(const DevGraph &, int, const VjpArgs<float> &, int, hipStream_t);
 template hipError_t launch_vjp_init<double>(const DevGraph &, int, const VjpArgs<double> &, int, hipStream_t);
+template hipError_t launch_diag<float>(int64_t, const void *, const void *, const int32_t *, const void *,
+                                       const void *, const void *, double, double *, double *, hipStream_t);
+template hipError_t launch_diag<double>(int64_t, const void *, const void *, const int32_t *, const void *,
+                                        const void *, const void *, double, double *, double *, hipStream_t);
 template hipError_t launch_order<float>(const void *, const int64_t *, const double *, int, double *, double *,
                                        const int64_t *, int64_t, hipStream_t);
 template hipError_t launch_order<double>(const void *, const int64_t *, const double *, int, double *, double *,

@@ -27,7 +27,7 @@ struct DevGraph {
 // The coupling factor of row m is K * unit[m] (unit = 1/deg_m) or K * inv_n when unit is null.
 template <typename T>
 struct RowArgs {
-    int stage;          // 0: write F to kout; 1..4: classical RK4 stage
+    int stage;          // 0: write F to kout; -1: write the coupling energy (see k_rows); 1..4: RK4 stage
     int compensate;     // compensated phase update in stage 4
     T dt, half_dt, dt6; // dt, dt/2, dt/6
     T K, inv_n;
@@ -81,6 +81,13 @@ template <typename T>
 hipError_t launch_vjp_init(const DevGraph &g, int ntiles, const VjpArgs<T> &a, int threads, hipStream_t st);
 
 // Dynamic LDS bytes of a tile workgroup gathering nv (sin, cos)-sized pairs per node.
+// Diagnostics at the current state: out[0..3) = (sum of unwrapped theta, sum of omega,
+// sum_m -omega_m theta_m - K/2 scale_m e_m) with e the rows' coupling energies; part holds
+// 3 ceil(n / 256) doubles of scratch.
+template <typename T>
+hipError_t launch_diag(int64_t n, const void *hi, const void *lo, const int32_t *wind, const void *omega,
+                       const void *unit, const void *e, double K, double *part, double *out, hipStream_t st);
+
 size_t rows_lds_bytes(int elem_bytes, int W, int tile_rows, int threads, int nv = 1);
 double two_pi_p1(int elem_bytes);
 double two_pi_p2(int elem_bytes);

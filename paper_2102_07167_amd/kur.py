@@ -74,6 +74,8 @@ SIGNATURES = {
     "kur_ens_row_pattern": (ST, [P, I64, P, P, P]),
     "kur_ens_kernel_time": (ST, [P, P]),
     "kur_ens_autotune_csr": (ST, [P, I64, P, P, P, I32, I32, P]),
+    "kur_diagnostics": (ST, [P, P]),
+    "kur_step_midpoint": (ST, [P, F64, I64, I32, I64, P, P]),
     "kur_eval_rhs_dev": (ST, [P, P, P]),
     "kur_get_phases_dev": (ST, [P, P]),
 }
@@ -310,6 +312,25 @@ class Kuramoto:
         gk = F64()
         self._chk(self._L.kur_adjoint_rk4_recorded(self._h, _ptr(seed), _ptr(gt), _ptr(gw), ctypes.byref(gk)))
         return gt, gw, gk.value
+
+    def step_midpoint(self, dt: float, nsteps: int, iters: int = 4, r_every: int = 0):
+        """Implicit midpoint rule with `iters` fixed-point iterations per step (kur_step_midpoint);
+        returns r and psi samples like step_rk4."""
+        if r_every > 0:
+            ns = nsteps // r_every + 1
+            r = np.empty(ns)
+            psi = np.empty(ns)
+            self._chk(self._L.kur_step_midpoint(self._h, float(dt), int(nsteps), int(iters), int(r_every), _ptr(r),
+                                                _ptr(psi)))
+            return r, psi
+        self._chk(self._L.kur_step_midpoint(self._h, float(dt), int(nsteps), int(iters), 0, None, None))
+        return None, None
+
+    def diagnostics(self) -> dict:
+        """Potential V, mean unwrapped phase and mean omega of the current state (kur_diagnostics)."""
+        out = np.zeros(3)
+        self._chk(self._L.kur_diagnostics(self._h, _ptr(out)))
+        return {"V": out[0], "mean_theta": out[1], "mean_omega": out[2]}
 
     def recorded_run(self):
         """(serial, dt, nsteps) of the run kept for adjoint_recorded (serial 0: none)."""

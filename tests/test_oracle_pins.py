@@ -327,3 +327,59 @@ def test_rhs_rows_subset_consistent():
     F = oracle.rhs(w.graph, w.omega, w.K, w.theta0)
     rows = np.array([0, 5, 255, 17, 17])
     np.testing.assert_array_equal(oracle.rhs_rows(w.graph, w.omega, w.K, w.theta0, rows), F[rows])
+
+
+# ---------------------------------------------------------------------------------------------
+# implicit midpoint rule (the second-order geometric integrator of Sec. 2)
+
+def _mid_setup(seed=31):
+    rng = np.random.default_rng(seed)
+    sizes = np.array([40, 25, 35])
+    g = gen.sbm(sizes, np.array([0.8, 0.6, 0.9]), 0.05, key=555, uperm=rng.permutation(100).astype(np.int32))
+    return g, rng.standard_normal(100), rng.uniform(0, 2 * np.pi, 100)
+
+
+def test_midpoint_few_iterations_are_textbook_methods():
+    """One iteration is explicit Euler, two are the explicit midpoint rule (both written out
+    here from the right-hand side)."""
+    g, om, th = _mid_setup()
+    K, dt = 2.5, 0.05
+    e1, _, _ = oracle.midpoint(g, om, K, th, dt, 1, 1)
+    assert np.abs(e1 - (th + dt * oracle.rhs(g, om, K, th))).max() < 1e-14
+    e2, _, _ = oracle.midpoint(g, om, K, th, dt, 1, 2)
+    want = th + dt * oracle.rhs(g, om, K, th + 0.5 * dt * oracle.rhs(g, om, K, th))
+    assert np.abs(e2 - want).max() < 1e-14
+
+
+def test_midpoint_converged_solves_the_implicit_equation():
+    g, om, th = _mid_setup(32)
+    K, dt = 3.0, 0.05
+    y1, _, _ = oracle.midpoint(g, om, K, th, dt, 1, 40)
+    res = y1 - th - dt * oracle.rhs(g, om, K, 0.5 * (th + y1))
+    assert np.abs(res).max() < 1e-13
+
+
+def test_midpoint_is_symmetric_and_second_order():
+    g, om, th = _mid_setup(33)
+    K = 3.0
+    # symmetry: a step of dt followed by a step of -dt returns to the start
+    y1, _, _ = oracle.midpoint(g, om, K, th, 0.05, 1, 40)
+    y0, _, _ = oracle.midpoint(g, om, K, y1, -0.05, 1, 40)
+    assert np.abs(y0 - th).max() < 1e-13
+    # order 2 against an RK4 reference at T = 0.8
+    ref, _, _ = oracle.rk4(g, om, K, th, 0.8 / 400, 400)
+    errs = []
+    for nst in (20, 40, 80):
+        y, _, _ = oracle.midpoint(g, om, K, th, 0.8 / nst, nst, 40)
+        errs.append(np.abs(y - ref).max())
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all(np.abs(ratios - 4.0) < 0.4), ratios
+
+
+def test_midpoint_conserves_the_mean():
+    """Symmetric A, uniform scaling: (1/N) sum (theta - theta0 - t omega) stays 0 (eq.
+    KuramotoGraphConservation), for any number of iterations."""
+    g, om, th = _mid_setup(34)
+    for iters in (1, 3, 8):
+        y, _, _ = oracle.midpoint(g, om, 2.0, th, 0.03, 50, iters)
+        assert abs(np.mean(y - th - 1.5 * om)) < 1e-13
