@@ -272,6 +272,21 @@ kur_status kur_step_midpoint(kur_ctx *ctx, double dt, int64_t nsteps, int32_t it
                              double *psi_out);
 
 /*
+ * Integrate from the current state over the time t_end > 0 with a variable step size: the
+ * explicit embedded Runge-Kutta pair of orders 4 and 5 of Fehlberg (six evaluations of F per
+ * attempted step), propagating the fourth-order solution (Sec. 2, numerical integration: a
+ * variable stepsize fourth-order explicit Runge-Kutta method). The local error estimate of a
+ * step of size h is e = max_m |h sum_j (b5_j - b4_j) k_{j,m}|; the step is accepted when
+ * e <= atol (an absolute tolerance on the phases), and the next size is
+ * h min(4, max(0.2, 0.9 (e / atol)^(-1/5))) (4 when e = 0); the last step is shortened to end
+ * at t_end. dt0 is the first trial size; at most max_steps steps are attempted. The phase
+ * update is compensated and wrapped as for kur_step_rk4. out[4] receives the time reached, the
+ * proposed next step size, the accepted and the rejected steps. In FP32 choose atol above the
+ * FP32 noise of the estimate (about 1e-6 h |F|). Synchronises once per attempted step.
+ */
+kur_status kur_step_adaptive(kur_ctx *ctx, double t_end, double dt0, double atol, int64_t max_steps, double *out);
+
+/*
  * Diagnostics of the current state (single systems; a batch returns KUR_ESTATE), computed on
  * the device with FP64 sums in a fixed order:
  *   out[0]  the potential V(theta) = -omega^T theta + K/2 sum_{m,l} At_ml (1 - cos(theta_l -

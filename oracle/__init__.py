@@ -11,6 +11,7 @@ Functions (all FP64; graphs are ``gen.Graph`` objects in user order):
   rhs_rows(graph, omega, K, theta, rows) the same on a subset of rows
   rk4(graph, omega, K, theta0, dt, n)    classical RK4, unwrapped phases, r(t) sampling
   midpoint(graph, omega, K, theta0, dt, n, iters)  implicit midpoint rule, fixed-point iterations
+  rkf45(graph, omega, K, theta0, t_end, dt0, atol)  variable-step embedded RK pair of orders 4(5)
   order_parameter(theta)                 Sec. 2 eq. OrderParameter
   vjp(graph, K, theta, lam)              J(theta)^T lam
   adjoint_rk4(...)                       discrete adjoint of ``rk4``
@@ -57,6 +58,10 @@ def _load():
         lib.orc_order_parameter.argtypes = [i64, P, P, P]
         lib.orc_rk4.restype = ci
         lib.orc_rk4.argtypes = [i64, ci, P, P, ci, P, f64, f64, i64, i64, P, P, P]
+        lib.orc_rkf45.restype = ci
+        lib.orc_rkf45.argtypes = [i64, ci, P, P, ci, P, f64, f64, f64, f64, i64, P, P]
+        lib.orc_rkf45_tableau.restype = None
+        lib.orc_rkf45_tableau.argtypes = [P, P, P]
         lib.orc_midpoint.restype = ci
         lib.orc_midpoint.argtypes = [i64, ci, P, P, ci, P, f64, f64, i64, ctypes.c_int32, i64, P, P, P]
         lib.orc_vjp.restype = None
@@ -136,6 +141,26 @@ def midpoint(graph, omega, K, theta0, dt, nsteps, iters, r_every: int = 0, scali
     if rc != 0:
         raise MemoryError("oracle midpoint")
     return theta, r, psi
+
+
+def rkf45(graph, omega, K, theta0, t_end, dt0, atol, max_steps: int = 1000000, scaling: int = 0):
+    """Variable-step embedded RK pair of orders 4(5) over [0, t_end]; returns (theta(T), stats)
+    with stats = (t reached, next dt, accepted, rejected)."""
+    omega = _f64(omega)
+    theta = _f64(theta0).copy()
+    stats = np.zeros(4)
+    rc = _load().orc_rkf45(*_g(graph), scaling, _p(omega), float(K), float(t_end), float(dt0), float(atol),
+                           int(max_steps), _p(theta), _p(stats))
+    if rc != 0:
+        raise ArithmeticError("oracle rkf45 failed (%d)" % rc)
+    return theta, stats
+
+
+def rkf45_tableau():
+    """(a 6x6, b4, b5) of the oracle's embedded pair."""
+    a, b4, b5 = np.zeros(36), np.zeros(6), np.zeros(6)
+    _load().orc_rkf45_tableau(_p(a), _p(b4), _p(b5))
+    return a.reshape(6, 6), b4, b5
 
 
 def vjp(graph, K, theta, lam, scaling: int = 0) -> np.ndarray:

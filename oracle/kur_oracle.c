@@ -179,6 +179,93 @@ int orc_midpoint(int64_t n, int complete, const int64_t *row_ptr, const int32_t 
 }
 
 /*
+ * Fehlberg's embedded Runge-Kutta pair of orders 4 and 5 (E. Fehlberg, NASA TR R-315, 1969),
+ * written as the tableau c, a (strictly lower triangular), b4 (propagated), b5 (error estimate).
+ */
+static const double RKF_A[6][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 4, 0, 0, 0, 0, 0},
+    {3.0 / 32, 9.0 / 32, 0, 0, 0, 0},
+    {1932.0 / 2197, -7200.0 / 2197, 7296.0 / 2197, 0, 0, 0},
+    {439.0 / 216, -8.0, 3680.0 / 513, -845.0 / 4104, 0, 0},
+    {-8.0 / 27, 2.0, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40, 0},
+};
+static const double RKF_B4[6] = {25.0 / 216, 0, 1408.0 / 2565, 2197.0 / 4104, -1.0 / 5, 0};
+static const double RKF_B5[6] = {16.0 / 135, 0, 6656.0 / 12825, 28561.0 / 56430, -9.0 / 50, 2.0 / 55};
+
+void orc_rkf45_tableau(double *a, double *b4, double *b5)
+{
+    for (int i = 0; i < 6; ++i) {
+        for (int j = 0; j < 6; ++j) a[6 * i + j] = RKF_A[i][j];
+        b4[i] = RKF_B4[i];
+        b5[i] = RKF_B5[i];
+    }
+}
+
+/*
+ * Variable step size integration over [0, t_end] with the pair above, in this order per
+ * attempted step of size h = min(dt, t_end - t): k_1 = F(theta), k_i = F(theta + h sum_{j<i}
+ * a_ij k_j); local error e = max_m |h sum_j (b5_j - b4_j) k_{j,m}|; accept if e <= atol
+ * (theta += h sum_j b4_j k_j, t += h); next dt = h min(4, max(0.2, 0.9 (e/atol)^(-1/5))), 4 when
+ * e = 0. stats = (t reached, next dt, accepted, rejected).
+ */
+int orc_rkf45(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, int scaling,
+              const double *omega, double K, double t_end, double dt0, double atol, int64_t max_steps,
+              double *theta, double *stats)
+{
+    orc_graph g = {n, complete, row_ptr, col, scaling};
+    double *k = (double *)malloc(sizeof(double) * 7 * (size_t)n);
+    if (!k) return -1;
+    double *y = k + 6 * n;
+    double t = 0.0, dt = dt0 < t_end ? dt0 : t_end;
+    int64_t acc = 0, rej = 0;
+    while (t < t_end && acc + rej < max_steps) {
+        const double h = dt < t_end - t ? dt : t_end - t;
+        rhs(&g, omega, K, theta, k);
+        for (int i = 1; i < 6; ++i) {
+            for (int64_t m = 0; m < n; ++m) {
+                double s = 0.0;
+                for (int j = 0; j < i; ++j) s += RKF_A[i][j] * k[j * n + m];
+                y[m] = theta[m] + h * s;
+            }
+            rhs(&g, omega, K, y, k + i * n);
+        }
+        double err = 0.0;
+        for (int64_t m = 0; m < n; ++m) {
+            double s = 0.0;
+            for (int j = 0; j < 6; ++j) s += (RKF_B5[j] - RKF_B4[j]) * k[j * n + m];
+            if (fabs(h * s) > err) err = fabs(h * s);
+        }
+        const double errn = err / atol;
+        if (!(errn == errn) || errn > 1e300) { free(k); return -2; }
+        if (errn <= 1.0) {
+            for (int64_t m = 0; m < n; ++m) {
+                double s = 0.0;
+                for (int j = 0; j < 6; ++j) s += RKF_B4[j] * k[j * n + m];
+                theta[m] += h * s;
+            }
+            t = h == t_end - t ? t_end : t + h;  /* a step clamped to the end lands on it */
+            ++acc;
+        } else {
+            ++rej;
+        }
+        double fac = 4.0;
+        if (errn > 0.0) {
+            fac = 0.9 * pow(errn, -0.2);
+            if (fac < 0.2) fac = 0.2;
+            if (fac > 4.0) fac = 4.0;
+        }
+        dt = h * fac;
+    }
+    stats[0] = t;
+    stats[1] = dt;
+    stats[2] = (double)acc;
+    stats[3] = (double)rej;
+    free(k);
+    return 0;
+}
+
+/*
  * Jacobian-transpose product out = J(theta)^T lam, with
  *   dF_m/dtheta_l = K s_m A_ml cos(theta_l - theta_m)             (l != m)
  *   dF_m/dtheta_m = -K s_m sum_l A_ml cos(theta_l - theta_m)

@@ -1081,6 +1081,130 @@ kur_status kur_step_midpoint(kur_ctx *c, double dt, int64_t nsteps, int32_t iter
     return fetch_samples(c, r_every > 0 ? nsteps / r_every + 1 : 0, r_out, psi_out);
 }
 
+}  // extern "C"
+
+// Fehlberg's embedded Runge-Kutta pair of orders 4 and 5 (E. Fehlberg, NASA TR R-315, 1969):
+// stage inputs Y_{i+1} = theta + dt sum_j kAemb[i][j] k_j, the order-4 weights propagate the
+// solution and the order-5 weights estimate its local error.
+static const double kAemb[5][5] = {
+    {1.0 / 4.0, 0, 0, 0, 0},
+    {3.0 / 32.0, 9.0 / 32.0, 0, 0, 0},
+    {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0, 0},
+    {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0},
+    {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0},
+};
+static const double kB4emb[6] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0, -1.0 / 5.0, 0.0};
+static const double kB5emb[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0, 2.0 / 55.0};
+
+template <typename T>
+static kur_status adaptive_impl(kur_ctx *c, double t_end, double dt0, double atol, int64_t max_steps, double *out)
+{
+    const int64_t n = c->n;
+    const size_t TN = sizeof(T) * (size_t)n;
+    DevBuf kbuf, hi2, lo2, wind2, errp, errv;
+    struct Release {
+        DevBuf *b[6];
+        ~Release()
+        {
+            for (DevBuf *x : b) dfree(*x);
+        }
+    } rel{{&kbuf, &hi2, &lo2, &wind2, &errp, &errv}};
+    hipError_t e;
+    if ((e = dalloc(kbuf, 6 * TN)) != hipSuccess || (e = dalloc(hi2, TN)) != hipSuccess ||
+        (e = dalloc(lo2, TN)) != hipSuccess || (e = dalloc(wind2, 4 * (size_t)n)) != hipSuccess ||
+        (e = dalloc(errp, sizeof(T) * (size_t)std::max(1, c->ntiles))) != hipSuccess ||
+        (e = dalloc(errv, sizeof(T))) != hipSuccess)
+        return hip_fail(c, e, "adaptive buffers");
+    const DevGraph g = devgraph(c);
+    double t = 0.0, dt = std::min(dt0, t_end);
+    int64_t acc = 0, rej = 0;
+    while (t < t_end && acc + rej < max_steps) {
+        const double h = std::min(dt, t_end - t);
+        if (!c->sc_valid) {
+            kur_status s = sc_init(c, c->d_hi.p, c->d_sc[c->cur], c->d_part[c->cur]);
+            if (s != KUR_OK) return s;
+            c->sc_valid = true;
+        }
+        for (int stage = 1; stage <= 6; ++stage) {
+            EmbArgs<T> a{};
+            a.stage = stage;
+            a.nstages = 6;
+            a.compensate = c->compensate;
+            a.dt = (T)h;
+            a.K = (T)c->K;
+            a.inv_n = (T)(1.0 / (double)n);
+            a.unit = (const T *)c->d_unit.p;
+            a.omega = (const T *)c->d_omega.p;
+            a.hi = (const T *)c->d_hi.p;
+            a.lo = (const T *)c->d_lo.p;
+            a.wind = (const int32_t *)c->d_wind.p;
+            a.hi_new = (T *)hi2.p;
+            a.lo_new = (T *)lo2.p;
+            a.wind_new = (int32_t *)wind2.p;
+            a.kbuf = (T *)kbuf.p;
+            a.n = n;
+            for (int j = 0; j < 6; ++j) {
+                a.coef[j] = (T)(stage < 6 ? (j < 5 ? kAemb[stage - 1][j] : 0.0) : kB4emb[j]);
+                a.coef2[j] = (T)(kB5emb[j] - kB4emb[j]);
+            }
+            a.err_part = (T *)errp.p;
+            a.sc_in = c->d_sc[c->cur].p;
+            a.part_in = c->d_part[c->cur].p;
+            a.sc_out = c->d_sc[c->cur ^ 1].p;
+            a.part_out = c->d_part[c->cur ^ 1].p;
+            if ((e = launch_emb<T>(g, a, c->threads, c->stream)) != hipSuccess) return hip_fail(c, e, "adaptive stage launch");
+            c->cur ^= 1;
+        }
+        T err_dev;
+        if ((e = launch_max_fold<T>(std::max(1, c->ntiles), (const T *)errp.p, (T *)errv.p, c->stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(&err_dev, errv.p, sizeof(T), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+            return hip_fail(c, e, "adaptive error estimate");
+        const double errn = (double)err_dev / atol;
+        if (!std::isfinite(errn)) {
+            c->sc_valid = false;
+            return fail(c, KUR_ENONFINITE, "non-finite local error estimate");
+        }
+        if (errn <= 1.0) {
+            // accept: the candidate becomes the state; sc of the current parity already holds
+            // its (sin, cos) and block partials
+            if ((e = hipMemcpyAsync(c->d_hi.p, hi2.p, TN, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
+                (e = hipMemcpyAsync(c->d_lo.p, lo2.p, TN, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
+                (e = hipMemcpyAsync(c->d_wind.p, wind2.p, 4 * (size_t)n, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+                return hip_fail(c, e, "adaptive accept");
+            t = h == t_end - t ? t_end : t + h;  // a step clamped to the end lands on it
+            ++acc;
+        } else {
+            ++rej;
+            c->sc_valid = false;  // the stages overwrote the (sin, cos) of the state
+        }
+        const double fac = errn == 0.0 ? 4.0 : std::min(4.0, std::max(0.2, 0.9 * std::pow(errn, -0.2)));
+        dt = h * fac;
+    }
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "adaptive sync");
+    out[0] = t;
+    out[1] = dt;
+    out[2] = (double)acc;
+    out[3] = (double)rej;
+    return KUR_OK;
+}
+
+extern "C" {
+
+kur_status kur_step_adaptive(kur_ctx *c, double t_end, double dt0, double atol, int64_t max_steps, double *out)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!out) return fail(c, KUR_EINVAL, "out must not be NULL");
+    if (!(std::isfinite(t_end) && t_end > 0.0) || !(std::isfinite(dt0) && dt0 > 0.0) || !(std::isfinite(atol) && atol > 0.0))
+        return fail(c, KUR_EINVAL, "t_end, dt0 and atol must be finite and positive");
+    if (max_steps < 1) return fail(c, KUR_EINVAL, "max_steps must be >= 1");
+    kur_status s = need_ready(c, true, true);
+    if (s != KUR_OK) return s;
+    return c->esz == 4 ? adaptive_impl<float>(c, t_end, dt0, atol, max_steps, out)
+                       : adaptive_impl<double>(c, t_end, dt0, atol, max_steps, out);
+}
+
 kur_status kur_get_phases(kur_ctx *c, double *theta, int wrapped)
 {
     if (!c) return KUR_EINVAL;

@@ -46,40 +46,18 @@ template <typename T> __device__ __forceinline__ void two_sum(T a, T b, T &s, T 
     e = (a - (s - bb)) + (b - bb);
 }
 
-// Bookkeeping of one oscillator given its stage derivative k, for classical RK4
-// (y_{n+1} = y_n + dt/6 (k1 + 2 k2 + 2 k3 + k4)) and for the implicit midpoint rule
-// (y_{n+1} = y_n + dt F((y_n + y_{n+1}) / 2), solved by fixed-point iteration on the midpoint).
-//   stages 1-3   RK4: accumulate k1 + 2 k2 + 2 k3 in *ksum and return the next stage input
-//                (theta + dt/2 k1, theta + dt/2 k2, theta + dt k3);
-//   stage 4      RK4: advance the phase by dt/6 (ksum + k4);
-//   stage 5      midpoint iterate: return theta + dt/2 k (the phase is not changed);
-//   stage 6      midpoint final: advance the phase by dt k.
-// The advance adds to hi + lo with error-free sums when `compensate`, wraps the result to
-// [-pi, pi) (the whole turns go to *wind), stores it and returns the new phase.
+// Advance one oscillator's phase (th + lo, winding wind) by delta: with error-free sums when
+// `compensate`, then wrapped to [-pi, pi) (the whole turns go to the winding count). Writes
+// the new (hi, lo, wind) and returns the new hi.
 template <typename T>
-__device__ __forceinline__ T rk4_stage(int stage, T k, T dt, T half_dt, T dt6, int compensate, T *ksum, T *hi_p,
-                                       T *lo_p, int32_t *wind_p)
+__device__ __forceinline__ T phase_advance(T th, T lo_in, int32_t wind_in, T delta, int compensate, T *hi_p, T *lo_p,
+                                           int32_t *wind_p)
 {
-    const T th = *hi_p;
-    if (stage == 1) {
-        *ksum = k;
-        return th + half_dt * k;
-    }
-    if (stage == 2) {
-        *ksum += T(2) * k;
-        return th + half_dt * k;
-    }
-    if (stage == 3) {
-        *ksum += T(2) * k;
-        return th + dt * k;
-    }
-    if (stage == 5) return th + half_dt * k;
-    const T delta = stage == 6 ? dt * k : dt6 * (*ksum + k);
     T hi, lo;
-    int wd = *wind_p;
+    int wd = wind_in;
     if (compensate) {
         T d1, e1, s, e2;
-        two_sum(delta, *lo_p, d1, e1);
+        two_sum(delta, lo_in, d1, e1);
         two_sum(th, d1, s, e2);
         hi = s;
         lo = e1 + e2;
@@ -99,6 +77,37 @@ __device__ __forceinline__ T rk4_stage(int stage, T k, T dt, T half_dt, T dt6, i
     *lo_p = e3;
     *wind_p = wd;
     return s2;
+}
+
+// Bookkeeping of one oscillator given its stage derivative k, for classical RK4
+// (y_{n+1} = y_n + dt/6 (k1 + 2 k2 + 2 k3 + k4)) and for the implicit midpoint rule
+// (y_{n+1} = y_n + dt F((y_n + y_{n+1}) / 2), solved by fixed-point iteration on the midpoint).
+//   stages 1-3   RK4: accumulate k1 + 2 k2 + 2 k3 in *ksum and return the next stage input
+//                (theta + dt/2 k1, theta + dt/2 k2, theta + dt k3);
+//   stage 4      RK4: advance the phase by dt/6 (ksum + k4);
+//   stage 5      midpoint iterate: return theta + dt/2 k (the phase is not changed);
+//   stage 6      midpoint final: advance the phase by dt k.
+// The advance is phase_advance in place.
+template <typename T>
+__device__ __forceinline__ T rk4_stage(int stage, T k, T dt, T half_dt, T dt6, int compensate, T *ksum, T *hi_p,
+                                       T *lo_p, int32_t *wind_p)
+{
+    const T th = *hi_p;
+    if (stage == 1) {
+        *ksum = k;
+        return th + half_dt * k;
+    }
+    if (stage == 2) {
+        *ksum += T(2) * k;
+        return th + half_dt * k;
+    }
+    if (stage == 3) {
+        *ksum += T(2) * k;
+        return th + dt * k;
+    }
+    if (stage == 5) return th + half_dt * k;
+    const T delta = stage == 6 ? dt * k : dt6 * (*ksum + k);
+    return phase_advance<T>(th, *lo_p, *wind_p, delta, compensate, hi_p, lo_p, wind_p);
 }
 
 }  // namespace kur

@@ -463,6 +463,96 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     if (a.stage > 0) block_sum_store<T2, NT>(part, L.red, reinterpret_cast<T2 *>(a.part_out) + tile_id);
 }
 
+// Maximum over the workgroup of a non-negative value, stored to *out by thread 0.
+template <typename T, int NT>
+__device__ __forceinline__ void block_max_store(T v, T *red, T *out)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T m = red[0];
+        for (int i = 1; i < NT / 64; ++i) m = fmax(m, red[i]);
+        *out = m;
+    }
+}
+
+// One stage of the embedded Runge-Kutta pair (see EmbArgs); the gathers are those of k_rows.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_rows_emb(DevGraph g, EmbArgs<T> a)
+{
+    using T2 = typename V2<T>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    TileLds<T2, NT> L(smem, g.W, g.tile_rows);
+    const int tile_id = g.order[blockIdx.x];
+    if (tile_id < 0) return;  // empty slot of the XCD-aware launch order
+    const Tile tl = g.tiles[tile_id];
+    const BlkInfo bi = g.blk[tl.block];
+    const int nrows = tl.r1 - tl.r0;
+    const int rowbase = bi.row0 + tl.r0;
+    const T2 *__restrict__ sc_in = reinterpret_cast<const T2 *>(a.sc_in);
+
+    tile_gather<T, NT, 1>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L);
+
+    T2 base = vzero<T2>();
+    if (bi.mode) base = L.red[NT / 64];
+    T2 part = vzero<T2>();
+    T emax = T(0);
+    const bool last = a.stage == a.nstages;
+    for (int r = threadIdx.x; r < nrows; r += NT) {
+        const int m = rowbase + r;
+        const T2 scm = sc_in[m];
+        const T As = base.x + L.acc[r].x;
+        const T Ac = base.y + L.acc[r].y;
+        const T scale = a.K * (a.unit ? a.unit[m] : a.inv_n);
+        const T k = a.omega[m] + scale * (As * scm.y - Ac * scm.x);
+        a.kbuf[(int64_t)(a.stage - 1) * a.n + m] = k;
+        // sum_{j <= stage} coef[j] k_j in increasing j
+        T acc = T(0);
+        for (int j = 0; j + 1 < a.stage; ++j) acc += a.coef[j] * a.kbuf[(int64_t)j * a.n + m];
+        acc += a.coef[a.stage - 1] * k;
+        T y;
+        if (!last) {
+            y = a.hi[m] + a.dt * acc;
+        } else {
+            T est = T(0);
+            for (int j = 0; j + 1 < a.stage; ++j) est += a.coef2[j] * a.kbuf[(int64_t)j * a.n + m];
+            est += a.coef2[a.stage - 1] * k;
+            emax = fmax(emax, fabs(a.dt * est));
+            y = phase_advance<T>(a.hi[m], a.lo[m], a.wind[m], a.dt * acc, a.compensate, a.hi_new + m, a.lo_new + m,
+                                 a.wind_new + m);
+        }
+        T s, c;
+        dev_sincos<T>(y, &s, &c);
+        T2 v;
+        v.x = s;
+        v.y = c;
+        reinterpret_cast<T2 *>(a.sc_out)[m] = v;
+        part.x += s;
+        part.y += c;
+    }
+    block_sum_store<T2, NT>(part, L.red, reinterpret_cast<T2 *>(a.part_out) + tile_id);
+    if (last) block_max_store<T, NT>(emax, reinterpret_cast<T *>(&L.red[0]), a.err_part + tile_id);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_max_fold(int64_t n, const T *__restrict__ in, T *__restrict__ out)
+{
+    __shared__ T red[256];
+    T m = T(0);
+    for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, in[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
 // Discrete adjoint of one classical RK4 stage (reverse order 4, 3, 2, 1). With x_in holding
 // (s, c, w s, w c) at the stage state Y_i, w = K scale_m l_i, the gathers give (A s, A c, A ws,
 // A wc) and, for symmetric A,
@@ -741,6 +831,36 @@ hipError_t launch_rows(const DevGraph &g, int ntiles, const RowArgs<T> &a, int t
 }
 
 template <typename T>
+hipError_t launch_emb(const DevGraph &g, const EmbArgs<T> &a, int threads, hipStream_t st)
+{
+    if (g.nlaunch <= 0) return hipSuccess;
+    const size_t lds = rows_lds_bytes(sizeof(T), g.W, g.tile_rows, threads);
+    static bool attr_done[3] = {false, false, false};
+    const int slot = threads == 256 ? 0 : threads == 1024 ? 2 : 1;
+    if (!attr_done[slot]) {
+        const void *fn = threads == 256 ? reinterpret_cast<const void *>(&k_rows_emb<T, 256>)
+                         : threads == 1024 ? reinterpret_cast<const void *>(&k_rows_emb<T, 1024>)
+                                           : reinterpret_cast<const void *>(&k_rows_emb<T, 512>);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+        if (e != hipSuccess) return e;
+        attr_done[slot] = true;
+    }
+    switch (threads) {
+    case 256: hipLaunchKernelGGL((k_rows_emb<T, 256>), dim3(g.nlaunch), dim3(256), lds, st, g, a); break;
+    case 1024: hipLaunchKernelGGL((k_rows_emb<T, 1024>), dim3(g.nlaunch), dim3(1024), lds, st, g, a); break;
+    default: hipLaunchKernelGGL((k_rows_emb<T, 512>), dim3(g.nlaunch), dim3(512), lds, st, g, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_max_fold(int64_t n, const T *in, T *out, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_max_fold<T>), dim3(1), dim3(256), 0, st, n, in, out);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_vjp(const DevGraph &g, int ntiles, const VjpArgs<T> &a, int threads, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
@@ -823,6 +943,10 @@ template hipError_t launch_vjp<float>(const DevGraph &, int, const VjpArgs<float
 template hipError_t launch_vjp<double>(const DevGraph &, int, const VjpArgs<double> &, int, hipStream_t);
 template hipError_t launch_vjp_init<float>(const DevGraph &, int, const VjpArgs<float> &, int, hipStream_t);
 template hipError_t launch_vjp_init<double>(const DevGraph &, int, const VjpArgs<double> &, int, hipStream_t);
+template hipError_t launch_emb<float>(const DevGraph &, const EmbArgs<float> &, int, hipStream_t);
+template hipError_t launch_emb<double>(const DevGraph &, const EmbArgs<double> &, int, hipStream_t);
+template hipError_t launch_max_fold<float>(int64_t, const float *, float *, hipStream_t);
+template hipError_t launch_max_fold<double>(int64_t, const double *, double *, hipStream_t);
 template hipError_t launch_diag<float>(int64_t, const void *, const void *, const int32_t *, const void *,
                                        const void *, const void *, double, double *, double *, hipStream_t);
 template hipError_t launch_diag<double>(int64_t, const void *, const void *, const int32_t *, const void *,

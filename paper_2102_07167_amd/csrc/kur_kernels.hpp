@@ -44,6 +44,41 @@ struct RowArgs {
     void *part_out;
 };
 
+// Arguments of one stage of the embedded Runge-Kutta pair (variable step size). Stage i of s
+// stores k_i = F(Y_i) and forms Y_{i+1} = theta + dt sum_{j <= i} coef[j] k_j; the last stage
+// forms the candidate theta + dt sum_j coef[j] k_j (coef = the propagated weights) into the
+// *_new arrays and the per-tile maximum of |dt sum_j coef2[j] k_j| (coef2 = the difference of
+// the two weight rows, the local error estimate).
+template <typename T>
+struct EmbArgs {
+    int stage;          // 1..nstages
+    int nstages;
+    int compensate;
+    T dt;
+    T K, inv_n;
+    const T *unit;
+    const T *omega;
+    const T *hi, *lo;         // start of the step (read only)
+    const int32_t *wind;
+    T *hi_new, *lo_new;       // candidate (last stage)
+    int32_t *wind_new;
+    T *kbuf;                  // nstages x n stage derivatives
+    int64_t n;
+    T coef[8];
+    T coef2[8];
+    T *err_part;              // per tile (last stage)
+    const void *sc_in;
+    void *sc_out;
+    const void *part_in;
+    void *part_out;
+};
+
+template <typename T>
+hipError_t launch_emb(const DevGraph &g, const EmbArgs<T> &a, int threads, hipStream_t st);
+// out[0] = max of in[0..n) (n >= 1), one workgroup
+template <typename T>
+hipError_t launch_max_fold(int64_t n, const T *in, T *out, hipStream_t st);
+
 // Arguments of one reverse RK4 stage (Jacobian-transpose product and adjoint bookkeeping).
 template <typename T>
 struct VjpArgs {

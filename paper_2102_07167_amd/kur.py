@@ -76,6 +76,7 @@ SIGNATURES = {
     "kur_ens_autotune_csr": (ST, [P, I64, P, P, P, I32, I32, P]),
     "kur_diagnostics": (ST, [P, P]),
     "kur_step_midpoint": (ST, [P, F64, I64, I32, I64, P, P]),
+    "kur_step_adaptive": (ST, [P, F64, F64, F64, I64, P]),
     "kur_eval_rhs_dev": (ST, [P, P, P]),
     "kur_get_phases_dev": (ST, [P, P]),
 }
@@ -325,6 +326,12 @@ class Kuramoto:
             return r, psi
         self._chk(self._L.kur_step_midpoint(self._h, float(dt), int(nsteps), int(iters), 0, None, None))
         return None, None
+
+    def step_adaptive(self, t_end: float, dt0: float, atol: float, max_steps: int = 1000000) -> dict:
+        """Variable-step embedded RK pair over t_end (kur_step_adaptive)."""
+        out = np.zeros(4)
+        self._chk(self._L.kur_step_adaptive(self._h, float(t_end), float(dt0), float(atol), int(max_steps), _ptr(out)))
+        return {"t": out[0], "dt": out[1], "accepted": int(out[2]), "rejected": int(out[3])}
 
     def diagnostics(self) -> dict:
         """Potential V, mean unwrapped phase and mean omega of the current state (kur_diagnostics)."""

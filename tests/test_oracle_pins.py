@@ -383,3 +383,46 @@ def test_midpoint_conserves_the_mean():
     for iters in (1, 3, 8):
         y, _, _ = oracle.midpoint(g, om, 2.0, th, 0.03, 50, iters)
         assert abs(np.mean(y - th - 1.5 * om)) < 1e-13
+
+
+# ---------------------------------------------------------------------------------------------
+# variable-step embedded Runge-Kutta pair (the variable stepsize fourth-order method of Sec. 2)
+
+def test_rkf45_tableau_order_conditions():
+    """The propagated weights satisfy the 8 conditions of order 4, the estimating weights the
+    17 of order 5 (rooted trees up to order 5), with c_i = sum_j a_ij."""
+    a, b4, b5 = oracle.rkf45_tableau()
+    c = a.sum(axis=1)
+    ac = a @ c
+    ac2 = a @ c ** 2
+    aac = a @ ac
+    o4 = [(np.ones(6), 1.0), (c, 1 / 2), (c ** 2, 1 / 3), (ac, 1 / 6), (c ** 3, 1 / 4), (c * ac, 1 / 8),
+          (ac2, 1 / 12), (aac, 1 / 24)]
+    o5 = o4 + [(c ** 4, 1 / 5), (c ** 2 * ac, 1 / 10), (c * ac2, 1 / 15), (c * aac, 1 / 30), (ac ** 2, 1 / 20),
+               (a @ c ** 3, 1 / 20), (a @ (c * ac), 1 / 40), (a @ ac2, 1 / 60), (a @ aac, 1 / 120)]
+    for vec, val in o4:
+        assert abs(b4 @ vec - val) < 1e-14, val
+    for vec, val in o5:
+        assert abs(b5 @ vec - val) < 1e-14, val
+    # b4 is not of order 5 (the estimate is a genuine one)
+    assert abs(b4 @ c ** 4 - 1 / 5) > 1e-4
+    assert np.all(np.triu(a) == 0)
+
+
+def test_rkf45_exact_without_coupling_and_error_control():
+    g, om, th = _mid_setup(35)
+    # K = 0: theta(T) = theta0 + T omega exactly, with growing steps
+    y, st = oracle.rkf45(g, om, 0.0, th, 2.0, 0.01, 1e-8)
+    assert np.abs(y - (th + 2.0 * om)).max() < 1e-13 and st[0] == 2.0 and st[3] == 0 and st[2] < 10
+    # tighter tolerance, smaller error against a fine RK4 reference; rejections occur from a
+    # too large first step
+    ref, _, _ = oracle.rk4(g, om, 3.0, th, 1.0 / 2000, 2000)
+    errs = []
+    for atol in (1e-4, 1e-7, 1e-10):
+        y, st = oracle.rkf45(g, om, 3.0, th, 1.0, 0.5, atol)
+        assert st[0] == 1.0 and (atol > 1e-9 or st[3] >= 1)
+        errs.append(np.abs(y - ref).max())
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-8
+    # the linear invariant (symmetric A, uniform scaling)
+    y, _ = oracle.rkf45(g, om, 3.0, th, 1.0, 0.5, 1e-6)
+    assert abs(np.mean(y - th - om)) < 1e-13
