@@ -91,6 +91,7 @@ class Graph:
     uperm: np.ndarray | None = None       # planted index -> user index
     key: int = 0
     meta: dict = field(default_factory=dict)
+    weight: np.ndarray | None = None      # int32 value A_ml of every CSR entry (None: all 1)
 
     @property
     def nnz(self) -> int:
@@ -102,13 +103,14 @@ class Graph:
         """Dense uint8 adjacency (tiny graphs only)."""
         if self.n > 8192:
             raise ValueError("dense() is for small graphs")
-        A = np.zeros((self.n, self.n), dtype=np.uint8)
+        A = np.zeros((self.n, self.n), dtype=np.uint8 if self.weight is None else np.int32)
         if self.complete:
             A[:] = 1
             np.fill_diagonal(A, 0)
             return A
         for m in range(self.n):
-            A[m, self.col[self.row_ptr[m]:self.row_ptr[m + 1]]] = 1
+            sl = slice(self.row_ptr[m], self.row_ptr[m + 1])
+            A[m, self.col[sl]] = 1 if self.weight is None else self.weight[sl]
         return A
 
 
@@ -177,12 +179,48 @@ def random_dense(n: int, p_one: float, rng: np.random.Generator, symmetric: bool
 
 
 def from_dense(A: np.ndarray, labels: np.ndarray | None = None) -> Graph:
+    """CSR of the nonzero entries of A; integer values other than 0/1 are kept as weights."""
     n = A.shape[0]
     rows, cols = np.nonzero(A)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(np.bincount(rows, minlength=n), out=row_ptr[1:])
+    vals = A[rows, cols]
+    weight = None if np.all(vals == 1) else vals.astype(np.int32)
     return Graph(n=n, labels=np.zeros(n, np.int32) if labels is None else labels.astype(np.int32),
-                 row_ptr=row_ptr, col=cols.astype(np.int32))
+                 row_ptr=row_ptr, col=cols.astype(np.int32), weight=weight)
+
+
+def weighted_sbm(sizes, prevalent, exception: float, J: int, p_out: float, rng: np.random.Generator,
+                 uperm: np.ndarray | None = None) -> Graph:
+    """Symmetric integer-weighted block model (small graphs, dense construction): inside block c
+    every pair takes the value prevalent[c] with probability 1 - exception, else a value drawn
+    uniformly from {0..J} without prevalent[c]; pairs across blocks are 0, or with probability
+    p_out a value drawn uniformly from {1..J}. uperm[p]: user index of planted node p."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    n = int(sizes.sum())
+    lab = np.repeat(np.arange(len(sizes)), sizes)
+    A = np.zeros((n, n), dtype=np.int32)
+    iu = np.triu_indices(n, 1)
+    same = lab[iu[0]] == lab[iu[1]]
+    vals = np.zeros(len(iu[0]), dtype=np.int32)
+    pv = np.asarray(prevalent)[lab[iu[0]]]
+    exc = rng.random(len(vals)) < exception
+    other = rng.integers(0, J, len(vals))  # uniform over {0..J} without the prevalent value
+    other = other + (other >= pv)
+    vals[same] = np.where(exc, other, pv)[same]
+    cross = ~same & (rng.random(len(vals)) < p_out)
+    vals[cross] = rng.integers(1, J + 1, int(cross.sum()))
+    A[iu] = vals
+    A = A + A.T
+    if uperm is not None:
+        B = np.zeros_like(A)
+        B[np.ix_(uperm, uperm)] = A
+        A = B
+        labels = np.empty(n, dtype=np.int32)
+        labels[uperm] = lab
+    else:
+        labels = lab.astype(np.int32)
+    return from_dense(A, labels)
 
 
 # ------------------------------------------------------------------------------------------------

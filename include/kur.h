@@ -123,6 +123,20 @@ kur_status kur_set_graph_csr(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, co
                              const int32_t *labels);
 
 /*
+ * Integer-weighted graph (Introduction, generalisations: coefficients in a finite set {0..J},
+ * one value prevalent per block): as kur_set_graph_csr, with weight[e] in [0, 255] the value
+ * A_ml of entry e (0: absent). Every community block is split into 0/1 layers
+ * A = sum_{t >= 1} [A >= t]; its prevalent value v (the most frequent value among its
+ * off-diagonal pairs, zeros included) is the number of layers evaluated with the localised
+ * order parameters (lists of zeros, eq. KuramotoGraphApproach); the layers above v store their
+ * ones. An entry with value a != v thus costs |a - v| list entries. Edges between blocks are
+ * summed straightforwardly, listed once per unit of weight. Non-uniform scaling uses the
+ * weighted row sums. The adjoint requires a symmetric weighted A.
+ */
+kur_status kur_set_graph_csr_w(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                               const int32_t *weight, const int32_t *labels);
+
+/*
  * Set the graph already in block form (the expert path; no community search is done).
  *   n, nb        nodes and diagonal blocks; block b owns block-order rows
  *                [block_ptr[b], block_ptr[b+1]), block sizes 1..65535
@@ -179,8 +193,8 @@ kur_status kur_get_perm(const kur_ctx *ctx, int32_t *perm);
 
 /*
  * Introspection of the host preprocessing, for host-only contexts (device = -1), which keep
- * the built layout in host memory. kur_get_blocks: block_ptr (nb+1) and mode (nb; 1 = list of
- * zeros). kur_get_row_lists: for block-order row `row`, the block-local columns stored in its
+ * the built layout in host memory. kur_get_blocks: block_ptr (nb+1) and mode (nb; the number of
+ * 0/1 layers stored as lists of zeros: 1 = list of zeros for a 0/1 block). kur_get_row_lists: for block-order row `row`, the block-local columns stored in its
  * list (ascending; zeros for a dense block, ones for a sparse one) and its inter-block columns
  * (block order, ascending). Pass NULL arrays to query the counts; otherwise the arrays must
  * hold *nlist and *ninter entries (the counts are written back). Device contexts return
@@ -189,6 +203,10 @@ kur_status kur_get_perm(const kur_ctx *ctx, int32_t *perm);
 kur_status kur_get_blocks(const kur_ctx *ctx, int64_t *block_ptr, uint8_t *mode);
 kur_status kur_get_row_lists(const kur_ctx *ctx, int64_t row, int32_t *list, int64_t *nlist, int32_t *inter,
                              int64_t *ninter);
+/* Host-only contexts: the stored list entries of block-order row `row` with their 0/1 layer
+ * (1-based; layers up to the block's mode hold zeros, the others ones): cols (block-local) and
+ * layer hold *count entries on entry (both NULL: count only); *count receives the count. */
+kur_status kur_get_row_layers(const kur_ctx *ctx, int64_t row, int32_t *cols, int32_t *layer, int64_t *count);
 
 /* Intrinsic frequencies omega (n, user order, finite) and coupling constant K (finite). */
 kur_status kur_set_params(kur_ctx *ctx, const double *omega, double K);

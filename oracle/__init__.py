@@ -51,25 +51,25 @@ def _load():
         lib = ctypes.CDLL(_SO)
         P, i64, f64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
         lib.orc_rhs.restype = None
-        lib.orc_rhs.argtypes = [i64, ci, P, P, ci, P, f64, P, P]
+        lib.orc_rhs.argtypes = [i64, ci, P, P, P, ci, P, f64, P, P]
         lib.orc_rhs_rows.restype = None
-        lib.orc_rhs_rows.argtypes = [i64, ci, P, P, ci, P, f64, P, i64, P, P]
+        lib.orc_rhs_rows.argtypes = [i64, ci, P, P, P, ci, P, f64, P, i64, P, P]
         lib.orc_order_parameter.restype = None
         lib.orc_order_parameter.argtypes = [i64, P, P, P]
         lib.orc_rk4.restype = ci
-        lib.orc_rk4.argtypes = [i64, ci, P, P, ci, P, f64, f64, i64, i64, P, P, P]
+        lib.orc_rk4.argtypes = [i64, ci, P, P, P, ci, P, f64, f64, i64, i64, P, P, P]
         lib.orc_rkf45.restype = ci
-        lib.orc_rkf45.argtypes = [i64, ci, P, P, ci, P, f64, f64, f64, f64, i64, P, P]
+        lib.orc_rkf45.argtypes = [i64, ci, P, P, P, ci, P, f64, f64, f64, f64, i64, P, P]
         lib.orc_rkf45_tableau.restype = None
         lib.orc_rkf45_tableau.argtypes = [P, P, P]
         lib.orc_midpoint.restype = ci
-        lib.orc_midpoint.argtypes = [i64, ci, P, P, ci, P, f64, f64, i64, ctypes.c_int32, i64, P, P, P]
+        lib.orc_midpoint.argtypes = [i64, ci, P, P, P, ci, P, f64, f64, i64, ctypes.c_int32, i64, P, P, P]
         lib.orc_vjp.restype = None
-        lib.orc_vjp.argtypes = [i64, ci, P, P, ci, f64, P, P, P]
+        lib.orc_vjp.argtypes = [i64, ci, P, P, P, ci, f64, P, P, P]
         lib.orc_adjoint_rk4.restype = ci
-        lib.orc_adjoint_rk4.argtypes = [i64, ci, P, P, ci, P, f64, f64, i64, P, P, P, P, P]
+        lib.orc_adjoint_rk4.argtypes = [i64, ci, P, P, P, ci, P, f64, f64, i64, P, P, P, P, P]
         lib.orc_potential.restype = f64
-        lib.orc_potential.argtypes = [i64, ci, P, P, ci, P, f64, P]
+        lib.orc_potential.argtypes = [i64, ci, P, P, P, ci, P, f64, P]
         _lib = lib
     return _lib
 
@@ -84,8 +84,9 @@ def _f64(x):
 
 def _g(graph):
     if graph.complete:
-        return graph.n, 1, None, None
-    return graph.n, 0, _p(graph.row_ptr), _p(graph.col)
+        return graph.n, 1, None, None, None
+    w = getattr(graph, "weight", None)
+    return graph.n, 0, _p(graph.row_ptr), _p(graph.col), None if w is None else _p(w)
 
 
 def rhs(graph, omega, K, theta, scaling: int = 0) -> np.ndarray:

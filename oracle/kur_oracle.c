@@ -31,17 +31,26 @@ typedef struct {
     int complete;            /* 1: all pairs l != m coupled; row_ptr/col unused */
     const int64_t *row_ptr;  /* CSR, n+1 */
     const int32_t *col;      /* neighbours of row m: col[row_ptr[m] .. row_ptr[m+1]) */
-    int scaling;             /* 0: uniform K/N; 1: K/deg_m */
+    const int32_t *w;        /* integer value A_ml of every entry (NULL: all 1) */
+    int scaling;             /* 0: uniform K/N; 1: K/deg_m with deg_m = sum_l A_ml */
 } orc_graph;
+
+static double weight_of(const orc_graph *g, int64_t e) { return g->w ? (double)g->w[e] : 1.0; }
 
 static double row_scale(const orc_graph *g, int64_t m)
 {
     if (g->scaling == 0) return 1.0 / (double)g->n;
-    int64_t deg = g->complete ? g->n - 1 : g->row_ptr[m + 1] - g->row_ptr[m];
-    return deg > 0 ? 1.0 / (double)deg : 0.0;
+    double deg = 0.0;
+    if (g->complete) {
+        deg = (double)(g->n - 1);
+    } else {
+        for (int64_t e = g->row_ptr[m]; e < g->row_ptr[m + 1]; ++e)
+            if (g->col[e] != m) deg += weight_of(g, e);
+    }
+    return deg > 0 ? 1.0 / deg : 0.0;
 }
 
-/* sum_{l : A_ml = 1} sin(theta_l - theta_m), straightforward summation (Sec. 3, eq.
+/* sum_l A_ml sin(theta_l - theta_m), straightforward summation (Sec. 3, eq.
  * KuramotoGraphApproach, first case, applied to the whole row) */
 static double coupling_sum(const orc_graph *g, const double *theta, int64_t m)
 {
@@ -51,7 +60,7 @@ static double coupling_sum(const orc_graph *g, const double *theta, int64_t m)
             if (l != m) acc += sin(theta[l] - theta[m]);
     } else {
         for (int64_t e = g->row_ptr[m]; e < g->row_ptr[m + 1]; ++e)
-            acc += sin(theta[g->col[e]] - theta[m]);
+            acc += weight_of(g, e) * sin(theta[g->col[e]] - theta[m]);
     }
     return acc;
 }
@@ -64,19 +73,19 @@ static void rhs(const orc_graph *g, const double *omega, double K, const double 
 }
 
 /* F(theta) for all rows */
-void orc_rhs(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, int scaling,
+void orc_rhs(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, const int32_t *weight, int scaling,
              const double *omega, double K, const double *theta, double *out)
 {
-    orc_graph g = {n, complete, row_ptr, col, scaling};
+    orc_graph g = {n, complete, row_ptr, col, weight, scaling};
     rhs(&g, omega, K, theta, out);
 }
 
 /* F(theta) for a subset of rows: out[i] = F_{rows[i]}(theta) */
-void orc_rhs_rows(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, int scaling,
+void orc_rhs_rows(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, const int32_t *weight, int scaling,
                   const double *omega, double K, const double *theta, int64_t nrows,
                   const int64_t *rows, double *out)
 {
-    orc_graph g = {n, complete, row_ptr, col, scaling};
+    orc_graph g = {n, complete, row_ptr, col, weight, scaling};
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < nrows; ++i) {
         int64_t m = rows[i];
@@ -120,11 +129,11 @@ static void rk4_step(const orc_graph *g, const double *omega, double K, double d
  * If r_every > 0, r_out/psi_out (may be NULL) receive r and psi at steps 0, r_every, 2 r_every,
  * ..., i.e. nsteps / r_every + 1 values. Returns 0, or -1 on allocation failure.
  */
-int orc_rk4(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, int scaling,
+int orc_rk4(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, const int32_t *weight, int scaling,
             const double *omega, double K, double dt, int64_t nsteps, int64_t r_every,
             double *theta, double *r_out, double *psi_out)
 {
-    orc_graph g = {n, complete, row_ptr, col, scaling};
+    orc_graph g = {n, complete, row_ptr, col, weight, scaling};
     double *work = (double *)malloc(sizeof(double) * 5 * (size_t)n);
     if (!work) return -1;
     int64_t k = 0;
@@ -148,11 +157,11 @@ int orc_rk4(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col,
  * order the iteration is defined: Y = theta_n; repeat iters - 1 times Y = theta_n + dt/2 F(Y);
  * then theta_{n+1} = theta_n + dt F(Y). Samples of (r, psi) as in orc_rk4.
  */
-int orc_midpoint(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, int scaling,
+int orc_midpoint(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, const int32_t *weight, int scaling,
                  const double *omega, double K, double dt, int64_t nsteps, int32_t iters, int64_t r_every,
                  double *theta, double *r_out, double *psi_out)
 {
-    orc_graph g = {n, complete, row_ptr, col, scaling};
+    orc_graph g = {n, complete, row_ptr, col, weight, scaling};
     double *y = (double *)malloc(sizeof(double) * 2 * (size_t)n);
     if (!y) return -1;
     double *f = y + n;
@@ -209,11 +218,11 @@ void orc_rkf45_tableau(double *a, double *b4, double *b5)
  * (theta += h sum_j b4_j k_j, t += h); next dt = h min(4, max(0.2, 0.9 (e/atol)^(-1/5))), 4 when
  * e = 0. stats = (t reached, next dt, accepted, rejected).
  */
-int orc_rkf45(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, int scaling,
+int orc_rkf45(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, const int32_t *weight, int scaling,
               const double *omega, double K, double t_end, double dt0, double atol, int64_t max_steps,
               double *theta, double *stats)
 {
-    orc_graph g = {n, complete, row_ptr, col, scaling};
+    orc_graph g = {n, complete, row_ptr, col, weight, scaling};
     double *k = (double *)malloc(sizeof(double) * 7 * (size_t)n);
     if (!k) return -1;
     double *y = k + 6 * n;
@@ -272,10 +281,10 @@ int orc_rkf45(int64_t n, int complete, const int64_t *row_ptr, const int32_t *co
  * (s_m the row scale), obtained by differentiating eq. KuramotoGraph term by term. Computed by
  * scattering every row's contributions, so an asymmetric A needs no transpose.
  */
-void orc_vjp(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, int scaling,
+void orc_vjp(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, const int32_t *weight, int scaling,
              double K, const double *theta, const double *lam, double *out)
 {
-    orc_graph g = {n, complete, row_ptr, col, scaling};
+    orc_graph g = {n, complete, row_ptr, col, weight, scaling};
     memset(out, 0, sizeof(double) * (size_t)n);
     for (int64_t m = 0; m < n; ++m) {
         double w = K * row_scale(&g, m) * lam[m];
@@ -290,7 +299,7 @@ void orc_vjp(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col
         } else {
             for (int64_t e = row_ptr[m]; e < row_ptr[m + 1]; ++e) {
                 int64_t l = col[e];
-                double c = cos(theta[l] - theta[m]);
+                double c = weight_of(&g, e) * cos(theta[l] - theta[m]);
                 out[l] += w * c;
                 out[m] -= w * c;
             }
@@ -319,11 +328,11 @@ static void dfdk(const orc_graph *g, const double *theta, double *out)
  *   dL/dtheta = lam + mu1 + mu2 + mu3 + mu4,  dL/domega += sum_i l_i,  dL/dK += sum_i <l_i, dF/dK(Y_i)>.
  * The whole forward trajectory is stored ((nsteps+1) n doubles).
  */
-int orc_adjoint_rk4(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, int scaling,
+int orc_adjoint_rk4(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, const int32_t *weight, int scaling,
                     const double *omega, double K, double dt, int64_t nsteps, const double *theta0,
                     const double *dl_dthetaT, double *g_theta0, double *g_omega, double *g_K)
 {
-    orc_graph g = {n, complete, row_ptr, col, scaling};
+    orc_graph g = {n, complete, row_ptr, col, weight, scaling};
     size_t N = (size_t)n;
     double *traj = (double *)malloc(sizeof(double) * N * (size_t)(nsteps + 1));
     double *work = (double *)malloc(sizeof(double) * 14 * N);
@@ -356,7 +365,7 @@ int orc_adjoint_rk4(int64_t n, int complete, const int64_t *row_ptr, const int32
         memset(mu_prev, 0, sizeof(double) * N);
         for (int i = 3; i >= 0; --i) {
             for (size_t m = 0; m < N; ++m) l[m] = bl[i] * dt * lam[m] + cm[i] * dt * mu_prev[m];
-            orc_vjp(n, complete, row_ptr, col, scaling, K, Ys[i], l, mu);
+            orc_vjp(n, complete, row_ptr, col, weight, scaling, K, Ys[i], l, mu);
             dfdk(&g, Ys[i], gk);
             for (size_t m = 0; m < N; ++m) {
                 g_omega[m] += l[m];
@@ -379,10 +388,10 @@ int orc_adjoint_rk4(int64_t n, int complete, const int64_t *row_ptr, const int32
  *   V = -omega^T theta + K/2 sum_{l,m} Ascaled_ml (1 - cos(theta_l - theta_m))
  * evaluated term by term.
  */
-double orc_potential(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, int scaling,
+double orc_potential(int64_t n, int complete, const int64_t *row_ptr, const int32_t *col, const int32_t *weight, int scaling,
                      const double *omega, double K, const double *theta)
 {
-    orc_graph g = {n, complete, row_ptr, col, scaling};
+    orc_graph g = {n, complete, row_ptr, col, weight, scaling};
     double lin = 0.0, pair = 0.0;
     for (int64_t m = 0; m < n; ++m) lin += omega[m] * theta[m];
     for (int64_t m = 0; m < n; ++m) {
@@ -391,7 +400,8 @@ double orc_potential(int64_t n, int complete, const int64_t *row_ptr, const int3
             for (int64_t l = 0; l < n; ++l)
                 if (l != m) acc += 1.0 - cos(theta[l] - theta[m]);
         } else {
-            for (int64_t e = row_ptr[m]; e < row_ptr[m + 1]; ++e) acc += 1.0 - cos(theta[col[e]] - theta[m]);
+            for (int64_t e = row_ptr[m]; e < row_ptr[m + 1]; ++e)
+                acc += weight_of(&g, e) * (1.0 - cos(theta[col[e]] - theta[m]));
         }
         pair += rs * acc;
     }

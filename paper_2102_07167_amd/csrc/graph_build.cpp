@@ -123,6 +123,7 @@ std::string finish(BlockGraph &g, const std::vector<int32_t> &block_of_row, cons
     int64_t tot_segs = 0;
     for (auto &b : g.blk) {
         b.nchunk = (b.size + W - 1) / W;
+        b.nlayer = 1;
         b.segbase = tot_segs;
         tot_segs += (int64_t)b.nchunk * b.size;
     }
@@ -381,6 +382,7 @@ std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &g)
     b.row0 = 0;
     b.size = (int32_t)n;
     b.nchunk = (int32_t)((n + opt.W - 1) / opt.W);
+    b.nlayer = 1;
     b.mode = n >= 2 ? 1 : 0;
     b.segbase = 0;
     g.blk.push_back(b);
@@ -603,6 +605,177 @@ std::string build_from_csr(int64_t n, const int64_t *row_ptr, const int32_t *col
     msg = finish(g, block_of_row, src, nullptr, opt);
     g.symmetric = symmetric;
     return msg;
+}
+
+std::string build_from_csr_w(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                             const int32_t *labels, const BuildOptions &opt, BlockGraph &g)
+{
+    std::string msg = validate_csr(n, row_ptr, col, labels);
+    if (!msg.empty()) return msg;
+    const int64_t nnz = row_ptr[n];
+    if (nnz > 0 && !weight) return "weight must not be NULL";
+    for (int64_t e = 0; e < nnz; ++e)
+        if (weight[e] < 0 || weight[e] > kMaxWeight) return "weights must be in [0, 255]";
+    const int32_t W = opt.W;
+    if ((int64_t)W * opt.esz2 > 65535) return "chunk too wide for 16-bit LDS byte offsets";
+    // symmetry of the weighted pattern (diagonal and zero weights ignored)
+    SymHash sym;
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        uint64_t f = 0, b = 0;
+        for (int64_t u = lo; u < hi; ++u)
+            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                if (col[e] == u || weight[e] == 0) continue;
+                f += pair_hash((uint64_t)u, (uint64_t)col[e]) * (uint64_t)weight[e];
+                b += pair_hash((uint64_t)col[e], (uint64_t)u) * (uint64_t)weight[e];
+            }
+        sym.add(f, b);
+    });
+    g = BlockGraph();
+    g.n = n;
+    g.W = W;
+    g.tile_rows = opt.tile_rows;
+    g.esz2 = opt.esz2;
+    std::vector<int32_t> node_at, block_of_row;
+    std::vector<int64_t> bptr;
+    g.nb = regroup_by_labels(n, labels, g.perm, node_at, block_of_row, bptr);
+    const int32_t nb = g.nb;
+    g.blk.resize(nb);
+    int32_t smax = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        g.blk[b] = BlkInfo{};
+        g.blk[b].row0 = (int32_t)bptr[b];
+        g.blk[b].size = (int32_t)(bptr[b + 1] - bptr[b]);
+        smax = std::max(smax, g.blk[b].size);
+    }
+    // per block: histogram of the weights of its off-diagonal pairs (duplicates rejected)
+    ErrFlag err;
+    std::vector<std::vector<int64_t>> hist(nb, std::vector<int64_t>(kMaxWeight + 1, 0));
+    std::vector<std::mutex> hist_mu(nb);
+    std::vector<int64_t> inter_row(n, 0), wdeg(n, 0);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        std::vector<uint8_t> val((size_t)smax + 1, 0);
+        std::vector<int64_t> h(kMaxWeight + 1, 0);
+        for (int64_t m = lo; m < hi && !err.bad.load(); ++m) {
+            const int32_t b = block_of_row[m];
+            const int64_t r0 = g.blk[b].row0, s = g.blk[b].size, u = node_at[m];
+            std::fill(h.begin(), h.end(), 0);
+            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                const int64_t pv = g.perm[col[e]];
+                const int32_t w = weight[e];
+                if (pv == m || w == 0) continue;
+                wdeg[m] += w;
+                if (pv < r0 || pv >= r0 + s) {
+                    inter_row[m] += w;  // listed once per unit of weight
+                    continue;
+                }
+                if (val[pv - r0]) err.set("duplicate column in a row");
+                val[pv - r0] = (uint8_t)w;
+                h[w]++;
+            }
+            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                const int64_t pv = g.perm[col[e]];
+                if (pv >= r0 && pv < r0 + s) val[pv - r0] = 0;
+            }
+            std::lock_guard<std::mutex> lk(hist_mu[b]);
+            for (int v = 1; v <= kMaxWeight; ++v) hist[b][v] += h[v];
+        }
+    });
+    if (err.bad) return err.msg;
+    // prevalent value (ties: the smaller) and layers per block
+    int64_t tot_segs = 0;
+    g.n_dense = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        BlkInfo &bi = g.blk[b];
+        const int64_t s = bi.size;
+        int64_t nz = 0;
+        int32_t jmax = 0;
+        for (int v = 1; v <= kMaxWeight; ++v)
+            if (hist[b][v]) {
+                nz += hist[b][v];
+                jmax = v;
+            }
+        hist[b][0] = s * (s - 1) - nz;
+        int32_t vb = 0;
+        for (int v = 1; v <= jmax; ++v)
+            if (hist[b][v] > hist[b][vb]) vb = v;
+        bi.mode = s >= 2 ? vb : 0;
+        bi.nlayer = std::max(1, jmax);
+        bi.nchunk = (int32_t)((s + W - 1) / W) * bi.nlayer;
+        bi.segbase = tot_segs;
+        tot_segs += (int64_t)bi.nchunk * s;
+        g.n_dense += bi.mode > 0;
+    }
+    // per segment (column chunk, layer) list lengths: layer t <= mode lists the columns (not the
+    // row itself) with weight < t, layer t > mode those with weight >= t
+    g.seg_ptr.assign(tot_segs + 1, 0);
+    std::vector<int64_t> unpadded(n, 0);
+    auto row_pass = [&](bool emit) {
+        parallel_for(n, [&](int64_t lo, int64_t hi) {
+            std::vector<uint8_t> val((size_t)smax + 1, 0);
+            std::vector<int32_t> tmp;
+            for (int64_t m = lo; m < hi; ++m) {
+                const BlkInfo &bi = g.blk[block_of_row[m]];
+                const int64_t r0 = bi.row0, s = bi.size, u = node_at[m], r = m - r0;
+                for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                    const int64_t pv = g.perm[col[e]];
+                    if (pv != m && weight[e] > 0 && pv >= r0 && pv < r0 + s) val[pv - r0] = (uint8_t)weight[e];
+                }
+                const int32_t ncc = bi.nchunk / bi.nlayer;
+                int64_t total = 0;
+                for (int32_t cc = 0; cc < ncc; ++cc) {
+                    const int64_t c0 = (int64_t)cc * W, c1 = std::min<int64_t>(s, c0 + W);
+                    for (int32_t t = 1; t <= bi.nlayer; ++t) {
+                        const int64_t idx = bi.segbase + (int64_t)((int64_t)cc * bi.nlayer + t - 1) * s + r;
+                        const bool zeros = t <= bi.mode;
+                        uint16_t *out = emit ? g.list.data() + g.seg_ptr[idx] : nullptr;
+                        int64_t k = 0;
+                        for (int64_t lc = c0; lc < c1; ++lc) {
+                            const bool listed = zeros ? (lc != r && val[lc] < t) : (val[lc] >= t);
+                            if (!listed) continue;
+                            if (emit) out[k] = (uint16_t)((lc - c0) * opt.esz2);
+                            ++k;
+                        }
+                        if (emit) {
+                            const int64_t padded = g.seg_ptr[idx + 1] - g.seg_ptr[idx];
+                            for (; k < padded; ++k) out[k] = (uint16_t)(W * opt.esz2);
+                        } else {
+                            g.seg_ptr[idx + 1] = round8(k);
+                            total += k;
+                        }
+                    }
+                }
+                if (!emit) unpadded[m] = total;
+                for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                    const int64_t pv = g.perm[col[e]];
+                    if (pv >= r0 && pv < r0 + s) val[pv - r0] = 0;
+                }
+                if (emit) {
+                    tmp.clear();
+                    for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                        const int64_t pv = g.perm[col[e]];
+                        if (pv != m && weight[e] > 0 && (pv < r0 || pv >= r0 + s))
+                            for (int32_t k = 0; k < weight[e]; ++k) tmp.push_back((int32_t)pv);
+                    }
+                    std::sort(tmp.begin(), tmp.end());
+                    std::copy(tmp.begin(), tmp.end(), g.inter_col.begin() + g.inter_ptr[m]);
+                }
+            }
+        });
+    };
+    row_pass(false);
+    for (int64_t i = 0; i < tot_segs; ++i) g.seg_ptr[i + 1] += g.seg_ptr[i];
+    g.list.assign((size_t)g.seg_ptr[tot_segs], (uint16_t)0);
+    g.list_unpadded = 0;
+    for (int64_t m = 0; m < n; ++m) g.list_unpadded += unpadded[m];
+    g.inter_ptr.assign(n + 1, 0);
+    for (int64_t m = 0; m < n; ++m) g.inter_ptr[m + 1] = g.inter_ptr[m] + inter_row[m];
+    g.inter_col.assign((size_t)g.inter_ptr[n], 0);
+    row_pass(true);
+    g.deg.assign(n, 0);
+    for (int64_t m = 0; m < n; ++m) g.deg[m] = (int32_t)std::min<int64_t>(wdeg[m], INT32_MAX);
+    g.symmetric = sym.fwd.load() == sym.bwd.load();
+    make_tiles(g, opt);
+    return "";
 }
 
 std::string build_from_blocks(int64_t n, int32_t nb, const int64_t *block_ptr, const uint8_t *mode,

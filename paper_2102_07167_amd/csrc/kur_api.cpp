@@ -625,6 +625,22 @@ kur_status kur_set_graph_csr(kur_ctx *c, int64_t n, const int64_t *row_ptr, cons
     return install_graph(c, g);
 }
 
+kur_status kur_set_graph_csr_w(kur_ctx *c, int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                               const int32_t *labels)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    BlockGraph g;
+    std::string msg;
+    try {
+        msg = build_from_csr_w(n, row_ptr, col, weight, labels, c->bopt, g);
+    } catch (const std::bad_alloc &) {
+        return fail(c, KUR_ENOMEM, "host allocation failed in graph preprocessing");
+    }
+    if (!msg.empty()) return fail(c, KUR_EINVAL, msg);
+    return install_graph(c, g);
+}
+
 kur_status kur_set_graph(kur_ctx *c, int64_t n, int32_t nb, const int64_t *block_ptr, const uint8_t *mode,
                          const int64_t *list_ptr, const uint16_t *list_col, const int64_t *inter_ptr,
                          const int32_t *inter_col, const int32_t *perm)
@@ -689,7 +705,7 @@ kur_status kur_get_row_lists(const kur_ctx *c, int64_t row, int32_t *list, int64
             if (g.list[e] == (uint16_t)(g.W * g.esz2)) continue;  // padding
             if (list) {
                 if (k >= *nlist) return KUR_EINVAL;
-                list[k] = (int32_t)ch * g.W + g.list[e] / g.esz2;
+                list[k] = (int32_t)(ch / bi.nlayer) * g.W + g.list[e] / g.esz2;
             }
             ++k;
         }
@@ -701,6 +717,33 @@ kur_status kur_get_row_lists(const kur_ctx *c, int64_t row, int32_t *list, int64
     }
     *nlist = k;
     *ninter = ni;
+    return KUR_OK;
+}
+
+kur_status kur_get_row_layers(const kur_ctx *c, int64_t row, int32_t *cols, int32_t *layer, int64_t *count)
+{
+    if (!c || !count) return KUR_EINVAL;
+    if (!c->has_graph || !c->host_only) return KUR_ESTATE;
+    const BlockGraph &g = c->host_graph;
+    if (row < 0 || row >= g.n) return KUR_EINVAL;
+    const int32_t b = (int32_t)(std::upper_bound(g.blk.begin(), g.blk.end(), (int32_t)row,
+                                                 [](int32_t r, const BlkInfo &x) { return r < x.row0; }) - g.blk.begin()) - 1;
+    const BlkInfo &bi = g.blk[b];
+    const int64_t r = row - bi.row0;
+    int64_t k = 0;
+    for (int32_t ch = 0; ch < bi.nchunk; ++ch) {
+        const int64_t idx = bi.segbase + (int64_t)ch * bi.size + r;
+        for (int64_t e = g.seg_ptr[idx]; e < g.seg_ptr[idx + 1]; ++e) {
+            if (g.list[e] == (uint16_t)(g.W * g.esz2)) continue;  // padding
+            if (cols || layer) {
+                if (k >= *count) return KUR_EINVAL;
+                if (cols) cols[k] = (int32_t)(ch / bi.nlayer) * g.W + g.list[e] / g.esz2;
+                if (layer) layer[k] = ch % bi.nlayer + 1;
+            }
+            ++k;
+        }
+    }
+    *count = k;
     return KUR_OK;
 }
 

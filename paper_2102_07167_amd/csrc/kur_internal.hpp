@@ -9,15 +9,22 @@
 namespace kur {
 
 // One diagonal block (a community after regrouping) as the kernels see it.
+// A weighted block is handled as a sum of 0/1 layers A = sum_{t >= 1} [A >= t]: layers t <= mode
+// are mostly ones and store their zeros (subtracted from the localised order parameters),
+// layers t > mode store their ones. A 0/1 block has one layer and mode 0 or 1.
 struct BlkInfo {
     int32_t row0;     // first block-order row
     int32_t size;     // rows (= columns) of the block
-    int32_t nchunk;   // column chunks of width W
-    int32_t mode;     // 1: list of zeros (localised order parameters), 0: list of ones
-    int64_t segbase;  // index into seg_ptr of (chunk 0, local row 0); chunk c, row r at
-                      // segbase + c * size + r
+    int32_t nchunk;   // segments per row: column chunks of width W times layers
+    int32_t mode;     // layers stored as lists of zeros (the block's prevalent value); the
+                      // localised order parameters enter with this factor
+    int64_t segbase;  // index into seg_ptr of (segment 0, local row 0); segment c, row r at
+                      // segbase + c * size + r; segment c is column chunk c / nlayer, layer
+                      // c % nlayer + 1
     int32_t tile0;    // first tile of this block (tiles of a block are contiguous)
     int32_t ntiles;
+    int32_t nlayer;   // 0/1 layers of the block (1 for a 0/1 block)
+    int32_t pad;
 };
 
 // One unit of work: rows [r0, r1) (block-local) of one block, G lanes per row (G == 0: each
@@ -80,6 +87,15 @@ std::string validate_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, 
 bool csr_symmetric(int64_t n, const int64_t *row_ptr, const int32_t *col);
 int32_t regroup_by_labels(int64_t n, const int32_t *labels, std::vector<int32_t> &perm, std::vector<int32_t> &node_at,
                           std::vector<int32_t> &block_of_row, std::vector<int64_t> &block_ptr);
+
+// Weighted adjacency: col as in build_from_csr, weight[e] in [0, kMaxWeight] the integer value
+// A_ml of entry e (0: absent). Every block is split into 0/1 layers A = sum_t [A >= t]; its
+// prevalent value (the most frequent value of its off-diagonal pairs, zeros included) is the
+// number of layers stored as zeros; edges between blocks are listed once per unit of weight.
+// deg holds the weighted row sums.
+constexpr int32_t kMaxWeight = 255;
+std::string build_from_csr_w(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                             const int32_t *labels, const BuildOptions &opt, BlockGraph &out);
 
 // The complete graph on n nodes: one dense block whose list of zeros is empty.
 std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &out);

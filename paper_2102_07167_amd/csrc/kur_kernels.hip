@@ -290,7 +290,8 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
     const int lane = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int ngrp = NT / G;
-    const T sign = bi.mode ? T(-1) : T(1);
+    const int nl = bi.nlayer;
+    int staged = -1;  // column chunk held in L.xs (uniform over the workgroup)
     const int ln = threadIdx.x & 63;
     // this wave's rows [ra, rb) in streaming mode (wave-uniform, kept in scalar registers)
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -301,10 +302,16 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
         const int64_t sb = bi.segbase + (int64_t)c * bi.size;
         const int64_t e0 = g.seg_ptr[sb + tl.r0], e1 = g.seg_ptr[sb + tl.r1];
         if (e0 == e1) continue;  // uniform over the workgroup
-        const int c0 = c * W;
+        const int cc = c / nl;   // column chunk; layer c % nl + 1
+        // a layer stored as zeros is subtracted from the localised order parameters
+        const T sign = c - cc * nl < bi.mode ? T(-1) : T(1);
+        const int c0 = cc * W;
         const int cw = min(W, bi.size - c0);
-        __syncthreads();  // previous chunk's gathers are done
-        for (int j = threadIdx.x; j < cw; j += NT) L.xs[j] = x_in[bi.row0 + c0 + j];
+        __syncthreads();  // previous segment's gathers are done
+        if (cc != staged) {
+            for (int j = threadIdx.x; j < cw; j += NT) L.xs[j] = x_in[bi.row0 + c0 + j];
+            staged = cc;
+        }
         // row starts of this chunk, in 8-entry vectors relative to the tile's first one
         for (int r = threadIdx.x; r <= nrows; r += NT) L.bnd[r] = (int)((g.seg_ptr[sb + tl.r0 + r] - e0) >> 3);
         __syncthreads();
@@ -431,7 +438,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     tile_gather<T, NT, 1>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L);
 
     T2 base = vzero<T2>();
-    if (bi.mode) base = L.red[NT / 64];
+    if (bi.mode) base = vscale(L.red[NT / 64], (T)bi.mode);
     T2 part = vzero<T2>();
     for (int r = threadIdx.x; r < nrows; r += NT) {
         const int m = rowbase + r;
@@ -442,10 +449,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         const T k = a.omega[m] + scale * (As * scm.y - Ac * scm.x);
         if (a.stage <= 0) {
             // 0: the derivative; -1: the row's coupling energy cos y (A cos y) + sin y (A sin y).
-            // The localised order parameters of a dense block include the row's own node, whose
-            // term cancels in the derivative but adds cos^2 y + sin^2 y here: it is removed.
+            // The localised order parameters of a dense block include the row's own node (with
+            // the block's factor), whose term cancels in the derivative but adds
+            // mode (cos^2 y + sin^2 y) here: it is removed.
             T en = scm.y * Ac + scm.x * As;
-            if (bi.mode) en -= scm.y * scm.y + scm.x * scm.x;
+            if (bi.mode) en -= (T)bi.mode * (scm.y * scm.y + scm.x * scm.x);
             a.kout[m] = a.stage == 0 ? k : en;
             continue;
         }
@@ -498,7 +506,7 @@ __global__ __launch_bounds__(NT) void k_rows_emb(DevGraph g, EmbArgs<T> a)
     tile_gather<T, NT, 1>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L);
 
     T2 base = vzero<T2>();
-    if (bi.mode) base = L.red[NT / 64];
+    if (bi.mode) base = vscale(L.red[NT / 64], (T)bi.mode);
     T2 part = vzero<T2>();
     T emax = T(0);
     const bool last = a.stage == a.nstages;
@@ -579,7 +587,7 @@ __global__ __launch_bounds__(NT) void k_vjp(DevGraph g, VjpArgs<T> a)
     tile_gather<T, NT, 2>(g, tl, bi, x_in, reinterpret_cast<const T4 *>(a.part_in), L);
 
     T4 base = vzero<T4>();
-    if (bi.mode) base = L.red[NT / 64];
+    if (bi.mode) base = vscale(L.red[NT / 64], (T)bi.mode);
     T4 part = vzero<T4>();
     double gk = 0.0;
     for (int r = threadIdx.x; r < nrows; r += NT) {

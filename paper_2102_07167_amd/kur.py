@@ -35,6 +35,8 @@ SIGNATURES = {
     "kur_set_option": (ST, [P, ctypes.c_char_p, F64]),
     "kur_set_graph_csr": (ST, [P, I64, P, P, P]),
     "kur_set_graph": (ST, [P, I64, I32, P, P, P, P, P, P, P]),
+    "kur_set_graph_csr_w": (ST, [P, I64, P, P, P, P]),
+    "kur_get_row_layers": (ST, [P, I64, P, P, P]),
     "kur_graph_info": (ST, [P, P]),
     "kur_get_perm": (ST, [P, P]),
     "kur_get_blocks": (ST, [P, P, P]),
@@ -181,12 +183,31 @@ class Kuramoto:
         self._chk(self._L.kur_set_graph_complete(self._h, int(n)))
         self.n = int(n)
 
+    def set_graph_csr_w(self, n, row_ptr, col, weight, labels):
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        weight = np.ascontiguousarray(weight, dtype=np.int32)
+        labels = np.ascontiguousarray(labels, dtype=np.int32)
+        self._chk(self._L.kur_set_graph_csr_w(self._h, int(n), _ptr(row_ptr), _ptr(col), _ptr(weight), _ptr(labels)))
+        self.n = int(n)
+
     def set_graph(self, graph):
-        """Any object with n, labels, row_ptr, col, complete (e.g. a generated graph)."""
+        """Any object with n, labels, row_ptr, col, complete and optionally integer weights."""
         if getattr(graph, "complete", False):
             self.set_graph_complete(graph.n)
+        elif getattr(graph, "weight", None) is not None:
+            self.set_graph_csr_w(graph.n, graph.row_ptr, graph.col, graph.weight, graph.labels)
         else:
             self.set_graph_csr(graph.n, graph.row_ptr, graph.col, graph.labels)
+
+    def row_layers(self, m: int):
+        """(block-local columns, layer) of the list entries of block-order row m (host-only)."""
+        cnt = I64(0)
+        self._chk(self._L.kur_get_row_layers(self._h, int(m), None, None, ctypes.byref(cnt)))
+        cols = np.empty(cnt.value, dtype=np.int32)
+        lay = np.empty(cnt.value, dtype=np.int32)
+        self._chk(self._L.kur_get_row_layers(self._h, int(m), _ptr(cols), _ptr(lay), ctypes.byref(cnt)))
+        return cols, lay
 
     def set_batch(self, instances):
         """instances: iterable of (graph, K, omega, theta0); graph as for set_graph."""

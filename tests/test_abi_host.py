@@ -226,3 +226,60 @@ def test_complete_graph_beyond_u16_block():
         k.set_graph_complete(70000)
         info = k.graph_info()
         assert info["blocks"] == 1 and info["list_entries"] == 0 and info["max_block"] == 70000
+
+
+def check_weighted_layout(k, g):
+    """Rebuild every row of the weighted adjacency from its 0/1 layers and inter list."""
+    A = g.dense()
+    n = g.n
+    perm = k.perm()
+    order = np.lexsort((np.arange(n), g.labels))
+    assert np.array_equal(perm[order], np.arange(n))
+    B = A[np.ix_(order, order)]
+    bp, mode = k.blocks()
+    for b in range(len(mode)):
+        s0, s1 = bp[b], bp[b + 1]
+        s = s1 - s0
+        sub = B[s0:s1, s0:s1]
+        if s >= 2:
+            full = np.bincount(sub[~np.eye(s, dtype=bool)], minlength=256)
+            assert mode[b] == int(np.argmax(full)), b
+        J = max(1, int(sub.max()))
+        for m in range(s0, s1):
+            cols, lay = k.row_layers(m)
+            assert lay.min(initial=1) >= 1 and lay.max(initial=1) <= J
+            row = np.zeros(s, dtype=np.int64)
+            for t in range(1, J + 1):
+                sel = cols[lay == t]
+                layer = np.zeros(s, dtype=np.int64)
+                if t <= mode[b]:
+                    layer[:] = 1
+                    layer[m - s0] = 0
+                    layer[sel] = 0
+                else:
+                    layer[sel] = 1
+                row += layer
+            assert np.array_equal(row, sub[m - s0]), (b, m)
+            _, itr = k.row_lists(m)
+            cross = np.zeros(n, dtype=np.int64)
+            np.add.at(cross, itr, 1)
+            want = B[m].astype(np.int64).copy()
+            want[s0:s1] = 0
+            assert np.array_equal(cross, want)
+
+
+@pytest.mark.parametrize("chunk", [64, 4096])
+def test_weighted_layout_matches_dense(chunk):
+    rng = np.random.default_rng(62)
+    g = gen.weighted_sbm([90, 1, 70, 130], [2, 0, 0, 3], 0.25, 4, 0.03, rng,
+                         uperm=rng.permutation(291).astype(np.int32))
+    with host_ctx(chunk=chunk, tile_rows=64) as k:
+        k.set_graph(g)
+        info = k.graph_info()
+        assert info["symmetric"] == 1
+        check_weighted_layout(k, g)
+    with host_ctx() as k:
+        bad = gen.Graph(n=g.n, labels=g.labels, row_ptr=g.row_ptr, col=g.col, weight=g.weight.copy())
+        bad.weight[0] = 300
+        with pytest.raises(K.KurError):
+            k.set_graph(bad)

@@ -426,3 +426,26 @@ def test_rkf45_exact_without_coupling_and_error_control():
     # the linear invariant (symmetric A, uniform scaling)
     y, _ = oracle.rkf45(g, om, 3.0, th, 1.0, 0.5, 1e-6)
     assert abs(np.mean(y - th - om)) < 1e-13
+
+
+# ---------------------------------------------------------------------------------------------
+# integer-weighted adjacency (Introduction: coefficients in a finite set)
+
+def test_weighted_rhs_brute_force_and_linearity():
+    rng = np.random.default_rng(61)
+    g = gen.weighted_sbm([30, 20, 25], [2, 0, 3], 0.2, 4, 0.05, rng, uperm=rng.permutation(75).astype(np.int32))
+    A = g.dense().astype(np.float64)
+    om, th = rng.standard_normal(75), rng.uniform(0, 2 * np.pi, 75)
+    K = 1.7
+    brute = om + K / 75 * (A * np.sin(th[None, :] - th[:, None])).sum(axis=1)
+    assert np.abs(oracle.rhs(g, om, K, th) - brute).max() < 1e-13
+    # degree scaling uses the weighted row sums
+    deg = A.sum(axis=1)
+    brute1 = om + K * np.where(deg > 0, 1 / np.maximum(deg, 1), 0) * (A * np.sin(th[None, :] - th[:, None])).sum(axis=1)
+    assert np.abs(oracle.rhs(g, om, K, th, scaling=1) - brute1).max() < 1e-13
+    # linear in A: F(A1 + A2) - omega = (F(A1) - omega) + (F(A2) - omega)
+    A1 = np.minimum(A, 1).astype(np.int32)
+    g1, g2 = gen.from_dense(A1, g.labels), gen.from_dense((A - A1).astype(np.int32), g.labels)
+    lhs = oracle.rhs(g, om, K, th) - om
+    rhs = (oracle.rhs(g1, om, K, th) - om) + (oracle.rhs(g2, om, K, th) - om)
+    assert np.abs(lhs - rhs).max() < 1e-13
