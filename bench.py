@@ -64,6 +64,8 @@ def make_workload(name: str):
         return gen.sbm_equal()
     if name == "a2a":
         return gen.all_to_all()
+    if name == "pairs":
+        return gen.sbm_paired_workload()
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -77,6 +79,10 @@ def workload_desc(name: str, w, info) -> dict:
                          "seed 1003")
     elif name == "sbm":
         d["workload"] = "SBM N=65536 = 64x1024, rho_in 0.97, p_out 2e-4, omega~N(0,1), K=4, dt=0.01, seed 1002"
+    elif name == "pairs":
+        d["workload"] = ("paired SBM N=65536 = 64x1024, rho_in 0.97, communities 2i and 2i+1 joined by a dense "
+                         "off-diagonal block of density 0.9, p_out 2e-4, omega~N(0,1), K=4, dt=0.01, seed 1008")
+        d["dense_offdiagonal_blocks"] = info.get("pairs")
     else:
         d["workload"] = "all-to-all N=512, omega~N(0,1), K=2, dt=0.01, seed 1001"
     return d
@@ -235,7 +241,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="het", choices=["het", "sbm", "a2a", "batch", "ens"])
+    ap.add_argument("--workload", default="het", choices=["het", "sbm", "a2a", "pairs", "batch", "ens"])
     ap.add_argument("--replicas", type=int, default=128, help="replicas of the ensemble workload (1..256)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -292,6 +298,7 @@ def main():
     k.set_params(w.omega, w.K)
     k.set_phases(w.theta0)
     info = k.graph_info()
+    info["pairs"] = k.graph_pairs()
     log("graph set in %.1f s: %s" % (time.perf_counter() - t0, info))
 
     k.step_rk4(w.dt, args.warmup)

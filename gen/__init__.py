@@ -223,6 +223,92 @@ def weighted_sbm(sizes, prevalent, exception: float, J: int, p_out: float, rng: 
     return from_dense(A, labels)
 
 
+def block_model(sizes, V, exception: float, J: int, rng: np.random.Generator,
+                uperm: np.ndarray | None = None) -> Graph:
+    """Symmetric integer-valued block model with a prevalent value per pair of blocks (small
+    graphs, dense construction): every pair of nodes (i, j) of blocks (a, c), i != j, takes the
+    value V[a][c] with probability 1 - exception, else a value drawn uniformly from {0..J}
+    without V[a][c]. V is a symmetric integer matrix with entries in {0..J}; with J = 1 the
+    result is a 0/1 graph whose block (a, c) has density 1 - exception where V[a][c] = 1 and
+    exception where it is 0. uperm[p]: user index of planted node p."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    V = np.asarray(V, dtype=np.int32)
+    n = int(sizes.sum())
+    lab = np.repeat(np.arange(len(sizes)), sizes)
+    iu = np.triu_indices(n, 1)
+    pv = V[lab[iu[0]], lab[iu[1]]]
+    exc = rng.random(len(pv)) < exception
+    other = rng.integers(0, J, len(pv))  # uniform over {0..J} without the prevalent value
+    other = other + (other >= pv)
+    A = np.zeros((n, n), dtype=np.int32)
+    A[iu] = np.where(exc, other, pv)
+    A = A + A.T
+    if uperm is not None:
+        B = np.zeros_like(A)
+        B[np.ix_(uperm, uperm)] = A
+        A = B
+        labels = np.empty(n, dtype=np.int32)
+        labels[uperm] = lab
+    else:
+        labels = lab.astype(np.int32)
+    return from_dense(A, labels)
+
+
+def paired_sbm(n_comm: int = 64, comm_size: int = 1024, rho_in: float = 0.97, rho_pair: float = 0.9,
+               p_out: float = 2e-4, seed: int = 1008) -> Graph:
+    """Equal communities coupled in pairs: community c is linked to community c xor 1 by a dense
+    off-diagonal block (pair probability rho_pair); inside a community the pair probability is
+    rho_in; other pairs of nodes are linked with probability p_out (the count drawn from the
+    binomial law, the pairs uniformly, duplicates dropped). Planted order is the user order."""
+    if n_comm % 2:
+        raise ValueError("n_comm must be even")
+    g_rng, b_rng = streams(seed, 2)
+    s = int(comm_size)
+    n = n_comm * s
+    lab = np.repeat(np.arange(n_comm, dtype=np.int32), s)
+    # background edges between unpaired communities (u < v)
+    npairs = n * (n - 1) // 2
+    m = int(b_rng.binomial(npairs, p_out))
+    u = b_rng.integers(0, n, 2 * m + 16)
+    v = b_rng.integers(0, n, 2 * m + 16)
+    keep = (u < v) & (lab[u] != lab[v]) & ((lab[u] ^ 1) != lab[v])
+    bg = np.unique(np.stack([u[keep], v[keep]], 1), axis=0)[:m]
+    bg_rows = np.concatenate([bg[:, 0], bg[:, 1]])
+    bg_cols = np.concatenate([bg[:, 1], bg[:, 0]])
+    order = np.argsort(bg_rows, kind="stable")
+    bg_rows, bg_cols = bg_rows[order], bg_cols[order]
+    bg_ptr = np.searchsorted(bg_rows, np.arange(0, n + 1, s))
+    # intra blocks (upper triangle mirrored) and pair blocks (drawn for a < c, transposed for c)
+    intra = []
+    for a in range(n_comm):
+        U = np.triu(g_rng.random((s, s)) < rho_in, 1)
+        intra.append(U | U.T)
+    pair = {}
+    for a in range(0, n_comm, 2):
+        pair[a] = g_rng.random((s, s)) < rho_pair
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    cols = []
+    for a in range(n_comm):
+        # the pair (a, a xor 1) occupies the columns [lo, lo + 2s); row-major keys r n + column
+        lo = (a & ~1) * s
+        strip = np.zeros((s, 2 * s), dtype=bool)
+        c = a ^ 1
+        strip[:, a * s - lo:(a + 1) * s - lo] = intra[a]
+        strip[:, c * s - lo:(c + 1) * s - lo] = pair[a] if a % 2 == 0 else pair[c].T
+        r, cc = np.nonzero(strip)
+        key = r.astype(np.int64) * n + cc + lo
+        sl = slice(bg_ptr[a], bg_ptr[a + 1])
+        keyb = np.sort((bg_rows[sl] - a * s).astype(np.int64) * n + bg_cols[sl])
+        key = np.insert(key, np.searchsorted(key, keyb), keyb)
+        row_ptr[a * s + 1:(a + 1) * s + 1] = np.bincount(key // n, minlength=s)
+        cols.append((key % n).astype(np.int32))
+    np.cumsum(row_ptr, out=row_ptr)
+    col = np.concatenate(cols)
+    return Graph(n=n, labels=lab, row_ptr=row_ptr, col=col, sizes=np.full(n_comm, s, dtype=np.int64),
+                 rho=np.full(n_comm, rho_in), p_out=float(p_out), uperm=np.arange(n, dtype=np.int32),
+                 meta={"rho_pair": rho_pair, "background_edges": int(len(bg))})
+
+
 # ------------------------------------------------------------------------------------------------
 # Frequencies and phases
 # ------------------------------------------------------------------------------------------------
@@ -281,6 +367,19 @@ def sbm_equal(n_comm: int = 64, comm_size: int = 1024, rho_in: float = 0.97, p_o
     uperm = _perm(p_rng, n) if permute else None
     g = sbm(np.full(n_comm, comm_size), np.full(n_comm, rho_in), p_out, key, uperm)
     return Workload(name="sbm_%dx%d" % (n_comm, comm_size), graph=g, omega=w_rng.standard_normal(n),
+                    theta0=uniform_theta(t_rng, n), K=K, dt=dt, steps=steps,
+                    target=uniform_theta(x_rng, n), r_every=10)
+
+
+def sbm_paired_workload(n_comm: int = 64, comm_size: int = 1024, rho_in: float = 0.97, rho_pair: float = 0.9,
+                        p_out: float = 2e-4, K: float = 4.0, dt: float = 0.01, steps: int = 1000,
+                        seed: int = 1008) -> Workload:
+    """Equal communities coupled in pairs by dense off-diagonal blocks (paired_sbm), with
+    omega ~ N(0, 1) and theta0 ~ U[0, 2 pi)."""
+    _, _, w_rng, t_rng, x_rng = streams(seed)
+    g = paired_sbm(n_comm, comm_size, rho_in, rho_pair, p_out, seed)
+    n = g.n
+    return Workload(name="paired_%dx%d" % (n_comm, comm_size), graph=g, omega=w_rng.standard_normal(n),
                     theta0=uniform_theta(t_rng, n), K=K, dt=dt, steps=steps,
                     target=uniform_theta(x_rng, n), r_every=10)
 

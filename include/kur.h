@@ -77,6 +77,16 @@ const char *kur_last_error(const kur_ctx *ctx);
  *   "tau"         density threshold: a diagonal block whose realised density is >= tau is
  *                 evaluated with localised order parameters (list of zeros), otherwise with its
  *                 list of ones. Default 0.5 (Sec. 3: precompute when ones outnumber zeros).
+ *                 With "pairs" on, the same test applies to every off-diagonal block (the
+ *                 submatrix of two communities) of a 0/1 graph.
+ *   "pairs"       1 (default): a dense off-diagonal block (both communities at least "pair_min"
+ *                 nodes; density >= tau for a 0/1 graph, positive prevalent value for an integer-
+ *                 weighted one) is evaluated with the localised order parameters of its column
+ *                 community minus its list of zeros (Sec. 3, extension to submatrices
+ *                 [M1..M2] x [M3..M4], eq. KuramotoGraphApproach) instead of through the
+ *                 inter-block list; 0: every edge between communities is listed. Graphs given
+ *                 block by block (kur_set_graph) keep the given layout.
+ *   "pair_min"    least nodes of both communities of such a block (1..65536). Default 32.
  *   "chunk"       columns of a diagonal block staged in LDS at a time: a multiple of 64, at
  *                 most 8128 (FP32) or 4032 (FP64). Default 4096 (FP32), 2048 (FP64).
  *   "tile_rows"   maximal rows per work tile (64..4096). Default 256.
@@ -194,19 +204,31 @@ kur_status kur_get_perm(const kur_ctx *ctx, int32_t *perm);
 /*
  * Introspection of the host preprocessing, for host-only contexts (device = -1), which keep
  * the built layout in host memory. kur_get_blocks: block_ptr (nb+1) and mode (nb; the number of
- * 0/1 layers stored as lists of zeros: 1 = list of zeros for a 0/1 block). kur_get_row_lists: for block-order row `row`, the block-local columns stored in its
- * list (ascending; zeros for a dense block, ones for a sparse one) and its inter-block columns
- * (block order, ascending). Pass NULL arrays to query the counts; otherwise the arrays must
- * hold *nlist and *ninter entries (the counts are written back). Device contexts return
- * KUR_ESTATE.
+ * 0/1 layers stored as lists of zeros: 1 = list of zeros for a 0/1 block). kur_get_row_lists:
+ * for block-order row `row`, the block-local columns stored in the list of its own block
+ * (ascending; zeros for a dense block, ones for a sparse one) and its inter-block columns
+ * (block order, ascending; without the dense off-diagonal blocks, see kur_get_row_layers).
+ * Pass NULL arrays to query the counts; otherwise the arrays must hold *nlist and *ninter
+ * entries (the counts are written back). Device contexts return KUR_ESTATE.
  */
 kur_status kur_get_blocks(const kur_ctx *ctx, int64_t *block_ptr, uint8_t *mode);
 kur_status kur_get_row_lists(const kur_ctx *ctx, int64_t row, int32_t *list, int64_t *nlist, int32_t *inter,
                              int64_t *ninter);
-/* Host-only contexts: the stored list entries of block-order row `row` with their 0/1 layer
- * (1-based; layers up to the block's mode hold zeros, the others ones): cols (block-local) and
- * layer hold *count entries on entry (both NULL: count only); *count receives the count. */
+/* Host-only contexts: every stored list entry of block-order row `row` (its own block and its
+ * dense off-diagonal blocks) with its 0/1 layer: cols receives block-order columns, layer the
+ * 1-based layer inside the column community's group; a layer up to the group's mode (see
+ * kur_get_block_groups; 0 for a community without a group) holds zeros, the others ones. cols
+ * and layer hold *count entries on entry (both NULL: count only); *count receives the count.
+ * Row m of A is then: mode_q on every column of every group q (but not m itself), minus one per
+ * zero entry, plus one per one entry, plus one per inter-block entry. */
 kur_status kur_get_row_layers(const kur_ctx *ctx, int64_t row, int32_t *cols, int32_t *layer, int64_t *count);
+/* Column groups of block `block` (any context with a graph): the communities whose localised
+ * order parameters enter every row of the block, with their factor (the prevalent value of that
+ * submatrix): the block itself when dense, then its dense off-diagonal blocks in block order.
+ * blk and mode hold *count entries on entry (both NULL: count only); *count receives the count. */
+kur_status kur_get_block_groups(const kur_ctx *ctx, int32_t block, int32_t *blk, int32_t *mode, int32_t *count);
+/* Number of dense off-diagonal blocks of the installed graph (ordered pairs of communities). */
+kur_status kur_graph_pairs(const kur_ctx *ctx, int64_t *n_pairs);
 
 /* Intrinsic frequencies omega (n, user order, finite) and coupling constant K (finite). */
 kur_status kur_set_params(kur_ctx *ctx, const double *omega, double K);

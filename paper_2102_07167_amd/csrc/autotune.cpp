@@ -167,11 +167,14 @@ kur_status search_tiles(Search &S, Choice &best)
     return KUR_OK;
 }
 
-// Which blocks a threshold makes dense; two thresholds with equal patterns build equal layouts.
-std::vector<uint8_t> modes_for(const std::vector<double> &rho, const std::vector<int32_t> &size, double tau)
+// Which blocks and off-diagonal blocks a threshold makes dense; two thresholds with equal
+// patterns build equal layouts.
+std::vector<uint8_t> modes_for(const std::vector<double> &rho, const std::vector<int32_t> &size,
+                               const std::vector<double> &pair_rho, double tau)
 {
-    std::vector<uint8_t> m(rho.size());
+    std::vector<uint8_t> m(rho.size() + pair_rho.size());
     for (size_t b = 0; b < rho.size(); ++b) m[b] = (size[b] >= 2 && rho[b] >= tau) ? 1 : 0;
+    for (size_t p = 0; p < pair_rho.size(); ++p) m[rho.size() + p] = pair_rho[p] >= tau ? 1 : 0;
     return m;
 }
 
@@ -260,9 +263,9 @@ extern "C" kur_status kur_autotune_csr(kur_ctx *c, int64_t n, const int64_t *row
     const LayoutParams l0 = best.l;
     if ((s = search_tiles(S, best)) != KUR_OK) return s;
 
-    std::vector<double> rho;
+    std::vector<double> rho, pair_rho;
     std::vector<int32_t> size;
-    ctx_block_stats(c, rho, size);
+    ctx_block_stats(c, rho, size, pair_rho);
     int32_t max_block = 0;
     for (int32_t v : size) max_block = std::max(max_block, v);
     Choice installed = best;
@@ -271,9 +274,9 @@ extern "C" kur_status kur_autotune_csr(kur_ctx *c, int64_t n, const int64_t *row
     std::vector<double> taus;
     if (effort == 1) taus = {0.4, 0.6};
     if (effort >= 2) taus = {0.3, 0.4, 0.45, 0.55, 0.6, 0.7};
-    std::vector<std::vector<uint8_t>> seen = {modes_for(rho, size, best.l.tau)};
+    std::vector<std::vector<uint8_t>> seen = {modes_for(rho, size, pair_rho, best.l.tau)};
     for (double tau : taus) {
-        const std::vector<uint8_t> m = modes_for(rho, size, tau);
+        const std::vector<uint8_t> m = modes_for(rho, size, pair_rho, tau);
         if (std::find(seen.begin(), seen.end(), m) != seen.end()) continue;  // same layout as one timed
         seen.push_back(m);
         Choice cand = best;

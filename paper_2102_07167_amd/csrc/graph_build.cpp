@@ -11,7 +11,10 @@
 //    the size of a staged (sin, cos) pair), chunk-major inside a block, every (row, chunk)
 //    segment padded to a multiple of 8 entries with the offset of slot W (all zero), so that a
 //    kernel reads them with aligned 16-byte loads while the chunk's values sit in LDS.
-// 4. All edges between blocks go to a CSR list with block-order columns.
+// 4. All edges between blocks go to a CSR list with block-order columns; then every dense
+//    off-diagonal block (a submatrix of two communities whose pairs are mostly nonzero) moves
+//    out of that list into lists of zeros against the localised order parameters of its column
+//    block (Sec. 3, extension of the approach to submatrices [M1..M2] x [M3..M4]).
 // 5. Cut every block into work tiles of similar cost and choose the lanes per row.
 #include <algorithm>
 #include <atomic>
@@ -20,6 +23,7 @@
 #include <mutex>
 #include <numeric>
 #include <thread>
+#include <unordered_map>
 
 #include "kur_internal.hpp"
 
@@ -171,6 +175,14 @@ std::string finish(BlockGraph &g, const std::vector<int32_t> &block_of_row, cons
         }
         g.n_dense += b.mode;
     }
+    g.blk_rho.assign(g.nb, 0.0);
+    for (int32_t bi = 0; bi < g.nb; ++bi) {
+        const BlkInfo &b = g.blk[bi];
+        int64_t ones = 0;
+        for (int64_t m = b.row0; m < b.row0 + b.size; ++m) ones += ones_row[m];
+        const double pairs = (double)b.size * (double)(b.size - 1);
+        g.blk_rho[bi] = pairs > 0 ? (double)ones / pairs : 0.0;
+    }
 
     // segment lengths and offsets
     g.seg_ptr.assign(tot_segs + 1, 0);
@@ -240,6 +252,11 @@ std::string finish(BlockGraph &g, const std::vector<int32_t> &block_of_row, cons
     });
     if (err.bad) return err.msg;
 
+    diag_segments(g);
+    if (!given_mode) {  // a layout given block by block is used as it is
+        std::string msg = add_dense_pairs(g, opt);
+        if (!msg.empty()) return msg;
+    }
     make_tiles(g, opt);
     return "";
 }
@@ -301,6 +318,18 @@ void make_tiles(BlockGraph &g, const BuildOptions &opt)
     order_tiles(g);
 }
 
+namespace {
+
+// The block holding block-order row (or column) r.
+int32_t block_at(const BlockGraph &g, int64_t r)
+{
+    return (int32_t)(std::upper_bound(g.blk.begin(), g.blk.end(), r,
+                                      [](int64_t x, const BlkInfo &b) { return x < (int64_t)b.row0; }) -
+                     g.blk.begin()) - 1;
+}
+
+}  // namespace
+
 void order_tiles(BlockGraph &g)
 {
     const size_t nt = g.tiles.size();
@@ -309,15 +338,15 @@ void order_tiles(BlockGraph &g)
         const Tile &tl = g.tiles[t];
         const BlkInfo &b = g.blk[tl.block];
         int64_t c = 32 * (int64_t)(tl.r1 - tl.r0);
-        int64_t nonempty = 0;
+        int64_t staging = 0;  // per nonempty segment the size of its column block
         for (int32_t ch = 0; ch < b.nchunk; ++ch) {
             const int64_t s0 = g.seg_ptr[b.segbase + (int64_t)ch * b.size + tl.r0];
             const int64_t s1 = g.seg_ptr[b.segbase + (int64_t)ch * b.size + tl.r1];
             c += s1 - s0;
-            nonempty += (s1 > s0);
+            if (s1 > s0) staging += g.blk[block_at(g, g.segd[b.sd0 + ch].col0)].size;
         }
         c += 4 * (g.inter_ptr[b.row0 + tl.r1] - g.inter_ptr[b.row0 + tl.r0]);
-        cost[t] = c + (int64_t)b.size * nonempty / 4;
+        cost[t] = c + staging / 4;
     }
     const int X = std::max(1, g.xcds);
     // units of placement: a block, or for a block costing more than total / (2 X) runs of its
@@ -391,6 +420,8 @@ std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &g)
     g.deg.assign(n, (int32_t)std::min<int64_t>(n - 1, INT32_MAX));
     g.n_dense = b.mode;
     g.symmetric = true;
+    g.blk_rho.assign(1, 1.0);
+    diag_segments(g);
     // tiles: only the epilogue works per row (no list entries), so use full-size tiles
     g.blk[0].tile0 = 0;
     for (int64_t r = 0; r < n; r += opt.tile_rows)
@@ -438,12 +469,26 @@ std::string merge_graphs(std::vector<BlockGraph> &parts, BlockGraph &g, std::vec
     int64_t roff = 0, segoff = 0, loff = 0, toff = 0, boff = 0;
     for (BlockGraph &p : parts) {
         for (int32_t v : p.perm) g.perm.push_back((int32_t)(v + roff));
+        const int32_t sdoff = (int32_t)g.segd.size(), goff = (int32_t)g.grp.size();
         for (BlkInfo b : p.blk) {
             b.row0 += (int32_t)roff;
             b.segbase += segoff;
             b.tile0 += (int32_t)toff;
+            b.sd0 += sdoff;
+            b.grp0 += goff;
             g.blk.push_back(b);
         }
+        for (SegD d : p.segd) {
+            d.col0 += (int32_t)roff;
+            g.segd.push_back(d);
+        }
+        for (Grp q : p.grp) {
+            q.blk += (int32_t)boff;
+            g.grp.push_back(q);
+        }
+        g.blk_rho.insert(g.blk_rho.end(), p.blk_rho.begin(), p.blk_rho.end());
+        g.pair_rho.insert(g.pair_rho.end(), p.pair_rho.begin(), p.pair_rho.end());
+        g.n_pairs += p.n_pairs;
         for (size_t i = 0; i + 1 < p.seg_ptr.size(); ++i) g.seg_ptr.push_back(p.seg_ptr[i] + loff);
         g.list.insert(g.list.end(), p.list.begin(), p.list.end());
         for (int64_t m = 0; m < p.n; ++m) g.inter_ptr.push_back(p.inter_ptr[m + 1] + (g.inter_ptr.size() > 0 ? g.inter_ptr[roff] : 0));
@@ -774,6 +819,15 @@ std::string build_from_csr_w(int64_t n, const int64_t *row_ptr, const int32_t *c
     g.deg.assign(n, 0);
     for (int64_t m = 0; m < n; ++m) g.deg[m] = (int32_t)std::min<int64_t>(wdeg[m], INT32_MAX);
     g.symmetric = sym.fwd.load() == sym.bwd.load();
+    g.weighted = true;
+    g.blk_rho.assign(nb, 0.0);
+    for (int32_t b = 0; b < nb; ++b) {
+        const double s = g.blk[b].size, pairs = s * (s - 1);
+        g.blk_rho[b] = pairs > 0 ? (pairs - (double)hist[b][0]) / pairs : 0.0;
+    }
+    diag_segments(g);
+    msg = add_dense_pairs(g, opt);
+    if (!msg.empty()) return msg;
     make_tiles(g, opt);
     return "";
 }
@@ -895,6 +949,226 @@ std::string build_from_blocks(int64_t n, int32_t nb, const int64_t *block_ptr, c
     std::string msg = finish(g, block_of_row, src, &modes, opt);
     g.symmetric = sym.fwd.load() == sym.bwd.load();
     return msg;
+}
+
+void diag_segments(BlockGraph &g)
+{
+    const int32_t W = g.W;
+    g.segd.clear();
+    g.grp.clear();
+    for (int32_t bi = 0; bi < g.nb; ++bi) {
+        BlkInfo &b = g.blk[bi];
+        b.sd0 = (int32_t)g.segd.size();
+        const int32_t ncc = (b.size + W - 1) / W;
+        for (int32_t cc = 0; cc < ncc; ++cc)
+            for (int32_t t = 1; t <= b.nlayer; ++t)
+                g.segd.push_back(SegD{b.row0 + cc * W, (int16_t)std::min(W, b.size - cc * W), (int16_t)(t <= b.mode)});
+        b.grp0 = (int32_t)g.grp.size();
+        b.ngrp = b.mode > 0 ? 1 : 0;
+        if (b.mode > 0) g.grp.push_back(Grp{bi, b.mode});
+    }
+}
+
+std::string add_dense_pairs(BlockGraph &g, const BuildOptions &opt)
+{
+    g.n_pairs = 0;
+    g.pair_rho.clear();
+    if (!opt.pairs || g.nb < 2 || g.inter_col.empty()) return "";
+    const int64_t n = g.n;
+    const int32_t nb = g.nb, W = g.W;
+    const int64_t pmin = std::max<int32_t>(1, opt.pair_min);
+    std::vector<int32_t> bor(n);
+    for (int32_t b = 0; b < nb; ++b)
+        std::fill(bor.begin() + g.blk[b].row0, bor.begin() + g.blk[b].row0 + g.blk[b].size, b);
+
+    // per row block, the distinct nonzero entries towards every other block (the inter list of
+    // a row is sorted and holds a column once per unit of weight), and for a weighted graph the
+    // value histogram of the blocks that can have a positive prevalent value
+    struct Pair {
+        int32_t c;
+        int32_t mode;
+        int32_t nlayer;
+    };
+    std::vector<std::vector<Pair>> dense(nb);
+    std::vector<std::vector<double>> rho_of(nb);
+    parallel_for(nb, [&](int64_t lo, int64_t hi) {
+        std::unordered_map<int32_t, int64_t> cnt;
+        std::unordered_map<int32_t, std::vector<int64_t>> hist;
+        for (int64_t a = lo; a < hi; ++a) {
+            const BlkInfo &ba = g.blk[a];
+            if (ba.size < pmin) continue;
+            cnt.clear();
+            for (int64_t m = ba.row0; m < ba.row0 + ba.size; ++m)
+                for (int64_t e = g.inter_ptr[m]; e < g.inter_ptr[m + 1]; ++e)
+                    if (e == g.inter_ptr[m] || g.inter_col[e] != g.inter_col[e - 1]) ++cnt[bor[g.inter_col[e]]];
+            std::vector<std::pair<int32_t, int64_t>> cand;
+            for (const auto &kv : cnt)
+                if (g.blk[kv.first].size >= pmin) cand.push_back(kv);
+            std::sort(cand.begin(), cand.end());
+            hist.clear();
+            for (const auto &cv : cand) {
+                const double cells = (double)ba.size * (double)g.blk[cv.first].size;
+                const double rho = (double)cv.second / cells;
+                if (!g.weighted) {
+                    rho_of[a].push_back(rho);
+                    if (rho >= opt.tau) dense[a].push_back(Pair{cv.first, 1, 1});
+                } else if (2.0 * (double)cv.second >= cells) {
+                    hist[cv.first].assign(kMaxWeight + 1, 0);
+                }
+            }
+            if (hist.empty()) continue;
+            for (int64_t m = ba.row0; m < ba.row0 + ba.size; ++m) {
+                const int64_t e1 = g.inter_ptr[m + 1];
+                for (int64_t e = g.inter_ptr[m]; e < e1;) {
+                    int64_t f = e + 1;
+                    while (f < e1 && g.inter_col[f] == g.inter_col[e]) ++f;
+                    auto it = hist.find(bor[g.inter_col[e]]);
+                    if (it != hist.end()) it->second[std::min<int64_t>(f - e, kMaxWeight)]++;
+                    e = f;
+                }
+            }
+            for (const auto &cv : cand) {
+                auto it = hist.find(cv.first);
+                if (it == hist.end()) continue;
+                std::vector<int64_t> &h = it->second;
+                h[0] = (int64_t)ba.size * g.blk[cv.first].size - cv.second;
+                int32_t vb = 0, jmax = 0;
+                for (int v = 1; v <= kMaxWeight; ++v) {
+                    if (h[v]) jmax = v;
+                    if (h[v] > h[vb]) vb = v;
+                }
+                if (vb > 0) dense[a].push_back(Pair{cv.first, vb, jmax});
+            }
+        }
+    });
+    for (int32_t a = 0; a < nb; ++a) {
+        g.pair_rho.insert(g.pair_rho.end(), rho_of[a].begin(), rho_of[a].end());
+        g.n_pairs += (int64_t)dense[a].size();
+    }
+    if (g.n_pairs == 0) return "";
+
+    // new segment descriptors and groups: a row block keeps its own segments and appends, per
+    // dense partner, the partner's column chunks, each in layers
+    std::vector<SegD> segd;
+    std::vector<Grp> grp;
+    std::vector<int32_t> nseg_old(nb);
+    std::vector<int64_t> segbase_old(nb);
+    int64_t tot = 0;
+    for (int32_t a = 0; a < nb; ++a) {
+        BlkInfo &b = g.blk[a];
+        nseg_old[a] = b.nchunk;
+        segbase_old[a] = b.segbase;
+        const int32_t sd0 = (int32_t)segd.size();
+        segd.insert(segd.end(), g.segd.begin() + b.sd0, g.segd.begin() + b.sd0 + b.nchunk);
+        const int32_t grp0 = (int32_t)grp.size();
+        grp.insert(grp.end(), g.grp.begin() + b.grp0, g.grp.begin() + b.grp0 + b.ngrp);
+        int64_t nseg = b.nchunk;
+        for (const Pair &p : dense[a]) {
+            const BlkInfo &bc = g.blk[p.c];
+            const int32_t ncc = (bc.size + W - 1) / W;
+            for (int32_t cc = 0; cc < ncc; ++cc)
+                for (int32_t t = 1; t <= p.nlayer; ++t)
+                    segd.push_back(SegD{bc.row0 + cc * W, (int16_t)std::min(W, bc.size - cc * W), (int16_t)(t <= p.mode)});
+            nseg += (int64_t)ncc * p.nlayer;
+            grp.push_back(Grp{p.c, p.mode});
+        }
+        if (nseg > INT32_MAX) return "too many segments in a block";
+        b.sd0 = sd0;
+        b.grp0 = grp0;
+        b.ngrp += (int32_t)dense[a].size();
+        b.nchunk = (int32_t)nseg;
+        b.segbase = tot;
+        tot += nseg * b.size;
+    }
+
+    // per row: its old segments as they are, then the partner segments (layer t <= mode lists
+    // the columns with a value below t, the others the columns with a value of at least t), and
+    // the inter entries of the other blocks
+    std::vector<int64_t> seg_ptr(tot + 1, 0);
+    std::vector<uint16_t> list;
+    std::vector<int64_t> inter_ptr(n + 1, 0);
+    std::vector<int32_t> inter_col;
+    std::vector<int64_t> unpadded(n, 0);
+    int32_t smax = 0;
+    for (const BlkInfo &b : g.blk) smax = std::max(smax, b.size);
+    auto row_pass = [&](bool emit) {
+        parallel_for(n, [&](int64_t lo, int64_t hi) {
+            std::vector<uint8_t> val((size_t)smax, 0);
+            for (int64_t m = lo; m < hi; ++m) {
+                const int32_t a = bor[m];
+                const BlkInfo &b = g.blk[a];
+                const int64_t r = m - b.row0;
+                for (int32_t ch = 0; ch < nseg_old[a]; ++ch) {
+                    const int64_t io = segbase_old[a] + (int64_t)ch * b.size + r;
+                    const int64_t in = b.segbase + (int64_t)ch * b.size + r;
+                    const int64_t len = g.seg_ptr[io + 1] - g.seg_ptr[io];
+                    if (emit)
+                        std::copy(g.list.begin() + g.seg_ptr[io], g.list.begin() + g.seg_ptr[io + 1],
+                                  list.begin() + seg_ptr[in]);
+                    else
+                        seg_ptr[in + 1] = len;
+                }
+                const int64_t e0 = g.inter_ptr[m], e1 = g.inter_ptr[m + 1];
+                int32_t ch = nseg_old[a];
+                int64_t kept = 0, added = 0;
+                int64_t prev = e0;  // entries before the next partner are kept
+                for (const Pair &p : dense[a]) {
+                    const BlkInfo &bc = g.blk[p.c];
+                    const int32_t *ic = g.inter_col.data();
+                    const int64_t f0 = std::lower_bound(ic + prev, ic + e1, bc.row0) - ic;
+                    const int64_t f1 = std::lower_bound(ic + f0, ic + e1, bc.row0 + bc.size) - ic;
+                    if (emit) std::copy(ic + prev, ic + f0, inter_col.begin() + inter_ptr[m] + kept);
+                    kept += f0 - prev;
+                    prev = f1;
+                    for (int64_t e = f0; e < f1; ++e) val[ic[e] - bc.row0]++;
+                    const int32_t ncc = (bc.size + W - 1) / W;
+                    for (int32_t cc = 0; cc < ncc; ++cc) {
+                        const int64_t c0 = (int64_t)cc * W, c1 = std::min<int64_t>(bc.size, c0 + W);
+                        for (int32_t t = 1; t <= p.nlayer; ++t, ++ch) {
+                            const int64_t idx = b.segbase + (int64_t)ch * b.size + r;
+                            const bool zeros = t <= p.mode;
+                            uint16_t *out = emit ? list.data() + seg_ptr[idx] : nullptr;
+                            int64_t k = 0;
+                            for (int64_t lc = c0; lc < c1; ++lc) {
+                                if (zeros ? val[lc] >= t : val[lc] < t) continue;
+                                if (emit) out[k] = (uint16_t)((lc - c0) * g.esz2);
+                                ++k;
+                            }
+                            if (emit) {
+                                for (const int64_t padded = seg_ptr[idx + 1] - seg_ptr[idx]; k < padded; ++k)
+                                    out[k] = (uint16_t)(W * g.esz2);
+                            } else {
+                                seg_ptr[idx + 1] = round8(k);
+                                added += k;
+                            }
+                        }
+                    }
+                    for (int64_t e = f0; e < f1; ++e) val[ic[e] - bc.row0] = 0;
+                }
+                if (emit) std::copy(g.inter_col.begin() + prev, g.inter_col.begin() + e1,
+                                    inter_col.begin() + inter_ptr[m] + kept);
+                kept += e1 - prev;
+                if (!emit) {
+                    inter_ptr[m + 1] = kept;
+                    unpadded[m] = added;
+                }
+            }
+        });
+    };
+    row_pass(false);
+    for (int64_t i = 0; i < tot; ++i) seg_ptr[i + 1] += seg_ptr[i];
+    for (int64_t m = 0; m < n; ++m) inter_ptr[m + 1] += inter_ptr[m];
+    list.assign((size_t)seg_ptr[tot], (uint16_t)0);
+    inter_col.assign((size_t)inter_ptr[n], 0);
+    row_pass(true);
+    for (int64_t m = 0; m < n; ++m) g.list_unpadded += unpadded[m];
+    g.seg_ptr.swap(seg_ptr);
+    g.list.swap(list);
+    g.inter_ptr.swap(inter_ptr);
+    g.inter_col.swap(inter_col);
+    g.segd.swap(segd);
+    g.grp.swap(grp);
+    return "";
 }
 
 }  // namespace kur

@@ -62,7 +62,7 @@ struct kur_ctx {
     double ens_tau = 0.5;        // ensembles: blocks at least this dense use the matrix cores
 
     // device graph
-    DevBuf d_blk, d_tiles, d_order, d_seg, d_list, d_iptr, d_icol;
+    DevBuf d_blk, d_segd, d_grp, d_tiles, d_order, d_seg, d_list, d_iptr, d_icol;
     // device state
     DevBuf d_omega, d_unit, d_hi, d_lo, d_wind, d_ksum, d_sc[2], d_part[2], d_sce, d_parte, d_kout, d_y;
     DevBuf d_r, d_psi;
@@ -173,7 +173,7 @@ hipError_t upload(DevBuf &b, const void *src, size_t bytes, hipStream_t st)
 
 void free_all(kur_ctx *c)
 {
-    DevBuf *bufs[] = {&c->d_blk, &c->d_tiles, &c->d_order, &c->d_seg, &c->d_list, &c->d_iptr, &c->d_icol,
+    DevBuf *bufs[] = {&c->d_blk, &c->d_segd, &c->d_grp, &c->d_tiles, &c->d_order, &c->d_seg, &c->d_list, &c->d_iptr, &c->d_icol,
                       &c->d_omega, &c->d_unit, &c->d_hi, &c->d_lo, &c->d_wind, &c->d_ksum, &c->d_sc[0],
                       &c->d_sc[1], &c->d_part[0], &c->d_part[1], &c->d_sce, &c->d_parte, &c->d_kout, &c->d_y,
                       &c->d_r, &c->d_psi, &c->d_tile_first, &c->d_inv_n, &c->d_ctr, &c->d_ck};
@@ -193,6 +193,8 @@ DevGraph devgraph(const kur_ctx *c)
 {
     DevGraph g;
     g.blk = (const BlkInfo *)c->d_blk.p;
+    g.segd = (const SegD *)c->d_segd.p;
+    g.grp = (const Grp *)c->d_grp.p;
     g.tiles = (const Tile *)c->d_tiles.p;
     g.order = (const int32_t *)c->d_order.p;
     g.seg_ptr = (const int64_t *)c->d_seg.p;
@@ -393,6 +395,8 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
         const int64_t n = g.n;
         const size_t T = (size_t)c->esz;
         if ((e = upload(c->d_blk, g.blk.data(), sizeof(BlkInfo) * g.blk.size(), c->stream)) != hipSuccess ||
+            (e = upload(c->d_segd, g.segd.data(), sizeof(SegD) * g.segd.size(), c->stream)) != hipSuccess ||
+            (e = upload(c->d_grp, g.grp.data(), sizeof(Grp) * g.grp.size(), c->stream)) != hipSuccess ||
             (e = upload(c->d_tiles, g.tiles.data(), sizeof(Tile) * g.tiles.size(), c->stream)) != hipSuccess ||
             (e = upload(c->d_order, g.order.data(), sizeof(int32_t) * g.order.size(), c->stream)) != hipSuccess ||
             (e = upload(c->d_seg, g.seg_ptr.data(), sizeof(int64_t) * g.seg_ptr.size(), c->stream)) != hipSuccess ||
@@ -448,7 +452,13 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
         c->skel.tile_rows = g.tile_rows;
         c->skel.esz2 = g.esz2;
         c->skel.blk.swap(g.blk);
+        c->skel.segd.swap(g.segd);
+        c->skel.grp.swap(g.grp);
         c->skel.seg_ptr.swap(g.seg_ptr);
+        c->skel.blk_rho.swap(g.blk_rho);
+        c->skel.pair_rho.swap(g.pair_rho);
+        c->skel.n_pairs = g.n_pairs;
+        c->skel.weighted = g.weighted;
         c->skel.inter_ptr.swap(g.inter_ptr);
     }
     c->has_graph = true;
@@ -568,6 +578,12 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
     } else if (k == "xcds") {
         if (v != (int64_t)v || v < 1 || v > 64) return fail(c, KUR_EINVAL, "xcds must be an integer in [1, 64]");
         c->bopt.xcds = (int32_t)v;
+    } else if (k == "pairs") {
+        if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "pairs must be 0 or 1");
+        c->bopt.pairs = v != 0;
+    } else if (k == "pair_min") {
+        if (v != (int64_t)v || v < 1 || v > 65536) return fail(c, KUR_EINVAL, "pair_min must be an integer in [1, 65536]");
+        c->bopt.pair_min = (int32_t)v;
     } else if (k == "threads") {
         if (v != 256 && v != 512 && v != 1024) return fail(c, KUR_EINVAL, "threads must be 256, 512 or 1024");
         if (c->has_graph && rows_lds_bytes(c->esz, c->W, c->tile_rows, (int)v, 1) > 156 * 1024)
@@ -700,12 +716,14 @@ kur_status kur_get_row_lists(const kur_ctx *c, int64_t row, int32_t *list, int64
     const int64_t r = row - bi.row0;
     int64_t k = 0;
     for (int32_t ch = 0; ch < bi.nchunk; ++ch) {
+        const SegD &sd = g.segd[bi.sd0 + ch];
+        if (sd.col0 < bi.row0 || sd.col0 >= bi.row0 + bi.size) continue;  // a dense off-diagonal block
         const int64_t idx = bi.segbase + (int64_t)ch * bi.size + r;
         for (int64_t e = g.seg_ptr[idx]; e < g.seg_ptr[idx + 1]; ++e) {
             if (g.list[e] == (uint16_t)(g.W * g.esz2)) continue;  // padding
             if (list) {
                 if (k >= *nlist) return KUR_EINVAL;
-                list[k] = (int32_t)(ch / bi.nlayer) * g.W + g.list[e] / g.esz2;
+                list[k] = sd.col0 - bi.row0 + g.list[e] / g.esz2;
             }
             ++k;
         }
@@ -731,19 +749,48 @@ kur_status kur_get_row_layers(const kur_ctx *c, int64_t row, int32_t *cols, int3
     const BlkInfo &bi = g.blk[b];
     const int64_t r = row - bi.row0;
     int64_t k = 0;
+    int32_t layer_no = 0, last_col0 = -1;
     for (int32_t ch = 0; ch < bi.nchunk; ++ch) {
+        const SegD &sd = g.segd[bi.sd0 + ch];
+        // the layers of one column chunk are consecutive segments
+        layer_no = sd.col0 == last_col0 ? layer_no + 1 : 1;
+        last_col0 = sd.col0;
         const int64_t idx = bi.segbase + (int64_t)ch * bi.size + r;
         for (int64_t e = g.seg_ptr[idx]; e < g.seg_ptr[idx + 1]; ++e) {
             if (g.list[e] == (uint16_t)(g.W * g.esz2)) continue;  // padding
             if (cols || layer) {
                 if (k >= *count) return KUR_EINVAL;
-                if (cols) cols[k] = (int32_t)(ch / bi.nlayer) * g.W + g.list[e] / g.esz2;
-                if (layer) layer[k] = ch % bi.nlayer + 1;
+                if (cols) cols[k] = sd.col0 + g.list[e] / g.esz2;
+                if (layer) layer[k] = layer_no;
             }
             ++k;
         }
     }
     *count = k;
+    return KUR_OK;
+}
+
+kur_status kur_get_block_groups(const kur_ctx *c, int32_t block, int32_t *blk, int32_t *mode, int32_t *count)
+{
+    if (!c || !count) return KUR_EINVAL;
+    if (!c->has_graph) return KUR_ESTATE;
+    const BlockGraph &g = c->host_only ? c->host_graph : c->skel;
+    if (block < 0 || block >= g.nb) return KUR_EINVAL;
+    const BlkInfo &bi = g.blk[block];
+    if ((blk || mode) && *count < bi.ngrp) return KUR_EINVAL;
+    for (int32_t q = 0; q < bi.ngrp; ++q) {
+        if (blk) blk[q] = g.grp[bi.grp0 + q].blk;
+        if (mode) mode[q] = g.grp[bi.grp0 + q].mode;
+    }
+    *count = bi.ngrp;
+    return KUR_OK;
+}
+
+kur_status kur_graph_pairs(const kur_ctx *c, int64_t *n_pairs)
+{
+    if (!c || !n_pairs) return KUR_EINVAL;
+    if (!c->has_graph) return KUR_ESTATE;
+    *n_pairs = (c->host_only ? c->host_graph : c->skel).n_pairs;
     return KUR_OK;
 }
 
@@ -2030,20 +2077,15 @@ kur_status ctx_time_steps(kur_ctx *c, int trials, double *ms_per_step)
     return KUR_OK;
 }
 
-void ctx_block_stats(const kur_ctx *c, std::vector<double> &density, std::vector<int32_t> &size)
+void ctx_block_stats(const kur_ctx *c, std::vector<double> &density, std::vector<int32_t> &size,
+                     std::vector<double> &pair_density)
 {
     const BlockGraph &L = c->host_only ? c->host_graph : c->skel;
-    density.assign(L.blk.size(), 0.0);
+    density = L.blk_rho;
+    density.resize(L.blk.size(), 0.0);
     size.assign(L.blk.size(), 0);
-    for (size_t b = 0; b < L.blk.size(); ++b) {
-        const BlkInfo &bi = L.blk[b];
-        double ones = 0.0;
-        for (int64_t m = bi.row0; m < (int64_t)bi.row0 + bi.size; ++m)
-            ones += (double)c->deg[m] - (double)(L.inter_ptr[m + 1] - L.inter_ptr[m]);
-        const double pairs = (double)bi.size * (double)(bi.size - 1);
-        density[b] = pairs > 0 ? ones / pairs : 0.0;
-        size[b] = bi.size;
-    }
+    for (size_t b = 0; b < L.blk.size(); ++b) size[b] = L.blk[b].size;
+    pair_density = L.pair_rho;
 }
 
 }  // namespace kur

@@ -8,23 +8,43 @@
 
 namespace kur {
 
-// One diagonal block (a community after regrouping) as the kernels see it.
-// A weighted block is handled as a sum of 0/1 layers A = sum_{t >= 1} [A >= t]: layers t <= mode
-// are mostly ones and store their zeros (subtracted from the localised order parameters),
-// layers t > mode store their ones. A 0/1 block has one layer and mode 0 or 1.
+// One diagonal block (a community after regrouping) as the kernels see it: the row block of its
+// rows. A weighted block is handled as a sum of 0/1 layers A = sum_{t >= 1} [A >= t]: layers
+// t <= mode are mostly ones and store their zeros (subtracted from the localised order
+// parameters), layers t > mode store their ones. A 0/1 block has one layer and mode 0 or 1.
+// The row block's segments run over column groups: first its own columns, then every dense
+// off-diagonal block of its rows (a partner column block whose pairs are mostly nonzero), each
+// in column chunks of width W and, inside a chunk, in layers.
 struct BlkInfo {
     int32_t row0;     // first block-order row
     int32_t size;     // rows (= columns) of the block
-    int32_t nchunk;   // segments per row: column chunks of width W times layers
-    int32_t mode;     // layers stored as lists of zeros (the block's prevalent value); the
-                      // localised order parameters enter with this factor
+    int32_t nchunk;   // segments per row (over all column groups), described by segd[sd0 ..]
+    int32_t mode;     // layers of the diagonal block stored as lists of zeros (its prevalent
+                      // value); 0 for a sparse diagonal block
     int64_t segbase;  // index into seg_ptr of (segment 0, local row 0); segment c, row r at
-                      // segbase + c * size + r; segment c is column chunk c / nlayer, layer
-                      // c % nlayer + 1
+                      // segbase + c * size + r
     int32_t tile0;    // first tile of this block (tiles of a block are contiguous)
     int32_t ntiles;
-    int32_t nlayer;   // 0/1 layers of the block (1 for a 0/1 block)
-    int32_t pad;
+    int32_t nlayer;   // 0/1 layers of the diagonal block (1 for a 0/1 block)
+    int32_t ngrp;     // column groups whose localised order parameters enter the rows: grp[grp0 ..]
+    int32_t grp0;
+    int32_t sd0;      // first segment descriptor of this block
+};
+
+// One segment of a row block: the columns [col0, col0 + cw) (block order) staged in LDS, and
+// whether its list holds zeros (subtracted) or ones (added).
+struct SegD {
+    int32_t col0;
+    int16_t cw;
+    int16_t zeros;
+};
+
+// A column block whose localised order parameters enter every row of a row block with factor
+// mode (the prevalent value of that submatrix): the diagonal block when dense, and every dense
+// off-diagonal block.
+struct Grp {
+    int32_t blk;
+    int32_t mode;
 };
 
 // One unit of work: rows [r0, r1) (block-local) of one block, G lanes per row (G == 0: each
@@ -46,6 +66,8 @@ struct BuildOptions {
     int32_t esz2 = 8;           // bytes of one staged (sin, cos) pair; list entries are LDS byte
                                 // offsets col * esz2, so W * esz2 must stay below 65536
     int32_t xcds = 1;           // launch order for this many round-robin XCDs (1: plain largest first)
+    bool pairs = true;          // dense off-diagonal blocks use localised order parameters
+    int32_t pair_min = 32;      // least rows and columns of such a block
 };
 
 // The graph in block order, ready for upload.
@@ -57,7 +79,9 @@ struct BlockGraph {
     int32_t esz2 = 8;
     std::vector<int32_t> perm;        // user node -> block-order row
     std::vector<BlkInfo> blk;
-    std::vector<int64_t> seg_ptr;     // total segments + 1 (chunk-major inside every block)
+    std::vector<SegD> segd;           // segment descriptors (every block's from blk[].sd0)
+    std::vector<Grp> grp;             // column groups with localised order parameters
+    std::vector<int64_t> seg_ptr;     // total segments + 1 (segment-major inside every block)
     std::vector<uint16_t> list;       // chunk-relative LDS byte offset (col * esz2), segments
                                       // padded to 8 entries with W * esz2 (the zero slot)
     std::vector<int64_t> inter_ptr;   // n + 1, block order
@@ -68,7 +92,14 @@ struct BlockGraph {
     std::vector<int32_t> deg;         // row degree (ones of the row), block order
     int64_t list_unpadded = 0;
     int64_t n_dense = 0;
+    int64_t n_pairs = 0;              // dense off-diagonal blocks
     bool symmetric = false;           // A equals its transpose (checked by a 64-bit hash)
+    // the density tests of the build (for the tuner: two thresholds with equal outcomes build
+    // equal layouts): per block its realised density; per nonzero off-diagonal block with at
+    // least pair_min rows and columns its density (0/1 graphs)
+    std::vector<double> blk_rho;
+    std::vector<double> pair_rho;
+    bool weighted = false;            // built from integer weights (prevalent-value rule)
 };
 
 // Host preprocessing entry points; return "" on success or an error message.
@@ -96,6 +127,18 @@ int32_t regroup_by_labels(int64_t n, const int32_t *labels, std::vector<int32_t>
 constexpr int32_t kMaxWeight = 255;
 std::string build_from_csr_w(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
                              const int32_t *labels, const BuildOptions &opt, BlockGraph &out);
+
+// Segment descriptors and column groups of the diagonal blocks alone (every builder ends with
+// this before add_dense_pairs): per block, for every column chunk its layers.
+void diag_segments(BlockGraph &g);
+
+// Moves every dense off-diagonal block (row block a, column block c) out of the inter-block
+// CSR into a column group of a: dense when a and c have at least pair_min nodes each and, for
+// a 0/1 graph, the realised density is at least tau, for a weighted graph the prevalent value
+// of its pairs (zeros included) is positive. Its layers are stored like those of a diagonal
+// block. Rebuilds seg_ptr, list, segd, grp, the inter CSR and the tiles; a no-op when
+// opt.pairs is false or no block is dense.
+std::string add_dense_pairs(BlockGraph &g, const BuildOptions &opt);
 
 // The complete graph on n nodes: one dense block whose list of zeros is empty.
 std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &out);

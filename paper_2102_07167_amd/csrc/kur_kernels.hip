@@ -255,10 +255,11 @@ struct TileLds {
     }
 };
 
-// For the rows of one tile, accumulate in L.acc[r] the sum over the row's stored list of x
-// (added for a sparse block, subtracted for a dense block) plus the sum over its inter-block
-// columns, and fold the block sum of x from the tile partials into L.red[NT/64] (dense blocks).
-// Ends with a barrier; the complete row sum is then (dense ? block sum : 0) + acc[r].
+// For the rows of one tile, accumulate in L.acc[r] the sum over the row's stored lists of x
+// (lists of ones added, lists of zeros subtracted) plus the sum over its inter-block columns,
+// and fold into L.red[NT/64] the localised order parameters of the row block's column groups,
+// sum_q mode_q (sum of x over column block q), from the tile partials of each column block.
+// Ends with a barrier; the complete row sum is then (ngrp ? L.red[NT/64] : 0) + acc[r].
 template <typename T, int NT, int NV>
 __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, const BlkInfo &bi,
                                             const typename VecT<T, NV>::type *__restrict__ x_in,
@@ -273,14 +274,30 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
 
     for (int r = threadIdx.x; r < nrows; r += NT) L.acc[r] = vzero<VT>();
     if (threadIdx.x == 0) L.xs[W] = vzero<VT>();
-    // localised order parameters of the block: fixed-order sum of its tile partials
-    if (bi.mode && threadIdx.x < 64) {
-        VT sx = vzero<VT>();
-        for (int i = threadIdx.x; i < bi.ntiles; i += 64) vacc(sx, part_in[bi.tile0 + i]);
-        sx = vwave_sum(sx);
-        if (threadIdx.x == 0) L.red[NT / 64] = sx;
+    // localised order parameters: wave w folds the groups w, w + NT/64, ... (each a fixed-order
+    // sum of the column block's tile partials, times the group's factor); with several groups
+    // thread 0 then adds the waves' results in wave order
+    const int ngq = bi.ngrp;
+    const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wq < ngq) {
+        VT sq = vzero<VT>();
+        for (int q = wq; q < ngq; q += NT / 64) {
+            const Grp gq = g.grp[bi.grp0 + q];
+            const int t0 = g.blk[gq.blk].tile0, nt = g.blk[gq.blk].ntiles;
+            VT sx = vzero<VT>();
+            for (int i = threadIdx.x & 63; i < nt; i += 64) vacc(sx, part_in[t0 + i]);
+            sx = vwave_sum(sx);
+            vacc(sq, vscale(sx, (T)gq.mode));
+        }
+        if ((threadIdx.x & 63) == 0) L.red[ngq == 1 ? NT / 64 : wq] = sq;
     }
-    __syncthreads();  // accumulators, pad slot and block sums visible to every wave
+    __syncthreads();  // accumulators, pad slot and group sums visible to every wave
+    if (ngq > 1 && threadIdx.x == 0) {
+        // read by the epilogue after the barrier that ends this function
+        VT s = L.red[0];
+        for (int w = 1; w < min(ngq, NT / 64); ++w) vacc(s, L.red[w]);
+        L.red[NT / 64] = s;
+    }
 
     // G > 0: G lanes per row (short rows); G == 0: every wave streams a contiguous run of rows;
     // G < 0: no list entries in any chunk (only inter-block entries)
@@ -290,8 +307,7 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
     const int lane = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int ngrp = NT / G;
-    const int nl = bi.nlayer;
-    int staged = -1;  // column chunk held in L.xs (uniform over the workgroup)
+    int staged = -1;  // first column of the chunk held in L.xs (uniform over the workgroup)
     const int ln = threadIdx.x & 63;
     // this wave's rows [ra, rb) in streaming mode (wave-uniform, kept in scalar registers)
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -302,15 +318,13 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
         const int64_t sb = bi.segbase + (int64_t)c * bi.size;
         const int64_t e0 = g.seg_ptr[sb + tl.r0], e1 = g.seg_ptr[sb + tl.r1];
         if (e0 == e1) continue;  // uniform over the workgroup
-        const int cc = c / nl;   // column chunk; layer c % nl + 1
-        // a layer stored as zeros is subtracted from the localised order parameters
-        const T sign = c - cc * nl < bi.mode ? T(-1) : T(1);
-        const int c0 = cc * W;
-        const int cw = min(W, bi.size - c0);
+        const SegD sd = g.segd[bi.sd0 + c];
+        // a list of zeros is subtracted from the localised order parameters
+        const T sign = sd.zeros ? T(-1) : T(1);
         __syncthreads();  // previous segment's gathers are done
-        if (cc != staged) {
-            for (int j = threadIdx.x; j < cw; j += NT) L.xs[j] = x_in[bi.row0 + c0 + j];
-            staged = cc;
+        if (sd.col0 != staged) {
+            for (int j = threadIdx.x; j < sd.cw; j += NT) L.xs[j] = x_in[sd.col0 + j];
+            staged = sd.col0;
         }
         // row starts of this chunk, in 8-entry vectors relative to the tile's first one
         for (int r = threadIdx.x; r <= nrows; r += NT) L.bnd[r] = (int)((g.seg_ptr[sb + tl.r0 + r] - e0) >> 3);
@@ -438,7 +452,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     tile_gather<T, NT, 1>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L);
 
     T2 base = vzero<T2>();
-    if (bi.mode) base = vscale(L.red[NT / 64], (T)bi.mode);
+    if (bi.ngrp) base = L.red[NT / 64];
     T2 part = vzero<T2>();
     for (int r = threadIdx.x; r < nrows; r += NT) {
         const int m = rowbase + r;
@@ -506,7 +520,7 @@ __global__ __launch_bounds__(NT) void k_rows_emb(DevGraph g, EmbArgs<T> a)
     tile_gather<T, NT, 1>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L);
 
     T2 base = vzero<T2>();
-    if (bi.mode) base = vscale(L.red[NT / 64], (T)bi.mode);
+    if (bi.ngrp) base = L.red[NT / 64];
     T2 part = vzero<T2>();
     T emax = T(0);
     const bool last = a.stage == a.nstages;
@@ -587,7 +601,7 @@ __global__ __launch_bounds__(NT) void k_vjp(DevGraph g, VjpArgs<T> a)
     tile_gather<T, NT, 2>(g, tl, bi, x_in, reinterpret_cast<const T4 *>(a.part_in), L);
 
     T4 base = vzero<T4>();
-    if (bi.mode) base = vscale(L.red[NT / 64], (T)bi.mode);
+    if (bi.ngrp) base = L.red[NT / 64];
     T4 part = vzero<T4>();
     double gk = 0.0;
     for (int r = threadIdx.x; r < nrows; r += NT) {

@@ -12,6 +12,8 @@ namespace kur {
 // The graph in device memory (block order).
 struct DevGraph {
     const BlkInfo *blk;
+    const SegD *segd;
+    const Grp *grp;
     const Tile *tiles;
     const int32_t *order;
     const int64_t *seg_ptr;

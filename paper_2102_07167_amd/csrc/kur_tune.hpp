@@ -65,8 +65,10 @@ kur_status ctx_retile(kur_ctx *c, const TileParams &t);
 // best of `trials` timings of whole RK4 steps with HIP events, in ms per step; the phases, the
 // compensation terms and the winding counts are restored afterwards
 kur_status ctx_time_steps(kur_ctx *c, int trials, double *ms_per_step);
-// realised density and size of every block of the installed graph
-void ctx_block_stats(const kur_ctx *c, std::vector<double> &density, std::vector<int32_t> &size);
+// realised density and size of every block of the installed graph, and the densities of its
+// nonzero off-diagonal blocks large enough to be made dense
+void ctx_block_stats(const kur_ctx *c, std::vector<double> &density, std::vector<int32_t> &size,
+                     std::vector<double> &pair_density);
 // the chunk width limit of the context's dtype (16-bit LDS byte offsets)
 int32_t ctx_max_chunk(const kur_ctx *c);
 

@@ -37,6 +37,8 @@ SIGNATURES = {
     "kur_set_graph": (ST, [P, I64, I32, P, P, P, P, P, P, P]),
     "kur_set_graph_csr_w": (ST, [P, I64, P, P, P, P]),
     "kur_get_row_layers": (ST, [P, I64, P, P, P]),
+    "kur_get_block_groups": (ST, [P, I32, P, P, P]),
+    "kur_graph_pairs": (ST, [P, P]),
     "kur_graph_info": (ST, [P, P]),
     "kur_get_perm": (ST, [P, P]),
     "kur_get_blocks": (ST, [P, P, P]),
@@ -200,8 +202,23 @@ class Kuramoto:
         else:
             self.set_graph_csr(graph.n, graph.row_ptr, graph.col, graph.labels)
 
+    def block_groups(self, b: int):
+        """(column blocks, factors) whose localised order parameters enter the rows of block b."""
+        cnt = I32(0)
+        self._chk(self._L.kur_get_block_groups(self._h, int(b), None, None, ctypes.byref(cnt)))
+        blk = np.empty(max(cnt.value, 1), dtype=np.int32)
+        md = np.empty(max(cnt.value, 1), dtype=np.int32)
+        self._chk(self._L.kur_get_block_groups(self._h, int(b), _ptr(blk), _ptr(md), ctypes.byref(cnt)))
+        return blk[: cnt.value], md[: cnt.value]
+
+    def graph_pairs(self) -> int:
+        """Number of dense off-diagonal blocks of the installed graph."""
+        v = I64(0)
+        self._chk(self._L.kur_graph_pairs(self._h, ctypes.byref(v)))
+        return int(v.value)
+
     def row_layers(self, m: int):
-        """(block-local columns, layer) of the list entries of block-order row m (host-only)."""
+        """(block-order columns, layer) of the list entries of block-order row m (host-only)."""
         cnt = I64(0)
         self._chk(self._L.kur_get_row_layers(self._h, int(m), None, None, ctypes.byref(cnt)))
         cols = np.empty(cnt.value, dtype=np.int32)

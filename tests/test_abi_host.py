@@ -37,7 +37,25 @@ def host_ctx(dtype="f32", **opts):
     return k
 
 
-def check_layout(k, g, tau):
+def rebuild_row(k, m, b, bp, groups):
+    """Row m of the block-order adjacency from the stored layout: every group's factor on its
+    columns (not m itself), minus one per zero entry, plus one per one entry and per inter entry."""
+    n = int(bp[-1])
+    blk_of = np.repeat(np.arange(len(bp) - 1), np.diff(bp))
+    R = np.zeros(n, dtype=np.int64)
+    for c, v in groups.items():
+        R[bp[c]:bp[c + 1]] += v
+    if b in groups:
+        R[m] -= groups[b]
+    cols, lay = k.row_layers(m)
+    for col, t in zip(cols, lay):
+        R[col] += -1 if t <= groups.get(int(blk_of[col]), 0) else 1
+    _, itr = k.row_lists(m)
+    np.add.at(R, itr, 1)
+    return R
+
+
+def check_layout(k, g, tau, pair_min=32, pairs=True):
     """Compare the stored layout with the dense adjacency of g (user order)."""
     A = g.dense()
     perm = k.perm()
@@ -50,22 +68,39 @@ def check_layout(k, g, tau):
     starts = np.flatnonzero(np.r_[True, labs[1:] != labs[:-1]])
     assert np.array_equal(bp[:-1], starts) and bp[-1] == n
     B = A[np.ix_(order, order)]  # block-order adjacency P A P^T
-    for b in range(len(mode)):
+    nb = len(mode)
+    blk_of = np.repeat(np.arange(nb), np.diff(bp))
+    npairs = 0
+    for b in range(nb):
         s0, s1 = bp[b], bp[b + 1]
         sub = B[s0:s1, s0:s1]
         s = s1 - s0
         rho = sub.sum() / (s * (s - 1)) if s > 1 else 0.0
         assert mode[b] == (1 if (s >= 2 and rho >= tau) else 0)
+        # dense off-diagonal blocks: both sides >= pair_min, nonzero, density >= tau
+        want = {b: 1} if mode[b] else {}
+        for c in range(nb):
+            sc = bp[c + 1] - bp[c]
+            nnz = int(B[s0:s1, bp[c]:bp[c + 1]].sum())
+            if pairs and c != b and s >= pair_min and sc >= pair_min and nnz > 0 and nnz / (s * sc) >= tau:
+                want[c] = 1
+                npairs += 1
+        gb, gm = k.block_groups(b)
+        groups = {int(c): int(v) for c, v in zip(gb, gm)}
+        assert groups == want, b
+        assert list(gb) == sorted(gb, key=lambda c: (c != b, c))  # own block first, then block order
         for m in range(s0, s1):
             lst, itr = k.row_lists(m)
             r = m - s0
             if mode[b]:
-                want = [c for c in range(s) if c != r and sub[r, c] == 0]
+                want_l = [c for c in range(s) if c != r and sub[r, c] == 0]
             else:
-                want = list(np.flatnonzero(sub[r]))
-            assert list(lst) == want, (b, m)
-            cross = [c for c in np.flatnonzero(B[m]) if not (s0 <= c < s1)]
+                want_l = list(np.flatnonzero(sub[r]))
+            assert list(lst) == want_l, (b, m)
+            cross = [c for c in np.flatnonzero(B[m]) if blk_of[c] != b and int(blk_of[c]) not in groups]
             assert list(itr) == cross
+            assert np.array_equal(rebuild_row(k, m, b, bp, groups), B[m].astype(np.int64)), (b, m)
+    assert k.graph_pairs() == npairs
 
 
 @pytest.mark.parametrize("chunk", [64, 8128])
@@ -79,7 +114,8 @@ def test_preprocessing_matches_dense_adjacency(chunk, tau):
         k.set_graph(g)
         info = k.graph_info()
         assert info["n"] == g.n and info["blocks"] == 5 and info["chunk"] == chunk
-        assert info["inter_entries"] == sum(
+        # tau = 0 also makes every nonzero off-diagonal block of two large enough blocks dense
+        assert tau == 0.0 or info["inter_entries"] == sum(
             int(np.sum(g.labels[g.col[g.row_ptr[u]:g.row_ptr[u + 1]]] != g.labels[u])) for u in range(g.n))
         check_layout(k, g, tau)
 
@@ -228,8 +264,8 @@ def test_complete_graph_beyond_u16_block():
         assert info["blocks"] == 1 and info["list_entries"] == 0 and info["max_block"] == 70000
 
 
-def check_weighted_layout(k, g):
-    """Rebuild every row of the weighted adjacency from its 0/1 layers and inter list."""
+def check_weighted_layout(k, g, pair_min=32):
+    """Rebuild every row of the weighted adjacency from its 0/1 layers, groups and inter list."""
     A = g.dense()
     n = g.n
     perm = k.perm()
@@ -237,35 +273,31 @@ def check_weighted_layout(k, g):
     assert np.array_equal(perm[order], np.arange(n))
     B = A[np.ix_(order, order)]
     bp, mode = k.blocks()
-    for b in range(len(mode)):
+    nb = len(mode)
+    for b in range(nb):
         s0, s1 = bp[b], bp[b + 1]
         s = s1 - s0
         sub = B[s0:s1, s0:s1]
         if s >= 2:
             full = np.bincount(sub[~np.eye(s, dtype=bool)], minlength=256)
             assert mode[b] == int(np.argmax(full)), b
-        J = max(1, int(sub.max()))
+        # groups: the block itself when its prevalent value is positive, then every off-diagonal
+        # block (both sides >= pair_min) whose prevalent value, zeros included, is positive
+        want = {b: int(mode[b])} if mode[b] else {}
+        for c in range(nb):
+            sc = bp[c + 1] - bp[c]
+            if c == b or s < pair_min or sc < pair_min:
+                continue
+            v = int(np.argmax(np.bincount(B[s0:s1, bp[c]:bp[c + 1]].ravel(), minlength=256)))
+            if v > 0:
+                want[c] = v
+        gb, gm = k.block_groups(b)
+        groups = {int(c): int(v) for c, v in zip(gb, gm)}
+        assert groups == want, b
         for m in range(s0, s1):
-            cols, lay = k.row_layers(m)
-            assert lay.min(initial=1) >= 1 and lay.max(initial=1) <= J
-            row = np.zeros(s, dtype=np.int64)
-            for t in range(1, J + 1):
-                sel = cols[lay == t]
-                layer = np.zeros(s, dtype=np.int64)
-                if t <= mode[b]:
-                    layer[:] = 1
-                    layer[m - s0] = 0
-                    layer[sel] = 0
-                else:
-                    layer[sel] = 1
-                row += layer
-            assert np.array_equal(row, sub[m - s0]), (b, m)
-            _, itr = k.row_lists(m)
-            cross = np.zeros(n, dtype=np.int64)
-            np.add.at(cross, itr, 1)
-            want = B[m].astype(np.int64).copy()
-            want[s0:s1] = 0
-            assert np.array_equal(cross, want)
+            _, lay = k.row_layers(m)
+            assert lay.min(initial=1) >= 1 and lay.max(initial=1) <= max(1, int(B[m].max()))
+            assert np.array_equal(rebuild_row(k, m, b, bp, groups), B[m].astype(np.int64)), (b, m)
 
 
 @pytest.mark.parametrize("chunk", [64, 4096])
@@ -283,3 +315,103 @@ def test_weighted_layout_matches_dense(chunk):
         bad.weight[0] = 300
         with pytest.raises(K.KurError):
             k.set_graph(bad)
+
+
+# ------------------------------------------------------------------------------------------------
+# Dense off-diagonal blocks (Sec. 3, extension to submatrices [M1..M2] x [M3..M4])
+# ------------------------------------------------------------------------------------------------
+
+def _pair_graph(rng, sizes, V, exception=0.1, J=1):
+    n = int(np.sum(sizes))
+    return gen.block_model(sizes, V, exception, J, rng, uperm=rng.permutation(n).astype(np.int32))
+
+
+@pytest.mark.parametrize("chunk", [64, 4096])
+@pytest.mark.parametrize("tau", [0.3, 0.5, 0.95])
+def test_dense_pairs_layout(chunk, tau):
+    """Blocks 0-2 and 1-3 are dense off-diagonal blocks (density 0.9), 0-1 about 0.1; block 4 is
+    below pair_min. Every row rebuilds exactly from groups, layers and inter entries."""
+    rng = np.random.default_rng(71)
+    sizes = [150, 70, 100, 40, 20]
+    V = np.zeros((5, 5), dtype=np.int32)
+    V[0, 0] = V[1, 1] = V[2, 2] = 1
+    V[0, 2] = V[2, 0] = V[1, 3] = V[3, 1] = 1
+    V[2, 4] = V[4, 2] = 1  # dense, but block 4 is smaller than pair_min
+    g = _pair_graph(rng, sizes, V)
+    with host_ctx(chunk=chunk, tau=tau, tile_rows=64) as k:
+        k.set_graph(g)
+        check_layout(k, g, tau)
+        if tau <= 0.5:
+            assert k.graph_pairs() == 4
+        assert k.graph_info()["symmetric"] == 1
+
+
+def test_dense_pairs_options():
+    rng = np.random.default_rng(72)
+    sizes = [64, 48, 80]
+    V = np.ones((3, 3), dtype=np.int32)
+    g = _pair_graph(rng, sizes, V, exception=0.2)
+    with host_ctx(chunk=64, pairs=0) as k:
+        k.set_graph(g)
+        check_layout(k, g, 0.5, pairs=False)
+        assert k.graph_pairs() == 0
+        inter_off = k.graph_info()["inter_entries"]
+    with host_ctx(chunk=64, pair_min=50) as k:
+        k.set_graph(g)
+        check_layout(k, g, 0.5, pair_min=50)
+        assert k.graph_pairs() == 2  # 0-2 and 2-0 (block 1 has 48 nodes)
+    with host_ctx(chunk=64) as k:
+        k.set_graph(g)
+        check_layout(k, g, 0.5)
+        assert k.graph_pairs() == 6
+        assert k.graph_info()["inter_entries"] == 0 < inter_off
+    with host_ctx() as k:
+        with pytest.raises(K.KurError):
+            k.set_option("pairs", 2)
+        with pytest.raises(K.KurError):
+            k.set_option("pair_min", 0)
+
+
+@pytest.mark.parametrize("chunk", [64, 4096])
+def test_dense_pairs_weighted_layout(chunk):
+    """Integer-weighted off-diagonal blocks with prevalent values 1 and 2 (two zero layers) and
+    a sparse weighted block; J = 3 gives one or two layers of ones above the prevalent value."""
+    rng = np.random.default_rng(73)
+    sizes = [90, 70, 60, 33]
+    V = np.array([[2, 1, 0, 0],
+                  [1, 0, 2, 0],
+                  [0, 2, 3, 0],
+                  [0, 0, 0, 1]], dtype=np.int32)
+    g = _pair_graph(rng, sizes, V, exception=0.2, J=3)
+    assert g.weight is not None
+    with host_ctx(chunk=chunk, tile_rows=64) as k:
+        k.set_graph(g)
+        check_weighted_layout(k, g)
+        assert k.graph_pairs() == 4
+
+
+def test_dense_pairs_in_batch():
+    """A batch of instances with dense off-diagonal blocks keeps every instance's groups."""
+    rng = np.random.default_rng(74)
+    V = np.array([[1, 1], [1, 0]], dtype=np.int32)
+    gs = [_pair_graph(rng, [40 + 10 * i, 50], V) for i in range(3)]
+    with host_ctx(chunk=64) as k:
+        k.set_batch([(g, 1.0, np.zeros(g.n), np.zeros(g.n)) for g in gs])
+        assert k.graph_pairs() == 6
+        off = 0
+        nb_off = 0
+        bp, _ = k.blocks()
+        for g in gs:
+            with host_ctx(chunk=64) as k1:
+                k1.set_graph(g)
+                bp1, _ = k1.blocks()
+                for b in range(len(bp1) - 1):
+                    g1, m1 = k1.block_groups(b)
+                    g2, m2 = k.block_groups(b + nb_off)
+                    assert np.array_equal(g1 + nb_off, g2) and np.array_equal(m1, m2)
+                for m in range(g.n):
+                    c1, l1 = k1.row_layers(m)
+                    c2, l2 = k.row_layers(m + off)
+                    assert np.array_equal(c1 + off, c2) and np.array_equal(l1, l2)
+                off += g.n
+                nb_off += len(bp1) - 1
