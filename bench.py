@@ -327,11 +327,12 @@ def main():
     achieved = b_eval / (avg_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
+        # counters taken on the same kernel source, workload and layout only
         try:
             tr = json.load(open(TRAFFIC_FILE))
-            if (tr.get("kernel_sha") == kernel_hash() and tr.get("workload") == args.workload
-                    and tr.get("layout") == layout_of(info)):
-                traffic = tr.get("bytes_per_launch")
+            e = tr.get("workloads", {}).get(args.workload, {})
+            if tr.get("kernel_sha") == kernel_hash() and e.get("layout") == layout_of(info):
+                traffic = e.get("bytes_per_launch")
         except Exception:
             traffic = None
     out = {

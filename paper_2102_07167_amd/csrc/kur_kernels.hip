@@ -434,9 +434,10 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
     __syncthreads();
 }
 
-// Right-hand side and classical RK4 stage bookkeeping, one tile per workgroup.
+// Right-hand side and classical RK4 stage bookkeeping, one tile per workgroup. Eight waves
+// per SIMD in FP32 (64 VGPRs); FP64 gets more registers and no scratch at six.
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_rows(DevGraph g, RowArgs<T> a)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_rows(DevGraph g, RowArgs<T> a)
 {
     using T2 = typename V2<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
