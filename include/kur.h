@@ -87,6 +87,10 @@ const char *kur_last_error(const kur_ctx *ctx);
  *                 inter-block list; 0: every edge between communities is listed. Graphs given
  *                 block by block (kur_set_graph) keep the given layout.
  *   "pair_min"    least nodes of both communities of such a block (1..65536). Default 32.
+ *   "transpose"   1: kur_set_graph_csr / kur_set_graph_csr_w on a device context also build and
+ *                 keep the layout of A^T when A is asymmetric (same block order; about the
+ *                 memory of A's layout again), which the adjoint of an asymmetric A needs.
+ *                 0 (default): not kept.
  *   "chunk"       columns of a diagonal block staged in LDS at a time: a multiple of 64, at
  *                 most 8128 (FP32) or 4032 (FP64). Default 4096 (FP32), 2048 (FP64).
  *   "tile_rows"   maximal rows per work tile (64..4096). Default 256.
@@ -141,7 +145,8 @@ kur_status kur_set_graph_csr(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, co
  * order parameters (lists of zeros, eq. KuramotoGraphApproach); the layers above v store their
  * ones. An entry with value a != v thus costs |a - v| list entries. Edges between blocks are
  * summed straightforwardly, listed once per unit of weight. Non-uniform scaling uses the
- * weighted row sums. The adjoint requires a symmetric weighted A.
+ * weighted row sums. As for kur_set_graph_csr, the adjoint of an asymmetric A needs the option
+ * "transpose".
  */
 kur_status kur_set_graph_csr_w(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col,
                                const int32_t *weight, const int32_t *labels);
@@ -278,8 +283,11 @@ kur_status kur_set_state(kur_ctx *ctx, const void *blob, size_t bytes);
  *   theta0      n, user order (NULL: the current phases)
  *   dl_dthetaT  n, user order: dL/dtheta(T)
  *   g_theta0, g_omega (n, user order) and g_K (scalar) receive the gradients (any may be NULL)
- * Requires a symmetric adjacency (KUR_EINVAL otherwise). Uses device memory of about
- * (4 ckpt_every + 15) n reals plus 2 n reals per checkpoint. Synchronous.
+ * J^T l needs the columns of A: for a symmetric adjacency the lists of A serve; an asymmetric
+ * one needs the layout of A^T, built by kur_set_graph_csr / kur_set_graph_csr_w when the option
+ * "transpose" is 1 (KUR_EINVAL otherwise). Its sums (A sin Y_i, A cos Y_i) then come from one
+ * more row-kernel pass per stage. Uses device memory of about (4 ckpt_every + 15) n reals plus
+ * 2 n reals per checkpoint. Synchronous.
  */
 kur_status kur_adjoint_rk4(kur_ctx *ctx, const double *theta0, double dt, int64_t nsteps, int64_t ckpt_every,
                            const double *dl_dthetaT, double *g_theta0, double *g_omega, double *g_K);

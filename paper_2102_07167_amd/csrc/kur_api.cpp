@@ -63,6 +63,11 @@ struct kur_ctx {
 
     // device graph
     DevBuf d_blk, d_segd, d_grp, d_tiles, d_order, d_seg, d_list, d_iptr, d_icol;
+    // layout of A^T for the adjoint of an asymmetric A (option "transpose")
+    int transpose = 0;
+    bool has_T = false;
+    int32_t ntT = 0, nlaunchT = 0, tile_rowsT = 0;
+    DevBuf d_blkT, d_segdT, d_grpT, d_tilesT, d_orderT, d_segT, d_listT, d_iptrT, d_icolT;
     // device state
     DevBuf d_omega, d_unit, d_hi, d_lo, d_wind, d_ksum, d_sc[2], d_part[2], d_sce, d_parte, d_kout, d_y;
     DevBuf d_r, d_psi;
@@ -176,8 +181,11 @@ void free_all(kur_ctx *c)
     DevBuf *bufs[] = {&c->d_blk, &c->d_segd, &c->d_grp, &c->d_tiles, &c->d_order, &c->d_seg, &c->d_list, &c->d_iptr, &c->d_icol,
                       &c->d_omega, &c->d_unit, &c->d_hi, &c->d_lo, &c->d_wind, &c->d_ksum, &c->d_sc[0],
                       &c->d_sc[1], &c->d_part[0], &c->d_part[1], &c->d_sce, &c->d_parte, &c->d_kout, &c->d_y,
-                      &c->d_r, &c->d_psi, &c->d_tile_first, &c->d_inv_n, &c->d_ctr, &c->d_ck};
+                      &c->d_r, &c->d_psi, &c->d_tile_first, &c->d_inv_n, &c->d_ctr, &c->d_ck,
+                      &c->d_blkT, &c->d_segdT, &c->d_grpT, &c->d_tilesT, &c->d_orderT, &c->d_segT,
+                      &c->d_listT, &c->d_iptrT, &c->d_icolT};
     for (DevBuf *b : bufs) dfree(*b);
+    c->has_T = false;
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
 }
@@ -204,6 +212,25 @@ DevGraph devgraph(const kur_ctx *c)
     g.W = c->W;
     g.tile_rows = c->tile_rows;
     g.nlaunch = c->nlaunch;
+    return g;
+}
+
+// The layout of A^T (same block order and chunk width; its own segments and tiles).
+DevGraph devgraph_t(const kur_ctx *c)
+{
+    DevGraph g;
+    g.blk = (const BlkInfo *)c->d_blkT.p;
+    g.segd = (const SegD *)c->d_segdT.p;
+    g.grp = (const Grp *)c->d_grpT.p;
+    g.tiles = (const Tile *)c->d_tilesT.p;
+    g.order = (const int32_t *)c->d_orderT.p;
+    g.seg_ptr = (const int64_t *)c->d_segT.p;
+    g.list = (const uint16_t *)c->d_listT.p;
+    g.inter_ptr = (const int64_t *)c->d_iptrT.p;
+    g.inter_col = (const int32_t *)c->d_icolT.p;
+    g.W = c->W;
+    g.tile_rows = c->tile_rowsT;
+    g.nlaunch = c->nlaunchT;
     return g;
 }
 
@@ -479,6 +506,64 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
     return KUR_OK;
 }
 
+// CSR of A^T in user order (columns ascending), with the weights when given.
+void transpose_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                   std::vector<int64_t> &rp, std::vector<int32_t> &ci, std::vector<int32_t> &wt)
+{
+    const int64_t nnz = row_ptr[n];
+    rp.assign(n + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) rp[col[e] + 1]++;
+    for (int64_t u = 0; u < n; ++u) rp[u + 1] += rp[u];
+    ci.resize(nnz);
+    if (weight) wt.resize(nnz);
+    std::vector<int64_t> fill(rp.begin(), rp.end() - 1);
+    for (int64_t u = 0; u < n; ++u)
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const int64_t f = fill[col[e]]++;
+            ci[f] = (int32_t)u;
+            if (weight) wt[f] = weight[e];
+        }
+}
+
+// After install_graph of an asymmetric A on a device context with option "transpose": build
+// the layout of A^T with the same labels and options (hence the same block order) and upload it.
+kur_status install_transpose(kur_ctx *c, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                             const int32_t *weight, const int32_t *labels)
+{
+    c->has_T = false;
+    if (c->host_only || c->symmetric || !c->transpose) return KUR_OK;
+    BlockGraph t;
+    std::string msg;
+    try {
+        std::vector<int64_t> rp;
+        std::vector<int32_t> ci, wt;
+        transpose_csr(n, row_ptr, col, weight, rp, ci, wt);
+        msg = weight ? build_from_csr_w(n, rp.data(), ci.data(), wt.data(), labels, c->bopt, t)
+                     : build_from_csr(n, rp.data(), ci.data(), labels, c->bopt, t);
+    } catch (const std::bad_alloc &) {
+        return fail(c, KUR_ENOMEM, "host allocation failed building the transposed layout");
+    }
+    if (!msg.empty()) return fail(c, KUR_EINVAL, "transposed layout: " + msg);
+    if (t.perm != c->perm || t.W != c->W) return fail(c, KUR_EINVAL, "transposed layout differs in block order");
+    if (t.tiles.size() > (size_t)INT32_MAX) return fail(c, KUR_EINVAL, "too many tiles");
+    hipError_t e;
+    if ((e = upload(c->d_blkT, t.blk.data(), sizeof(BlkInfo) * t.blk.size(), c->stream)) != hipSuccess ||
+        (e = upload(c->d_segdT, t.segd.data(), sizeof(SegD) * t.segd.size(), c->stream)) != hipSuccess ||
+        (e = upload(c->d_grpT, t.grp.data(), sizeof(Grp) * t.grp.size(), c->stream)) != hipSuccess ||
+        (e = upload(c->d_tilesT, t.tiles.data(), sizeof(Tile) * t.tiles.size(), c->stream)) != hipSuccess ||
+        (e = upload(c->d_orderT, t.order.data(), sizeof(int32_t) * t.order.size(), c->stream)) != hipSuccess ||
+        (e = upload(c->d_segT, t.seg_ptr.data(), sizeof(int64_t) * t.seg_ptr.size(), c->stream)) != hipSuccess ||
+        (e = upload(c->d_listT, t.list.data(), sizeof(uint16_t) * t.list.size(), c->stream)) != hipSuccess ||
+        (e = upload(c->d_iptrT, t.inter_ptr.data(), sizeof(int64_t) * t.inter_ptr.size(), c->stream)) != hipSuccess ||
+        (e = upload(c->d_icolT, t.inter_col.data(), sizeof(int32_t) * t.inter_col.size(), c->stream)) != hipSuccess)
+        return hip_fail(c, e, "transposed layout upload");
+    c->ntT = (int32_t)t.tiles.size();
+    c->nlaunchT = (int32_t)t.order.size();
+    c->tile_rowsT = t.tile_rows;
+    c->has_T = true;
+    return KUR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -578,6 +663,9 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
     } else if (k == "xcds") {
         if (v != (int64_t)v || v < 1 || v > 64) return fail(c, KUR_EINVAL, "xcds must be an integer in [1, 64]");
         c->bopt.xcds = (int32_t)v;
+    } else if (k == "transpose") {
+        if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "transpose must be 0 or 1");
+        c->transpose = (int)v;
     } else if (k == "pairs") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "pairs must be 0 or 1");
         c->bopt.pairs = v != 0;
@@ -638,7 +726,9 @@ kur_status kur_set_graph_csr(kur_ctx *c, int64_t n, const int64_t *row_ptr, cons
         return fail(c, KUR_ENOMEM, "host allocation failed in graph preprocessing");
     }
     if (!msg.empty()) return fail(c, KUR_EINVAL, msg);
-    return install_graph(c, g);
+    kur_status s = install_graph(c, g);
+    if (s != KUR_OK) return s;
+    return install_transpose(c, n, row_ptr, col, nullptr, labels);
 }
 
 kur_status kur_set_graph_csr_w(kur_ctx *c, int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
@@ -654,7 +744,9 @@ kur_status kur_set_graph_csr_w(kur_ctx *c, int64_t n, const int64_t *row_ptr, co
         return fail(c, KUR_ENOMEM, "host allocation failed in graph preprocessing");
     }
     if (!msg.empty()) return fail(c, KUR_EINVAL, msg);
-    return install_graph(c, g);
+    kur_status s = install_graph(c, g);
+    if (s != KUR_OK) return s;
+    return install_transpose(c, n, row_ptr, col, weight, labels);
 }
 
 kur_status kur_set_graph(kur_ctx *c, int64_t n, int32_t nb, const int64_t *block_ptr, const uint8_t *mode,
@@ -1465,11 +1557,11 @@ kur_status kur_kernel_time(kur_ctx *c, int64_t *launches, double *total_ms)
 namespace {
 
 struct AdjBufs {
-    DevBuf hi, lo, wind, ksum, ck, slots, fpart[2], x[2], xpart[2], lam, lam_acc, lbuf, gom, gk;
+    DevBuf hi, lo, wind, ksum, ck, slots, pslots, fpart[2], x[2], xpart[2], lam, lam_acc, lbuf, gom, gk, ac;
     ~AdjBufs()
     {
-        DevBuf *b[] = {&hi, &lo, &wind, &ksum, &ck, &slots, &fpart[0], &fpart[1], &x[0], &x[1],
-                       &xpart[0], &xpart[1], &lam, &lam_acc, &lbuf, &gom, &gk};
+        DevBuf *b[] = {&hi, &lo, &wind, &ksum, &ck, &slots, &pslots, &fpart[0], &fpart[1], &x[0], &x[1],
+                       &xpart[0], &xpart[1], &lam, &lam_acc, &lbuf, &gom, &gk, &ac};
         for (DevBuf *p : b) dfree(*p);
     }
 };
@@ -1487,18 +1579,23 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
     hipStream_t st = c->stream;
     const int64_t nseg = nsteps > 0 ? (nsteps + C - 1) / C : 0;
     const int64_t nslot = 4 * std::min<int64_t>(C, std::max<int64_t>(nsteps, 1)) + 1;
+    // asymmetric A: the Jacobian-transpose gathers run over the layout of A^T (its own tiles),
+    // and (A s, A c) at every stage state come from one row-kernel pass over A
+    const bool asym = !c->symmetric;
+    const int ntv = asym ? c->ntT : nt;
     AdjBufs B;
     hipError_t e;
     if ((e = dalloc(B.hi, TN)) != hipSuccess || (e = dalloc(B.lo, TN)) != hipSuccess ||
         (e = dalloc(B.wind, 4 * (size_t)n)) != hipSuccess || (e = dalloc(B.ksum, TN)) != hipSuccess ||
         (!ck_ext && (e = dalloc(B.ck, 2 * TN * (size_t)std::max<int64_t>(nseg, 1))) != hipSuccess) ||
         (e = dalloc(B.slots, 2 * TN * (size_t)nslot)) != hipSuccess ||
+        (e = dalloc(B.pslots, 2 * sizeof(T) * (size_t)nt * (size_t)nslot)) != hipSuccess ||
         (e = dalloc(B.fpart[0], 2 * sizeof(T) * nt)) != hipSuccess || (e = dalloc(B.fpart[1], 2 * sizeof(T) * nt)) != hipSuccess ||
         (e = dalloc(B.x[0], 4 * TN)) != hipSuccess || (e = dalloc(B.x[1], 4 * TN)) != hipSuccess ||
-        (e = dalloc(B.xpart[0], 4 * sizeof(T) * nt)) != hipSuccess || (e = dalloc(B.xpart[1], 4 * sizeof(T) * nt)) != hipSuccess ||
+        (e = dalloc(B.xpart[0], 4 * sizeof(T) * ntv)) != hipSuccess || (e = dalloc(B.xpart[1], 4 * sizeof(T) * ntv)) != hipSuccess ||
         (e = dalloc(B.lam, TN)) != hipSuccess || (e = dalloc(B.lam_acc, TN)) != hipSuccess ||
         (e = dalloc(B.lbuf, TN)) != hipSuccess || (e = dalloc(B.gom, 8 * (size_t)n)) != hipSuccess ||
-        (e = dalloc(B.gk, 8 * (size_t)nt)) != hipSuccess)
+        (e = dalloc(B.gk, 8 * (size_t)ntv)) != hipSuccess || (asym && (e = dalloc(B.ac, 2 * TN)) != hipSuccess))
         return hip_fail(c, e, "adjoint buffers");
 
     // initial phases (block order), split as in kur_set_phases; the seed dL/dtheta(T)
@@ -1521,17 +1618,19 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
             (e = hipMemcpyAsync(B.wind.p, wind.data(), 4 * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
             (e = hipMemcpyAsync(B.lam.p, lam.data(), TN, hipMemcpyHostToDevice, st)) != hipSuccess ||
             (e = hipMemsetAsync(B.gom.p, 0, 8 * (size_t)n, st)) != hipSuccess ||
-            (e = hipMemsetAsync(B.gk.p, 0, 8 * (size_t)nt, st)) != hipSuccess ||
+            (e = hipMemsetAsync(B.gk.p, 0, 8 * (size_t)ntv, st)) != hipSuccess ||
             (e = hipStreamSynchronize(st)) != hipSuccess)
             return hip_fail(c, e, "adjoint upload");
     }
     const DevGraph g = devgraph(c);
+    const DevGraph gv = asym ? devgraph_t(c) : g;  // layout of the Jacobian-transpose gathers
     auto rows = [&](int stage, const void *sc_in, const void *p_in, void *sc_out, void *p_out) -> hipError_t {
         RowArgs<T> a = row_args<T>(c, stage, dt);
         a.hi = (T *)B.hi.p;
         a.lo = (T *)B.lo.p;
         a.wind = (int32_t *)B.wind.p;
         a.ksum = (T *)B.ksum.p;
+        a.kout = (T *)B.ac.p;  // stage -2 only
         a.sc_in = sc_in;
         a.part_in = p_in;
         a.sc_out = sc_out;
@@ -1539,6 +1638,7 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
         return launch_rows<T>(g, nt, a, c->threads, st);
     };
     auto slot = [&](int64_t i) -> void * { return (char *)B.slots.p + (size_t)i * 2 * TN; };
+    auto pslot = [&](int64_t i) -> void * { return (char *)B.pslots.p + (size_t)i * 2 * sizeof(T) * nt; };
 
     const char *ckbase = ck_ext ? (const char *)ck_ext : (const char *)B.ck.p;
     // forward pass, keeping (hi, lo) every C steps (unless recorded by the caller's run)
@@ -1570,16 +1670,15 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
         if ((e = hipMemcpyAsync(B.hi.p, ck, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
             (e = hipMemcpyAsync(B.lo.p, ck + TN, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess)
             return hip_fail(c, e, "adjoint restore");
-        // recompute the segment, keeping (sin, cos) of every stage state: Y_i of step k at slot 4k+i-1
-        int cur = 0;
-        if ((e = launch_sc_init<T>(g, nt, (const T *)B.hi.p, slot(0), B.fpart[0].p, c->threads, st)) != hipSuccess)
+        // recompute the segment, keeping (sin, cos) of every stage state and its tile partials:
+        // Y_i of step k at slot 4k+i-1
+        if ((e = launch_sc_init<T>(g, nt, (const T *)B.hi.p, slot(0), pslot(0), c->threads, st)) != hipSuccess)
             return hip_fail(c, e, "adjoint recompute");
         for (int64_t k = 0; k < len; ++k)
             for (int stage = 1; stage <= 4; ++stage) {
                 const int64_t i = 4 * k + stage;
-                if ((e = rows(stage, slot(i - 1), B.fpart[cur].p, slot(i), B.fpart[cur ^ 1].p)) != hipSuccess)
+                if ((e = rows(stage, slot(i - 1), pslot(i - 1), slot(i), pslot(i))) != hipSuccess)
                     return hip_fail(c, e, "adjoint recompute");
-                cur ^= 1;
             }
         for (int64_t k = len - 1; k >= 0; --k) {
             VjpArgs<T> v;
@@ -1591,6 +1690,7 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
             v.lbuf = (T *)B.lbuf.p;
             v.g_omega = (double *)B.gom.p;
             v.gk_part = (double *)B.gk.p;
+            v.ac_rows = asym ? B.ac.p : nullptr;
             int xc = 0;
             v.stage = 4;
             v.cl = (T)(dt / 6.0);
@@ -1600,7 +1700,7 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
             v.part_in = nullptr;
             v.x_out = B.x[0].p;
             v.part_out = B.xpart[0].p;
-            if ((e = launch_vjp_init<T>(g, nt, v, c->threads, st)) != hipSuccess) return hip_fail(c, e, "adjoint init");
+            if ((e = launch_vjp_init<T>(gv, ntv, v, c->threads, st)) != hipSuccess) return hip_fail(c, e, "adjoint init");
             for (int i = 4; i >= 1; --i) {
                 v.stage = i;
                 // l_{i-1} = cl lam + cm mu_i: (dt/3, dt), (dt/3, dt/2), (dt/6, dt/2)
@@ -1611,7 +1711,9 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
                 v.part_in = B.xpart[xc].p;
                 v.x_out = B.x[xc ^ 1].p;
                 v.part_out = B.xpart[xc ^ 1].p;
-                if ((e = launch_vjp<T>(g, nt, v, c->threads, st)) != hipSuccess) return hip_fail(c, e, "adjoint stage");
+                if (asym && (e = rows(-2, slot(4 * k + i - 1), pslot(4 * k + i - 1), nullptr, nullptr)) != hipSuccess)
+                    return hip_fail(c, e, "adjoint row sums");
+                if ((e = launch_vjp<T>(gv, ntv, v, c->threads, st)) != hipSuccess) return hip_fail(c, e, "adjoint stage");
                 xc ^= 1;
             }
         }
@@ -1619,10 +1721,10 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
 
     // results
     vector<T> lam(n);
-    vector<double> gom(n), gk(nt);
+    vector<double> gom(n), gk(ntv);
     if ((e = hipMemcpyAsync(lam.data(), B.lam.p, TN, hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipMemcpyAsync(gom.data(), B.gom.p, 8 * (size_t)n, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(gk.data(), B.gk.p, 8 * (size_t)nt, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(gk.data(), B.gk.p, 8 * (size_t)ntv, hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
         return hip_fail(c, e, "adjoint download");
     for (int64_t u = 0; u < n; ++u) {
@@ -1631,7 +1733,7 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
     }
     if (g_K) {
         double t = 0.0;
-        for (int i = 0; i < nt; ++i) t += gk[i];
+        for (int i = 0; i < ntv; ++i) t += gk[i];
         *g_K = t;
     }
     return KUR_OK;
@@ -1649,9 +1751,11 @@ extern "C" kur_status kur_adjoint_rk4(kur_ctx *c, const double *theta0, double d
     if (!dl_dthetaT) return fail(c, KUR_EINVAL, "dl_dthetaT must not be NULL");
     kur_status s = need_ready(c, true, theta0 == nullptr);
     if (s != KUR_OK) return s;
-    if (!c->symmetric) return fail(c, KUR_EINVAL, "the adjoint needs a symmetric adjacency");
+    if (!c->symmetric && !c->has_T)
+        return fail(c, KUR_EINVAL, "the adjoint of an asymmetric adjacency needs its transposed layout: set option "
+                                   "\"transpose\" to 1 before kur_set_graph_csr / kur_set_graph_csr_w");
     if (c->batch) return fail(c, KUR_EINVAL, "the adjoint of a batch is not supported");
-    if (rows_lds_bytes(c->esz, c->W, c->tile_rows, c->threads, 2) > 156 * 1024)
+    if (rows_lds_bytes(c->esz, c->W, c->symmetric ? c->tile_rows : c->tile_rowsT, c->threads, 2) > 156 * 1024)
         return fail(c, KUR_EINVAL, "chunk/tile_rows too large for the adjoint's LDS (4 values per node)");
     std::vector<double> th0;
     if (!theta0) {
@@ -1846,9 +1950,11 @@ extern "C" kur_status kur_adjoint_rk4_recorded(kur_ctx *c, const double *dl_dthe
     if (s != KUR_OK) return s;
     if (!c->rec_valid || c->rec_gen != c->gen)
         return fail(c, KUR_ESTATE, "no checkpoints recorded by kur_step_rk4 for the current graph, omega and K");
-    if (!c->symmetric) return fail(c, KUR_EINVAL, "the adjoint needs a symmetric adjacency");
+    if (!c->symmetric && !c->has_T)
+        return fail(c, KUR_EINVAL, "the adjoint of an asymmetric adjacency needs its transposed layout: set option "
+                                   "\"transpose\" to 1 before kur_set_graph_csr / kur_set_graph_csr_w");
     if (c->batch) return fail(c, KUR_EINVAL, "the adjoint of a batch is not supported");
-    if (rows_lds_bytes(c->esz, c->W, c->tile_rows, c->threads, 2) > 156 * 1024)
+    if (rows_lds_bytes(c->esz, c->W, c->symmetric ? c->tile_rows : c->tile_rowsT, c->threads, 2) > 156 * 1024)
         return fail(c, KUR_EINVAL, "chunk/tile_rows too large for the adjoint's LDS (4 values per node)");
     for (int64_t u = 0; u < c->n; ++u)
         if (!std::isfinite(dl_dthetaT[u])) return fail(c, KUR_EINVAL, "dl_dthetaT must be finite");
@@ -1907,7 +2013,7 @@ TileParams ctx_tile_params(const kur_ctx *c) { return c->tiles_installed; }
 bool ctx_layout_fits(const kur_ctx *c, int32_t chunk, const TileParams &t)
 {
     // the row kernel, and for a symmetric graph also the adjoint kernel (twice the staged width)
-    const int nv = c->has_graph && c->symmetric ? 2 : 1;
+    const int nv = c->has_graph && (c->symmetric || c->has_T) ? 2 : 1;
     return rows_lds_bytes(c->esz, chunk > 0 ? chunk : c->W, t.tile_rows, t.threads, nv) <= 156 * 1024;
 }
 

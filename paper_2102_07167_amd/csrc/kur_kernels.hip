@@ -466,7 +466,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             // 0: the derivative; -1: the row's coupling energy cos y (A cos y) + sin y (A sin y).
             // The localised order parameters of a dense block include the row's own node (with
             // the block's factor), whose term cancels in the derivative but adds
-            // mode (cos^2 y + sin^2 y) here: it is removed.
+            // mode (cos^2 y + sin^2 y) here: it is removed. -2: the sums (A sin y, A cos y)
+            // themselves, with that term (it cancels wherever they are used).
+            if (a.stage == -2) {
+                T2 v;
+                v.x = As;
+                v.y = Ac;
+                reinterpret_cast<T2 *>(a.kout)[m] = v;
+                continue;
+            }
             T en = scm.y * Ac + scm.x * As;
             if (bi.mode) en -= (T)bi.mode * (scm.y * scm.y + scm.x * scm.x);
             a.kout[m] = a.stage == 0 ? k : en;
@@ -577,11 +585,13 @@ __global__ __launch_bounds__(256) void k_max_fold(int64_t n, const T *__restrict
 }
 
 // Discrete adjoint of one classical RK4 stage (reverse order 4, 3, 2, 1). With x_in holding
-// (s, c, w s, w c) at the stage state Y_i, w = K scale_m l_i, the gathers give (A s, A c, A ws,
-// A wc) and, for symmetric A,
-//   (J^T l_i)_m = c_m (A wc)_m + s_m (A ws)_m - w_m (c_m (A c)_m + s_m (A s)_m)      (= mu_i)
+// (s, c, w s, w c) at the stage state Y_i, w = K scale_m l_i, the gathers over the lists of A^T
+// give (A^T ws, A^T wc), and
+//   (J^T l_i)_m = c_m (A^T wc)_m + s_m (A^T ws)_m - w_m (c_m (A c)_m + s_m (A s)_m)  (= mu_i)
 //   dF_m/dK     = scale_m ((A s)_m c_m - (A c)_m s_m),
-// obtained by differentiating eq. KuramotoGraph term by term. The epilogue accumulates
+// obtained by differentiating eq. KuramotoGraph term by term. For symmetric A the lists of A
+// serve both (the same gathers give A s and A c); otherwise the kernel runs over the layout of
+// A^T and (A s, A c) come from ac_rows. The epilogue accumulates
 // lam_acc += mu_i, g_omega += l_i, dK += l_i dF/dK, and forms l_{i-1} = a dt lam + b dt mu_i
 // and the next stage's x; at stage 1 it stores the new lam = lam_acc.
 template <typename T, int NT>
@@ -609,8 +619,14 @@ __global__ __launch_bounds__(NT) void k_vjp(DevGraph g, VjpArgs<T> a)
         const int m = rowbase + r;
         const T4 xm = x_in[m];
         const T s = xm.x, c = xm.y;
-        const T As = base.x + L.acc[r].x, Ac = base.y + L.acc[r].y;
+        T As = base.x + L.acc[r].x, Ac = base.y + L.acc[r].y;
         const T Aws = base.z + L.acc[r].z, Awc = base.w + L.acc[r].w;
+        if (a.ac_rows) {
+            // asymmetric A: the gathers ran over A^T; the plain sums come from A
+            const T2 ac = reinterpret_cast<const T2 *>(a.ac_rows)[m];
+            As = ac.x;
+            Ac = ac.y;
+        }
         const T unit = a.unit ? a.unit[m] : a.inv_n;
         const T l = a.lbuf[m];
         const T w = a.K * unit * l;

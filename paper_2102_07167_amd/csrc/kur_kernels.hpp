@@ -29,7 +29,8 @@ struct DevGraph {
 // The coupling factor of row m is K * unit[m] (unit = 1/deg_m) or K * inv_n when unit is null.
 template <typename T>
 struct RowArgs {
-    int stage;          // 0: write F to kout; -1: write the coupling energy (see k_rows); 1..4: RK4 stage
+    int stage;          // 0: write F to kout; -1: write the coupling energy (see k_rows); -2: write the
+                        // pair ((A sin y)_m, (A cos y)_m) to kout (2 n values); 1..4: RK4 stage
     int compensate;     // compensated phase update in stage 4
     T dt, half_dt, dt6; // dt, dt/2, dt/6
     T K, inv_n;
@@ -98,6 +99,8 @@ struct VjpArgs {
     T *lbuf;            // l_i
     double *g_omega;    // dL/domega, accumulated
     double *gk_part;    // per tile dL/dK, accumulated
+    const void *ac_rows;// asymmetric A: ((A s)_m, (A c)_m) at Y_i from a row-kernel pass over A, while
+                        // the gathers run over the lists of A^T; null for symmetric A
 };
 template <typename T>
 hipError_t launch_sc_init(const DevGraph &g, int ntiles, const T *y, void *sc, void *part, int threads, hipStream_t st);

@@ -415,3 +415,17 @@ def test_dense_pairs_in_batch():
                     assert np.array_equal(c1 + off, c2) and np.array_equal(l1, l2)
                 off += g.n
                 nb_off += len(bp1) - 1
+
+
+def test_transpose_option_values():
+    with host_ctx() as k:
+        k.set_option("transpose", 1)
+        k.set_option("transpose", 0)
+        with pytest.raises(K.KurError):
+            k.set_option("transpose", 2)
+        # host-only contexts build no device layouts; an asymmetric graph still installs
+        k.set_option("transpose", 1)
+        rng = np.random.default_rng(8)
+        g = gen.random_dense(50, 0.3, rng, symmetric=False)
+        k.set_graph(g)
+        assert k.graph_info()["symmetric"] == 0
