@@ -285,9 +285,9 @@ kur_status kur_set_state(kur_ctx *ctx, const void *blob, size_t bytes);
  *   g_theta0, g_omega (n, user order) and g_K (scalar) receive the gradients (any may be NULL)
  * J^T l needs the columns of A: for a symmetric adjacency the lists of A serve; an asymmetric
  * one needs the layout of A^T, built by kur_set_graph_csr / kur_set_graph_csr_w when the option
- * "transpose" is 1 (KUR_EINVAL otherwise). Its sums (A sin Y_i, A cos Y_i) then come from one
- * more row-kernel pass per stage. Uses device memory of about (4 ckpt_every + 15) n reals plus
- * 2 n reals per checkpoint. Synchronous.
+ * "transpose" is 1 (KUR_EINVAL otherwise). The recompute of a segment keeps (sin, cos) and the
+ * row sums (A sin, A cos) of every stage state. Uses device memory of about
+ * (16 ckpt_every + 16) n reals plus 2 n reals per checkpoint. Synchronous.
  */
 kur_status kur_adjoint_rk4(kur_ctx *ctx, const double *theta0, double dt, int64_t nsteps, int64_t ckpt_every,
                            const double *dl_dthetaT, double *g_theta0, double *g_omega, double *g_K);

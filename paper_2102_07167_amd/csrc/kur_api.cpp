@@ -335,6 +335,7 @@ RowArgs<T> row_args(kur_ctx *c, int stage, double dt)
     a.part_in = c->d_part[c->cur].p;
     a.sc_out = c->d_sc[c->cur ^ 1].p;
     a.part_out = c->d_part[c->cur ^ 1].p;
+    a.ac_out = nullptr;
     return a;
 }
 
@@ -412,7 +413,7 @@ kur_status upload_instances(kur_ctx *c)
 
 kur_status install_graph(kur_ctx *c, BlockGraph &g)
 {
-    const size_t lds = rows_lds_bytes(c->esz, g.W, g.tile_rows, c->threads, 1);
+    const size_t lds = rows_lds_bytes(c->esz, g.W, g.tile_rows, c->threads);
     if (lds > 156 * 1024) return fail(c, KUR_EINVAL, "chunk/tile_rows/threads exceed the LDS of a workgroup");
     if (g.tiles.size() > (size_t)INT32_MAX) return fail(c, KUR_EINVAL, "too many tiles");
     if (!c->host_only) {
@@ -674,7 +675,7 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
         c->bopt.pair_min = (int32_t)v;
     } else if (k == "threads") {
         if (v != 256 && v != 512 && v != 1024) return fail(c, KUR_EINVAL, "threads must be 256, 512 or 1024");
-        if (c->has_graph && rows_lds_bytes(c->esz, c->W, c->tile_rows, (int)v, 1) > 156 * 1024)
+        if (c->has_graph && rows_lds_bytes(c->esz, c->W, c->tile_rows, (int)v) > 156 * 1024)
             return fail(c, KUR_EINVAL, "threads exceed the LDS budget of the current graph layout");
         c->threads = (int)v;
         c->gen++;
@@ -1557,11 +1558,11 @@ kur_status kur_kernel_time(kur_ctx *c, int64_t *launches, double *total_ms)
 namespace {
 
 struct AdjBufs {
-    DevBuf hi, lo, wind, ksum, ck, slots, pslots, fpart[2], x[2], xpart[2], lam, lam_acc, lbuf, gom, gk, ac;
+    DevBuf hi, lo, wind, ksum, ck, slots, acs, fpart[2], x[2], xpart[2], lam, lam_acc, lbuf, gom, gk;
     ~AdjBufs()
     {
-        DevBuf *b[] = {&hi, &lo, &wind, &ksum, &ck, &slots, &pslots, &fpart[0], &fpart[1], &x[0], &x[1],
-                       &xpart[0], &xpart[1], &lam, &lam_acc, &lbuf, &gom, &gk, &ac};
+        DevBuf *b[] = {&hi, &lo, &wind, &ksum, &ck, &slots, &acs, &fpart[0], &fpart[1], &x[0], &x[1],
+                       &xpart[0], &xpart[1], &lam, &lam_acc, &lbuf, &gom, &gk};
         for (DevBuf *p : b) dfree(*p);
     }
 };
@@ -1579,8 +1580,7 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
     hipStream_t st = c->stream;
     const int64_t nseg = nsteps > 0 ? (nsteps + C - 1) / C : 0;
     const int64_t nslot = 4 * std::min<int64_t>(C, std::max<int64_t>(nsteps, 1)) + 1;
-    // asymmetric A: the Jacobian-transpose gathers run over the layout of A^T (its own tiles),
-    // and (A s, A c) at every stage state come from one row-kernel pass over A
+    // asymmetric A: the Jacobian-transpose gathers run over the layout of A^T (its own tiles)
     const bool asym = !c->symmetric;
     const int ntv = asym ? c->ntT : nt;
     AdjBufs B;
@@ -1589,13 +1589,13 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
         (e = dalloc(B.wind, 4 * (size_t)n)) != hipSuccess || (e = dalloc(B.ksum, TN)) != hipSuccess ||
         (!ck_ext && (e = dalloc(B.ck, 2 * TN * (size_t)std::max<int64_t>(nseg, 1))) != hipSuccess) ||
         (e = dalloc(B.slots, 2 * TN * (size_t)nslot)) != hipSuccess ||
-        (e = dalloc(B.pslots, 2 * sizeof(T) * (size_t)nt * (size_t)nslot)) != hipSuccess ||
+        (e = dalloc(B.acs, 2 * TN * (size_t)(nslot - 1))) != hipSuccess ||
         (e = dalloc(B.fpart[0], 2 * sizeof(T) * nt)) != hipSuccess || (e = dalloc(B.fpart[1], 2 * sizeof(T) * nt)) != hipSuccess ||
-        (e = dalloc(B.x[0], 4 * TN)) != hipSuccess || (e = dalloc(B.x[1], 4 * TN)) != hipSuccess ||
-        (e = dalloc(B.xpart[0], 4 * sizeof(T) * ntv)) != hipSuccess || (e = dalloc(B.xpart[1], 4 * sizeof(T) * ntv)) != hipSuccess ||
+        (e = dalloc(B.x[0], 2 * TN)) != hipSuccess || (e = dalloc(B.x[1], 2 * TN)) != hipSuccess ||
+        (e = dalloc(B.xpart[0], 2 * sizeof(T) * ntv)) != hipSuccess || (e = dalloc(B.xpart[1], 2 * sizeof(T) * ntv)) != hipSuccess ||
         (e = dalloc(B.lam, TN)) != hipSuccess || (e = dalloc(B.lam_acc, TN)) != hipSuccess ||
         (e = dalloc(B.lbuf, TN)) != hipSuccess || (e = dalloc(B.gom, 8 * (size_t)n)) != hipSuccess ||
-        (e = dalloc(B.gk, 8 * (size_t)ntv)) != hipSuccess || (asym && (e = dalloc(B.ac, 2 * TN)) != hipSuccess))
+        (e = dalloc(B.gk, 8 * (size_t)ntv)) != hipSuccess)
         return hip_fail(c, e, "adjoint buffers");
 
     // initial phases (block order), split as in kur_set_phases; the seed dL/dtheta(T)
@@ -1624,21 +1624,22 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
     }
     const DevGraph g = devgraph(c);
     const DevGraph gv = asym ? devgraph_t(c) : g;  // layout of the Jacobian-transpose gathers
-    auto rows = [&](int stage, const void *sc_in, const void *p_in, void *sc_out, void *p_out) -> hipError_t {
+    auto rows = [&](int stage, const void *sc_in, const void *p_in, void *sc_out, void *p_out,
+                    void *ac_out) -> hipError_t {
         RowArgs<T> a = row_args<T>(c, stage, dt);
         a.hi = (T *)B.hi.p;
         a.lo = (T *)B.lo.p;
         a.wind = (int32_t *)B.wind.p;
         a.ksum = (T *)B.ksum.p;
-        a.kout = (T *)B.ac.p;  // stage -2 only
         a.sc_in = sc_in;
         a.part_in = p_in;
         a.sc_out = sc_out;
         a.part_out = p_out;
+        a.ac_out = ac_out;
         return launch_rows<T>(g, nt, a, c->threads, st);
     };
     auto slot = [&](int64_t i) -> void * { return (char *)B.slots.p + (size_t)i * 2 * TN; };
-    auto pslot = [&](int64_t i) -> void * { return (char *)B.pslots.p + (size_t)i * 2 * sizeof(T) * nt; };
+    auto acslot = [&](int64_t i) -> void * { return (char *)B.acs.p + (size_t)i * 2 * TN; };
 
     const char *ckbase = ck_ext ? (const char *)ck_ext : (const char *)B.ck.p;
     // forward pass, keeping (hi, lo) every C steps (unless recorded by the caller's run)
@@ -1655,7 +1656,7 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
                     return hip_fail(c, e, "adjoint checkpoint");
             }
             for (int stage = 1; stage <= 4; ++stage) {
-                if ((e = rows(stage, fsc[cur], B.fpart[cur].p, fsc[cur ^ 1], B.fpart[cur ^ 1].p)) != hipSuccess)
+                if ((e = rows(stage, fsc[cur], B.fpart[cur].p, fsc[cur ^ 1], B.fpart[cur ^ 1].p, nullptr)) != hipSuccess)
                     return hip_fail(c, e, "adjoint forward");
                 cur ^= 1;
             }
@@ -1670,15 +1671,18 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
         if ((e = hipMemcpyAsync(B.hi.p, ck, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
             (e = hipMemcpyAsync(B.lo.p, ck + TN, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess)
             return hip_fail(c, e, "adjoint restore");
-        // recompute the segment, keeping (sin, cos) of every stage state and its tile partials:
-        // Y_i of step k at slot 4k+i-1
-        if ((e = launch_sc_init<T>(g, nt, (const T *)B.hi.p, slot(0), pslot(0), c->threads, st)) != hipSuccess)
+        // recompute the segment, keeping (sin, cos) of every stage state and its row sums
+        // (A sin, A cos): Y_i of step k at slot 4k+i-1
+        int cur = 0;
+        if ((e = launch_sc_init<T>(g, nt, (const T *)B.hi.p, slot(0), B.fpart[0].p, c->threads, st)) != hipSuccess)
             return hip_fail(c, e, "adjoint recompute");
         for (int64_t k = 0; k < len; ++k)
             for (int stage = 1; stage <= 4; ++stage) {
                 const int64_t i = 4 * k + stage;
-                if ((e = rows(stage, slot(i - 1), pslot(i - 1), slot(i), pslot(i))) != hipSuccess)
+                if ((e = rows(stage, slot(i - 1), B.fpart[cur].p, slot(i), B.fpart[cur ^ 1].p, acslot(i - 1))) !=
+                    hipSuccess)
                     return hip_fail(c, e, "adjoint recompute");
+                cur ^= 1;
             }
         for (int64_t k = len - 1; k >= 0; --k) {
             VjpArgs<T> v;
@@ -1690,12 +1694,13 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
             v.lbuf = (T *)B.lbuf.p;
             v.g_omega = (double *)B.gom.p;
             v.gk_part = (double *)B.gk.p;
-            v.ac_rows = asym ? B.ac.p : nullptr;
             int xc = 0;
             v.stage = 4;
             v.cl = (T)(dt / 6.0);
             v.cm = T(0);
             v.sc_next = slot(4 * k + 3);
+            v.sc_cur = nullptr;
+            v.ac_rows = nullptr;
             v.x_in = nullptr;
             v.part_in = nullptr;
             v.x_out = B.x[0].p;
@@ -1706,13 +1711,13 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
                 // l_{i-1} = cl lam + cm mu_i: (dt/3, dt), (dt/3, dt/2), (dt/6, dt/2)
                 v.cl = i == 4 ? (T)(dt / 3.0) : i == 3 ? (T)(dt / 3.0) : (T)(dt / 6.0);
                 v.cm = i == 4 ? tdt : (T)(0.5 * dt);
+                v.sc_cur = slot(4 * k + i - 1);
+                v.ac_rows = acslot(4 * k + i - 1);
                 v.sc_next = i > 1 ? slot(4 * k + i - 2) : nullptr;
                 v.x_in = B.x[xc].p;
                 v.part_in = B.xpart[xc].p;
                 v.x_out = B.x[xc ^ 1].p;
                 v.part_out = B.xpart[xc ^ 1].p;
-                if (asym && (e = rows(-2, slot(4 * k + i - 1), pslot(4 * k + i - 1), nullptr, nullptr)) != hipSuccess)
-                    return hip_fail(c, e, "adjoint row sums");
                 if ((e = launch_vjp<T>(gv, ntv, v, c->threads, st)) != hipSuccess) return hip_fail(c, e, "adjoint stage");
                 xc ^= 1;
             }
@@ -1755,8 +1760,8 @@ extern "C" kur_status kur_adjoint_rk4(kur_ctx *c, const double *theta0, double d
         return fail(c, KUR_EINVAL, "the adjoint of an asymmetric adjacency needs its transposed layout: set option "
                                    "\"transpose\" to 1 before kur_set_graph_csr / kur_set_graph_csr_w");
     if (c->batch) return fail(c, KUR_EINVAL, "the adjoint of a batch is not supported");
-    if (rows_lds_bytes(c->esz, c->W, c->symmetric ? c->tile_rows : c->tile_rowsT, c->threads, 2) > 156 * 1024)
-        return fail(c, KUR_EINVAL, "chunk/tile_rows too large for the adjoint's LDS (4 values per node)");
+    if (rows_lds_bytes(c->esz, c->W, c->symmetric ? c->tile_rows : c->tile_rowsT, c->threads) > 156 * 1024)
+        return fail(c, KUR_EINVAL, "chunk/tile_rows of the transposed layout exceed the LDS of a workgroup");
     std::vector<double> th0;
     if (!theta0) {
         th0.resize(c->n);
@@ -1954,8 +1959,8 @@ extern "C" kur_status kur_adjoint_rk4_recorded(kur_ctx *c, const double *dl_dthe
         return fail(c, KUR_EINVAL, "the adjoint of an asymmetric adjacency needs its transposed layout: set option "
                                    "\"transpose\" to 1 before kur_set_graph_csr / kur_set_graph_csr_w");
     if (c->batch) return fail(c, KUR_EINVAL, "the adjoint of a batch is not supported");
-    if (rows_lds_bytes(c->esz, c->W, c->symmetric ? c->tile_rows : c->tile_rowsT, c->threads, 2) > 156 * 1024)
-        return fail(c, KUR_EINVAL, "chunk/tile_rows too large for the adjoint's LDS (4 values per node)");
+    if (rows_lds_bytes(c->esz, c->W, c->symmetric ? c->tile_rows : c->tile_rowsT, c->threads) > 156 * 1024)
+        return fail(c, KUR_EINVAL, "chunk/tile_rows of the transposed layout exceed the LDS of a workgroup");
     for (int64_t u = 0; u < c->n; ++u)
         if (!std::isfinite(dl_dthetaT[u])) return fail(c, KUR_EINVAL, "dl_dthetaT must be finite");
     try {
@@ -2012,9 +2017,8 @@ TileParams ctx_tile_params(const kur_ctx *c) { return c->tiles_installed; }
 
 bool ctx_layout_fits(const kur_ctx *c, int32_t chunk, const TileParams &t)
 {
-    // the row kernel, and for a symmetric graph also the adjoint kernel (twice the staged width)
-    const int nv = c->has_graph && (c->symmetric || c->has_T) ? 2 : 1;
-    return rows_lds_bytes(c->esz, chunk > 0 ? chunk : c->W, t.tile_rows, t.threads, nv) <= 156 * 1024;
+    // the row kernel (the adjoint kernel stages the same width)
+    return rows_lds_bytes(c->esz, chunk > 0 ? chunk : c->W, t.tile_rows, t.threads) <= 156 * 1024;
 }
 
 LayoutParams ctx_layout_params(const kur_ctx *c)

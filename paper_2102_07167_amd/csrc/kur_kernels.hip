@@ -94,10 +94,6 @@ __device__ __forceinline__ void block_sum_store(VT v, VT *red, VT *out)
 {
     v.x = wave_sum(v.x);
     v.y = wave_sum(v.y);
-    if constexpr (sizeof(VT) / sizeof(v.x) == 4) {
-        v.z = wave_sum(v.z);
-        v.w = wave_sum(v.w);
-    }
     const int w = threadIdx.x >> 6;
     __syncthreads();  // red may still be read by other waves
     if ((threadIdx.x & 63) == 0) red[w] = v;
@@ -107,10 +103,6 @@ __device__ __forceinline__ void block_sum_store(VT v, VT *red, VT *out)
         for (int i = 1; i < NT / 64; ++i) {
             s.x += red[i].x;
             s.y += red[i].y;
-            if constexpr (sizeof(VT) / sizeof(v.x) == 4) {
-                s.z += red[i].z;
-                s.w += red[i].w;
-            }
         }
         *out = s;
     }
@@ -145,25 +137,15 @@ __global__ __launch_bounds__(NT) void k_sc_init(const Tile *__restrict__ tiles, 
 }
 
 // ------------------------------------------------------------------------------------------------
-// Gather core shared by the right-hand side (NV = 1: per node (sin, cos)) and the Jacobian-
-// transpose product (NV = 2: per node (sin, cos, w sin, w cos)).
+// Gather core shared by the right-hand side (per node (sin, cos)) and the Jacobian-transpose
+// product (per node (w sin, w cos)): one value pair per list entry.
 // ------------------------------------------------------------------------------------------------
-
-template <typename T, int NV> struct VecT;
-template <> struct VecT<float, 1> { using type = float2; };
-template <> struct VecT<double, 1> { using type = double2; };
-template <> struct VecT<float, 2> { using type = float4; };
-template <> struct VecT<double, 2> { using type = double4; };
 
 template <typename VT> __device__ __forceinline__ VT vzero()
 {
     VT v;
     v.x = 0;
     v.y = 0;
-    if constexpr (sizeof(VT) / sizeof(v.x) == 4) {
-        v.z = 0;
-        v.w = 0;
-    }
     return v;
 }
 
@@ -171,10 +153,6 @@ template <typename VT> __device__ __forceinline__ void vacc(VT &a, const VT &b)
 {
     a.x += b.x;
     a.y += b.y;
-    if constexpr (sizeof(VT) / sizeof(a.x) == 4) {
-        a.z += b.z;
-        a.w += b.w;
-    }
 }
 
 template <typename VT, typename S> __device__ __forceinline__ VT vscale(const VT &a, S s)
@@ -182,10 +160,6 @@ template <typename VT, typename S> __device__ __forceinline__ VT vscale(const VT
     VT r = a;
     r.x *= s;
     r.y *= s;
-    if constexpr (sizeof(VT) / sizeof(a.x) == 4) {
-        r.z *= s;
-        r.w *= s;
-    }
     return r;
 }
 
@@ -193,10 +167,6 @@ template <typename VT> __device__ __forceinline__ VT vwave_sum_dpp(VT v)
 {
     v.x = wave_sum_dpp(v.x);
     v.y = wave_sum_dpp(v.y);
-    if constexpr (sizeof(VT) / sizeof(v.x) == 4) {
-        v.z = wave_sum_dpp(v.z);
-        v.w = wave_sum_dpp(v.w);
-    }
     return v;
 }
 
@@ -204,10 +174,6 @@ template <typename VT> __device__ __forceinline__ VT vgroup_sum_dpp(VT v, int G)
 {
     v.x = group_sum_dpp(v.x, G);
     v.y = group_sum_dpp(v.y, G);
-    if constexpr (sizeof(VT) / sizeof(v.x) == 4) {
-        v.z = group_sum_dpp(v.z, G);
-        v.w = group_sum_dpp(v.w, G);
-    }
     return v;
 }
 
@@ -215,24 +181,20 @@ template <typename VT> __device__ __forceinline__ VT vwave_sum(VT v)
 {
     v.x = wave_sum(v.x);
     v.y = wave_sum(v.y);
-    if constexpr (sizeof(VT) / sizeof(v.x) == 4) {
-        v.z = wave_sum(v.z);
-        v.w = wave_sum(v.w);
-    }
     return v;
 }
 
 // Accumulate the 8 list entries of one 16-byte vector. Entries are LDS byte offsets of a
-// (sin, cos) pair; with NV = 2 every node occupies twice that, hence the shift.
-template <int SHIFT, typename VT>
+// staged value pair.
+template <typename VT>
 __device__ __forceinline__ void gather8(const VT *lds, const u32x4 q, VT &acc)
 {
     const uint32_t w[4] = {q.x, q.y, q.z, q.w};
     const char *base = reinterpret_cast<const char *>(lds);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const VT t0 = *reinterpret_cast<const VT *>(base + ((w[k] & 0xffffu) << SHIFT));
-        const VT t1 = *reinterpret_cast<const VT *>(base + ((w[k] >> 16) << SHIFT));
+        const VT t0 = *reinterpret_cast<const VT *>(base + (w[k] & 0xffffu));
+        const VT t1 = *reinterpret_cast<const VT *>(base + (w[k] >> 16));
         vacc(acc, t0);
         vacc(acc, t1);
     }
@@ -260,14 +222,13 @@ struct TileLds {
 // and fold into L.red[NT/64] the localised order parameters of the row block's column groups,
 // sum_q mode_q (sum of x over column block q), from the tile partials of each column block.
 // Ends with a barrier; the complete row sum is then (ngrp ? L.red[NT/64] : 0) + acc[r].
-template <typename T, int NT, int NV>
+template <typename T, int NT>
 __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, const BlkInfo &bi,
-                                            const typename VecT<T, NV>::type *__restrict__ x_in,
-                                            const typename VecT<T, NV>::type *__restrict__ part_in,
-                                            TileLds<typename VecT<T, NV>::type, NT> &L)
+                                            const typename V2<T>::type *__restrict__ x_in,
+                                            const typename V2<T>::type *__restrict__ part_in,
+                                            TileLds<typename V2<T>::type, NT> &L)
 {
-    using VT = typename VecT<T, NV>::type;
-    constexpr int SHIFT = NV == 2 ? 1 : 0;
+    using VT = typename V2<T>::type;
     const int W = g.W;
     const int nrows = tl.r1 - tl.r0;
     const int rowbase = bi.row0 + tl.r0;
@@ -349,7 +310,7 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
                 u32x4 q3 = __builtin_nontemporal_load(Lv + min((uint32_t)(192 + ln), last));
                 auto span = [&](const u32x4 q, const int s0) {
                     VT p = vzero<VT>();
-                    gather8<SHIFT>(L.xs, q, p);
+                    gather8(L.xs, q, p);
                     if (s0 + ln >= nvec) p = vzero<VT>();
                     // rows that end inside (or right at the end of) this span
                     while (nbnd <= s0 + 64 && r < rb) {
@@ -386,10 +347,10 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
                 for (; v + G < nv; v += 2 * G) {
                     const u32x4 qa = __builtin_nontemporal_load(p + v);
                     const u32x4 qb = __builtin_nontemporal_load(p + v + G);
-                    gather8<SHIFT>(L.xs, qa, acc);
-                    gather8<SHIFT>(L.xs, qb, acc);
+                    gather8(L.xs, qa, acc);
+                    gather8(L.xs, qb, acc);
                 }
-                if (v < nv) gather8<SHIFT>(L.xs, __builtin_nontemporal_load(p + v), acc);
+                if (v < nv) gather8(L.xs, __builtin_nontemporal_load(p + v), acc);
                 acc = vgroup_sum_dpp(acc, G);
                 if (lane == G - 1) vacc(L.acc[r], vscale(acc, sign));
             }
@@ -450,7 +411,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int rowbase = bi.row0 + tl.r0;
     const T2 *__restrict__ sc_in = reinterpret_cast<const T2 *>(a.sc_in);
 
-    tile_gather<T, NT, 1>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L);
+    tile_gather<T, NT>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L);
 
     T2 base = vzero<T2>();
     if (bi.ngrp) base = L.red[NT / 64];
@@ -466,19 +427,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             // 0: the derivative; -1: the row's coupling energy cos y (A cos y) + sin y (A sin y).
             // The localised order parameters of a dense block include the row's own node (with
             // the block's factor), whose term cancels in the derivative but adds
-            // mode (cos^2 y + sin^2 y) here: it is removed. -2: the sums (A sin y, A cos y)
-            // themselves, with that term (it cancels wherever they are used).
-            if (a.stage == -2) {
-                T2 v;
-                v.x = As;
-                v.y = Ac;
-                reinterpret_cast<T2 *>(a.kout)[m] = v;
-                continue;
-            }
+            // mode (cos^2 y + sin^2 y) here: it is removed.
             T en = scm.y * Ac + scm.x * As;
             if (bi.mode) en -= (T)bi.mode * (scm.y * scm.y + scm.x * scm.x);
             a.kout[m] = a.stage == 0 ? k : en;
             continue;
+        }
+        if (a.ac_out) {
+            // the adjoint's recompute keeps (A sin y, A cos y) of the stage state; the row's own
+            // term in a dense block's sums cancels wherever they are used
+            T2 v;
+            v.x = As;
+            v.y = Ac;
+            reinterpret_cast<T2 *>(a.ac_out)[m] = v;
         }
         const T y = rk4_stage<T>(a.stage, k, a.dt, a.half_dt, a.dt6, a.compensate, a.ksum + m, a.hi + m, a.lo + m,
                                  a.wind + m);
@@ -526,7 +487,7 @@ __global__ __launch_bounds__(NT) void k_rows_emb(DevGraph g, EmbArgs<T> a)
     const int rowbase = bi.row0 + tl.r0;
     const T2 *__restrict__ sc_in = reinterpret_cast<const T2 *>(a.sc_in);
 
-    tile_gather<T, NT, 1>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L);
+    tile_gather<T, NT>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L);
 
     T2 base = vzero<T2>();
     if (bi.ngrp) base = L.red[NT / 64];
@@ -584,49 +545,42 @@ __global__ __launch_bounds__(256) void k_max_fold(int64_t n, const T *__restrict
     if (threadIdx.x == 0) *out = red[0];
 }
 
-// Discrete adjoint of one classical RK4 stage (reverse order 4, 3, 2, 1). With x_in holding
-// (s, c, w s, w c) at the stage state Y_i, w = K scale_m l_i, the gathers over the lists of A^T
-// give (A^T ws, A^T wc), and
+// Discrete adjoint of one classical RK4 stage (reverse order 4, 3, 2, 1). With w = K scale_m l_i
+// and x_in holding (w s, w c) at the stage state Y_i, the gathers over the lists of A^T give
+// (A^T ws, A^T wc), and
 //   (J^T l_i)_m = c_m (A^T wc)_m + s_m (A^T ws)_m - w_m (c_m (A c)_m + s_m (A s)_m)  (= mu_i)
 //   dF_m/dK     = scale_m ((A s)_m c_m - (A c)_m s_m),
-// obtained by differentiating eq. KuramotoGraph term by term. For symmetric A the lists of A
-// serve both (the same gathers give A s and A c); otherwise the kernel runs over the layout of
-// A^T and (A s, A c) come from ac_rows. The epilogue accumulates
-// lam_acc += mu_i, g_omega += l_i, dK += l_i dF/dK, and forms l_{i-1} = a dt lam + b dt mu_i
-// and the next stage's x; at stage 1 it stores the new lam = lam_acc.
+// obtained by differentiating eq. KuramotoGraph term by term. (s, c) of Y_i come from sc_cur
+// and (A s, A c) from ac_rows, both kept by the forward recompute of the stage, so the gathers
+// move one value pair per list entry, as in the forward kernel. For symmetric A the layout is
+// that of A itself. The epilogue accumulates lam_acc += mu_i, g_omega += l_i, dK += l_i dF/dK,
+// and forms l_{i-1} = a dt lam + b dt mu_i and the next stage's x; at stage 1 it stores the
+// new lam = lam_acc. Register budget as for k_rows.
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_vjp(DevGraph g, VjpArgs<T> a)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_vjp(DevGraph g, VjpArgs<T> a)
 {
     using T2 = typename V2<T>::type;
-    using T4 = typename VecT<T, 2>::type;
     extern __shared__ __align__(16) unsigned char smem[];
-    TileLds<T4, NT> L(smem, g.W, g.tile_rows);
+    TileLds<T2, NT> L(smem, g.W, g.tile_rows);
     const int tile_id = g.order[blockIdx.x];
     if (tile_id < 0) return;  // empty slot of the XCD-aware launch order
     const Tile tl = g.tiles[tile_id];
     const BlkInfo bi = g.blk[tl.block];
     const int nrows = tl.r1 - tl.r0;
     const int rowbase = bi.row0 + tl.r0;
-    const T4 *__restrict__ x_in = reinterpret_cast<const T4 *>(a.x_in);
 
-    tile_gather<T, NT, 2>(g, tl, bi, x_in, reinterpret_cast<const T4 *>(a.part_in), L);
+    tile_gather<T, NT>(g, tl, bi, reinterpret_cast<const T2 *>(a.x_in), reinterpret_cast<const T2 *>(a.part_in), L);
 
-    T4 base = vzero<T4>();
+    T2 base = vzero<T2>();
     if (bi.ngrp) base = L.red[NT / 64];
-    T4 part = vzero<T4>();
+    T2 part = vzero<T2>();
     double gk = 0.0;
     for (int r = threadIdx.x; r < nrows; r += NT) {
         const int m = rowbase + r;
-        const T4 xm = x_in[m];
-        const T s = xm.x, c = xm.y;
-        T As = base.x + L.acc[r].x, Ac = base.y + L.acc[r].y;
-        const T Aws = base.z + L.acc[r].z, Awc = base.w + L.acc[r].w;
-        if (a.ac_rows) {
-            // asymmetric A: the gathers ran over A^T; the plain sums come from A
-            const T2 ac = reinterpret_cast<const T2 *>(a.ac_rows)[m];
-            As = ac.x;
-            Ac = ac.y;
-        }
+        const T2 scm = reinterpret_cast<const T2 *>(a.sc_cur)[m];
+        const T2 ac = reinterpret_cast<const T2 *>(a.ac_rows)[m];
+        const T s = scm.x, c = scm.y, As = ac.x, Ac = ac.y;
+        const T Aws = base.x + L.acc[r].x, Awc = base.y + L.acc[r].y;
         const T unit = a.unit ? a.unit[m] : a.inv_n;
         const T l = a.lbuf[m];
         const T w = a.K * unit * l;
@@ -641,18 +595,16 @@ __global__ __launch_bounds__(NT) void k_vjp(DevGraph g, VjpArgs<T> a)
             a.lbuf[m] = ln;
             const T wn = a.K * unit * ln;
             const T2 scn = reinterpret_cast<const T2 *>(a.sc_next)[m];
-            T4 xn;
-            xn.x = scn.x;
-            xn.y = scn.y;
-            xn.z = wn * scn.x;
-            xn.w = wn * scn.y;
-            reinterpret_cast<T4 *>(a.x_out)[m] = xn;
+            T2 xn;
+            xn.x = wn * scn.x;
+            xn.y = wn * scn.y;
+            reinterpret_cast<T2 *>(a.x_out)[m] = xn;
             vacc(part, xn);
         } else {
             a.lam[m] = la;
         }
     }
-    if (a.stage > 1) block_sum_store<T4, NT>(part, L.red, reinterpret_cast<T4 *>(a.part_out) + tile_id);
+    if (a.stage > 1) block_sum_store<T2, NT>(part, L.red, reinterpret_cast<T2 *>(a.part_out) + tile_id);
     // the tile's dK contribution, accumulated over all launches in a fixed order
     __shared__ double gks[NT / 64];
     gk = wave_sum(gk);
@@ -666,19 +618,18 @@ __global__ __launch_bounds__(NT) void k_vjp(DevGraph g, VjpArgs<T> a)
     }
 }
 
-// Start of a reverse RK4 step: l_4 = dt/6 lam, lam_acc = lam, x = (s, c, w s, w c) at Y_4.
+// Start of a reverse RK4 step: l_4 = dt/6 lam, lam_acc = lam, x = (w s, w c) at Y_4.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_vjp_init(const Tile *__restrict__ tiles, const BlkInfo *__restrict__ blk,
                                                  VjpArgs<T> a)
 {
     using T2 = typename V2<T>::type;
-    using T4 = typename VecT<T, 2>::type;
-    __shared__ T4 red[NT / 64];
+    __shared__ T2 red[NT / 64];
     const int t = blockIdx.x;
     const Tile tl = tiles[t];
     const int row0 = blk[tl.block].row0 + tl.r0;
     const int nrows = tl.r1 - tl.r0;
-    T4 part = vzero<T4>();
+    T2 part = vzero<T2>();
     for (int r = threadIdx.x; r < nrows; r += NT) {
         const int m = row0 + r;
         const T lam = a.lam[m];
@@ -687,15 +638,13 @@ __global__ __launch_bounds__(NT) void k_vjp_init(const Tile *__restrict__ tiles,
         a.lam_acc[m] = lam;
         const T w = a.K * (a.unit ? a.unit[m] : a.inv_n) * l4;
         const T2 sc = reinterpret_cast<const T2 *>(a.sc_next)[m];
-        T4 x;
-        x.x = sc.x;
-        x.y = sc.y;
-        x.z = w * sc.x;
-        x.w = w * sc.y;
-        reinterpret_cast<T4 *>(a.x_out)[m] = x;
+        T2 x;
+        x.x = w * sc.x;
+        x.y = w * sc.y;
+        reinterpret_cast<T2 *>(a.x_out)[m] = x;
         vacc(part, x);
     }
-    block_sum_store<T4, NT>(part, red, reinterpret_cast<T4 *>(a.part_out) + t);
+    block_sum_store<T2, NT>(part, red, reinterpret_cast<T2 *>(a.part_out) + t);
 }
 
 // r e^{i psi} = (1/N) sum_m e^{i theta_m} (Sec. 2, eq. OrderParameter) for every instance of a
@@ -838,9 +787,9 @@ hipError_t launch_sc_init(const DevGraph &g, int ntiles, const T *y, void *sc, v
 // dynamic LDS limit requested for the tile kernels (the rest of the 160 KiB stays for static use)
 constexpr int kMaxDynLds = 156 * 1024;
 
-size_t rows_lds_bytes(int elem_bytes, int W, int tile_rows, int threads, int nv)
+size_t rows_lds_bytes(int elem_bytes, int W, int tile_rows, int threads)
 {
-    const size_t vt = (size_t)2 * nv * elem_bytes;
+    const size_t vt = (size_t)2 * elem_bytes;
     size_t b = (size_t)(W + 1) * vt + (size_t)tile_rows * vt + (size_t)(threads / 64 + 1) * vt +
                (size_t)(tile_rows + 1) * 4;
     return (b + 15) & ~size_t(15);
@@ -903,7 +852,7 @@ template <typename T>
 hipError_t launch_vjp(const DevGraph &g, int ntiles, const VjpArgs<T> &a, int threads, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    const size_t lds = rows_lds_bytes(sizeof(T), g.W, g.tile_rows, threads, 2);
+    const size_t lds = rows_lds_bytes(sizeof(T), g.W, g.tile_rows, threads);
     static bool attr_done[3] = {false, false, false};
     const int slot = threads == 256 ? 0 : threads == 1024 ? 2 : 1;
     if (!attr_done[slot]) {

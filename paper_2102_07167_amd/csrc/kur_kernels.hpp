@@ -29,8 +29,7 @@ struct DevGraph {
 // The coupling factor of row m is K * unit[m] (unit = 1/deg_m) or K * inv_n when unit is null.
 template <typename T>
 struct RowArgs {
-    int stage;          // 0: write F to kout; -1: write the coupling energy (see k_rows); -2: write the
-                        // pair ((A sin y)_m, (A cos y)_m) to kout (2 n values); 1..4: RK4 stage
+    int stage;          // 0: write F to kout; -1: write the coupling energy (see k_rows); 1..4: RK4 stage
     int compensate;     // compensated phase update in stage 4
     T dt, half_dt, dt6; // dt, dt/2, dt/6
     T K, inv_n;
@@ -45,6 +44,7 @@ struct RowArgs {
     void *sc_out;       // (sin, cos) of the next stage input
     const void *part_in;
     void *part_out;
+    void *ac_out;       // stages 1..4: if not null, ((A sin y)_m, (A cos y)_m) of the stage input
 };
 
 // Arguments of one stage of the embedded Runge-Kutta pair (variable step size). Stage i of s
@@ -89,18 +89,19 @@ struct VjpArgs {
     T K, inv_n;
     const T *unit;
     T cl, cm;           // l_{i-1} = cl * lam + cm * mu_i (k_vjp); l_4 = cl * lam (k_vjp_init)
-    const void *x_in;   // (s, c, w s, w c) at Y_i
+    const void *x_in;   // (w s, w c) at Y_i
     const void *part_in;
     void *x_out;        // the same for the next stage
     void *part_out;
+    const void *sc_cur; // (sin, cos) at Y_i
     const void *sc_next;// (sin, cos) of the next stage's state
     T *lam;             // dL/dtheta at the end of the step; the start of the step after stage 1
     T *lam_acc;         // lam + sum of mu_i
     T *lbuf;            // l_i
     double *g_omega;    // dL/domega, accumulated
     double *gk_part;    // per tile dL/dK, accumulated
-    const void *ac_rows;// asymmetric A: ((A s)_m, (A c)_m) at Y_i from a row-kernel pass over A, while
-                        // the gathers run over the lists of A^T; null for symmetric A
+    const void *ac_rows;// ((A s)_m, (A c)_m) at Y_i, kept by the forward recompute (the gathers run
+                        // over the lists of A^T, which are A's own for symmetric A)
 };
 template <typename T>
 hipError_t launch_sc_init(const DevGraph &g, int ntiles, const T *y, void *sc, void *part, int threads, hipStream_t st);
@@ -128,7 +129,7 @@ template <typename T>
 hipError_t launch_diag(int64_t n, const void *hi, const void *lo, const int32_t *wind, const void *omega,
                        const void *unit, const void *e, double K, double *part, double *out, hipStream_t st);
 
-size_t rows_lds_bytes(int elem_bytes, int W, int tile_rows, int threads, int nv = 1);
+size_t rows_lds_bytes(int elem_bytes, int W, int tile_rows, int threads);
 double two_pi_p1(int elem_bytes);
 double two_pi_p2(int elem_bytes);
 
