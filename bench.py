@@ -372,8 +372,12 @@ def main():
             res = fn()
             k.sync()
             return time.perf_counter() - t0, res
-        k.set_phases(w.theta0)
-        t_fwd, _ = timed(lambda: k.step_rk4(w.dt, na))
+        # the plain forward twice (the first may capture its step graph); the faster is the
+        # denominator of every ratio
+        t_fwd = math.inf
+        for _ in range(2):
+            k.set_phases(w.theta0)
+            t_fwd = min(t_fwd, timed(lambda: k.step_rk4(w.dt, na))[0])
         k.set_phases(w.theta0)
         k.set_option("checkpoint_every", ck)
         t_fwd_ck, _ = timed(lambda: k.step_rk4(w.dt, na))
@@ -382,13 +386,29 @@ def main():
         t_full, (gt2, gw2, gk2) = timed(lambda: k.adjoint_rk4(w.dt, na, seed, theta0=w.theta0, ckpt_every=ck))
         assert np.isfinite(gt).all() and np.isfinite(gw).all() and math.isfinite(gk)
         assert np.array_equal(gt, gt2) and np.array_equal(gw, gw2) and gk == gk2
+        # the same run recording every stage state (16 N reals per step): no recompute
+        k.set_phases(w.theta0)
+        k.set_option("checkpoint_every", ck)
+        k.set_option("record_stages", 1)
+        t_fwd_st, _ = timed(lambda: k.step_rk4(w.dt, na))
+        k.set_option("checkpoint_every", 0)
+        k.set_option("record_stages", 0)
+        t_bwd_st, (gt3, gw3, gk3) = timed(lambda: k.adjoint_recorded(seed))
+        assert np.array_equal(gt, gt3) and np.array_equal(gw, gw3) and gk == gk3
         out["adjoint"] = {"steps": na, "ckpt_every": ck, "fwd_ms": 1e3 * t_fwd, "fwd_checkpointed_ms": 1e3 * t_fwd_ck,
                           "backward_ms": 1e3 * t_bwd, "ratio": t_bwd / t_fwd,
                           "adjoint_with_forward_ms": 1e3 * t_full, "ratio_with_forward": t_full / t_fwd,
+                          "fwd_recording_stages_ms": 1e3 * t_fwd_st, "backward_from_stages_ms": 1e3 * t_bwd_st,
+                          "ratio_from_stages": t_bwd_st / t_fwd,
+                          "stage_record_gb": 16 * elem * w.graph.n * na / 1e9,
                           "note": "ratio = backward (recompute per segment + 4 VJP stages per step, using the "
-                                  "forward run's checkpoints) / plain forward; ratio_with_forward also repeats the forward"}
-        log("adjoint %d steps: backward %.1f ms, with forward %.1f ms, forward %.1f ms (ratio %.2f / %.2f)" % (
-            na, 1e3 * t_bwd, 1e3 * t_full, 1e3 * t_fwd, t_bwd / t_fwd, t_full / t_fwd))
+                                  "forward run's checkpoints) / plain forward; ratio_with_forward also repeats the "
+                                  "forward; ratio_from_stages = backward from a forward run that kept every stage "
+                                  "state (option record_stages, no recompute) / plain forward; all three give the "
+                                  "same gradients bit for bit"}
+        log("adjoint %d steps: backward %.1f ms, with forward %.1f ms, from recorded stages %.1f ms, forward %.1f ms "
+            "(ratios %.2f / %.2f / %.2f)" % (na, 1e3 * t_bwd, 1e3 * t_full, 1e3 * t_bwd_st, 1e3 * t_fwd,
+                                             t_bwd / t_fwd, t_full / t_fwd, t_bwd_st / t_fwd))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, %.0f s budget)" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

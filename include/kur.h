@@ -111,6 +111,10 @@ const char *kur_last_error(const kur_ctx *ctx);
  *   "checkpoint_every" C > 0: kur_step_rk4 keeps the phases every C steps for
  *                 kur_adjoint_rk4_recorded (and launches without graph replay); 0 (default) off.
  *                 Immediate.
+ *   "record_stages" 1: such a recording run also keeps (sin, cos) and the row sums
+ *                 (A sin, A cos) of every stage state, 16 n reals per step (KUR_ENOMEM if the
+ *                 device cannot hold them), so that kur_adjoint_rk4_recorded recomputes nothing;
+ *                 0 (default): checkpoints only. Immediate.
  *   "graph"       1 (default): kur_step_rk4 captures one sampling period (r_every steps, else
  *                 "graph_steps" steps) into a HIP graph and replays it; 0: plain launches.
  *   "graph_steps" steps per replayed graph when no order parameter is sampled (default 16).
@@ -295,7 +299,8 @@ kur_status kur_adjoint_rk4(kur_ctx *ctx, const double *theta0, double dt, int64_
 /*
  * The same gradients for the run of the last kur_step_rk4 call made with the option
  * "checkpoint_every" = C > 0, which kept the phases every C steps: the forward pass is not
- * repeated. Returns KUR_ESTATE if no such run is recorded or the graph, omega, K or an option
+ * repeated. If that run had "record_stages" = 1, the segments are not recomputed either: the
+ * reverse sweep reads the recorded stage states. Returns KUR_ESTATE if no such run is recorded or the graph, omega, K or an option
  * changed since. Synchronous.
  */
 kur_status kur_adjoint_rk4_recorded(kur_ctx *ctx, const double *dl_dthetaT, double *g_theta0, double *g_omega,

@@ -91,6 +91,11 @@ struct kur_ctx {
     int64_t ckpt_every = 0;
     DevBuf d_ck;
     bool rec_valid = false;
+    // option "record_stages": the recording run also keeps (sin, cos) and (A sin, A cos) of every
+    // stage state, so that the recorded adjoint needs no recompute
+    int record_stages = 0;
+    bool rec_stages = false;
+    DevBuf d_rsc, d_rac;
     double rec_dt = 0.0;
     int64_t rec_nsteps = 0, rec_C = 0;
     uint64_t rec_gen = 0;
@@ -183,7 +188,7 @@ void free_all(kur_ctx *c)
                       &c->d_sc[1], &c->d_part[0], &c->d_part[1], &c->d_sce, &c->d_parte, &c->d_kout, &c->d_y,
                       &c->d_r, &c->d_psi, &c->d_tile_first, &c->d_inv_n, &c->d_ctr, &c->d_ck,
                       &c->d_blkT, &c->d_segdT, &c->d_grpT, &c->d_tilesT, &c->d_orderT, &c->d_segT,
-                      &c->d_listT, &c->d_iptrT, &c->d_icolT};
+                      &c->d_listT, &c->d_iptrT, &c->d_icolT, &c->d_rsc, &c->d_rac};
     for (DevBuf *b : bufs) dfree(*b);
     c->has_T = false;
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -687,6 +692,9 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "compensate must be 0 or 1");
         c->compensate = (int)v;
         c->gen++;
+    } else if (k == "record_stages") {
+        if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "record_stages must be 0 or 1");
+        c->record_stages = (int)v;
     } else if (k == "checkpoint_every") {
         if (v != (int64_t)v || v < 0 || v > 1e9) return fail(c, KUR_EINVAL, "checkpoint_every must be an integer >= 0");
         c->ckpt_every = (int64_t)v;
@@ -1057,15 +1065,31 @@ static hipError_t launch_sample(kur_ctx *c, const int64_t *idx_dev, int64_t idx)
                                       c->n_inst, (double *)c->d_r.p, (double *)c->d_psi.p, idx_dev, idx, c->stream);
 }
 
-static hipError_t launch_step(kur_ctx *c, const DevGraph &g, double dt)
+// One RK4 step. With rsc/rac (a recording run with option "record_stages"), the stage inputs'
+// (sin, cos) are read from and written to rsc[4 s + i - 1] (step s, stage i) instead of the
+// context's double buffer, and their row sums go to rac[4 s + i - 1].
+static hipError_t launch_step(kur_ctx *c, const DevGraph &g, double dt, char *rsc = nullptr, char *rac = nullptr,
+                              int64_t step = 0)
 {
+    const size_t P = 2 * (size_t)c->esz * (size_t)c->n;
     for (int stage = 1; stage <= 4; ++stage) {
         hipError_t e;
+        const int64_t i = 4 * step + stage;
         if (c->esz == 4) {
             RowArgs<float> a = row_args<float>(c, stage, dt);
+            if (rsc) {
+                a.sc_in = rsc + (size_t)(i - 1) * P;
+                a.sc_out = rsc + (size_t)i * P;
+                a.ac_out = rac + (size_t)(i - 1) * P;
+            }
             e = timed_rows(c, g, &a);
         } else {
             RowArgs<double> a = row_args<double>(c, stage, dt);
+            if (rsc) {
+                a.sc_in = rsc + (size_t)(i - 1) * P;
+                a.sc_out = rsc + (size_t)i * P;
+                a.ac_out = rac + (size_t)(i - 1) * P;
+            }
             e = timed_rows(c, g, &a);
         }
         if (e != hipSuccess) return e;
@@ -1132,11 +1156,29 @@ static kur_status run_steps(kur_ctx *c, double dt, int64_t nsteps, int64_t r_eve
     const int64_t period = r_every > 0 ? r_every : std::max<int64_t>(1, c->graph_steps);
     const int64_t reps = nsteps / period;
     const int64_t C = c->batch ? 0 : c->ckpt_every;  // record checkpoints: plain launches
+    const bool stages = C > 0 && c->record_stages;
+    const size_t P = 2 * (size_t)c->esz * (size_t)c->n;  // bytes of one (sin, cos) or row-sum slot
     if (C > 0) {
         const size_t TN = (size_t)c->esz * (size_t)c->n;
         const int64_t nseg = nsteps > 0 ? (nsteps + C - 1) / C : 0;
         c->rec_valid = false;
+        c->rec_stages = false;
         if ((e = dalloc(c->d_ck, 2 * TN * (size_t)std::max<int64_t>(nseg, 1))) != hipSuccess) return hip_fail(c, e, "checkpoints");
+        if (!stages) {
+            dfree(c->d_rsc);  // a previous stage record
+            dfree(c->d_rac);
+        } else {
+            if ((e = dalloc(c->d_rsc, P * (size_t)(4 * nsteps + 1))) != hipSuccess ||
+                (e = dalloc(c->d_rac, P * (size_t)std::max<int64_t>(4 * nsteps, 1))) != hipSuccess) {
+                dfree(c->d_rsc);
+                dfree(c->d_rac);
+                return fail(c, KUR_ENOMEM, "device memory for the stage record (" +
+                                               std::to_string((double)P * (8.0 * nsteps + 1) / 1e9) +
+                                               " GB): lower nsteps or set record_stages to 0");
+            }
+            if ((e = hipMemcpyAsync(c->d_rsc.p, c->d_sc[c->cur].p, P, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+                return hip_fail(c, e, "stage record");
+        }
     }
     if (C == 0 && c->use_graph && !c->timing && reps >= 2) {
         if (r_every > 0) {
@@ -1159,14 +1201,20 @@ static kur_status run_steps(kur_ctx *c, double dt, int64_t nsteps, int64_t r_eve
                 (e = hipMemcpyAsync(ck + TN, c->d_lo.p, TN, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
                 return hip_fail(c, e, "checkpoint copy");
         }
-        if ((e = launch_step(c, g, dt)) != hipSuccess) return hip_fail(c, e, "rk4 stage launch");
+        if ((e = stages ? launch_step(c, g, dt, (char *)c->d_rsc.p, (char *)c->d_rac.p, step) : launch_step(c, g, dt)) !=
+            hipSuccess)
+            return hip_fail(c, e, "rk4 stage launch");
         if (r_every > 0 && (step + 1) % r_every == 0) {
             if ((e = launch_sample(c, nullptr, k)) != hipSuccess) return hip_fail(c, e, "order parameter launch");
             ++k;
         }
     }
+    if (stages && (e = hipMemcpyAsync(c->d_sc[c->cur].p, (char *)c->d_rsc.p + (size_t)(4 * nsteps) * P, P,
+                                      hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "stage record");
     if (C > 0) {
         c->rec_valid = true;
+        c->rec_stages = stages;
         c->rec_dt = dt;
         c->rec_nsteps = nsteps;
         c->rec_C = C;
@@ -1569,17 +1617,22 @@ struct AdjBufs {
 
 // theta0_user: start of the forward run (then the forward pass runs here); ck_ext: device
 // checkpoints recorded by kur_step_rk4 instead (then theta0_user is unused).
+// rec_sc, rec_ac: the stage record of that run (option "record_stages"), or null: then no
+// segment is recomputed and the reverse sweep reads the recorded stage states.
 template <typename T>
 kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ext, double dt, int64_t nsteps,
-                        int64_t C, const double *seed_user, double *g_theta0, double *g_omega, double *g_K)
+                        int64_t C, const double *seed_user, double *g_theta0, double *g_omega, double *g_K,
+                        const void *rec_sc = nullptr, const void *rec_ac = nullptr)
 {
     using std::vector;
     const int64_t n = c->n;
     const int nt = c->ntiles;
     const size_t TN = sizeof(T) * (size_t)n;
     hipStream_t st = c->stream;
+    const bool stored = rec_sc != nullptr;
+    if (stored) C = std::max<int64_t>(nsteps, 1);  // one segment: the whole recorded run
     const int64_t nseg = nsteps > 0 ? (nsteps + C - 1) / C : 0;
-    const int64_t nslot = 4 * std::min<int64_t>(C, std::max<int64_t>(nsteps, 1)) + 1;
+    const int64_t nslot = stored ? 1 : 4 * std::min<int64_t>(C, std::max<int64_t>(nsteps, 1)) + 1;
     // asymmetric A: the Jacobian-transpose gathers run over the layout of A^T (its own tiles)
     const bool asym = !c->symmetric;
     const int ntv = asym ? c->ntT : nt;
@@ -1638,8 +1691,12 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
         a.ac_out = ac_out;
         return launch_rows<T>(g, nt, a, c->threads, st);
     };
-    auto slot = [&](int64_t i) -> void * { return (char *)B.slots.p + (size_t)i * 2 * TN; };
-    auto acslot = [&](int64_t i) -> void * { return (char *)B.acs.p + (size_t)i * 2 * TN; };
+    auto slot = [&](int64_t i) -> void * {
+        return (stored ? (char *)rec_sc : (char *)B.slots.p) + (size_t)i * 2 * TN;
+    };
+    auto acslot = [&](int64_t i) -> void * {
+        return (stored ? (char *)rec_ac : (char *)B.acs.p) + (size_t)i * 2 * TN;
+    };
 
     const char *ckbase = ck_ext ? (const char *)ck_ext : (const char *)B.ck.p;
     // forward pass, keeping (hi, lo) every C steps (unless recorded by the caller's run)
@@ -1667,23 +1724,25 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
     const T tdt = (T)dt;
     for (int64_t seg = nseg - 1; seg >= 0; --seg) {
         const int64_t s0 = seg * C, len = std::min<int64_t>(C, nsteps - s0);
-        const char *ck = ckbase + (size_t)seg * 2 * TN;
-        if ((e = hipMemcpyAsync(B.hi.p, ck, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
-            (e = hipMemcpyAsync(B.lo.p, ck + TN, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess)
-            return hip_fail(c, e, "adjoint restore");
-        // recompute the segment, keeping (sin, cos) of every stage state and its row sums
-        // (A sin, A cos): Y_i of step k at slot 4k+i-1
-        int cur = 0;
-        if ((e = launch_sc_init<T>(g, nt, (const T *)B.hi.p, slot(0), B.fpart[0].p, c->threads, st)) != hipSuccess)
-            return hip_fail(c, e, "adjoint recompute");
-        for (int64_t k = 0; k < len; ++k)
-            for (int stage = 1; stage <= 4; ++stage) {
-                const int64_t i = 4 * k + stage;
-                if ((e = rows(stage, slot(i - 1), B.fpart[cur].p, slot(i), B.fpart[cur ^ 1].p, acslot(i - 1))) !=
-                    hipSuccess)
-                    return hip_fail(c, e, "adjoint recompute");
-                cur ^= 1;
-            }
+        if (!stored) {
+            const char *ck = ckbase + (size_t)seg * 2 * TN;
+            if ((e = hipMemcpyAsync(B.hi.p, ck, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+                (e = hipMemcpyAsync(B.lo.p, ck + TN, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+                return hip_fail(c, e, "adjoint restore");
+            // recompute the segment, keeping (sin, cos) of every stage state and its row sums
+            // (A sin, A cos): Y_i of step k at slot 4k+i-1
+            int cur = 0;
+            if ((e = launch_sc_init<T>(g, nt, (const T *)B.hi.p, slot(0), B.fpart[0].p, c->threads, st)) != hipSuccess)
+                return hip_fail(c, e, "adjoint recompute");
+            for (int64_t k = 0; k < len; ++k)
+                for (int stage = 1; stage <= 4; ++stage) {
+                    const int64_t i = 4 * k + stage;
+                    if ((e = rows(stage, slot(i - 1), B.fpart[cur].p, slot(i), B.fpart[cur ^ 1].p, acslot(i - 1))) !=
+                        hipSuccess)
+                        return hip_fail(c, e, "adjoint recompute");
+                    cur ^= 1;
+                }
+        }
         for (int64_t k = len - 1; k >= 0; --k) {
             VjpArgs<T> v;
             v.K = (T)c->K;
@@ -1964,10 +2023,11 @@ extern "C" kur_status kur_adjoint_rk4_recorded(kur_ctx *c, const double *dl_dthe
     for (int64_t u = 0; u < c->n; ++u)
         if (!std::isfinite(dl_dthetaT[u])) return fail(c, KUR_EINVAL, "dl_dthetaT must be finite");
     try {
+        const void *rsc = c->rec_stages ? c->d_rsc.p : nullptr, *rac = c->rec_stages ? c->d_rac.p : nullptr;
         return c->esz == 4 ? adjoint_impl<float>(c, nullptr, c->d_ck.p, c->rec_dt, c->rec_nsteps, c->rec_C, dl_dthetaT,
-                                                 g_theta0, g_omega, g_K)
+                                                 g_theta0, g_omega, g_K, rsc, rac)
                            : adjoint_impl<double>(c, nullptr, c->d_ck.p, c->rec_dt, c->rec_nsteps, c->rec_C, dl_dthetaT,
-                                                  g_theta0, g_omega, g_K);
+                                                  g_theta0, g_omega, g_K, rsc, rac);
     } catch (const std::bad_alloc &) {
         return fail(c, KUR_ENOMEM, "host allocation failed in the adjoint");
     }

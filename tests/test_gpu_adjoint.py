@@ -231,6 +231,43 @@ def test_recorded_adjoint_matches_full_adjoint(need_gpu):
                 k.adjoint_recorded(seed)
 
 
+@pytest.mark.parametrize("asym", [False, True])
+def test_recorded_stages_adjoint(need_gpu, asym):
+    """With option record_stages the recording run keeps every stage state and the recorded
+    adjoint recomputes nothing: the gradients equal bit for bit those of the checkpoint path
+    (both use the same stage states); the run itself, its r samples and the steps after it equal
+    those of a plain run bit for bit."""
+    w = asymmetric_workload(41) if asym else ragged_sbm(9)
+    n = w.graph.n
+    seed = np.random.default_rng(4).standard_normal(n)
+    opts = dict(transpose=1) if asym else {}
+    for dtype in ("f64", "f32"):
+        with ctx(w, dtype, **opts) as k:
+            r0, _ = k.step_rk4(w.dt, 30, r_every=5)
+            th0 = k.get_phases(wrapped=False)
+            k.step_rk4(w.dt, 7)
+            th_a = k.get_phases(wrapped=False)
+        with ctx(w, dtype, **opts) as k:
+            k.set_option("checkpoint_every", 8)
+            k.set_option("record_stages", 1)
+            r1, _ = k.step_rk4(w.dt, 30, r_every=5)
+            k.set_option("checkpoint_every", 0)
+            assert np.array_equal(r0, r1)
+            assert np.array_equal(k.get_phases(wrapped=False), th0)
+            a = k.adjoint_recorded(seed)
+            k.step_rk4(w.dt, 7)
+            assert np.array_equal(k.get_phases(wrapped=False), th_a)
+        with ctx(w, dtype, **opts) as k:
+            k.set_option("checkpoint_every", 8)
+            k.step_rk4(w.dt, 30)
+            k.set_option("checkpoint_every", 0)
+            b = k.adjoint_recorded(seed)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+        if dtype == "f64":
+            go = oracle.adjoint_rk4(w.graph, w.omega, w.K, w.theta0, w.dt, 30, seed)
+            assert np.abs(a[0] - go[0]).max() <= 1e-10 * np.abs(go[0]).max()
+
+
 def test_autograd_two_forwards(need_gpu):
     """Backward of an earlier forward after a later one on the same model still gets its own
     gradients (the recording belongs to the later run, so the adjoint repeats the forward)."""
