@@ -20,15 +20,18 @@ def _host(t) -> np.ndarray:
 
 class KuramotoRK4(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, theta0, omega, K, model: Kuramoto, dt: float, nsteps: int, ckpt_every: int = 32):
+    def forward(ctx, theta0, omega, K, model: Kuramoto, dt: float, nsteps: int, ckpt_every: int = 32,
+                record_stages: bool = False):
         th0 = _host(theta0)
         om = _host(omega)
         k = float(K)
         model.set_params(om, k)
         model.set_phases(th0)
         model.set_option("checkpoint_every", ckpt_every)  # keep checkpoints for the backward pass
+        model.set_option("record_stages", 1 if record_stages else 0)  # and every stage state
         model.step_rk4(dt, nsteps)
         model.set_option("checkpoint_every", 0)
+        model.set_option("record_stages", 0)
         ctx.rec = model.recorded_run()[0]
         thT = model.get_phases(wrapped=False)
         ctx.model, ctx.dt, ctx.nsteps, ctx.ckpt = model, dt, nsteps, ckpt_every
@@ -48,12 +51,15 @@ class KuramotoRK4(torch.autograd.Function):
             gt, gw, gk = m.adjoint_rk4(ctx.dt, ctx.nsteps, seed, theta0=ctx.th0, ckpt_every=ctx.ckpt)
         to = dict(device=ctx.dev, dtype=ctx.dtype)
         g_k = torch.tensor(gk, **to) if ctx.k_is_tensor else None
-        return torch.from_numpy(gt).to(**to), torch.from_numpy(gw).to(**to), g_k, None, None, None, None
+        return torch.from_numpy(gt).to(**to), torch.from_numpy(gw).to(**to), g_k, None, None, None, None, None
 
 
-def integrate(model: Kuramoto, theta0, omega, K, dt: float, nsteps: int, ckpt_every: int = 32):
-    """theta(T) as a differentiable function of (theta0, omega, K)."""
-    return KuramotoRK4.apply(theta0, omega, K, model, dt, nsteps, ckpt_every)
+def integrate(model: Kuramoto, theta0, omega, K, dt: float, nsteps: int, ckpt_every: int = 32,
+              record_stages: bool = False):
+    """theta(T) as a differentiable function of (theta0, omega, K). record_stages: the forward
+    run keeps every stage state (16 n reals per step of device memory) and the backward pass
+    recomputes nothing."""
+    return KuramotoRK4.apply(theta0, omega, K, model, dt, nsteps, ckpt_every, record_stages)
 
 
 def order_parameter(theta):

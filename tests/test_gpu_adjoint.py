@@ -185,7 +185,8 @@ def test_adjoint_config5_central_differences(need_gpu):
         assert abs(gk - fd) <= 1e-4 * max(abs(fd), 1e-2 * gmax) + noise, (gk, fd)
 
 
-def test_autograd_function(need_gpu):
+@pytest.mark.parametrize("record_stages", [False, True])
+def test_autograd_function(need_gpu, record_stages):
     import torch
     from paper_2102_07167_amd.autograd import integrate, order_parameter
     w = ragged_sbm(9)
@@ -193,7 +194,7 @@ def test_autograd_function(need_gpu):
         th0 = torch.tensor(w.theta0, requires_grad=True)
         om = torch.tensor(w.omega, requires_grad=True)
         K = torch.tensor(w.K, dtype=torch.float64, requires_grad=True)
-        thT = integrate(k, th0, om, K, w.dt, w.steps, ckpt_every=8)
+        thT = integrate(k, th0, om, K, w.dt, w.steps, ckpt_every=8, record_stages=record_stages)
         tgt = torch.tensor(w.target)
         loss = (1 - order_parameter(thT)) ** 2 + (2 * (1 - torch.cos(thT - tgt))).mean()
         loss.backward()
