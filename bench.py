@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--option", action="append", default=[], help="library option key=value")
+    ap.add_argument("--dtype", choices=["f32", "f64"], default=None,
+                    help="arithmetic type of the single-graph workloads (default: f64 for a2a, else f32)")
     ap.add_argument("--tune-effort", type=int, default=1, choices=[-1, 0, 1, 2],
                     help="layout autotuning effort (-1: defaults and --option values only)")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
@@ -281,7 +283,7 @@ def main():
     t0 = time.perf_counter()
     w = make_workload(args.workload)
     log("workload %s generated in %.1f s (nnz %d)" % (w.name, time.perf_counter() - t0, w.graph.nnz))
-    dtype = "f64" if args.workload == "a2a" else "f32"
+    dtype = args.dtype or ("f64" if args.workload == "a2a" else "f32")
     elem = 8 if dtype == "f64" else 4
     k = Kuramoto(dtype, device=0)
     for kv in args.option:
