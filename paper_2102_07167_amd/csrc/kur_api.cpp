@@ -1722,28 +1722,23 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
 
     // reverse sweep, segment by segment
     const T tdt = (T)dt;
-    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-        const int64_t s0 = seg * C, len = std::min<int64_t>(C, nsteps - s0);
-        if (!stored) {
-            const char *ck = ckbase + (size_t)seg * 2 * TN;
-            if ((e = hipMemcpyAsync(B.hi.p, ck, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
-                (e = hipMemcpyAsync(B.lo.p, ck + TN, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess)
-                return hip_fail(c, e, "adjoint restore");
-            // recompute the segment, keeping (sin, cos) of every stage state and its row sums
-            // (A sin, A cos): Y_i of step k at slot 4k+i-1
-            int cur = 0;
-            if ((e = launch_sc_init<T>(g, nt, (const T *)B.hi.p, slot(0), B.fpart[0].p, c->threads, st)) != hipSuccess)
-                return hip_fail(c, e, "adjoint recompute");
-            for (int64_t k = 0; k < len; ++k)
-                for (int stage = 1; stage <= 4; ++stage) {
-                    const int64_t i = 4 * k + stage;
-                    if ((e = rows(stage, slot(i - 1), B.fpart[cur].p, slot(i), B.fpart[cur ^ 1].p, acslot(i - 1))) !=
-                        hipSuccess)
-                        return hip_fail(c, e, "adjoint recompute");
-                    cur ^= 1;
-                }
-        }
-        for (int64_t k = len - 1; k >= 0; --k) {
+    // recompute a segment of len steps from (hi, lo), keeping (sin, cos) of every stage state and
+    // its row sums (A sin, A cos): Y_i of step k at slot 4k+i-1
+    auto recompute = [&](int64_t len) -> hipError_t {
+        hipError_t r = launch_sc_init<T>(g, nt, (const T *)B.hi.p, slot(0), B.fpart[0].p, c->threads, st);
+        int cur = 0;
+        for (int64_t k = 0; k < len && r == hipSuccess; ++k)
+            for (int stage = 1; stage <= 4 && r == hipSuccess; ++stage) {
+                const int64_t i = 4 * k + stage;
+                r = rows(stage, slot(i - 1), B.fpart[cur].p, slot(i), B.fpart[cur ^ 1].p, acslot(i - 1));
+                cur ^= 1;
+            }
+        return r;
+    };
+    // the reverse steps len-1 .. 0 of a segment (slots as above)
+    auto sweep = [&](int64_t len) -> hipError_t {
+        hipError_t r = hipSuccess;
+        for (int64_t k = len - 1; k >= 0 && r == hipSuccess; --k) {
             VjpArgs<T> v;
             v.K = (T)c->K;
             v.inv_n = (T)(1.0 / (double)n);
@@ -1764,8 +1759,8 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
             v.part_in = nullptr;
             v.x_out = B.x[0].p;
             v.part_out = B.xpart[0].p;
-            if ((e = launch_vjp_init<T>(gv, ntv, v, c->threads, st)) != hipSuccess) return hip_fail(c, e, "adjoint init");
-            for (int i = 4; i >= 1; --i) {
+            r = launch_vjp_init<T>(gv, ntv, v, c->threads, st);
+            for (int i = 4; i >= 1 && r == hipSuccess; --i) {
                 v.stage = i;
                 // l_{i-1} = cl lam + cm mu_i: (dt/3, dt), (dt/3, dt/2), (dt/6, dt/2)
                 v.cl = i == 4 ? (T)(dt / 3.0) : i == 3 ? (T)(dt / 3.0) : (T)(dt / 6.0);
@@ -1777,10 +1772,22 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
                 v.part_in = B.xpart[xc].p;
                 v.x_out = B.x[xc ^ 1].p;
                 v.part_out = B.xpart[xc ^ 1].p;
-                if ((e = launch_vjp<T>(gv, ntv, v, c->threads, st)) != hipSuccess) return hip_fail(c, e, "adjoint stage");
+                r = launch_vjp<T>(gv, ntv, v, c->threads, st);
                 xc ^= 1;
             }
         }
+        return r;
+    };
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t s0 = seg * C, len = std::min<int64_t>(C, nsteps - s0);
+        if (!stored) {
+            const char *ck = ckbase + (size_t)seg * 2 * TN;
+            if ((e = hipMemcpyAsync(B.hi.p, ck, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+                (e = hipMemcpyAsync(B.lo.p, ck + TN, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+                return hip_fail(c, e, "adjoint restore");
+            if ((e = recompute(len)) != hipSuccess) return hip_fail(c, e, "adjoint recompute");
+        }
+        if ((e = sweep(len)) != hipSuccess) return hip_fail(c, e, "adjoint stage");
     }
 
     // results
