@@ -177,7 +177,7 @@ def bench_ensemble(args):
     import gen
     from paper_2102_07167_amd import Kuramoto
     B = args.replicas
-    w = gen.sbm_equal(seed=1002)
+    w = gen.sbm_paired_workload() if args.ens_graph == "paired" else gen.sbm_equal(seed=1002)
     g = w.graph
     rng = np.random.default_rng(1006)
     K = np.linspace(0.0, 6.0, B)
@@ -218,17 +218,18 @@ def bench_ensemble(args):
            "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "%d replicas of the equal-community SBM N=65536 (64 x 1024, rho 0.97, p_out 2e-4), "
+           "config": {"workload": "%d replicas of the %s N=65536 (64 x 1024, rho 0.97, p_out 2e-4%s), "
                                   "K=linspace(0,6,%d), omega~N(0,1), theta0~U[0,2pi) per replica, dt=0.01, r every 10 "
-                                  "steps, seed 1006" % (B, B), "layout": info, "tuning": tuning}}
+                                  "steps, seed 1006" % (
+                                      B, "paired SBM" if args.ens_graph == "paired" else "equal-community SBM",
+                                      ", communities 2i and 2i+1 joined at density 0.9" if args.ens_graph == "paired"
+                                      else "", B), "layout": info, "tuning": tuning}}
     if kt["gemm_launches"] > 0:
-        # issued matrix-core work per launch: every 256 x 128 output tile of a block runs over
-        # the block's width padded to 32, with three bf16 terms and 2 flops per multiply-add
-        modes, _ = k.ens_block_modes()
-        sizes = np.bincount(np.unique(g.labels, return_inverse=True)[1])
+        # issued matrix-core work per launch: every 256 x 128 output tile of a row block runs
+        # over its ranges' widths, each padded to 32, with three bf16 terms and 2 flops per
+        # multiply-add
         J = 2 * info["Bp"]
-        issued = sum(2.0 * 3 * 256 * 128 * (-(-s // 32) * 32) * (-(-s // 256)) * (J // 128)
-                     for s, m in zip(sizes, modes) if m)
+        issued = 2.0 * 3 * info["gemm_cells_issued"] * J
         useful = 2.0 * info["gemm_pairs"] * 2 * B
         gms = kt["gemm_ms"] / kt["gemm_launches"]
         out["roofline"] = {"bound": "mfma", "achieved": issued / (gms * 1e-3) / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
@@ -247,6 +248,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="het", choices=["het", "sbm", "a2a", "pairs", "batch", "ens"])
     ap.add_argument("--replicas", type=int, default=128, help="replicas of the ensemble workload (1..256)")
+    ap.add_argument("--ens-graph", choices=["sbm", "paired"], default="sbm",
+                    help="graph of the ensemble workload: the equal-community SBM or the paired SBM")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",

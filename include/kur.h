@@ -118,9 +118,9 @@ const char *kur_last_error(const kur_ctx *ctx);
  *   "graph"       1 (default): kur_step_rk4 captures one sampling period (r_every steps, else
  *                 "graph_steps" steps) into a HIP graph and replays it; 0: plain launches.
  *   "graph_steps" steps per replayed graph when no order parameter is sampled (default 16).
- *   "ens_tau"     shared-graph ensembles: blocks at least this dense form their products on the
- *                 matrix cores (0..2, above 1: none). Default 0.5. Takes effect at the next
- *                 kur_ens_set_graph_csr.
+ *   "ens_tau"     shared-graph ensembles: blocks (and off-diagonal blocks, see below) at least
+ *                 this dense form their products on the matrix cores (0..2, above 1: none).
+ *                 Default 0.5. Takes effect at the next kur_ens_set_graph_csr.
  * Unknown keys and out-of-range values return KUR_EINVAL.
  */
 kur_status kur_set_option(kur_ctx *ctx, const char *key, double value);
@@ -408,10 +408,12 @@ kur_status kur_tune_key(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const i
  * phases, integrated together with classical RK4. The replicas' coupling sums of a row are the
  * row of A X with X = [sin Theta, cos Theta] (n x 2B), the sums of eq.
  * KuramotoGraphReformulation for all replicas at once. For every community block whose realised
- * density is at least the option "ens_tau" (default 0.5; above 1: none) this is a dense matrix
- * product A_b X_b, run on the matrix cores (0/1 pattern stored as a bitmask, X split exactly into
- * three bf16 terms, FP32 accumulation); the remaining blocks' edges and all inter-block edges are
- * summed as CSR rows (Sec. 3: block structure with dense and sparse parts). Replica e follows
+ * density is at least the option "ens_tau" (default 0.5; above 1: none), and every off-diagonal
+ * block of two communities of at least 32 nodes whose density is at least max(ens_tau, 0.01),
+ * this is a dense matrix product A_{a,c} X_c, run on the matrix cores (0/1 pattern stored as a
+ * bitmask, X split exactly into three bf16 terms, FP32 accumulation; the products of one row
+ * community accumulate in one pass); all other edges are summed as CSR rows (Sec. 3: block
+ * structure with dense and sparse parts, and its extension to submatrices). Replica e follows
  * d theta_m / dt = omega_{e,m} + (K_e / N) sum_l A_ml sin(theta_l - theta_m).
  * FP32 contexts only (KUR_EINVAL otherwise). Independent of the single-system graph and state.
  *
@@ -424,16 +426,19 @@ kur_status kur_tune_key(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const i
  *                        (nsteps / r_every + 1) x B, sample-major, may be NULL) receive the order
  *                        parameter of every replica at step 0 and every r_every steps
  * kur_ens_get_phases     theta (B x n), wrapped to [-pi, pi) or unwrapped (winding counts)
- * kur_ens_info           out[10]: n, blocks, matrix-core blocks, their rows, sum of their
- *                        squared sizes, CSR entries, B, B padded to 64, matrix-product work
- *                        items, symmetric
- * kur_ens_block_modes    per block (either may be NULL): 1 if on the matrix cores, realised density
+ * kur_ens_info           out[12]: n, blocks, matrix-core row blocks, their rows, cells of their
+ *                        products (sum of rows x columns), CSR entries, B, B padded to 64,
+ *                        matrix-product work items, symmetric, off-diagonal blocks on the matrix
+ *                        cores, cells the product tiles issue (rows padded to 256, columns of
+ *                        every range to 32)
+ * kur_ens_block_modes    per block (either may be NULL): 1 if its own block is on the matrix
+ *                        cores, realised density of its own block
  * kur_ens_get_perm       user node -> block-order row (n)
  * kur_ens_row_pattern    host-only contexts: block-order row m's CSR columns (block order) into
  *                        csr_cols, which holds *ncsr entries on entry (NULL: count only; too few:
- *                        KUR_EINVAL); *ncsr receives the count. If the row's block is on the
- *                        matrix cores, dense (block size bytes, may be NULL) receives its 0/1
- *                        pattern over the block
+ *                        KUR_EINVAL); *ncsr receives the count. dense (n bytes, block order,
+ *                        may be NULL) receives the row's 0/1 pattern on the columns of its
+ *                        matrix-core products and 0 elsewhere
  * kur_ens_kernel_time    with option "timing" = 1: out[4] = matrix-product launches, their total
  *                        ms, row-kernel launches, their total ms, since the previous call
  * kur_ens_autotune_csr   times RK4 steps of B replicas (synthetic values) for candidate

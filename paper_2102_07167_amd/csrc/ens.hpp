@@ -9,12 +9,26 @@
 
 namespace kur {
 
-// A diagonal block whose product A_b X_b runs on the matrix cores.
+// A row block (community) whose products run on the matrix cores: A_{a,c} X_c for every column
+// community c of its ranges (its own block when dense and its dense off-diagonal blocks, in
+// block order). The ranges are laid end to end along k, each padded to a multiple of 32 columns.
 struct EnsBlk {
     int64_t bits_off;  // first 32-bit word of the block's 0/1 pattern (row-major)
     int32_t row0;      // first block-order row
-    int32_t size;      // rows = columns
-    int32_t words;     // words per pattern row = ceil(size / 32); bit (k & 31) of word k / 32 is A(row, k)
+    int32_t size;      // rows
+    int32_t words;     // words per pattern row (k extent / 32); bit (k & 31) of word k / 32 is the
+                       // entry at position k along the ranges
+    int32_t rng0;      // first range (EnsRng) of this block
+    int32_t nrng;      // ranges
+    int32_t pad;
+};
+
+// One column range of a matrix-core row block: k in [koff, koff + len) are the block-order
+// columns col0 .. col0 + len - 1; k up to the next multiple of 32 is padding (pattern bits 0).
+struct EnsRng {
+    int32_t koff;
+    int32_t col0;
+    int32_t len;
     int32_t pad;
 };
 
@@ -29,6 +43,7 @@ constexpr int kEnsTileCols = 128;
 
 struct EnsGemmArgs {
     const EnsBlk *blk;
+    const EnsRng *rng;
     const EnsItem *items;
     const uint32_t *bits;
     const float *x;  // [n][J]: sin of every replica, then cos (J = 2 Bp)
@@ -44,7 +59,7 @@ struct EnsRowArgs {
     float dt, half_dt, dt6;
     const int64_t *csr_ptr;  // n + 1, block order
     const int32_t *csr_col;  // block-order columns
-    const uint8_t *row_gemm; // 1 where y holds the row's dense-block product
+    const uint8_t *row_gemm; // 1 where y holds the row's matrix-core products
     const float *x;          // [n][J] stage input (sin | cos)
     const float *y;
     float *x_out;            // [n][J] next stage input (sin | cos)

@@ -1,9 +1,12 @@
 // ens_kernels.hip -- gfx950 kernels of the shared-graph ensemble path.
 //
 // With B replicas of one graph, the coupling sums of a row for all replicas at once are the row
-// of A X with X = [sin Theta, cos Theta] (n x 2B). For a dense community block this is a real
-// matrix product A_b X_b (Sec. 3: the block structure; eq. KuramotoGraphReformulation: the sine
-// difference expanded into sums of sin and cos), which k_ens_gemm runs on the matrix cores:
+// of A X with X = [sin Theta, cos Theta] (n x 2B). For a dense submatrix (a community block, or
+// a dense off-diagonal block of two communities) this is a real matrix product A_{a,c} X_c
+// (Sec. 3: the block structure and its extension to submatrices; eq.
+// KuramotoGraphReformulation: the sine difference expanded into sums of sin and cos). The
+// products of one row block's ranges accumulate in one pass along k; k_ens_gemm runs them on the
+// matrix cores:
 //   * A_b is 0/1 and stored as a bitmask; each lane expands one byte into eight bf16 ones and
 //     zeros, which are exact;
 //   * X is split exactly into three bf16 terms x = t0 + t1 + t2 (each the truncated upper half
@@ -71,7 +74,9 @@ __global__ __launch_bounds__(256) void k_ens_gemm(EnsGemmArgs a)
     const uint32_t *ab1 = a.bits + b.bits_off + (int64_t)(ok1 ? arow1 : 0) * b.words;
     // staging: thread -> one column, k groups sg and sg + 2 of each 32-wide step
     const int sc = tid & (kEnsTileCols - 1), sg = tid >> 7;
-    const float *xcol = a.x + (int64_t)b.row0 * a.J + it.c0 + sc;
+    const float *xbase = a.x + it.c0 + sc;
+    const EnsRng *rg = a.rng + b.rng0;
+    int rl = 0;  // range of the next load (k only grows; every 32-wide step lies in one range)
     f32x16 acc[2][4];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
@@ -83,14 +88,18 @@ __global__ __launch_bounds__(256) void k_ens_gemm(EnsGemmArgs a)
     const int kend = b.words * 32;
     float v[2][8];
     auto load = [&](int k0) {
+        while (rl + 1 < b.nrng && k0 >= rg[rl + 1].koff) ++rl;
+        const EnsRng R = rg[rl];
+        const float *xcol = xbase + (int64_t)R.col0 * a.J;
+        const int kl = k0 - R.koff;
 #pragma unroll
         for (int gi = 0; gi < 2; ++gi)
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 // unconditional load of a clamped row (no branch per load), then the mask
-                const int k = k0 + 8 * (sg + 2 * gi) + i;
-                const float t = xcol[(int64_t)(k < b.size ? k : b.size - 1) * a.J];
-                v[gi][i] = k < b.size ? t : 0.f;
+                const int k = kl + 8 * (sg + 2 * gi) + i;
+                const float t = xcol[(int64_t)(k < R.len ? k : R.len - 1) * a.J];
+                v[gi][i] = k < R.len ? t : 0.f;
             }
     };
     load(0);

@@ -17,7 +17,9 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/kur.h"
@@ -77,8 +79,12 @@ struct EnsLayout {
     std::vector<int32_t> perm;        // user node -> block-order row
     std::vector<int64_t> block_ptr;   // nb + 1
     std::vector<double> density;      // realised density per block
-    std::vector<uint8_t> gemm;        // per block
-    std::vector<EnsBlk> gblk;         // matrix-core blocks, largest first
+    std::vector<uint8_t> gemm;        // per block: its own (diagonal) block on the matrix cores
+    std::vector<EnsBlk> gblk;         // matrix-core row blocks, largest k extent first
+    std::vector<EnsRng> rng;          // their column ranges
+    std::vector<double> pair_density; // densities of the off-diagonal blocks that a threshold can
+                                      // put on the matrix cores (both sides >= kPairMin, >= kPairFloor)
+    int64_t n_pair_ranges = 0;        // dense off-diagonal blocks on the matrix cores
     std::vector<uint32_t> bits;
     std::vector<int64_t> csr_ptr;     // n + 1
     std::vector<int32_t> csr_col;
@@ -86,8 +92,17 @@ struct EnsLayout {
     int64_t gemm_rows = 0, gemm_pairs = 0;
 };
 
+// Off-diagonal blocks go on the matrix cores only with both communities of at least kPairMin
+// nodes and a density of at least max(threshold, kPairFloor): below about 1 % the CSR rows are
+// cheaper (a matrix-core cell costs about 1/100 of a gathered entry at B = 128), and the floor
+// bounds the pattern memory by the edge count.
+constexpr int64_t kPairMin = 32;
+constexpr double kPairFloor = 0.01;
+
 // Builds the ensemble layout; "" on success. Duplicate columns in a row are an error, diagonal
-// entries are ignored (A_mm = 0), as in the single-system builder.
+// entries are ignored (A_mm = 0), as in the single-system builder. A community's own block and
+// its off-diagonal blocks with density >= tau (see kPairMin, kPairFloor) become column ranges of
+// its matrix-core row block; every other edge goes to the CSR rows.
 std::string build_layout(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *labels, double tau,
                          EnsLayout &L)
 {
@@ -98,127 +113,137 @@ std::string build_layout(int64_t n, const int64_t *row_ptr, const int32_t *col, 
     L.symmetric = csr_symmetric(n, row_ptr, col);
     std::vector<int32_t> node_at, block_of_row;
     L.nb = regroup_by_labels(n, labels, L.perm, node_at, block_of_row, L.block_ptr);
-    int64_t smax = 0;
-    for (int32_t b = 0; b < L.nb; ++b) smax = std::max(smax, L.block_ptr[b + 1] - L.block_ptr[b]);
-    const int64_t words64 = (smax + 63) / 64 + 1;
+    const int32_t nb = L.nb;
+    auto bsize = [&](int32_t b) { return L.block_ptr[b + 1] - L.block_ptr[b]; };
 
-    std::vector<int64_t> ones_row(n), out_row(n);
-    std::atomic<bool> dup{false};
-    // pass 1: one entries inside the row's block (local bitmap, duplicates detected) and outside
-    parallel_for(n, [&](int64_t lo, int64_t hi) {
-        std::vector<uint64_t> bm(words64, 0);
-        for (int64_t m = lo; m < hi && !dup.load(); ++m) {
-            const int64_t u = node_at[m];
-            const int64_t r0 = L.block_ptr[block_of_row[m]], r1 = L.block_ptr[block_of_row[m] + 1];
-            int64_t in = 0, out = 0;
-            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
-                const int64_t pv = L.perm[col[e]];
-                if (pv == m) continue;
-                if (pv < r0 || pv >= r1) {
-                    ++out;
-                    continue;
+    // pass 1 (per row block): entries towards every column block; duplicates are found in pass 2
+    std::vector<std::vector<std::pair<int32_t, int64_t>>> cnt(nb);
+    parallel_for(nb, [&](int64_t lo, int64_t hi) {
+        std::unordered_map<int32_t, int64_t> h;
+        for (int64_t a = lo; a < hi; ++a) {
+            h.clear();
+            for (int64_t m = L.block_ptr[a]; m < L.block_ptr[a + 1]; ++m) {
+                const int64_t u = node_at[m];
+                for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                    const int64_t pv = L.perm[col[e]];
+                    if (pv != m) ++h[block_of_row[pv]];
                 }
-                const int64_t lc = pv - r0;
-                const uint64_t bit = uint64_t(1) << (lc & 63);
-                if (bm[lc >> 6] & bit) dup = true;
-                bm[lc >> 6] |= bit;
-                ++in;
             }
-            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
-                const int64_t pv = L.perm[col[e]];
-                if (pv >= r0 && pv < r1) bm[(pv - r0) >> 6] = 0;
-            }
-            ones_row[m] = in;
-            out_row[m] = out;
+            cnt[a].assign(h.begin(), h.end());
+            std::sort(cnt[a].begin(), cnt[a].end());
         }
     });
-    if (dup) return "duplicate column in a row";
 
-    L.density.assign(L.nb, 0.0);
-    L.gemm.assign(L.nb, 0);
+    // column ranges of every row block, in block order: its own block when dense and its dense
+    // partners (pass 2 walks the ranges and the sorted columns of a row together)
+    L.density.assign(nb, 0.0);
+    L.gemm.assign(nb, 0);
+    std::vector<std::vector<int32_t>> ranges(nb);
+    for (int32_t a = 0; a < nb; ++a) {
+        const int64_t s = bsize(a);
+        for (const auto &kv : cnt[a]) {
+            const int32_t c = kv.first;
+            if (c == a) {
+                const double pairs = (double)s * (double)(s - 1);
+                L.density[a] = pairs > 0 ? (double)kv.second / pairs : 0.0;
+                continue;
+            }
+            if (s < kPairMin || bsize(c) < kPairMin) continue;
+            const double rho = (double)kv.second / ((double)s * (double)bsize(c));
+            if (rho < kPairFloor) continue;
+            L.pair_density.push_back(rho);
+            if (rho >= tau) ranges[a].push_back(c);
+        }
+        L.gemm[a] = (s >= 2 && L.density[a] >= tau) ? 1 : 0;
+        L.n_pair_ranges += (int64_t)ranges[a].size();
+        if (L.gemm[a]) ranges[a].insert(std::lower_bound(ranges[a].begin(), ranges[a].end(), a), a);  // block order
+    }
+    // matrix-core row blocks and their ranges; bit position of (row block a, column block c)
+    std::vector<int32_t> gidx(nb, -1);
     int64_t words_total = 0;
-    std::vector<int64_t> bits_off(L.nb, -1);
-    for (int32_t b = 0; b < L.nb; ++b) {
-        const int64_t r0 = L.block_ptr[b], s = L.block_ptr[b + 1] - r0;
-        int64_t ones = 0;
-        for (int64_t m = r0; m < r0 + s; ++m) ones += ones_row[m];
-        const double pairs = (double)s * (double)(s - 1);
-        L.density[b] = pairs > 0 ? (double)ones / pairs : 0.0;
-        L.gemm[b] = (s >= 2 && L.density[b] >= tau) ? 1 : 0;
-        if (L.gemm[b]) {
-            bits_off[b] = words_total;
-            words_total += s * ((s + 31) / 32);
-            L.gemm_rows += s;
-            L.gemm_pairs += s * s;
-        }
-    }
-    L.row_gemm.assign(n, 0);
-    L.csr_ptr.assign(n + 1, 0);
-    for (int64_t m = 0; m < n; ++m) {
-        const bool g = L.gemm[block_of_row[m]] != 0;
-        L.row_gemm[m] = g ? 1 : 0;
-        L.csr_ptr[m + 1] = L.csr_ptr[m] + out_row[m] + (g ? 0 : ones_row[m]);
-    }
-    L.csr_col.assign((size_t)L.csr_ptr[n], 0);
-    L.bits.assign((size_t)words_total, 0u);
-
-    // pass 2: bitmask rows of matrix-core blocks, sorted CSR rows of everything else
-    parallel_for(n, [&](int64_t lo, int64_t hi) {
-        std::vector<uint64_t> bm(words64, 0);
-        std::vector<int32_t> outc;
-        for (int64_t m = lo; m < hi; ++m) {
-            const int32_t b = block_of_row[m];
-            const int64_t u = node_at[m];
-            const int64_t r0 = L.block_ptr[b], s = L.block_ptr[b + 1] - r0;
-            outc.clear();
-            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
-                const int64_t pv = L.perm[col[e]];
-                if (pv == m) continue;
-                if (pv < r0 || pv >= r0 + s) {
-                    outc.push_back((int32_t)pv);
-                    continue;
-                }
-                bm[(pv - r0) >> 6] |= uint64_t(1) << ((pv - r0) & 63);
-            }
-            std::sort(outc.begin(), outc.end());
-            for (size_t i = 1; i < outc.size(); ++i)
-                if (outc[i] == outc[i - 1]) dup = true;
-            int32_t *dst = L.csr_col.data() + L.csr_ptr[m];
-            size_t k = 0;
-            auto below = std::lower_bound(outc.begin(), outc.end(), (int32_t)r0);
-            for (auto it = outc.begin(); it != below; ++it) dst[k++] = *it;
-            const int64_t nw = (s + 63) / 64;
-            if (L.gemm[b]) {
-                uint32_t *row = L.bits.data() + bits_off[b] + (m - r0) * ((s + 31) / 32);
-                const int64_t w32 = (s + 31) / 32;
-                for (int64_t w = 0; w < w32; ++w) row[w] = (uint32_t)(bm[w >> 1] >> (32 * (w & 1)));
-            } else {
-                for (int64_t w = 0; w < nw; ++w) {
-                    uint64_t x = bm[w];
-                    while (x) {
-                        const int t = __builtin_ctzll(x);
-                        x &= x - 1;
-                        dst[k++] = (int32_t)(r0 + w * 64 + t);
-                    }
-                }
-            }
-            for (auto it = below; it != outc.end(); ++it) dst[k++] = *it;
-            for (int64_t w = 0; w < nw; ++w) bm[w] = 0;
-        }
-    });
-    if (dup) return "duplicate column in a row (inter-block entry)";
-
-    // matrix-core blocks, largest first (longest work items launch first)
-    for (int32_t b = 0; b < L.nb; ++b) {
-        if (!L.gemm[b]) continue;
+    for (int32_t a = 0; a < nb; ++a) {
+        if (ranges[a].empty()) continue;
         EnsBlk e{};
-        e.bits_off = bits_off[b];
-        e.row0 = (int32_t)L.block_ptr[b];
-        e.size = (int32_t)(L.block_ptr[b + 1] - L.block_ptr[b]);
-        e.words = (e.size + 31) / 32;
+        e.row0 = (int32_t)L.block_ptr[a];
+        e.size = (int32_t)bsize(a);
+        e.rng0 = (int32_t)L.rng.size();
+        e.nrng = (int32_t)ranges[a].size();
+        int64_t koff = 0;
+        for (int32_t c : ranges[a]) {
+            L.rng.push_back(EnsRng{(int32_t)koff, (int32_t)L.block_ptr[c], (int32_t)bsize(c), 0});
+            koff += (bsize(c) + 31) / 32 * 32;
+            L.gemm_pairs += (int64_t)e.size * bsize(c);
+        }
+        if (koff / 32 > INT32_MAX) return "matrix-core row block too wide";
+        e.words = (int32_t)(koff / 32);
+        e.bits_off = words_total;
+        words_total += (int64_t)e.size * e.words;
+        L.gemm_rows += e.size;
+        gidx[a] = (int32_t)L.gblk.size();
         L.gblk.push_back(e);
     }
-    std::stable_sort(L.gblk.begin(), L.gblk.end(), [](const EnsBlk &a, const EnsBlk &b) { return a.size > b.size; });
+    L.row_gemm.assign(n, 0);
+    for (int64_t m = 0; m < n; ++m) L.row_gemm[m] = gidx[block_of_row[m]] >= 0 ? 1 : 0;
+    L.bits.assign((size_t)words_total, 0u);
+
+    // pass 2: per row, its columns sorted; those inside a range set pattern bits, the others
+    // form the CSR row (counted first, then emitted)
+    std::vector<int64_t> csr_cnt(n, 0);
+    std::atomic<bool> dup{false};
+    auto row_pass = [&](bool emit) {
+        parallel_for(n, [&](int64_t lo, int64_t hi) {
+            std::vector<int32_t> cols;
+            for (int64_t m = lo; m < hi; ++m) {
+                const int32_t a = block_of_row[m];
+                const int64_t u = node_at[m];
+                cols.clear();
+                for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                    const int64_t pv = L.perm[col[e]];
+                    if (pv != m) cols.push_back((int32_t)pv);
+                }
+                std::sort(cols.begin(), cols.end());
+                if (!emit) {
+                    for (size_t i = 1; i < cols.size(); ++i)
+                        if (cols[i] == cols[i - 1]) dup = true;
+                }
+                const EnsBlk *g = gidx[a] >= 0 ? &L.gblk[gidx[a]] : nullptr;
+                uint32_t *bits = g && emit ? L.bits.data() + g->bits_off + (m - g->row0) * (int64_t)g->words : nullptr;
+                int32_t *dst = emit ? L.csr_col.data() + L.csr_ptr[m] : nullptr;
+                int64_t k = 0;
+                int32_t r = 0;  // ranges are in block order, as are the sorted columns
+                for (int32_t v : cols) {
+                    while (g && r < g->nrng && v >= L.rng[g->rng0 + r].col0 + L.rng[g->rng0 + r].len) ++r;
+                    if (g && r < g->nrng && v >= L.rng[g->rng0 + r].col0) {
+                        const EnsRng &R = L.rng[g->rng0 + r];
+                        if (bits) {
+                            const int64_t pos = R.koff + (v - R.col0);
+                            bits[pos >> 5] |= 1u << (pos & 31);
+                        }
+                        continue;
+                    }
+                    if (dst) dst[k] = v;
+                    ++k;
+                }
+                if (!emit) csr_cnt[m] = k;
+            }
+        });
+    };
+    row_pass(false);
+    if (dup) return "duplicate column in a row";
+    L.csr_ptr.assign(n + 1, 0);
+    for (int64_t m = 0; m < n; ++m) L.csr_ptr[m + 1] = L.csr_ptr[m] + csr_cnt[m];
+    L.csr_col.assign((size_t)L.csr_ptr[n], 0);
+    row_pass(true);
+
+    // longest work items launch first
+    std::vector<size_t> ord(L.gblk.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
+        return (int64_t)L.gblk[x].size * L.gblk[x].words > (int64_t)L.gblk[y].size * L.gblk[y].words;
+    });
+    std::vector<EnsBlk> sorted;
+    for (size_t i : ord) sorted.push_back(L.gblk[i]);
+    L.gblk.swap(sorted);
     return "";
 }
 
@@ -230,7 +255,7 @@ struct EnsState {
     EnsLayout L;
     bool has_graph = false;
     // device layout
-    DBuf d_gblk, d_bits, d_csr_ptr, d_csr_col, d_row_gemm, d_items;
+    DBuf d_gblk, d_rng, d_bits, d_csr_ptr, d_csr_col, d_row_gemm, d_items;
     int64_t nitems = 0;
     int64_t items_J = -1;
     // replicas
@@ -333,6 +358,7 @@ hipError_t launch_stage(kur_ctx *c, EnsState &S, int stage, double dt)
     if (S.nitems > 0) {
         EnsGemmArgs g;
         g.blk = S.d_gblk.as<EnsBlk>();
+        g.rng = S.d_rng.as<EnsRng>();
         g.items = S.d_items.as<EnsItem>();
         g.bits = S.d_bits.as<uint32_t>();
         g.x = S.d_x[S.cur].as<float>();
@@ -401,6 +427,7 @@ kur_status install_layout(kur_ctx *c, EnsState &S, EnsLayout &L)
         hipError_t e;
         if ((e = hipSetDevice(ctx_device(c))) != hipSuccess ||
             (e = put(S.d_gblk, S.L.gblk.data(), sizeof(EnsBlk) * S.L.gblk.size(), st)) != hipSuccess ||
+            (e = put(S.d_rng, S.L.rng.data(), sizeof(EnsRng) * S.L.rng.size(), st)) != hipSuccess ||
             (e = put(S.d_bits, S.L.bits.data(), 4 * S.L.bits.size(), st)) != hipSuccess ||
             (e = put(S.d_csr_ptr, S.L.csr_ptr.data(), 8 * S.L.csr_ptr.size(), st)) != hipSuccess ||
             (e = put(S.d_csr_col, S.L.csr_col.data(), 4 * S.L.csr_col.size(), st)) != hipSuccess ||
@@ -579,6 +606,10 @@ kur_status kur_ens_info(kur_ctx *c, int64_t *out)
     out[7] = S->Bp;
     out[8] = S->nitems;
     out[9] = L.symmetric ? 1 : 0;
+    out[10] = L.n_pair_ranges;
+    int64_t padded = 0;  // cells the product tiles issue: rows to 256, k extent to 32
+    for (const EnsBlk &g : L.gblk) padded += (int64_t)((g.size + kEnsTileRows - 1) / kEnsTileRows) * kEnsTileRows * g.words * 32;
+    out[11] = padded;
     return KUR_OK;
 }
 
@@ -619,14 +650,23 @@ kur_status kur_ens_row_pattern(kur_ctx *c, int64_t m, int32_t *csr_cols, int64_t
         if (cap < cnt) return ctx_fail(c, KUR_EINVAL, "csr_cols holds fewer entries than the row");
         std::memcpy(csr_cols, L.csr_col.data() + L.csr_ptr[m], 4 * (size_t)cnt);
     }
-    if (dense && L.row_gemm[m]) {
-        const int32_t b = (int32_t)(std::upper_bound(L.block_ptr.begin(), L.block_ptr.end(), m) - L.block_ptr.begin()) - 1;
-        const int64_t r0 = L.block_ptr[b], sz = L.block_ptr[b + 1] - r0;
-        for (const EnsBlk &g : L.gblk)
-            if (g.row0 == r0) {
-                const uint32_t *row = L.bits.data() + g.bits_off + (m - r0) * g.words;
-                for (int64_t k = 0; k < sz; ++k) dense[k] = (row[k >> 5] >> (k & 31)) & 1u;
-            }
+    if (dense) {
+        std::memset(dense, 0, (size_t)L.n);
+        if (L.row_gemm[m]) {
+            const int32_t b = (int32_t)(std::upper_bound(L.block_ptr.begin(), L.block_ptr.end(), m) - L.block_ptr.begin()) - 1;
+            const int64_t r0 = L.block_ptr[b];
+            for (const EnsBlk &g : L.gblk)
+                if (g.row0 == r0) {
+                    const uint32_t *row = L.bits.data() + g.bits_off + (m - r0) * g.words;
+                    for (int32_t q = 0; q < g.nrng; ++q) {
+                        const EnsRng &R = L.rng[g.rng0 + q];
+                        for (int64_t j = 0; j < R.len; ++j) {
+                            const int64_t k = R.koff + j;
+                            dense[R.col0 + j] = (row[k >> 5] >> (k & 31)) & 1u;
+                        }
+                    }
+                }
+        }
     }
     return KUR_OK;
 }
@@ -782,14 +822,17 @@ kur_status kur_ens_autotune_csr(kur_ctx *c, int64_t n, const int64_t *row_ptr, c
     std::vector<double> seen_ms;
     double best_tau = ctx_ens_tau(c), best_ms = 1e300;
     int timed = 0;
-    std::vector<double> density;
+    std::vector<double> density, pair_density;
     std::vector<int64_t> bsize;
+    // which blocks and off-diagonal blocks a threshold puts on the matrix cores
+    auto selection = [&](double tau) {
+        std::vector<uint8_t> m(density.size() + pair_density.size());
+        for (size_t b = 0; b < density.size(); ++b) m[b] = (bsize[b] >= 2 && density[b] >= tau) ? 1 : 0;
+        for (size_t q = 0; q < pair_density.size(); ++q) m[density.size() + q] = pair_density[q] >= tau ? 1 : 0;
+        return m;
+    };
     for (double tau : taus) {
-        if (!density.empty()) {
-            std::vector<uint8_t> m(density.size());
-            for (size_t b = 0; b < density.size(); ++b) m[b] = (bsize[b] >= 2 && density[b] >= tau) ? 1 : 0;
-            if (std::find(seen.begin(), seen.end(), m) != seen.end()) continue;
-        }
+        if (!density.empty() && std::find(seen.begin(), seen.end(), selection(tau)) != seen.end()) continue;
         EnsLayout L;
         std::string msg;
         try {
@@ -800,9 +843,10 @@ kur_status kur_ens_autotune_csr(kur_ctx *c, int64_t n, const int64_t *row_ptr, c
         if (!msg.empty()) return ctx_fail(c, KUR_EINVAL, msg);
         if (density.empty()) {
             density = L.density;
+            pair_density = L.pair_density;
             for (int32_t b = 0; b < L.nb; ++b) bsize.push_back(L.block_ptr[b + 1] - L.block_ptr[b]);
         }
-        seen.push_back(L.gemm);
+        seen.push_back(selection(tau));
         if ((s = install_layout(c, *S, L)) != KUR_OK) return s;
         std::vector<double> K(B, 1.0), om((size_t)B * n, 0.0), th((size_t)B * n);
         for (size_t i = 0; i < th.size(); ++i) th[i] = 2.0 * kPi * std::fmod(0.6180339887498949 * (double)i, 1.0);

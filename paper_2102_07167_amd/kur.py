@@ -421,7 +421,7 @@ class Kuramoto:
 
     # -- shared-graph ensembles (FP32) ------------------------------------------------------
     _ENS_INFO = ("n", "blocks", "gemm_blocks", "gemm_rows", "gemm_pairs", "csr_entries", "B", "Bp", "gemm_items",
-                 "symmetric")
+                 "symmetric", "offdiag_blocks", "gemm_cells_issued")
 
     def ens_set_graph(self, graph):
         """Install `graph` (CSR with planted labels) for replicas; see kur_ens_set_graph_csr."""
@@ -464,7 +464,7 @@ class Kuramoto:
         return out
 
     def ens_info(self) -> dict:
-        out = np.zeros(10, dtype=np.int64)
+        out = np.zeros(12, dtype=np.int64)
         self._chk(self._L.kur_ens_info(self._h, _ptr(out)))
         return dict(zip(self._ENS_INFO, (int(x) for x in out)))
 

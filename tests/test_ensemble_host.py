@@ -23,43 +23,59 @@ def mixed_sbm(seed=5, symmetric=True):
     return gen.from_dense(A, labels)
 
 
-def check_ens_layout(k, g, tau):
+def check_ens_layout(k, g, tau, pair_min=32, pair_floor=0.01):
+    """The matrix-core ranges of every row block (its own block when at least tau dense, then its
+    off-diagonal blocks of two communities of >= pair_min nodes at least max(tau, pair_floor)
+    dense), their bit patterns and the CSR rows rebuild the dense adjacency exactly."""
     A = g.dense()
     n = g.n
     perm = k.ens_perm()
     order = np.lexsort((np.arange(n), g.labels))
     assert np.array_equal(perm[order], np.arange(n))
     B = A[np.ix_(order, order)]
+    np.fill_diagonal(B, 0)
     labs = g.labels[order]
     bp = np.r_[np.flatnonzero(np.r_[True, labs[1:] != labs[:-1]]), n]
+    nb = len(bp) - 1
     modes, dens = k.ens_block_modes()
     info = k.ens_info()
-    assert info["blocks"] == len(bp) - 1 == len(modes)
-    gemm_rows = gemm_pairs = csr = 0
-    for b in range(len(bp) - 1):
+    assert info["blocks"] == nb == len(modes)
+    gemm_blocks = gemm_rows = gemm_cells = csr = offdiag = 0
+    for b in range(nb):
         s0, s1 = bp[b], bp[b + 1]
         s = s1 - s0
         sub = B[s0:s1, s0:s1]
-        rho = (sub.sum() - np.trace(sub)) / (s * (s - 1)) if s > 1 else 0.0
+        rho = sub.sum() / (s * (s - 1)) if s > 1 else 0.0
         assert abs(dens[b] - rho) < 1e-12
         assert modes[b] == (1 if (s >= 2 and rho >= tau) else 0), (b, rho, tau)
+        cols_on = np.zeros(n, dtype=bool)  # columns of the row block's matrix-core ranges
         if modes[b]:
+            cols_on[s0:s1] = True
+            gemm_cells += s * s
+        for c in range(nb):
+            c0, c1 = bp[c], bp[c + 1]
+            sc = c1 - c0
+            if c == b or s < pair_min or sc < pair_min:
+                continue
+            r = B[s0:s1, c0:c1].sum() / (s * sc)
+            if r >= max(tau, pair_floor):
+                cols_on[c0:c1] = True
+                gemm_cells += s * sc
+                offdiag += 1
+        if cols_on.any():
+            gemm_blocks += 1
             gemm_rows += s
-            gemm_pairs += s * s
         for m in range(s0, s1):
             cols, dense = k.ens_row_pattern(m)
             assert np.all(np.diff(cols) > 0)
+            assert not np.any(cols_on[cols])
+            assert not np.any(dense[~cols_on])
             csr += len(cols)
-            got = np.zeros(n, dtype=np.uint8)
-            got[cols] = 1
-            if modes[b]:
-                assert not np.any((cols >= s0) & (cols < s1))
-                got[s0:s1] = dense[:s]
-            want = B[m].copy()
-            want[m] = 0
-            assert np.array_equal(got, want), (b, m)
-    assert (info["gemm_rows"], info["gemm_pairs"], info["csr_entries"]) == (gemm_rows, gemm_pairs, csr)
-    assert info["gemm_blocks"] == int(modes.sum())
+            got = dense.astype(np.uint8).copy()
+            got[cols] += 1
+            assert np.array_equal(got, B[m]), (b, m)
+    assert (info["gemm_blocks"], info["gemm_rows"], info["gemm_pairs"], info["csr_entries"], info["offdiag_blocks"]) == \
+        (gemm_blocks, gemm_rows, gemm_cells, csr, offdiag)
 
 
 @pytest.mark.parametrize("tau", [0.0, 0.5, 0.9, 2.0])
@@ -111,3 +127,22 @@ def test_ensemble_validation():
             assert k._L.kur_ens_row_pattern(k._h, 0, K._ptr(buf), K.ctypes.byref(cap), None) == K.KUR_EINVAL
         with pytest.raises(K.KurError):
             k.set_option("ens_tau", -0.1)
+
+
+@pytest.mark.parametrize("tau", [0.0, 0.3, 0.8])
+def test_ensemble_layout_dense_offdiagonal_blocks(tau):
+    """Communities 0-2 and 1-3 joined by dense off-diagonal blocks (density 0.9), 0-1 at 0.1, a
+    partner below 32 nodes; 0 is sparse itself, so its row block holds only its partner range."""
+    rng = np.random.default_rng(17)
+    sizes = [90, 70, 100, 40, 20, 50]
+    V = np.zeros((6, 6), dtype=np.int32)
+    for a, c in [(1, 1), (2, 2), (3, 3), (4, 4), (0, 2), (1, 3), (2, 4), (5, 5), (0, 1)]:
+        V[a, c] = V[c, a] = 1
+    V[0, 1] = V[1, 0] = 0
+    n = sum(sizes)
+    g = gen.block_model(sizes, V, 0.1, 1, rng, uperm=rng.permutation(n).astype(np.int32))
+    with host_ctx("f32", ens_tau=tau) as k:
+        k.ens_set_graph(g)
+        check_ens_layout(k, g, tau)
+        if tau == 0.3:
+            assert k.ens_info()["offdiag_blocks"] == 4  # 0-2 and 1-3, both ways

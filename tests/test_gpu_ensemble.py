@@ -159,3 +159,37 @@ def test_ens_config2_graph_sampled(need_gpu):
     T = 50 * float(np.float32(0.01))
     drift = np.abs(np.mean(thT - th - T * om, axis=1))
     assert drift.max() < 2e-5, drift.max()
+
+
+def paired_graph(seed=21):
+    """Dense off-diagonal blocks 0-2 (0.9), 1-3 (0.9), a sparse community 4 with a dense
+    partner 5, and a partner below 32 nodes (block 6)."""
+    rng = np.random.default_rng(seed)
+    sizes = [300, 97, 257, 130, 64, 96, 20]
+    V = np.zeros((7, 7), dtype=np.int32)
+    for a, c in [(0, 0), (1, 1), (2, 2), (3, 3), (5, 5), (6, 6), (0, 2), (1, 3), (4, 5), (2, 6)]:
+        V[a, c] = V[c, a] = 1
+    n = sum(sizes)
+    return gen.block_model(sizes, V, 0.1, 1, rng, uperm=rng.permutation(n).astype(np.int32))
+
+
+@pytest.mark.parametrize("tau", [0.0, 0.5, 2.0])
+@pytest.mark.parametrize("B", [1, 130])
+def test_ens_dense_offdiagonal_blocks(need_gpu, tau, B):
+    """Off-diagonal dense blocks on the matrix cores (accumulated with the row block's own
+    product in one pass along k) against the oracle: RHS, then 100 RK4 steps."""
+    g = paired_graph()
+    K, om, th = replicas(g.n, B, seed=8)
+    with ens_ctx(g, tau, K, om, th) as k:
+        info = k.ens_info()
+        if tau == 0.5:
+            assert info["offdiag_blocks"] == 6  # 0-2, 1-3, 4-5 both ways
+        F = k.ens_eval_rhs()
+        r, _ = k.ens_step(0.01, 100, 50)
+        thT = k.ens_get_phases()
+    for e in checked(B):
+        Fo = oracle.rhs(g, om[e], float(K[e]), th[e])
+        assert np.abs(F[e] - Fo).max() <= 1e-5 * np.abs(Fo).max(), (e, np.abs(F[e] - Fo).max())
+        tho, ro, _ = oracle.rk4(g, om[e], float(K[e]), th[e], float(np.float32(0.01)), 100, r_every=50)
+        assert np.abs(wrap(thT[e] - tho)).max() < 1e-5
+        assert np.abs(r[:, e] - ro).max() < 1e-5
