@@ -32,7 +32,7 @@ struct EnsRng {
     int32_t pad;
 };
 
-// One workgroup of the dense product: rows [r0, r0 + 256) of block `blk` (block-local) and
+// One workgroup of the dense product: rows [r0, r0 + kEnsTileRows) of block `blk` (block-local) and
 // columns [c0, c0 + 128) of X.
 struct EnsItem {
     int32_t blk, r0, c0, pad;

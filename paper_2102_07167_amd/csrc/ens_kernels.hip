@@ -8,13 +8,15 @@
 // products of one row block's ranges accumulate in one pass along k; k_ens_gemm runs them on the
 // matrix cores:
 //   * A_b is 0/1 and stored as a bitmask; each lane expands one byte into eight bf16 ones and
-//     zeros, which are exact;
+//     zeros (exact) by two lookups in a 16-entry nibble table in LDS;
 //   * X is split exactly into three bf16 terms x = t0 + t1 + t2 (each the truncated upper half
 //     of the remainder: 8 + 8 + 8 significant bits cover the 24 of FP32), so every product is
 //     exact and only the FP32 accumulation of the matrix core rounds;
 //   * v_mfma_f32_32x32x16_bf16, a 256 x 128 output tile per workgroup (four waves of 64 rows,
-//     two 32-row by four 32-column tiles each, so every LDS read of X feeds two products); X is staged in LDS per 32 columns of A, double-buffered, with
-//     the next step's X and pattern words loaded into registers while the matrix cores run.
+//     two 32-row by four 32-column tiles each, so every LDS read of X feeds two products); X is
+//     staged in LDS per 32 columns of A, double-buffered, with the next step's X and pattern
+//     words loaded into registers while the matrix cores run (512-row tiles, halving the
+//     staging per product, measured no faster).
 // k_ens_rows then adds the CSR edges (sparse blocks and inter-block edges) by gathering whole
 // X rows (all replicas contiguous), and runs the stage epilogue of every replica:
 // F = omega + K_e / N ((sum A sin) cos y - (sum A cos) sin y), the RK4 bookkeeping and the next
@@ -33,35 +35,59 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4_e __attribute__((ext_vector_type(4)));
 
 // bits 0..7 of b as eight bf16 values (bit v -> element v): 1.0 = 0x3F80, 0.0 = 0
-__device__ __forceinline__ bf16x8 expand_bits(uint32_t b)
+// the four bf16 values of a nibble's bits (bit v -> element v), as two words
+__device__ __forceinline__ uint2 nibble_bf16(uint32_t n)
 {
+    uint2 v;
+    v.x = ((n >> 0) & 1u) * 0x3F80u | ((n >> 1) & 1u) * 0x3F800000u;
+    v.y = ((n >> 2) & 1u) * 0x3F80u | ((n >> 3) & 1u) * 0x3F800000u;
+    return v;
+}
+
+// bits 8 g .. 8 g + 7 of w as eight bf16 values, from a 16-entry table of nibbles in LDS
+__device__ __forceinline__ bf16x8 expand_byte(const uint2 *tab, uint32_t w, int g)
+{
+    const uint2 lo = tab[(w >> (8 * g)) & 15u], hi = tab[(w >> (8 * g + 4)) & 15u];
     u32x4_e v;
-    v.x = ((b >> 0) & 1u) * 0x3F80u | ((b >> 1) & 1u) * 0x3F800000u;
-    v.y = ((b >> 2) & 1u) * 0x3F80u | ((b >> 3) & 1u) * 0x3F800000u;
-    v.z = ((b >> 4) & 1u) * 0x3F80u | ((b >> 5) & 1u) * 0x3F800000u;
-    v.w = ((b >> 6) & 1u) * 0x3F80u | ((b >> 7) & 1u) * 0x3F800000u;
+    v.x = lo.x;
+    v.y = lo.y;
+    v.z = hi.x;
+    v.w = hi.y;
     return __builtin_bit_cast(bf16x8, v);
 }
 
-// x = t0 + t1 + t2 exactly, each term a bf16 bit pattern in the low 16 bits: t0 keeps the upper
+
+// x = t0 + t1 + t2 exactly, each term a bf16 (the upper half of a float): t0 keeps the upper
 // half of x (8 significant bits), the remainder x - t0 is exact and has at most 16 significant
-// bits, of which t1 keeps the upper 8; the last remainder has at most 8 and is t2 itself.
-__device__ __forceinline__ void split3(float x, uint32_t &t0, uint32_t &t1, uint32_t &t2)
+// bits, of which t1 keeps the upper 8; the last remainder has at most 8 and is t2 itself. Done
+// for two values a, b at once and packed as the B operand wants them: word t holds term t of a
+// (low 16 bits) and of b (high 16 bits). v_perm_b32 with selector 0x07060302 takes bytes 2-3 of
+// its second operand and bytes 2-3 of its first.
+__device__ __forceinline__ void split3_pair(float a, float b, uint32_t &p0, uint32_t &p1, uint32_t &p2)
 {
-    const uint32_t h0 = __float_as_uint(x) & 0xFFFF0000u;
-    const float r1 = x - __uint_as_float(h0);
-    const uint32_t h1 = __float_as_uint(r1) & 0xFFFF0000u;
-    const float r2 = r1 - __uint_as_float(h1);
-    t0 = h0 >> 16;
-    t1 = h1 >> 16;
-    t2 = __float_as_uint(r2) >> 16;
+    const uint32_t ua = __float_as_uint(a), ub = __float_as_uint(b);
+    const float ra = a - __uint_as_float(ua & 0xFFFF0000u), rb = b - __uint_as_float(ub & 0xFFFF0000u);
+    const uint32_t va = __float_as_uint(ra), vb = __float_as_uint(rb);
+    const float qa = ra - __uint_as_float(va & 0xFFFF0000u), qb = rb - __uint_as_float(vb & 0xFFFF0000u);
+    p0 = __builtin_amdgcn_perm(ub, ua, 0x07060302u);
+    p1 = __builtin_amdgcn_perm(vb, va, 0x07060302u);
+    p2 = __builtin_amdgcn_perm(__float_as_uint(qb), __float_as_uint(qa), 0x07060302u);
 }
 
-__global__ __launch_bounds__(256) void k_ens_gemm(EnsGemmArgs a)
+// kEnsTileRows / 64 waves, each owning 64 rows; the X staging of a 32-wide k step (4 groups of
+// 8 k for 128 columns) is spread over all threads: SGN threads per column, NG groups each
+constexpr int kGemmThreads = kEnsTileRows;
+constexpr int kStageSGN = kGemmThreads / kEnsTileCols;
+constexpr int kStageNG = 4 / kStageSGN;
+static_assert(kStageSGN * kStageNG == 4, "staging covers the four 8-wide groups of a step");
+
+__global__ __launch_bounds__(kGemmThreads) void k_ens_gemm(EnsGemmArgs a)
 {
     // double buffer of [term][group of 8 k][column]: 8 bf16 of one column, the layout of the B
     // operand; step i is staged into buffer i & 1 while the matrix cores work on the other
     __shared__ u32x4_e xs[2][3][4][kEnsTileCols];
+    __shared__ uint2 ntab[16];  // read after the first barrier of the k loop
+    if (threadIdx.x < 16) ntab[threadIdx.x] = nibble_bf16(threadIdx.x);
     const EnsItem it = a.items[blockIdx.x];
     const EnsBlk b = a.blk[it.blk];
     const int tid = threadIdx.x;
@@ -72,11 +98,15 @@ __global__ __launch_bounds__(256) void k_ens_gemm(EnsGemmArgs a)
     const bool ok0 = arow0 < b.size, ok1 = arow1 < b.size;
     const uint32_t *ab0 = a.bits + b.bits_off + (int64_t)(ok0 ? arow0 : 0) * b.words;
     const uint32_t *ab1 = a.bits + b.bits_off + (int64_t)(ok1 ? arow1 : 0) * b.words;
-    // staging: thread -> one column, k groups sg and sg + 2 of each 32-wide step
+    // staging: thread -> one column, k groups sg, sg + SGN, ... of each 32-wide step
     const int sc = tid & (kEnsTileCols - 1), sg = tid >> 7;
-    const float *xbase = a.x + it.c0 + sc;
+    // range of the next load: k only grows and every 32-wide step lies in one range, so the
+    // table is read again only where the next range begins
     const EnsRng *rg = a.rng + b.rng0;
-    int rl = 0;  // range of the next load (k only grows; every 32-wide step lies in one range)
+    int rl = 0;
+    int r_koff = __builtin_amdgcn_readfirstlane(rg[0].koff), r_col0 = __builtin_amdgcn_readfirstlane(rg[0].col0),
+        r_len = __builtin_amdgcn_readfirstlane(rg[0].len);
+    int next_koff = b.nrng > 1 ? __builtin_amdgcn_readfirstlane(rg[1].koff) : INT32_MAX;
     f32x16 acc[2][4];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
@@ -86,20 +116,38 @@ __global__ __launch_bounds__(256) void k_ens_gemm(EnsGemmArgs a)
             for (int r = 0; r < 16; ++r) acc[rt][c][r] = 0.f;
 
     const int kend = b.words * 32;
-    float v[2][8];
+    float v[kStageNG][8];
+    // X rows of a step are addressed from a workgroup-uniform base (the range's first row, the
+    // tile's first column) with 32-bit per-lane offsets (k J + sc < 2^31 inside one range)
+    const uint32_t Ju = (uint32_t)a.J;
     auto load = [&](int k0) {
-        while (rl + 1 < b.nrng && k0 >= rg[rl + 1].koff) ++rl;
-        const EnsRng R = rg[rl];
-        const float *xcol = xbase + (int64_t)R.col0 * a.J;
-        const int kl = k0 - R.koff;
+        if (k0 >= next_koff) {
+            ++rl;
+            r_koff = __builtin_amdgcn_readfirstlane(rg[rl].koff);
+            r_col0 = __builtin_amdgcn_readfirstlane(rg[rl].col0);
+            r_len = __builtin_amdgcn_readfirstlane(rg[rl].len);
+            next_koff = rl + 1 < b.nrng ? __builtin_amdgcn_readfirstlane(rg[rl + 1].koff) : INT32_MAX;
+        }
+        const float *xb = a.x + (int64_t)r_col0 * a.J + it.c0;
+        const int kl = k0 - r_koff;
+        if (kl + 32 <= r_len) {
+            // the whole step inside the range: rows kl + 8 (sg + SGN gi) + i, no clamps
 #pragma unroll
-        for (int gi = 0; gi < 2; ++gi)
+            for (int gi = 0; gi < kStageNG; ++gi) {
+                const uint32_t off = (uint32_t)(kl + 8 * (sg + kStageSGN * gi)) * Ju + (uint32_t)sc;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[gi][i] = xb[off + (uint32_t)i * Ju];
+            }
+            return;
+        }
+#pragma unroll
+        for (int gi = 0; gi < kStageNG; ++gi)
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 // unconditional load of a clamped row (no branch per load), then the mask
-                const int k = kl + 8 * (sg + 2 * gi) + i;
-                const float t = xcol[(int64_t)(k < R.len ? k : R.len - 1) * a.J];
-                v[gi][i] = k < R.len ? t : 0.f;
+                const int k = kl + 8 * (sg + kStageSGN * gi) + i;
+                const float t = xb[(uint32_t)(k < r_len ? k : r_len - 1) * Ju + (uint32_t)sc];
+                v[gi][i] = k < r_len ? t : 0.f;
             }
     };
     load(0);
@@ -109,15 +157,15 @@ __global__ __launch_bounds__(256) void k_ens_gemm(EnsGemmArgs a)
     int buf = 0;
     for (int k0 = 0; k0 < kend; k0 += 32) {
 #pragma unroll
-        for (int gi = 0; gi < 2; ++gi) {
-            uint32_t t0[8], t1[8], t2[8];
+        for (int gi = 0; gi < kStageNG; ++gi) {
+            uint32_t q0[4], q1[4], q2[4];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) split3(v[gi][i], t0[i], t1[i], t2[i]);
+            for (int j = 0; j < 4; ++j) split3_pair(v[gi][2 * j], v[gi][2 * j + 1], q0[j], q1[j], q2[j]);
             u32x4_e p0, p1, p2;
-            p0.x = t0[0] | (t0[1] << 16); p0.y = t0[2] | (t0[3] << 16); p0.z = t0[4] | (t0[5] << 16); p0.w = t0[6] | (t0[7] << 16);
-            p1.x = t1[0] | (t1[1] << 16); p1.y = t1[2] | (t1[3] << 16); p1.z = t1[4] | (t1[5] << 16); p1.w = t1[6] | (t1[7] << 16);
-            p2.x = t2[0] | (t2[1] << 16); p2.y = t2[2] | (t2[3] << 16); p2.z = t2[4] | (t2[5] << 16); p2.w = t2[6] | (t2[7] << 16);
-            const int g = sg + 2 * gi;
+            p0.x = q0[0]; p0.y = q0[1]; p0.z = q0[2]; p0.w = q0[3];
+            p1.x = q1[0]; p1.y = q1[1]; p1.z = q1[2]; p1.w = q1[3];
+            p2.x = q2[0]; p2.y = q2[1]; p2.z = q2[2]; p2.w = q2[3];
+            const int g = sg + kStageSGN * gi;
             xs[buf][0][g][sc] = p0;
             xs[buf][1][g][sc] = p1;
             xs[buf][2][g][sc] = p2;
@@ -135,8 +183,8 @@ __global__ __launch_bounds__(256) void k_ens_gemm(EnsGemmArgs a)
 #pragma unroll
         for (int sub = 0; sub < 2; ++sub) {
             const int g = 2 * sub + half;
-            const bf16x8 av0 = expand_bits(c0 >> (8 * g));
-            const bf16x8 av1 = expand_bits(c1 >> (8 * g));
+            const bf16x8 av0 = expand_byte(ntab, c0, g);
+            const bf16x8 av1 = expand_byte(ntab, c1, g);
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
@@ -297,7 +345,7 @@ __global__ __launch_bounds__(64) void k_ens_order(int64_t nchunk, int32_t Bp, in
 hipError_t launch_ens_gemm(const EnsGemmArgs &a, int64_t nitems, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ens_gemm, dim3((unsigned)nitems), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_ens_gemm, dim3((unsigned)nitems), dim3(kGemmThreads), 0, st, a);
     return hipGetLastError();
 }
 
