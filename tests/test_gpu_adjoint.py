@@ -158,7 +158,7 @@ def _loss(k, w, th0, om, K, steps):
     return oracle.loss_and_seed(k.get_phases(), w.target)
 
 
-def test_adjoint_config5_central_differences(need_gpu):
+def test_adjoint_sbm_64x1024_2000_steps_central_differences(need_gpu):
     """Equal-community SBM N = 65536 (64 x 1024), 2000 steps of dt 0.01, checkpoint every 32,
     loss (1 - r(T))^2 + mean chordal distance to seeded targets: 16 theta0, 15 omega coordinates
     and K against central differences (h = 1e-6) of the GPU FP64 forward."""

@@ -139,7 +139,7 @@ def test_ens_one_full_block_and_small_blocks(need_gpu):
             assert np.abs(wrap(thT[e] - tho)).max() < 1e-5, e
 
 
-def test_ens_config2_graph_sampled(need_gpu):
+def test_ens_sbm_64x1024_sampled(need_gpu):
     """The equal-community SBM (64 x 1024, rho 0.97, p_out 2e-4) with 128 replicas: sampled rows
     of the right-hand side of four replicas against the oracle, and conservation of
     mean(theta - theta0 - t omega) over 50 steps for every replica (symmetric A)."""

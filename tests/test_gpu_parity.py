@@ -247,7 +247,7 @@ def test_eval_at_given_theta(need_gpu):
     assert rel_err(F, oracle.rhs(w.graph, w.omega, w.K, th)) < 1e-12
 
 
-def test_config2_full_size_sampled_rows(need_gpu):
+def test_sbm_64x1024_sampled_rows(need_gpu):
     """N = 65536 = 64 x 1024, rho 0.97, p_out 2e-4: FP64 and FP32 right-hand side on a seeded
     1/64 subsample of rows at theta0 and at a partially synchronised state; conservation over
     100 steps."""
@@ -274,7 +274,7 @@ def test_config2_full_size_sampled_rows(need_gpu):
                 assert abs(dev) < 1e-10
 
 
-def test_config3_full_size_sampled_rows(need_gpu):
+def test_het_sbm_n2p20_sampled_rows(need_gpu):
     """Heterogeneous SBM, N = 2^20 (power-law communities in [256, 16384], densities U[0.3, 1],
     inter mean degree 8), FP32, in the layout bench.py times (installed through the committed
     tuning cache). The coupling sums of a seeded 1/64 subsample of rows (omega = 0 so that the
