@@ -106,3 +106,21 @@ def test_autotune_stores_and_reloads(need_gpu, tmp_path):
         k2.set_phases(th32)
         k2.step_rk4(0.01, 100)
         assert np.array_equal(k2.get_phases(), thA)
+
+
+def test_autotune_with_dense_offdiagonal_blocks(need_gpu, tmp_path):
+    """The tuner on a graph with dense off-diagonal blocks (its density thresholds also decide
+    those blocks) keeps the result within the oracle's tolerance."""
+    rng = np.random.default_rng(41)
+    sizes = [300, 200, 257, 130]
+    V = np.array([[1, 1, 0, 0], [1, 1, 0, 1], [0, 0, 1, 0], [0, 1, 0, 1]], dtype=np.int32)
+    n = sum(sizes)
+    g = gen.block_model(sizes, V, 0.4, 1, rng, uperm=rng.permutation(n).astype(np.int32))
+    om, th = rng.standard_normal(n), rng.uniform(0, TWO_PI, n)
+    with Kuramoto("f64", device=0) as k:
+        rep = k.autotune(g, effort=1, cache=str(tmp_path / "cache.tsv"))
+        assert rep["timed"] >= 2
+        k.set_params(om, 1.5)
+        F = k.eval_rhs(th)
+    Fo = oracle.rhs(g, om, 1.5, th)
+    assert np.abs(F - Fo).max() <= 1e-12 * np.abs(Fo).max()

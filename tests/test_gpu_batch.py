@@ -147,3 +147,28 @@ def test_batch_ensemble_full_size(need_gpu):
     Kf = float(np.float32(K))
     tho, _, _ = oracle.rk4(gen.complete_graph(n), om, Kf, th0, float(np.float32(dt)), steps)
     assert np.abs(wrap(th_all[rf[i]:rf[i + 1]] - tho)).max() < 2e-5
+
+
+def test_batch_with_dense_offdiagonal_blocks(need_gpu):
+    """Instances whose communities are joined by dense off-diagonal blocks keep their column
+    groups in the union (block, tile and group indices offset per instance) and match the
+    oracle per instance."""
+    rng = np.random.default_rng(31)
+    inst = []
+    for i, K in enumerate([0.5, 2.0, 4.0]):
+        sizes = [40 + 20 * i, 50, 64]
+        V = np.array([[1, 1, 0], [1, 0, 1], [0, 1, 1]], dtype=np.int32)
+        n = sum(sizes)
+        g = gen.block_model(sizes, V, 0.1, 1, rng, uperm=rng.permutation(n).astype(np.int32))
+        inst.append((g, K, rng.standard_normal(n), rng.uniform(0, TWO_PI, n)))
+    dt, steps, r_every = 0.01, 100, 10
+    with Kuramoto("f64", device=0) as k:
+        k.set_batch(inst)
+        assert k.graph_pairs() == 12
+        rf = k.batch_info()
+        r, _ = k.batch_step(dt, steps, r_every)
+        th = k.get_phases()
+    for i, (g, K, om, th0) in enumerate(inst):
+        thT, ro, _ = oracle.rk4(g, om, K, th0, dt, steps, r_every=r_every)
+        assert np.abs(wrap(th[rf[i]:rf[i + 1]] - thT)).max() < 1e-12 * max(1.0, np.abs(thT).max()), i
+        assert np.abs(r[:, i] - ro).max() < 1e-12, i
