@@ -183,7 +183,8 @@ def bench_ensemble(args):
     K = np.linspace(0.0, 6.0, B)
     om = rng.standard_normal((B, g.n))
     th = rng.uniform(0.0, 2 * np.pi, (B, g.n))
-    k = Kuramoto("f32", device=0)
+    dtype = args.dtype or "f32"
+    k = Kuramoto(dtype, device=0)
     for kv in args.option:
         key, v = kv.split("=")
         k.set_option(key, float(v))
@@ -217,7 +218,7 @@ def bench_ensemble(args):
     out = {"metric": "aggregate node-steps/s of a shared-graph ensemble (RK4)", "value": g.n * B * args.steps / el,
            "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32", "data": "synthetic",
+           "dtype": dtype, "data": "synthetic",
            "config": {"workload": "%d replicas of the %s N=65536 (64 x 1024, rho 0.97, p_out 2e-4%s), "
                                   "K=linspace(0,6,%d), omega~N(0,1), theta0~U[0,2pi) per replica, dt=0.01, r every 10 "
                                   "steps, seed 1006" % (
@@ -225,17 +226,21 @@ def bench_ensemble(args):
                                       ", communities 2i and 2i+1 joined at density 0.9" if args.ens_graph == "paired"
                                       else "", B), "layout": info, "tuning": tuning}}
     if kt["gemm_launches"] > 0:
-        # issued matrix-core work per launch: every 256 x 128 output tile of a row block runs
-        # over its ranges' widths, each padded to 32, with three bf16 terms and 2 flops per
-        # multiply-add
+        # issued matrix-core work per launch: every output tile of a row block (256 x 128 in
+        # FP32, 128 x 64 in FP64) runs over its ranges' widths, each padded to 32, with 2 flops
+        # per multiply-add; FP32 products issue three bf16 terms, FP64 products one FP64 term
         J = 2 * info["Bp"]
-        issued = 2.0 * 3 * info["gemm_cells_issued"] * J
+        terms = 3 if dtype == "f32" else 1
+        peak = 2500.0 if dtype == "f32" else 78.6
+        issued = 2.0 * terms * info["gemm_cells_issued"] * J
         useful = 2.0 * info["gemm_pairs"] * 2 * B
         gms = kt["gemm_ms"] / kt["gemm_launches"]
-        out["roofline"] = {"bound": "mfma", "achieved": issued / (gms * 1e-3) / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
-                           "frac": issued / (gms * 1e-3) / 1e12 / 2500.0, "traffic": None, "kernel": "k_ens_gemm",
-                           "avg_launch_ms": gms, "issued_bf16_flops_per_launch": issued,
-                           "useful_fp32_flops_per_launch": useful,
+        out["roofline"] = {"bound": "mfma", "achieved": issued / (gms * 1e-3) / 1e12, "peak": peak, "unit": "TFLOP/s",
+                           "frac": issued / (gms * 1e-3) / 1e12 / peak, "traffic": None,
+                           "kernel": "k_ens_gemm" if dtype == "f32" else "k_ens_gemm_f64",
+                           "avg_launch_ms": gms,
+                           ("issued_bf16_flops_per_launch" if dtype == "f32" else "issued_fp64_flops_per_launch"): issued,
+                           "useful_%s_flops_per_launch" % ("fp32" if dtype == "f32" else "fp64"): useful,
                            "rows_kernel_avg_ms": kt["rows_ms"] / max(1, kt["rows_launches"])}
     print(json.dumps(out), flush=True)
     k.close()
@@ -256,7 +261,7 @@ def main():
                     help="first run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--option", action="append", default=[], help="library option key=value")
     ap.add_argument("--dtype", choices=["f32", "f64"], default=None,
-                    help="arithmetic type of the single-graph workloads (default: f64 for a2a, else f32)")
+                    help="arithmetic type (default: f64 for a2a, else f32)")
     ap.add_argument("--tune-effort", type=int, default=1, choices=[-1, 0, 1, 2],
                     help="layout autotuning effort (-1: defaults and --option values only)")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,

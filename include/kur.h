@@ -411,11 +411,13 @@ kur_status kur_tune_key(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const i
  * density is at least the option "ens_tau" (default 0.5; above 1: none), and every off-diagonal
  * block of two communities of at least 32 nodes whose density is at least max(ens_tau, 0.01),
  * this is a dense matrix product A_{a,c} X_c, run on the matrix cores (0/1 pattern stored as a
- * bitmask, X split exactly into three bf16 terms, FP32 accumulation; the products of one row
- * community accumulate in one pass); all other edges are summed as CSR rows (Sec. 3: block
+ * bitmask; FP32 contexts split X exactly into three bf16 terms with FP32 accumulation, FP64
+ * contexts multiply FP64 X by exact 0.0/1.0 entries with FP64 accumulation; the products of one
+ * row community accumulate in one pass); all other edges are summed as CSR rows (Sec. 3: block
  * structure with dense and sparse parts, and its extension to submatrices). Replica e follows
  * d theta_m / dt = omega_{e,m} + (K_e / N) sum_l A_ml sin(theta_l - theta_m).
- * FP32 contexts only (KUR_EINVAL otherwise). Independent of the single-system graph and state.
+ * FP32 and FP64 contexts (the context's reals throughout). Independent of the single-system
+ * graph and state.
  *
  * kur_ens_set_graph_csr  CSR with planted labels, as kur_set_graph_csr; host-only contexts keep
  *                        the layout for inspection (kur_ens_row_pattern); params and phases unset
@@ -429,8 +431,8 @@ kur_status kur_tune_key(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const i
  * kur_ens_info           out[12]: n, blocks, matrix-core row blocks, their rows, cells of their
  *                        products (sum of rows x columns), CSR entries, B, B padded to 64,
  *                        matrix-product work items, symmetric, off-diagonal blocks on the matrix
- *                        cores, cells the product tiles issue (rows padded to 256, columns of
- *                        every range to 32)
+ *                        cores, cells the product tiles issue (rows padded to the tile
+ *                        height, 256 in FP32 and 128 in FP64; columns of every range to 32)
  * kur_ens_block_modes    per block (either may be NULL): 1 if its own block is on the matrix
  *                        cores, realised density of its own block
  * kur_ens_get_perm       user node -> block-order row (n)

@@ -38,46 +38,56 @@ struct EnsItem {
     int32_t blk, r0, c0, pad;
 };
 
+// output tile of one product workgroup: FP32 (three bf16 terms) and FP64
 constexpr int kEnsTileRows = 256;
 constexpr int kEnsTileCols = 128;
+constexpr int kEnsTileRowsF64 = 128;
+constexpr int kEnsTileColsF64 = 64;
 
 struct EnsGemmArgs {
     const EnsBlk *blk;
     const EnsRng *rng;
     const EnsItem *items;
     const uint32_t *bits;
-    const float *x;  // [n][J]: sin of every replica, then cos (J = 2 Bp)
-    float *y;        // [n][J]: (A sin, A cos) for the rows of matrix-core blocks
+    const void *x;  // [n][J] of the context's reals: sin of every replica, then cos (J = 2 Bp)
+    void *y;        // [n][J]: (A sin, A cos) for the rows of matrix-core blocks
     int64_t J;
 };
 
+template <typename T>
 struct EnsRowArgs {
     int64_t n;
     int32_t Bp;
     int32_t stage;  // 0: derivative only (kout); 1..4: RK4 stage
     int32_t compensate;
-    float dt, half_dt, dt6;
+    T dt, half_dt, dt6;
     const int64_t *csr_ptr;  // n + 1, block order
     const int32_t *csr_col;  // block-order columns
     const uint8_t *row_gemm; // 1 where y holds the row's matrix-core products
-    const float *x;          // [n][J] stage input (sin | cos)
-    const float *y;
-    float *x_out;            // [n][J] next stage input (sin | cos)
-    const float *omega;      // [n][Bp]
-    const float *unit;       // [Bp]: K_e / N
-    float *hi, *lo;          // [n][Bp] phase and its compensation term
+    const T *x;              // [n][J] stage input (sin | cos)
+    const T *y;
+    T *x_out;                // [n][J] next stage input (sin | cos)
+    const T *omega;          // [n][Bp]
+    const T *unit;           // [Bp]: K_e / N
+    T *hi, *lo;              // [n][Bp] phase and its compensation term
     int32_t *wind;           // [n][Bp]
-    float *ksum;             // [n][Bp]
-    float *kout;             // [n][Bp], stage 0
+    T *ksum;                 // [n][Bp]
+    T *kout;                 // [n][Bp], stage 0
 };
 
+// FP32 products (X split exactly into three bf16 terms) and FP64 products
 hipError_t launch_ens_gemm(const EnsGemmArgs &a, int64_t nitems, hipStream_t st);
-hipError_t launch_ens_rows(const EnsRowArgs &a, hipStream_t st);
-hipError_t launch_ens_sincos(int64_t n, int32_t Bp, const float *hi, float *x, hipStream_t st);
+hipError_t launch_ens_gemm_f64(const EnsGemmArgs &a, int64_t nitems, hipStream_t st);
+template <typename T>
+hipError_t launch_ens_rows(const EnsRowArgs<T> &a, hipStream_t st);
+template <typename T>
+hipError_t launch_ens_sincos(int64_t n, int32_t Bp, const T *hi, T *x, hipStream_t st);
 // partial column sums of x over chunks of 256 rows: part [ceil(n / 256)][J]
-hipError_t launch_ens_colsum(int64_t n, int64_t J, const float *x, float *part, hipStream_t st);
+template <typename T>
+hipError_t launch_ens_colsum(int64_t n, int64_t J, const T *x, T *part, hipStream_t st);
 // r and psi of replicas [0, B) from the partials, written to r[0..B) and psi[0..B)
-hipError_t launch_ens_order(int64_t n, int32_t Bp, int32_t B, const float *part, double *r, double *psi,
+template <typename T>
+hipError_t launch_ens_order(int64_t n, int32_t Bp, int32_t B, const T *part, double *r, double *psi,
                             hipStream_t st);
 
 }  // namespace kur

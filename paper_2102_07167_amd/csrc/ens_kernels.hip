@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_ens_gemm(EnsGemmArgs a)
             r_len = __builtin_amdgcn_readfirstlane(rg[rl].len);
             next_koff = rl + 1 < b.nrng ? __builtin_amdgcn_readfirstlane(rg[rl + 1].koff) : INT32_MAX;
         }
-        const float *xb = a.x + (int64_t)r_col0 * a.J + it.c0;
+        const float *xb = reinterpret_cast<const float *>(a.x) + (int64_t)r_col0 * a.J + it.c0;
         const int kl = k0 - r_koff;
         if (kl + 32 <= r_len) {
             // the whole step inside the range: rows kl + 8 (sg + SGN gi) + i, no clamps
@@ -205,15 +205,116 @@ __global__ __launch_bounds__(kGemmThreads) void k_ens_gemm(EnsGemmArgs a)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = it.r0 + wave * 64 + rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                if (row < b.size) a.y[(int64_t)(b.row0 + row) * a.J + it.c0 + ct * 32 + l32] = acc[rt][ct][r];
+                if (row < b.size)
+                    reinterpret_cast<float *>(a.y)[(int64_t)(b.row0 + row) * a.J + it.c0 + ct * 32 + l32] = acc[rt][ct][r];
+            }
+}
+
+// FP64 products on the FP64 matrix cores with v_mfma_f64_16x16x4f64, whose operands are laid
+// out as follows: lane l holds A[l % 16][l / 16] of the 16 x 4 A tile and B[l / 16][l % 16] of
+// the 4 x 16 B tile, and register j of lane l holds D[l / 16 + 4 j][l % 16] of the 16 x 16
+// result. A workgroup computes a 128 x 64 tile of Y = sum_c A_{a,c} X_c over the row block's
+// ranges: four waves of 32 rows, each two 16-row by four 16-column tiles. The 0/1 entries of A
+// enter as exact 0.0 and 1.0, so only the FP64 accumulation rounds. X is staged in LDS per 32
+// columns of A, double-buffered, with the next step's X and pattern words loaded into
+// registers while the matrix cores run; the LDS row pitch puts the k rows read by the two
+// halves of a wave on different banks.
+constexpr int kF64Pitch = kEnsTileColsF64 + 16;
+
+__global__ __launch_bounds__(256) void k_ens_gemm_f64(EnsGemmArgs a)
+{
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    __shared__ double xs[2][32][kF64Pitch];
+    const EnsItem it = a.items[blockIdx.x];
+    const EnsBlk b = a.blk[it.blk];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, kq = lane >> 4;
+    const int arow0 = it.r0 + wave * 32 + l16, arow1 = arow0 + 16;
+    const bool ok0 = arow0 < b.size, ok1 = arow1 < b.size;
+    const uint32_t *ab0 = a.bits + b.bits_off + (int64_t)(ok0 ? arow0 : 0) * b.words;
+    const uint32_t *ab1 = a.bits + b.bits_off + (int64_t)(ok1 ? arow1 : 0) * b.words;
+    // staging: thread -> one column, k rows 8 sg .. 8 sg + 7 of each 32-wide step
+    const int sc = tid & (kEnsTileColsF64 - 1), sg = tid >> 6;
+    const double *X = reinterpret_cast<const double *>(a.x);
+    const EnsRng *rg = a.rng + b.rng0;
+    int rl = 0;
+    int r_koff = __builtin_amdgcn_readfirstlane(rg[0].koff), r_col0 = __builtin_amdgcn_readfirstlane(rg[0].col0),
+        r_len = __builtin_amdgcn_readfirstlane(rg[0].len);
+    int next_koff = b.nrng > 1 ? __builtin_amdgcn_readfirstlane(rg[1].koff) : INT32_MAX;
+    const uint32_t Ju = (uint32_t)a.J;
+    double v[8];
+    auto load = [&](int k0) {
+        if (k0 >= next_koff) {
+            ++rl;
+            r_koff = __builtin_amdgcn_readfirstlane(rg[rl].koff);
+            r_col0 = __builtin_amdgcn_readfirstlane(rg[rl].col0);
+            r_len = __builtin_amdgcn_readfirstlane(rg[rl].len);
+            next_koff = rl + 1 < b.nrng ? __builtin_amdgcn_readfirstlane(rg[rl + 1].koff) : INT32_MAX;
+        }
+        const double *xb = X + (int64_t)r_col0 * a.J + it.c0;
+        const int kl = k0 - r_koff + 8 * sg;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            // unconditional load of a clamped row, then the mask
+            const int k = kl + i;
+            const double t = xb[(uint32_t)(k < r_len ? k : r_len - 1) * Ju + (uint32_t)sc];
+            v[i] = k < r_len ? t : 0.0;
+        }
+    };
+    d4 acc[2][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = d4{0.0, 0.0, 0.0, 0.0};
+    const int kend = b.words * 32;
+    load(0);
+    uint32_t w0 = ab0[0], w1 = ab1[0];
+    w0 = ok0 ? w0 : 0u;
+    w1 = ok1 ? w1 : 0u;
+    int buf = 0;
+    for (int k0 = 0; k0 < kend; k0 += 32) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xs[buf][8 * sg + i][sc] = v[i];
+        // one barrier per step: a wave past it has finished its reads of the other buffer
+        // (step - 1), which the next step overwrites
+        __syncthreads();
+        const uint32_t c0 = w0, c1 = w1;
+        if (k0 + 32 < kend) {
+            load(k0 + 32);
+            const uint32_t n0 = ab0[(k0 >> 5) + 1], n1 = ab1[(k0 >> 5) + 1];
+            w0 = ok0 ? n0 : 0u;
+            w1 = ok1 ? n1 : 0u;
+        }
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+            const double a0 = ((c0 >> (4 * kk + kq)) & 1u) ? 1.0 : 0.0;
+            const double a1 = ((c1 >> (4 * kk + kq)) & 1u) ? 1.0 : 0.0;
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                const double bv = xs[buf][4 * kk + kq][ct * 16 + l16];
+                acc[0][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc[0][ct], 0, 0, 0);
+                acc[1][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc[1][ct], 0, 0, 0);
+            }
+        }
+        buf ^= 1;
+    }
+    double *Y = reinterpret_cast<double *>(a.y);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = it.r0 + wave * 32 + rt * 16 + kq + 4 * j;
+                if (row < b.size) Y[(int64_t)(b.row0 + row) * a.J + it.c0 + ct * 16 + l16] = acc[rt][ct][j];
             }
 }
 
 // One wave per row; lane l handles replicas l + 64 q, q < NE. Every load of the row's own data
 // (dense-block sums, stage input, omega and the RK4 state) is issued before the CSR gathers, so
 // a wave waits on memory about as often as it has groups of CSR entries.
-template <int NE>
-__global__ __launch_bounds__(256) void k_ens_rows(EnsRowArgs a)
+template <typename T, int NE>
+__global__ __launch_bounds__(256) void k_ens_rows(EnsRowArgs<T> a)
 {
     constexpr int GRP = NE <= 2 ? 8 : 4;  // CSR entries gathered per round
     const int lane = threadIdx.x & 63;
@@ -224,12 +325,12 @@ __global__ __launch_bounds__(256) void k_ens_rows(EnsRowArgs a)
     const int stage = a.stage;
     // y holds rows of matrix-core blocks only: the branch is uniform over the wave
     const bool dense = __builtin_amdgcn_readfirstlane((int)a.row_gemm[m]) != 0;
-    float as[NE], ac[NE], sm[NE], cm[NE], om[NE], th[NE], ks[NE], lo[NE];
+    T as[NE], ac[NE], sm[NE], cm[NE], om[NE], th[NE], ks[NE], lo[NE];
     int32_t wd[NE];
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
-        as[q] = 0.f;
-        ac[q] = 0.f;
+        as[q] = T(0);
+        ac[q] = T(0);
     }
     if (dense) {
 #pragma unroll
@@ -246,8 +347,8 @@ __global__ __launch_bounds__(256) void k_ens_rows(EnsRowArgs a)
         cm[q] = a.x[m * J + Bp + e];
         om[q] = a.omega[ix];
         th[q] = a.hi[ix];
-        ks[q] = stage >= 2 ? a.ksum[ix] : 0.f;
-        lo[q] = stage == 4 ? a.lo[ix] : 0.f;
+        ks[q] = stage >= 2 ? a.ksum[ix] : T(0);
+        lo[q] = stage == 4 ? a.lo[ix] : T(0);
         wd[q] = stage == 4 ? a.wind[ix] : 0;
     }
     const int64_t p0 = a.csr_ptr[m], p1 = a.csr_ptr[m + 1];
@@ -256,7 +357,7 @@ __global__ __launch_bounds__(256) void k_ens_rows(EnsRowArgs a)
         int64_t col[GRP];
 #pragma unroll
         for (int i = 0; i < GRP; ++i) col[i] = a.csr_col[p + i];
-        float vs[GRP][NE], vc[GRP][NE];
+        T vs[GRP][NE], vc[GRP][NE];
 #pragma unroll
         for (int i = 0; i < GRP; ++i)
 #pragma unroll
@@ -284,49 +385,52 @@ __global__ __launch_bounds__(256) void k_ens_rows(EnsRowArgs a)
     for (int q = 0; q < NE; ++q) {
         const int64_t e = lane + 64 * q;
         const int64_t ix = m * Bp + e;
-        const float k = om[q] + a.unit[e] * (as[q] * cm[q] - ac[q] * sm[q]);
+        const T k = om[q] + a.unit[e] * (as[q] * cm[q] - ac[q] * sm[q]);
         if (stage == 0) {
             a.kout[ix] = k;
             continue;
         }
-        const float y = rk4_stage<float>(stage, k, a.dt, a.half_dt, a.dt6, a.compensate, &ks[q], &th[q], &lo[q], &wd[q]);
+        const T y = rk4_stage<T>(stage, k, a.dt, a.half_dt, a.dt6, a.compensate, &ks[q], &th[q], &lo[q], &wd[q]);
         a.ksum[ix] = ks[q];
         if (stage == 4) {
             a.hi[ix] = th[q];
             a.lo[ix] = lo[q];
             a.wind[ix] = wd[q];
         }
-        float sy, cy;
-        dev_sincos<float>(y, &sy, &cy);
+        T sy, cy;
+        dev_sincos<T>(y, &sy, &cy);
         a.x_out[m * J + e] = sy;
         a.x_out[m * J + Bp + e] = cy;
     }
 }
 
-__global__ __launch_bounds__(256) void k_ens_sincos(int64_t n, int32_t Bp, const float *__restrict__ hi, float *__restrict__ x)
+template <typename T>
+__global__ __launch_bounds__(256) void k_ens_sincos(int64_t n, int32_t Bp, const T *__restrict__ hi, T *__restrict__ x)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n * Bp) return;
     const int64_t m = i / Bp, e = i - m * Bp;
-    float s, c;
-    dev_sincos<float>(hi[i], &s, &c);
+    T s, c;
+    dev_sincos<T>(hi[i], &s, &c);
     x[m * 2 * Bp + e] = s;
     x[m * 2 * Bp + Bp + e] = c;
 }
 
-__global__ __launch_bounds__(256) void k_ens_colsum(int64_t n, int64_t J, const float *__restrict__ x, float *__restrict__ part)
+template <typename T>
+__global__ __launch_bounds__(256) void k_ens_colsum(int64_t n, int64_t J, const T *__restrict__ x, T *__restrict__ part)
 {
     const int64_t r0 = (int64_t)blockIdx.x * 256;
     const int64_t r1 = r0 + 256 < n ? r0 + 256 : n;
     for (int64_t j = threadIdx.x; j < J; j += 256) {
-        float s = 0.f;
+        T s = T(0);
         for (int64_t m = r0; m < r1; ++m) s += x[m * J + j];
         part[(int64_t)blockIdx.x * J + j] = s;
     }
 }
 
+template <typename T>
 __global__ __launch_bounds__(64) void k_ens_order(int64_t nchunk, int32_t Bp, int32_t B, double inv_n,
-                                                  const float *__restrict__ part, double *__restrict__ r,
+                                                  const T *__restrict__ part, double *__restrict__ r,
                                                   double *__restrict__ psi)
 {
     const int e = blockIdx.x * 64 + threadIdx.x;
@@ -349,42 +453,62 @@ hipError_t launch_ens_gemm(const EnsGemmArgs &a, int64_t nitems, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_ens_rows(const EnsRowArgs &a, hipStream_t st)
+hipError_t launch_ens_gemm_f64(const EnsGemmArgs &a, int64_t nitems, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ens_gemm_f64, dim3((unsigned)nitems), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ens_rows(const EnsRowArgs<T> &a, hipStream_t st)
 {
     if (a.n <= 0) return hipSuccess;
     const dim3 grid((unsigned)((a.n + 3) / 4)), block(256);
     switch (a.Bp / 64) {
-    case 1: hipLaunchKernelGGL(k_ens_rows<1>, grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_ens_rows<2>, grid, block, 0, st, a); break;
-    case 3: hipLaunchKernelGGL(k_ens_rows<3>, grid, block, 0, st, a); break;
-    case 4: hipLaunchKernelGGL(k_ens_rows<4>, grid, block, 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_ens_rows<T, 1>), grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_ens_rows<T, 2>), grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_ens_rows<T, 3>), grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_ens_rows<T, 4>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_ens_sincos(int64_t n, int32_t Bp, const float *hi, float *x, hipStream_t st)
+template <typename T>
+hipError_t launch_ens_sincos(int64_t n, int32_t Bp, const T *hi, T *x, hipStream_t st)
 {
     const int64_t tot = n * Bp;
     if (tot <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ens_sincos, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, Bp, hi, x);
+    hipLaunchKernelGGL((k_ens_sincos<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, Bp, hi, x);
     return hipGetLastError();
 }
 
-hipError_t launch_ens_colsum(int64_t n, int64_t J, const float *x, float *part, hipStream_t st)
+template <typename T>
+hipError_t launch_ens_colsum(int64_t n, int64_t J, const T *x, T *part, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ens_colsum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, J, x, part);
+    hipLaunchKernelGGL((k_ens_colsum<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, J, x, part);
     return hipGetLastError();
 }
 
-hipError_t launch_ens_order(int64_t n, int32_t Bp, int32_t B, const float *part, double *r, double *psi, hipStream_t st)
+template <typename T>
+hipError_t launch_ens_order(int64_t n, int32_t Bp, int32_t B, const T *part, double *r, double *psi, hipStream_t st)
 {
     if (B <= 0) return hipSuccess;
     const int64_t nchunk = (n + 255) / 256;
-    hipLaunchKernelGGL(k_ens_order, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, nchunk, Bp, B, 1.0 / (double)n,
-                       part, r, psi);
+    hipLaunchKernelGGL((k_ens_order<T>), dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, nchunk, Bp, B,
+                       1.0 / (double)n, part, r, psi);
     return hipGetLastError();
 }
+
+template hipError_t launch_ens_rows<float>(const EnsRowArgs<float> &, hipStream_t);
+template hipError_t launch_ens_rows<double>(const EnsRowArgs<double> &, hipStream_t);
+template hipError_t launch_ens_sincos<float>(int64_t, int32_t, const float *, float *, hipStream_t);
+template hipError_t launch_ens_sincos<double>(int64_t, int32_t, const double *, double *, hipStream_t);
+template hipError_t launch_ens_colsum<float>(int64_t, int64_t, const float *, float *, hipStream_t);
+template hipError_t launch_ens_colsum<double>(int64_t, int64_t, const double *, double *, hipStream_t);
+template hipError_t launch_ens_order<float>(int64_t, int32_t, int32_t, const float *, double *, double *, hipStream_t);
+template hipError_t launch_ens_order<double>(int64_t, int32_t, int32_t, const double *, double *, double *, hipStream_t);
 
 }  // namespace kur

@@ -293,21 +293,26 @@ kur_status hipfail(kur_ctx *c, hipError_t e, const char *what)
     return ctx_fail(c, e == hipErrorOutOfMemory ? KUR_ENOMEM : KUR_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-kur_status need_f32(kur_ctx *c)
+kur_status need_real(kur_ctx *c)
 {
-    if (ctx_esz(c) != 4) return ctx_fail(c, KUR_EINVAL, "ensembles run in FP32 (create the context with KUR_F32)");
+    if (ctx_esz(c) != 4 && ctx_esz(c) != 8) return ctx_fail(c, KUR_EINVAL, "ensembles run in FP32 or FP64");
     return KUR_OK;
 }
+
+// output tile of the dense products for the context's reals
+int tile_rows(kur_ctx *c) { return ctx_esz(c) == 8 ? kEnsTileRowsF64 : kEnsTileRows; }
+int tile_cols(kur_ctx *c) { return ctx_esz(c) == 8 ? kEnsTileColsF64 : kEnsTileCols; }
 
 // items of the dense products for J columns
 hipError_t upload_items(kur_ctx *c, EnsState &S)
 {
     const int64_t J = 2 * (int64_t)S.Bp;
     if (S.items_J == J) return hipSuccess;
+    const int TR = tile_rows(c), TC = tile_cols(c);
     std::vector<EnsItem> items;
     for (size_t g = 0; g < S.L.gblk.size(); ++g)
-        for (int32_t r0 = 0; r0 < S.L.gblk[g].size; r0 += kEnsTileRows)
-            for (int64_t c0 = 0; c0 < J; c0 += kEnsTileCols) items.push_back(EnsItem{(int32_t)g, r0, (int32_t)c0, 0});
+        for (int32_t r0 = 0; r0 < S.L.gblk[g].size; r0 += TR)
+            for (int64_t c0 = 0; c0 < J; c0 += TC) items.push_back(EnsItem{(int32_t)g, r0, (int32_t)c0, 0});
     S.nitems = (int64_t)items.size();
     S.items_J = J;
     return put(S.d_items, items.data(), sizeof(EnsItem) * items.size(), ctx_stream(c));
@@ -350,7 +355,8 @@ hipError_t harvest(kur_ctx *c, EnsState &S)
 }
 
 // one stage: dense products, then rows (CSR gathers + epilogue) from x[cur] into x[cur ^ 1]
-hipError_t launch_stage(kur_ctx *c, EnsState &S, int stage, double dt)
+template <typename T>
+hipError_t launch_stage_t(kur_ctx *c, EnsState &S, int stage, double dt)
 {
     const hipStream_t st = ctx_stream(c);
     const int64_t J = 2 * (int64_t)S.Bp;
@@ -361,35 +367,36 @@ hipError_t launch_stage(kur_ctx *c, EnsState &S, int stage, double dt)
         g.rng = S.d_rng.as<EnsRng>();
         g.items = S.d_items.as<EnsItem>();
         g.bits = S.d_bits.as<uint32_t>();
-        g.x = S.d_x[S.cur].as<float>();
-        g.y = S.d_y.as<float>();
+        g.x = S.d_x[S.cur].p;
+        g.y = S.d_y.p;
         g.J = J;
-        if ((e = record(c, S, 0, false)) != hipSuccess || (e = launch_ens_gemm(g, S.nitems, st)) != hipSuccess ||
+        if ((e = record(c, S, 0, false)) != hipSuccess ||
+            (e = sizeof(T) == 8 ? launch_ens_gemm_f64(g, S.nitems, st) : launch_ens_gemm(g, S.nitems, st)) != hipSuccess ||
             (e = record(c, S, 0, true)) != hipSuccess)
             return e;
     }
-    EnsRowArgs a;
+    EnsRowArgs<T> a;
     a.n = S.L.n;
     a.Bp = S.Bp;
     a.stage = stage;
     a.compensate = ctx_compensate(c);
-    a.dt = (float)dt;
-    a.half_dt = (float)(0.5 * dt);
-    a.dt6 = (float)(dt / 6.0);
+    a.dt = (T)dt;
+    a.half_dt = (T)(0.5 * dt);
+    a.dt6 = (T)(dt / 6.0);
     a.csr_ptr = S.d_csr_ptr.as<int64_t>();
     a.csr_col = S.d_csr_col.as<int32_t>();
     a.row_gemm = S.d_row_gemm.as<uint8_t>();
-    a.x = S.d_x[S.cur].as<float>();
-    a.y = S.d_y.as<float>();
-    a.x_out = S.d_x[S.cur ^ 1].as<float>();
-    a.omega = S.d_omega.as<float>();
-    a.unit = S.d_unit.as<float>();
-    a.hi = S.d_hi.as<float>();
-    a.lo = S.d_lo.as<float>();
+    a.x = S.d_x[S.cur].as<T>();
+    a.y = S.d_y.as<T>();
+    a.x_out = S.d_x[S.cur ^ 1].as<T>();
+    a.omega = S.d_omega.as<T>();
+    a.unit = S.d_unit.as<T>();
+    a.hi = S.d_hi.as<T>();
+    a.lo = S.d_lo.as<T>();
     a.wind = S.d_wind.as<int32_t>();
-    a.ksum = S.d_ksum.as<float>();
-    a.kout = S.d_kout.as<float>();
-    if ((e = record(c, S, 1, false)) != hipSuccess || (e = launch_ens_rows(a, st)) != hipSuccess ||
+    a.ksum = S.d_ksum.as<T>();
+    a.kout = S.d_kout.as<T>();
+    if ((e = record(c, S, 1, false)) != hipSuccess || (e = launch_ens_rows<T>(a, st)) != hipSuccess ||
         (e = record(c, S, 1, true)) != hipSuccess)
         return e;
     if (stage != 0) S.cur ^= 1;
@@ -397,10 +404,17 @@ hipError_t launch_stage(kur_ctx *c, EnsState &S, int stage, double dt)
     return hipSuccess;
 }
 
+hipError_t launch_stage(kur_ctx *c, EnsState &S, int stage, double dt)
+{
+    return ctx_esz(c) == 8 ? launch_stage_t<double>(c, S, stage, dt) : launch_stage_t<float>(c, S, stage, dt);
+}
+
 hipError_t ensure_x(kur_ctx *c, EnsState &S)
 {
     if (S.x_valid) return hipSuccess;
-    hipError_t e = launch_ens_sincos(S.L.n, S.Bp, S.d_hi.as<float>(), S.d_x[S.cur].as<float>(), ctx_stream(c));
+    hipError_t e = ctx_esz(c) == 8
+                       ? launch_ens_sincos<double>(S.L.n, S.Bp, S.d_hi.as<double>(), S.d_x[S.cur].as<double>(), ctx_stream(c))
+                       : launch_ens_sincos<float>(S.L.n, S.Bp, S.d_hi.as<float>(), S.d_x[S.cur].as<float>(), ctx_stream(c));
     if (e == hipSuccess) S.x_valid = true;
     return e;
 }
@@ -408,10 +422,13 @@ hipError_t ensure_x(kur_ctx *c, EnsState &S)
 hipError_t sample(kur_ctx *c, EnsState &S, int64_t k)
 {
     const hipStream_t st = ctx_stream(c);
-    hipError_t e = launch_ens_colsum(S.L.n, 2 * (int64_t)S.Bp, S.d_x[S.cur].as<float>(), S.d_part.as<float>(), st);
-    if (e != hipSuccess) return e;
-    return launch_ens_order(S.L.n, S.Bp, S.B, S.d_part.as<float>(), S.d_r.as<double>() + k * S.B,
-                            S.d_psi.as<double>() + k * S.B, st);
+    double *r = S.d_r.as<double>() + k * S.B, *psi = S.d_psi.as<double>() + k * S.B;
+    if (ctx_esz(c) == 8) {
+        hipError_t e = launch_ens_colsum<double>(S.L.n, 2 * (int64_t)S.Bp, S.d_x[S.cur].as<double>(), S.d_part.as<double>(), st);
+        return e != hipSuccess ? e : launch_ens_order<double>(S.L.n, S.Bp, S.B, S.d_part.as<double>(), r, psi, st);
+    }
+    hipError_t e = launch_ens_colsum<float>(S.L.n, 2 * (int64_t)S.Bp, S.d_x[S.cur].as<float>(), S.d_part.as<float>(), st);
+    return e != hipSuccess ? e : launch_ens_order<float>(S.L.n, S.Bp, S.B, S.d_part.as<float>(), r, psi, st);
 }
 
 kur_status install_layout(kur_ctx *c, EnsState &S, EnsLayout &L)
@@ -444,7 +461,7 @@ kur_status install_layout(kur_ctx *c, EnsState &S, EnsLayout &L)
 kur_status ens_ready(kur_ctx *c, EnsState *&S, bool phases)
 {
     if (!c) return KUR_EINVAL;
-    kur_status s = need_f32(c);
+    kur_status s = need_real(c);
     if (s != KUR_OK) return s;
     if (!ctx_is_device(c)) return ctx_fail(c, KUR_EDEVICE, "host-only context (device = -1)");
     S = state(c);
@@ -457,25 +474,27 @@ kur_status ens_ready(kur_ctx *c, EnsState *&S, bool phases)
     return KUR_OK;
 }
 
-kur_status set_params_impl(kur_ctx *c, EnsState &S, int32_t B, const double *K, const double *omega)
+template <typename T>
+kur_status set_params_t(kur_ctx *c, EnsState &S, int32_t B, const double *K, const double *omega)
 {
     const int64_t n = S.L.n;
     const int32_t Bp = (B + 63) / 64 * 64;
-    std::vector<float> om((size_t)n * Bp, 0.0f), unit(Bp, 0.0f);
+    const size_t z = sizeof(T);
+    std::vector<T> om((size_t)n * Bp, T(0)), unit(Bp, T(0));
     for (int32_t e = 0; e < B; ++e) {
-        unit[e] = (float)(K[e] / (double)n);
-        for (int64_t u = 0; u < n; ++u) om[(size_t)S.L.perm[u] * Bp + e] = (float)omega[(size_t)e * n + u];
+        unit[e] = (T)(K[e] / (double)n);
+        for (int64_t u = 0; u < n; ++u) om[(size_t)S.L.perm[u] * Bp + e] = (T)omega[(size_t)e * n + u];
     }
     const hipStream_t st = ctx_stream(c);
     const size_t NB = (size_t)n * Bp;
     const int64_t nchunk = (n + 255) / 256;
     hipError_t err;
-    if ((err = put(S.d_omega, om.data(), 4 * NB, st)) != hipSuccess || (err = put(S.d_unit, unit.data(), 4 * Bp, st)) != hipSuccess ||
-        (err = S.d_hi.ensure(4 * NB)) != hipSuccess || (err = S.d_lo.ensure(4 * NB)) != hipSuccess ||
-        (err = S.d_wind.ensure(4 * NB)) != hipSuccess || (err = S.d_ksum.ensure(4 * NB)) != hipSuccess ||
-        (err = S.d_x[0].ensure(8 * NB)) != hipSuccess || (err = S.d_x[1].ensure(8 * NB)) != hipSuccess ||
-        (err = S.d_y.ensure(8 * NB)) != hipSuccess || (err = S.d_kout.ensure(4 * NB)) != hipSuccess ||
-        (err = S.d_part.ensure(8 * (size_t)nchunk * Bp)) != hipSuccess)
+    if ((err = put(S.d_omega, om.data(), z * NB, st)) != hipSuccess || (err = put(S.d_unit, unit.data(), z * Bp, st)) != hipSuccess ||
+        (err = S.d_hi.ensure(z * NB)) != hipSuccess || (err = S.d_lo.ensure(z * NB)) != hipSuccess ||
+        (err = S.d_wind.ensure(4 * NB)) != hipSuccess || (err = S.d_ksum.ensure(z * NB)) != hipSuccess ||
+        (err = S.d_x[0].ensure(2 * z * NB)) != hipSuccess || (err = S.d_x[1].ensure(2 * z * NB)) != hipSuccess ||
+        (err = S.d_y.ensure(2 * z * NB)) != hipSuccess || (err = S.d_kout.ensure(z * NB)) != hipSuccess ||
+        (err = S.d_part.ensure(2 * z * (size_t)nchunk * Bp)) != hipSuccess)
         return hipfail(c, err, "ensemble buffers");
     if (Bp != S.Bp) S.has_phases = false;
     S.B = B;
@@ -485,33 +504,44 @@ kur_status set_params_impl(kur_ctx *c, EnsState &S, int32_t B, const double *K, 
     return KUR_OK;
 }
 
-kur_status set_phases_impl(kur_ctx *c, EnsState &S, const double *theta)
+kur_status set_params_impl(kur_ctx *c, EnsState &S, int32_t B, const double *K, const double *omega)
+{
+    return ctx_esz(c) == 8 ? set_params_t<double>(c, S, B, K, omega) : set_params_t<float>(c, S, B, K, omega);
+}
+
+template <typename T>
+kur_status set_phases_t(kur_ctx *c, EnsState &S, const double *theta)
 {
     const int64_t n = S.L.n;
     const int32_t B = S.B, Bp = S.Bp;
     const size_t NB = (size_t)n * Bp;
-    std::vector<float> hi(NB, 0.0f), lo(NB, 0.0f);
+    std::vector<T> hi(NB, T(0)), lo(NB, T(0));
     std::vector<int32_t> wind(NB, 0);
-    const double P1 = two_pi_p1(4), P2 = two_pi_p2(4);
+    const double P1 = two_pi_p1(sizeof(T)), P2 = two_pi_p2(sizeof(T));
     for (int32_t e = 0; e < B; ++e)
         for (int64_t u = 0; u < n; ++u) {
             const double t = theta[(size_t)e * n + u];
             const double q = std::nearbyint(t / (2.0 * kPi));
             const double red = (t - q * P1) - q * P2;
             const size_t ix = (size_t)S.L.perm[u] * Bp + e;
-            hi[ix] = (float)red;
-            lo[ix] = (float)(red - (double)hi[ix]);
+            hi[ix] = (T)red;
+            lo[ix] = (T)(red - (double)hi[ix]);
             wind[ix] = (int32_t)q;
         }
     const hipStream_t st = ctx_stream(c);
     hipError_t err;
-    if ((err = put(S.d_hi, hi.data(), 4 * NB, st)) != hipSuccess || (err = put(S.d_lo, lo.data(), 4 * NB, st)) != hipSuccess ||
+    if ((err = put(S.d_hi, hi.data(), sizeof(T) * NB, st)) != hipSuccess || (err = put(S.d_lo, lo.data(), sizeof(T) * NB, st)) != hipSuccess ||
         (err = put(S.d_wind, wind.data(), 4 * NB, st)) != hipSuccess)
         return hipfail(c, err, "ensemble phase upload");
     S.has_phases = true;
     S.x_valid = false;
     S.cur = 0;
     return KUR_OK;
+}
+
+kur_status set_phases_impl(kur_ctx *c, EnsState &S, const double *theta)
+{
+    return ctx_esz(c) == 8 ? set_phases_t<double>(c, S, theta) : set_phases_t<float>(c, S, theta);
 }
 
 bool finite_all(const double *a, size_t n)
@@ -525,12 +555,12 @@ bool finite_all(const double *a, size_t n)
 kur_status time_steps(kur_ctx *c, EnsState &S, int trials, double *ms_per_step)
 {
     const hipStream_t st = ctx_stream(c);
-    const size_t NB = (size_t)S.L.n * S.Bp;
+    const size_t NB = (size_t)S.L.n * S.Bp, z = (size_t)ctx_esz(c);
     DBuf sh, sl, sw;
     hipError_t e;
-    if ((e = sh.ensure(4 * NB)) != hipSuccess || (e = sl.ensure(4 * NB)) != hipSuccess || (e = sw.ensure(4 * NB)) != hipSuccess ||
-        (e = hipMemcpyAsync(sh.p, S.d_hi.p, 4 * NB, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(sl.p, S.d_lo.p, 4 * NB, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+    if ((e = sh.ensure(z * NB)) != hipSuccess || (e = sl.ensure(z * NB)) != hipSuccess || (e = sw.ensure(4 * NB)) != hipSuccess ||
+        (e = hipMemcpyAsync(sh.p, S.d_hi.p, z * NB, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(sl.p, S.d_lo.p, z * NB, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(sw.p, S.d_wind.p, 4 * NB, hipMemcpyDeviceToDevice, st)) != hipSuccess)
         return hipfail(c, e, "ensemble state save");
     const int cur0 = S.cur;
@@ -555,8 +585,8 @@ kur_status time_steps(kur_ctx *c, EnsState &S, int trials, double *ms_per_step)
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (e == hipSuccess) {
-        if ((e = hipMemcpyAsync(S.d_hi.p, sh.p, 4 * NB, hipMemcpyDeviceToDevice, st)) == hipSuccess &&
-            (e = hipMemcpyAsync(S.d_lo.p, sl.p, 4 * NB, hipMemcpyDeviceToDevice, st)) == hipSuccess &&
+        if ((e = hipMemcpyAsync(S.d_hi.p, sh.p, z * NB, hipMemcpyDeviceToDevice, st)) == hipSuccess &&
+            (e = hipMemcpyAsync(S.d_lo.p, sl.p, z * NB, hipMemcpyDeviceToDevice, st)) == hipSuccess &&
             (e = hipMemcpyAsync(S.d_wind.p, sw.p, 4 * NB, hipMemcpyDeviceToDevice, st)) == hipSuccess)
             e = hipStreamSynchronize(st);
     }
@@ -574,7 +604,7 @@ extern "C" {
 kur_status kur_ens_set_graph_csr(kur_ctx *c, int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *labels)
 {
     if (!c) return KUR_EINVAL;
-    kur_status s = need_f32(c);
+    kur_status s = need_real(c);
     if (s != KUR_OK) return s;
     EnsState *S = state(c);
     if (!S) return ctx_fail(c, KUR_ENOMEM, "host allocation failed");
@@ -607,8 +637,9 @@ kur_status kur_ens_info(kur_ctx *c, int64_t *out)
     out[8] = S->nitems;
     out[9] = L.symmetric ? 1 : 0;
     out[10] = L.n_pair_ranges;
-    int64_t padded = 0;  // cells the product tiles issue: rows to 256, k extent to 32
-    for (const EnsBlk &g : L.gblk) padded += (int64_t)((g.size + kEnsTileRows - 1) / kEnsTileRows) * kEnsTileRows * g.words * 32;
+    int64_t padded = 0;  // cells the product tiles issue: rows to the tile height, k extent to 32
+    const int64_t TR = tile_rows(c);
+    for (const EnsBlk &g : L.gblk) padded += (int64_t)((g.size + TR - 1) / TR) * TR * g.words * 32;
     out[11] = padded;
     return KUR_OK;
 }
@@ -674,7 +705,7 @@ kur_status kur_ens_row_pattern(kur_ctx *c, int64_t m, int32_t *csr_cols, int64_t
 kur_status kur_ens_set_params(kur_ctx *c, int32_t B, const double *K, const double *omega)
 {
     if (!c) return KUR_EINVAL;
-    kur_status s = need_f32(c);
+    kur_status s = need_real(c);
     if (s != KUR_OK) return s;
     if (!ctx_is_device(c)) return ctx_fail(c, KUR_EDEVICE, "host-only context (device = -1)");
     EnsState *S = state(c);
@@ -710,6 +741,15 @@ kur_status kur_ens_eval_rhs(kur_ctx *c, double *dtheta)
     if ((e = ensure_x(c, *S)) != hipSuccess || (e = launch_stage(c, *S, 0, 0.0)) != hipSuccess) return hipfail(c, e, "ensemble rhs");
     const int64_t n = S->L.n;
     const size_t NB = (size_t)n * S->Bp;
+    if (ctx_esz(c) == 8) {
+        std::vector<double> k(NB);
+        if ((e = hipMemcpyAsync(k.data(), S->d_kout.p, 8 * NB, hipMemcpyDeviceToHost, ctx_stream(c))) != hipSuccess ||
+            (e = hipStreamSynchronize(ctx_stream(c))) != hipSuccess)
+            return hipfail(c, e, "ensemble rhs download");
+        for (int32_t r = 0; r < S->B; ++r)
+            for (int64_t u = 0; u < n; ++u) dtheta[(size_t)r * n + u] = k[(size_t)S->L.perm[u] * S->Bp + r];
+        return KUR_OK;
+    }
     std::vector<float> k(NB);
     if ((e = hipMemcpyAsync(k.data(), S->d_kout.p, 4 * NB, hipMemcpyDeviceToHost, ctx_stream(c))) != hipSuccess ||
         (e = hipStreamSynchronize(ctx_stream(c))) != hipSuccess)
@@ -759,21 +799,32 @@ kur_status kur_ens_get_phases(kur_ctx *c, double *theta, int wrapped)
     if (s != KUR_OK) return s;
     if (!theta) return ctx_fail(c, KUR_EINVAL, "theta must not be NULL");
     const int64_t n = S->L.n;
-    const size_t NB = (size_t)n * S->Bp;
-    std::vector<float> hi(NB), lo(NB);
+    const size_t NB = (size_t)n * S->Bp, z = (size_t)ctx_esz(c);
+    // the phase and its compensation term as stored (FP32 or FP64), widened to double below
+    std::vector<unsigned char> hi(z * NB), lo(z * NB);
     std::vector<int32_t> wind(NB);
     const hipStream_t st = ctx_stream(c);
     hipError_t e;
-    if ((e = hipMemcpyAsync(hi.data(), S->d_hi.p, 4 * NB, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(lo.data(), S->d_lo.p, 4 * NB, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+    if ((e = hipMemcpyAsync(hi.data(), S->d_hi.p, z * NB, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(lo.data(), S->d_lo.p, z * NB, hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipMemcpyAsync(wind.data(), S->d_wind.p, 4 * NB, hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
         return hipfail(c, e, "ensemble phase download");
-    const double P1 = two_pi_p1(4), P2 = two_pi_p2(4);
+    auto real_at = [&](const std::vector<unsigned char> &v, size_t i) {
+        if (z == 8) {
+            double d;
+            std::memcpy(&d, v.data() + 8 * i, 8);
+            return d;
+        }
+        float f;
+        std::memcpy(&f, v.data() + 4 * i, 4);
+        return (double)f;
+    };
+    const double P1 = two_pi_p1((int)z), P2 = two_pi_p2((int)z);
     for (int32_t r = 0; r < S->B; ++r)
         for (int64_t u = 0; u < n; ++u) {
             const size_t ix = (size_t)S->L.perm[u] * S->Bp + r;
-            double x = (double)hi[ix] + (double)lo[ix];
+            double x = real_at(hi, ix) + real_at(lo, ix);
             if (wrapped) {
                 x = std::remainder(x, 2.0 * kPi);
                 if (x >= kPi) x -= 2.0 * kPi;
@@ -807,7 +858,7 @@ kur_status kur_ens_autotune_csr(kur_ctx *c, int64_t n, const int64_t *row_ptr, c
                                 int32_t B, int32_t effort, double *report)
 {
     if (!c) return KUR_EINVAL;
-    kur_status s = need_f32(c);
+    kur_status s = need_real(c);
     if (s != KUR_OK) return s;
     if (!ctx_is_device(c)) return ctx_fail(c, KUR_EDEVICE, "tuning needs a device context");
     if (effort < 0 || effort > 2) return ctx_fail(c, KUR_EINVAL, "effort must be 0, 1 or 2");
