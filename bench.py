@@ -153,6 +153,17 @@ def bench_batch(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     assert np.isfinite(r).all()
+    # row-kernel launch time from HIP events on a separate short run (event timing replaces the
+    # graph replay by plain launches of the same kernels)
+    k.set_option("timing", 1)
+    k.kernel_time()
+    k.batch_step(dt, 50, 10)
+    k.sync()
+    launches, kms = k.kernel_time()
+    k.set_option("timing", 0)
+    avg_ms = kms / max(1, launches)
+    b_eval = algorithmic_bytes_per_eval(info, 4)
+    achieved = b_eval / (avg_ms * 1e-3) / 1e9
     out = {"metric": "aggregate node-steps/s of a batched ensemble (RK4)", "value": ntot * args.steps / el,
            "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -162,7 +173,10 @@ def bench_batch(args):
                                   "r every 10 steps, seed 1004", "nodes": ntot, "list_entries": info["list_entries"],
                       "inter_entries": info["inter_entries"], "tiles": info["tiles"]},
            "layout": {"tuning": tuning, "chunk": info["chunk"]},
-           "r_final_K0": float(r[-1, 0]), "r_final_K6": float(r[-1, -1])}
+           "r_final_K0": float(r[-1, 0]), "r_final_K6": float(r[-1, -1]),
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_rows", "avg_launch_ms": avg_ms,
+                        "algorithmic_bytes_per_launch": b_eval}}
     print(json.dumps(out), flush=True)
     k.close()
 
