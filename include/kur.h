@@ -421,7 +421,10 @@ kur_status kur_tune_key(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const i
  *
  * kur_ens_set_graph_csr  CSR with planted labels, as kur_set_graph_csr; host-only contexts keep
  *                        the layout for inspection (kur_ens_row_pattern); params and phases unset
- * kur_ens_set_params     K (B) and omega (B x n, replica-major, user order); copied
+ * kur_ens_set_params     K (B) and omega (B x n, replica-major, user order); copied. KUR_EINVAL
+ *                        when a matrix-core community's rows times 2 Bp reach 2^31 (the products
+ *                        address one community's X rows with 32-bit offsets: 4.19 M nodes at
+ *                        B = 256)
  * kur_ens_set_phases     theta (B x n, replica-major, user order, |theta| <= 1e9)
  * kur_ens_eval_rhs       dtheta (B x n) at the current phases
  * kur_ens_step           nsteps RK4 steps of size dt; with r_every > 0, r_out and psi_out (each

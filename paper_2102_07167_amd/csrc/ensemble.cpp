@@ -714,6 +714,15 @@ kur_status kur_ens_set_params(kur_ctx *c, int32_t B, const double *K, const doub
     if (B < 1 || B > kMaxReplicas) return ctx_fail(c, KUR_EINVAL, "B must be in [1, 256]");
     if (!K || !omega) return ctx_fail(c, KUR_EINVAL, "K and omega must not be NULL");
     if (!finite_all(K, B) || !finite_all(omega, (size_t)B * S->L.n)) return ctx_fail(c, KUR_EINVAL, "K and omega must be finite");
+    {
+        // the matrix-product kernels address the X rows of one range with 32-bit offsets k J + c
+        const int64_t J = 2 * (int64_t)((B + 63) / 64 * 64);
+        int64_t maxlen = 0;
+        for (const EnsRng &R : S->L.rng) maxlen = std::max<int64_t>(maxlen, R.len);
+        if (maxlen * J >= ((int64_t)1 << 31))
+            return ctx_fail(c, KUR_EINVAL, "a matrix-core community of " + std::to_string(maxlen) + " nodes is too large for " +
+                                               std::to_string(B) + " replicas (its rows x 2 Bp must stay below 2^31)");
+    }
     hipError_t e = hipSetDevice(ctx_device(c));
     if (e != hipSuccess) return hipfail(c, e, "hipSetDevice");
     return set_params_impl(c, *S, B, K, omega);
