@@ -233,14 +233,38 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
     const int nrows = tl.r1 - tl.r0;
     const int rowbase = bi.row0 + tl.r0;
 
-    for (int r = threadIdx.x; r < nrows; r += NT) L.acc[r] = vzero<VT>();
-    if (threadIdx.x == 0) L.xs[W] = vzero<VT>();
-    // localised order parameters: wave w folds the groups w, w + NT/64, ... (each a fixed-order
-    // sum of the column block's tile partials, times the group's factor); with several groups
-    // thread 0 then adds the waves' results in wave order
+    // Small tiles are a chain of dependent memory round trips, so the loads that depend only on
+    // the tile are issued first: the tile's inter-block range and the first row bound of every
+    // thread, and the tile partials of the localised order parameters, which are folded only at
+    // the end (one group per wave, at most 64 partials per group).
+    const int64_t i0 = g.inter_ptr[rowbase], i1 = g.inter_ptr[rowbase + nrows];
+    const int64_t ib0 = (int)threadIdx.x <= nrows ? g.inter_ptr[rowbase + (int)threadIdx.x] : 0;
     const int ngq = bi.ngrp;
     const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wq < ngq) {
+    bool late = false;     // this tile folds at the end (uniform over the workgroup)
+    VT pv = vzero<VT>();   // late fold: this lane's partial of the wave's group
+    T pmode = T(0);
+    if (ngq <= NT / 64) {
+        late = true;
+        if (wq < ngq) {
+            const Grp gq = g.grp[bi.grp0 + wq];
+            const int t0 = g.blk[gq.blk].tile0, nt = g.blk[gq.blk].ntiles;
+            pmode = (T)gq.mode;
+            const int i = threadIdx.x & 63;
+            if (nt <= 64) {
+                if (i < nt) pv = part_in[t0 + i];
+            } else {
+                for (int j = i; j < nt; j += 64) vacc(pv, part_in[t0 + j]);
+            }
+        }
+    }
+
+    for (int r = threadIdx.x; r < nrows; r += NT) L.acc[r] = vzero<VT>();
+    if (threadIdx.x == 0) L.xs[W] = vzero<VT>();
+    if (!late) {
+        // more groups than waves: wave w folds the groups w, w + NT/64, ... (each a fixed-order
+        // sum of the column block's tile partials, times the group's factor) and thread 0 then
+        // adds the waves' results in wave order
         VT sq = vzero<VT>();
         for (int q = wq; q < ngq; q += NT / 64) {
             const Grp gq = g.grp[bi.grp0 + q];
@@ -250,15 +274,17 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
             sx = vwave_sum(sx);
             vacc(sq, vscale(sx, (T)gq.mode));
         }
-        if ((threadIdx.x & 63) == 0) L.red[ngq == 1 ? NT / 64 : wq] = sq;
+        if ((threadIdx.x & 63) == 0) L.red[wq] = sq;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // read by the epilogue after the barrier that ends this function
+            VT s = L.red[0];
+            for (int w = 1; w < NT / 64; ++w) vacc(s, L.red[w]);
+            L.red[NT / 64] = s;
+        }
     }
-    __syncthreads();  // accumulators, pad slot and group sums visible to every wave
-    if (ngq > 1 && threadIdx.x == 0) {
-        // read by the epilogue after the barrier that ends this function
-        VT s = L.red[0];
-        for (int w = 1; w < min(ngq, NT / 64); ++w) vacc(s, L.red[w]);
-        L.red[NT / 64] = s;
-    }
+    // the accumulators and the pad slot become visible at the first barrier below (every path
+    // to a reader passes one)
 
     // G > 0: G lanes per row (short rows); G == 0: every wave streams a contiguous run of rows;
     // G < 0: no list entries in any chunk (only inter-block entries)
@@ -361,13 +387,13 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
     // own the contiguous entries [i0, i1) of the inter CSR; they are gathered in rounds of
     // 4 NT entries (all loads of a round in flight together) into the staging area, which is
     // free now, and each row then adds its entries in order.
-    const int64_t i0 = g.inter_ptr[rowbase], i1 = g.inter_ptr[rowbase + nrows];
     if (i1 > i0) {  // uniform over the workgroup
         const int total = (int)(i1 - i0);
         constexpr int U = 4;
         const int round = min(U * NT, W);  // entries per round: at most the staging area
         __syncthreads();  // the staging area and bnd are no longer read by the list pass
-        for (int r = threadIdx.x; r <= nrows; r += NT) L.bnd[r] = (int)(g.inter_ptr[rowbase + r] - i0);
+        if ((int)threadIdx.x <= nrows) L.bnd[threadIdx.x] = (int)(ib0 - i0);
+        for (int r = threadIdx.x + NT; r <= nrows; r += NT) L.bnd[r] = (int)(g.inter_ptr[rowbase + r] - i0);
         for (int base = 0; base < total; base += round) {
             if (base > 0) __syncthreads();  // the previous round's values are consumed
             const int end = min(total, base + round);
@@ -389,6 +415,19 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
                 VT a = L.xs[lo - base];
                 for (int j = lo + 1; j < hi; ++j) vacc(a, L.xs[j - base]);
                 vacc(L.acc[r], a);
+            }
+        }
+    }
+    if (late) {
+        // the late fold: wave w sums its group's partials (fixed order), times the group's factor
+        VT sx = vwave_sum(pv);
+        if (wq < ngq && (threadIdx.x & 63) == 0) L.red[ngq == 1 ? NT / 64 : wq] = vscale(sx, pmode);
+        if (ngq > 1) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                VT s = L.red[0];
+                for (int w = 1; w < ngq; ++w) vacc(s, L.red[w]);
+                L.red[NT / 64] = s;
             }
         }
     }
