@@ -193,3 +193,36 @@ def test_ens_dense_offdiagonal_blocks(need_gpu, tau, B):
         tho, ro, _ = oracle.rk4(g, om[e], float(K[e]), th[e], float(np.float32(0.01)), 100, r_every=50)
         assert np.abs(wrap(thT[e] - tho)).max() < 1e-5
         assert np.abs(r[:, e] - ro).max() < 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_ens_autotune_then_matches_oracle(need_gpu, dtype):
+    """kur_ens_autotune_csr times whole RK4 steps for candidate thresholds (effort 0: 0, 0.5 and
+    2, the last putting no block on the matrix cores), installs the graph with the fastest and
+    leaves the replicas unset; the installed layout then matches the oracle at the dtype's bound."""
+    g = paired_graph(23)
+    B = 70
+    K, om, th = replicas(g.n, B, seed=10)
+    tol = 1e-5 if dtype == "f32" else 1e-12
+    with Kuramoto(dtype, device=0) as k:
+        rep = k.ens_autotune(g, B, 0)
+        assert rep["ens_tau"] in (0.0, 0.5, 2.0) and 2 <= rep["timed"] <= 3
+        assert rep["ms_per_step"] > 0
+        assert rep["ms_per_step"] <= np.nanmin([rep["ms_all_gemm"], rep["ms_no_gemm"]]) + 1e-9
+        info = k.ens_info()
+        assert info["B"] == 0
+        if rep["ens_tau"] == 2.0:
+            assert info["gemm_blocks"] == 0
+        else:
+            assert info["gemm_blocks"] > 0
+        k.ens_set_params(K, om)
+        k.ens_set_phases(th)
+        F = k.ens_eval_rhs()
+        k.ens_step(0.01, 50)
+        thT = k.ens_get_phases()
+    dt = float(np.float32(0.01)) if dtype == "f32" else 0.01
+    for e in (0, 35, 69):
+        Fo = oracle.rhs(g, om[e], float(K[e]), th[e])
+        assert np.abs(F[e] - Fo).max() <= tol * np.abs(Fo).max(), e
+        tho, _, _ = oracle.rk4(g, om[e], float(K[e]), th[e], dt, 50)
+        assert np.abs(wrap(thT[e] - tho)).max() < tol, e
