@@ -66,6 +66,8 @@ def make_workload(name: str):
         return gen.all_to_all()
     if name == "pairs":
         return gen.sbm_paired_workload()
+    if name == "paper":
+        return gen.paper_four_communities()
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -83,6 +85,10 @@ def workload_desc(name: str, w, info) -> dict:
         d["workload"] = ("paired SBM N=65536 = 64x1024, rho_in 0.97, communities 2i and 2i+1 joined by a dense "
                          "off-diagonal block of density 0.9, p_out 2e-4, omega~N(0,1), K=4, dt=0.01, seed 1008")
         d["dense_offdiagonal_blocks"] = info.get("pairs")
+    elif name == "paper":
+        d["workload"] = ("paper-shaped: M=4096 in 4 equal communities (rho_in 0.95, p_out 0.05: densities not stated "
+                         "in the paper, a stated guess), omega_m the paper's special choice with omega0=2, splay "
+                         "theta0, K=3, T=200 with fixed dt=0.01 (20000 classical RK4 steps), seed 1006")
     else:
         d["workload"] = "all-to-all N=512, omega~N(0,1), K=2, dt=0.01, seed 1001"
     return d
@@ -265,7 +271,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="het", choices=["het", "sbm", "a2a", "pairs", "batch", "ens"])
+    ap.add_argument("--workload", default="het", choices=["het", "sbm", "a2a", "pairs", "paper", "batch", "ens"])
     ap.add_argument("--replicas", type=int, default=128, help="replicas of the ensemble workload (1..256)")
     ap.add_argument("--ens-graph", choices=["sbm", "paired"], default="sbm",
                     help="graph of the ensemble workload: the equal-community SBM or the paired SBM")
@@ -275,7 +281,7 @@ def main():
                     help="first run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--option", action="append", default=[], help="library option key=value")
     ap.add_argument("--dtype", choices=["f32", "f64"], default=None,
-                    help="arithmetic type (default: f64 for a2a, else f32)")
+                    help="arithmetic type (default: f64 for a2a and paper, else f32)")
     ap.add_argument("--tune-effort", type=int, default=1, choices=[-1, 0, 1, 2],
                     help="layout autotuning effort (-1: defaults and --option values only)")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
@@ -309,7 +315,9 @@ def main():
     t0 = time.perf_counter()
     w = make_workload(args.workload)
     log("workload %s generated in %.1f s (nnz %d)" % (w.name, time.perf_counter() - t0, w.graph.nnz))
-    dtype = args.dtype or ("f64" if args.workload == "a2a" else "f32")
+    if args.workload == "paper" and "--steps" not in sys.argv:
+        args.steps = w.steps  # the whole T = 200 integration
+    dtype = args.dtype or ("f64" if args.workload in ("a2a", "paper") else "f32")
     elem = 8 if dtype == "f64" else 4
     k = Kuramoto(dtype, device=0)
     for kv in args.option:
@@ -437,6 +445,15 @@ def main():
         log("adjoint %d steps: backward %.1f ms, with forward %.1f ms, from recorded stages %.1f ms, forward %.1f ms "
             "(ratios %.2f / %.2f / %.2f)" % (na, 1e3 * t_bwd, 1e3 * t_full, 1e3 * t_bwd_st, 1e3 * t_fwd,
                                              t_bwd / t_fwd, t_full / t_fwd, t_bwd_st / t_fwd))
+    if args.workload == "paper":
+        # the paper's own wall times for this experiment (MATLAB, hardware and precision not
+        # stated, variable-step integrator): context beside the same integration here, not a target
+        out["paper_context"] = {"seconds_for_T200": el * w.steps / args.steps,
+                                "paper_seconds_localised": 54.0, "paper_seconds_straightforward": 890.0,
+                                "paper_hardware": "not stated (MATLAB)",
+                                "note": "Sec. 3 numerical comparison, M = 4096, four communities; the paper's "
+                                        "integrator and step are not stated for this run, here fixed-step classical "
+                                        "RK4 with dt = 0.01"}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, %.0f s budget)" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

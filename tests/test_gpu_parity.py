@@ -311,3 +311,30 @@ def test_het_sbm_n2p20_sampled_rows(need_gpu):
     assert abs(math.fsum(th - th0 - T * om) / g.n) < 1e-5
     ro, _ = oracle.order_parameter(th)
     assert abs(r - ro) < 1e-5
+
+
+def test_paper_four_communities(need_gpu):
+    """The paper-shaped workload of the bench (M = 4096 in four equal communities, the special
+    omega with omega0 = 2, splay theta0, K = 3): RHS and 200 FP64 RK4 steps against the oracle
+    at 1e-12; then the whole T = 200 integration (20000 steps) keeps the mean of
+    theta - theta0 - t omega at 0 (symmetric A) and stays finite."""
+    w = gen.paper_four_communities()
+    g = w.graph
+    assert g.n == 4096 and w.steps == 20000
+    with Kuramoto("f64", device=0) as k:
+        k.set_graph(g)
+        k.set_params(w.omega, w.K)
+        k.set_phases(w.theta0)
+        F = k.eval_rhs()
+        Fo = oracle.rhs(g, w.omega, w.K, w.theta0)
+        assert np.abs(F - Fo).max() <= 1e-12 * np.abs(Fo).max()
+        k.step_rk4(w.dt, 200)
+        th = k.get_phases(wrapped=False)
+        tho, _, _ = oracle.rk4(g, w.omega, w.K, w.theta0, w.dt, 200)
+        assert np.abs(th - tho).max() <= 1e-12 * max(1.0, np.abs(tho).max())
+        k.set_phases(w.theta0)
+        r, _ = k.step_rk4(w.dt, w.steps, 1000)
+        thT = k.get_phases(wrapped=False)
+    assert np.isfinite(r).all() and np.isfinite(thT).all()
+    T = w.steps * w.dt
+    assert abs(np.mean(thT - w.theta0 - T * w.omega)) < 1e-9
