@@ -92,7 +92,7 @@ const char *kur_last_error(const kur_ctx *ctx);
  *                 memory of A's layout again), which the adjoint of an asymmetric A needs.
  *                 0 (default): not kept.
  *   "chunk"       columns of a diagonal block staged in LDS at a time: a multiple of 64, at
- *                 most 8128 (FP32) or 4032 (FP64). Default 4096 (FP32), 2048 (FP64).
+ *                 most 8128 (FP32) or 4032 (FP64). Default 4096 (FP32), 4032 (FP64).
  *   "tile_rows"   maximal rows per work tile (64..4096). Default 256.
  *   "tiles"       target number of work tiles (>= 1). Default 4096.
  *   "tile_min_cost" least work per tile in list-entry equivalents (a row costs its stored list
