@@ -117,7 +117,7 @@ def cpu_baseline(w, seconds: float) -> dict:
         if el >= seconds or reps >= 1000:
             break
     t_eval = el / reps * (g.n / len(rows))  # extrapolated full evaluation
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle.threads()  # the OpenMP threads of the oracle's row loop
     return {"value": 1.0 / (4.0 * t_eval), "unit": "RK4 steps/s", "cores": cores, "kind": "oracle",
             "sample": "FP64 direct-summation RHS on a seeded 1/64 row sample (%d rows) x%d repeats in %.1f s, "
                       "extrapolated x%d per RHS and x4 RHS per RK4 step" % (len(rows), reps, el, g.n // len(rows)),

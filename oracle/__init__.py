@@ -70,6 +70,8 @@ def _load():
         lib.orc_adjoint_rk4.argtypes = [i64, ci, P, P, P, ci, P, f64, f64, i64, P, P, P, P, P]
         lib.orc_potential.restype = f64
         lib.orc_potential.argtypes = [i64, ci, P, P, P, ci, P, f64, P]
+        lib.orc_threads.argtypes = []
+        lib.orc_threads.restype = ci
         _lib = lib
     return _lib
 
@@ -187,6 +189,11 @@ def adjoint_rk4(graph, omega, K, theta0, dt, nsteps, dl_dthetaT, scaling: int = 
 def potential(graph, omega, K, theta, scaling: int = 0) -> float:
     omega, theta = _f64(omega), _f64(theta)
     return _load().orc_potential(*_g(graph), scaling, _p(omega), float(K), _p(theta))
+
+
+def threads() -> int:
+    """Threads the oracle's parallel row loops run on (OpenMP)."""
+    return int(_load().orc_threads())
 
 
 def loss_and_seed(theta_T, target):

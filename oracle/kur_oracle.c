@@ -25,6 +25,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 typedef struct {
     int64_t n;
@@ -92,6 +93,9 @@ void orc_rhs_rows(int64_t n, int complete, const int64_t *row_ptr, const int32_t
         out[i] = omega[m] + K * row_scale(&g, m) * coupling_sum(&g, theta, m);
     }
 }
+
+/* threads of the parallel row loops (timing reports only) */
+int orc_threads(void) { return omp_get_max_threads(); }
 
 /* r and psi of (1/N) sum_m e^{i theta_m} (Sec. 2, eq. OrderParameter) */
 void orc_order_parameter(int64_t n, const double *theta, double *r, double *psi)
