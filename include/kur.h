@@ -118,6 +118,11 @@ const char *kur_last_error(const kur_ctx *ctx);
  *   "graph"       1 (default): kur_step_rk4 captures one sampling period (r_every steps, else
  *                 "graph_steps" steps) into a HIP graph and replays it; 0: plain launches.
  *   "graph_steps" steps per replayed graph when no order parameter is sampled (default 16).
+ *   "persistent"  1 (default): kur_step_rk4 on a complete graph (kur_set_graph_complete) of at
+ *                 most 1024 nodes, without checkpoints or "timing", runs the whole call in one
+ *                 workgroup that keeps the state in registers (Sec. 2: the classical model
+ *                 through its order parameter), one launch instead of four per step; 0: the
+ *                 row kernel as for any graph. Equal results up to the order of the sums.
  *   "ens_tau"     shared-graph ensembles: blocks (and off-diagonal blocks, see below) at least
  *                 this dense form their products on the matrix cores (0..2, above 1: none).
  *                 Default 0.5. Takes effect at the next kur_ens_set_graph_csr.

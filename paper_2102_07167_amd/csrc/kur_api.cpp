@@ -73,6 +73,8 @@ struct kur_ctx {
     DevBuf d_r, d_psi;
     int cur = 0;
     bool sc_valid = false;
+    bool complete_graph = false;  // the installed graph came from kur_set_graph_complete
+    int persistent = 1;           // complete graphs of at most 1024 nodes: one-workgroup RK4 runs
     bool has_params = false, has_phases = false;
     double K = 0.0;
 
@@ -418,6 +420,7 @@ kur_status upload_instances(kur_ctx *c)
 
 kur_status install_graph(kur_ctx *c, BlockGraph &g)
 {
+    c->complete_graph = false;  // set again by kur_set_graph_complete after a successful install
     const size_t lds = rows_lds_bytes(c->esz, g.W, g.tile_rows, c->threads);
     if (lds > 156 * 1024) return fail(c, KUR_EINVAL, "chunk/tile_rows/threads exceed the LDS of a workgroup");
     if (g.tiles.size() > (size_t)INT32_MAX) return fail(c, KUR_EINVAL, "too many tiles");
@@ -570,6 +573,31 @@ kur_status install_transpose(kur_ctx *c, int64_t n, const int64_t *row_ptr, cons
     return KUR_OK;
 }
 
+// The whole run of a small complete graph in one workgroup (k_persist_complete); leaves the
+// (sin, cos) of the state to be rebuilt by the next call that needs them.
+template <typename T>
+hipError_t run_persistent(kur_ctx *c, double dt, int64_t nsteps, int64_t r_every)
+{
+    PersistArgs<T> a;
+    a.n = c->n;
+    a.nsteps = nsteps;
+    a.r_every = r_every;
+    a.compensate = c->compensate;
+    a.dt = (T)dt;
+    a.half_dt = (T)(0.5 * dt);
+    a.dt6 = (T)(dt / 6.0);
+    a.K = (T)c->K;
+    a.inv_n = (T)(1.0 / (double)c->n);
+    a.unit = (const T *)c->d_unit.p;
+    a.omega = (const T *)c->d_omega.p;
+    a.hi = (T *)c->d_hi.p;
+    a.lo = (T *)c->d_lo.p;
+    a.wind = (int32_t *)c->d_wind.p;
+    a.r_out = (double *)c->d_r.p;
+    a.psi_out = (double *)c->d_psi.p;
+    return launch_persist_complete<T>(a, c->stream);
+}
+
 }  // namespace
 
 extern "C" {
@@ -703,6 +731,9 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
     } else if (k == "graph") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "graph must be 0 or 1");
         c->use_graph = (int)v;
+    } else if (k == "persistent") {
+        if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "persistent must be 0 or 1");
+        c->persistent = (int)v;
     } else if (k == "ens_tau") {
         if (v < 0.0 || v > 2.0) return fail(c, KUR_EINVAL, "ens_tau must be in [0, 2] (above 1: no block on the matrix cores)");
         c->ens_tau = v;
@@ -1143,6 +1174,15 @@ static kur_status run_steps(kur_ctx *c, double dt, int64_t nsteps, int64_t r_eve
         if ((e = dalloc(c->d_r, sizeof(double) * nsamp * c->n_inst)) != hipSuccess ||
             (e = dalloc(c->d_psi, sizeof(double) * nsamp * c->n_inst)) != hipSuccess)
             return hip_fail(c, e, "r buffer");
+    }
+    // a small complete graph without checkpoints or kernel timing: one launch for the whole run
+    if (c->complete_graph && c->persistent && !c->batch && c->ckpt_every == 0 && !c->timing &&
+        c->n <= (int64_t)kPersistThreads * kPersistMaxRows) {
+        if (nsteps == 0 && r_every == 0) return KUR_OK;
+        e = c->esz == 4 ? run_persistent<float>(c, dt, nsteps, r_every) : run_persistent<double>(c, dt, nsteps, r_every);
+        if (e != hipSuccess) return hip_fail(c, e, "persistent rk4 launch");
+        c->sc_valid = false;
+        return KUR_OK;
     }
     if (!c->sc_valid) {
         kur_status s = sc_init(c, c->d_hi.p, c->d_sc[c->cur], c->d_part[c->cur]);
@@ -1865,7 +1905,9 @@ extern "C" kur_status kur_set_graph_complete(kur_ctx *c, int64_t n)
         return fail(c, KUR_ENOMEM, "host allocation failed in graph preprocessing");
     }
     if (!msg.empty()) return fail(c, KUR_EINVAL, msg);
-    return install_graph(c, g);
+    kur_status s = install_graph(c, g);
+    if (s == KUR_OK) c->complete_graph = true;
+    return s;
 }
 
 extern "C" kur_status kur_batch_begin(kur_ctx *c)

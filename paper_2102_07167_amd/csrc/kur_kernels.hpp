@@ -116,6 +116,30 @@ template <typename T>
 hipError_t launch_phase_out(int64_t n, const void *hi, const void *lo, const int32_t *wind, int unwrapped, void *out,
                             hipStream_t st);
 
+// nsteps classical RK4 steps of the complete graph (Sec. 2, the classical model through its order
+// parameter) in one workgroup that keeps every oscillator's state in registers: per stage a
+// fixed-order block sum of (sin y, cos y), then the right-hand side and the stage bookkeeping of
+// every row. r and psi are written for steps 0, r_every, 2 r_every, ... (r_every > 0): the
+// kernel stores the mean (sin, cos) of each sample there and a one-workgroup pass converts them.
+constexpr int kPersistThreads = 512;
+constexpr int kPersistMaxRows = 2;  // rows per thread: n <= 1024
+template <typename T>
+struct PersistArgs {
+    int64_t n;
+    int64_t nsteps;
+    int64_t r_every;
+    int compensate;
+    T dt, half_dt, dt6;
+    T K, inv_n;
+    const T *unit;
+    const T *omega;
+    T *hi, *lo;
+    int32_t *wind;
+    double *r_out, *psi_out;
+};
+template <typename T>
+hipError_t launch_persist_complete(const PersistArgs<T> &a, hipStream_t st);
+
 template <typename T>
 hipError_t launch_vjp(const DevGraph &g, int ntiles, const VjpArgs<T> &a, int threads, hipStream_t st);
 template <typename T>

@@ -338,3 +338,65 @@ def test_paper_four_communities(need_gpu):
     assert np.isfinite(r).all() and np.isfinite(thT).all()
     T = w.steps * w.dt
     assert abs(np.mean(thT - w.theta0 - T * w.omega)) < 1e-9
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1, 2, 97, 512, 1000, 1024, 1025])
+def test_complete_graph_one_workgroup_run(need_gpu, dtype, n):
+    """Complete graphs of at most 1024 nodes run kur_step_rk4 in one workgroup (option
+    persistent, default 1); 1025 nodes take the row kernel. Against the row kernel (persistent = 0)
+    and the oracle: phases and r samples (including step 0 and a last step that is not a multiple
+    of r_every) at 1e-12 (FP64) or 1e-5 (FP32), both scalings; the order parameter and the
+    right-hand side afterwards come from the updated state."""
+    rng = np.random.default_rng(n)
+    om = rng.standard_normal(n)
+    th0 = rng.uniform(0, 2 * np.pi, n)
+    K, dt, steps, r_every = 2.5, 0.01, 203, 10
+    if dtype == "f32":
+        om, th0, K, dt = f32(om), f32(th0), float(np.float32(K)), float(np.float32(dt))
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    g = gen.complete_graph(n)
+    for scaling in (0, 1):
+        out = {}
+        for pers in (1, 0):
+            with Kuramoto(dtype, device=0) as k:
+                k.set_option("persistent", pers)
+                k.set_option("scaling", scaling)
+                k.set_graph(g)
+                k.set_params(om, K)
+                k.set_phases(th0)
+                r, psi = k.step_rk4(dt, steps, r_every)
+                r2, _ = k.step_rk4(dt, 7, 7)  # a second call continues from the updated state
+                th = k.get_phases(wrapped=False)
+                rn, _ = k.order_parameter()
+                F = k.eval_rhs()
+                out[pers] = (r, psi, r2, th, rn, F)
+        a, b = out[1], out[0]
+        assert a[0].shape == (steps // r_every + 1,)
+        assert np.abs(a[0] - b[0]).max() < tol and np.abs(a[2] - b[2]).max() < tol
+        live = a[0] > 1e-3  # psi is defined where r is not 0
+        if live.any():
+            assert np.abs(wrap(a[1] - b[1])[live]).max() < (1e-9 if dtype == "f64" else 1e-3)
+        assert np.abs(a[3] - b[3]).max() <= tol * max(1.0, np.abs(b[3]).max())
+        assert abs(a[4] - a[2][-1]) < tol
+        assert np.abs(a[5] - b[5]).max() <= tol * max(1.0, np.abs(b[5]).max())
+        if n <= 512:  # the oracle's complete graph costs n^2 per evaluation
+            tho, ro, _ = oracle.rk4(g, om, K, th0, dt, steps + 7, r_every=1, scaling=scaling)
+            assert np.abs(wrap(a[3] - tho)).max() < (tol * max(1.0, np.abs(tho).max()) if dtype == "f64" else 1e-5)
+            assert np.abs(a[0] - ro[:steps + 1:r_every]).max() < tol
+
+
+def test_complete_graph_one_workgroup_zero_steps(need_gpu):
+    """nsteps = 0 with sampling: one sample, of the initial phases; nothing else changes."""
+    rng = np.random.default_rng(3)
+    n = 300
+    th0 = rng.uniform(0, 2 * np.pi, n)
+    with Kuramoto("f64", device=0) as k:
+        k.set_graph(gen.complete_graph(n))
+        k.set_params(rng.standard_normal(n), 1.0)
+        k.set_phases(th0)
+        r, psi = k.step_rk4(0.01, 0, 5)
+        th = k.get_phases(wrapped=False)
+    ro, po = oracle.order_parameter(th0)
+    assert r.shape == (1,) and abs(r[0] - ro) < 1e-14 and abs(psi[0] - po) < 1e-12
+    assert np.abs(th - th0).max() < 1e-15 * 2 * np.pi
