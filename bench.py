@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RK4 steps/s and RHS evals/s at N=2^20 (fraction of HBM roofline); adjoint/fwd ratio"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2102_07167_amd", "csrc", "kur_kernels.hip")
+# the device code of the row kernel: its source file and the device helpers it includes
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2102_07167_amd", "csrc", f) for f in ("kur_kernels.hip", "kur_device.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rows_kernel_traffic.json")
 TUNE_CACHE = os.path.join(ROOT, "paper_2102_07167_amd", "tuned_layouts.tsv")
 
@@ -37,8 +38,11 @@ def log(msg):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def layout_of(info: dict) -> dict:

@@ -573,14 +573,14 @@ kur_status install_transpose(kur_ctx *c, int64_t n, const int64_t *row_ptr, cons
     return KUR_OK;
 }
 
-// The whole run of a small complete graph in one workgroup (k_persist_complete); leaves the
-// (sin, cos) of the state to be rebuilt by the next call that needs them.
+// The run of a small complete graph in one workgroup (k_persist_complete), in launches of at
+// most about 65536 steps (whole sampling periods) so that no launch holds the device for long;
+// leaves the (sin, cos) of the state to be rebuilt by the next call that needs them.
 template <typename T>
 hipError_t run_persistent(kur_ctx *c, double dt, int64_t nsteps, int64_t r_every)
 {
     PersistArgs<T> a;
     a.n = c->n;
-    a.nsteps = nsteps;
     a.r_every = r_every;
     a.compensate = c->compensate;
     a.dt = (T)dt;
@@ -593,9 +593,18 @@ hipError_t run_persistent(kur_ctx *c, double dt, int64_t nsteps, int64_t r_every
     a.hi = (T *)c->d_hi.p;
     a.lo = (T *)c->d_lo.p;
     a.wind = (int32_t *)c->d_wind.p;
-    a.r_out = (double *)c->d_r.p;
-    a.psi_out = (double *)c->d_psi.p;
-    return launch_persist_complete<T>(a, c->stream);
+    const int64_t chunk = r_every > 0 ? std::max<int64_t>(1, 65536 / r_every) * r_every : 65536;
+    int64_t done = 0;
+    do {
+        a.nsteps = std::min(chunk, nsteps - done);
+        a.final_sample = done + a.nsteps == nsteps;  // else the next launch's step 0 is that sample
+        a.r_out = (double *)c->d_r.p + (r_every > 0 ? done / r_every : 0);
+        a.psi_out = (double *)c->d_psi.p + (r_every > 0 ? done / r_every : 0);
+        const hipError_t e = launch_persist_complete<T>(a, c->stream);
+        if (e != hipSuccess) return e;
+        done += a.nsteps;
+    } while (done < nsteps);
+    return hipSuccess;
 }
 
 }  // namespace

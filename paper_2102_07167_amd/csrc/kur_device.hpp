@@ -1,6 +1,6 @@
 // kur_device.hpp -- device helpers shared by the kernel files: (sin, cos), rounding, the two-part
-// split of 2 pi used to wrap phases, the error-free sum, and the per-oscillator bookkeeping of
-// one classical RK4 stage.
+// split of 2 pi used to wrap phases, the error-free sum, the per-oscillator bookkeeping of one
+// classical RK4 stage, and wave-level sums.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -108,6 +108,68 @@ __device__ __forceinline__ T rk4_stage(int stage, T k, T dt, T half_dt, T dt6, i
     if (stage == 5) return th + half_dt * k;
     const T delta = stage == 6 ? dt * k : dt6 * (*ksum + k);
     return phase_advance<T>(th, *lo_p, *wind_p, delta, compensate, hi_p, lo_p, wind_p);
+}
+
+// Wave-level sums. wave_sum leaves the sum in every lane (butterfly of shuffles); the DPP forms
+// use VALU cross-lane moves only, in a fixed order.
+template <typename T> __device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Cross-lane moves with DPP (VALU only, no LDS traffic). Rows are the 16-lane DPP rows of a
+// wave64; lanes of disabled rows receive 0.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp_mov(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_mov(double x)
+{
+    const int2 v = __builtin_bit_cast(int2, x);
+    int2 o;
+    o.x = __builtin_amdgcn_update_dpp(0, v.x, CTRL, ROWS, 0xf, false);
+    o.y = __builtin_amdgcn_update_dpp(0, v.y, CTRL, ROWS, 0xf, false);
+    return __builtin_bit_cast(double, o);
+}
+
+enum : int {
+    DPP_XOR1 = 0xB1,        // quad_perm [1,0,3,2]
+    DPP_XOR2 = 0x4E,        // quad_perm [2,3,0,1]
+    DPP_HALF_MIRROR = 0x141,
+    DPP_MIRROR = 0x140,
+    DPP_BCAST15 = 0x142,
+    DPP_BCAST31 = 0x143,
+};
+
+// Sum over aligned groups of G lanes (G a power of two, 2..64) in a fixed order; the result is
+// valid in the last lane of every group (for G <= 16 in every lane of the group).
+template <typename T>
+__device__ __forceinline__ T group_sum_dpp(T v, int G)
+{
+    v += dpp_mov<DPP_XOR1>(v);
+    if (G >= 4) v += dpp_mov<DPP_XOR2>(v);
+    if (G >= 8) v += dpp_mov<DPP_HALF_MIRROR>(v);
+    if (G >= 16) v += dpp_mov<DPP_MIRROR>(v);
+    if (G >= 32) v += dpp_mov<DPP_BCAST15, 0xa>(v);
+    if (G >= 64) v += dpp_mov<DPP_BCAST31, 0xc>(v);
+    return v;
+}
+
+// Sum over the whole wave; valid in lane 63.
+template <typename T>
+__device__ __forceinline__ T wave_sum_dpp(T v)
+{
+    v += dpp_mov<DPP_XOR1>(v);
+    v += dpp_mov<DPP_XOR2>(v);
+    v += dpp_mov<DPP_HALF_MIRROR>(v);
+    v += dpp_mov<DPP_MIRROR>(v);
+    v += dpp_mov<DPP_BCAST15, 0xa>(v);
+    v += dpp_mov<DPP_BCAST31, 0xc>(v);
+    return v;
 }
 
 }  // namespace kur

@@ -28,65 +28,6 @@ namespace kur {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-template <typename T> __device__ __forceinline__ T wave_sum(T v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Cross-lane moves with DPP (VALU only, no LDS traffic). Rows are the 16-lane DPP rows of a
-// wave64; lanes of disabled rows receive 0.
-template <int CTRL, int ROWS = 0xf>
-__device__ __forceinline__ float dpp_mov(float x)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROWS, 0xf, false));
-}
-template <int CTRL, int ROWS = 0xf>
-__device__ __forceinline__ double dpp_mov(double x)
-{
-    const int2 v = __builtin_bit_cast(int2, x);
-    int2 o;
-    o.x = __builtin_amdgcn_update_dpp(0, v.x, CTRL, ROWS, 0xf, false);
-    o.y = __builtin_amdgcn_update_dpp(0, v.y, CTRL, ROWS, 0xf, false);
-    return __builtin_bit_cast(double, o);
-}
-
-enum : int {
-    DPP_XOR1 = 0xB1,        // quad_perm [1,0,3,2]
-    DPP_XOR2 = 0x4E,        // quad_perm [2,3,0,1]
-    DPP_HALF_MIRROR = 0x141,
-    DPP_MIRROR = 0x140,
-    DPP_BCAST15 = 0x142,
-    DPP_BCAST31 = 0x143,
-};
-
-// Sum over aligned groups of G lanes (G a power of two, 2..64) in a fixed order; the result is
-// valid in the last lane of every group (for G <= 16 in every lane of the group).
-template <typename T>
-__device__ __forceinline__ T group_sum_dpp(T v, int G)
-{
-    v += dpp_mov<DPP_XOR1>(v);
-    if (G >= 4) v += dpp_mov<DPP_XOR2>(v);
-    if (G >= 8) v += dpp_mov<DPP_HALF_MIRROR>(v);
-    if (G >= 16) v += dpp_mov<DPP_MIRROR>(v);
-    if (G >= 32) v += dpp_mov<DPP_BCAST15, 0xa>(v);
-    if (G >= 64) v += dpp_mov<DPP_BCAST31, 0xc>(v);
-    return v;
-}
-
-// Sum over the whole wave; valid in lane 63.
-template <typename T>
-__device__ __forceinline__ T wave_sum_dpp(T v)
-{
-    v += dpp_mov<DPP_XOR1>(v);
-    v += dpp_mov<DPP_XOR2>(v);
-    v += dpp_mov<DPP_HALF_MIRROR>(v);
-    v += dpp_mov<DPP_MIRROR>(v);
-    v += dpp_mov<DPP_BCAST15, 0xa>(v);
-    v += dpp_mov<DPP_BCAST31, 0xc>(v);
-    return v;
-}
 
 // Sum v over the workgroup in a fixed order and store it to *out (thread 0).
 template <typename VT, int NT>
@@ -719,111 +660,6 @@ __global__ __launch_bounds__(256) void k_order(const typename V2<T>::type *__res
     }
 }
 
-// Classical RK4 on the complete graph in one workgroup (see PersistArgs). Thread t owns rows
-// t + 1024 j, j < kPersistMaxRows, and keeps their phase, compensation term, winding count, RK4
-// accumulator and the (sin, cos) of the current stage input in registers for the whole run. The
-// right-hand side of row m is omega_m + scale_m (S cos y_m - C sin y_m) with (S, C) the sums of
-// (sin y, cos y) over all rows: the row's own term cancels, so this is the coupling to every
-// other node (Sec. 2, eq. KuramotoReformulation). Each stage folds the waves' sums in wave order
-// (every thread reads the same LDS slots), so all threads hold identical (S, C); the slots
-// alternate between stages, so one barrier per stage orders the writes and reads.
-template <typename T>
-__global__ __launch_bounds__(kPersistThreads) void k_persist_complete(PersistArgs<T> a)
-{
-    constexpr int NW = kPersistThreads / 64, R = kPersistMaxRows;
-    __shared__ T red_s[2][NW], red_c[2][NW];
-    __shared__ double rd_s[2][NW], rd_c[2][NW];
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int64_t n = a.n;
-    T th[R], lo[R], ks[R], om[R], scl[R], sn[R], cs[R];
-    int32_t wd[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int64_t m = tid + (int64_t)kPersistThreads * j;
-        const bool ok = m < n;
-        th[j] = ok ? a.hi[m] : T(0);
-        lo[j] = ok ? a.lo[m] : T(0);
-        wd[j] = ok ? a.wind[m] : 0;
-        om[j] = ok ? a.omega[m] : T(0);
-        scl[j] = ok ? a.K * (a.unit ? a.unit[m] : a.inv_n) : T(0);
-        ks[j] = T(0);
-        dev_sincos<T>(th[j], &sn[j], &cs[j]);
-        if (!ok) sn[j] = cs[j] = T(0);  // padding rows add nothing to the sums
-    }
-    int buf = 0;
-    for (int64_t step = 0; step <= a.nsteps; ++step) {
-        const bool sample = a.r_every > 0 && step % a.r_every == 0;
-        if (step == a.nsteps && !sample) break;
-        for (int stage = 1; stage <= 4; ++stage) {
-            T ps = T(0), pc = T(0);
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                ps += sn[j];
-                pc += cs[j];
-            }
-            ps = wave_sum_dpp(ps);
-            pc = wave_sum_dpp(pc);
-            const bool smp = stage == 1 && sample;
-            if (lane == 63) {
-                red_s[buf][w] = ps;
-                red_c[buf][w] = pc;
-            }
-            if (smp) {
-                // the order parameter of the phases at this step, summed in FP64
-                double ds = 0.0, dc = 0.0;
-#pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    ds += (double)sn[j];
-                    dc += (double)cs[j];
-                }
-                ds = wave_sum_dpp(ds);
-                dc = wave_sum_dpp(dc);
-                if (lane == 63) {
-                    rd_s[buf][w] = ds;
-                    rd_c[buf][w] = dc;
-                }
-            }
-            __syncthreads();
-            T S = red_s[buf][0], C = red_c[buf][0];
-#pragma unroll
-            for (int i = 1; i < NW; ++i) {
-                S += red_s[buf][i];
-                C += red_c[buf][i];
-            }
-            if (smp && tid == 0) {
-                // the mean (sin, cos); k_persist_samples turns it into (r, psi)
-                double DS = rd_s[buf][0], DC = rd_c[buf][0];
-                for (int i = 1; i < NW; ++i) {
-                    DS += rd_s[buf][i];
-                    DC += rd_c[buf][i];
-                }
-                const double inv = 1.0 / (double)n;
-                const int64_t k = step / a.r_every;
-                a.r_out[k] = DS * inv;
-                a.psi_out[k] = DC * inv;
-            }
-            buf ^= 1;
-            if (step == a.nsteps) break;  // the last sample only
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const T k = om[j] + scl[j] * (S * cs[j] - C * sn[j]);
-                const T y = rk4_stage<T>(stage, k, a.dt, a.half_dt, a.dt6, a.compensate, &ks[j], &th[j], &lo[j], &wd[j]);
-                dev_sincos<T>(y, &sn[j], &cs[j]);
-                if (tid + (int64_t)kPersistThreads * j >= n) sn[j] = cs[j] = T(0);
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int64_t m = tid + (int64_t)kPersistThreads * j;
-        if (m < n) {
-            a.hi[m] = th[j];
-            a.lo[m] = lo[j];
-            a.wind[m] = wd[j];
-        }
-    }
-}
-
 // Streaming read of n 16-byte words (a bandwidth reference for the roofline): every lane
 // reads a grid-strided sequence with non-temporal loads and folds it into one word.
 __global__ __launch_bounds__(512) void k_stream_read(const u32x4 *__restrict__ p, int64_t n, uint32_t *__restrict__ out)
@@ -1071,28 +907,6 @@ template hipError_t launch_sc_init<float>(const DevGraph &, int, const float *, 
 template hipError_t launch_sc_init<double>(const DevGraph &, int, const double *, void *, void *, int, hipStream_t);
 template hipError_t launch_rows<float>(const DevGraph &, int, const RowArgs<float> &, int, hipStream_t);
 template hipError_t launch_rows<double>(const DevGraph &, int, const RowArgs<double> &, int, hipStream_t);
-// (mean sin, mean cos) of every sample -> (r, psi), in place
-__global__ __launch_bounds__(256) void k_persist_samples(int64_t count, double *__restrict__ r, double *__restrict__ psi)
-{
-    for (int64_t k = threadIdx.x; k < count; k += 256) {
-        const double s = r[k], c = psi[k];
-        r[k] = sqrt(s * s + c * c);
-        psi[k] = atan2(s, c);
-    }
-}
-
-template <typename T>
-hipError_t launch_persist_complete(const PersistArgs<T> &a, hipStream_t st)
-{
-    if (a.n < 1 || a.n > (int64_t)kPersistThreads * kPersistMaxRows) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_persist_complete<T>), dim3(1), dim3(kPersistThreads), 0, st, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || a.r_every <= 0) return e;
-    hipLaunchKernelGGL(k_persist_samples, dim3(1), dim3(256), 0, st, a.nsteps / a.r_every + 1, a.r_out, a.psi_out);
-    return hipGetLastError();
-}
-template hipError_t launch_persist_complete<float>(const PersistArgs<float> &, hipStream_t);
-template hipError_t launch_persist_complete<double>(const PersistArgs<double> &, hipStream_t);
 
 template hipError_t launch_vjp<float>(const DevGraph &, int, const VjpArgs<float> &, int, hipStream_t);
 template hipError_t launch_vjp<double>(const DevGraph &, int, const VjpArgs<double> &, int, hipStream_t);

@@ -119,8 +119,9 @@ hipError_t launch_phase_out(int64_t n, const void *hi, const void *lo, const int
 // nsteps classical RK4 steps of the complete graph (Sec. 2, the classical model through its order
 // parameter) in one workgroup that keeps every oscillator's state in registers: per stage a
 // fixed-order block sum of (sin y, cos y), then the right-hand side and the stage bookkeeping of
-// every row. r and psi are written for steps 0, r_every, 2 r_every, ... (r_every > 0): the
-// kernel stores the mean (sin, cos) of each sample there and a one-workgroup pass converts them.
+// every row. r and psi are written for steps 0, r_every, 2 r_every, ... below nsteps, and for
+// nsteps itself when final_sample (r_every > 0): the kernel stores the mean (sin, cos) of each
+// sample there and a one-workgroup pass converts them.
 constexpr int kPersistThreads = 512;
 constexpr int kPersistMaxRows = 2;  // rows per thread: n <= 1024
 template <typename T>
@@ -128,6 +129,7 @@ struct PersistArgs {
     int64_t n;
     int64_t nsteps;
     int64_t r_every;
+    int final_sample;
     int compensate;
     T dt, half_dt, dt6;
     T K, inv_n;

@@ -400,3 +400,27 @@ def test_complete_graph_one_workgroup_zero_steps(need_gpu):
     ro, po = oracle.order_parameter(th0)
     assert r.shape == (1,) and abs(r[0] - ro) < 1e-14 and abs(psi[0] - po) < 1e-12
     assert np.abs(th - th0).max() < 1e-15 * 2 * np.pi
+
+
+@pytest.mark.parametrize("r_every", [0, 1000, 7])
+def test_complete_graph_one_workgroup_long_run(need_gpu, r_every):
+    """A call longer than one launch of the one-workgroup run (launches of whole sampling
+    periods, at most about 65536 steps): 70001 steps give the same phases and r samples as the
+    row kernel, with every sample present exactly once."""
+    rng = np.random.default_rng(5)
+    n, K, dt, steps = 64, 5.0, 0.002, 70001  # synchronised regime: differences in rounding contract
+    om = rng.standard_normal(n)
+    th0 = rng.uniform(0, 2 * np.pi, n)
+    out = {}
+    for pers in (1, 0):
+        with Kuramoto("f64", device=0) as k:
+            k.set_option("persistent", pers)
+            k.set_graph(gen.complete_graph(n))
+            k.set_params(om, K)
+            k.set_phases(th0)
+            r, psi = k.step_rk4(dt, steps, r_every)
+            out[pers] = (r, k.get_phases(wrapped=False))
+    if r_every:
+        assert out[1][0].shape == (steps // r_every + 1,)
+        assert np.abs(out[1][0] - out[0][0]).max() < 1e-10
+    assert np.abs(out[1][1] - out[0][1]).max() < 1e-9 * max(1.0, np.abs(out[0][1]).max())

@@ -14,7 +14,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
 @pytest.mark.skipif(not shutil.which(HIPCC) and not os.path.exists(HIPCC), reason="hipcc not found")
-@pytest.mark.parametrize("src", ["kur_kernels.hip", "ens_kernels.hip"])
+@pytest.mark.parametrize("src", ["kur_kernels.hip", "ens_kernels.hip", "persist_kernels.hip"])
 def test_no_kernel_uses_scratch(src, tmp_path):
     cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
            "-packed-fp32-ops", "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", str(tmp_path / "k.o"),
