@@ -10,7 +10,7 @@
 namespace kur {
 
 // Classical RK4 on the complete graph in one workgroup (see PersistArgs). Thread t owns rows
-// t + 1024 j, j < kPersistMaxRows, and keeps their phase, compensation term, winding count, RK4
+// t + kPersistThreads j, j < kPersistMaxRows, and keeps their phase, compensation term, winding count, RK4
 // accumulator and the (sin, cos) of the current stage input in registers for the whole run. The
 // right-hand side of row m is omega_m + scale_m (S cos y_m - C sin y_m) with (S, C) the sums of
 // (sin y, cos y) over all rows: the row's own term cancels, so this is the coupling to every
