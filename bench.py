@@ -11,6 +11,11 @@ omega ~ Cauchy(0, 0.5), K = 3, dt = 0.005, FP32 (seeded synthetic input).
 
 Prints one JSON line with the throughput, the roofline of the dominant kernel (the row kernel,
 timed live with HIP events on its own stream) and the CPU oracle timed on a bounded sample.
+
+Other workloads (--workload): sbm (64 x 1024 SBM), a2a (N = 512 all-to-all, FP64), pairs (the
+paired SBM with dense off-diagonal blocks), paper (M = 4096 in four communities to T = 200, with
+the paper's timing as context), homo (a homogeneous N = 2^20 diagnostic), batch (256 independent
+instances) and ens (B replicas of one graph on the matrix cores, --dtype f32 or f64).
 """
 from __future__ import annotations
 
