@@ -185,6 +185,29 @@ def test_adjoint_sbm_64x1024_2000_steps_central_differences(need_gpu):
         assert abs(gk - fd) <= 1e-4 * max(abs(fd), 1e-2 * gmax) + noise, (gk, fd)
 
 
+def test_adjoint_sbm_64x1024_2000_steps_fp32(need_gpu):
+    """The same full-size adjoint in FP32 (central differences of an FP32 forward carry no
+    signal at this step): its gradients against the FP64 adjoint on the same FP32-rounded
+    inputs, within 1e-3 of the largest gradient (the FP32 bound of the smaller adjoint tests),
+    for theta0, omega and K, with the loss and its seed formed from each run's own phases."""
+    w = gen.sbm_equal(steps=2000, seed=1005)
+    r32 = lambda x: np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+    w.theta0, w.omega = r32(w.theta0), r32(w.omega)
+    w.K, w.dt = float(np.float32(w.K)), float(np.float32(w.dt))
+    grads = {}
+    for dtype in ("f64", "f32"):
+        with ctx(w, dtype) as k:
+            L, seed = _loss(k, w, w.theta0, w.omega, w.K, w.steps)
+            grads[dtype] = (L,) + tuple(k.adjoint_rk4(w.dt, w.steps, seed, theta0=w.theta0, ckpt_every=32))
+    L64, gt64, gw64, gk64 = grads["f64"]
+    L32, gt32, gw32, gk32 = grads["f32"]
+    assert abs(L32 - L64) <= 1e-4 * abs(L64)
+    assert np.isfinite(gt32).all() and np.isfinite(gw32).all() and np.isfinite(gk32)
+    assert np.abs(gt32 - gt64).max() <= 1e-3 * np.abs(gt64).max()
+    assert np.abs(gw32 - gw64).max() <= 1e-3 * np.abs(gw64).max()
+    assert abs(gk32 - gk64) <= 1e-3 * max(abs(gk64), 1e-3 * np.abs(gw64).max())
+
+
 @pytest.mark.parametrize("record_stages", [False, True])
 def test_autograd_function(need_gpu, record_stages):
     import torch
