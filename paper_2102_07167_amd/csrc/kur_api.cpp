@@ -1810,7 +1810,9 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
             v.part_in = nullptr;
             v.x_out = B.x[0].p;
             v.part_out = B.xpart[0].p;
-            r = launch_vjp_init<T>(gv, ntv, v, c->threads, st);
+            // the first step of the segment starts here; every later one was started by the
+            // stage-1 launch of the step before it (same arithmetic, one launch less per step)
+            if (k == len - 1) r = launch_vjp_init<T>(gv, ntv, v, c->threads, st);
             for (int i = 4; i >= 1 && r == hipSuccess; --i) {
                 v.stage = i;
                 // l_{i-1} = cl lam + cm mu_i: (dt/3, dt), (dt/3, dt/2), (dt/6, dt/2)
@@ -1818,7 +1820,7 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
                 v.cm = i == 4 ? tdt : (T)(0.5 * dt);
                 v.sc_cur = slot(4 * k + i - 1);
                 v.ac_rows = acslot(4 * k + i - 1);
-                v.sc_next = i > 1 ? slot(4 * k + i - 2) : nullptr;
+                v.sc_next = i > 1 ? slot(4 * k + i - 2) : k > 0 ? slot(4 * (k - 1) + 3) : nullptr;
                 v.x_in = B.x[xc].p;
                 v.part_in = B.xpart[xc].p;
                 v.x_out = B.x[xc ^ 1].p;

@@ -582,9 +582,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             vacc(part, xn);
         } else {
             a.lam[m] = la;
+            if (a.sc_next) {
+                // the start of the next reverse step, in the arithmetic of k_vjp_init (cl =
+                // dt/6): l_4 = cl lam, lam_acc = lam, x = (w s, w c) at that step's Y_4
+                const T l4 = a.cl * la;
+                a.lbuf[m] = l4;
+                a.lam_acc[m] = la;
+                const T w4 = a.K * unit * l4;
+                const T2 scn = reinterpret_cast<const T2 *>(a.sc_next)[m];
+                T2 xn;
+                xn.x = w4 * scn.x;
+                xn.y = w4 * scn.y;
+                reinterpret_cast<T2 *>(a.x_out)[m] = xn;
+                vacc(part, xn);
+            }
         }
     }
-    if (a.stage > 1) block_sum_store<T2, NT>(part, L.red, reinterpret_cast<T2 *>(a.part_out) + tile_id);
+    if (a.stage > 1 || a.sc_next) block_sum_store<T2, NT>(part, L.red, reinterpret_cast<T2 *>(a.part_out) + tile_id);
     // the tile's dK contribution, accumulated over all launches in a fixed order
     __shared__ double gks[NT / 64];
     gk = wave_sum(gk);

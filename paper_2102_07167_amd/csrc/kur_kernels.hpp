@@ -94,7 +94,8 @@ struct VjpArgs {
     void *x_out;        // the same for the next stage
     void *part_out;
     const void *sc_cur; // (sin, cos) at Y_i
-    const void *sc_next;// (sin, cos) of the next stage's state
+    const void *sc_next;// (sin, cos) of the next stage's state; at stage 1, if not null, the Y_4
+                        // of the next reverse step, whose start (k_vjp_init's work) is then done here
     T *lam;             // dL/dtheta at the end of the step; the start of the step after stage 1
     T *lam_acc;         // lam + sum of mu_i
     T *lbuf;            // l_i
