@@ -107,7 +107,8 @@ const char *kur_last_error(const kur_ctx *ctx);
  *   "scaling"     0: K/N (uniform, default); 1: K/deg_m (non-uniform). Immediate.
  *   "compensate"  1: compensated phase update with winding (default); 0: plain update. Immediate.
  *   "timing"      1: time every launch of the row kernel with HIP events (see kur_kernel_time).
- *                 Immediate; disables graph replay while on.
+ *                 Immediate; disables graph replay and the one-workgroup run ("persistent")
+ *                 while on.
  *   "checkpoint_every" C > 0: kur_step_rk4 keeps the phases every C steps for
  *                 kur_adjoint_rk4_recorded (and launches without graph replay); 0 (default) off.
  *                 Immediate.
@@ -119,10 +120,11 @@ const char *kur_last_error(const kur_ctx *ctx);
  *                 "graph_steps" steps) into a HIP graph and replays it; 0: plain launches.
  *   "graph_steps" steps per replayed graph when no order parameter is sampled (default 16).
  *   "persistent"  1 (default): kur_step_rk4 on a complete graph (kur_set_graph_complete) of at
- *                 most 1024 nodes, without checkpoints or "timing", runs the whole call in one
+ *                 most 1024 nodes, without checkpoints or "timing", runs the call in one
  *                 workgroup that keeps the state in registers (Sec. 2: the classical model
- *                 through its order parameter), one launch instead of four per step; 0: the
- *                 row kernel as for any graph. Equal results up to the order of the sums.
+ *                 through its order parameter): launches of whole sampling periods of at most
+ *                 about 65536 steps, instead of four launches per step; 0: the row kernel as
+ *                 for any graph. Equal results up to the order of the sums.
  *   "ens_tau"     shared-graph ensembles: blocks (and off-diagonal blocks, see below) at least
  *                 this dense form their products on the matrix cores (0..2, above 1: none).
  *                 Default 0.5. Takes effect at the next kur_ens_set_graph_csr.
