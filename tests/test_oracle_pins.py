@@ -322,6 +322,73 @@ def test_potential_gradient_and_decrease():
     assert np.all(np.diff(V) <= 1e-12)
 
 
+@pytest.mark.parametrize("M", [1, 2, 5, 64, 300])
+def test_potential_complete_graph_closed_form(M):
+    """Classical model (Sec. 2, eq. Potential): the pair sum of 1 - cos over all l, m equals
+    M^2 (1 - C^2 - S^2) with C, S the normalised order-parameter sums, so
+    V = -omega^T theta + (K M / 2)(1 - C_M^2 - S_M^2). C, S come from numpy's exact sums."""
+    rng = np.random.default_rng(40 + M)
+    omega, th = rng.standard_normal(M), rng.uniform(-7, 7, M)
+    K = 1.7
+    C = math.fsum(np.cos(th)) / M
+    S = math.fsum(np.sin(th)) / M
+    ref = -math.fsum(omega * th) + 0.5 * K * M * (1.0 - C * C - S * S)
+    got = oracle.potential(gen.complete_graph(M), omega, K, th)
+    scale = math.fsum(np.abs(omega * th)) + K * M
+    assert abs(got - ref) <= 1e-12 * scale, (got, ref)
+    # with omega = 0 the potential is (K M / 2)(1 - r^2) >= 0; 0 only at synchrony
+    r, _ = oracle.order_parameter(th)
+    got0 = oracle.potential(gen.complete_graph(M), np.zeros(M), K, th)
+    assert abs(got0 - 0.5 * K * M * (1.0 - r * r)) <= 1e-12 * K * M
+    # the splay state has r = 0, hence V = K M / 2 for omega = 0 (M >= 2)
+    if M >= 2:
+        sp = gen.splay_theta(M)
+        assert abs(oracle.potential(gen.complete_graph(M), np.zeros(M), K, sp) - 0.5 * K * M) <= 1e-12 * K * M
+
+
+def _potential_dense(A, omega, K, th, scale):
+    """-omega^T theta + K/2 (sum Ahat - cos^T Ahat cos - sin^T Ahat sin) with Ahat = diag(scale) A
+    (Sec. 3, eq. ExtendedPotentialConservation, second form), by numpy products."""
+    Ah = scale[:, None] * A.astype(np.float64)
+    c, s = np.cos(th), np.sin(th)
+    return -float(omega @ th) + 0.5 * K * (float(Ah.sum()) - float(c @ (Ah @ c)) - float(s @ (Ah @ s)))
+
+
+@pytest.mark.parametrize("kind", ["sbm", "weighted", "asym"])
+def test_potential_graph_closed_form_and_synchrony(kind):
+    """Graph potential (Sec. 3, eq. ExtendedPotentialConservation): the term-by-term form equals
+    the order-parameter form K/2 (sum Ahat - c^T Ahat c - s^T Ahat s) for symmetric, weighted and
+    asymmetric A, uniform and degree scaling (the potential's definition stays valid for
+    non-symmetric scaled matrices); and at equal phases with omega = 0 it is exactly 0, the
+    constant of integration fixed by synchrony (Sec. 2, indicator for synchronisation)."""
+    rng = np.random.default_rng(7)
+    if kind == "sbm":
+        g = gen.sbm_equal(n_comm=3, comm_size=40, rho_in=0.8, p_out=0.05, steps=1).graph
+    elif kind == "weighted":
+        g = gen.weighted_sbm([20, 30, 17], [3, 1, 2], 0.2, 4, 0.05, rng)
+    else:
+        g = gen.random_dense(45, 0.4, rng, symmetric=False)
+    A = g.dense()
+    n = g.n
+    omega, th = rng.standard_normal(n), rng.uniform(-5, 5, n)
+    K = 2.3
+    for scaling in (0, 1):
+        deg = A.sum(1).astype(np.float64)
+        scale = np.full(n, 1.0 / n) if scaling == 0 else np.where(deg > 0, 1.0 / np.maximum(deg, 1), 0.0)
+        ref = _potential_dense(A, omega, K, th, scale)
+        got = oracle.potential(g, omega, K, th, scaling=scaling)
+        bound = 1e-12 * (np.abs(omega * th).sum() + K * (np.abs(A) * scale[:, None]).sum())
+        assert abs(got - ref) <= bound, (kind, scaling, got, ref)
+        # synchrony: every 1 - cos(0) is exactly 0
+        for c0 in (0.0, 2.1, -40.0):
+            assert oracle.potential(g, np.zeros(n), K, np.full(n, c0), scaling=scaling) == 0.0
+    # a constant shift of all phases changes V only through -omega^T theta
+    d = 0.37
+    v0 = oracle.potential(g, omega, K, th)
+    v1 = oracle.potential(g, omega, K, th + d)
+    assert abs((v1 - v0) + d * omega.sum()) <= 1e-11 * (1 + abs(v0))
+
+
 def test_rhs_rows_subset_consistent():
     w = gen.sbm_equal(n_comm=4, comm_size=64, steps=10)
     F = oracle.rhs(w.graph, w.omega, w.K, w.theta0)
