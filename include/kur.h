@@ -112,6 +112,9 @@ const char *kur_last_error(const kur_ctx *ctx);
  *   "checkpoint_every" C > 0: kur_step_rk4 keeps the phases every C steps for
  *                 kur_adjoint_rk4_recorded (and launches without graph replay); 0 (default) off.
  *                 Immediate.
+ *   "adjoint_keep" 1 (default): the adjoint calls keep their work buffers (about
+ *                 (16 ckpt_every + 16) n reals) in the context for the next call; 0: release
+ *                 them now and after every adjoint call. Immediate.
  *   "record_stages" 1: such a recording run also keeps (sin, cos) and the row sums
  *                 (A sin, A cos) of every stage state, 16 n reals per step (KUR_ENOMEM if the
  *                 device cannot hold them), so that kur_adjoint_rk4_recorded recomputes nothing;
@@ -133,10 +136,13 @@ const char *kur_last_error(const kur_ctx *ctx);
 kur_status kur_set_option(kur_ctx *ctx, const char *key, double value);
 
 /*
- * Set the graph from a CSR adjacency in user order plus a community label per node; the
- * library does the host preprocessing: a stable counting sort of the nodes by label (the
- * permutation to block structure), the per-block dense/sparse choice at "tau", the list
- * build and the work decomposition.
+ * Set the graph from a CSR adjacency in user order plus a community label per node (the 0/1
+ * adjacency A of Sec. 3, eq. KuramotoGraph; the labels are the planted communities of Sec. 3,
+ * community detection in graphs); the library does the host preprocessing: a stable counting
+ * sort of the nodes by label (the permutation P A P^T to block structure), the per-block
+ * dense/sparse choice at "tau" (Sec. 3, eq. KuramotoGraphApproach: list of zeros or list of
+ * ones), the list build and the work decomposition. Synchronous; KUR_EINVAL on any
+ * inconsistency (nothing installed), KUR_ENOMEM if host or device memory runs out.
  *   n           number of oscillators (1 <= n < 2^31)
  *   row_ptr     n+1 offsets, row_ptr[0] = 0, non-decreasing
  *   col         row_ptr[n] column indices in [0, n); row m lists the l with A_ml = 1, in any
@@ -163,7 +169,11 @@ kur_status kur_set_graph_csr_w(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, 
                                const int32_t *weight, const int32_t *labels);
 
 /*
- * Set the graph already in block form (the expert path; no community search is done).
+ * Set the graph already in block form (the expert path; no community search is done): the
+ * regrouped adjacency of Sec. 3, eq. KuramotoGraphApproach, given block by block as the lists
+ * that equation evaluates (zeros of a dense diagonal block, ones of a sparse one, and the
+ * straightforwardly summed entries between blocks). Arrays are borrowed for the call and
+ * copied; KUR_EINVAL on any inconsistency listed below.
  *   n, nb        nodes and diagonal blocks; block b owns block-order rows
  *                [block_ptr[b], block_ptr[b+1]), block sizes 1..65535
  *   block_ptr    nb+1 offsets, block_ptr[0] = 0, strictly increasing, block_ptr[nb] = n
@@ -246,20 +256,33 @@ kur_status kur_get_block_groups(const kur_ctx *ctx, int32_t block, int32_t *blk,
 /* Number of dense off-diagonal blocks of the installed graph (ordered pairs of communities). */
 kur_status kur_graph_pairs(const kur_ctx *ctx, int64_t *n_pairs);
 
-/* Intrinsic frequencies omega (n, user order, finite) and coupling constant K (finite). */
+/* Intrinsic frequencies omega_m and coupling constant K of Sec. 3, eq. KuramotoGraph (Sec. 2,
+ * eq. Kuramoto for the complete graph): omega has n entries in user order, finite; K finite.
+ * Copied to the device (rounded to float in a KUR_F32 context). KUR_ESTATE before a graph is
+ * set; KUR_EINVAL (nothing changed) on a NULL or non-finite argument. */
 kur_status kur_set_params(kur_ctx *ctx, const double *omega, double K);
 
-/* Phases theta (n, user order, finite, any real value; stored wrapped plus a winding count). */
+/* Phases theta_m (n, user order, finite, |theta| <= 1e9, any real value) of the state of
+ * Sec. 3, eq. KuramotoGraph, phases on the circle S^1 (Sec. 2): stored as a wrapped value in
+ * [-pi, pi] plus a compensation term and an int32 winding count, so that kur_get_phases can
+ * return the unwrapped trajectory. KUR_ESTATE before a graph; KUR_EINVAL (nothing changed) on a
+ * NULL or out-of-range argument. */
 kur_status kur_set_phases(kur_ctx *ctx, const double *theta);
 
 /*
- * Evaluate the right-hand side F(theta) (n, user order) at theta (n, user order; NULL = the
- * current phases). Synchronous.
+ * Evaluate the right-hand side F_m(theta) = omega_m + K/Mscale_m sum_l A_ml sin(theta_l -
+ * theta_m) of Sec. 3, eq. KuramotoGraph, by the block method of eq. KuramotoGraphApproach
+ * (localised order parameters minus zeros for dense blocks, straightforward sums elsewhere), at
+ * theta (n, user order, finite; NULL = the current phases), into dtheta (n, user order).
+ * Synchronous. KUR_ESTATE without graph, omega/K or (theta NULL) phases; KUR_EINVAL on NULL
+ * dtheta or non-finite theta.
  */
 kur_status kur_eval_rhs(kur_ctx *ctx, const double *theta, double *dtheta);
 
 /*
- * Advance the current phases by nsteps classical RK4 steps of size dt (finite, nonzero).
+ * Advance the current phases by nsteps classical RK4 steps of size dt (finite, nonzero) of
+ * the system of Sec. 3, eq. KuramotoGraph (the explicit fourth-order Runge-Kutta method of Sec. 2,
+ * numerical integration, here with a fixed step): y_{n+1} = y_n + dt/6 (k1 + 2 k2 + 2 k3 + k4).
  * If r_every > 0 the order parameter is sampled at steps 0, r_every, 2 r_every, ...,
  * floor(nsteps/r_every) r_every, i.e. nsteps/r_every + 1 values, written to r_out and psi_out
  * (either may be NULL). With r_out == psi_out == NULL the call only enqueues work.
@@ -268,11 +291,14 @@ kur_status kur_eval_rhs(kur_ctx *ctx, const double *theta, double *dtheta);
 kur_status kur_step_rk4(kur_ctx *ctx, double dt, int64_t nsteps, int64_t r_every, double *r_out,
                         double *psi_out);
 
-/* Current phases (n, user order): wrapped != 0 gives values in [-pi, pi), wrapped == 0 the
- * unwrapped phases (wrapped value plus 2 pi times the winding count). Synchronous. */
+/* Current phases theta_m (n, user order; Sec. 3, eq. KuramotoGraph): wrapped != 0 gives values
+ * in [-pi, pi), wrapped == 0 the unwrapped phases (wrapped value plus 2 pi times the winding
+ * count). Synchronous. KUR_ESTATE without phases; KUR_EINVAL on NULL theta. */
 kur_status kur_get_phases(kur_ctx *ctx, double *theta, int wrapped);
 
-/* Order parameter r and angle psi of the current phases. Synchronous. */
+/* Order parameter r e^{i psi} = (1/N) sum_m e^{i theta_m} of the current phases (Sec. 2, eq.
+ * OrderParameter): r in [0, 1], psi = atan2 of the mean sine and cosine. Synchronous.
+ * KUR_ESTATE without phases; KUR_EINVAL on NULL r or psi. */
 kur_status kur_order_parameter(kur_ctx *ctx, double *r, double *psi);
 
 /*
@@ -298,7 +324,9 @@ kur_status kur_set_state(kur_ctx *ctx, const void *blob, size_t bytes);
  * one needs the layout of A^T, built by kur_set_graph_csr / kur_set_graph_csr_w when the option
  * "transpose" is 1 (KUR_EINVAL otherwise). The recompute of a segment keeps (sin, cos) and the
  * row sums (A sin, A cos) of every stage state. Uses device memory of about
- * (16 ckpt_every + 16) n reals plus 2 n reals per checkpoint. Synchronous.
+ * (16 ckpt_every + 16) n reals plus 2 n reals per checkpoint, kept for the next call unless
+ * the option "adjoint_keep" is 0. Synchronous. KUR_ENOMEM (with the failing allocation in
+ * kur_last_error) if the device cannot hold them.
  */
 kur_status kur_adjoint_rk4(kur_ctx *ctx, const double *theta0, double dt, int64_t nsteps, int64_t ckpt_every,
                            const double *dl_dthetaT, double *g_theta0, double *g_omega, double *g_K);
@@ -474,10 +502,53 @@ kur_status kur_ens_kernel_time(kur_ctx *ctx, double *out);
 kur_status kur_ens_autotune_csr(kur_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col,
                                 const int32_t *labels, int32_t B, int32_t effort, double *report);
 
-/* Device-pointer variants. Arrays are in BLOCK order and of the context dtype
- * (float or double); they enqueue on the context stream. */
+/*
+ * Device-pointer variants, for callers whose data already lives on the device (torch tensors:
+ * data_ptr()). Every array is a device array on the context's device, in USER order, of the
+ * context dtype (float for KUR_F32, double for KUR_F64), n entries unless stated. The calls
+ * enqueue on the context stream (kur_stream) and return without synchronising; the pointers
+ * are borrowed and must stay valid until that stream work completes, and the caller orders its
+ * own streams against the context stream. Device arrays are not read on the host, so their
+ * values are not validated: non-finite inputs propagate (a sampled order parameter then reports
+ * KUR_ENONFINITE). Host-side checks (NULL pointers, call order) return as for the host calls.
+ *
+ * kur_stream                    the hipStream_t the context enqueues on
+ * kur_set_params_dev            omega_dev (Sec. 3, eq. KuramotoGraph) and K (host value, finite),
+ *                               as kur_set_params
+ * kur_set_phases_dev            theta_dev, as kur_set_phases (the same split into wrapped value,
+ *                               compensation term and winding count, computed in FP64 on the
+ *                               device; |theta| must stay below 1e9)
+ * kur_eval_rhs_dev              F(theta) into dtheta_dev, as kur_eval_rhs (theta_dev NULL: the
+ *                               current phases)
+ * kur_get_phases_dev            the current phases into theta_dev, wrapped or unwrapped, as
+ *                               kur_get_phases
+ * kur_order_parameter_dev       rpsi_dev[0] = r, rpsi_dev[1] = psi of theta_dev (NULL: the current
+ *                               phases), Sec. 2 eq. OrderParameter, with FP64 sums in a fixed order
+ * kur_order_parameter_vjp_dev   the vector-Jacobian product of that map: with (r, psi) = rpsi_dev
+ *                               and (g_r, g_psi) = grad_dev, dtheta_dev[m] (accumulate = 1: +=)
+ *                               g_r sin(psi - theta_m) / N + g_psi cos(psi - theta_m) / (N r),
+ *                               the derivative of r = |(1/N) sum e^{i theta}| and of its angle;
+ *                               both terms are 0 when r = 0 (a loss on r(T) differentiates to
+ *                               dL/dtheta(T) on the device)
+ * kur_adjoint_rk4_dev           as kur_adjoint_rk4 with theta0_dev (NULL: the current phases),
+ *                               dl_dthetaT_dev and the gradients g_theta0_dev, g_omega_dev (n) and
+ *                               g_K_dev (one value) on the device (any output may be NULL)
+ * kur_adjoint_rk4_recorded_dev  as kur_adjoint_rk4_recorded, device seed and gradients
+ * The adjoint calls keep their work buffers in the context for the next call (option
+ * "adjoint_keep" = 0 releases them after every call, which then synchronises).
+ */
+kur_status kur_stream(const kur_ctx *ctx, void **hip_stream);
+kur_status kur_set_params_dev(kur_ctx *ctx, const void *omega_dev, double K);
+kur_status kur_set_phases_dev(kur_ctx *ctx, const void *theta_dev);
 kur_status kur_eval_rhs_dev(kur_ctx *ctx, const void *theta_dev, void *dtheta_dev);
-kur_status kur_get_phases_dev(kur_ctx *ctx, void *theta_dev);
+kur_status kur_get_phases_dev(kur_ctx *ctx, void *theta_dev, int wrapped);
+kur_status kur_order_parameter_dev(kur_ctx *ctx, const void *theta_dev, void *rpsi_dev);
+kur_status kur_order_parameter_vjp_dev(kur_ctx *ctx, const void *theta_dev, const void *rpsi_dev, const void *grad_dev,
+                                       void *dtheta_dev, int accumulate);
+kur_status kur_adjoint_rk4_dev(kur_ctx *ctx, const void *theta0_dev, double dt, int64_t nsteps, int64_t ckpt_every,
+                               const void *dl_dthetaT_dev, void *g_theta0_dev, void *g_omega_dev, void *g_K_dev);
+kur_status kur_adjoint_rk4_recorded_dev(kur_ctx *ctx, const void *dl_dthetaT_dev, void *g_theta0_dev,
+                                        void *g_omega_dev, void *g_K_dev);
 
 #ifdef __cplusplus
 }

@@ -13,6 +13,7 @@
 
 #include "../../include/kur.h"
 #include "kur_internal.hpp"
+#include "kur_io.hpp"
 #include "kur_kernels.hpp"
 #include "kur_tune.hpp"
 
@@ -25,6 +26,11 @@ namespace {
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+};
+
+// Work buffers of the adjoint, kept by the context between calls (option "adjoint_keep").
+struct AdjBufs {
+    DevBuf hi, lo, wind, ksum, ck, slots, acs, fpart[2], x[2], xpart[2], lam, lam_acc, lbuf, gom, gk;
 };
 
 }  // namespace
@@ -71,6 +77,10 @@ struct kur_ctx {
     // device state
     DevBuf d_omega, d_unit, d_hi, d_lo, d_wind, d_ksum, d_sc[2], d_part[2], d_sce, d_parte, d_kout, d_y;
     DevBuf d_r, d_psi;
+    DevBuf d_perm;   // user node -> block-order row, for the device-pointer calls
+    DevBuf d_opart;  // FP64 partials of the order parameter of a device phase vector
+    AdjBufs adj;     // adjoint work buffers
+    int adjoint_keep = 1;
     int cur = 0;
     bool sc_valid = false;
     bool complete_graph = false;  // the installed graph came from kur_set_graph_complete
@@ -183,6 +193,13 @@ hipError_t upload(DevBuf &b, const void *src, size_t bytes, hipStream_t st)
     return hipStreamSynchronize(st);
 }
 
+void free_adj(AdjBufs &B)
+{
+    DevBuf *b[] = {&B.hi, &B.lo, &B.wind, &B.ksum, &B.ck, &B.slots, &B.acs, &B.fpart[0], &B.fpart[1], &B.x[0], &B.x[1],
+                   &B.xpart[0], &B.xpart[1], &B.lam, &B.lam_acc, &B.lbuf, &B.gom, &B.gk};
+    for (DevBuf *p : b) dfree(*p);
+}
+
 void free_all(kur_ctx *c)
 {
     DevBuf *bufs[] = {&c->d_blk, &c->d_segd, &c->d_grp, &c->d_tiles, &c->d_order, &c->d_seg, &c->d_list, &c->d_iptr, &c->d_icol,
@@ -190,8 +207,9 @@ void free_all(kur_ctx *c)
                       &c->d_sc[1], &c->d_part[0], &c->d_part[1], &c->d_sce, &c->d_parte, &c->d_kout, &c->d_y,
                       &c->d_r, &c->d_psi, &c->d_tile_first, &c->d_inv_n, &c->d_ctr, &c->d_ck,
                       &c->d_blkT, &c->d_segdT, &c->d_grpT, &c->d_tilesT, &c->d_orderT, &c->d_segT,
-                      &c->d_listT, &c->d_iptrT, &c->d_icolT, &c->d_rsc, &c->d_rac};
+                      &c->d_listT, &c->d_iptrT, &c->d_icolT, &c->d_rsc, &c->d_rac, &c->d_perm, &c->d_opart};
     for (DevBuf *b : bufs) dfree(*b);
+    free_adj(c->adj);
     c->has_T = false;
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
@@ -446,7 +464,8 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
             (e = dalloc(c->d_part[0], 2 * T * g.tiles.size())) != hipSuccess ||
             (e = dalloc(c->d_part[1], 2 * T * g.tiles.size())) != hipSuccess ||
             (e = dalloc(c->d_parte, 2 * T * g.tiles.size())) != hipSuccess ||
-            (e = dalloc(c->d_kout, T * n)) != hipSuccess || (e = dalloc(c->d_y, T * n)) != hipSuccess) {
+            (e = dalloc(c->d_kout, T * n)) != hipSuccess || (e = dalloc(c->d_y, T * n)) != hipSuccess ||
+            (e = upload(c->d_perm, g.perm.data(), sizeof(int32_t) * n, c->stream)) != hipSuccess) {
             free_all(c);
             c->has_graph = false;
             return hip_fail(c, e, "graph upload");
@@ -731,6 +750,14 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "compensate must be 0 or 1");
         c->compensate = (int)v;
         c->gen++;
+    } else if (k == "adjoint_keep") {
+        if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "adjoint_keep must be 0 or 1");
+        c->adjoint_keep = (int)v;
+        if (!v && !c->host_only) {
+            HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+            HIPCHK(c, hipStreamSynchronize(c->stream), "adjoint buffers");
+            free_adj(c->adj);
+        }
     } else if (k == "record_stages") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "record_stages must be 0 or 1");
         c->record_stages = (int)v;
@@ -1051,10 +1078,106 @@ kur_status kur_eval_rhs_dev(kur_ctx *c, const void *theta_dev, void *dtheta_dev)
 {
     if (!c) return KUR_EINVAL;
     c->err.clear();
-    if (!theta_dev || !dtheta_dev) return fail(c, KUR_EINVAL, "device pointers must not be NULL");
-    kur_status s = need_ready(c, true, false);
+    if (!dtheta_dev) return fail(c, KUR_EINVAL, "dtheta_dev must not be NULL");
+    kur_status s = need_ready(c, true, theta_dev == nullptr);
     if (s != KUR_OK) return s;
-    return eval_common(c, theta_dev, dtheta_dev);
+    const int32_t *perm = (const int32_t *)c->d_perm.p;
+    const void *y = c->d_hi.p;
+    if (theta_dev) {
+        hipError_t e = c->esz == 4 ? launch_reduce_in<float>(c->n, perm, theta_dev, c->d_y.p, c->stream)
+                                   : launch_reduce_in<double>(c->n, perm, theta_dev, c->d_y.p, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "theta scatter");
+        y = c->d_y.p;
+    }
+    s = eval_common(c, y, c->d_kout.p);
+    if (s != KUR_OK) return s;
+    hipError_t e = c->esz == 4 ? launch_gather_out<float, float>(c->n, perm, c->d_kout.p, dtheta_dev, c->stream)
+                               : launch_gather_out<double, double>(c->n, perm, c->d_kout.p, dtheta_dev, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "rhs gather");
+    return KUR_OK;
+}
+
+kur_status kur_set_params_dev(kur_ctx *c, const void *omega_dev, double K)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!c->has_graph) return fail(c, KUR_ESTATE, "no graph set");
+    if (!omega_dev) return fail(c, KUR_EINVAL, "omega_dev must not be NULL");
+    if (!std::isfinite(K)) return fail(c, KUR_EINVAL, "K must be finite");
+    kur_status s = need_device(c);
+    if (s != KUR_OK) return s;
+    const int32_t *perm = (const int32_t *)c->d_perm.p;
+    hipError_t e = c->esz == 4 ? launch_scatter_in<float>(c->n, perm, omega_dev, c->d_omega.p, c->stream)
+                               : launch_scatter_in<double>(c->n, perm, omega_dev, c->d_omega.p, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "omega scatter");
+    c->K = K;
+    c->has_params = true;
+    c->gen++;
+    return KUR_OK;
+}
+
+kur_status kur_set_phases_dev(kur_ctx *c, const void *theta_dev)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!c->has_graph) return fail(c, KUR_ESTATE, "no graph set");
+    if (!theta_dev) return fail(c, KUR_EINVAL, "theta_dev must not be NULL");
+    kur_status s = need_device(c);
+    if (s != KUR_OK) return s;
+    const int32_t *perm = (const int32_t *)c->d_perm.p;
+    const double P1 = two_pi_p1(c->esz), P2 = two_pi_p2(c->esz);
+    hipError_t e = c->esz == 4
+                       ? launch_phase_in<float>(c->n, perm, theta_dev, P1, P2, c->d_hi.p, c->d_lo.p, (int32_t *)c->d_wind.p, c->stream)
+                       : launch_phase_in<double>(c->n, perm, theta_dev, P1, P2, c->d_hi.p, c->d_lo.p, (int32_t *)c->d_wind.p, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "phase split");
+    c->has_phases = true;
+    c->sc_valid = false;
+    return KUR_OK;
+}
+
+kur_status kur_order_parameter_dev(kur_ctx *c, const void *theta_dev, void *rpsi_dev)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!rpsi_dev) return fail(c, KUR_EINVAL, "rpsi_dev must not be NULL");
+    kur_status s = need_ready(c, false, theta_dev == nullptr);
+    if (s != KUR_OK) return s;
+    hipError_t e;
+    if ((e = dalloc(c->d_opart, 2 * sizeof(double) * kOpParts)) != hipSuccess) return hip_fail(c, e, "partials");
+    const void *th = theta_dev;
+    if (!th) {  // the current phases (wrapped; any order)
+        e = c->esz == 4 ? launch_phase_out<float>(c->n, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, 0, c->d_y.p, c->stream)
+                        : launch_phase_out<double>(c->n, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, 0, c->d_y.p, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "phase launch");
+        th = c->d_y.p;
+    }
+    e = c->esz == 4 ? launch_order_param<float>(c->n, th, (double *)c->d_opart.p, rpsi_dev, c->stream)
+                    : launch_order_param<double>(c->n, th, (double *)c->d_opart.p, rpsi_dev, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "order parameter launch");
+    return KUR_OK;
+}
+
+kur_status kur_order_parameter_vjp_dev(kur_ctx *c, const void *theta_dev, const void *rpsi_dev, const void *grad_dev,
+                                       void *dtheta_dev, int accumulate)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!theta_dev || !rpsi_dev || !grad_dev || !dtheta_dev)
+        return fail(c, KUR_EINVAL, "device pointers must not be NULL");
+    if (accumulate != 0 && accumulate != 1) return fail(c, KUR_EINVAL, "accumulate must be 0 or 1");
+    kur_status s = need_ready(c, false, false);
+    if (s != KUR_OK) return s;
+    hipError_t e = c->esz == 4 ? launch_order_param_vjp<float>(c->n, theta_dev, rpsi_dev, grad_dev, accumulate, dtheta_dev, c->stream)
+                               : launch_order_param_vjp<double>(c->n, theta_dev, rpsi_dev, grad_dev, accumulate, dtheta_dev, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "order parameter vjp launch");
+    return KUR_OK;
+}
+
+kur_status kur_stream(const kur_ctx *c, void **hip_stream)
+{
+    if (!c || !hip_stream) return KUR_EINVAL;
+    *hip_stream = (void *)c->stream;
+    return KUR_OK;
 }
 
 kur_status kur_diagnostics(kur_ctx *c, double *out)
@@ -1530,15 +1653,18 @@ kur_status kur_get_phases(kur_ctx *c, double *theta, int wrapped)
     return KUR_OK;
 }
 
-kur_status kur_get_phases_dev(kur_ctx *c, void *theta_dev)
+kur_status kur_get_phases_dev(kur_ctx *c, void *theta_dev, int wrapped)
 {
     if (!c) return KUR_EINVAL;
     c->err.clear();
     if (!theta_dev) return fail(c, KUR_EINVAL, "theta_dev must not be NULL");
     kur_status s = need_ready(c, false, true);
     if (s != KUR_OK) return s;
-    hipError_t e = c->esz == 4 ? launch_phase_out<float>(c->n, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, 0, theta_dev, c->stream)
-                               : launch_phase_out<double>(c->n, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, 0, theta_dev, c->stream);
+    const int32_t *perm = (const int32_t *)c->d_perm.p;
+    const double P1 = two_pi_p1(c->esz), P2 = two_pi_p2(c->esz);
+    const int w = wrapped ? 1 : 0;
+    hipError_t e = c->esz == 4 ? launch_phase_out_user<float>(c->n, perm, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, w, P1, P2, theta_dev, c->stream)
+                               : launch_phase_out_user<double>(c->n, perm, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, w, P1, P2, theta_dev, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "phase launch");
     return KUR_OK;
 }
@@ -1656,23 +1782,26 @@ kur_status kur_kernel_time(kur_ctx *c, int64_t *launches, double *total_ms)
 
 namespace {
 
-struct AdjBufs {
-    DevBuf hi, lo, wind, ksum, ck, slots, acs, fpart[2], x[2], xpart[2], lam, lam_acc, lbuf, gom, gk;
-    ~AdjBufs()
-    {
-        DevBuf *b[] = {&hi, &lo, &wind, &ksum, &ck, &slots, &acs, &fpart[0], &fpart[1], &x[0], &x[1],
-                       &xpart[0], &xpart[1], &lam, &lam_acc, &lbuf, &gom, &gk};
-        for (DevBuf *p : b) dfree(*p);
-    }
+
+// Inputs and outputs of one adjoint call, all in user order: host FP64 arrays, or (dev) device
+// arrays of the context type.
+struct AdjIO {
+    bool dev = false;
+    const double *theta0_host = nullptr;  // start of the forward run (host calls)
+    const void *theta0_dev = nullptr;     // start of the forward run (device calls)
+    const double *seed_host = nullptr;    // dL/dtheta(T)
+    const void *seed_dev = nullptr;
+    double *gt_host = nullptr, *gw_host = nullptr, *gk_host = nullptr;
+    void *gt_dev = nullptr, *gw_dev = nullptr, *gk_dev = nullptr;
 };
 
-// theta0_user: start of the forward run (then the forward pass runs here); ck_ext: device
-// checkpoints recorded by kur_step_rk4 instead (then theta0_user is unused).
+// The forward run starts at io's theta0, or at the context's current phases when neither is
+// given; ck_ext: device checkpoints recorded by kur_step_rk4 instead (then the forward pass is
+// not run here and theta0 is unused).
 // rec_sc, rec_ac: the stage record of that run (option "record_stages"), or null: then no
 // segment is recomputed and the reverse sweep reads the recorded stage states.
 template <typename T>
-kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ext, double dt, int64_t nsteps,
-                        int64_t C, const double *seed_user, double *g_theta0, double *g_omega, double *g_K,
+kur_status adjoint_impl(kur_ctx *c, const AdjIO &io, const void *ck_ext, double dt, int64_t nsteps, int64_t C,
                         const void *rec_sc = nullptr, const void *rec_ac = nullptr)
 {
     using std::vector;
@@ -1687,7 +1816,7 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
     // asymmetric A: the Jacobian-transpose gathers run over the layout of A^T (its own tiles)
     const bool asym = !c->symmetric;
     const int ntv = asym ? c->ntT : nt;
-    AdjBufs B;
+    AdjBufs &B = c->adj;
     hipError_t e;
     if ((e = dalloc(B.hi, TN)) != hipSuccess || (e = dalloc(B.lo, TN)) != hipSuccess ||
         (e = dalloc(B.wind, 4 * (size_t)n)) != hipSuccess || (e = dalloc(B.ksum, TN)) != hipSuccess ||
@@ -1705,26 +1834,46 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
     // initial phases (block order), split as in kur_set_phases; the seed dL/dtheta(T)
     {
         const double P1 = two_pi_p1(c->esz), P2 = two_pi_p2(c->esz);
-        vector<T> hi(n), lo(n), lam(n);
-        vector<int32_t> wind(n);
-        for (int64_t u = 0; u < n; ++u) {
-            const int64_t m = c->perm[u];
-            lam[m] = (T)seed_user[u];
-            if (ck_ext) continue;
-            const double q = std::nearbyint(theta0_user[u] / (2.0 * kPi));
-            const double red = (theta0_user[u] - q * P1) - q * P2;
-            hi[m] = (T)red;
-            lo[m] = (T)(red - (double)hi[m]);
-            wind[m] = (int32_t)q;
+        const bool from_state = !ck_ext && !io.theta0_host && !io.theta0_dev;
+        if (from_state &&
+            ((e = hipMemcpyAsync(B.hi.p, c->d_hi.p, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+             (e = hipMemcpyAsync(B.lo.p, c->d_lo.p, TN, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+             (e = hipMemcpyAsync(B.wind.p, c->d_wind.p, 4 * n, hipMemcpyDeviceToDevice, st)) != hipSuccess))
+            return hip_fail(c, e, "adjoint start state");
+        if (io.dev) {
+            if (!ck_ext && io.theta0_dev &&
+                (e = launch_phase_in<T>(n, (const int32_t *)c->d_perm.p, io.theta0_dev, P1, P2, B.hi.p, B.lo.p,
+                                        (int32_t *)B.wind.p, st)) != hipSuccess)
+                return hip_fail(c, e, "adjoint start phases");
+            if ((e = launch_scatter_in<T>(n, (const int32_t *)c->d_perm.p, io.seed_dev, B.lam.p, st)) != hipSuccess)
+                return hip_fail(c, e, "adjoint seed");
+        } else {
+            const bool up = !ck_ext && io.theta0_host;
+            vector<T> hi(up ? n : 0), lo(up ? n : 0), lam(n);
+            vector<int32_t> wind(up ? n : 0);
+            for (int64_t u = 0; u < n; ++u) {
+                const int64_t m = c->perm[u];
+                lam[m] = (T)io.seed_host[u];
+                if (!up) continue;
+                const double th = io.theta0_host[u];
+                const double q = std::nearbyint(th / (2.0 * kPi));
+                const double red = (th - q * P1) - q * P2;
+                hi[m] = (T)red;
+                lo[m] = (T)(red - (double)hi[m]);
+                wind[m] = (int32_t)q;
+            }
+            if ((up && ((e = hipMemcpyAsync(B.hi.p, hi.data(), TN, hipMemcpyHostToDevice, st)) != hipSuccess ||
+                        (e = hipMemcpyAsync(B.lo.p, lo.data(), TN, hipMemcpyHostToDevice, st)) != hipSuccess ||
+                        (e = hipMemcpyAsync(B.wind.p, wind.data(), 4 * n, hipMemcpyHostToDevice, st)) != hipSuccess)) ||
+                (e = hipMemcpyAsync(B.lam.p, lam.data(), TN, hipMemcpyHostToDevice, st)) != hipSuccess ||
+                (e = hipStreamSynchronize(st)) != hipSuccess)
+                return hip_fail(c, e, "adjoint upload");
         }
-        if ((e = hipMemcpyAsync(B.hi.p, hi.data(), TN, hipMemcpyHostToDevice, st)) != hipSuccess ||
-            (e = hipMemcpyAsync(B.lo.p, lo.data(), TN, hipMemcpyHostToDevice, st)) != hipSuccess ||
-            (e = hipMemcpyAsync(B.wind.p, wind.data(), 4 * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
-            (e = hipMemcpyAsync(B.lam.p, lam.data(), TN, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        // a recompute from recorded checkpoints restores (hi, lo) only: its winding counts start at 0
+        if ((ck_ext && (e = hipMemsetAsync(B.wind.p, 0, 4 * (size_t)n, st)) != hipSuccess) ||
             (e = hipMemsetAsync(B.gom.p, 0, 8 * (size_t)n, st)) != hipSuccess ||
-            (e = hipMemsetAsync(B.gk.p, 0, 8 * (size_t)ntv, st)) != hipSuccess ||
-            (e = hipStreamSynchronize(st)) != hipSuccess)
-            return hip_fail(c, e, "adjoint upload");
+            (e = hipMemsetAsync(B.gk.p, 0, 8 * (size_t)ntv, st)) != hipSuccess)
+            return hip_fail(c, e, "adjoint clear");
     }
     const DevGraph g = devgraph(c);
     const DevGraph gv = asym ? devgraph_t(c) : g;  // layout of the Jacobian-transpose gathers
@@ -1844,23 +1993,71 @@ kur_status adjoint_impl(kur_ctx *c, const double *theta0_user, const void *ck_ex
     }
 
     // results
-    vector<T> lam(n);
-    vector<double> gom(n), gk(ntv);
-    if ((e = hipMemcpyAsync(lam.data(), B.lam.p, TN, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(gom.data(), B.gom.p, 8 * (size_t)n, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(gk.data(), B.gk.p, 8 * (size_t)ntv, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess)
-        return hip_fail(c, e, "adjoint download");
-    for (int64_t u = 0; u < n; ++u) {
-        if (g_theta0) g_theta0[u] = (double)lam[c->perm[u]];
-        if (g_omega) g_omega[u] = gom[c->perm[u]];
+    if (io.dev) {
+        const int32_t *perm = (const int32_t *)c->d_perm.p;
+        if ((io.gt_dev && (e = launch_gather_out<T, T>(n, perm, B.lam.p, io.gt_dev, st)) != hipSuccess) ||
+            (io.gw_dev && (e = launch_gather_out<double, T>(n, perm, B.gom.p, io.gw_dev, st)) != hipSuccess) ||
+            (io.gk_dev && (e = launch_fold_sum<T>(ntv, (const double *)B.gk.p, io.gk_dev, st)) != hipSuccess))
+            return hip_fail(c, e, "adjoint results");
+    } else {
+        vector<T> lam(n);
+        vector<double> gom(n), gk(ntv);
+        if ((e = hipMemcpyAsync(lam.data(), B.lam.p, TN, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(gom.data(), B.gom.p, 8 * (size_t)n, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(gk.data(), B.gk.p, 8 * (size_t)ntv, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(c, e, "adjoint download");
+        for (int64_t u = 0; u < n; ++u) {
+            if (io.gt_host) io.gt_host[u] = (double)lam[c->perm[u]];
+            if (io.gw_host) io.gw_host[u] = gom[c->perm[u]];
+        }
+        if (io.gk_host) {
+            double t = 0.0;
+            for (int i = 0; i < ntv; ++i) t += gk[i];
+            *io.gk_host = t;
+        }
     }
-    if (g_K) {
-        double t = 0.0;
-        for (int i = 0; i < ntv; ++i) t += gk[i];
-        *g_K = t;
+    if (!c->adjoint_keep) {
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "adjoint");
+        free_adj(B);
     }
     return KUR_OK;
+}
+
+// Validation shared by the adjoint calls (host-side; nothing is enqueued).
+kur_status adjoint_check(kur_ctx *c)
+{
+    if (!c->symmetric && !c->has_T)
+        return fail(c, KUR_EINVAL, "the adjoint of an asymmetric adjacency needs its transposed layout: set option "
+                                   "\"transpose\" to 1 before kur_set_graph_csr / kur_set_graph_csr_w");
+    if (c->batch) return fail(c, KUR_EINVAL, "the adjoint of a batch is not supported");
+    if (rows_lds_bytes(c->esz, c->W, c->symmetric ? c->tile_rows : c->tile_rowsT, c->threads) > 156 * 1024)
+        return fail(c, KUR_EINVAL, "chunk/tile_rows of the transposed layout exceed the LDS of a workgroup");
+    return KUR_OK;
+}
+
+kur_status adjoint_run(kur_ctx *c, const AdjIO &io, double dt, int64_t nsteps, int64_t ckpt_every)
+{
+    const int64_t C = std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1));
+    try {
+        return c->esz == 4 ? adjoint_impl<float>(c, io, nullptr, dt, nsteps, C)
+                           : adjoint_impl<double>(c, io, nullptr, dt, nsteps, C);
+    } catch (const std::bad_alloc &) {
+        return fail(c, KUR_ENOMEM, "host allocation failed in the adjoint");
+    }
+}
+
+kur_status adjoint_run_recorded(kur_ctx *c, const AdjIO &io)
+{
+    if (!c->rec_valid || c->rec_gen != c->gen)
+        return fail(c, KUR_ESTATE, "no checkpoints recorded by kur_step_rk4 for the current graph, omega and K");
+    try {
+        const void *rsc = c->rec_stages ? c->d_rsc.p : nullptr, *rac = c->rec_stages ? c->d_rac.p : nullptr;
+        return c->esz == 4 ? adjoint_impl<float>(c, io, c->d_ck.p, c->rec_dt, c->rec_nsteps, c->rec_C, rsc, rac)
+                           : adjoint_impl<double>(c, io, c->d_ck.p, c->rec_dt, c->rec_nsteps, c->rec_C, rsc, rac);
+    } catch (const std::bad_alloc &) {
+        return fail(c, KUR_ENOMEM, "host allocation failed in the adjoint");
+    }
 }
 
 }  // namespace
@@ -1875,29 +2072,39 @@ extern "C" kur_status kur_adjoint_rk4(kur_ctx *c, const double *theta0, double d
     if (!dl_dthetaT) return fail(c, KUR_EINVAL, "dl_dthetaT must not be NULL");
     kur_status s = need_ready(c, true, theta0 == nullptr);
     if (s != KUR_OK) return s;
-    if (!c->symmetric && !c->has_T)
-        return fail(c, KUR_EINVAL, "the adjoint of an asymmetric adjacency needs its transposed layout: set option "
-                                   "\"transpose\" to 1 before kur_set_graph_csr / kur_set_graph_csr_w");
-    if (c->batch) return fail(c, KUR_EINVAL, "the adjoint of a batch is not supported");
-    if (rows_lds_bytes(c->esz, c->W, c->symmetric ? c->tile_rows : c->tile_rowsT, c->threads) > 156 * 1024)
-        return fail(c, KUR_EINVAL, "chunk/tile_rows of the transposed layout exceed the LDS of a workgroup");
-    std::vector<double> th0;
-    if (!theta0) {
-        th0.resize(c->n);
-        s = kur_get_phases(c, th0.data(), 0);
-        if (s != KUR_OK) return s;
-        theta0 = th0.data();
-    }
+    if ((s = adjoint_check(c)) != KUR_OK) return s;
     for (int64_t u = 0; u < c->n; ++u)
-        if (!std::isfinite(theta0[u]) || std::fabs(theta0[u]) > 1e9 || !std::isfinite(dl_dthetaT[u]))
+        if ((theta0 && (!std::isfinite(theta0[u]) || std::fabs(theta0[u]) > 1e9)) || !std::isfinite(dl_dthetaT[u]))
             return fail(c, KUR_EINVAL, "theta0 and dl_dthetaT must be finite (|theta0| <= 1e9)");
-    const int64_t C = std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1));
-    try {
-        return c->esz == 4 ? adjoint_impl<float>(c, theta0, nullptr, dt, nsteps, C, dl_dthetaT, g_theta0, g_omega, g_K)
-                           : adjoint_impl<double>(c, theta0, nullptr, dt, nsteps, C, dl_dthetaT, g_theta0, g_omega, g_K);
-    } catch (const std::bad_alloc &) {
-        return fail(c, KUR_ENOMEM, "host allocation failed in the adjoint");
-    }
+    AdjIO io;
+    io.theta0_host = theta0;
+    io.seed_host = dl_dthetaT;
+    io.gt_host = g_theta0;
+    io.gw_host = g_omega;
+    io.gk_host = g_K;
+    return adjoint_run(c, io, dt, nsteps, ckpt_every);
+}
+
+extern "C" kur_status kur_adjoint_rk4_dev(kur_ctx *c, const void *theta0_dev, double dt, int64_t nsteps,
+                                          int64_t ckpt_every, const void *dl_dthetaT_dev, void *g_theta0_dev,
+                                          void *g_omega_dev, void *g_K_dev)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!std::isfinite(dt) || dt == 0.0) return fail(c, KUR_EINVAL, "dt must be finite and nonzero");
+    if (nsteps < 0 || ckpt_every < 1) return fail(c, KUR_EINVAL, "nsteps must be >= 0 and ckpt_every >= 1");
+    if (!dl_dthetaT_dev) return fail(c, KUR_EINVAL, "dl_dthetaT_dev must not be NULL");
+    kur_status s = need_ready(c, true, theta0_dev == nullptr);
+    if (s != KUR_OK) return s;
+    if ((s = adjoint_check(c)) != KUR_OK) return s;
+    AdjIO io;
+    io.dev = true;
+    io.theta0_dev = theta0_dev;
+    io.seed_dev = dl_dthetaT_dev;
+    io.gt_dev = g_theta0_dev;
+    io.gw_dev = g_omega_dev;
+    io.gk_dev = g_K_dev;
+    return adjoint_run(c, io, dt, nsteps, ckpt_every);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -2074,25 +2281,33 @@ extern "C" kur_status kur_adjoint_rk4_recorded(kur_ctx *c, const double *dl_dthe
     if (!dl_dthetaT) return fail(c, KUR_EINVAL, "dl_dthetaT must not be NULL");
     kur_status s = need_ready(c, true, true);
     if (s != KUR_OK) return s;
-    if (!c->rec_valid || c->rec_gen != c->gen)
-        return fail(c, KUR_ESTATE, "no checkpoints recorded by kur_step_rk4 for the current graph, omega and K");
-    if (!c->symmetric && !c->has_T)
-        return fail(c, KUR_EINVAL, "the adjoint of an asymmetric adjacency needs its transposed layout: set option "
-                                   "\"transpose\" to 1 before kur_set_graph_csr / kur_set_graph_csr_w");
-    if (c->batch) return fail(c, KUR_EINVAL, "the adjoint of a batch is not supported");
-    if (rows_lds_bytes(c->esz, c->W, c->symmetric ? c->tile_rows : c->tile_rowsT, c->threads) > 156 * 1024)
-        return fail(c, KUR_EINVAL, "chunk/tile_rows of the transposed layout exceed the LDS of a workgroup");
+    if ((s = adjoint_check(c)) != KUR_OK) return s;
     for (int64_t u = 0; u < c->n; ++u)
         if (!std::isfinite(dl_dthetaT[u])) return fail(c, KUR_EINVAL, "dl_dthetaT must be finite");
-    try {
-        const void *rsc = c->rec_stages ? c->d_rsc.p : nullptr, *rac = c->rec_stages ? c->d_rac.p : nullptr;
-        return c->esz == 4 ? adjoint_impl<float>(c, nullptr, c->d_ck.p, c->rec_dt, c->rec_nsteps, c->rec_C, dl_dthetaT,
-                                                 g_theta0, g_omega, g_K, rsc, rac)
-                           : adjoint_impl<double>(c, nullptr, c->d_ck.p, c->rec_dt, c->rec_nsteps, c->rec_C, dl_dthetaT,
-                                                  g_theta0, g_omega, g_K, rsc, rac);
-    } catch (const std::bad_alloc &) {
-        return fail(c, KUR_ENOMEM, "host allocation failed in the adjoint");
-    }
+    AdjIO io;
+    io.seed_host = dl_dthetaT;
+    io.gt_host = g_theta0;
+    io.gw_host = g_omega;
+    io.gk_host = g_K;
+    return adjoint_run_recorded(c, io);
+}
+
+extern "C" kur_status kur_adjoint_rk4_recorded_dev(kur_ctx *c, const void *dl_dthetaT_dev, void *g_theta0_dev,
+                                                   void *g_omega_dev, void *g_K_dev)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!dl_dthetaT_dev) return fail(c, KUR_EINVAL, "dl_dthetaT_dev must not be NULL");
+    kur_status s = need_ready(c, true, true);
+    if (s != KUR_OK) return s;
+    if ((s = adjoint_check(c)) != KUR_OK) return s;
+    AdjIO io;
+    io.dev = true;
+    io.seed_dev = dl_dthetaT_dev;
+    io.gt_dev = g_theta0_dev;
+    io.gw_dev = g_omega_dev;
+    io.gk_dev = g_K_dev;
+    return adjoint_run_recorded(c, io);
 }
 
 extern "C" kur_status kur_recorded_run(const kur_ctx *c, int64_t *serial, double *dt, int64_t *nsteps)

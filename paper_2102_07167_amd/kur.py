@@ -81,8 +81,15 @@ SIGNATURES = {
     "kur_diagnostics": (ST, [P, P]),
     "kur_step_midpoint": (ST, [P, F64, I64, I32, I64, P, P]),
     "kur_step_adaptive": (ST, [P, F64, F64, F64, I64, P]),
+    "kur_stream": (ST, [P, ctypes.POINTER(P)]),
+    "kur_set_params_dev": (ST, [P, P, F64]),
+    "kur_set_phases_dev": (ST, [P, P]),
     "kur_eval_rhs_dev": (ST, [P, P, P]),
-    "kur_get_phases_dev": (ST, [P, P]),
+    "kur_get_phases_dev": (ST, [P, P, ctypes.c_int]),
+    "kur_order_parameter_dev": (ST, [P, P, P]),
+    "kur_order_parameter_vjp_dev": (ST, [P, P, P, P, P, ctypes.c_int]),
+    "kur_adjoint_rk4_dev": (ST, [P, P, F64, I64, I64, P, P, P, P]),
+    "kur_adjoint_rk4_recorded_dev": (ST, [P, P, P, P, P]),
 }
 
 
@@ -134,11 +141,13 @@ class Kuramoto:
             raise KurError(rc, "kur_create(dtype=%s, device=%d) failed" % (dtype, device))
         self._h = h
         self.n = 0
+        self.device = int(device)
 
     def close(self):
         if getattr(self, "_h", None):
             self._L.kur_destroy(self._h)
             self._h = None
+        self._ext_stream = None
 
     def __del__(self):
         try:
@@ -520,9 +529,92 @@ class Kuramoto:
         self._chk(self._L.kur_kernel_time(self._h, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
 
-    # -- device tensors (block order, context dtype) ----------------------------------------
-    def eval_rhs_dev(self, theta_t, out_t):
-        self._chk(self._L.kur_eval_rhs_dev(self._h, P(theta_t.data_ptr()), P(out_t.data_ptr())))
+    # -- device tensors (user order, context dtype) -----------------------------------------
+    # The library enqueues on its own stream. Around every call the context stream waits for
+    # the caller's current torch stream, and the caller's stream then waits for the context
+    # stream; so work the caller enqueues later (including the reuse of a freed tensor's memory
+    # by torch's caching allocator, which follows the allocating stream) runs after the call.
+    # Tensors must therefore belong to the caller's current stream. (Tensors are not marked with
+    # record_stream on the context stream: that stream ends with the context, and torch would
+    # later record events on its stale handle.)
+    def stream_handle(self) -> int:
+        h = P()
+        self._chk(self._L.kur_stream(self._h, ctypes.byref(h)))
+        return int(h.value or 0)
 
-    def get_phases_dev(self, out_t):
-        self._chk(self._L.kur_get_phases_dev(self._h, P(out_t.data_ptr())))
+    def _dev_args(self, tensors, n=None):
+        import torch
+        want = torch.float32 if self.dtype in ("f32", "float32") else torch.float64
+        for t in tensors:
+            if t is None:
+                continue
+            if not t.is_cuda or t.dtype != want or not t.is_contiguous():
+                raise ValueError("device calls take contiguous %s tensors on the GPU" % want)
+            if n is not None and t.numel() != n:
+                raise ValueError("expected %d entries, got %d" % (n, t.numel()))
+        return want
+
+    def _dev_call(self, fn, tensors, *args):
+        import torch
+        ext = getattr(self, "_ext_stream", None)
+        if ext is None:
+            ext = torch.cuda.ExternalStream(self.stream_handle())
+            self._ext_stream = ext
+        cur = torch.cuda.current_stream()
+        same = cur.cuda_stream == ext.cuda_stream
+        if not same:
+            ext.wait_stream(cur)
+        self._chk(fn(self._h, *args))
+        if not same:
+            cur.wait_stream(ext)
+
+    @staticmethod
+    def _dp(t):
+        return None if t is None else P(t.data_ptr())
+
+    def set_params_dev(self, omega_t, K: float):
+        self._dev_args([omega_t], self.n)
+        self._dev_call(self._L.kur_set_params_dev, [omega_t], self._dp(omega_t), float(K))
+
+    def set_phases_dev(self, theta_t):
+        self._dev_args([theta_t], self.n)
+        self._dev_call(self._L.kur_set_phases_dev, [theta_t], self._dp(theta_t))
+
+    def eval_rhs_dev(self, theta_t, out_t):
+        """F(theta) into out_t (theta_t None: the current phases)."""
+        self._dev_args([theta_t, out_t], self.n)
+        self._dev_call(self._L.kur_eval_rhs_dev, [theta_t, out_t], self._dp(theta_t), self._dp(out_t))
+
+    def get_phases_dev(self, out_t, wrapped: bool = False):
+        self._dev_args([out_t], self.n)
+        self._dev_call(self._L.kur_get_phases_dev, [out_t], self._dp(out_t), 1 if wrapped else 0)
+
+    def order_parameter_dev(self, theta_t, out_t):
+        """out_t[0] = r, out_t[1] = psi of theta_t (None: the current phases)."""
+        self._dev_args([theta_t], self.n)
+        self._dev_args([out_t], 2)
+        self._dev_call(self._L.kur_order_parameter_dev, [theta_t, out_t], self._dp(theta_t), self._dp(out_t))
+
+    def order_parameter_vjp_dev(self, theta_t, rpsi_t, grad_t, out_t, accumulate: bool = False):
+        """out_t (+)= g_r dr/dtheta + g_psi dpsi/dtheta at (r, psi) = rpsi_t, (g_r, g_psi) = grad_t."""
+        self._dev_args([theta_t, out_t], self.n)
+        self._dev_args([rpsi_t, grad_t], 2)
+        self._dev_call(self._L.kur_order_parameter_vjp_dev, [theta_t, rpsi_t, grad_t, out_t], self._dp(theta_t),
+                       self._dp(rpsi_t), self._dp(grad_t), self._dp(out_t), 1 if accumulate else 0)
+
+    def adjoint_rk4_dev(self, dt: float, nsteps: int, seed_t, gt_t, gw_t, gk_t, theta0_t=None,
+                        ckpt_every: int = 32):
+        """kur_adjoint_rk4_dev: the gradients into gt_t, gw_t (n) and gk_t (1 entry); any output may
+        be None."""
+        self._dev_args([seed_t, gt_t, gw_t, theta0_t], self.n)
+        self._dev_args([gk_t], 1)
+        ts = [theta0_t, seed_t, gt_t, gw_t, gk_t]
+        self._dev_call(self._L.kur_adjoint_rk4_dev, ts, self._dp(theta0_t), float(dt), int(nsteps), int(ckpt_every),
+                       self._dp(seed_t), self._dp(gt_t), self._dp(gw_t), self._dp(gk_t))
+
+    def adjoint_recorded_dev(self, seed_t, gt_t, gw_t, gk_t):
+        """kur_adjoint_rk4_recorded_dev with device seed and gradients."""
+        self._dev_args([seed_t, gt_t, gw_t], self.n)
+        self._dev_args([gk_t], 1)
+        self._dev_call(self._L.kur_adjoint_rk4_recorded_dev, [seed_t, gt_t, gw_t, gk_t], self._dp(seed_t),
+                       self._dp(gt_t), self._dp(gw_t), self._dp(gk_t))

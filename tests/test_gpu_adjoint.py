@@ -209,25 +209,57 @@ def test_adjoint_sbm_64x1024_2000_steps_fp32(need_gpu):
 
 
 @pytest.mark.parametrize("record_stages", [False, True])
-def test_autograd_function(need_gpu, record_stages):
+@pytest.mark.parametrize("where", ["cuda", "cpu"])
+def test_autograd_function(need_gpu, record_stages, where):
+    """The loss of config 5, (1 - r(T))^2 + mean chordal distance to a target, through the
+    autograd wrappers: theta(T) and r(T) both come from the library (device calls), and the
+    gradients of theta0, omega and K match the oracle's discrete adjoint to 1e-10. Tensors on
+    the GPU stay there; CPU tensors are moved to the device and their gradients moved back."""
     import torch
     from paper_2102_07167_amd.autograd import integrate, order_parameter
     w = ragged_sbm(9)
     with ctx(w, "f64") as k:
-        th0 = torch.tensor(w.theta0, requires_grad=True)
-        om = torch.tensor(w.omega, requires_grad=True)
-        K = torch.tensor(w.K, dtype=torch.float64, requires_grad=True)
+        th0 = torch.tensor(w.theta0, device=where, requires_grad=True)
+        om = torch.tensor(w.omega, device=where, requires_grad=True)
+        K = torch.tensor(w.K, dtype=torch.float64, device=where, requires_grad=True)
         thT = integrate(k, th0, om, K, w.dt, w.steps, ckpt_every=8, record_stages=record_stages)
-        tgt = torch.tensor(w.target)
-        loss = (1 - order_parameter(thT)) ** 2 + (2 * (1 - torch.cos(thT - tgt))).mean()
+        assert thT.device.type == where
+        tgt = torch.tensor(w.target, device=where)
+        r, _ = order_parameter(k, thT)
+        loss = (1 - r) ** 2 + (2 * (1 - torch.cos(thT - tgt))).mean()
         loss.backward()
         thT_o, _, _ = oracle.rk4(w.graph, w.omega, w.K, w.theta0, w.dt, w.steps)
         L_o, seed = oracle.loss_and_seed(thT_o, w.target)
         assert abs(loss.item() - L_o) < 1e-12
         gt_o, gw_o, gk_o = oracle.adjoint_rk4(w.graph, w.omega, w.K, w.theta0, w.dt, w.steps, seed)
-        assert np.abs(th0.grad.numpy() - gt_o).max() <= 1e-10 * np.abs(gt_o).max()
-        assert np.abs(om.grad.numpy() - gw_o).max() <= 1e-10 * np.abs(gw_o).max()
+        assert th0.grad.device.type == where and om.grad.device.type == where
+        assert np.abs(th0.grad.cpu().numpy() - gt_o).max() <= 1e-10 * np.abs(gt_o).max()
+        assert np.abs(om.grad.cpu().numpy() - gw_o).max() <= 1e-10 * np.abs(gw_o).max()
         assert abs(K.grad.item() - gk_o) <= 1e-10 * max(abs(gk_o), 1e-3)
+
+
+def test_autograd_fp32_and_psi(need_gpu):
+    """FP32 model with float32 tensors: gradients within the FP32 bound (1e-3) of the oracle's
+    FP64 adjoint; a loss on psi(T) differentiates through the library's order parameter."""
+    import torch
+    from paper_2102_07167_amd.autograd import integrate, order_parameter
+    w = ragged_sbm(13)
+    w.omega = w.omega.astype(np.float32).astype(np.float64)
+    w.theta0 = w.theta0.astype(np.float32).astype(np.float64)
+    with ctx(w, "f32") as k:
+        th0 = torch.tensor(w.theta0, dtype=torch.float32, device="cuda", requires_grad=True)
+        om = torch.tensor(w.omega, dtype=torch.float32, device="cuda", requires_grad=True)
+        thT = integrate(k, th0, om, w.K, w.dt, w.steps, ckpt_every=8)
+        r, psi = order_parameter(k, thT)
+        (torch.sin(psi) + r).backward()
+    thT_o, _, _ = oracle.rk4(w.graph, w.omega, w.K, w.theta0, w.dt, w.steps)
+    ro, po = oracle.order_parameter(thT_o)
+    n = w.graph.n
+    # d(sin psi + r)/dtheta_m = cos(psi) cos(psi - theta_m)/(N r) + sin(psi - theta_m)/N
+    seed = (np.cos(po) * np.cos(po - thT_o) / ro + np.sin(po - thT_o)) / n
+    gt_o, gw_o, _ = oracle.adjoint_rk4(w.graph, w.omega, w.K, w.theta0, w.dt, w.steps, seed)
+    assert np.abs(th0.grad.cpu().numpy() - gt_o).max() <= 1e-3 * np.abs(gt_o).max()
+    assert np.abs(om.grad.cpu().numpy() - gw_o).max() <= 1e-3 * np.abs(gw_o).max()
 
 
 def test_recorded_adjoint_matches_full_adjoint(need_gpu):
@@ -299,13 +331,13 @@ def test_autograd_two_forwards(need_gpu):
     from paper_2102_07167_amd.autograd import integrate
     w = ragged_sbm(11)
     with ctx(w, "f64") as k:
-        th_a = torch.tensor(w.theta0, requires_grad=True)
-        th_b = torch.tensor(w.theta0[::-1].copy(), requires_grad=True)
-        om = torch.tensor(w.omega)
-        K = torch.tensor(w.K, dtype=torch.float64)
+        th_a = torch.tensor(w.theta0, device="cuda", requires_grad=True)
+        th_b = torch.tensor(w.theta0[::-1].copy(), device="cuda", requires_grad=True)
+        om = torch.tensor(w.omega, device="cuda")
+        K = torch.tensor(w.K, dtype=torch.float64, device="cuda")
         out_a = integrate(k, th_a, om, K, w.dt, 20, 8)
         out_b = integrate(k, th_b, om, K, w.dt, 20, 8)
         out_a.sum().backward()
         out_b.sum().backward()
     # L = sum theta(T): dL/dtheta0 = 1 (symmetric A, uniform scaling)
-    assert np.abs(th_a.grad.numpy() - 1).max() < 1e-12 and np.abs(th_b.grad.numpy() - 1).max() < 1e-12
+    assert np.abs(th_a.grad.cpu().numpy() - 1).max() < 1e-12 and np.abs(th_b.grad.cpu().numpy() - 1).max() < 1e-12
