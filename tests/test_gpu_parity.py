@@ -5,8 +5,9 @@ Tolerances (from the arithmetic and the stated targets):
   FP64 phases            max |wrap(dtheta)| <= 1e-12 * max(1, max |theta_oracle|)  (unwrapped scale)
   FP32 phases            max |wrap(dtheta)| <= 1e-5 after 1000 RK4 steps; the oracle integrates in FP64
                          from the FP32-rounded theta0, omega, K and dt
-  FP32 right-hand side   |dG_m| <= 1e-5 * scale_m * (deg_m + 2 s_b [dense]) where G = F - omega
-                         (rounding scale of the complement form: u * (|S_b| + |C_b| + sum |terms|))
+  FP32 right-hand side   |dG_m| <= 1e-5 * scale_m * (deg_m + 2 s_b [block of row m stores zeros])
+                         where G = F - omega (rounding scale of the complement form:
+                         u * (|S_b| + |C_b| + sum |terms|); summed for every column group of the row)
 """
 import math
 
@@ -44,20 +45,27 @@ def rel_err(a, b):
     return np.abs(a - b).max() / max(1.0, np.abs(b).max())
 
 
-def fp32_rhs_bound(k, w, theta):
+def dense_term(k, g):
+    """Per user row, sum over the column groups whose localised order parameters enter the row
+    (its own community when that block stores its zeros, and dense off-diagonal blocks) of
+    2 x group size x factor: the rounding scale |S_b| + |C_b| <= 2 s_b of the complement form,
+    which rows summed straightforwardly do not carry. Blocks follow the label order."""
+    if g.complete:
+        return np.full(g.n, 2.0 * g.n)
+    _, inv, cnt = np.unique(g.labels, return_inverse=True, return_counts=True)
+    assert k.graph_info()["blocks"] == len(cnt)
+    per_block = np.zeros(len(cnt))
+    for b in range(len(cnt)):
+        blk, md = k.block_groups(b)
+        per_block[b] = 2.0 * float((cnt[blk] * md).sum())
+    return per_block[inv]
+
+
+def fp32_rhs_bound(k, w, theta=None):
     """Per-row rounding scale for an FP32 evaluation (see module docstring)."""
     g = w.graph
     deg = np.diff(g.row_ptr) if not g.complete else np.full(g.n, g.n - 1)
-    bp, mode = None, None
-    perm = k.perm()
-    info = k.graph_info()
-    # block size of every user node: size of its label's community
-    if g.complete:
-        sb = np.full(g.n, g.n)
-    else:
-        _, inv, cnt = np.unique(g.labels, return_inverse=True, return_counts=True)
-        sb = cnt[inv]
-    return 1e-5 * (w.K / g.n) * (deg + 2 * sb) + 1e-6 * np.abs(w.omega) + 1e-7
+    return 1e-5 * (w.K / g.n) * (deg + dense_term(k, g)) + 1e-6 * np.abs(w.omega) + 1e-7
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -118,10 +126,13 @@ def test_sbm_fp32_trajectory_1000_steps(need_gpu, flat):
 @pytest.mark.parametrize("opts", [dict(chunk=64, tile_rows=64), dict(tau=0.0, chunk=128), dict(tau=1.0),
                                   dict(threads=256, tile_rows=128), dict(threads=1024),
                                   dict(flat_min_vec=0.1, chunk=128, tile_rows=64), dict(flat_min_vec=0.1, tau=0.0),
-                                  dict(flat_min_vec=0), dict(tile_min_cost=1), dict(tile_min_cost=1, tiles=100000)])
+                                  dict(flat_min_vec=0), dict(tile_min_cost=1), dict(tile_min_cost=1, tiles=100000),
+                                  dict(xcds=8, tile_min_cost=1), dict(xcds=8, tile_rows=64, chunk=128),
+                                  dict(xcds=3, tile_min_cost=64)])
 def test_ragged_layouts(need_gpu, dtype, opts):
     """Odd block sizes, several chunks per block, several tiles per block, all-dense and
-    all-sparse evaluation, a size-1 block and a complete block."""
+    all-sparse evaluation, a size-1 block and a complete block; launch orders for 8 and 3 XCDs
+    (tiles of a block on one XCD, empty slots in the launch order)."""
     rng = np.random.default_rng(77)
     sizes = np.array([333, 1, 129, 700, 64, 2, 515])
     rho = np.array([0.95, 0.5, 0.3, 0.75, 1.0, 1.0, 0.55])
@@ -274,7 +285,79 @@ def test_sbm_64x1024_sampled_rows(need_gpu):
                 assert abs(dev) < 1e-10
 
 
-def test_het_sbm_n2p20_sampled_rows(need_gpu):
+def load_trajectory_fixture(name):
+    """(steps of the r samples, r, psi, rows, theta(T) of those rows) of a fixture written by
+    tests/golden/make_sbm64x1024_trajectory.py (oracle only)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    rs, rows, th = [], [], []
+    with open(path) as f:
+        for line in f:
+            p = line.split()
+            if not p or p[0].startswith("#"):
+                continue
+            if p[0] == "r":
+                rs.append((int(p[1]), float(p[2]), float(p[3])))
+            elif p[0] == "theta":
+                rows.append(int(p[1]))
+                th.append(float(p[2]))
+    rs = np.array(rs)
+    return rs[:, 0].astype(int), rs[:, 1], rs[:, 2], np.array(rows, dtype=np.int64), np.array(th)
+
+
+# The committed cached layout of the 64 x 1024 SBM (tile options chosen by the tuner on MI355X,
+# launch order for 8 XCDs); FP64 contexts take the same tile options with their own chunk width.
+SBM64_CACHED = dict(tile_rows=64, tile_min_cost=8192, flat_min_vec=8, xcds=8)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("layout", ["default", "cached"])
+def test_sbm_64x1024_trajectory_1000_steps(need_gpu, dtype, layout):
+    """The 64 x 1024 SBM workload at full size (N = 65536, rho 0.97, p_out 2e-4, permuted), 1000
+    RK4 steps: phases of a seeded 1/16 of the rows and r every 10 steps (all rows) against the
+    oracle's trajectory stored in tests/golden/ (Sec. 3, eq. KuramotoGraph; classical RK4).
+    FP64 from the FP64 inputs: |wrap(dtheta)| and |dr| <= 1e-12 max(1, max |theta_oracle|).
+    FP32 from the FP32-rounded inputs (the oracle integrated those in FP64): <= 1e-5. Run in the
+    default layout and in the committed tuned layout (8-XCD launch order), the one bench.py uses."""
+    import os
+    w = gen.sbm_equal()
+    g = w.graph
+    steps_r, ro, psio, rows, tho = load_trajectory_fixture(
+        "sbm64x1024_rk4_1000_%sin.txt" % ("f64" if dtype == "f64" else "f32"))
+    om, th0, K, dt = w.omega, w.theta0, w.K, w.dt
+    if dtype == "f32":
+        om, th0, K, dt = f32(om), f32(th0), float(np.float32(K)), float(np.float32(dt))
+    with Kuramoto(dtype, device=0) as k:
+        if layout == "cached" and dtype == "f32":
+            cache = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                 "paper_2102_07167_amd", "tuned_layouts.tsv")
+            rep = k.autotune(g, effort=1, cache=cache)
+            assert rep["cache"] == 1 and rep["xcds"] == 8
+        else:
+            if layout == "cached":
+                for key, v in SBM64_CACHED.items():
+                    k.set_option(key, v)
+            k.set_graph(g)
+        k.set_params(om, K)
+        k.set_phases(th0)
+        r, psi = k.step_rk4(dt, 1000, r_every=10)
+        th = k.get_phases(wrapped=False)
+    assert np.array_equal(np.arange(0, 1001, 10), steps_r)
+    tol = 1e-12 * max(1.0, np.abs(tho).max()) if dtype == "f64" else 1e-5
+    err = np.abs(wrap(th[rows] - tho)).max()
+    assert err <= tol, (err, tol)
+    assert np.abs(r - ro).max() <= tol
+    live = ro > 1e-3
+    assert np.abs(wrap(psi - psio)[live]).max() <= tol / 1e-3
+
+
+@pytest.fixture(scope="module")
+def het_workload():
+    """The heterogeneous N = 2^20 SBM workload, generated once for the tests of this module."""
+    return gen.sbm_heterogeneous()
+
+
+def test_het_sbm_n2p20_sampled_rows(need_gpu, het_workload):
     """Heterogeneous SBM, N = 2^20 (power-law communities in [256, 16384], densities U[0.3, 1],
     inter mean degree 8), FP32, in the layout bench.py times (installed through the committed
     tuning cache). The coupling sums of a seeded 1/64 subsample of rows (omega = 0 so that the
@@ -283,7 +366,7 @@ def test_het_sbm_n2p20_sampled_rows(need_gpu):
     below the ~0.6 K/N of one missing or extra edge; then, with the real omega, the conserved
     mean over 20 RK4 steps and r against the GPU's own phases."""
     import os
-    w = gen.sbm_heterogeneous()
+    w = het_workload
     g = w.graph
     cache = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2102_07167_amd",
                          "tuned_layouts.tsv")
@@ -311,6 +394,51 @@ def test_het_sbm_n2p20_sampled_rows(need_gpu):
     assert abs(math.fsum(th - th0 - T * om) / g.n) < 1e-5
     ro, _ = oracle.order_parameter(th)
     assert abs(r - ro) < 1e-5
+
+
+def test_het_sbm_n2p20_evolved_states(need_gpu, het_workload):
+    """Heterogeneous SBM, N = 2^20, FP32 with the real Cauchy(0, 0.5) frequencies, in the layout
+    bench.py times: at the GPU's own states after 0, 100, ..., 500 RK4 steps (dt 0.005), the
+    coupling sums G = F - omega of a seeded 1/64 of the rows against the FP64 oracle at the same
+    (FP32) phases, within 1e-5 (K/N)(deg_m + 2 s_b [dense]) (Sec. 3, eq. KuramotoGraphApproach);
+    G is evaluated with omega = 0 so that the FP32 rounding of F = omega + G at the Cauchy tails
+    does not hide it, and F with the real omega within that bound plus half an FP32 ulp of |F|.
+    r at every state against the oracle's r of the same phases."""
+    import os
+    w = het_workload
+    g = w.graph
+    cache = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2102_07167_amd",
+                         "tuned_layouts.tsv")
+    rows = np.sort(np.random.default_rng(0).choice(g.n, g.n // 64, replace=False))
+    th0 = f32(w.theta0)
+    om = f32(w.omega)
+    K = float(np.float32(w.K))
+    dt = float(np.float32(w.dt))
+    scale = K / g.n
+    deg = np.diff(g.row_ptr)[rows]
+    zero = np.zeros(g.n)
+    with Kuramoto("f32", device=0) as k:
+        k.autotune(g, effort=1, cache=cache)
+        dense = dense_term(k, g)[rows]
+        k.set_params(om, K)
+        k.set_phases(th0)
+        for n_done in range(0, 501, 100):
+            if n_done:
+                k.step_rk4(dt, 100)
+            th = f32(k.get_phases(wrapped=True))
+            r, _ = k.order_parameter()
+            F = k.eval_rhs(th)[rows]
+            k.set_params(zero, K)
+            G = k.eval_rhs(th)[rows]
+            k.set_params(om, K)
+            # set_params keeps the phase state; the next steps continue from it
+            Go = oracle.rhs_rows(g, zero, K, th, rows)
+            bound = 1e-5 * scale * (deg + dense)
+            assert np.all(np.abs(G - Go) <= bound), (n_done, np.max(np.abs(G - Go) / bound))
+            Fo = Go + om[rows]
+            assert np.all(np.abs(F - Fo) <= bound + 2.0 ** -24 * np.abs(Fo) + 1e-30), n_done
+            ro, _ = oracle.order_parameter(th)
+            assert abs(r - ro) < 1e-5, n_done
 
 
 def test_paper_four_communities(need_gpu):
