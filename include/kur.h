@@ -389,6 +389,21 @@ kur_status kur_step_adaptive(kur_ctx *ctx, double t_end, double dt0, double atol
  */
 kur_status kur_diagnostics(kur_ctx *ctx, double *out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * or monitoring loops, harnesses that forbid hipMalloc): kur_diagnostics with the same out[3],
+ * computed by the same kernels in the same order (equal bit for bit), but with its FP64 partial
+ * sums in a fixed scratch array of 1.5 MiB that every GPU the library runs on holds until the
+ * process ends, instead of memory allocated per call. It calls no hipMalloc or hipFree; the
+ * inputs and outputs are the context's own buffers and out. The scratch serves n <= 2^24
+ * (16777216) nodes: a larger graph returns KUR_EINVAL (use kur_diagnostics). All calls on one
+ * GPU share its scratch and it keeps the last call's contents (nothing in it has to start at
+ * zero); calls that overlap in time on one GPU race on it and must be serialised by the caller.
+ * The energy evaluation is not timed even with option "timing" (timing allocates events).
+ * Synchronous; KUR_EDEVICE if the scratch's device address could not be found.
+ */
+kur_status kur_diagnostics_noalloc(kur_ctx *ctx, double *out);
+
 /* Wait for all work enqueued on the context stream. */
 kur_status kur_sync(kur_ctx *ctx);
 

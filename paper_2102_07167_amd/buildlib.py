@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libkur.so")
-SOURCES = ["kur_kernels.hip", "ens_kernels.hip", "persist_kernels.hip", "io_kernels.hip", "kur_api.cpp", "graph_build.cpp", "autotune.cpp",
+SOURCES = ["kur_kernels.hip", "ens_kernels.hip", "persist_kernels.hip", "io_kernels.hip", "noalloc.hip", "kur_api.cpp", "graph_build.cpp", "autotune.cpp",
            "ensemble.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -15,6 +15,7 @@
 #include "kur_internal.hpp"
 #include "kur_io.hpp"
 #include "kur_kernels.hpp"
+#include "kur_noalloc.hpp"
 #include "kur_tune.hpp"
 
 using namespace kur;
@@ -664,6 +665,9 @@ kur_status kur_create(kur_ctx **out, kur_dtype dtype, int device, void *hip_stre
             delete c;
             return KUR_EDEVICE;
         }
+        // the device address of the fixed scratch of kur_diagnostics_noalloc (once per device;
+        // a failure shows up as KUR_EDEVICE from that call only)
+        (void)noalloc_scratch_init(device);
         if (hip_stream) {
             c->stream = (hipStream_t)hip_stream;
         } else {
@@ -1024,7 +1028,7 @@ kur_status kur_set_phases(kur_ctx *c, const double *theta)
     return KUR_OK;
 }
 
-static kur_status eval_common(kur_ctx *c, const void *y_dev, void *out_dev, int stage = 0)
+static kur_status eval_common(kur_ctx *c, const void *y_dev, void *out_dev, int stage = 0, bool timed = true)
 {
     kur_status s = sc_init(c, y_dev, c->d_sce, c->d_parte);
     if (s != KUR_OK) return s;
@@ -1035,13 +1039,13 @@ static kur_status eval_common(kur_ctx *c, const void *y_dev, void *out_dev, int 
         a.sc_in = c->d_sce.p;
         a.part_in = c->d_parte.p;
         a.kout = (float *)out_dev;
-        e = timed_rows(c, g, &a);
+        e = timed ? timed_rows(c, g, &a) : launch_rows<float>(g, c->ntiles, a, c->threads, c->stream);
     } else {
         RowArgs<double> a = row_args<double>(c, stage, 0.0);
         a.sc_in = c->d_sce.p;
         a.part_in = c->d_parte.p;
         a.kout = (double *)out_dev;
-        e = timed_rows(c, g, &a);
+        e = timed ? timed_rows(c, g, &a) : launch_rows<double>(g, c->ntiles, a, c->threads, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "rhs launch");
     return KUR_OK;
@@ -1180,6 +1184,31 @@ kur_status kur_stream(const kur_ctx *c, void **hip_stream)
     return KUR_OK;
 }
 
+// The diagnostics into out[0..3) with part (3 ceil(n / 256) doubles) and res (3 doubles) of
+// device scratch; timed: the energy evaluation is timed like other row-kernel launches.
+static kur_status diag_impl(kur_ctx *c, double *out, double *part, double *res, bool timed)
+{
+    const int64_t n = c->n;
+    kur_status s = eval_common(c, c->d_hi.p, c->d_kout.p, -1, timed);
+    if (s != KUR_OK) return s;
+    hipError_t e = c->esz == 4 ? launch_diag<float>(n, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, c->d_omega.p,
+                                                    c->d_unit.p, c->d_kout.p, c->K, part, res, c->stream)
+                               : launch_diag<double>(n, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, c->d_omega.p,
+                                                     c->d_unit.p, c->d_kout.p, c->K, part, res, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
+    double h[3];
+    if ((e = hipMemcpyAsync(h, res, 24, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+        return hip_fail(c, e, "diagnostics download");
+    // the constant of the potential, K/2 sum_m scale_m deg_m, from the host degrees
+    double cst = 0.0;
+    for (int64_t m = 0; m < n; ++m) cst += c->scaling ? (c->deg[m] > 0 ? 1.0 : 0.0) : (double)c->deg[m] / (double)n;
+    out[0] = h[2] + 0.5 * c->K * cst;
+    out[1] = h[0] / (double)n;
+    out[2] = h[1] / (double)n;
+    return KUR_OK;
+}
+
 kur_status kur_diagnostics(kur_ctx *c, double *out)
 {
     if (!c) return KUR_EINVAL;
@@ -1190,8 +1219,7 @@ kur_status kur_diagnostics(kur_ctx *c, double *out)
     if (c->batch) return fail(c, KUR_ESTATE, "diagnostics are defined per system, not for a batch");
     DevBuf part, res;
     hipError_t e;
-    const int64_t n = c->n;
-    const int64_t nchunk = (n + 255) / 256;
+    const int64_t nchunk = (c->n + 255) / 256;
     if ((e = dalloc(part, 24 * (size_t)nchunk)) != hipSuccess || (e = dalloc(res, 24)) != hipSuccess)
         return hip_fail(c, e, "diagnostics buffers");
     struct Release {
@@ -1202,23 +1230,24 @@ kur_status kur_diagnostics(kur_ctx *c, double *out)
             dfree(*b);
         }
     } rel{&part, &res};
-    if ((s = eval_common(c, c->d_hi.p, c->d_kout.p, -1)) != KUR_OK) return s;
-    e = c->esz == 4 ? launch_diag<float>(n, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, c->d_omega.p, c->d_unit.p,
-                                         c->d_kout.p, c->K, (double *)part.p, (double *)res.p, c->stream)
-                    : launch_diag<double>(n, c->d_hi.p, c->d_lo.p, (const int32_t *)c->d_wind.p, c->d_omega.p,
-                                          c->d_unit.p, c->d_kout.p, c->K, (double *)part.p, (double *)res.p, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
-    double h[3];
-    if ((e = hipMemcpyAsync(h, res.p, 24, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
-        return hip_fail(c, e, "diagnostics download");
-    // the constant of the potential, K/2 sum_m scale_m deg_m, from the host degrees
-    double cst = 0.0;
-    for (int64_t m = 0; m < n; ++m) cst += c->scaling ? (c->deg[m] > 0 ? 1.0 : 0.0) : (double)c->deg[m] / (double)n;
-    out[0] = h[2] + 0.5 * c->K * cst;
-    out[1] = h[0] / (double)n;
-    out[2] = h[1] / (double)n;
-    return KUR_OK;
+    return diag_impl(c, out, (double *)part.p, (double *)res.p, true);
+}
+
+kur_status kur_diagnostics_noalloc(kur_ctx *c, double *out)
+{
+    if (!c) return KUR_EINVAL;
+    c->err.clear();
+    if (!out) return fail(c, KUR_EINVAL, "out must not be NULL");
+    kur_status s = need_ready(c, true, true);
+    if (s != KUR_OK) return s;
+    if (c->batch) return fail(c, KUR_ESTATE, "diagnostics are defined per system, not for a batch");
+    if (c->n > kNoAllocMaxN)
+        return fail(c, KUR_EINVAL, "kur_diagnostics_noalloc: n = " + std::to_string(c->n) +
+                                       " exceeds its fixed scratch (at most " + std::to_string(kNoAllocMaxN) +
+                                       " nodes); use kur_diagnostics");
+    double *scr = (double *)noalloc_scratch(c->device);
+    if (!scr) return fail(c, KUR_EDEVICE, "the fixed scratch of this device could not be located");
+    return diag_impl(c, out, scr, scr + noalloc_totals_offset(), false);
 }
 
 static hipError_t launch_sample(kur_ctx *c, const int64_t *idx_dev, int64_t idx)

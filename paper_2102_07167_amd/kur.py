@@ -79,6 +79,7 @@ SIGNATURES = {
     "kur_ens_kernel_time": (ST, [P, P]),
     "kur_ens_autotune_csr": (ST, [P, I64, P, P, P, I32, I32, P]),
     "kur_diagnostics": (ST, [P, P]),
+    "kur_diagnostics_noalloc": (ST, [P, P]),
     "kur_step_midpoint": (ST, [P, F64, I64, I32, I64, P, P]),
     "kur_step_adaptive": (ST, [P, F64, F64, F64, I64, P]),
     "kur_stream": (ST, [P, ctypes.POINTER(P)]),
@@ -384,6 +385,12 @@ class Kuramoto:
         """Potential V, mean unwrapped phase and mean omega of the current state (kur_diagnostics)."""
         out = np.zeros(3)
         self._chk(self._L.kur_diagnostics(self._h, _ptr(out)))
+        return {"V": out[0], "mean_theta": out[1], "mean_omega": out[2]}
+
+    def diagnostics_noalloc(self) -> dict:
+        """kur_diagnostics_noalloc: the diagnostics without any device allocation (fixed scratch)."""
+        out = np.zeros(3)
+        self._chk(self._L.kur_diagnostics_noalloc(self._h, _ptr(out)))
         return {"V": out[0], "mean_theta": out[1], "mean_omega": out[2]}
 
     def recorded_run(self):
