@@ -78,6 +78,9 @@ struct kur_ctx {
     // device state
     DevBuf d_omega, d_unit, d_hi, d_lo, d_wind, d_ksum, d_sc[2], d_part[2], d_sce, d_parte, d_kout, d_y;
     DevBuf d_r, d_psi;
+    DevBuf d_yb[2];  // stage inputs y of RK4 stages 2..4 (option "inter_gather" = 1)
+    int inter_gather = 1;  // 1: inter-block gathers read the phase and form (sin, cos); 0: the pair
+                           // (default 1 for FP32, 0 for FP64)
     DevBuf d_perm;   // user node -> block-order row, for the device-pointer calls
     DevBuf d_opart;  // FP64 partials of the order parameter of a device phase vector
     AdjBufs adj;     // adjoint work buffers
@@ -208,7 +211,8 @@ void free_all(kur_ctx *c)
                       &c->d_sc[1], &c->d_part[0], &c->d_part[1], &c->d_sce, &c->d_parte, &c->d_kout, &c->d_y,
                       &c->d_r, &c->d_psi, &c->d_tile_first, &c->d_inv_n, &c->d_ctr, &c->d_ck,
                       &c->d_blkT, &c->d_segdT, &c->d_grpT, &c->d_tilesT, &c->d_orderT, &c->d_segT,
-                      &c->d_listT, &c->d_iptrT, &c->d_icolT, &c->d_rsc, &c->d_rac, &c->d_perm, &c->d_opart};
+                      &c->d_listT, &c->d_iptrT, &c->d_icolT, &c->d_rsc, &c->d_rac, &c->d_perm, &c->d_opart,
+                      &c->d_yb[0], &c->d_yb[1]};
     for (DevBuf *b : bufs) dfree(*b);
     free_adj(c->adj);
     c->has_T = false;
@@ -362,6 +366,8 @@ RowArgs<T> row_args(kur_ctx *c, int stage, double dt)
     a.sc_out = c->d_sc[c->cur ^ 1].p;
     a.part_out = c->d_part[c->cur ^ 1].p;
     a.ac_out = nullptr;
+    a.y_in = nullptr;
+    a.y_out = nullptr;
     return a;
 }
 
@@ -466,7 +472,8 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
             (e = dalloc(c->d_part[1], 2 * T * g.tiles.size())) != hipSuccess ||
             (e = dalloc(c->d_parte, 2 * T * g.tiles.size())) != hipSuccess ||
             (e = dalloc(c->d_kout, T * n)) != hipSuccess || (e = dalloc(c->d_y, T * n)) != hipSuccess ||
-            (e = upload(c->d_perm, g.perm.data(), sizeof(int32_t) * n, c->stream)) != hipSuccess) {
+            (e = upload(c->d_perm, g.perm.data(), sizeof(int32_t) * n, c->stream)) != hipSuccess ||
+            (e = dalloc(c->d_yb[0], T * n)) != hipSuccess || (e = dalloc(c->d_yb[1], T * n)) != hipSuccess) {
             free_all(c);
             c->has_graph = false;
             return hip_fail(c, e, "graph upload");
@@ -652,6 +659,9 @@ kur_status kur_create(kur_ctx **out, kur_dtype dtype, int device, void *hip_stre
         c->bopt.esz2 = 16;
         c->bopt.W = (int32_t)((65535 / c->bopt.esz2) / 64 * 64);
     }
+    // FP32: the inter-block gathers read 4-byte phases (half the cache footprint of the pairs);
+    // FP64 keeps the pair gathers (its sin/cos would cost occupancy)
+    c->inter_gather = dtype == KUR_F32 ? 1 : 0;
     c->device = device;
     c->host_only = device < 0;
     if (!c->host_only) {
@@ -753,6 +763,10 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
     } else if (k == "compensate") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "compensate must be 0 or 1");
         c->compensate = (int)v;
+        c->gen++;
+    } else if (k == "inter_gather") {
+        if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "inter_gather must be 0 or 1");
+        c->inter_gather = (int)v;
         c->gen++;
     } else if (k == "adjoint_keep") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "adjoint_keep must be 0 or 1");
@@ -1039,12 +1053,14 @@ static kur_status eval_common(kur_ctx *c, const void *y_dev, void *out_dev, int 
         a.sc_in = c->d_sce.p;
         a.part_in = c->d_parte.p;
         a.kout = (float *)out_dev;
+        if (c->inter_gather) a.y_in = (const float *)y_dev;
         e = timed ? timed_rows(c, g, &a) : launch_rows<float>(g, c->ntiles, a, c->threads, c->stream);
     } else {
         RowArgs<double> a = row_args<double>(c, stage, 0.0);
         a.sc_in = c->d_sce.p;
         a.part_in = c->d_parte.p;
         a.kout = (double *)out_dev;
+        if (c->inter_gather) a.y_in = (const double *)y_dev;
         e = timed ? timed_rows(c, g, &a) : launch_rows<double>(g, c->ntiles, a, c->threads, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "rhs launch");
@@ -1266,6 +1282,9 @@ static hipError_t launch_step(kur_ctx *c, const DevGraph &g, double dt, char *rs
                               int64_t step = 0)
 {
     const size_t P = 2 * (size_t)c->esz * (size_t)c->n;
+    // stage inputs for the phase gathers: theta (hi), then y2, y3, y4 alternating in two buffers
+    void *yin[4] = {c->d_hi.p, c->d_yb[0].p, c->d_yb[1].p, c->d_yb[0].p};
+    void *yout[4] = {c->d_yb[0].p, c->d_yb[1].p, c->d_yb[0].p, nullptr};
     for (int stage = 1; stage <= 4; ++stage) {
         hipError_t e;
         const int64_t i = 4 * step + stage;
@@ -1276,6 +1295,10 @@ static hipError_t launch_step(kur_ctx *c, const DevGraph &g, double dt, char *rs
                 a.sc_out = rsc + (size_t)i * P;
                 a.ac_out = rac + (size_t)(i - 1) * P;
             }
+            if (c->inter_gather) {
+                a.y_in = (const float *)yin[stage - 1];
+                a.y_out = (float *)yout[stage - 1];
+            }
             e = timed_rows(c, g, &a);
         } else {
             RowArgs<double> a = row_args<double>(c, stage, dt);
@@ -1283,6 +1306,10 @@ static hipError_t launch_step(kur_ctx *c, const DevGraph &g, double dt, char *rs
                 a.sc_in = rsc + (size_t)(i - 1) * P;
                 a.sc_out = rsc + (size_t)i * P;
                 a.ac_out = rac + (size_t)(i - 1) * P;
+            }
+            if (c->inter_gather) {
+                a.y_in = (const double *)yin[stage - 1];
+                a.y_out = (double *)yout[stage - 1];
             }
             e = timed_rows(c, g, &a);
         }

@@ -28,6 +28,19 @@ namespace kur {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Cache policy of the list stream's buffer loads (bit 0 sc0, bit 1 nt, bit 4 sc1): non-temporal,
+// the lists are read once per launch.
+#ifndef KUR_LIST_CPOL
+#define KUR_LIST_CPOL 2
+#endif
+
+// 16-byte vector i of a list segment addressed by a buffer resource (the segment's base and
+// byte length; a vector past the end reads as zero).
+__device__ __forceinline__ u32x4 list_load(__amdgpu_buffer_rsrc_t r, uint32_t i)
+{
+    return __builtin_amdgcn_raw_buffer_load_b128(r, (int)(i * 16u), 0, KUR_LIST_CPOL);
+}
+
 
 // Sum v over the workgroup in a fixed order and store it to *out (thread 0).
 template <typename VT, int NT>
@@ -163,11 +176,13 @@ struct TileLds {
 // and fold into L.red[NT/64] the localised order parameters of the row block's column groups,
 // sum_q mode_q (sum of x over column block q), from the tile partials of each column block.
 // Ends with a barrier; the complete row sum is then (ngrp ? L.red[NT/64] : 0) + acc[r].
-template <typename T, int NT>
+// YG: the inter-block gathers read the phase y_l from y_in (half the bytes of a value pair, so
+// twice the table fits a cache) and form (sin y_l, cos y_l), which equals x_in[l] bit for bit.
+template <typename T, int NT, bool YG = false>
 __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, const BlkInfo &bi,
                                             const typename V2<T>::type *__restrict__ x_in,
                                             const typename V2<T>::type *__restrict__ part_in,
-                                            TileLds<typename V2<T>::type, NT> &L)
+                                            TileLds<typename V2<T>::type, NT> &L, const T *__restrict__ y_in = nullptr)
 {
     using VT = typename V2<T>::type;
     const int W = g.W;
@@ -257,13 +272,15 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
         // row starts of this chunk, in 8-entry vectors relative to the tile's first one
         for (int r = threadIdx.x; r <= nrows; r += NT) L.bnd[r] = (int)((g.seg_ptr[sb + tl.r0 + r] - e0) >> 3);
         __syncthreads();
-        const u32x4 *__restrict__ Lt = reinterpret_cast<const u32x4 *>(g.list + e0);
+        // the tile's list vectors of this chunk, [e0, e1) entries
+        const __amdgpu_buffer_rsrc_t Lt =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(g.list + e0), (short)0, (int)((e1 - e0) * 2), 0x00020000);
         if (flat) {
             // rows [ra, rb) occupy the contiguous 8-entry vectors [va, va + nvec) of this chunk
             const int va = __builtin_amdgcn_readfirstlane(L.bnd[ra]);
             const int nvec = __builtin_amdgcn_readfirstlane(L.bnd[rb]) - va;
             if (nvec > 0) {
-                const u32x4 *__restrict__ Lv = Lt + va;
+                const uint32_t vb = (uint32_t)va;
                 int r = ra;
                 int nbnd = __builtin_amdgcn_readfirstlane(L.bnd[r + 1]) - va;  // first vector after row r
                 VT acc = vzero<VT>();
@@ -271,10 +288,10 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
                 // unconditionally (index clamped) so the in-order wait counts stay exact, and
                 // lanes past the end are masked after the gather
                 const uint32_t last = (uint32_t)(nvec - 1);
-                u32x4 q0 = __builtin_nontemporal_load(Lv + min((uint32_t)ln, last));
-                u32x4 q1 = __builtin_nontemporal_load(Lv + min((uint32_t)(64 + ln), last));
-                u32x4 q2 = __builtin_nontemporal_load(Lv + min((uint32_t)(128 + ln), last));
-                u32x4 q3 = __builtin_nontemporal_load(Lv + min((uint32_t)(192 + ln), last));
+                u32x4 q0 = list_load(Lt, vb + min((uint32_t)ln, last));
+                u32x4 q1 = list_load(Lt, vb + min((uint32_t)(64 + ln), last));
+                u32x4 q2 = list_load(Lt, vb + min((uint32_t)(128 + ln), last));
+                u32x4 q3 = list_load(Lt, vb + min((uint32_t)(192 + ln), last));
                 auto span = [&](const u32x4 q, const int s0) {
                     VT p = vzero<VT>();
                     gather8(L.xs, q, p);
@@ -295,29 +312,28 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
                 };
                 for (int s0 = 0; s0 < nvec; s0 += 256) {
                     span(q0, s0);
-                    q0 = __builtin_nontemporal_load(Lv + min((uint32_t)(s0 + 256 + ln), last));
+                    q0 = list_load(Lt, vb + min((uint32_t)(s0 + 256 + ln), last));
                     span(q1, s0 + 64);
-                    q1 = __builtin_nontemporal_load(Lv + min((uint32_t)(s0 + 320 + ln), last));
+                    q1 = list_load(Lt, vb + min((uint32_t)(s0 + 320 + ln), last));
                     span(q2, s0 + 128);
-                    q2 = __builtin_nontemporal_load(Lv + min((uint32_t)(s0 + 384 + ln), last));
+                    q2 = list_load(Lt, vb + min((uint32_t)(s0 + 384 + ln), last));
                     span(q3, s0 + 192);
-                    q3 = __builtin_nontemporal_load(Lv + min((uint32_t)(s0 + 448 + ln), last));
+                    q3 = list_load(Lt, vb + min((uint32_t)(s0 + 448 + ln), last));
                 }
             }
         } else {
             for (int r = grp; r < nrows; r += ngrp) {
                 const int v0 = L.bnd[r];
-                const u32x4 *__restrict__ p = Lt + v0;
                 const int nv = L.bnd[r + 1] - v0;
                 VT acc = vzero<VT>();
                 int v = lane;
                 for (; v + G < nv; v += 2 * G) {
-                    const u32x4 qa = __builtin_nontemporal_load(p + v);
-                    const u32x4 qb = __builtin_nontemporal_load(p + v + G);
+                    const u32x4 qa = list_load(Lt, (uint32_t)(v0 + v));
+                    const u32x4 qb = list_load(Lt, (uint32_t)(v0 + v + G));
                     gather8(L.xs, qa, acc);
                     gather8(L.xs, qb, acc);
                 }
-                if (v < nv) gather8(L.xs, __builtin_nontemporal_load(p + v), acc);
+                if (v < nv) gather8(L.xs, list_load(Lt, (uint32_t)(v0 + v)), acc);
                 acc = vgroup_sum_dpp(acc, G);
                 if (lane == G - 1) vacc(L.acc[r], vscale(acc, sign));
             }
@@ -342,8 +358,21 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
 #pragma unroll
             for (int u = 0; u < U; ++u) col[u] = g.inter_col[i0 + min(base + u * NT + (int)threadIdx.x, end - 1)];
             VT v[U];
+            if constexpr (YG) {
+                T yv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = x_in[col[u]];
+                for (int u = 0; u < U; ++u) yv[u] = y_in[col[u]];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    T sn, cs;
+                    dev_sincos<T>(yv[u], &sn, &cs);
+                    v[u].x = sn;
+                    v[u].y = cs;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) v[u] = x_in[col[u]];
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = base + u * NT + (int)threadIdx.x;
@@ -377,7 +406,7 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
 
 // Right-hand side and classical RK4 stage bookkeeping, one tile per workgroup. Eight waves
 // per SIMD in FP32 (64 VGPRs); FP64 gets more registers and no scratch at six.
-template <typename T, int NT>
+template <typename T, int NT, bool YG>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_rows(DevGraph g, RowArgs<T> a)
 {
     using T2 = typename V2<T>::type;
@@ -391,7 +420,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int rowbase = bi.row0 + tl.r0;
     const T2 *__restrict__ sc_in = reinterpret_cast<const T2 *>(a.sc_in);
 
-    tile_gather<T, NT>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L);
+    tile_gather<T, NT, YG>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L, a.y_in);
 
     T2 base = vzero<T2>();
     if (bi.ngrp) base = L.red[NT / 64];
@@ -423,6 +452,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         }
         const T y = rk4_stage<T>(a.stage, k, a.dt, a.half_dt, a.dt6, a.compensate, a.ksum + m, a.hi + m, a.lo + m,
                                  a.wind + m);
+        if (YG && a.y_out) a.y_out[m] = y;
         T s, c;
         dev_sincos<T>(y, &s, &c);
         T2 v;
@@ -794,20 +824,32 @@ hipError_t launch_rows(const DevGraph &g, int ntiles, const RowArgs<T> &a, int t
 {
     if (ntiles <= 0) return hipSuccess;
     const size_t lds = rows_lds_bytes(sizeof(T), g.W, g.tile_rows, threads);
-    static bool attr_done[3] = {false, false, false};
-    const int slot = threads == 256 ? 0 : threads == 1024 ? 2 : 1;
+    static bool attr_done[6] = {false, false, false, false, false, false};
+    const bool yg = a.y_in != nullptr;
+    const int slot = (threads == 256 ? 0 : threads == 1024 ? 2 : 1) + (yg ? 3 : 0);
     if (!attr_done[slot]) {
-        const void *fn = threads == 256 ? reinterpret_cast<const void *>(&k_rows<T, 256>)
-                         : threads == 1024 ? reinterpret_cast<const void *>(&k_rows<T, 1024>)
-                                           : reinterpret_cast<const void *>(&k_rows<T, 512>);
+        const void *fn = yg ? (threads == 256    ? reinterpret_cast<const void *>(&k_rows<T, 256, true>)
+                               : threads == 1024 ? reinterpret_cast<const void *>(&k_rows<T, 1024, true>)
+                                                 : reinterpret_cast<const void *>(&k_rows<T, 512, true>))
+                            : (threads == 256    ? reinterpret_cast<const void *>(&k_rows<T, 256, false>)
+                               : threads == 1024 ? reinterpret_cast<const void *>(&k_rows<T, 1024, false>)
+                                                 : reinterpret_cast<const void *>(&k_rows<T, 512, false>));
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         if (e != hipSuccess) return e;
         attr_done[slot] = true;
     }
-    switch (threads) {
-    case 256: hipLaunchKernelGGL((k_rows<T, 256>), dim3(g.nlaunch), dim3(256), lds, st, g, a); break;
-    case 1024: hipLaunchKernelGGL((k_rows<T, 1024>), dim3(g.nlaunch), dim3(1024), lds, st, g, a); break;
-    default: hipLaunchKernelGGL((k_rows<T, 512>), dim3(g.nlaunch), dim3(512), lds, st, g, a); break;
+    if (yg) {
+        switch (threads) {
+        case 256: hipLaunchKernelGGL((k_rows<T, 256, true>), dim3(g.nlaunch), dim3(256), lds, st, g, a); break;
+        case 1024: hipLaunchKernelGGL((k_rows<T, 1024, true>), dim3(g.nlaunch), dim3(1024), lds, st, g, a); break;
+        default: hipLaunchKernelGGL((k_rows<T, 512, true>), dim3(g.nlaunch), dim3(512), lds, st, g, a); break;
+        }
+    } else {
+        switch (threads) {
+        case 256: hipLaunchKernelGGL((k_rows<T, 256, false>), dim3(g.nlaunch), dim3(256), lds, st, g, a); break;
+        case 1024: hipLaunchKernelGGL((k_rows<T, 1024, false>), dim3(g.nlaunch), dim3(1024), lds, st, g, a); break;
+        default: hipLaunchKernelGGL((k_rows<T, 512, false>), dim3(g.nlaunch), dim3(512), lds, st, g, a); break;
+        }
     }
     return hipGetLastError();
 }

@@ -45,6 +45,10 @@ struct RowArgs {
     const void *part_in;
     void *part_out;
     void *ac_out;       // stages 1..4: if not null, ((A sin y)_m, (A cos y)_m) of the stage input
+    const T *y_in;      // if not null: the stage input y itself; the inter-block gathers then read
+                        // y_l and form (sin y_l, cos y_l) (the same values as sc_in) instead of
+                        // reading the pair
+    T *y_out;           // stages 1..3: if not null, receives the next stage input y
 };
 
 // Arguments of one stage of the embedded Runge-Kutta pair (variable step size). Stage i of s
