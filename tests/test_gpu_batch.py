@@ -106,19 +106,54 @@ def test_complete_graph_70000(need_gpu):
     assert np.abs(F[rows] - Fo).max() < 1e-12 * np.abs(Fo).max()
 
 
+def load_batch_fixture():
+    """{batch index: (n, K, r samples, rows, theta(T), sensitivity)} written by
+    tests/golden/make_batch_sbm_instances.py (oracle only)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_sbm_instances_rk4_2000.txt")
+    out, cur = {}, None
+    with open(path) as f:
+        for line in f:
+            p = line.split()
+            if not p or p[0].startswith("#"):
+                continue
+            if p[0] == "instance":
+                cur = int(p[1])
+                out[cur] = [int(p[2]), float(p[3]), [], [], [], []]
+            elif p[0] == "r":
+                out[cur][2].append(float(p[2]))
+            elif p[0] == "theta":
+                out[cur][3].append(int(p[1]))
+                out[cur][4].append(float(p[2]))
+                out[cur][5].append(float(p[3]))
+    return {i: (v[0], v[1], np.array(v[2]), np.array(v[3], dtype=np.int64), np.array(v[4]), np.array(v[5]))
+            for i, v in out.items()}
+
+
 def test_batch_ensemble_full_size(need_gpu):
     """The full ensemble: 256 instances, N log-uniform in [1024, 65536], all-to-all or SBM,
     K = linspace(0, 6, 256), 2000 RK4 steps of dt 0.01 in FP32, r every 10 steps. Checked by
     properties that hold at any size (per-instance conservation, free rotation at K = 0, r(0)
-    of every instance) and by the oracle trajectory of the smallest all-to-all instance (FP32
-    bound 2e-5 after 2000 steps: the 1e-5 bound stated for 1000 steps, doubled)."""
+    of every instance), by the oracle trajectory of the smallest all-to-all instance and by the
+    oracle trajectories (stored in tests/golden/) of the two smallest SBM instances and the
+    smallest one above 16000 nodes: r every 10 steps within the FP32 bound 2e-5 after 2000 steps
+    (the 1e-5 bound stated for 1000 steps, doubled), and every stored phase within 2e-5 plus
+    eight times its stored sensitivity (how far the oracle's own theta(T) moves when the inputs
+    move by FP32 rounding: drifting oscillators of a partially synchronised instance amplify
+    every rounding of the FP32 run). The union's per-instance
+    offsets (blocks, tiles, inter-block lists) are checked at the final state by the right-hand
+    side of sampled rows of the first, middle and last SBM instances against the oracle."""
     keep = []
+    graphs = {}
+    fixture = load_batch_fixture()
 
     def feed():
-        for w in gen.batch_instances_iter():
+        for i, w in enumerate(gen.batch_instances_iter()):
             om = w.omega.astype(np.float32).astype(np.float64)
             th = w.theta0.astype(np.float32).astype(np.float64)
             keep.append((w.graph.n, w.meta["kind"], w.K, om, th))
+            if w.meta["kind"] == "sbm":
+                graphs[i] = w.graph
             yield w.graph, w.K, om, th
     dt, steps = 0.01, 2000
     with Kuramoto("f32", device=0) as k:
@@ -126,6 +161,9 @@ def test_batch_ensemble_full_size(need_gpu):
         rf = k.batch_info()
         r, _ = k.batch_step(dt, steps, 10)
         th_all = k.get_phases()
+        # the union's right-hand side at its final (FP32-rounded) phases
+        th_x = th_all.astype(np.float32).astype(np.float64)
+        F_all = k.eval_rhs(th_x)
     T = steps * dt
     assert r.shape == (steps // 10 + 1, 256) and np.isfinite(r).all()
     for i, (n, kind, K, om, th0) in enumerate(keep):
@@ -147,6 +185,27 @@ def test_batch_ensemble_full_size(need_gpu):
     Kf = float(np.float32(K))
     tho, _, _ = oracle.rk4(gen.complete_graph(n), om, Kf, th0, float(np.float32(dt)), steps)
     assert np.abs(wrap(th_all[rf[i]:rf[i + 1]] - tho)).max() < 2e-5
+    # stored oracle trajectories of SBM instances
+    assert len(fixture) == 3 and max(v[0] for v in fixture.values()) > 16000
+    for i, (n, K, ro, rows, tho, sens) in fixture.items():
+        assert keep[i][1] == "sbm" and keep[i][0] == n and abs(K - float(np.float32(keep[i][2]))) == 0.0
+        err = np.abs(wrap(th_all[rf[i]:rf[i + 1]][rows] - tho))
+        assert np.all(err <= 2e-5 + 8 * sens), (i, np.max(err - 8 * sens))
+        assert np.abs(r[:, i] - ro).max() < 2e-5, i
+    # per-instance offsets of the union: its right-hand side on sampled rows of the first, middle
+    # and last SBM instances at the final phases (every block of these instances is dense, so the
+    # FP32 bound carries the 2 s_b term on every row)
+    sbm_ids = sorted(graphs)
+    for i in (sbm_ids[0], sbm_ids[len(sbm_ids) // 2], sbm_ids[-1]):
+        n, kind, K, om, th0 = keep[i]
+        g = graphs[i]
+        thT = th_x[rf[i]:rf[i + 1]]
+        rows = np.sort(np.random.default_rng(i).choice(n, min(n, 256), replace=False))
+        F = F_all[rf[i]:rf[i + 1]][rows]
+        Fo = oracle.rhs_rows(g, om, K, thT, rows)
+        _, inv, cnt = np.unique(g.labels, return_inverse=True, return_counts=True)
+        bound = 1e-5 * (K / n) * (np.diff(g.row_ptr)[rows] + 2 * cnt[inv][rows]) + 1e-6 * np.abs(om[rows]) + 1e-7
+        assert np.all(np.abs(F - Fo) <= bound), i
 
 
 def test_batch_with_dense_offdiagonal_blocks(need_gpu):
