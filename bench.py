@@ -463,18 +463,27 @@ def main():
         k.set_option("checkpoint_every", 0)
         k.set_option("record_stages", 0)
         t_bwd_st, (gt3, gw3, gk3) = timed(lambda: k.adjoint_recorded(seed))
-        assert np.array_equal(gt, gt3) and np.array_equal(gw, gw3) and gk == gk3
+        # a small complete graph runs the adjoint (and its checkpointed forward) in one workgroup;
+        # the stage record comes from the row kernel, whose sums run in another order
+        one_wg = getattr(w.graph, "complete", False) and w.graph.n <= 1024
+        if one_wg:
+            tol = 1e-9 * max(np.abs(gt).max(), np.abs(gw).max())
+            assert np.abs(gt - gt3).max() <= tol and np.abs(gw - gw3).max() <= tol
+        else:
+            assert np.array_equal(gt, gt3) and np.array_equal(gw, gw3) and gk == gk3
         out["adjoint"] = {"steps": na, "ckpt_every": ck, "fwd_ms": 1e3 * t_fwd, "fwd_checkpointed_ms": 1e3 * t_fwd_ck,
                           "backward_ms": 1e3 * t_bwd, "ratio": t_bwd / t_fwd,
                           "adjoint_with_forward_ms": 1e3 * t_full, "ratio_with_forward": t_full / t_fwd,
                           "fwd_recording_stages_ms": 1e3 * t_fwd_st, "backward_from_stages_ms": 1e3 * t_bwd_st,
                           "ratio_from_stages": t_bwd_st / t_fwd,
                           "stage_record_gb": 16 * elem * w.graph.n * na / 1e9,
+                          "one_workgroup": bool(one_wg),
                           "note": "ratio = backward (recompute per segment + 4 VJP stages per step, using the "
                                   "forward run's checkpoints) / plain forward; ratio_with_forward also repeats the "
                                   "forward; ratio_from_stages = backward from a forward run that kept every stage "
-                                  "state (option record_stages, no recompute) / plain forward; all three give the "
-                                  "same gradients bit for bit"}
+                                  "state (option record_stages, no recompute) / plain forward; the first two give "
+                                  "the same gradients bit for bit, and so does the third unless one_workgroup (a "
+                                  "small complete graph, whose adjoint runs in one workgroup per launch)"}
         log("adjoint %d steps: backward %.1f ms, with forward %.1f ms, from recorded stages %.1f ms, forward %.1f ms "
             "(ratios %.2f / %.2f / %.2f)" % (na, 1e3 * t_bwd, 1e3 * t_full, 1e3 * t_bwd_st, 1e3 * t_fwd,
                                              t_bwd / t_fwd, t_full / t_fwd, t_bwd_st / t_fwd))

@@ -602,9 +602,11 @@ kur_status install_transpose(kur_ctx *c, int64_t n, const int64_t *row_ptr, cons
 
 // The run of a small complete graph in one workgroup (k_persist_complete), in launches of at
 // most about 65536 steps (whole sampling periods) so that no launch holds the device for long;
-// leaves the (sin, cos) of the state to be rebuilt by the next call that needs them.
+// leaves the (sin, cos) of the state to be rebuilt by the next call that needs them. ck (null:
+// none) receives (hi, lo) before every step that is a multiple of ck_every.
 template <typename T>
-hipError_t run_persistent(kur_ctx *c, double dt, int64_t nsteps, int64_t r_every)
+hipError_t run_persistent(kur_ctx *c, double dt, int64_t nsteps, int64_t r_every, T *ck = nullptr,
+                          int64_t ck_every = 1)
 {
     PersistArgs<T> a;
     a.n = c->n;
@@ -620,9 +622,12 @@ hipError_t run_persistent(kur_ctx *c, double dt, int64_t nsteps, int64_t r_every
     a.hi = (T *)c->d_hi.p;
     a.lo = (T *)c->d_lo.p;
     a.wind = (int32_t *)c->d_wind.p;
+    a.ck = ck;
+    a.ck_every = ck_every;
     const int64_t chunk = r_every > 0 ? std::max<int64_t>(1, 65536 / r_every) * r_every : 65536;
     int64_t done = 0;
     do {
+        a.step0 = done;
         a.nsteps = std::min(chunk, nsteps - done);
         a.final_sample = done + a.nsteps == nsteps;  // else the next launch's step 0 is that sample
         a.r_out = (double *)c->d_r.p + (r_every > 0 ? done / r_every : 0);
@@ -1363,13 +1368,38 @@ static kur_status run_steps(kur_ctx *c, double dt, int64_t nsteps, int64_t r_eve
             (e = dalloc(c->d_psi, sizeof(double) * nsamp * c->n_inst)) != hipSuccess)
             return hip_fail(c, e, "r buffer");
     }
-    // a small complete graph without checkpoints or kernel timing: one launch for the whole run
-    if (c->complete_graph && c->persistent && !c->batch && c->ckpt_every == 0 && !c->timing &&
+    // a small complete graph without kernel timing or a stage record: one launch for the whole
+    // run (checkpoints for the adjoint written by the same launch)
+    if (c->complete_graph && c->persistent && !c->batch && !(c->ckpt_every > 0 && c->record_stages) && !c->timing &&
         c->n <= (int64_t)kPersistThreads * kPersistMaxRows) {
-        if (nsteps == 0 && r_every == 0) return KUR_OK;
-        e = c->esz == 4 ? run_persistent<float>(c, dt, nsteps, r_every) : run_persistent<double>(c, dt, nsteps, r_every);
-        if (e != hipSuccess) return hip_fail(c, e, "persistent rk4 launch");
-        c->sc_valid = false;
+        const int64_t C = c->ckpt_every;
+        void *ck = nullptr;
+        if (C > 0) {
+            const int64_t nseg = nsteps > 0 ? (nsteps + C - 1) / C : 0;
+            c->rec_valid = false;
+            c->rec_stages = false;
+            if ((e = dalloc(c->d_ck, 2 * (size_t)c->esz * (size_t)c->n * (size_t)std::max<int64_t>(nseg, 1))) !=
+                hipSuccess)
+                return hip_fail(c, e, "checkpoints");
+            dfree(c->d_rsc);  // a previous stage record
+            dfree(c->d_rac);
+            ck = c->d_ck.p;
+        }
+        if (nsteps > 0 || r_every > 0) {
+            e = c->esz == 4 ? run_persistent<float>(c, dt, nsteps, r_every, (float *)ck, C > 0 ? C : 1)
+                            : run_persistent<double>(c, dt, nsteps, r_every, (double *)ck, C > 0 ? C : 1);
+            if (e != hipSuccess) return hip_fail(c, e, "persistent rk4 launch");
+            c->sc_valid = false;
+        }
+        if (C > 0) {
+            c->rec_valid = true;
+            c->rec_stages = false;
+            c->rec_dt = dt;
+            c->rec_nsteps = nsteps;
+            c->rec_C = C;
+            c->rec_gen = c->gen;
+            c->rec_serial++;
+        }
         return KUR_OK;
     }
     if (!c->sc_valid) {
@@ -1872,6 +1902,10 @@ kur_status adjoint_impl(kur_ctx *c, const AdjIO &io, const void *ck_ext, double 
     // asymmetric A: the Jacobian-transpose gathers run over the layout of A^T (its own tiles)
     const bool asym = !c->symmetric;
     const int ntv = asym ? c->ntT : nt;
+    // small complete graphs: the whole adjoint in one workgroup per launch (k_persist_adjoint),
+    // with the forward pass in the one-workgroup RK4 run; dK partials per thread of it
+    const bool pers = c->complete_graph && c->persistent && n <= (int64_t)kPersistThreads * kPersistMaxRows && !stored;
+    const int ngk = pers ? kPersistThreads : ntv;
     AdjBufs &B = c->adj;
     hipError_t e;
     if ((e = dalloc(B.hi, TN)) != hipSuccess || (e = dalloc(B.lo, TN)) != hipSuccess ||
@@ -1884,7 +1918,7 @@ kur_status adjoint_impl(kur_ctx *c, const AdjIO &io, const void *ck_ext, double 
         (e = dalloc(B.xpart[0], 2 * sizeof(T) * ntv)) != hipSuccess || (e = dalloc(B.xpart[1], 2 * sizeof(T) * ntv)) != hipSuccess ||
         (e = dalloc(B.lam, TN)) != hipSuccess || (e = dalloc(B.lam_acc, TN)) != hipSuccess ||
         (e = dalloc(B.lbuf, TN)) != hipSuccess || (e = dalloc(B.gom, 8 * (size_t)n)) != hipSuccess ||
-        (e = dalloc(B.gk, 8 * (size_t)ntv)) != hipSuccess)
+        (e = dalloc(B.gk, 8 * (size_t)ngk)) != hipSuccess)
         return hip_fail(c, e, "adjoint buffers");
 
     // initial phases (block order), split as in kur_set_phases; the seed dL/dtheta(T)
@@ -1928,8 +1962,62 @@ kur_status adjoint_impl(kur_ctx *c, const AdjIO &io, const void *ck_ext, double 
         // a recompute from recorded checkpoints restores (hi, lo) only: its winding counts start at 0
         if ((ck_ext && (e = hipMemsetAsync(B.wind.p, 0, 4 * (size_t)n, st)) != hipSuccess) ||
             (e = hipMemsetAsync(B.gom.p, 0, 8 * (size_t)n, st)) != hipSuccess ||
-            (e = hipMemsetAsync(B.gk.p, 0, 8 * (size_t)ntv, st)) != hipSuccess)
+            (e = hipMemsetAsync(B.gk.p, 0, 8 * (size_t)ngk, st)) != hipSuccess)
             return hip_fail(c, e, "adjoint clear");
+    }
+    if (pers && nsteps > 0) {
+        // forward: launches of at most about 65536 steps, checkpoints every C steps
+        if (!ck_ext) {
+            PersistArgs<T> a;
+            a.n = n;
+            a.r_every = 0;
+            a.final_sample = 0;
+            a.compensate = c->compensate;
+            a.dt = (T)dt;
+            a.half_dt = (T)(0.5 * dt);
+            a.dt6 = (T)(dt / 6.0);
+            a.K = (T)c->K;
+            a.inv_n = (T)(1.0 / (double)n);
+            a.unit = (const T *)c->d_unit.p;
+            a.omega = (const T *)c->d_omega.p;
+            a.hi = (T *)B.hi.p;
+            a.lo = (T *)B.lo.p;
+            a.wind = (int32_t *)B.wind.p;
+            a.r_out = a.psi_out = nullptr;
+            a.ck = (T *)B.ck.p;
+            a.ck_every = C;
+            const int64_t chunk = std::max<int64_t>(1, 65536 / C) * C;
+            for (int64_t done = 0; done < nsteps; done += chunk) {
+                a.step0 = done;
+                a.nsteps = std::min(chunk, nsteps - done);
+                if ((e = launch_persist_complete<T>(a, st)) != hipSuccess) return hip_fail(c, e, "adjoint forward");
+            }
+        }
+        // reverse: launches of whole segments, at most about 65536 steps each
+        PersistAdjArgs<T> v;
+        v.n = n;
+        v.nsteps = nsteps;
+        v.ck_every = C;
+        v.compensate = c->compensate;
+        v.dt = (T)dt;
+        v.half_dt = (T)(0.5 * dt);
+        v.dt6 = (T)(dt / 6.0);
+        v.dt3 = (T)(dt / 3.0);
+        v.K = (T)c->K;
+        v.inv_n = (T)(1.0 / (double)n);
+        v.unit = (const T *)c->d_unit.p;
+        v.omega = (const T *)c->d_omega.p;
+        v.ck = ck_ext ? (const T *)ck_ext : (const T *)B.ck.p;
+        v.ystore = (T *)B.slots.p;
+        v.lam = (T *)B.lam.p;
+        v.g_omega = (double *)B.gom.p;
+        v.gk_part = (double *)B.gk.p;
+        const int64_t per = std::max<int64_t>(1, 65536 / C);
+        for (int64_t hi = nseg - 1; hi >= 0; hi -= per) {
+            v.seg_hi = hi;
+            v.seg_lo = std::max<int64_t>(0, hi - per + 1);
+            if ((e = launch_persist_adjoint<T>(v, st)) != hipSuccess) return hip_fail(c, e, "adjoint reverse");
+        }
     }
     const DevGraph g = devgraph(c);
     const DevGraph gv = asym ? devgraph_t(c) : g;  // layout of the Jacobian-transpose gathers
@@ -1956,7 +2044,7 @@ kur_status adjoint_impl(kur_ctx *c, const AdjIO &io, const void *ck_ext, double 
 
     const char *ckbase = ck_ext ? (const char *)ck_ext : (const char *)B.ck.p;
     // forward pass, keeping (hi, lo) every C steps (unless recorded by the caller's run)
-    if (nsteps > 0 && !ck_ext) {
+    if (nsteps > 0 && !ck_ext && !pers) {
         int cur = 0;
         if ((e = launch_sc_init<T>(g, nt, (const T *)B.hi.p, slot(0), B.fpart[0].p, c->threads, st)) != hipSuccess)
             return hip_fail(c, e, "adjoint forward");
@@ -2036,7 +2124,7 @@ kur_status adjoint_impl(kur_ctx *c, const AdjIO &io, const void *ck_ext, double 
         }
         return r;
     };
-    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    for (int64_t seg = pers ? -1 : nseg - 1; seg >= 0; --seg) {
         const int64_t s0 = seg * C, len = std::min<int64_t>(C, nsteps - s0);
         if (!stored) {
             const char *ck = ckbase + (size_t)seg * 2 * TN;
@@ -2053,14 +2141,14 @@ kur_status adjoint_impl(kur_ctx *c, const AdjIO &io, const void *ck_ext, double 
         const int32_t *perm = (const int32_t *)c->d_perm.p;
         if ((io.gt_dev && (e = launch_gather_out<T, T>(n, perm, B.lam.p, io.gt_dev, st)) != hipSuccess) ||
             (io.gw_dev && (e = launch_gather_out<double, T>(n, perm, B.gom.p, io.gw_dev, st)) != hipSuccess) ||
-            (io.gk_dev && (e = launch_fold_sum<T>(ntv, (const double *)B.gk.p, io.gk_dev, st)) != hipSuccess))
+            (io.gk_dev && (e = launch_fold_sum<T>(ngk, (const double *)B.gk.p, io.gk_dev, st)) != hipSuccess))
             return hip_fail(c, e, "adjoint results");
     } else {
         vector<T> lam(n);
-        vector<double> gom(n), gk(ntv);
+        vector<double> gom(n), gk(ngk);
         if ((e = hipMemcpyAsync(lam.data(), B.lam.p, TN, hipMemcpyDeviceToHost, st)) != hipSuccess ||
             (e = hipMemcpyAsync(gom.data(), B.gom.p, 8 * (size_t)n, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-            (e = hipMemcpyAsync(gk.data(), B.gk.p, 8 * (size_t)ntv, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(gk.data(), B.gk.p, 8 * (size_t)ngk, hipMemcpyDeviceToHost, st)) != hipSuccess ||
             (e = hipStreamSynchronize(st)) != hipSuccess)
             return hip_fail(c, e, "adjoint download");
         for (int64_t u = 0; u < n; ++u) {
@@ -2069,7 +2157,7 @@ kur_status adjoint_impl(kur_ctx *c, const AdjIO &io, const void *ck_ext, double 
         }
         if (io.gk_host) {
             double t = 0.0;
-            for (int i = 0; i < ntv; ++i) t += gk[i];
+            for (int i = 0; i < ngk; ++i) t += gk[i];
             *io.gk_host = t;
         }
     }

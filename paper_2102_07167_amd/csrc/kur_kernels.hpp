@@ -143,9 +143,35 @@ struct PersistArgs {
     T *hi, *lo;
     int32_t *wind;
     double *r_out, *psi_out;
+    T *ck;              // if not null: (hi, lo) before global step s (s a multiple of ck_every) to
+    int64_t ck_every;   // ck + 2 n (s / ck_every); step0 is the global index of this launch's
+    int64_t step0;      // first step
 };
 template <typename T>
 hipError_t launch_persist_complete(const PersistArgs<T> &a, hipStream_t st);
+
+// The discrete adjoint of the one-workgroup RK4 run of the complete graph (same arithmetic as
+// k_vjp on the complete graph's single dense block). One launch sweeps the checkpoint segments
+// seg_hi down to seg_lo: each is recomputed from its checkpoint, keeping the (sin, cos) of every
+// stage input in ystore, then swept in reverse. lam, g_omega and gk_part carry the state between
+// launches.
+template <typename T>
+struct PersistAdjArgs {
+    int64_t n, nsteps, ck_every;
+    int64_t seg_hi, seg_lo;
+    int compensate;
+    T dt, half_dt, dt6, dt3;
+    T K, inv_n;
+    const T *unit;
+    const T *omega;
+    const T *ck;        // checkpoint s: (hi, lo) at step s ck_every, at ck + 2 n s
+    T *ystore;          // (sin, cos) of the 4 ck_every stage inputs of one segment: 8 ck_every n
+    T *lam;             // dL/dtheta at the end of segment seg_hi (in); at the start of seg_lo (out)
+    double *g_omega;    // dL/domega, accumulated
+    double *gk_part;    // kPersistThreads partial sums of dL/dK, accumulated
+};
+template <typename T>
+hipError_t launch_persist_adjoint(const PersistAdjArgs<T> &a, hipStream_t st);
 
 template <typename T>
 hipError_t launch_vjp(const DevGraph &g, int ntiles, const VjpArgs<T> &a, int threads, hipStream_t st);

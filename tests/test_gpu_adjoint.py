@@ -61,6 +61,67 @@ def test_adjoint_matches_oracle(need_gpu, dtype, ckpt, opts):
     assert abs(gk - gk_o) <= tol * max(abs(gk_o), np.abs(gw_o).max())
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1, 2, 97, 512, 1024, 1025])
+def test_adjoint_complete_graph_one_workgroup(need_gpu, dtype, n):
+    """Complete graphs of at most 1024 nodes run the whole adjoint in one workgroup (forward in
+    the one-workgroup RK4 run, each checkpoint segment recomputed and swept back inside one
+    launch); 1025 nodes take the row kernel. 30 steps, checkpoints every 7 (a ragged last
+    segment), both scalings: against the oracle's discrete adjoint (1e-10 FP64, 1e-3 FP32, of
+    the largest gradient) and against the row-kernel adjoint (option persistent = 0); the
+    recorded variant (checkpoints kept by kur_step_rk4) gives the same gradients."""
+    rng = np.random.default_rng(100 + n)
+    om, th0, tgt = rng.standard_normal(n), rng.uniform(0, 2 * np.pi, n), rng.uniform(0, 2 * np.pi, n)
+    K, dt, steps = 2.5, 0.01, 30
+    if dtype == "f32":
+        r32 = lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)
+        om, th0, K, dt = r32(om), r32(th0), float(np.float32(K)), float(np.float32(dt))
+    tol = 1e-10 if dtype == "f64" else 1e-3
+    g = gen.complete_graph(n)
+    for scaling in (0, 1):
+        thT, _, _ = oracle.rk4(g, om, K, th0, dt, steps, scaling=scaling)
+        _, seed = oracle.loss_and_seed(thT, tgt)
+        go = oracle.adjoint_rk4(g, om, K, th0, dt, steps, seed, scaling=scaling)
+        got = {}
+        for pers in (1, 0):
+            with Kuramoto(dtype, device=0) as k:
+                k.set_option("persistent", pers)
+                k.set_option("scaling", scaling)
+                k.set_graph(g)
+                k.set_params(om, K)
+                k.set_phases(th0)
+                got[pers] = k.adjoint_rk4(dt, steps, seed, theta0=th0, ckpt_every=7)
+                if pers:
+                    k.set_option("checkpoint_every", 7)
+                    k.step_rk4(dt, steps)
+                    k.set_option("checkpoint_every", 0)
+                    got["rec"] = k.adjoint_recorded(seed)
+        gmax = max(np.abs(go[0]).max(), np.abs(go[1]).max())
+        for key in (1, 0, "rec"):
+            gt, gw, gk = got[key]
+            assert np.abs(gt - go[0]).max() <= tol * np.abs(go[0]).max(), (key, scaling)
+            assert np.abs(gw - go[1]).max() <= tol * np.abs(go[1]).max(), (key, scaling)
+            assert abs(gk - go[2]) <= tol * max(abs(go[2]), gmax), (key, scaling)
+
+
+def test_adjoint_complete_graph_long_run(need_gpu):
+    """The one-workgroup adjoint over 70001 steps (two forward launches and two reverse
+    launches of whole checkpoint segments): L = sum theta(T) gives dL/dtheta0 = 1, dL/domega = T
+    and dL/dK = 0 (the linear invariant of the symmetric uniform model)."""
+    rng = np.random.default_rng(9)
+    n, dt, steps = 64, 0.001, 70001
+    with Kuramoto("f64", device=0) as k:
+        k.set_graph(gen.complete_graph(n))
+        k.set_params(rng.standard_normal(n), 3.0)
+        th0 = rng.uniform(0, 2 * np.pi, n)
+        k.set_phases(th0)
+        gt, gw, gk = k.adjoint_rk4(dt, steps, np.ones(n), theta0=th0, ckpt_every=1000)
+    T = steps * dt
+    assert np.abs(gt - 1).max() < 1e-9
+    assert np.abs(gw - T).max() < 1e-9 * T
+    assert abs(gk) < 1e-9 * T * n
+
+
 def test_adjoint_exact_cases(need_gpu):
     """L = sum theta(T): dL/dtheta0 = 1, dL/domega = T, dL/dK = 0 (linear invariant, symmetric A,
     uniform scaling); K = 0: dL/dtheta0 = seed, dL/domega = T seed."""
