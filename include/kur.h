@@ -101,6 +101,10 @@ const char *kur_last_error(const kur_ctx *ctx);
  *                 of a block all run on one XCD, whose L2 then serves the block's re-staged
  *                 (sin, cos) chunks; 1: plain largest-first order (default; the tuner tries
  *                 8, the XCD count of MI355X).
+ *   "inter_gather" 1: the row kernel's inter-block gathers read the 4-byte stage phase and form
+ *                 (sin, cos) (half the cache footprint of the pairs; the same values bit for bit);
+ *                 0: they read the (sin, cos) pair. Default 1 in FP32, 0 in FP64; the tuner tries
+ *                 both. Immediate.
  *   "flat_min_vec" rows of a tile averaging at least this many 8-entry list vectors per chunk
  *                 are streamed one contiguous run per wavefront; shorter rows get a group of
  *                 lanes each. 0 disables streaming. Default 8.
@@ -424,15 +428,16 @@ kur_status kur_read_bandwidth(kur_ctx *ctx, int64_t bytes, int32_t repeats, doub
  * Introduction and Sec. 3: precomputed sums pay off once ones outnumber zeros, so tau = 1/2
  * minimises the stored bytes. The tuner times whole RK4 steps of the row kernel with HIP events
  * for candidate values of tau, the chunk width ("chunk") and the tile options ("tile_rows",
- * "tile_min_cost", "flat_min_vec", "threads", "xcds"), by coordinate descent from the options in
+ * "tile_min_cost", "flat_min_vec", "threads", "xcds", "inter_gather"), by coordinate descent from the options in
  * force; a candidate wins only when it is at least 1 % faster. Results do not change with the
  * layout beyond rounding order.
  *
- * report (may be NULL) receives 13 doubles: tau, chunk, threads, tile_rows, tile_min_cost,
+ * report (may be NULL) receives 14 doubles: tau, chunk, threads, tile_rows, tile_min_cost,
  * flat_min_vec, ms per RK4 step of the chosen layout, ms per step of the starting layout (NaN
  * when taken from the cache), candidates timed, cache status (1: loaded from the cache, 0:
  * tuned and stored or no cache given, -1: tuned but the cache file could not be written), list
- * builds, seconds spent, xcds. Synchronous; effort 0, 1 or 2 widens the candidate sets.
+ * builds, seconds spent, xcds, inter_gather (-1: a cache line that leaves the dtype's
+ * default). Synchronous; effort 0, 1 or 2 widens the candidate sets.
  *
  * kur_autotune_csr: takes the arguments of kur_set_graph_csr and ends with that graph installed
  * in the chosen layout, as kur_set_graph_csr would (omega, K and phases unset); the options

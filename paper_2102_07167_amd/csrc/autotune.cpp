@@ -60,8 +60,9 @@ struct Choice {
     double ms = 1e300;
 };
 
-// Cache lines: "<key>\t<tau> <chunk> <threads> <tile_rows> <tile_min_cost> <flat_min_vec> <xcds> <ms>".
-// The last line with a matching key wins; malformed lines are skipped.
+// Cache lines: "<key>\t<tau> <chunk> <threads> <tile_rows> <tile_min_cost> <flat_min_vec> <xcds> <ms>
+// [<inter_gather>]" (lines without the last field keep the dtype's default gathers). The last
+// line with a matching key wins; malformed lines are skipped.
 bool cache_lookup(const char *path, const std::string &key, Choice &out)
 {
     if (!path) return false;
@@ -73,11 +74,13 @@ bool cache_lookup(const char *path, const std::string &key, Choice &out)
         char *tab = std::strchr(line, '\t');
         if (!tab || (size_t)(tab - line) != key.size() || std::strncmp(line, key.c_str(), key.size()) != 0) continue;
         Choice ch;
-        int chunk = 0, threads = 0, rows = 0, xcds = 0;
+        int chunk = 0, threads = 0, rows = 0, xcds = 0, ig = -1;
         long long cost = 0;
-        if (std::sscanf(tab + 1, "%lf %d %d %d %lld %lf %d %lf", &ch.l.tau, &chunk, &threads, &rows, &cost,
-                        &ch.t.flat_min_vec, &xcds, &ch.ms) != 8)
-            continue;
+        const int got = std::sscanf(tab + 1, "%lf %d %d %d %lld %lf %d %lf %d", &ch.l.tau, &chunk, &threads, &rows,
+                                    &cost, &ch.t.flat_min_vec, &xcds, &ch.ms, &ig);
+        if (got != 8 && got != 9) continue;
+        if (got == 9 && ig != 0 && ig != 1) continue;
+        ch.t.inter_gather = got == 9 ? ig : -1;
         ch.t.xcds = xcds;
         ch.l.chunk = chunk;
         ch.t.threads = threads;
@@ -95,9 +98,9 @@ bool cache_store(const char *path, const std::string &key, const Choice &ch)
     if (!path) return true;
     FILE *f = std::fopen(path, "a");
     if (!f) return false;
-    const int r = std::fprintf(f, "%s\t%.17g %d %d %d %lld %.17g %d %.6g\n", key.c_str(), ch.l.tau, ch.l.chunk,
+    const int r = std::fprintf(f, "%s\t%.17g %d %d %d %lld %.17g %d %.6g %d\n", key.c_str(), ch.l.tau, ch.l.chunk,
                                ch.t.threads, ch.t.tile_rows, (long long)ch.t.tile_min_cost, ch.t.flat_min_vec,
-                               ch.t.xcds, ch.ms);
+                               ch.t.xcds, ch.ms, ch.t.inter_gather);
     return std::fclose(f) == 0 && r > 0;
 }
 
@@ -136,7 +139,7 @@ kur_status search_tiles(Search &S, Choice &best)
 {
     const int sweeps = S.effort >= 2 ? 2 : 1;
     for (int sweep = 0; sweep < sweeps; ++sweep) {
-        for (int dim = 0; dim < 5; ++dim) {
+        for (int dim = 0; dim < 6; ++dim) {
             std::vector<TileParams> cands;
             if (dim == 0)
                 for (int64_t v : cost_values(S.effort)) { TileParams t = best.t; t.tile_min_cost = v; cands.push_back(t); }
@@ -148,6 +151,8 @@ kur_status search_tiles(Search &S, Choice &best)
                 for (double v : flat_values(S.effort)) { TileParams t = best.t; t.flat_min_vec = v; cands.push_back(t); }
             if (dim == 4)  // XCD-aware launch order on or off
                 for (int32_t v : {1, 8}) { TileParams t = best.t; t.xcds = v; cands.push_back(t); }
+            if (dim == 5)  // inter-block gathers of phases or of (sin, cos) pairs
+                for (int32_t v : {0, 1}) { TileParams t = best.t; t.inter_gather = v; cands.push_back(t); }
             const TileParams incumbent = best.t;
             for (const TileParams &t : cands) {
                 if (t == incumbent || t == best.t || !ctx_layout_fits(S.c, 0, t)) continue;
@@ -195,6 +200,7 @@ void fill_report(double *report, const Choice &best, double ms_default, const Se
     report[10] = S.builds;
     report[11] = seconds;
     report[12] = best.t.xcds;
+    report[13] = best.t.inter_gather;
 }
 
 }  // namespace

@@ -505,6 +505,7 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
     c->tiles_installed.tile_min_cost = c->bopt.tile_min_cost;
     c->tiles_installed.flat_min_vec = c->bopt.flat_min_vec;
     c->tiles_installed.xcds = c->bopt.xcds;
+    c->tiles_installed.inter_gather = c->inter_gather;
     if (c->host_only) {
         c->host_graph = std::move(g);
     } else {
@@ -772,6 +773,7 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
     } else if (k == "inter_gather") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "inter_gather must be 0 or 1");
         c->inter_gather = (int)v;
+        c->tiles_installed.inter_gather = c->inter_gather;
         c->gen++;
     } else if (k == "adjoint_keep") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "adjoint_keep must be 0 or 1");
@@ -2514,8 +2516,10 @@ kur_status ctx_set_build_options(kur_ctx *c, const LayoutParams &l, const TilePa
 {
     if (!(l.tau >= 0.0 && l.tau <= 1.0) || l.chunk < 64 || l.chunk % 64 || l.chunk > ctx_max_chunk(c) ||
         t.tile_rows < 64 || t.tile_rows > 4096 || t.tile_min_cost < 1 || !(t.flat_min_vec >= 0.0) ||
-        (t.threads != 256 && t.threads != 512 && t.threads != 1024) || t.xcds < 1 || t.xcds > 64)
+        (t.threads != 256 && t.threads != 512 && t.threads != 1024) || t.xcds < 1 || t.xcds > 64 ||
+        t.inter_gather < -1 || t.inter_gather > 1)
         return fail(c, KUR_EINVAL, "layout options out of range");
+    if (t.inter_gather >= 0) c->inter_gather = t.inter_gather;
     c->bopt.tau = l.tau;
     c->bopt.W = l.chunk;
     c->bopt.tile_rows = t.tile_rows;
@@ -2531,8 +2535,10 @@ kur_status ctx_retile(kur_ctx *c, const TileParams &t)
 {
     if (!c->has_graph) return fail(c, KUR_ESTATE, "no graph set");
     if (t.tile_rows < 64 || t.tile_rows > 4096 || t.tile_min_cost < 1 || !(t.flat_min_vec >= 0.0) ||
-        (t.threads != 256 && t.threads != 512 && t.threads != 1024) || t.xcds < 1 || t.xcds > 64)
+        (t.threads != 256 && t.threads != 512 && t.threads != 1024) || t.xcds < 1 || t.xcds > 64 ||
+        t.inter_gather < -1 || t.inter_gather > 1)
         return fail(c, KUR_EINVAL, "tile options out of range");
+    if (t.inter_gather >= 0) c->inter_gather = t.inter_gather;
     if (!ctx_layout_fits(c, c->W, t)) return fail(c, KUR_EINVAL, "chunk/tile_rows/threads exceed the LDS of a workgroup");
     BlockGraph &L = c->host_only ? c->host_graph : c->skel;
     BuildOptions o = c->bopt;
@@ -2556,6 +2562,7 @@ kur_status ctx_retile(kur_ctx *c, const TileParams &t)
     c->bopt.flat_min_vec = t.flat_min_vec;
     c->bopt.xcds = t.xcds;
     c->tiles_installed = t;
+    c->tiles_installed.inter_gather = c->inter_gather;
     // tiles never span blocks and an instance is a run of whole blocks: its first tile is the
     // first tile of the first block at or after its first row
     c->inst_tile_first.assign(c->n_inst + 1, (int64_t)c->ntiles);

@@ -13,17 +13,19 @@
 
 namespace kur {
 
-// Options that only change how rows are grouped into tiles (no list rebuild).
+// Options that only change how rows are grouped into tiles or how the row kernel gathers (no list
+// rebuild).
 struct TileParams {
     int32_t threads = 512;
     int32_t tile_rows = 256;
     int64_t tile_min_cost = 16384;
     double flat_min_vec = 8.0;
     int32_t xcds = 1;
+    int32_t inter_gather = -1;  // inter-block gathers: 1 phases, 0 (sin, cos) pairs, -1 the dtype's default
     bool operator==(const TileParams &o) const
     {
         return threads == o.threads && tile_rows == o.tile_rows && tile_min_cost == o.tile_min_cost &&
-               flat_min_vec == o.flat_min_vec && xcds == o.xcds;
+               flat_min_vec == o.flat_min_vec && xcds == o.xcds && inter_gather == o.inter_gather;
     }
     bool operator!=(const TileParams &o) const { return !(*this == o); }
 };

@@ -401,11 +401,11 @@ class Kuramoto:
 
     # -- layout autotuning -------------------------------------------------------------------
     _TUNE_FIELDS = ("tau", "chunk", "threads", "tile_rows", "tile_min_cost", "flat_min_vec", "ms_per_step",
-                    "ms_per_step_start", "timed", "cache", "builds", "seconds", "xcds")
+                    "ms_per_step_start", "timed", "cache", "builds", "seconds", "xcds", "inter_gather")
 
     def _tune_report(self, rep):
         d = dict(zip(self._TUNE_FIELDS, (float(x) for x in rep)))
-        for k in ("chunk", "threads", "tile_rows", "tile_min_cost", "timed", "cache", "builds", "xcds"):
+        for k in ("chunk", "threads", "tile_rows", "tile_min_cost", "timed", "cache", "builds", "xcds", "inter_gather"):
             d[k] = int(d[k])
         return d
 
@@ -415,7 +415,7 @@ class Kuramoto:
         rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int64)
         cl = np.ascontiguousarray(graph.col, dtype=np.int32)
         lb = np.ascontiguousarray(graph.labels, dtype=np.int32)
-        rep = np.zeros(13)
+        rep = np.zeros(14)
         self._chk(self._L.kur_autotune_csr(self._h, int(graph.n), _ptr(rp), _ptr(cl), _ptr(lb), int(effort),
                                            None if cache is None else os.fsencode(cache), _ptr(rep)))
         self.n = int(graph.n)
@@ -423,7 +423,7 @@ class Kuramoto:
 
     def tune_tiles(self, effort: int = 1) -> dict:
         """Re-tile the installed graph or batch with the fastest tile options (kur_tune_tiles)."""
-        rep = np.zeros(13)
+        rep = np.zeros(14)
         self._chk(self._L.kur_tune_tiles(self._h, int(effort), _ptr(rep)))
         return self._tune_report(rep)
 

@@ -78,6 +78,23 @@ def test_cached_choice_installs_its_layout(tmp_path):
         check_layout(k, g, 0.4)
 
 
+def test_cached_gather_choice(tmp_path):
+    """A cache line's optional ninth field selects the inter-block gathers (0 pairs, 1 phases);
+    lines without it report -1 (the dtype's default); a ninth field other than 0 or 1 makes the
+    line malformed, so an earlier matching line wins."""
+    g = small_sbm()
+    path = tmp_path / "tune.tsv"
+    with host_ctx() as k:
+        key = k.tune_key(g)
+        path.write_text(key + "\t0.5 128 512 256 16384 8 1 1.0\n")
+        assert k.autotune(g, cache=str(path))["inter_gather"] == -1
+        path.write_text(key + "\t0.5 128 512 256 16384 8 1 1.0 0\n")
+        assert k.autotune(g, cache=str(path))["inter_gather"] == 0
+        path.write_text(key + "\t0.5 128 512 256 16384 8 1 1.0 1\n" + key + "\t0.5 128 512 256 16384 8 1 2.0 5\n")
+        rep = k.autotune(g, cache=str(path))
+        assert rep["inter_gather"] == 1 and rep["ms_per_step"] == 1.0
+
+
 def test_cached_choice_out_of_range_is_rejected(tmp_path):
     g = small_sbm()
     path = tmp_path / "tune.tsv"

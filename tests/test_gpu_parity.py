@@ -307,7 +307,7 @@ def load_trajectory_fixture(name):
 
 # The committed cached layout of the 64 x 1024 SBM (tile options chosen by the tuner on MI355X,
 # launch order for 8 XCDs); FP64 contexts take the same tile options with their own chunk width.
-SBM64_CACHED = dict(tile_rows=64, tile_min_cost=8192, flat_min_vec=8, xcds=8)
+SBM64_CACHED = dict(tile_rows=128, tile_min_cost=16384, flat_min_vec=8, xcds=8, inter_gather=0)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -332,7 +332,7 @@ def test_sbm_64x1024_trajectory_1000_steps(need_gpu, dtype, layout):
             cache = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                                  "paper_2102_07167_amd", "tuned_layouts.tsv")
             rep = k.autotune(g, effort=1, cache=cache)
-            assert rep["cache"] == 1 and rep["xcds"] == 8
+            assert rep["cache"] == 1 and rep["xcds"] == 8 and rep["inter_gather"] == 0
         else:
             if layout == "cached":
                 for key, v in SBM64_CACHED.items():
