@@ -94,6 +94,10 @@ const char *kur_last_error(const kur_ctx *ctx);
  *   "chunk"       columns of a diagonal block staged in LDS at a time: a multiple of 64, at
  *                 most 8128 (FP32) or 4032 (FP64). Default 4096 (FP32), 4032 (FP64).
  *   "tile_rows"   maximal rows per work tile (64..4096). Default 256.
+ *   "threads"     threads per workgroup of the tile kernels: 128, 256, 512 or 1024. Default 512.
+ *                 Smaller workgroups let a compute unit hold more tiles at once, which pays
+ *                 where tiles carry little work each. The staged chunk, tile_rows and the
+ *                 threads must fit the LDS of one workgroup (else KUR_EINVAL).
  *   "tiles"       target number of work tiles (>= 1). Default 4096.
  *   "tile_min_cost" least work per tile in list-entry equivalents (a row costs its stored list
  *                 entries + 4 per inter-block entry + 32). Default 16384.

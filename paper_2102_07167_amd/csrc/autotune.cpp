@@ -144,7 +144,7 @@ kur_status search_tiles(Search &S, Choice &best)
             if (dim == 0)
                 for (int64_t v : cost_values(S.effort)) { TileParams t = best.t; t.tile_min_cost = v; cands.push_back(t); }
             if (dim == 1)
-                for (int32_t v : {256, 512, 1024}) { TileParams t = best.t; t.threads = v; cands.push_back(t); }
+                for (int32_t v : {128, 256, 512, 1024}) { TileParams t = best.t; t.threads = v; cands.push_back(t); }
             if (dim == 2)
                 for (int32_t v : row_values(S.effort)) { TileParams t = best.t; t.tile_rows = v; cands.push_back(t); }
             if (dim == 3)

@@ -757,7 +757,8 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
         if (v != (int64_t)v || v < 1 || v > 65536) return fail(c, KUR_EINVAL, "pair_min must be an integer in [1, 65536]");
         c->bopt.pair_min = (int32_t)v;
     } else if (k == "threads") {
-        if (v != 256 && v != 512 && v != 1024) return fail(c, KUR_EINVAL, "threads must be 256, 512 or 1024");
+        if (v != 128 && v != 256 && v != 512 && v != 1024)
+            return fail(c, KUR_EINVAL, "threads must be 128, 256, 512 or 1024");
         if (c->has_graph && rows_lds_bytes(c->esz, c->W, c->tile_rows, (int)v) > 156 * 1024)
             return fail(c, KUR_EINVAL, "threads exceed the LDS budget of the current graph layout");
         c->threads = (int)v;
@@ -1327,6 +1328,19 @@ static hipError_t launch_step(kur_ctx *c, const DevGraph &g, double dt, char *rs
     return hipSuccess;
 }
 
+// Device buffers for nsamp order-parameter samples of every instance: room for at least 256
+// samples, grown by powers of two. The captured step graph names these buffers, so runs of
+// different lengths keep one graph.
+static hipError_t sample_alloc(kur_ctx *c, int64_t nsamp)
+{
+    int64_t cap = 256;
+    while (cap < nsamp) cap *= 2;
+    const size_t bytes = sizeof(double) * (size_t)cap * (size_t)c->n_inst;
+    hipError_t e = dalloc(c->d_r, bytes);
+    if (e == hipSuccess) e = dalloc(c->d_psi, bytes);
+    return e;
+}
+
 // Capture `period` steps (and, when sampling, the order-parameter kernel with a device-side
 // sample index) into one executable graph, reusing the cached one when nothing changed.
 static hipError_t step_graph(kur_ctx *c, const DevGraph &g, double dt, int64_t period, bool sample)
@@ -1365,11 +1379,7 @@ static kur_status run_steps(kur_ctx *c, double dt, int64_t nsteps, int64_t r_eve
 {
     const int64_t nsamp = r_every > 0 ? nsteps / r_every + 1 : 0;
     hipError_t e;
-    if (nsamp > 0) {
-        if ((e = dalloc(c->d_r, sizeof(double) * nsamp * c->n_inst)) != hipSuccess ||
-            (e = dalloc(c->d_psi, sizeof(double) * nsamp * c->n_inst)) != hipSuccess)
-            return hip_fail(c, e, "r buffer");
-    }
+    if (nsamp > 0 && (e = sample_alloc(c, nsamp)) != hipSuccess) return hip_fail(c, e, "r buffer");
     // a small complete graph without kernel timing or a stage record: one launch for the whole
     // run (checkpoints for the adjoint written by the same launch)
     if (c->complete_graph && c->persistent && !c->batch && !(c->ckpt_every > 0 && c->record_stages) && !c->timing &&
@@ -1523,11 +1533,7 @@ static kur_status run_midpoint(kur_ctx *c, double dt, int64_t nsteps, int32_t it
 {
     const int64_t nsamp = r_every > 0 ? nsteps / r_every + 1 : 0;
     hipError_t e;
-    if (nsamp > 0) {
-        if ((e = dalloc(c->d_r, sizeof(double) * nsamp * c->n_inst)) != hipSuccess ||
-            (e = dalloc(c->d_psi, sizeof(double) * nsamp * c->n_inst)) != hipSuccess)
-            return hip_fail(c, e, "r buffer");
-    }
+    if (nsamp > 0 && (e = sample_alloc(c, nsamp)) != hipSuccess) return hip_fail(c, e, "r buffer");
     if (!c->sc_valid) {
         kur_status s = sc_init(c, c->d_hi.p, c->d_sc[c->cur], c->d_part[c->cur]);
         if (s != KUR_OK) return s;
@@ -2516,7 +2522,7 @@ kur_status ctx_set_build_options(kur_ctx *c, const LayoutParams &l, const TilePa
 {
     if (!(l.tau >= 0.0 && l.tau <= 1.0) || l.chunk < 64 || l.chunk % 64 || l.chunk > ctx_max_chunk(c) ||
         t.tile_rows < 64 || t.tile_rows > 4096 || t.tile_min_cost < 1 || !(t.flat_min_vec >= 0.0) ||
-        (t.threads != 256 && t.threads != 512 && t.threads != 1024) || t.xcds < 1 || t.xcds > 64 ||
+        (t.threads != 128 && t.threads != 256 && t.threads != 512 && t.threads != 1024) || t.xcds < 1 || t.xcds > 64 ||
         t.inter_gather < -1 || t.inter_gather > 1)
         return fail(c, KUR_EINVAL, "layout options out of range");
     if (t.inter_gather >= 0) c->inter_gather = t.inter_gather;
@@ -2535,7 +2541,7 @@ kur_status ctx_retile(kur_ctx *c, const TileParams &t)
 {
     if (!c->has_graph) return fail(c, KUR_ESTATE, "no graph set");
     if (t.tile_rows < 64 || t.tile_rows > 4096 || t.tile_min_cost < 1 || !(t.flat_min_vec >= 0.0) ||
-        (t.threads != 256 && t.threads != 512 && t.threads != 1024) || t.xcds < 1 || t.xcds > 64 ||
+        (t.threads != 128 && t.threads != 256 && t.threads != 512 && t.threads != 1024) || t.xcds < 1 || t.xcds > 64 ||
         t.inter_gather < -1 || t.inter_gather > 1)
         return fail(c, KUR_EINVAL, "tile options out of range");
     if (t.inter_gather >= 0) c->inter_gather = t.inter_gather;

@@ -794,22 +794,43 @@ __global__ void k_phase_out(int64_t n, const T *__restrict__ hi, const T *__rest
 // launchers
 // ------------------------------------------------------------------------------------------------
 
+// Calls f(std::integral_constant<int, NT>{}) with NT the workgroup size `threads` of the tile
+// kernels: 128, 256, 512 or 1024 (the option checks admit nothing else; anything else takes 512).
+template <typename F>
+hipError_t with_nt(int threads, F &&f)
+{
+    switch (threads) {
+    case 128: return f(std::integral_constant<int, 128>{});
+    case 256: return f(std::integral_constant<int, 256>{});
+    case 1024: return f(std::integral_constant<int, 1024>{});
+    default: return f(std::integral_constant<int, 512>{});
+    }
+}
+
+// dynamic LDS limit requested for the tile kernels (the rest of the 160 KiB stays for static use)
+constexpr int kMaxDynLds = 156 * 1024;
+
+// Raise the dynamic LDS limit of the tile kernel Fn, once per process (one static per kernel).
+template <auto Fn>
+hipError_t dyn_lds_attr()
+{
+    static const hipError_t e =
+        hipFuncSetAttribute(reinterpret_cast<const void *>(Fn), hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+    return e;
+}
+
 template <typename T>
 hipError_t launch_sc_init(const DevGraph &g, int ntiles, const T *y, void *sc, void *part, int threads,
                           hipStream_t st)
 {
     using T2 = typename V2<T>::type;
     if (ntiles <= 0) return hipSuccess;
-    switch (threads) {
-    case 256: hipLaunchKernelGGL((k_sc_init<T, 256>), dim3(ntiles), dim3(256), 0, st, g.tiles, g.blk, y, (T2 *)sc, (T2 *)part); break;
-    case 1024: hipLaunchKernelGGL((k_sc_init<T, 1024>), dim3(ntiles), dim3(1024), 0, st, g.tiles, g.blk, y, (T2 *)sc, (T2 *)part); break;
-    default: hipLaunchKernelGGL((k_sc_init<T, 512>), dim3(ntiles), dim3(512), 0, st, g.tiles, g.blk, y, (T2 *)sc, (T2 *)part); break;
-    }
-    return hipGetLastError();
+    return with_nt(threads, [&](auto nt) -> hipError_t {
+        constexpr int NT = decltype(nt)::value;
+        hipLaunchKernelGGL((k_sc_init<T, NT>), dim3(ntiles), dim3(NT), 0, st, g.tiles, g.blk, y, (T2 *)sc, (T2 *)part);
+        return hipGetLastError();
+    });
 }
-
-// dynamic LDS limit requested for the tile kernels (the rest of the 160 KiB stays for static use)
-constexpr int kMaxDynLds = 156 * 1024;
 
 size_t rows_lds_bytes(int elem_bytes, int W, int tile_rows, int threads)
 {
@@ -824,34 +845,17 @@ hipError_t launch_rows(const DevGraph &g, int ntiles, const RowArgs<T> &a, int t
 {
     if (ntiles <= 0) return hipSuccess;
     const size_t lds = rows_lds_bytes(sizeof(T), g.W, g.tile_rows, threads);
-    static bool attr_done[6] = {false, false, false, false, false, false};
     const bool yg = a.y_in != nullptr;
-    const int slot = (threads == 256 ? 0 : threads == 1024 ? 2 : 1) + (yg ? 3 : 0);
-    if (!attr_done[slot]) {
-        const void *fn = yg ? (threads == 256    ? reinterpret_cast<const void *>(&k_rows<T, 256, true>)
-                               : threads == 1024 ? reinterpret_cast<const void *>(&k_rows<T, 1024, true>)
-                                                 : reinterpret_cast<const void *>(&k_rows<T, 512, true>))
-                            : (threads == 256    ? reinterpret_cast<const void *>(&k_rows<T, 256, false>)
-                               : threads == 1024 ? reinterpret_cast<const void *>(&k_rows<T, 1024, false>)
-                                                 : reinterpret_cast<const void *>(&k_rows<T, 512, false>));
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+    return with_nt(threads, [&](auto nt) -> hipError_t {
+        constexpr int NT = decltype(nt)::value;
+        hipError_t e = yg ? dyn_lds_attr<&k_rows<T, NT, true>>() : dyn_lds_attr<&k_rows<T, NT, false>>();
         if (e != hipSuccess) return e;
-        attr_done[slot] = true;
-    }
-    if (yg) {
-        switch (threads) {
-        case 256: hipLaunchKernelGGL((k_rows<T, 256, true>), dim3(g.nlaunch), dim3(256), lds, st, g, a); break;
-        case 1024: hipLaunchKernelGGL((k_rows<T, 1024, true>), dim3(g.nlaunch), dim3(1024), lds, st, g, a); break;
-        default: hipLaunchKernelGGL((k_rows<T, 512, true>), dim3(g.nlaunch), dim3(512), lds, st, g, a); break;
-        }
-    } else {
-        switch (threads) {
-        case 256: hipLaunchKernelGGL((k_rows<T, 256, false>), dim3(g.nlaunch), dim3(256), lds, st, g, a); break;
-        case 1024: hipLaunchKernelGGL((k_rows<T, 1024, false>), dim3(g.nlaunch), dim3(1024), lds, st, g, a); break;
-        default: hipLaunchKernelGGL((k_rows<T, 512, false>), dim3(g.nlaunch), dim3(512), lds, st, g, a); break;
-        }
-    }
-    return hipGetLastError();
+        if (yg)
+            hipLaunchKernelGGL((k_rows<T, NT, true>), dim3(g.nlaunch), dim3(NT), lds, st, g, a);
+        else
+            hipLaunchKernelGGL((k_rows<T, NT, false>), dim3(g.nlaunch), dim3(NT), lds, st, g, a);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
@@ -859,22 +863,13 @@ hipError_t launch_emb(const DevGraph &g, const EmbArgs<T> &a, int threads, hipSt
 {
     if (g.nlaunch <= 0) return hipSuccess;
     const size_t lds = rows_lds_bytes(sizeof(T), g.W, g.tile_rows, threads);
-    static bool attr_done[3] = {false, false, false};
-    const int slot = threads == 256 ? 0 : threads == 1024 ? 2 : 1;
-    if (!attr_done[slot]) {
-        const void *fn = threads == 256 ? reinterpret_cast<const void *>(&k_rows_emb<T, 256>)
-                         : threads == 1024 ? reinterpret_cast<const void *>(&k_rows_emb<T, 1024>)
-                                           : reinterpret_cast<const void *>(&k_rows_emb<T, 512>);
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+    return with_nt(threads, [&](auto nt) -> hipError_t {
+        constexpr int NT = decltype(nt)::value;
+        hipError_t e = dyn_lds_attr<&k_rows_emb<T, NT>>();
         if (e != hipSuccess) return e;
-        attr_done[slot] = true;
-    }
-    switch (threads) {
-    case 256: hipLaunchKernelGGL((k_rows_emb<T, 256>), dim3(g.nlaunch), dim3(256), lds, st, g, a); break;
-    case 1024: hipLaunchKernelGGL((k_rows_emb<T, 1024>), dim3(g.nlaunch), dim3(1024), lds, st, g, a); break;
-    default: hipLaunchKernelGGL((k_rows_emb<T, 512>), dim3(g.nlaunch), dim3(512), lds, st, g, a); break;
-    }
-    return hipGetLastError();
+        hipLaunchKernelGGL((k_rows_emb<T, NT>), dim3(g.nlaunch), dim3(NT), lds, st, g, a);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
@@ -889,34 +884,24 @@ hipError_t launch_vjp(const DevGraph &g, int ntiles, const VjpArgs<T> &a, int th
 {
     if (ntiles <= 0) return hipSuccess;
     const size_t lds = rows_lds_bytes(sizeof(T), g.W, g.tile_rows, threads);
-    static bool attr_done[3] = {false, false, false};
-    const int slot = threads == 256 ? 0 : threads == 1024 ? 2 : 1;
-    if (!attr_done[slot]) {
-        const void *fn = threads == 256 ? reinterpret_cast<const void *>(&k_vjp<T, 256>)
-                         : threads == 1024 ? reinterpret_cast<const void *>(&k_vjp<T, 1024>)
-                                           : reinterpret_cast<const void *>(&k_vjp<T, 512>);
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+    return with_nt(threads, [&](auto nt) -> hipError_t {
+        constexpr int NT = decltype(nt)::value;
+        hipError_t e = dyn_lds_attr<&k_vjp<T, NT>>();
         if (e != hipSuccess) return e;
-        attr_done[slot] = true;
-    }
-    switch (threads) {
-    case 256: hipLaunchKernelGGL((k_vjp<T, 256>), dim3(g.nlaunch), dim3(256), lds, st, g, a); break;
-    case 1024: hipLaunchKernelGGL((k_vjp<T, 1024>), dim3(g.nlaunch), dim3(1024), lds, st, g, a); break;
-    default: hipLaunchKernelGGL((k_vjp<T, 512>), dim3(g.nlaunch), dim3(512), lds, st, g, a); break;
-    }
-    return hipGetLastError();
+        hipLaunchKernelGGL((k_vjp<T, NT>), dim3(g.nlaunch), dim3(NT), lds, st, g, a);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
 hipError_t launch_vjp_init(const DevGraph &g, int ntiles, const VjpArgs<T> &a, int threads, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    switch (threads) {
-    case 256: hipLaunchKernelGGL((k_vjp_init<T, 256>), dim3(ntiles), dim3(256), 0, st, g.tiles, g.blk, a); break;
-    case 1024: hipLaunchKernelGGL((k_vjp_init<T, 1024>), dim3(ntiles), dim3(1024), 0, st, g.tiles, g.blk, a); break;
-    default: hipLaunchKernelGGL((k_vjp_init<T, 512>), dim3(ntiles), dim3(512), 0, st, g.tiles, g.blk, a); break;
-    }
-    return hipGetLastError();
+    return with_nt(threads, [&](auto nt) -> hipError_t {
+        constexpr int NT = decltype(nt)::value;
+        hipLaunchKernelGGL((k_vjp_init<T, NT>), dim3(ntiles), dim3(NT), 0, st, g.tiles, g.blk, a);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>

@@ -183,7 +183,7 @@ def asymmetric_workload(seed, weighted=False):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("opts", [dict(), dict(chunk=64, tile_rows=64, flat_min_vec=0.5, ckpt=7),
-                                  dict(scaling=1, threads=256), dict(weighted=True)])
+                                  dict(scaling=1, threads=256), dict(weighted=True), dict(threads=128, chunk=64)])
 def test_adjoint_asymmetric_with_transpose(need_gpu, dtype, opts):
     """Asymmetric A with the option "transpose": the gathers of J^T l run over the layout of A^T
     and match the oracle's discrete adjoint, which scatters the rows of A."""

@@ -95,10 +95,10 @@ def test_pairs_on_and_off_agree(need_gpu):
     assert np.abs(out[0] - out[1]).max() <= 1e-12 * np.abs(out[1]).max()
 
 
-@pytest.mark.parametrize("threads", [256, 512, 1024])
+@pytest.mark.parametrize("threads", [128, 256, 512, 1024])
 def test_pairs_more_groups_than_waves(need_gpu, threads):
     """Twelve mutually dense blocks: every row block has twelve column groups, more than the
-    waves of a 256- or 512-thread workgroup."""
+    waves of a 128-, 256- or 512-thread workgroup."""
     sizes = [33, 40, 47, 54, 61, 68, 75, 82, 89, 96, 103, 110]
     g, om, th = pair_graph(83, sizes, np.ones((12, 12), dtype=np.int32), exception=0.15)
     K = 1.1

@@ -124,7 +124,8 @@ def test_sbm_fp32_trajectory_1000_steps(need_gpu, flat):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("opts", [dict(chunk=64, tile_rows=64), dict(tau=0.0, chunk=128), dict(tau=1.0),
-                                  dict(threads=256, tile_rows=128), dict(threads=1024),
+                                  dict(threads=256, tile_rows=128), dict(threads=1024), dict(threads=128, tile_rows=64, chunk=128),
+                                  dict(threads=128, xcds=8),
                                   dict(flat_min_vec=0.1, chunk=128, tile_rows=64), dict(flat_min_vec=0.1, tau=0.0),
                                   dict(flat_min_vec=0), dict(tile_min_cost=1), dict(tile_min_cost=1, tiles=100000),
                                   dict(xcds=8, tile_min_cost=1), dict(xcds=8, tile_rows=64, chunk=128),
