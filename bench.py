@@ -10,7 +10,10 @@ Default workload: heterogeneous stochastic block model, N = 2^20, power-law comm
 omega ~ Cauchy(0, 0.5), K = 3, dt = 0.005, FP32 (seeded synthetic input).
 
 Prints one JSON line with the throughput, the roofline of the dominant kernel (the row kernel,
-timed live with HIP events on its own stream) and the CPU oracle timed on a bounded sample.
+timed live with HIP events on its own stream) and the CPU oracle timed on a bounded sample. The
+default run also times the other workloads (the 64 x 1024 SBM with its 2000-step adjoint in FP32
+and FP64, the N = 512 all-to-all graph in FP64, the 256-instance batch) in child runs and reports
+them under "other_configs" (--no-other-configs skips them).
 
 Other workloads (--workload): sbm (64 x 1024 SBM), a2a (N = 512 all-to-all, FP64), pairs (the
 paired SBM with dense off-diagonal blocks), paper (M = 4096 in four communities to T = 200, with
@@ -282,6 +285,51 @@ def bench_ensemble(args):
     k.close()
 
 
+# The other workloads of the hot path, each timed by a child run of this script before the main
+# workload touches the GPU (label, arguments). The 64 x 1024 SBM runs 2000 steps with its adjoint
+# over the same 2000 steps (checkpoints every 32) in FP32 and FP64; the all-to-all N = 512 graph
+# runs in FP64 with its one-workgroup adjoint; the batch is the 256-instance ensemble.
+OTHER_CONFIGS = [
+    ("a2a_n512_f64", ["--workload", "a2a", "--steps", "2000", "--warmup", "20", "--adjoint-steps", "2000"]),
+    ("sbm_64x1024_f32", ["--workload", "sbm", "--steps", "2000", "--warmup", "20", "--adjoint-steps", "2000"]),
+    ("sbm_64x1024_f64", ["--workload", "sbm", "--dtype", "f64", "--steps", "2000", "--warmup", "20",
+                         "--adjoint-steps", "2000"]),
+    ("batch_256_f32", ["--workload", "batch", "--steps", "200", "--warmup", "20"]),
+]
+
+
+def other_configs(timeout_s: float = 300.0) -> dict:
+    """Run every entry of OTHER_CONFIGS as a child process (its progress goes to stderr) and keep
+    the figures of its JSON line: throughput, row-kernel launch time and roofline fraction, and
+    the adjoint/forward ratios where the run has them."""
+    import subprocess
+    res = {}
+    for label, extra in OTHER_CONFIGS:
+        log("other workload %s" % label)
+        cmd = [sys.executable, os.path.abspath(__file__), "--no-cpu-baseline", "--no-other-configs"] + extra
+        t0 = time.perf_counter()
+        try:
+            p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=timeout_s)
+        except subprocess.TimeoutExpired:
+            res[label] = {"error": "timed out after %.0f s" % timeout_s}
+            continue
+        lines = [x for x in p.stdout.splitlines() if x.startswith("{")]
+        if p.returncode != 0 or not lines:
+            res[label] = {"error": "exit status %d" % p.returncode}
+            continue
+        d = json.loads(lines[-1])
+        e = {"metric": d["metric"], "value": d["value"], "unit": d["unit"], "ms_per_step": d["ms_per_step"],
+             "steps": d["steps"], "dtype": d["dtype"], "workload": d["config"].get("workload"),
+             "row_kernel_avg_launch_ms": d["roofline"]["avg_launch_ms"], "roofline_frac": d["roofline"]["frac"],
+             "wall_s": time.perf_counter() - t0}
+        a = d.get("adjoint")
+        if a:
+            e["adjoint"] = {x: a[x] for x in ("steps", "ckpt_every", "ratio", "ratio_with_forward",
+                                               "ratio_from_stages", "one_workgroup")}
+        res[label] = e
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,6 +341,8 @@ def main():
                     help="graph of the ensemble workload: the equal-community SBM or the paired SBM")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the child runs of the other workloads (default workload only)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--option", action="append", default=[], help="library option key=value")
@@ -310,6 +360,10 @@ def main():
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    others = None
+    if args.workload == "het" and not args.no_other_configs:
+        others = other_configs()
 
     import torch
 
@@ -496,6 +550,8 @@ def main():
                                 "note": "Sec. 3 numerical comparison, M = 4096, four communities; the paper's "
                                         "integrator and step are not stated for this run, here fixed-step classical "
                                         "RK4 with dt = 0.01"}
+    if others is not None:
+        out["other_configs"] = others
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, %.0f s budget)" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
