@@ -87,6 +87,14 @@ const char *kur_last_error(const kur_ctx *ctx);
  *                 inter-block list; 0: every edge between communities is listed. Graphs given
  *                 block by block (kur_set_graph) keep the given layout.
  *   "pair_min"    least nodes of both communities of such a block (1..65536). Default 32.
+ *   "mask_min"    a segment (one column chunk of a block, one layer) whose stored list holds at
+ *                 least this many entries per cell (0..1e9; above 1: never) is stored instead as
+ *                 a bitmask, 1 bit per cell, in units of 128 columns per row. The kernels sum a
+ *                 bitmask row through tables of the 16 subset sums of every 4 columns, built in
+ *                 LDS per chunk (the method of four Russians for Boolean matrix-vector
+ *                 products): one table read per 4 cells instead of one staged-value read per
+ *                 list entry. Needs a chunk of at least 512 columns. The same sums in another
+ *                 order. Takes effect at the next graph set. Default 2 (off).
  *   "transpose"   1: kur_set_graph_csr / kur_set_graph_csr_w on a device context also build and
  *                 keep the layout of A^T when A is asymmetric (same block order; about the
  *                 memory of A's layout again), which the adjoint of an asymmetric A needs.
@@ -231,6 +239,10 @@ kur_status kur_batch_step(kur_ctx *ctx, double dt, int64_t nsteps, int64_t r_eve
  * (unpadded), list entries (padded, as stored), inter entries, tiles, chunk width, 1 if the
  * adjacency is symmetric, largest block size. */
 kur_status kur_graph_info(const kur_ctx *ctx, int64_t out[10]);
+
+/* Bitmask segments of the installed layout (option "mask_min"): out[0] = segments stored as
+ * bitmasks, out[1] = their bytes. KUR_ESTATE without a graph. */
+kur_status kur_graph_masks(const kur_ctx *ctx, int64_t out[2]);
 
 /* Permutation in use: perm[u] = block-order index of user node u (n entries). */
 kur_status kur_get_perm(const kur_ctx *ctx, int32_t *perm);

@@ -257,11 +257,103 @@ std::string finish(BlockGraph &g, const std::vector<int32_t> &block_of_row, cons
         std::string msg = add_dense_pairs(g, opt);
         if (!msg.empty()) return msg;
     }
+    std::string msg = to_masks(g, opt);
+    if (!msg.empty()) return msg;
     make_tiles(g, opt);
     return "";
 }
 
 }  // namespace
+
+std::string to_masks(BlockGraph &g, const BuildOptions &opt)
+{
+    g.mask.clear();
+    g.mask_segments = 0;
+    if (!(opt.mask_min <= 1.0) || g.W < kMaskMinW || g.seg_ptr.empty()) return "";
+    const int64_t n = g.n;
+    const uint16_t pad = (uint16_t)(g.W * g.esz2);
+    const size_t nsd = g.segd.size();
+    // the segments whose stored entries (padded to 8 per row) fill at least mask_min of the cells
+    std::vector<int64_t> mbase(nsd, -1);
+    int64_t units = 0;
+    for (int32_t bi = 0; bi < g.nb; ++bi) {
+        const BlkInfo &b = g.blk[bi];
+        for (int32_t ch = 0; ch < b.nchunk; ++ch) {
+            const SegD &sd = g.segd[b.sd0 + ch];
+            const int64_t sb = b.segbase + (int64_t)ch * b.size;
+            const double stored = (double)(g.seg_ptr[sb + b.size] - g.seg_ptr[sb]);
+            const double cells = (double)b.size * (double)sd.cw;
+            if (cells <= 0 || stored <= 0 || stored < opt.mask_min * cells) continue;
+            const int64_t seg_units = (int64_t)b.size * ((sd.cw + kMaskUnitCols - 1) / kMaskUnitCols);
+            if (seg_units * 16 > INT32_MAX) continue;  // the kernels address a segment with 32-bit offsets
+            mbase[b.sd0 + ch] = units;
+            units += seg_units;
+        }
+    }
+    if (units == 0) return "";
+    if (units > ((int64_t)1 << 40)) return "bitmask layout too large";
+    g.mask.assign((size_t)units * 4, 0u);
+    std::vector<int32_t> bor(n);
+    for (int32_t bi = 0; bi < g.nb; ++bi)
+        std::fill(bor.begin() + g.blk[bi].row0, bor.begin() + g.blk[bi].row0 + g.blk[bi].size, bi);
+    // fill the bits row by row (each row owns its units) and the new segment lengths
+    const int64_t tot = (int64_t)g.seg_ptr.size() - 1;
+    std::vector<int64_t> len(tot + 1, 0);
+    std::vector<int64_t> moved(n, 0);
+    ErrFlag err;
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t m = lo; m < hi && !err.bad.load(); ++m) {
+            const BlkInfo &b = g.blk[bor[m]];
+            const int64_t r = m - b.row0;
+            for (int32_t ch = 0; ch < b.nchunk; ++ch) {
+                const int64_t idx = b.segbase + (int64_t)ch * b.size + r;
+                const int64_t mb = mbase[b.sd0 + ch];
+                if (mb < 0) {
+                    len[idx + 1] = g.seg_ptr[idx + 1] - g.seg_ptr[idx];
+                    continue;
+                }
+                for (int64_t e = g.seg_ptr[idx]; e < g.seg_ptr[idx + 1]; ++e) {
+                    if (g.list[e] == pad) continue;
+                    const int64_t col = g.list[e] / g.esz2;
+                    const int64_t q = col / kMaskUnitCols, j = col % kMaskUnitCols;
+                    uint32_t &word = g.mask[(size_t)(mb + q * b.size + r) * 4 + (size_t)(j >> 5)];
+                    const uint32_t bit = 1u << (j & 31);
+                    if (word & bit) {
+                        err.set("repeated column in a list segment");
+                        break;
+                    }
+                    word |= bit;
+                    ++moved[m];
+                }
+            }
+        }
+    });
+    if (err.bad) return err.msg;
+    // the lists without the bitmask segments
+    for (int64_t i = 0; i < tot; ++i) len[i + 1] += len[i];
+    std::vector<uint16_t> list((size_t)len[tot]);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t m = lo; m < hi; ++m) {
+            const BlkInfo &b = g.blk[bor[m]];
+            const int64_t r = m - b.row0;
+            for (int32_t ch = 0; ch < b.nchunk; ++ch) {
+                const int64_t idx = b.segbase + (int64_t)ch * b.size + r;
+                if (mbase[b.sd0 + ch] >= 0) continue;
+                std::copy(g.list.begin() + g.seg_ptr[idx], g.list.begin() + g.seg_ptr[idx + 1], list.begin() + len[idx]);
+            }
+        }
+    });
+    g.list.swap(list);
+    g.seg_ptr.swap(len);
+    for (int64_t m = 0; m < n; ++m) g.list_unpadded -= moved[m];
+    for (size_t i = 0; i < nsd; ++i) {
+        if (mbase[i] < 0) continue;
+        g.segd[i].mask = 1;
+        g.segd[i].mbase = mbase[i];
+        ++g.mask_segments;
+    }
+    return "";
+}
 
 void make_tiles(BlockGraph &g, const BuildOptions &opt)
 {
@@ -278,6 +370,8 @@ void make_tiles(BlockGraph &g, const BuildOptions &opt)
             for (int32_t ch = 0; ch < b.nchunk; ++ch) {
                 int64_t idx = b.segbase + (int64_t)ch * b.size + r;
                 c += g.seg_ptr[idx + 1] - g.seg_ptr[idx];
+                // a bitmask row: cw / 8 bytes and cw / 4 conflict-free table reads
+                if (g.segd[b.sd0 + ch].mask) c += (g.segd[b.sd0 + ch].cw + 7) / 8;
             }
             rowcost[m] = c;
             total += c;
@@ -298,18 +392,19 @@ void make_tiles(BlockGraph &g, const BuildOptions &opt)
                 ++r1;
             }
             // lanes per row: about two 8-entry vectors per lane in a non-empty chunk
-            int64_t vec = 0, nonempty = 0;
+            int64_t vec = 0, nonempty = 0, masks = 0;
             for (int32_t ch = 0; ch < b.nchunk; ++ch) {
                 int64_t s0 = g.seg_ptr[b.segbase + (int64_t)ch * b.size + r];
                 int64_t s1 = g.seg_ptr[b.segbase + (int64_t)ch * b.size + r1];
                 vec += (s1 - s0) / 8;
                 nonempty += (s1 > s0);
+                masks += g.segd[b.sd0 + ch].mask;
             }
             double avg = nonempty ? (double)vec / ((double)(r1 - r) * (double)nonempty) : 0.0;
             int32_t G = 2;
             while (G < 64 && G * 2 < avg) G *= 2;
             if (opt.flat_min_vec > 0 && avg >= opt.flat_min_vec) G = 0;  // wave-streaming mode
-            if (nonempty == 0) G = -1;                                    // no list entries at all
+            if (nonempty == 0 && masks == 0) G = -1;                      // no list entries at all
             g.tiles.push_back(Tile{bi, r, r1, G});
             r = r1;
         }
@@ -478,10 +573,14 @@ std::string merge_graphs(std::vector<BlockGraph> &parts, BlockGraph &g, std::vec
             b.grp0 += goff;
             g.blk.push_back(b);
         }
+        const int64_t moff = (int64_t)g.mask.size() / 4;  // mask units before this part
         for (SegD d : p.segd) {
             d.col0 += (int32_t)roff;
+            if (d.mask) d.mbase += moff;
             g.segd.push_back(d);
         }
+        g.mask.insert(g.mask.end(), p.mask.begin(), p.mask.end());
+        g.mask_segments += p.mask_segments;
         for (Grp q : p.grp) {
             q.blk += (int32_t)boff;
             g.grp.push_back(q);
@@ -828,6 +927,8 @@ std::string build_from_csr_w(int64_t n, const int64_t *row_ptr, const int32_t *c
     diag_segments(g);
     msg = add_dense_pairs(g, opt);
     if (!msg.empty()) return msg;
+    msg = to_masks(g, opt);
+    if (!msg.empty()) return msg;
     make_tiles(g, opt);
     return "";
 }
@@ -962,7 +1063,7 @@ void diag_segments(BlockGraph &g)
         const int32_t ncc = (b.size + W - 1) / W;
         for (int32_t cc = 0; cc < ncc; ++cc)
             for (int32_t t = 1; t <= b.nlayer; ++t)
-                g.segd.push_back(SegD{b.row0 + cc * W, (int16_t)std::min(W, b.size - cc * W), (int16_t)(t <= b.mode)});
+                g.segd.push_back(SegD{b.row0 + cc * W, (int16_t)std::min(W, b.size - cc * W), (int8_t)(t <= b.mode), 0, 0});
         b.grp0 = (int32_t)g.grp.size();
         b.ngrp = b.mode > 0 ? 1 : 0;
         if (b.mode > 0) g.grp.push_back(Grp{bi, b.mode});
@@ -1068,7 +1169,7 @@ std::string add_dense_pairs(BlockGraph &g, const BuildOptions &opt)
             const int32_t ncc = (bc.size + W - 1) / W;
             for (int32_t cc = 0; cc < ncc; ++cc)
                 for (int32_t t = 1; t <= p.nlayer; ++t)
-                    segd.push_back(SegD{bc.row0 + cc * W, (int16_t)std::min(W, bc.size - cc * W), (int16_t)(t <= p.mode)});
+                    segd.push_back(SegD{bc.row0 + cc * W, (int16_t)std::min(W, bc.size - cc * W), (int8_t)(t <= p.mode), 0, 0});
             nseg += (int64_t)ncc * p.nlayer;
             grp.push_back(Grp{p.c, p.mode});
         }

@@ -61,6 +61,7 @@ struct kur_ctx {
     std::vector<int32_t> perm;
     std::vector<int32_t> deg;
     int64_t info[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t mask_info[2] = {0, 0};  // bitmask segments, their bytes
     bool symmetric = false;
     BlockGraph host_graph;  // full layout, kept by host-only contexts for introspection
     BlockGraph skel;        // device contexts: blocks, segment and inter offsets (no lists), for re-tiling
@@ -69,12 +70,14 @@ struct kur_ctx {
     double ens_tau = 0.5;        // ensembles: blocks at least this dense use the matrix cores
 
     // device graph
-    DevBuf d_blk, d_segd, d_grp, d_tiles, d_order, d_seg, d_list, d_iptr, d_icol;
+    DevBuf d_blk, d_segd, d_grp, d_tiles, d_order, d_seg, d_list, d_iptr, d_icol, d_mask;
+    DevBuf d_msum;              // per-row bitmask segment sums (k_mask), when a layout has any
+    bool masks = false, masksT = false;  // the layout (of A, of A^T) has bitmask segments
     // layout of A^T for the adjoint of an asymmetric A (option "transpose")
     int transpose = 0;
     bool has_T = false;
     int32_t ntT = 0, nlaunchT = 0, tile_rowsT = 0;
-    DevBuf d_blkT, d_segdT, d_grpT, d_tilesT, d_orderT, d_segT, d_listT, d_iptrT, d_icolT;
+    DevBuf d_blkT, d_segdT, d_grpT, d_tilesT, d_orderT, d_segT, d_listT, d_iptrT, d_icolT, d_maskT;
     // device state
     DevBuf d_omega, d_unit, d_hi, d_lo, d_wind, d_ksum, d_sc[2], d_part[2], d_sce, d_parte, d_kout, d_y;
     DevBuf d_r, d_psi;
@@ -212,10 +215,11 @@ void free_all(kur_ctx *c)
                       &c->d_r, &c->d_psi, &c->d_tile_first, &c->d_inv_n, &c->d_ctr, &c->d_ck,
                       &c->d_blkT, &c->d_segdT, &c->d_grpT, &c->d_tilesT, &c->d_orderT, &c->d_segT,
                       &c->d_listT, &c->d_iptrT, &c->d_icolT, &c->d_rsc, &c->d_rac, &c->d_perm, &c->d_opart,
-                      &c->d_yb[0], &c->d_yb[1]};
+                      &c->d_yb[0], &c->d_yb[1], &c->d_mask, &c->d_maskT, &c->d_msum};
     for (DevBuf *b : bufs) dfree(*b);
     free_adj(c->adj);
     c->has_T = false;
+    c->masks = c->masksT = false;
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
 }
@@ -237,11 +241,13 @@ DevGraph devgraph(const kur_ctx *c)
     g.order = (const int32_t *)c->d_order.p;
     g.seg_ptr = (const int64_t *)c->d_seg.p;
     g.list = (const uint16_t *)c->d_list.p;
+    g.mask = (const uint32_t *)c->d_mask.p;
     g.inter_ptr = (const int64_t *)c->d_iptr.p;
     g.inter_col = (const int32_t *)c->d_icol.p;
     g.W = c->W;
     g.tile_rows = c->tile_rows;
     g.nlaunch = c->nlaunch;
+    g.msum = c->masks ? c->d_msum.p : nullptr;
     return g;
 }
 
@@ -256,6 +262,8 @@ DevGraph devgraph_t(const kur_ctx *c)
     g.order = (const int32_t *)c->d_orderT.p;
     g.seg_ptr = (const int64_t *)c->d_segT.p;
     g.list = (const uint16_t *)c->d_listT.p;
+    g.mask = (const uint32_t *)c->d_maskT.p;
+    g.msum = c->masksT ? c->d_msum.p : nullptr;
     g.inter_ptr = (const int64_t *)c->d_iptrT.p;
     g.inter_col = (const int32_t *)c->d_icolT.p;
     g.W = c->W;
@@ -462,6 +470,7 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
             (e = upload(c->d_order, g.order.data(), sizeof(int32_t) * g.order.size(), c->stream)) != hipSuccess ||
             (e = upload(c->d_seg, g.seg_ptr.data(), sizeof(int64_t) * g.seg_ptr.size(), c->stream)) != hipSuccess ||
             (e = upload(c->d_list, g.list.data(), sizeof(uint16_t) * g.list.size(), c->stream)) != hipSuccess ||
+            (e = upload(c->d_mask, g.mask.data(), sizeof(uint32_t) * g.mask.size(), c->stream)) != hipSuccess ||
             (e = upload(c->d_iptr, g.inter_ptr.data(), sizeof(int64_t) * g.inter_ptr.size(), c->stream)) != hipSuccess ||
             (e = upload(c->d_icol, g.inter_col.data(), sizeof(int32_t) * g.inter_col.size(), c->stream)) != hipSuccess ||
             (e = dalloc(c->d_omega, T * n)) != hipSuccess || (e = dalloc(c->d_hi, T * n)) != hipSuccess ||
@@ -473,7 +482,8 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
             (e = dalloc(c->d_parte, 2 * T * g.tiles.size())) != hipSuccess ||
             (e = dalloc(c->d_kout, T * n)) != hipSuccess || (e = dalloc(c->d_y, T * n)) != hipSuccess ||
             (e = upload(c->d_perm, g.perm.data(), sizeof(int32_t) * n, c->stream)) != hipSuccess ||
-            (e = dalloc(c->d_yb[0], T * n)) != hipSuccess || (e = dalloc(c->d_yb[1], T * n)) != hipSuccess) {
+            (e = dalloc(c->d_yb[0], T * n)) != hipSuccess || (e = dalloc(c->d_yb[1], T * n)) != hipSuccess ||
+            (g.mask_segments > 0 && (e = dalloc(c->d_msum, 2 * T * n)) != hipSuccess)) {
             free_all(c);
             c->has_graph = false;
             return hip_fail(c, e, "graph upload");
@@ -499,6 +509,10 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
     int64_t smax = 0;
     for (const BlkInfo &b : g.blk) smax = std::max<int64_t>(smax, b.size);
     c->info[9] = smax;
+    c->mask_info[0] = g.mask_segments;
+    c->mask_info[1] = (int64_t)g.mask.size() * 4;
+    c->masks = g.mask_segments > 0;
+    c->masksT = false;
     c->symmetric = g.symmetric;
     c->tiles_installed.threads = c->threads;
     c->tiles_installed.tile_rows = g.tile_rows;
@@ -568,6 +582,7 @@ kur_status install_transpose(kur_ctx *c, int64_t n, const int64_t *row_ptr, cons
                              const int32_t *weight, const int32_t *labels)
 {
     c->has_T = false;
+    c->masksT = false;
     if (c->host_only || c->symmetric || !c->transpose) return KUR_OK;
     BlockGraph t;
     std::string msg;
@@ -591,11 +606,14 @@ kur_status install_transpose(kur_ctx *c, int64_t n, const int64_t *row_ptr, cons
         (e = upload(c->d_orderT, t.order.data(), sizeof(int32_t) * t.order.size(), c->stream)) != hipSuccess ||
         (e = upload(c->d_segT, t.seg_ptr.data(), sizeof(int64_t) * t.seg_ptr.size(), c->stream)) != hipSuccess ||
         (e = upload(c->d_listT, t.list.data(), sizeof(uint16_t) * t.list.size(), c->stream)) != hipSuccess ||
+        (e = upload(c->d_maskT, t.mask.data(), sizeof(uint32_t) * t.mask.size(), c->stream)) != hipSuccess ||
+        (t.mask_segments > 0 && (e = dalloc(c->d_msum, 2 * (size_t)c->esz * (size_t)c->n)) != hipSuccess) ||
         (e = upload(c->d_iptrT, t.inter_ptr.data(), sizeof(int64_t) * t.inter_ptr.size(), c->stream)) != hipSuccess ||
         (e = upload(c->d_icolT, t.inter_col.data(), sizeof(int32_t) * t.inter_col.size(), c->stream)) != hipSuccess)
         return hip_fail(c, e, "transposed layout upload");
     c->ntT = (int32_t)t.tiles.size();
     c->nlaunchT = (int32_t)t.order.size();
+    c->masksT = t.mask_segments > 0;
     c->tile_rowsT = t.tile_rows;
     c->has_T = true;
     return KUR_OK;
@@ -753,6 +771,9 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
     } else if (k == "pairs") {
         if (v != 0 && v != 1) return fail(c, KUR_EINVAL, "pairs must be 0 or 1");
         c->bopt.pairs = v != 0;
+    } else if (k == "mask_min") {
+        if (!(v >= 0.0) || v > 1e9) return fail(c, KUR_EINVAL, "mask_min must be in [0, 1e9]");
+        c->bopt.mask_min = v;
     } else if (k == "pair_min") {
         if (v != (int64_t)v || v < 1 || v > 65536) return fail(c, KUR_EINVAL, "pair_min must be an integer in [1, 65536]");
         c->bopt.pair_min = (int32_t)v;
@@ -878,6 +899,15 @@ kur_status kur_graph_info(const kur_ctx *c, int64_t out[10])
     return KUR_OK;
 }
 
+kur_status kur_graph_masks(const kur_ctx *c, int64_t out[2])
+{
+    if (!c || !out) return KUR_EINVAL;
+    if (!c->has_graph) return KUR_ESTATE;
+    out[0] = c->mask_info[0];
+    out[1] = c->mask_info[1];
+    return KUR_OK;
+}
+
 kur_status kur_get_perm(const kur_ctx *c, int32_t *perm)
 {
     if (!c || !perm) return KUR_EINVAL;
@@ -899,6 +929,33 @@ kur_status kur_get_blocks(const kur_ctx *c, int64_t *block_ptr, uint8_t *mode)
     return KUR_OK;
 }
 
+// The chunk-relative columns of segment ch of block-local row r, ascending, from its list or its
+// bitmask; f(col) returns false to stop (then so does this call).
+extern "C++" template <typename F>
+bool seg_row_cols(const BlockGraph &g, const BlkInfo &bi, int32_t ch, int64_t r, F &&f)
+{
+    const SegD &sd = g.segd[bi.sd0 + ch];
+    if (sd.mask) {
+        const int64_t nq = (sd.cw + kMaskUnitCols - 1) / kMaskUnitCols;
+        for (int64_t q = 0; q < nq; ++q)
+            for (int w = 0; w < 4; ++w) {
+                uint32_t x = g.mask[(size_t)(sd.mbase + q * bi.size + r) * 4 + w];
+                while (x) {
+                    const int t = __builtin_ctz(x);
+                    x &= x - 1;
+                    if (!f((int32_t)(q * kMaskUnitCols + 32 * w + t))) return false;
+                }
+            }
+        return true;
+    }
+    const int64_t idx = bi.segbase + (int64_t)ch * bi.size + r;
+    for (int64_t e = g.seg_ptr[idx]; e < g.seg_ptr[idx + 1]; ++e) {
+        if (g.list[e] == (uint16_t)(g.W * g.esz2)) continue;  // padding
+        if (!f((int32_t)(g.list[e] / g.esz2))) return false;
+    }
+    return true;
+}
+
 kur_status kur_get_row_lists(const kur_ctx *c, int64_t row, int32_t *list, int64_t *nlist, int32_t *inter,
                              int64_t *ninter)
 {
@@ -914,15 +971,15 @@ kur_status kur_get_row_lists(const kur_ctx *c, int64_t row, int32_t *list, int64
     for (int32_t ch = 0; ch < bi.nchunk; ++ch) {
         const SegD &sd = g.segd[bi.sd0 + ch];
         if (sd.col0 < bi.row0 || sd.col0 >= bi.row0 + bi.size) continue;  // a dense off-diagonal block
-        const int64_t idx = bi.segbase + (int64_t)ch * bi.size + r;
-        for (int64_t e = g.seg_ptr[idx]; e < g.seg_ptr[idx + 1]; ++e) {
-            if (g.list[e] == (uint16_t)(g.W * g.esz2)) continue;  // padding
+        const bool ok = seg_row_cols(g, bi, ch, r, [&](int32_t col) {
             if (list) {
-                if (k >= *nlist) return KUR_EINVAL;
-                list[k] = sd.col0 - bi.row0 + g.list[e] / g.esz2;
+                if (k >= *nlist) return false;
+                list[k] = sd.col0 - bi.row0 + col;
             }
             ++k;
-        }
+            return true;
+        });
+        if (!ok) return KUR_EINVAL;
     }
     const int64_t ni = g.inter_ptr[row + 1] - g.inter_ptr[row];
     if (inter) {
@@ -951,16 +1008,16 @@ kur_status kur_get_row_layers(const kur_ctx *c, int64_t row, int32_t *cols, int3
         // the layers of one column chunk are consecutive segments
         layer_no = sd.col0 == last_col0 ? layer_no + 1 : 1;
         last_col0 = sd.col0;
-        const int64_t idx = bi.segbase + (int64_t)ch * bi.size + r;
-        for (int64_t e = g.seg_ptr[idx]; e < g.seg_ptr[idx + 1]; ++e) {
-            if (g.list[e] == (uint16_t)(g.W * g.esz2)) continue;  // padding
+        const bool ok = seg_row_cols(g, bi, ch, r, [&](int32_t col) {
             if (cols || layer) {
-                if (k >= *count) return KUR_EINVAL;
-                if (cols) cols[k] = sd.col0 + g.list[e] / g.esz2;
+                if (k >= *count) return false;
+                if (cols) cols[k] = sd.col0 + col;
                 if (layer) layer[k] = layer_no;
             }
             ++k;
-        }
+            return true;
+        });
+        if (!ok) return KUR_EINVAL;
     }
     *count = k;
     return KUR_OK;

@@ -31,13 +31,25 @@ struct BlkInfo {
     int32_t sd0;      // first segment descriptor of this block
 };
 
-// One segment of a row block: the columns [col0, col0 + cw) (block order) staged in LDS, and
-// whether its list holds zeros (subtracted) or ones (added).
+// One segment of a row block: the columns [col0, col0 + cw) (block order), whether its entries
+// are zeros (subtracted from the localised order parameters) or ones (added), and how they are
+// stored. mask == 0: a 16-bit list per row (seg_ptr, list), read against the chunk staged in LDS.
+// mask == 1: a bitmask of kMaskUnitCols-column units, unit q of local row r at
+// mask[mbase + q * size + r] (size = rows of the row block); bit j of 32-bit word w of unit q is
+// column kMaskUnitCols * q + 32 w + j of the segment. Such a segment's list is empty.
 struct SegD {
     int32_t col0;
     int16_t cw;
-    int16_t zeros;
+    int8_t zeros;
+    int8_t mask;
+    int64_t mbase;
 };
+
+// Columns of one bitmask unit (four 32-bit words, one 16-byte load).
+constexpr int32_t kMaskUnitCols = 128;
+// Least chunk width for bitmask segments: the subset-sum tables of a quarter of the chunk
+// (16 entries per 4 columns) must cover at least one unit.
+constexpr int32_t kMaskMinW = 4 * kMaskUnitCols;
 
 // A column block whose localised order parameters enter every row of a row block with factor
 // mode (the prevalent value of that submatrix): the diagonal block when dense, and every dense
@@ -68,6 +80,8 @@ struct BuildOptions {
     int32_t xcds = 1;           // launch order for this many round-robin XCDs (1: plain largest first)
     bool pairs = true;          // dense off-diagonal blocks use localised order parameters
     int32_t pair_min = 32;      // least rows and columns of such a block
+    double mask_min = 2.0;      // a segment holding at least this many list entries per cell is
+                                // stored as a bitmask (needs W >= kMaskMinW); above 1: never
 };
 
 // The graph in block order, ready for upload.
@@ -84,6 +98,8 @@ struct BlockGraph {
     std::vector<int64_t> seg_ptr;     // total segments + 1 (segment-major inside every block)
     std::vector<uint16_t> list;       // chunk-relative LDS byte offset (col * esz2), segments
                                       // padded to 8 entries with W * esz2 (the zero slot)
+    std::vector<uint32_t> mask;       // bitmask segments, 4 words per unit (see SegD)
+    int64_t mask_segments = 0;        // segment descriptors stored as bitmasks
     std::vector<int64_t> inter_ptr;   // n + 1, block order
     std::vector<int32_t> inter_col;   // block-order columns
     std::vector<Tile> tiles;
@@ -139,6 +155,13 @@ void diag_segments(BlockGraph &g);
 // block. Rebuilds seg_ptr, list, segd, grp, the inter CSR and the tiles; a no-op when
 // opt.pairs is false or no block is dense.
 std::string add_dense_pairs(BlockGraph &g, const BuildOptions &opt);
+
+// Stores every segment whose list (entries padded to 8 per row) fills at least opt.mask_min of
+// its cells as a bitmask (see SegD) and removes it from the lists; a no-op when mask_min is
+// above 1 or W < kMaskMinW. Runs after the segments are final, before the tiles are cut. The
+// kernels sum a bitmask segment's row through subset-sum tables of four columns (the method of
+// four Russians for Boolean matrix-vector products): one table read per four cells.
+std::string to_masks(BlockGraph &g, const BuildOptions &opt);
 
 // The complete graph on n nodes: one dense block whose list of zeros is empty.
 std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &out);

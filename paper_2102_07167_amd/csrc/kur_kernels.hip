@@ -41,6 +41,22 @@ __device__ __forceinline__ u32x4 list_load(__amdgpu_buffer_rsrc_t r, uint32_t i)
     return __builtin_amdgcn_raw_buffer_load_b128(r, (int)(i * 16u), 0, KUR_LIST_CPOL);
 }
 
+// Buffer resource over the bytes [p, p + bytes), where p and bytes are the same in every lane of
+// the wave. Built from readfirstlane copies so that the compiler keeps it in scalar registers;
+// from values it cannot prove uniform (loaded from memory) it would otherwise wrap every load in
+// a loop over the lanes' distinct resources.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void *p, int64_t bytes)
+{
+    // readfirstlane returns int: each half goes through uint32_t before widening, or a low half
+    // with bit 31 set would sign-extend into the high half
+    const uint64_t a = (uint64_t)p;
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint64_t au = ((uint64_t)hi << 32) | (uint64_t)lo;
+    return __builtin_amdgcn_make_buffer_rsrc((void *)au, (short)0, __builtin_amdgcn_readfirstlane((int)bytes),
+                                             0x00020000);
+}
+
 
 // Sum v over the workgroup in a fixed order and store it to *out (thread 0).
 template <typename VT, int NT>
@@ -154,8 +170,155 @@ __device__ __forceinline__ void gather8(const VT *lds, const u32x4 q, VT &acc)
     }
 }
 
+// Slots of the staging area beyond the chunk: slot W is the zero slot of the lists' padding; the
+// subset-sum tables of a bitmask sub-chunk of at most W/4 columns take 16 (W/16 + 1) <= W + 16
+// slots.
+constexpr int kXsSlack = 17;
+
+// The 16 subset sums of four values x0..x3, entry m = sum of x_j over the set bits j of m, stored
+// at t[m * P] (P: the table pitch). Each entry is a smaller entry plus one value, in a fixed order:
+// t[m] = t[m without its lowest set bit] + x[that bit].
+template <typename VT>
+__device__ __forceinline__ void subset_sums4(VT *t, int P, const VT x0, const VT x1, const VT x2, const VT x3)
+{
+    auto add = [](VT a, const VT &b) {
+        vacc(a, b);
+        return a;
+    };
+    // stored four at a time, so that few sums are live at once (the row kernel's register budget)
+    t[0] = vzero<VT>();
+    t[P] = x0;
+    t[2 * P] = x1;
+    t[3 * P] = add(x1, x0);
+    __builtin_amdgcn_sched_barrier(0);
+    t[4 * P] = x2;
+    t[5 * P] = add(x2, x0);
+    const VT v6 = add(x2, x1);
+    t[6 * P] = v6;
+    t[7 * P] = add(v6, x0);
+    __builtin_amdgcn_sched_barrier(0);
+    t[8 * P] = x3;
+    t[9 * P] = add(x3, x0);
+    const VT v10 = add(x3, x1);
+    t[10 * P] = v10;
+    t[11 * P] = add(v10, x0);
+    __builtin_amdgcn_sched_barrier(0);
+    const VT v12 = add(x3, x2);
+    t[12 * P] = v12;
+    t[13 * P] = add(v12, x0);
+    const VT v14 = add(v12, x1);
+    t[14 * P] = v14;
+    t[15 * P] = add(v14, x0);
+}
+
+// Add to acc the row sums of one 128-column bitmask unit: per nibble (4 columns, in column
+// order) one read of the subset-sum table of that column group. tb points at the unit's first
+// group; entry m of group j sits at tb[m * P + j]. With an odd pitch, the lanes of a wave (rows,
+// all at the same group) read distinct banks for distinct entries.
+template <typename VT>
+__device__ __forceinline__ void mask_unit(const VT *tb, int P, const u32x4 u, VT &acc)
+{
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+            const uint32_t m = (w[k] >> (4 * n)) & 15u;
+            vacc(acc, tb[m * (uint32_t)P + (uint32_t)(8 * k + n)]);
+        }
+        // one word's eight reads in flight at a time (the row kernel's register budget): an empty
+        // statement that no memory access may cross
+        asm volatile("" ::: "memory");
+    }
+}
+
+// Row sums of the bitmask segments (see SegD) of one tile per workgroup, into g.msum (block
+// order; zero for rows without any): for a segment of ones the sum of x over the row's set bits,
+// for a segment of zeros minus that sum (subtracted from the localised order parameters, Sec. 3,
+// eq. KuramotoGraphApproach). Per sub-chunk of at most W/4 columns the workgroup builds in LDS the
+// 16 subset sums of every 4 columns (the method of four Russians for Boolean matrix-vector
+// products); then thread r mod NT owns row r, keeps four 16-byte units of its bits in flight and
+// adds one table entry per nibble. x_in holds the values summed (the tile kernel's staged pairs).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_mask(DevGraph g, const typename V2<T>::type *__restrict__ x_in)
+{
+    using VT = typename V2<T>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int W = g.W;
+    VT *xs = reinterpret_cast<VT *>(smem);  // W + kXsSlack table slots
+    VT *macc = xs + W + kXsSlack;           // tile_rows partial sums
+    const int tile_id = g.order[blockIdx.x];
+    if (tile_id < 0) return;  // empty slot of the XCD-aware launch order
+    const Tile tl = g.tiles[tile_id];
+    const BlkInfo bi = g.blk[tl.block];
+    const int nrows = tl.r1 - tl.r0;
+    const int rowbase = bi.row0 + tl.r0;
+    for (int r = threadIdx.x; r < nrows; r += NT) macc[r] = vzero<VT>();
+    const int S = (W >> 2) & ~(kMaskUnitCols - 1);
+    for (int c = 0; c < bi.nchunk; ++c) {
+        const SegD sd = g.segd[bi.sd0 + c];
+        if (!__builtin_amdgcn_readfirstlane(sd.mask)) continue;
+        const T sign = sd.zeros ? T(-1) : T(1);
+        const int cw = __builtin_amdgcn_readfirstlane((int)sd.cw);
+        const int col0 = __builtin_amdgcn_readfirstlane(sd.col0);
+        const int nq = (cw + kMaskUnitCols - 1) / kMaskUnitCols;
+        const uint32_t ustride = (uint32_t)bi.size;  // units of one row are size apart
+        const __amdgpu_buffer_rsrc_t Mt = uniform_rsrc(g.mask + 4 * sd.mbase, (int64_t)bi.size * nq * 16);
+        for (int s0 = 0; s0 < cw; s0 += S) {
+            const int ncol = min(S, cw - s0);
+            // tables for every group of the units touched (a unit's bits past the segment are zero
+            // and read entry 0 of their group, which must exist and be zero); an odd pitch, and
+            // 16 P <= W + 16 slots since ng <= S / 4 <= W / 16
+            const int ng = (ncol + kMaskUnitCols - 1) / kMaskUnitCols * (kMaskUnitCols / 4);
+            const int P = ng | 1;
+            const int qa = s0 / kMaskUnitCols, qb = (s0 + ncol + kMaskUnitCols - 1) / kMaskUnitCols;
+            // the first four units of the thread's first row load while the tables are built
+            u32x4 u0 = {0u, 0u, 0u, 0u}, u1 = u0, u2 = u0, u3 = u0;
+            if ((int)threadIdx.x < nrows) {
+                const uint32_t rr = (uint32_t)(tl.r0 + (int)threadIdx.x);
+                u0 = list_load(Mt, (uint32_t)qa * ustride + rr);
+                if (qa + 1 < qb) u1 = list_load(Mt, (uint32_t)(qa + 1) * ustride + rr);
+                if (qa + 2 < qb) u2 = list_load(Mt, (uint32_t)(qa + 2) * ustride + rr);
+                if (qa + 3 < qb) u3 = list_load(Mt, (uint32_t)(qa + 3) * ustride + rr);
+            }
+            __syncthreads();  // the previous sub-chunk's readers of the tables are done
+            for (int j = threadIdx.x; j < ng; j += NT) {
+                const int c0 = col0 + s0 + 4 * j, c1 = col0 + s0 + ncol;
+                const VT x0 = c0 < c1 ? x_in[c0] : vzero<VT>();
+                const VT x1 = c0 + 1 < c1 ? x_in[c0 + 1] : vzero<VT>();
+                const VT x2 = c0 + 2 < c1 ? x_in[c0 + 2] : vzero<VT>();
+                const VT x3 = c0 + 3 < c1 ? x_in[c0 + 3] : vzero<VT>();
+                subset_sums4(xs + j, P, x0, x1, x2, x3);
+            }
+            __syncthreads();
+            for (int r = threadIdx.x; r < nrows; r += NT) {
+                const uint32_t rr = (uint32_t)(tl.r0 + r);
+                if (r != (int)threadIdx.x) {  // a later row of this thread
+                    u0 = list_load(Mt, (uint32_t)qa * ustride + rr);
+                    if (qa + 1 < qb) u1 = list_load(Mt, (uint32_t)(qa + 1) * ustride + rr);
+                    if (qa + 2 < qb) u2 = list_load(Mt, (uint32_t)(qa + 2) * ustride + rr);
+                    if (qa + 3 < qb) u3 = list_load(Mt, (uint32_t)(qa + 3) * ustride + rr);
+                }
+                VT acc = vzero<VT>();
+                for (int q = qa; q < qb; ++q) {
+                    // units in column order; the one four ahead replaces the one just read
+                    mask_unit(xs + 32 * (q - qa), P, u0, acc);
+                    u0 = u1;
+                    u1 = u2;
+                    u2 = u3;
+                    if (q + 4 < qb) u3 = list_load(Mt, (uint32_t)(q + 4) * ustride + rr);
+                }
+                vacc(macc[r], vscale(acc, sign));  // row r's own thread, in segment order
+            }
+        }
+    }
+    VT *out = reinterpret_cast<VT *>(g.msum) + rowbase;
+    for (int r = threadIdx.x; r < nrows; r += NT) out[r] = macc[r];
+}
+
 // LDS layout of a tile workgroup (bytes are computed by rows_lds_bytes):
-//   xs[W + 1] staged chunk values (slot W all zero) | acc[tile_rows] | red[NT/64 + 1] | bnd[tile_rows + 1]
+//   xs[W + kXsSlack] staged chunk values (slot W all zero while a list is read), or the subset-sum
+//   tables of a bitmask segment | acc[tile_rows] | red[NT/64 + 1] | bnd[tile_rows + 1]
 template <typename VT, int NT>
 struct TileLds {
     VT *xs;
@@ -165,7 +328,7 @@ struct TileLds {
     __device__ TileLds(unsigned char *smem, int W, int tile_rows)
     {
         xs = reinterpret_cast<VT *>(smem);
-        acc = xs + W + 1;
+        acc = xs + W + kXsSlack;
         red = acc + tile_rows;
         bnd = reinterpret_cast<int *>(red + NT / 64 + 1);
     }
@@ -258,12 +421,13 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
     const int rb = (int)(((int64_t)nrows * (wv + 1)) / (NT / 64));
 
     for (int c = 0; c < nchunk; ++c) {
+        const SegD sd = g.segd[bi.sd0 + c];
+        // a list (or bitmask) of zeros is subtracted from the localised order parameters
+        const T sign = sd.zeros ? T(-1) : T(1);
+        if (sd.mask) continue;  // summed by k_mask into g.msum, added below
         const int64_t sb = bi.segbase + (int64_t)c * bi.size;
         const int64_t e0 = g.seg_ptr[sb + tl.r0], e1 = g.seg_ptr[sb + tl.r1];
         if (e0 == e1) continue;  // uniform over the workgroup
-        const SegD sd = g.segd[bi.sd0 + c];
-        // a list of zeros is subtracted from the localised order parameters
-        const T sign = sd.zeros ? T(-1) : T(1);
         __syncthreads();  // previous segment's gathers are done
         if (sd.col0 != staged) {
             for (int j = threadIdx.x; j < sd.cw; j += NT) L.xs[j] = x_in[sd.col0 + j];
@@ -273,8 +437,7 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
         for (int r = threadIdx.x; r <= nrows; r += NT) L.bnd[r] = (int)((g.seg_ptr[sb + tl.r0 + r] - e0) >> 3);
         __syncthreads();
         // the tile's list vectors of this chunk, [e0, e1) entries
-        const __amdgpu_buffer_rsrc_t Lt =
-            __builtin_amdgcn_make_buffer_rsrc((void *)(g.list + e0), (short)0, (int)((e1 - e0) * 2), 0x00020000);
+        const __amdgpu_buffer_rsrc_t Lt = uniform_rsrc(g.list + e0, (e1 - e0) * 2);
         if (flat) {
             // rows [ra, rb) occupy the contiguous 8-entry vectors [va, va + nvec) of this chunk
             const int va = __builtin_amdgcn_readfirstlane(L.bnd[ra]);
@@ -338,6 +501,15 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
                 if (lane == G - 1) vacc(L.acc[r], vscale(acc, sign));
             }
         }
+    }
+
+    // the rows' sums over the bitmask segments (written by k_mask before this launch), added by
+    // thread r mod NT once the list pass's leaders have finished with acc; the barriers below
+    // order them before the epilogue reads acc
+    if (g.msum) {  // uniform (a kernel argument)
+        __syncthreads();
+        const VT *ms = reinterpret_cast<const VT *>(g.msum) + rowbase;
+        for (int r = threadIdx.x; r < nrows; r += NT) vacc(L.acc[r], ms[r]);
     }
 
     // edges between blocks: straightforward summation from the global table. The tile's rows
@@ -832,10 +1004,26 @@ hipError_t launch_sc_init(const DevGraph &g, int ntiles, const T *y, void *sc, v
     });
 }
 
+// Bitmask segment sums of every tile into g.msum, before a tile kernel that adds them (no-op
+// for a layout without bitmask segments). x_in: the pairs that tile kernel stages. Always 256
+// threads (the row loop covers any tile height), whatever the tile kernel's workgroup size.
+template <typename T>
+hipError_t launch_mask(const DevGraph &g, const void *x_in, hipStream_t st)
+{
+    if (!g.msum || g.nlaunch <= 0) return hipSuccess;
+    constexpr int NT = 256;
+    const size_t lds = ((size_t)(g.W + kXsSlack) + (size_t)g.tile_rows) * 2 * sizeof(T);
+    hipError_t e = dyn_lds_attr<&k_mask<T, NT>>();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_mask<T, NT>), dim3(g.nlaunch), dim3(NT), lds, st, g,
+                       reinterpret_cast<const typename V2<T>::type *>(x_in));
+    return hipGetLastError();
+}
+
 size_t rows_lds_bytes(int elem_bytes, int W, int tile_rows, int threads)
 {
     const size_t vt = (size_t)2 * elem_bytes;
-    size_t b = (size_t)(W + 1) * vt + (size_t)tile_rows * vt + (size_t)(threads / 64 + 1) * vt +
+    size_t b = (size_t)(W + kXsSlack) * vt + (size_t)tile_rows * vt + (size_t)(threads / 64 + 1) * vt +
                (size_t)(tile_rows + 1) * 4;
     return (b + 15) & ~size_t(15);
 }
@@ -844,6 +1032,8 @@ template <typename T>
 hipError_t launch_rows(const DevGraph &g, int ntiles, const RowArgs<T> &a, int threads, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
+    hipError_t em = launch_mask<T>(g, a.sc_in, st);
+    if (em != hipSuccess) return em;
     const size_t lds = rows_lds_bytes(sizeof(T), g.W, g.tile_rows, threads);
     const bool yg = a.y_in != nullptr;
     return with_nt(threads, [&](auto nt) -> hipError_t {
@@ -862,6 +1052,8 @@ template <typename T>
 hipError_t launch_emb(const DevGraph &g, const EmbArgs<T> &a, int threads, hipStream_t st)
 {
     if (g.nlaunch <= 0) return hipSuccess;
+    hipError_t em = launch_mask<T>(g, a.sc_in, st);
+    if (em != hipSuccess) return em;
     const size_t lds = rows_lds_bytes(sizeof(T), g.W, g.tile_rows, threads);
     return with_nt(threads, [&](auto nt) -> hipError_t {
         constexpr int NT = decltype(nt)::value;
@@ -883,6 +1075,8 @@ template <typename T>
 hipError_t launch_vjp(const DevGraph &g, int ntiles, const VjpArgs<T> &a, int threads, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
+    hipError_t em = launch_mask<T>(g, a.x_in, st);
+    if (em != hipSuccess) return em;
     const size_t lds = rows_lds_bytes(sizeof(T), g.W, g.tile_rows, threads);
     return with_nt(threads, [&](auto nt) -> hipError_t {
         constexpr int NT = decltype(nt)::value;

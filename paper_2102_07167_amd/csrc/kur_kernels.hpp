@@ -18,11 +18,15 @@ struct DevGraph {
     const int32_t *order;
     const int64_t *seg_ptr;
     const uint16_t *list;
+    const uint32_t *mask;  // bitmask segments, 4 words per unit (see SegD)
     const int64_t *inter_ptr;
     const int32_t *inter_col;
     int32_t W;
     int32_t tile_rows;
     int32_t nlaunch;  // entries of order (workgroups of a tile launch); -1 entries are empty slots
+    void *msum;       // per row (block order) the sum over its bitmask segments, one (x, y) pair of
+                      // the dtype, written by k_mask before every tile-kernel launch; null when the
+                      // layout has no bitmask segment
 };
 
 // Arguments of one row-kernel launch (one RK stage, or a plain evaluation when stage == 0).

@@ -40,6 +40,7 @@ SIGNATURES = {
     "kur_get_block_groups": (ST, [P, I32, P, P, P]),
     "kur_graph_pairs": (ST, [P, P]),
     "kur_graph_info": (ST, [P, P]),
+    "kur_graph_masks": (ST, [P, P]),
     "kur_get_perm": (ST, [P, P]),
     "kur_get_blocks": (ST, [P, P, P]),
     "kur_get_row_lists": (ST, [P, I64, P, P, P, P]),
@@ -220,6 +221,12 @@ class Kuramoto:
         md = np.empty(max(cnt.value, 1), dtype=np.int32)
         self._chk(self._L.kur_get_block_groups(self._h, int(b), _ptr(blk), _ptr(md), ctypes.byref(cnt)))
         return blk[: cnt.value], md[: cnt.value]
+
+    def graph_masks(self) -> dict:
+        """Bitmask segments of the installed layout (option "mask_min"): their count and bytes."""
+        out = np.zeros(2, dtype=np.int64)
+        self._chk(self._L.kur_graph_masks(self._h, _ptr(out)))
+        return {"mask_segments": int(out[0]), "mask_bytes": int(out[1])}
 
     def graph_pairs(self) -> int:
         """Number of dense off-diagonal blocks of the installed graph."""

@@ -429,3 +429,90 @@ def test_transpose_option_values():
         g = gen.random_dense(50, 0.3, rng, symmetric=False)
         k.set_graph(g)
         assert k.graph_info()["symmetric"] == 0
+
+
+# ------------------------------------------------------------------------------------------------
+# Bitmask segments (option "mask_min")
+# ------------------------------------------------------------------------------------------------
+
+def _same_rows(k1, k2, n, off=0):
+    """Row lists and layers of k2 (rows shifted by off) equal those of k1."""
+    for m in range(n):
+        a1, b1 = k1.row_lists(m)
+        a2, b2 = k2.row_lists(m + off)
+        assert np.array_equal(a1, a2) and np.array_equal(b1 + off, b2), m
+        c1, l1 = k1.row_layers(m)
+        c2, l2 = k2.row_layers(m + off)
+        assert np.array_equal(c1 + off, c2) and np.array_equal(l1, l2), m
+
+
+@pytest.mark.parametrize("mask_min", [0.0, 0.1])
+def test_mask_segments_match_lists(mask_min):
+    """With bitmask segments the layout holds the same entries as with lists: every row's listed
+    columns, layers and inter entries are unchanged, the adjacency rebuilds exactly, and the
+    lists keep only the segments below the threshold."""
+    rng = np.random.default_rng(81)
+    sizes = np.array([700, 1, 64, 1300, 7, 530])
+    rho = np.array([0.9, 0.5, 0.3, 0.6, 1.0, 0.97])
+    g = gen.sbm(sizes, rho, 0.004, key=777, uperm=rng.permutation(sizes.sum()).astype(np.int32))
+    with host_ctx(chunk=512, tile_rows=64) as k0, host_ctx(chunk=512, tile_rows=64, mask_min=mask_min) as k1:
+        k0.set_graph(g)
+        k1.set_graph(g)
+        assert k0.graph_masks() == {"mask_segments": 0, "mask_bytes": 0}
+        ms = k1.graph_masks()
+        assert ms["mask_segments"] > 0
+        i0, i1 = k0.graph_info(), k1.graph_info()
+        assert i1["list_padded"] < i0["list_padded"] and i1["list_entries"] < i0["list_entries"]
+        assert i1["inter_entries"] == i0["inter_entries"]
+        # 16 bytes per 128-column unit and row of every bitmask segment
+        assert ms["mask_bytes"] % 16 == 0
+        _same_rows(k0, k1, g.n)
+        check_layout(k1, g, 0.5)
+    # below the least chunk width nothing is converted
+    with host_ctx(chunk=448, mask_min=0.0) as k:
+        k.set_graph(g)
+        assert k.graph_masks()["mask_segments"] == 0
+
+
+def test_mask_segments_weighted_and_pairs():
+    """Weighted layers and dense off-diagonal blocks convert segment by segment as well."""
+    rng = np.random.default_rng(82)
+    gw = gen.weighted_sbm([600, 1, 70, 650], [2, 0, 0, 3], 0.25, 4, 0.03, rng,
+                          uperm=rng.permutation(1321).astype(np.int32))
+    V = np.zeros((3, 3), dtype=np.int32)
+    V[0, 0] = V[1, 1] = V[0, 1] = V[1, 0] = 1
+    gp = _pair_graph(rng, [600, 540, 40], V)
+    for g in (gw, gp):
+        with host_ctx(chunk=512, tile_rows=64) as k0, host_ctx(chunk=512, tile_rows=64, mask_min=0.0) as k1:
+            k0.set_graph(g)
+            k1.set_graph(g)
+            assert k1.graph_masks()["mask_segments"] > 0
+            assert k1.graph_pairs() == k0.graph_pairs()
+            _same_rows(k0, k1, g.n)
+        if g is gw:
+            with host_ctx(chunk=512, tile_rows=64, mask_min=0.0) as k:
+                k.set_graph(g)
+                check_weighted_layout(k, g)
+        else:
+            with host_ctx(chunk=512, tile_rows=64, mask_min=0.0) as k:
+                k.set_graph(g)
+                check_layout(k, g, 0.5)
+
+
+def test_mask_segments_in_batch():
+    """A batch keeps every instance's bitmask segments, with their offsets shifted."""
+    rng = np.random.default_rng(83)
+    gs = [gen.sbm(np.array([520 + 40 * i, 600]), np.array([0.8, 0.4]), 0.01, key=90 + i,
+                  uperm=rng.permutation(1120 + 40 * i).astype(np.int32)) for i in range(3)]
+    with host_ctx(chunk=512, mask_min=0.0) as k:
+        k.set_batch([(g, 1.0, np.zeros(g.n), np.zeros(g.n)) for g in gs])
+        total = k.graph_masks()
+        off = 0
+        segs = 0
+        for g in gs:
+            with host_ctx(chunk=512, mask_min=0.0) as k1:
+                k1.set_graph(g)
+                segs += k1.graph_masks()["mask_segments"]
+                _same_rows(k1, k, g.n, off)
+            off += g.n
+        assert total["mask_segments"] == segs > 0

@@ -30,7 +30,8 @@ def ctx(w, dtype, opts=None):
 
 
 @pytest.mark.parametrize("atol", [1e-5, 1e-9])
-@pytest.mark.parametrize("opts", [dict(), dict(chunk=64, tile_rows=64, flat_min_vec=0.5), dict(scaling=1)])
+@pytest.mark.parametrize("opts", [dict(), dict(chunk=64, tile_rows=64, flat_min_vec=0.5), dict(scaling=1),
+                                  dict(mask_min=0.0, chunk=512)])
 def test_adaptive_fp64_matches_oracle(need_gpu, atol, opts):
     w = ragged_sbm(51)
     with ctx(w, "f64", opts) as k:

@@ -42,7 +42,8 @@ def ragged_sbm(seed=3):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("ckpt", [1, 7, 100])
-@pytest.mark.parametrize("opts", [dict(), dict(chunk=64, tile_rows=64, flat_min_vec=0.5), dict(scaling=1)])
+@pytest.mark.parametrize("opts", [dict(), dict(chunk=64, tile_rows=64, flat_min_vec=0.5), dict(scaling=1),
+                                  dict(mask_min=0.0, chunk=512)])
 def test_adjoint_matches_oracle(need_gpu, dtype, ckpt, opts):
     w = ragged_sbm()
     scaling = opts.get("scaling", 0)
@@ -183,7 +184,8 @@ def asymmetric_workload(seed, weighted=False):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("opts", [dict(), dict(chunk=64, tile_rows=64, flat_min_vec=0.5, ckpt=7),
-                                  dict(scaling=1, threads=256), dict(weighted=True), dict(threads=128, chunk=64)])
+                                  dict(scaling=1, threads=256), dict(weighted=True), dict(threads=128, chunk=64),
+                                  dict(mask_min=0.0, chunk=512), dict(mask_min=0.0, chunk=512, weighted=True)])
 def test_adjoint_asymmetric_with_transpose(need_gpu, dtype, opts):
     """Asymmetric A with the option "transpose": the gathers of J^T l run over the layout of A^T
     and match the oracle's discrete adjoint, which scatters the rows of A."""

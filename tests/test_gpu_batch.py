@@ -208,10 +208,11 @@ def test_batch_ensemble_full_size(need_gpu):
         assert np.all(np.abs(F - Fo) <= bound), i
 
 
-def test_batch_with_dense_offdiagonal_blocks(need_gpu):
+@pytest.mark.parametrize("masks", [False, True])
+def test_batch_with_dense_offdiagonal_blocks(need_gpu, masks):
     """Instances whose communities are joined by dense off-diagonal blocks keep their column
     groups in the union (block, tile and group indices offset per instance) and match the
-    oracle per instance."""
+    oracle per instance; with masks, every segment is a bitmask with per-instance offsets."""
     rng = np.random.default_rng(31)
     inst = []
     for i, K in enumerate([0.5, 2.0, 4.0]):
@@ -222,8 +223,12 @@ def test_batch_with_dense_offdiagonal_blocks(need_gpu):
         inst.append((g, K, rng.standard_normal(n), rng.uniform(0, TWO_PI, n)))
     dt, steps, r_every = 0.01, 100, 10
     with Kuramoto("f64", device=0) as k:
+        if masks:
+            k.set_option("chunk", 512)
+            k.set_option("mask_min", 0.0)
         k.set_batch(inst)
         assert k.graph_pairs() == 12
+        assert (k.graph_masks()["mask_segments"] > 0) == masks
         rf = k.batch_info()
         r, _ = k.batch_step(dt, steps, r_every)
         th = k.get_phases()

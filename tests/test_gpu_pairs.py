@@ -69,7 +69,8 @@ def deg_of(g):
 
 
 @pytest.mark.parametrize("opts", [dict(), dict(chunk=64, tile_rows=64, flat_min_vec=0.5),
-                                  dict(chunk=64, threads=256, flat_min_vec=1000), dict(scaling=1)])
+                                  dict(chunk=64, threads=256, flat_min_vec=1000), dict(scaling=1),
+                                  dict(mask_min=0.0, chunk=512)])
 def test_pairs_fp64_rhs_and_rk4(need_gpu, opts):
     g, om, th = pair_graph(81, SIZES, V6)
     K, dt, steps = 0.8, 0.01, 100

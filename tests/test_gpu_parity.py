@@ -129,7 +129,9 @@ def test_sbm_fp32_trajectory_1000_steps(need_gpu, flat):
                                   dict(flat_min_vec=0.1, chunk=128, tile_rows=64), dict(flat_min_vec=0.1, tau=0.0),
                                   dict(flat_min_vec=0), dict(tile_min_cost=1), dict(tile_min_cost=1, tiles=100000),
                                   dict(xcds=8, tile_min_cost=1), dict(xcds=8, tile_rows=64, chunk=128),
-                                  dict(xcds=3, tile_min_cost=64)])
+                                  dict(xcds=3, tile_min_cost=64),
+                                  dict(mask_min=0.0, chunk=512), dict(mask_min=0.0, chunk=512, threads=256, tile_rows=64, xcds=8),
+                                  dict(mask_min=0.0, chunk=1024, threads=128), dict(mask_min=0.1, chunk=2048, flat_min_vec=0.1)])
 def test_ragged_layouts(need_gpu, dtype, opts):
     """Odd block sizes, several chunks per block, several tiles per block, all-dense and
     all-sparse evaluation, a size-1 block and a complete block; launch orders for 8 and 3 XCDs
