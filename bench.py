@@ -58,13 +58,15 @@ def layout_of(info: dict) -> dict:
     return {k: int(info[k]) for k in ("chunk", "tiles", "list_padded", "dense_blocks")}
 
 
-def algorithmic_bytes_per_eval(info: dict, elem: int) -> int:
+def algorithmic_bytes_per_eval(info: dict, elem: int, mask_bytes: int = 0) -> int:
     """Bytes one right-hand-side evaluation must move: the stored index lists (2 B per entry,
-    unpadded), the inter-block columns (4 B), the list and inter row offsets (2 x 8 (N+1)),
-    four per-node vectors (theta, the previous stage, omega read; the stage result written) and
-    the block sums."""
+    unpadded), the bitmask segments (1 bit per cell, in 128-column units), the inter-block
+    columns (4 B), the list and inter row offsets (2 x 8 (N+1)), four per-node vectors (theta, the
+    previous stage, omega read; the stage result written) and the block sums. With bitmask
+    segments, their per-row sums (one pair per row) are written and read once more."""
     n, nb = info["n"], info["blocks"]
-    return (2 * info["list_entries"] + 4 * info["inter_entries"] + 16 * (n + 1) + 4 * n * elem
+    masks = mask_bytes + (2 * 2 * elem * n if mask_bytes else 0)
+    return (2 * info["list_entries"] + masks + 4 * info["inter_entries"] + 16 * (n + 1) + 4 * n * elem
             + 2 * nb * elem * 4)
 
 
@@ -187,7 +189,8 @@ def bench_batch(args):
     launches, kms = k.kernel_time()
     k.set_option("timing", 0)
     avg_ms = kms / max(1, launches)
-    b_eval = algorithmic_bytes_per_eval(info, 4)
+    masks = k.graph_masks()
+    b_eval = algorithmic_bytes_per_eval(info, 4, masks["mask_bytes"])
     achieved = b_eval / (avg_ms * 1e-3) / 1e9
     out = {"metric": "aggregate node-steps/s of a batched ensemble (RK4)", "value": ntot * args.steps / el,
            "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -197,10 +200,11 @@ def bench_batch(args):
                                   "communities, rho 0.97, p_out 2e-4) by a coin, K=linspace(0,6,256), dt=0.01, "
                                   "r every 10 steps, seed 1004", "nodes": ntot, "list_entries": info["list_entries"],
                       "inter_entries": info["inter_entries"], "tiles": info["tiles"]},
-           "layout": {"tuning": tuning, "chunk": info["chunk"]},
+           "layout": {"tuning": tuning, "chunk": info["chunk"], "masks": masks},
            "r_final_K0": float(r[-1, 0]), "r_final_K6": float(r[-1, -1]),
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_rows", "avg_launch_ms": avg_ms,
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "k_mask + k_rows" if masks["mask_segments"] else "k_rows", "avg_launch_ms": avg_ms,
                         "algorithmic_bytes_per_launch": b_eval}}
     print(json.dumps(out), flush=True)
     k.close()
@@ -441,7 +445,8 @@ def main():
 
     steps_per_s = args.steps / el
     avg_ms = kms / max(1, launches)
-    b_eval = algorithmic_bytes_per_eval(info, elem)
+    masks = k.graph_masks()
+    b_eval = algorithmic_bytes_per_eval(info, elem, masks["mask_bytes"])
     achieved = b_eval / (avg_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -468,11 +473,12 @@ def main():
         "data": "synthetic",
         "config": workload_desc(args.workload, w, info),
         "rhs_evals_per_s": 4 * steps_per_s,
-        "layout": {"tuning": tuning, "chunk": info["chunk"], "tiles": info["tiles"],
+        "layout": {"tuning": tuning, "chunk": info["chunk"], "tiles": info["tiles"], "masks": masks,
                    "dense_blocks": info["dense_blocks"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_rows", "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": b_eval,
+                     "kernel": "k_mask + k_rows" if masks["mask_segments"] else "k_rows", "avg_launch_ms": avg_ms,
+                     "algorithmic_bytes_per_launch": b_eval,
                      "launch_timing": "HIP events around every launch in the timed region" if in_region else
                                       "HIP events on a separate run of plain launches of the same steps"},
     }

@@ -4,12 +4,13 @@
 // the density threshold tau above which a block stores its zeros (localised order parameters)
 // rather than its ones (Introduction and Sec. 3: precomputed block sums pay off once a block
 // holds more ones than zeros, which makes tau = 1/2 the byte-minimal threshold; the timing
-// decides whether another value runs faster on this device).
+// decides whether another value runs faster on this device), and whether segments dense in list
+// entries are stored as bitmasks (option mask_min).
 //
 // The search is a coordinate descent: each option in turn is set to every candidate value while
 // the others keep their best values so far, and a candidate replaces the incumbent only when it
-// is at least 1 % faster. Tile options re-group the installed rows (no list rebuild); tau and
-// the chunk width rebuild the lists from the adjacency. Results are kept in a plain-text cache,
+// is at least 1 % faster. Tile options re-group the installed rows (no list rebuild); tau, the
+// chunk width and the bitmask threshold rebuild the lists from the adjacency. Results are kept in a plain-text cache,
 // one line per graph signature, so a graph of the same shape on the same device is configured
 // without timing.
 #include <algorithm>
@@ -21,6 +22,7 @@
 #include <vector>
 
 #include "../../include/kur.h"
+#include "kur_internal.hpp"
 #include "kur_tune.hpp"
 
 using namespace kur;
@@ -61,8 +63,9 @@ struct Choice {
 };
 
 // Cache lines: "<key>\t<tau> <chunk> <threads> <tile_rows> <tile_min_cost> <flat_min_vec> <xcds> <ms>
-// [<inter_gather>]" (lines without the last field keep the dtype's default gathers). The last
-// line with a matching key wins; malformed lines are skipped.
+// [<inter_gather> [<mask_min>]]" (without the inter_gather field the dtype's default gathers,
+// without mask_min no bitmask segments). The last line with a matching key wins; malformed lines
+// are skipped.
 bool cache_lookup(const char *path, const std::string &key, Choice &out)
 {
     if (!path) return false;
@@ -76,11 +79,14 @@ bool cache_lookup(const char *path, const std::string &key, Choice &out)
         Choice ch;
         int chunk = 0, threads = 0, rows = 0, xcds = 0, ig = -1;
         long long cost = 0;
-        const int got = std::sscanf(tab + 1, "%lf %d %d %d %lld %lf %d %lf %d", &ch.l.tau, &chunk, &threads, &rows,
-                                    &cost, &ch.t.flat_min_vec, &xcds, &ch.ms, &ig);
-        if (got != 8 && got != 9) continue;
-        if (got == 9 && ig != 0 && ig != 1) continue;
-        ch.t.inter_gather = got == 9 ? ig : -1;
+        double mm = 2.0;
+        const int got = std::sscanf(tab + 1, "%lf %d %d %d %lld %lf %d %lf %d %lf", &ch.l.tau, &chunk, &threads,
+                                    &rows, &cost, &ch.t.flat_min_vec, &xcds, &ch.ms, &ig, &mm);
+        if (got < 8 || got > 10) continue;
+        if (got >= 9 && ig != 0 && ig != 1) continue;
+        if (got == 10 && !(mm >= 0.0 && mm <= 1e9)) continue;
+        ch.t.inter_gather = got >= 9 ? ig : -1;
+        ch.l.mask_min = got == 10 ? mm : 2.0;
         ch.t.xcds = xcds;
         ch.l.chunk = chunk;
         ch.t.threads = threads;
@@ -98,9 +104,9 @@ bool cache_store(const char *path, const std::string &key, const Choice &ch)
     if (!path) return true;
     FILE *f = std::fopen(path, "a");
     if (!f) return false;
-    const int r = std::fprintf(f, "%s\t%.17g %d %d %d %lld %.17g %d %.6g %d\n", key.c_str(), ch.l.tau, ch.l.chunk,
-                               ch.t.threads, ch.t.tile_rows, (long long)ch.t.tile_min_cost, ch.t.flat_min_vec,
-                               ch.t.xcds, ch.ms, ch.t.inter_gather);
+    const int r = std::fprintf(f, "%s\t%.17g %d %d %d %lld %.17g %d %.6g %d %.17g\n", key.c_str(), ch.l.tau,
+                               ch.l.chunk, ch.t.threads, ch.t.tile_rows, (long long)ch.t.tile_min_cost,
+                               ch.t.flat_min_vec, ch.t.xcds, ch.ms, ch.t.inter_gather, ch.l.mask_min);
     return std::fclose(f) == 0 && r > 0;
 }
 
@@ -315,6 +321,26 @@ extern "C" kur_status kur_autotune_csr(kur_ctx *c, int64_t n, const int64_t *row
         tried.push_back(w);
         Choice cand = best;
         cand.l.chunk = w;
+        if ((s = ctx_set_build_options(c, cand.l, cand.t)) != KUR_OK) return s;
+        if ((s = kur_set_graph_csr(c, n, row_ptr, col, labels)) != KUR_OK) return s;
+        ++S.builds;
+        if ((s = ctx_time_steps(c, 3, &cand.ms)) != KUR_OK) return s;
+        ++S.timed;
+        installed = cand;
+        if (cand.ms < best.ms * kGain) best = cand;
+    }
+
+    // bitmask segments (needs a chunk of at least kMaskMinW): off, or from a list density
+    std::vector<double> mask_mins;
+    if (best.l.chunk >= kMaskMinW) {
+        if (effort == 1) mask_mins = {0.3};
+        if (effort >= 2) mask_mins = {0.2, 0.3, 0.4};
+        if (best.l.mask_min <= 1.0) mask_mins.push_back(2.0);
+    }
+    for (double mm : mask_mins) {
+        if (mm == best.l.mask_min) continue;
+        Choice cand = best;
+        cand.l.mask_min = mm;
         if ((s = ctx_set_build_options(c, cand.l, cand.t)) != KUR_OK) return s;
         if ((s = kur_set_graph_csr(c, n, row_ptr, col, labels)) != KUR_OK) return s;
         ++S.builds;

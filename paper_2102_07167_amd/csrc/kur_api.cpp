@@ -2572,12 +2572,14 @@ LayoutParams ctx_layout_params(const kur_ctx *c)
     LayoutParams l;
     l.tau = c->bopt.tau;
     l.chunk = c->bopt.W;
+    l.mask_min = c->bopt.mask_min;
     return l;
 }
 
 kur_status ctx_set_build_options(kur_ctx *c, const LayoutParams &l, const TileParams &t)
 {
     if (!(l.tau >= 0.0 && l.tau <= 1.0) || l.chunk < 64 || l.chunk % 64 || l.chunk > ctx_max_chunk(c) ||
+        !(l.mask_min >= 0.0 && l.mask_min <= 1e9) ||
         t.tile_rows < 64 || t.tile_rows > 4096 || t.tile_min_cost < 1 || !(t.flat_min_vec >= 0.0) ||
         (t.threads != 128 && t.threads != 256 && t.threads != 512 && t.threads != 1024) || t.xcds < 1 || t.xcds > 64 ||
         t.inter_gather < -1 || t.inter_gather > 1)
@@ -2585,6 +2587,7 @@ kur_status ctx_set_build_options(kur_ctx *c, const LayoutParams &l, const TilePa
     if (t.inter_gather >= 0) c->inter_gather = t.inter_gather;
     c->bopt.tau = l.tau;
     c->bopt.W = l.chunk;
+    c->bopt.mask_min = l.mask_min;
     c->bopt.tile_rows = t.tile_rows;
     c->bopt.tile_min_cost = t.tile_min_cost;
     c->bopt.flat_min_vec = t.flat_min_vec;

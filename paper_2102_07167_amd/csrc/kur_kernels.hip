@@ -235,12 +235,15 @@ __device__ __forceinline__ void mask_unit(const VT *tb, int P, const u32x4 u, VT
 // Row sums of the bitmask segments (see SegD) of one tile per workgroup, into g.msum (block
 // order; zero for rows without any): for a segment of ones the sum of x over the row's set bits,
 // for a segment of zeros minus that sum (subtracted from the localised order parameters, Sec. 3,
-// eq. KuramotoGraphApproach). Per sub-chunk of at most W/4 columns the workgroup builds in LDS the
-// 16 subset sums of every 4 columns (the method of four Russians for Boolean matrix-vector
-// products); then thread r mod NT owns row r, keeps four 16-byte units of its bits in flight and
-// adds one table entry per nibble. x_in holds the values summed (the tile kernel's staged pairs).
+// eq. KuramotoGraphApproach). Per sub-chunk of at most min(W/4, 4 NT) columns the workgroup builds
+// in LDS the 16 subset sums of every 4 columns (the method of four Russians for Boolean
+// matrix-vector products); then thread r mod NT owns row r, keeps four 16-byte units of its bits
+// in flight and adds one table entry per nibble. The values of the next sub-chunk's tables are
+// fetched into registers while the current one is read, so a table build after its barrier only
+// writes LDS. x_in holds the values summed (the tile kernel's staged pairs).
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_mask(DevGraph g, const typename V2<T>::type *__restrict__ x_in)
+__global__ __launch_bounds__(NT) void k_mask(
+    DevGraph g, const typename V2<T>::type *__restrict__ x_in)
 {
     using VT = typename V2<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -254,13 +257,38 @@ __global__ __launch_bounds__(NT) void k_mask(DevGraph g, const typename V2<T>::t
     const int nrows = tl.r1 - tl.r0;
     const int rowbase = bi.row0 + tl.r0;
     for (int r = threadIdx.x; r < nrows; r += NT) macc[r] = vzero<VT>();
-    const int S = (W >> 2) & ~(kMaskUnitCols - 1);
-    for (int c = 0; c < bi.nchunk; ++c) {
+    // columns per sub-chunk: a multiple of the unit, at most W/4 (the tables fit the staging
+    // area) and at most 4 NT (one column group per thread)
+    const int S = min((W >> 2), 4 * NT) & ~(kMaskUnitCols - 1);
+    const int nseg = bi.nchunk;
+    // the next bitmask segment at or after c (nseg if none)
+    auto next_mask = [&](int c) {
+        while (c < nseg && !__builtin_amdgcn_readfirstlane(g.segd[bi.sd0 + c].mask)) ++c;
+        return c;
+    };
+    // this thread's four values of column group j of the sub-chunk starting at column s0 of
+    // segment c (zero past the sub-chunk)
+    VT f0 = vzero<VT>(), f1 = f0, f2 = f0, f3 = f0;
+    auto fetch = [&](int c, int s0) {
         const SegD sd = g.segd[bi.sd0 + c];
-        if (!__builtin_amdgcn_readfirstlane(sd.mask)) continue;
+        const int ncol = min(S, (int)sd.cw - s0);
+        const int ng = (ncol + kMaskUnitCols - 1) / kMaskUnitCols * (kMaskUnitCols / 4);
+        const int j = threadIdx.x;
+        const int c0 = sd.col0 + s0 + 4 * j, c1 = sd.col0 + s0 + ncol;
+        f0 = f1 = f2 = f3 = vzero<VT>();
+        if (j < ng) {
+            if (c0 < c1) f0 = x_in[c0];
+            if (c0 + 1 < c1) f1 = x_in[c0 + 1];
+            if (c0 + 2 < c1) f2 = x_in[c0 + 2];
+            if (c0 + 3 < c1) f3 = x_in[c0 + 3];
+        }
+    };
+    int c = next_mask(0);
+    if (c < nseg) fetch(c, 0);
+    while (c < nseg) {
+        const SegD sd = g.segd[bi.sd0 + c];
         const T sign = sd.zeros ? T(-1) : T(1);
         const int cw = __builtin_amdgcn_readfirstlane((int)sd.cw);
-        const int col0 = __builtin_amdgcn_readfirstlane(sd.col0);
         const int nq = (cw + kMaskUnitCols - 1) / kMaskUnitCols;
         const uint32_t ustride = (uint32_t)bi.size;  // units of one row are size apart
         const __amdgpu_buffer_rsrc_t Mt = uniform_rsrc(g.mask + 4 * sd.mbase, (int64_t)bi.size * nq * 16);
@@ -282,13 +310,15 @@ __global__ __launch_bounds__(NT) void k_mask(DevGraph g, const typename V2<T>::t
                 if (qa + 3 < qb) u3 = list_load(Mt, (uint32_t)(qa + 3) * ustride + rr);
             }
             __syncthreads();  // the previous sub-chunk's readers of the tables are done
-            for (int j = threadIdx.x; j < ng; j += NT) {
-                const int c0 = col0 + s0 + 4 * j, c1 = col0 + s0 + ncol;
-                const VT x0 = c0 < c1 ? x_in[c0] : vzero<VT>();
-                const VT x1 = c0 + 1 < c1 ? x_in[c0 + 1] : vzero<VT>();
-                const VT x2 = c0 + 2 < c1 ? x_in[c0 + 2] : vzero<VT>();
-                const VT x3 = c0 + 3 < c1 ? x_in[c0 + 3] : vzero<VT>();
-                subset_sums4(xs + j, P, x0, x1, x2, x3);
+            if ((int)threadIdx.x < ng) subset_sums4(xs + threadIdx.x, P, f0, f1, f2, f3);
+            // fetch the values of the next sub-chunk (of this segment or the next bitmask one)
+            {
+                int cn = c, sn = s0 + S;
+                if (sn >= cw) {
+                    cn = next_mask(c + 1);
+                    sn = 0;
+                }
+                if (cn < nseg) fetch(cn, sn);
             }
             __syncthreads();
             for (int r = threadIdx.x; r < nrows; r += NT) {
@@ -311,6 +341,7 @@ __global__ __launch_bounds__(NT) void k_mask(DevGraph g, const typename V2<T>::t
                 vacc(macc[r], vscale(acc, sign));  // row r's own thread, in segment order
             }
         }
+        c = next_mask(c + 1);
     }
     VT *out = reinterpret_cast<VT *>(g.msum) + rowbase;
     for (int r = threadIdx.x; r < nrows; r += NT) out[r] = macc[r];

@@ -34,7 +34,11 @@ struct TileParams {
 struct LayoutParams {
     double tau = 0.5;
     int32_t chunk = 4096;
-    bool operator==(const LayoutParams &o) const { return tau == o.tau && chunk == o.chunk; }
+    double mask_min = 2.0;  // bitmask segments from this many list entries per cell (above 1: none)
+    bool operator==(const LayoutParams &o) const
+    {
+        return tau == o.tau && chunk == o.chunk && mask_min == o.mask_min;
+    }
     bool operator!=(const LayoutParams &o) const { return !(*this == o); }
 };
 

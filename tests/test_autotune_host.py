@@ -103,3 +103,23 @@ def test_cached_choice_out_of_range_is_rejected(tmp_path):
         with pytest.raises(K.KurError) as ei:
             k.autotune(g, cache=str(path))
         assert ei.value.status == K.KUR_EINVAL
+
+
+def test_cached_mask_choice(tmp_path):
+    """A cache line's optional tenth field is the bitmask threshold: the graph is built with
+    bitmask segments from it; lines without it build lists only; a negative tenth field makes the
+    line malformed, so an earlier matching line wins."""
+    g = small_sbm()
+    path = tmp_path / "tune.tsv"
+    with host_ctx() as k:
+        key = k.tune_key(g)
+        path.write_text(key + "\t0.5 512 512 256 16384 8 1 1.0 1\n")
+        k.autotune(g, cache=str(path))
+        assert k.graph_masks()["mask_segments"] == 0
+        path.write_text(key + "\t0.5 512 512 256 16384 8 1 1.0 1 0\n")
+        k.autotune(g, cache=str(path))
+        with_masks = k.graph_masks()
+        assert with_masks["mask_segments"] > 0 and with_masks["mask_bytes"] > 0
+        path.write_text(key + "\t0.5 512 512 256 16384 8 1 1.0 1 0\n" + key + "\t0.5 512 512 256 16384 8 1 2.0 1 -1\n")
+        rep = k.autotune(g, cache=str(path))
+        assert rep["ms_per_step"] == 1.0 and k.graph_masks() == with_masks
