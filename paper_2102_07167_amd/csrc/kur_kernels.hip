@@ -214,20 +214,22 @@ __device__ __forceinline__ void subset_sums4(VT *t, int P, const VT x0, const VT
 // Add to acc the row sums of one 128-column bitmask unit: per nibble (4 columns, in column
 // order) one read of the subset-sum table of that column group. tb points at the unit's first
 // group; entry m of group j sits at tb[m * P + j]. With an odd pitch, the lanes of a wave (rows,
-// all at the same group) read distinct banks for distinct entries.
+// all at the same group) read distinct banks for distinct entries. The address is formed in bytes
+// as one 24-bit multiply-add (m < 16, P < 2^16); the group offset is a constant of the read.
 template <typename VT>
 __device__ __forceinline__ void mask_unit(const VT *tb, int P, const u32x4 u, VT &acc)
 {
     const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+    const uint32_t pb = (uint32_t)P * (uint32_t)sizeof(VT);  // bytes between entries of a group
+    const char *base = reinterpret_cast<const char *>(tb);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
 #pragma unroll
         for (int n = 0; n < 8; ++n) {
             const uint32_t m = (w[k] >> (4 * n)) & 15u;
-            vacc(acc, tb[m * (uint32_t)P + (uint32_t)(8 * k + n)]);
+            vacc(acc, *reinterpret_cast<const VT *>(base + __umul24(m, pb) + (8 * k + n) * sizeof(VT)));
         }
-        // one word's eight reads in flight at a time (the row kernel's register budget): an empty
-        // statement that no memory access may cross
+        // an empty statement that no memory access may cross, after every word (measured with it)
         asm volatile("" ::: "memory");
     }
 }
