@@ -355,11 +355,23 @@ std::string to_masks(BlockGraph &g, const BuildOptions &opt)
     return "";
 }
 
+namespace {
+
+// The bitmask sub-chunk width (the option, at most the chunk, in whole units) and item size.
+void mask_params(BlockGraph &g, const BuildOptions &opt)
+{
+    g.mask_sub = std::max(kMaskUnitCols, std::min(opt.mask_sub, g.W) / kMaskUnitCols * kMaskUnitCols);
+    g.mask_item = opt.mask_item;
+}
+
+}  // namespace
+
 void make_tiles(BlockGraph &g, const BuildOptions &opt)
 {
     const int64_t n = g.n;
     g.tile_rows = opt.tile_rows;
     g.xcds = opt.xcds;
+    mask_params(g, opt);
     // work tiles: consecutive rows of one block with similar cost
     std::vector<int64_t> rowcost(n);
     int64_t total = 0;
@@ -488,6 +500,50 @@ void order_tiles(BlockGraph &g)
         for (size_t j = 0; j < lists[x].size(); ++j) g.order[j * X + x] = lists[x][j];
     // drop empty slots after the last tile
     while (!g.order.empty() && g.order.back() < 0) g.order.pop_back();
+    mask_items(g);
+}
+
+void mask_items(BlockGraph &g)
+{
+    g.mitems.clear();
+    g.mtiles.clear();
+    g.mask_part_rows = 0;
+    if (g.mask_segments == 0) return;
+    const int64_t S = g.mask_sub;
+    g.mtiles.assign(g.tiles.size(), MaskTile{0, 0, 0});
+    std::vector<int64_t> cells;
+    for (size_t t = 0; t < g.tiles.size(); ++t) {
+        const Tile &tl = g.tiles[t];
+        const BlkInfo &b = g.blk[tl.block];
+        const int64_t h = tl.r1 - tl.r0;
+        MaskTile &mt = g.mtiles[t];
+        mt.off = g.mask_part_rows;
+        bool open = false;
+        for (int32_t ch = 0; ch < b.nchunk; ++ch) {
+            const SegD &sd = g.segd[b.sd0 + ch];
+            if (!sd.mask) continue;
+            for (int64_t s0 = 0; s0 < sd.cw; s0 += S) {
+                const int64_t cc = h * std::min<int64_t>(S, sd.cw - s0);
+                if (open && cells.back() + cc > g.mask_item) open = false;
+                if (!open) {
+                    g.mitems.push_back(MaskItem{(int32_t)t, ch, (int32_t)(s0 / S), 0, g.mask_part_rows});
+                    cells.push_back(0);
+                    g.mask_part_rows += h;
+                    ++mt.cnt;
+                    open = true;
+                }
+                ++g.mitems.back().nsub;
+                cells.back() += cc;
+            }
+        }
+    }
+    // largest first (ties in tile order)
+    std::vector<int64_t> idx(g.mitems.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int64_t)i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return cells[a] > cells[b]; });
+    std::vector<MaskItem> sorted(idx.size());
+    for (size_t i = 0; i < idx.size(); ++i) sorted[i] = g.mitems[idx[i]];
+    g.mitems.swap(sorted);
 }
 
 std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &g)
@@ -523,6 +579,7 @@ std::string build_complete(int64_t n, const BuildOptions &opt, BlockGraph &g)
         g.tiles.push_back(Tile{0, (int32_t)r, (int32_t)std::min<int64_t>(n, r + opt.tile_rows), -1});
     g.blk[0].ntiles = (int32_t)g.tiles.size();
     g.xcds = opt.xcds;
+    mask_params(g, opt);
     order_tiles(g);
     return "";
 }
@@ -536,10 +593,14 @@ std::string merge_graphs(std::vector<BlockGraph> &parts, BlockGraph &g, std::vec
     g.tile_rows = parts[0].tile_rows;
     g.esz2 = parts[0].esz2;
     g.xcds = parts[0].xcds;
+    g.mask_sub = parts[0].mask_sub;
+    g.mask_item = parts[0].mask_item;
     g.symmetric = true;
     int64_t n = 0, nb = 0, segs = 0, entries = 0, inter = 0, tiles = 0;
     for (const BlockGraph &p : parts) {
-        if (p.W != g.W || p.tile_rows != g.tile_rows || p.esz2 != g.esz2) return "instances built with different layouts";
+        if (p.W != g.W || p.tile_rows != g.tile_rows || p.esz2 != g.esz2 || p.mask_sub != g.mask_sub ||
+            p.mask_item != g.mask_item)
+            return "instances built with different layouts";
         n += p.n;
         nb += p.nb;
         segs += (int64_t)p.seg_ptr.size() - 1;

@@ -71,7 +71,9 @@ struct kur_ctx {
 
     // device graph
     DevBuf d_blk, d_segd, d_grp, d_tiles, d_order, d_seg, d_list, d_iptr, d_icol, d_mask;
-    DevBuf d_msum;              // per-row bitmask segment sums (k_mask), when a layout has any
+    DevBuf d_msum;              // bitmask item partial sums (k_mask), when a layout has any
+    DevBuf d_mitem, d_mtile, d_mitemT, d_mtileT;  // bitmask items and per-tile item runs (A, A^T)
+    int32_t nmitem = 0, nmitemT = 0, mask_sub = 512, mask_subT = 512;
     bool masks = false, masksT = false;  // the layout (of A, of A^T) has bitmask segments
     // layout of A^T for the adjoint of an asymmetric A (option "transpose")
     int transpose = 0;
@@ -200,6 +202,19 @@ hipError_t upload(DevBuf &b, const void *src, size_t bytes, hipStream_t st)
     return hipStreamSynchronize(st);
 }
 
+// The bitmask items and per-tile item runs of a layout, and room for their partial sums (T:
+// bytes of the dtype); nothing for a layout without bitmask segments.
+hipError_t upload_mask_items(DevBuf &items, DevBuf &tiles, DevBuf &sums, const BlockGraph &g, size_t T,
+                             hipStream_t st)
+{
+    if (g.mitems.empty()) return hipSuccess;
+    hipError_t e;
+    if ((e = upload(items, g.mitems.data(), sizeof(MaskItem) * g.mitems.size(), st)) != hipSuccess ||
+        (e = upload(tiles, g.mtiles.data(), sizeof(MaskTile) * g.mtiles.size(), st)) != hipSuccess)
+        return e;
+    return dalloc(sums, 2 * T * (size_t)g.mask_part_rows);
+}
+
 void free_adj(AdjBufs &B)
 {
     DevBuf *b[] = {&B.hi, &B.lo, &B.wind, &B.ksum, &B.ck, &B.slots, &B.acs, &B.fpart[0], &B.fpart[1], &B.x[0], &B.x[1],
@@ -215,7 +230,8 @@ void free_all(kur_ctx *c)
                       &c->d_r, &c->d_psi, &c->d_tile_first, &c->d_inv_n, &c->d_ctr, &c->d_ck,
                       &c->d_blkT, &c->d_segdT, &c->d_grpT, &c->d_tilesT, &c->d_orderT, &c->d_segT,
                       &c->d_listT, &c->d_iptrT, &c->d_icolT, &c->d_rsc, &c->d_rac, &c->d_perm, &c->d_opart,
-                      &c->d_yb[0], &c->d_yb[1], &c->d_mask, &c->d_maskT, &c->d_msum};
+                      &c->d_yb[0], &c->d_yb[1], &c->d_mask, &c->d_maskT, &c->d_msum,
+                      &c->d_mitem, &c->d_mtile, &c->d_mitemT, &c->d_mtileT};
     for (DevBuf *b : bufs) dfree(*b);
     free_adj(c->adj);
     c->has_T = false;
@@ -248,6 +264,10 @@ DevGraph devgraph(const kur_ctx *c)
     g.tile_rows = c->tile_rows;
     g.nlaunch = c->nlaunch;
     g.msum = c->masks ? c->d_msum.p : nullptr;
+    g.mitem = (const MaskItem *)c->d_mitem.p;
+    g.mtile = (const MaskTile *)c->d_mtile.p;
+    g.nmitem = c->nmitem;
+    g.mask_sub = c->mask_sub;
     return g;
 }
 
@@ -264,6 +284,10 @@ DevGraph devgraph_t(const kur_ctx *c)
     g.list = (const uint16_t *)c->d_listT.p;
     g.mask = (const uint32_t *)c->d_maskT.p;
     g.msum = c->masksT ? c->d_msum.p : nullptr;
+    g.mitem = (const MaskItem *)c->d_mitemT.p;
+    g.mtile = (const MaskTile *)c->d_mtileT.p;
+    g.nmitem = c->nmitemT;
+    g.mask_sub = c->mask_subT;
     g.inter_ptr = (const int64_t *)c->d_iptrT.p;
     g.inter_col = (const int32_t *)c->d_icolT.p;
     g.W = c->W;
@@ -483,7 +507,7 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
             (e = dalloc(c->d_kout, T * n)) != hipSuccess || (e = dalloc(c->d_y, T * n)) != hipSuccess ||
             (e = upload(c->d_perm, g.perm.data(), sizeof(int32_t) * n, c->stream)) != hipSuccess ||
             (e = dalloc(c->d_yb[0], T * n)) != hipSuccess || (e = dalloc(c->d_yb[1], T * n)) != hipSuccess ||
-            (g.mask_segments > 0 && (e = dalloc(c->d_msum, 2 * T * n)) != hipSuccess)) {
+            (e = upload_mask_items(c->d_mitem, c->d_mtile, c->d_msum, g, T, c->stream)) != hipSuccess) {
             free_all(c);
             c->has_graph = false;
             return hip_fail(c, e, "graph upload");
@@ -512,6 +536,8 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
     c->mask_info[0] = g.mask_segments;
     c->mask_info[1] = (int64_t)g.mask.size() * 4;
     c->masks = g.mask_segments > 0;
+    c->nmitem = (int32_t)g.mitems.size();
+    c->mask_sub = g.mask_sub;
     c->masksT = false;
     c->symmetric = g.symmetric;
     c->tiles_installed.threads = c->threads;
@@ -537,6 +563,7 @@ kur_status install_graph(kur_ctx *c, BlockGraph &g)
         c->skel.pair_rho.swap(g.pair_rho);
         c->skel.n_pairs = g.n_pairs;
         c->skel.weighted = g.weighted;
+        c->skel.mask_segments = g.mask_segments;
         c->skel.inter_ptr.swap(g.inter_ptr);
     }
     c->has_graph = true;
@@ -607,13 +634,15 @@ kur_status install_transpose(kur_ctx *c, int64_t n, const int64_t *row_ptr, cons
         (e = upload(c->d_segT, t.seg_ptr.data(), sizeof(int64_t) * t.seg_ptr.size(), c->stream)) != hipSuccess ||
         (e = upload(c->d_listT, t.list.data(), sizeof(uint16_t) * t.list.size(), c->stream)) != hipSuccess ||
         (e = upload(c->d_maskT, t.mask.data(), sizeof(uint32_t) * t.mask.size(), c->stream)) != hipSuccess ||
-        (t.mask_segments > 0 && (e = dalloc(c->d_msum, 2 * (size_t)c->esz * (size_t)c->n)) != hipSuccess) ||
+        (e = upload_mask_items(c->d_mitemT, c->d_mtileT, c->d_msum, t, (size_t)c->esz, c->stream)) != hipSuccess ||
         (e = upload(c->d_iptrT, t.inter_ptr.data(), sizeof(int64_t) * t.inter_ptr.size(), c->stream)) != hipSuccess ||
         (e = upload(c->d_icolT, t.inter_col.data(), sizeof(int32_t) * t.inter_col.size(), c->stream)) != hipSuccess)
         return hip_fail(c, e, "transposed layout upload");
     c->ntT = (int32_t)t.tiles.size();
     c->nlaunchT = (int32_t)t.order.size();
     c->masksT = t.mask_segments > 0;
+    c->nmitemT = (int32_t)t.mitems.size();
+    c->mask_subT = t.mask_sub;
     c->tile_rowsT = t.tile_rows;
     c->has_T = true;
     return KUR_OK;
@@ -774,6 +803,13 @@ kur_status kur_set_option(kur_ctx *c, const char *key, double v)
     } else if (k == "mask_min") {
         if (!(v >= 0.0) || v > 1e9) return fail(c, KUR_EINVAL, "mask_min must be in [0, 1e9]");
         c->bopt.mask_min = v;
+    } else if (k == "mask_sub") {
+        if (v != (int64_t)v || v < kMaskUnitCols || v > kMaskSubMax || (int64_t)v % kMaskUnitCols)
+            return fail(c, KUR_EINVAL, "mask_sub must be a multiple of 128 in [128, 1024]");
+        c->bopt.mask_sub = (int32_t)v;
+    } else if (k == "mask_item") {
+        if (v != (int64_t)v || v < 1 || v > 1e12) return fail(c, KUR_EINVAL, "mask_item must be an integer in [1, 1e12]");
+        c->bopt.mask_item = (int64_t)v;
     } else if (k == "pair_min") {
         if (v != (int64_t)v || v < 1 || v > 65536) return fail(c, KUR_EINVAL, "pair_min must be an integer in [1, 65536]");
         c->bopt.pair_min = (int32_t)v;
@@ -2649,14 +2685,19 @@ kur_status ctx_retile(kur_ctx *c, const TileParams &t)
         (e = upload(c->d_order, L.order.data(), sizeof(int32_t) * L.order.size(), c->stream)) != hipSuccess ||
         (e = dalloc(c->d_part[0], 2 * T * L.tiles.size())) != hipSuccess ||
         (e = dalloc(c->d_part[1], 2 * T * L.tiles.size())) != hipSuccess ||
-        (e = dalloc(c->d_parte, 2 * T * L.tiles.size())) != hipSuccess) {
+        (e = dalloc(c->d_parte, 2 * T * L.tiles.size())) != hipSuccess ||
+        (e = upload_mask_items(c->d_mitem, c->d_mtile, c->d_msum, L, T, c->stream)) != hipSuccess) {
         c->has_graph = false;  // partially replaced device layout: unusable until the next set_graph
         return hip_fail(c, e, "re-tiled layout upload");
     }
+    c->nmitem = (int32_t)L.mitems.size();
+    c->mask_sub = L.mask_sub;
     L.tiles.clear();
     L.tiles.shrink_to_fit();
     L.order.clear();
     L.order.shrink_to_fit();
+    L.mitems = std::vector<MaskItem>();
+    L.mtiles = std::vector<MaskTile>();
     return upload_instances(c);
 }
 

@@ -47,9 +47,32 @@ struct SegD {
 
 // Columns of one bitmask unit (four 32-bit words, one 16-byte load).
 constexpr int32_t kMaskUnitCols = 128;
-// Least chunk width for bitmask segments: the subset-sum tables of a quarter of the chunk
-// (16 entries per 4 columns) must cover at least one unit.
+// Least chunk width for bitmask segments.
 constexpr int32_t kMaskMinW = 4 * kMaskUnitCols;
+// Most columns of one sub-chunk of a bitmask segment (one set of subset-sum tables in LDS, built
+// by one thread per four columns of the 256 threads of the bitmask kernel).
+constexpr int32_t kMaskSubMax = 1024;
+
+// The bitmask work of a layout is cut into items: consecutive sub-chunks (of mask_sub columns,
+// the last one of a segment shorter) of the bitmask segments of one tile, in segment order,
+// starting at sub-chunk sub of segment seg (an index into the block's segd). One workgroup of
+// the bitmask kernel sums an item over the tile's rows into the partial sums at rows
+// [out, out + tile rows) of the item buffer; the tile kernel adds its tile's partial sums.
+struct MaskItem {
+    int32_t tile;
+    int32_t seg;
+    int32_t sub;
+    int32_t nsub;
+    int64_t out;
+};
+
+// Per tile: its items' partial sums, cnt runs of (tile rows) pairs from row off of the item
+// buffer, in segment order.
+struct MaskTile {
+    int64_t off;
+    int32_t cnt;
+    int32_t pad;
+};
 
 // A column block whose localised order parameters enter every row of a row block with factor
 // mode (the prevalent value of that submatrix): the diagonal block when dense, and every dense
@@ -82,6 +105,10 @@ struct BuildOptions {
     int32_t pair_min = 32;      // least rows and columns of such a block
     double mask_min = 2.0;      // a segment holding at least this many list entries per cell is
                                 // stored as a bitmask (needs W >= kMaskMinW); above 1: never
+    int32_t mask_sub = 512;     // columns of a bitmask sub-chunk (a multiple of kMaskUnitCols,
+                                // at most kMaskSubMax)
+    int64_t mask_item = 1 << 19;  // cells (rows x columns) of a bitmask work item, at most (an
+                                  // item holds at least one sub-chunk)
 };
 
 // The graph in block order, ready for upload.
@@ -104,6 +131,11 @@ struct BlockGraph {
     std::vector<int32_t> inter_col;   // block-order columns
     std::vector<Tile> tiles;
     std::vector<int32_t> order;       // launch order of tiles; -1 marks an empty slot (see order_tiles)
+    int32_t mask_sub = 512;           // columns of a bitmask sub-chunk (see MaskItem)
+    int64_t mask_item = 1 << 19;      // most cells of a bitmask item beyond its first sub-chunk
+    std::vector<MaskItem> mitems;     // bitmask items in launch order (largest first)
+    std::vector<MaskTile> mtiles;     // per tile its items' partial sums (empty without bitmasks)
+    int64_t mask_part_rows = 0;       // rows of the item buffer
     int32_t xcds = 1;
     std::vector<int32_t> deg;         // row degree (ones of the row), block order
     int64_t list_unpadded = 0;
@@ -186,6 +218,13 @@ void make_tiles(BlockGraph &g, const BuildOptions &opt);
 // tiles run largest first; slot j * xcds + x holds the j-th tile of XCD x, and -1 where XCD x
 // has fewer tiles. xcds = 1 gives the plain largest-first order.
 void order_tiles(BlockGraph &g);
+
+// The bitmask items of the tiles (see MaskItem), rebuilt with every tiling: per tile its bitmask
+// sub-chunks in segment order, cut into items of at most g.mask_item cells (rows x columns, at
+// least one sub-chunk each); partial-sum rows assigned tile by tile; the launch order is the
+// largest item first, so that the last workgroups to start are the shortest. Called by
+// order_tiles.
+void mask_items(BlockGraph &g);
 
 // Runs f(i) for i in [0, n) on the host threads (static contiguous ranges).
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &f);

@@ -170,10 +170,13 @@ __device__ __forceinline__ void gather8(const VT *lds, const u32x4 q, VT &acc)
     }
 }
 
-// Slots of the staging area beyond the chunk: slot W is the zero slot of the lists' padding; the
-// subset-sum tables of a bitmask sub-chunk of at most W/4 columns take 16 (W/16 + 1) <= W + 16
-// slots.
-constexpr int kXsSlack = 17;
+// Slots of the staging area beyond the chunk: slot W is the zero slot of the lists' padding.
+constexpr int kXsSlack = 1;
+
+// A 16-byte vector index whose byte offset (0x7FFFFFF0) lies past the end of every bitmask
+// segment's buffer resource (at most INT32_MAX bytes, a multiple of 16): such a load returns
+// zeros and touches no memory.
+constexpr uint32_t kUnitPastEnd = 0x07FFFFFFu;
 
 // The 16 subset sums of four values x0..x3, entry m = sum of x_j over the set bits j of m, stored
 // at t[m * P] (P: the table pitch). Each entry is a smaller entry plus one value, in a fixed order:
@@ -234,34 +237,30 @@ __device__ __forceinline__ void mask_unit(const VT *tb, int P, const u32x4 u, VT
     }
 }
 
-// Row sums of the bitmask segments (see SegD) of one tile per workgroup, into g.msum (block
-// order; zero for rows without any): for a segment of ones the sum of x over the row's set bits,
-// for a segment of zeros minus that sum (subtracted from the localised order parameters, Sec. 3,
-// eq. KuramotoGraphApproach). Per sub-chunk of at most min(W/4, 4 NT) columns the workgroup builds
-// in LDS the 16 subset sums of every 4 columns (the method of four Russians for Boolean
-// matrix-vector products); then thread r mod NT owns row r, keeps four 16-byte units of its bits
-// in flight and adds one table entry per nibble. The values of the next sub-chunk's tables are
-// fetched into registers while the current one is read, so a table build after its barrier only
-// writes LDS. x_in holds the values summed (the tile kernel's staged pairs).
+// Partial row sums of one bitmask item (see MaskItem) per workgroup, into g.msum at rows
+// [out, out + tile rows): over the item's sub-chunks of bitmask segments (see SegD), for a
+// segment of ones the sum of x over the row's set bits, for a segment of zeros minus that sum
+// (subtracted from the localised order parameters, Sec. 3, eq. KuramotoGraphApproach). Per
+// sub-chunk the workgroup builds in LDS the 16 subset sums of every 4 columns (the method of four
+// Russians for Boolean matrix-vector products); then thread r mod NT owns row r, keeps four
+// 16-byte units of its bits in flight and adds one table entry per nibble. The values of the next
+// sub-chunk's tables are fetched into registers while the current one is read, so a table build
+// after its barrier only writes LDS. x_in holds the values summed (the tile kernel's staged
+// pairs).
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_mask(
     DevGraph g, const typename V2<T>::type *__restrict__ x_in)
 {
     using VT = typename V2<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int W = g.W;
-    VT *xs = reinterpret_cast<VT *>(smem);  // W + kXsSlack table slots
-    VT *macc = xs + W + kXsSlack;           // tile_rows partial sums
-    const int tile_id = g.order[blockIdx.x];
-    if (tile_id < 0) return;  // empty slot of the XCD-aware launch order
-    const Tile tl = g.tiles[tile_id];
+    const int S = g.mask_sub;  // a multiple of the unit, at most 4 NT (one column group per thread)
+    VT *xs = reinterpret_cast<VT *>(smem);  // 16 (S/4 + 1) table slots
+    VT *macc = xs + 16 * (S / 4 + 1);       // tile rows partial sums
+    const MaskItem it = g.mitem[blockIdx.x];
+    const Tile tl = g.tiles[it.tile];
     const BlkInfo bi = g.blk[tl.block];
     const int nrows = tl.r1 - tl.r0;
-    const int rowbase = bi.row0 + tl.r0;
     for (int r = threadIdx.x; r < nrows; r += NT) macc[r] = vzero<VT>();
-    // columns per sub-chunk: a multiple of the unit, at most W/4 (the tables fit the staging
-    // area) and at most 4 NT (one column group per thread)
-    const int S = min((W >> 2), 4 * NT) & ~(kMaskUnitCols - 1);
     const int nseg = bi.nchunk;
     // the next bitmask segment at or after c (nseg if none)
     auto next_mask = [&](int c) {
@@ -285,73 +284,75 @@ __global__ __launch_bounds__(NT) void k_mask(
             if (c0 + 3 < c1) f3 = x_in[c0 + 3];
         }
     };
-    int c = next_mask(0);
-    if (c < nseg) fetch(c, 0);
-    while (c < nseg) {
+    int c = it.seg, s0 = it.sub * S;
+    fetch(c, s0);
+    for (int k = 0; k < it.nsub; ++k) {
         const SegD sd = g.segd[bi.sd0 + c];
         const T sign = sd.zeros ? T(-1) : T(1);
         const int cw = __builtin_amdgcn_readfirstlane((int)sd.cw);
         const int nq = (cw + kMaskUnitCols - 1) / kMaskUnitCols;
         const uint32_t ustride = (uint32_t)bi.size;  // units of one row are size apart
         const __amdgpu_buffer_rsrc_t Mt = uniform_rsrc(g.mask + 4 * sd.mbase, (int64_t)bi.size * nq * 16);
-        for (int s0 = 0; s0 < cw; s0 += S) {
-            const int ncol = min(S, cw - s0);
-            // tables for every group of the units touched (a unit's bits past the segment are zero
-            // and read entry 0 of their group, which must exist and be zero); an odd pitch, and
-            // 16 P <= W + 16 slots since ng <= S / 4 <= W / 16
-            const int ng = (ncol + kMaskUnitCols - 1) / kMaskUnitCols * (kMaskUnitCols / 4);
-            const int P = ng | 1;
-            const int qa = s0 / kMaskUnitCols, qb = (s0 + ncol + kMaskUnitCols - 1) / kMaskUnitCols;
-            // the first four units of the thread's first row load while the tables are built
-            u32x4 u0 = {0u, 0u, 0u, 0u}, u1 = u0, u2 = u0, u3 = u0;
-            if ((int)threadIdx.x < nrows) {
-                const uint32_t rr = (uint32_t)(tl.r0 + (int)threadIdx.x);
-                u0 = list_load(Mt, (uint32_t)qa * ustride + rr);
-                if (qa + 1 < qb) u1 = list_load(Mt, (uint32_t)(qa + 1) * ustride + rr);
-                if (qa + 2 < qb) u2 = list_load(Mt, (uint32_t)(qa + 2) * ustride + rr);
-                if (qa + 3 < qb) u3 = list_load(Mt, (uint32_t)(qa + 3) * ustride + rr);
-            }
-            __syncthreads();  // the previous sub-chunk's readers of the tables are done
-            if ((int)threadIdx.x < ng) subset_sums4(xs + threadIdx.x, P, f0, f1, f2, f3);
-            // fetch the values of the next sub-chunk (of this segment or the next bitmask one)
-            {
-                int cn = c, sn = s0 + S;
-                if (sn >= cw) {
-                    cn = next_mask(c + 1);
-                    sn = 0;
-                }
-                if (cn < nseg) fetch(cn, sn);
-            }
-            __syncthreads();
-            for (int r = threadIdx.x; r < nrows; r += NT) {
-                const uint32_t rr = (uint32_t)(tl.r0 + r);
-                if (r != (int)threadIdx.x) {  // a later row of this thread
-                    u0 = list_load(Mt, (uint32_t)qa * ustride + rr);
-                    if (qa + 1 < qb) u1 = list_load(Mt, (uint32_t)(qa + 1) * ustride + rr);
-                    if (qa + 2 < qb) u2 = list_load(Mt, (uint32_t)(qa + 2) * ustride + rr);
-                    if (qa + 3 < qb) u3 = list_load(Mt, (uint32_t)(qa + 3) * ustride + rr);
-                }
-                VT acc = vzero<VT>();
-                for (int q = qa; q < qb; ++q) {
-                    // units in column order; the one four ahead replaces the one just read
-                    mask_unit(xs + 32 * (q - qa), P, u0, acc);
-                    u0 = u1;
-                    u1 = u2;
-                    u2 = u3;
-                    if (q + 4 < qb) u3 = list_load(Mt, (uint32_t)(q + 4) * ustride + rr);
-                }
-                vacc(macc[r], vscale(acc, sign));  // row r's own thread, in segment order
-            }
+        const int ncol = min(S, cw - s0);
+        // tables for every group of the units touched (a unit's bits past the segment are zero
+        // and read entry 0 of their group, which must exist and be zero); an odd pitch, and
+        // 16 P <= 16 (S/4 + 1) slots since ng <= S / 4
+        const int ng = (ncol + kMaskUnitCols - 1) / kMaskUnitCols * (kMaskUnitCols / 4);
+        const int P = ng | 1;
+        const int qa = s0 / kMaskUnitCols, qb = (s0 + ncol + kMaskUnitCols - 1) / kMaskUnitCols;
+        // unit q of row r, or (q past the sub-chunk, or r past the tile) an offset past the end of
+        // the buffer, which reads as zero without a memory access: every load is issued
+        // unconditionally, so the wave's in-order wait counts stay exact
+        auto unit = [&](int q, int r) {
+            const bool in = q < qb && r < nrows;
+            return list_load(Mt, in ? (uint32_t)q * ustride + (uint32_t)(tl.r0 + r) : kUnitPastEnd);
+        };
+        // the first four units of the thread's first row load while the tables are built
+        u32x4 u0 = unit(qa, threadIdx.x), u1 = unit(qa + 1, threadIdx.x), u2 = unit(qa + 2, threadIdx.x),
+              u3 = unit(qa + 3, threadIdx.x);
+        __syncthreads();  // the previous sub-chunk's readers of the tables are done
+        if ((int)threadIdx.x < ng) subset_sums4(xs + threadIdx.x, P, f0, f1, f2, f3);
+        // the item's next sub-chunk (of this segment or the next bitmask one), whose values are
+        // fetched now
+        int cn = c, sn = s0 + S;
+        if (sn >= cw) {
+            cn = next_mask(c + 1);
+            sn = 0;
         }
-        c = next_mask(c + 1);
+        if (k + 1 < it.nsub) fetch(cn, sn);
+        __syncthreads();
+        for (int r = threadIdx.x; r < nrows; r += NT) {
+            if (r != (int)threadIdx.x) {  // a later row of this thread
+                u0 = unit(qa, r);
+                u1 = unit(qa + 1, r);
+                u2 = unit(qa + 2, r);
+                u3 = unit(qa + 3, r);
+            }
+            VT acc = vzero<VT>();
+            // units in column order; the one four ahead loads into the registers of the one just
+            // read (unrolled by four: no register copy of a load in flight)
+            for (int q = qa; q < qb; q += 4) {
+                mask_unit(xs + 32 * (q - qa), P, u0, acc);
+                u0 = unit(q + 4, r);
+                if (q + 1 < qb) mask_unit(xs + 32 * (q + 1 - qa), P, u1, acc);
+                u1 = unit(q + 5, r);
+                if (q + 2 < qb) mask_unit(xs + 32 * (q + 2 - qa), P, u2, acc);
+                u2 = unit(q + 6, r);
+                if (q + 3 < qb) mask_unit(xs + 32 * (q + 3 - qa), P, u3, acc);
+                u3 = unit(q + 7, r);
+            }
+            vacc(macc[r], vscale(acc, sign));  // row r's own thread, in segment order
+        }
+        c = cn;
+        s0 = sn;
     }
-    VT *out = reinterpret_cast<VT *>(g.msum) + rowbase;
+    VT *out = reinterpret_cast<VT *>(g.msum) + it.out;
     for (int r = threadIdx.x; r < nrows; r += NT) out[r] = macc[r];
 }
 
 // LDS layout of a tile workgroup (bytes are computed by rows_lds_bytes):
-//   xs[W + kXsSlack] staged chunk values (slot W all zero while a list is read), or the subset-sum
-//   tables of a bitmask segment | acc[tile_rows] | red[NT/64 + 1] | bnd[tile_rows + 1]
+//   xs[W + kXsSlack] staged chunk values (slot W all zero while a list is read) | acc[tile_rows] |
+//   red[NT/64 + 1] | bnd[tile_rows + 1]
 template <typename VT, int NT>
 struct TileLds {
     VT *xs;
@@ -375,7 +376,7 @@ struct TileLds {
 // YG: the inter-block gathers read the phase y_l from y_in (half the bytes of a value pair, so
 // twice the table fits a cache) and form (sin y_l, cos y_l), which equals x_in[l] bit for bit.
 template <typename T, int NT, bool YG = false>
-__device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, const BlkInfo &bi,
+__device__ __forceinline__ void tile_gather(const DevGraph &g, int tile_id, const Tile &tl, const BlkInfo &bi,
                                             const typename V2<T>::type *__restrict__ x_in,
                                             const typename V2<T>::type *__restrict__ part_in,
                                             TileLds<typename V2<T>::type, NT> &L, const T *__restrict__ y_in = nullptr)
@@ -536,13 +537,20 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, const Tile &tl, c
         }
     }
 
-    // the rows' sums over the bitmask segments (written by k_mask before this launch), added by
-    // thread r mod NT once the list pass's leaders have finished with acc; the barriers below
-    // order them before the epilogue reads acc
+    // the rows' sums over the bitmask segments (the tile's item partial sums, written by k_mask
+    // before this launch, in segment order), added by thread r mod NT once the list pass's
+    // leaders have finished with acc; the barriers below order them before the epilogue reads acc
     if (g.msum) {  // uniform (a kernel argument)
-        __syncthreads();
-        const VT *ms = reinterpret_cast<const VT *>(g.msum) + rowbase;
-        for (int r = threadIdx.x; r < nrows; r += NT) vacc(L.acc[r], ms[r]);
+        const MaskTile mt = g.mtile[tile_id];
+        if (mt.cnt > 0) {
+            __syncthreads();
+            const VT *ms = reinterpret_cast<const VT *>(g.msum) + mt.off;
+            for (int r = threadIdx.x; r < nrows; r += NT) {
+                VT s = ms[r];
+                for (int k = 1; k < mt.cnt; ++k) vacc(s, ms[(int64_t)k * nrows + r]);
+                vacc(L.acc[r], s);
+            }
+        }
     }
 
     // edges between blocks: straightforward summation from the global table. The tile's rows
@@ -625,7 +633,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int rowbase = bi.row0 + tl.r0;
     const T2 *__restrict__ sc_in = reinterpret_cast<const T2 *>(a.sc_in);
 
-    tile_gather<T, NT, YG>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L, a.y_in);
+    tile_gather<T, NT, YG>(g, tile_id, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L, a.y_in);
 
     T2 base = vzero<T2>();
     if (bi.ngrp) base = L.red[NT / 64];
@@ -702,7 +710,7 @@ __global__ __launch_bounds__(NT) void k_rows_emb(DevGraph g, EmbArgs<T> a)
     const int rowbase = bi.row0 + tl.r0;
     const T2 *__restrict__ sc_in = reinterpret_cast<const T2 *>(a.sc_in);
 
-    tile_gather<T, NT>(g, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L);
+    tile_gather<T, NT>(g, tile_id, tl, bi, sc_in, reinterpret_cast<const T2 *>(a.part_in), L);
 
     T2 base = vzero<T2>();
     if (bi.ngrp) base = L.red[NT / 64];
@@ -784,7 +792,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int nrows = tl.r1 - tl.r0;
     const int rowbase = bi.row0 + tl.r0;
 
-    tile_gather<T, NT>(g, tl, bi, reinterpret_cast<const T2 *>(a.x_in), reinterpret_cast<const T2 *>(a.part_in), L);
+    tile_gather<T, NT>(g, tile_id, tl, bi, reinterpret_cast<const T2 *>(a.x_in), reinterpret_cast<const T2 *>(a.part_in), L);
 
     T2 base = vzero<T2>();
     if (bi.ngrp) base = L.red[NT / 64];
@@ -1037,18 +1045,19 @@ hipError_t launch_sc_init(const DevGraph &g, int ntiles, const T *y, void *sc, v
     });
 }
 
-// Bitmask segment sums of every tile into g.msum, before a tile kernel that adds them (no-op
-// for a layout without bitmask segments). x_in: the pairs that tile kernel stages. Always 256
-// threads (the row loop covers any tile height), whatever the tile kernel's workgroup size.
+// Bitmask item partial sums into g.msum, before a tile kernel that adds them (no-op for a layout
+// without bitmask segments). x_in: the pairs that tile kernel stages. Always 256 threads (the row
+// loop covers any tile height), whatever the tile kernel's workgroup size.
 template <typename T>
 hipError_t launch_mask(const DevGraph &g, const void *x_in, hipStream_t st)
 {
-    if (!g.msum || g.nlaunch <= 0) return hipSuccess;
+    if (!g.msum || g.nmitem <= 0) return hipSuccess;
     constexpr int NT = 256;
-    const size_t lds = ((size_t)(g.W + kXsSlack) + (size_t)g.tile_rows) * 2 * sizeof(T);
+    static_assert(kMaskSubMax <= 4 * NT, "one column group per thread");
+    const size_t lds = ((size_t)16 * (g.mask_sub / 4 + 1) + (size_t)g.tile_rows) * 2 * sizeof(T);
     hipError_t e = dyn_lds_attr<&k_mask<T, NT>>();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_mask<T, NT>), dim3(g.nlaunch), dim3(NT), lds, st, g,
+    hipLaunchKernelGGL((k_mask<T, NT>), dim3(g.nmitem), dim3(NT), lds, st, g,
                        reinterpret_cast<const typename V2<T>::type *>(x_in));
     return hipGetLastError();
 }

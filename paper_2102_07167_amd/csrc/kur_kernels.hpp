@@ -24,9 +24,13 @@ struct DevGraph {
     int32_t W;
     int32_t tile_rows;
     int32_t nlaunch;  // entries of order (workgroups of a tile launch); -1 entries are empty slots
-    void *msum;       // per row (block order) the sum over its bitmask segments, one (x, y) pair of
-                      // the dtype, written by k_mask before every tile-kernel launch; null when the
+    void *msum;       // the bitmask items' partial sums (see MaskItem), one (x, y) pair of the dtype
+                      // per row, written by k_mask before every tile-kernel launch; null when the
                       // layout has no bitmask segment
+    const MaskItem *mitem;  // bitmask items in launch order
+    const MaskTile *mtile;  // per tile its items' partial sums
+    int32_t nmitem;
+    int32_t mask_sub;       // columns of a bitmask sub-chunk
 };
 
 // Arguments of one row-kernel launch (one RK stage, or a plain evaluation when stage == 0).

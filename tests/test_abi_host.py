@@ -187,7 +187,8 @@ def test_validation_errors_before_device_work():
         _expect(K.KUR_EINVAL, k.set_graph_csr, 2, np.array([0, 2, 2]), np.array([1, 1]), np.zeros(2))  # dup
         _expect(K.KUR_EINVAL, k.set_graph_csr, 0, np.array([0]), np.zeros(0), np.zeros(0))
         for key, v in [("tau", -0.1), ("chunk", 100), ("chunk", 8192), ("tile_rows", 10), ("threads", 64),
-                       ("scaling", 2), ("nonsense", 1.0), ("tau", float("nan")), ("flat_min_vec", -1)]:
+                       ("scaling", 2), ("nonsense", 1.0), ("tau", float("nan")), ("flat_min_vec", -1),
+                       ("mask_sub", 192), ("mask_sub", 2048), ("mask_sub", 0), ("mask_item", 0), ("mask_item", 1.5)]:
             _expect(K.KUR_EINVAL, k.set_option, key, v)
         with host_ctx("f64") as k64:
             _expect(K.KUR_EINVAL, k64.set_option, "chunk", 4096)

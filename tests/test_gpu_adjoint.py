@@ -185,7 +185,8 @@ def asymmetric_workload(seed, weighted=False):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("opts", [dict(), dict(chunk=64, tile_rows=64, flat_min_vec=0.5, ckpt=7),
                                   dict(scaling=1, threads=256), dict(weighted=True), dict(threads=128, chunk=64),
-                                  dict(mask_min=0.0, chunk=512), dict(mask_min=0.0, chunk=512, weighted=True)])
+                                  dict(mask_min=0.0, chunk=512), dict(mask_min=0.0, chunk=512, weighted=True),
+                                  dict(mask_min=0.0, chunk=512, mask_sub=128, mask_item=5000)])
 def test_adjoint_asymmetric_with_transpose(need_gpu, dtype, opts):
     """Asymmetric A with the option "transpose": the gathers of J^T l run over the layout of A^T
     and match the oracle's discrete adjoint, which scatters the rows of A."""

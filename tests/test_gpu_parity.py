@@ -131,11 +131,16 @@ def test_sbm_fp32_trajectory_1000_steps(need_gpu, flat):
                                   dict(xcds=8, tile_min_cost=1), dict(xcds=8, tile_rows=64, chunk=128),
                                   dict(xcds=3, tile_min_cost=64),
                                   dict(mask_min=0.0, chunk=512), dict(mask_min=0.0, chunk=512, threads=256, tile_rows=64, xcds=8),
-                                  dict(mask_min=0.0, chunk=1024, threads=128), dict(mask_min=0.1, chunk=2048, flat_min_vec=0.1)])
+                                  dict(mask_min=0.0, chunk=1024, threads=128), dict(mask_min=0.1, chunk=2048, flat_min_vec=0.1),
+                                  dict(mask_min=0.0, chunk=1024, mask_sub=128, mask_item=1),
+                                  dict(mask_min=0.0, chunk=512, tile_rows=64, mask_sub=128, mask_item=20000),
+                                  dict(mask_min=0.0, chunk=2048, tile_rows=512, mask_sub=1024, mask_item=10**9)])
 def test_ragged_layouts(need_gpu, dtype, opts):
     """Odd block sizes, several chunks per block, several tiles per block, all-dense and
     all-sparse evaluation, a size-1 block and a complete block; launch orders for 8 and 3 XCDs
-    (tiles of a block on one XCD, empty slots in the launch order)."""
+    (tiles of a block on one XCD, empty slots in the launch order); bitmask segments, with
+    bitmask items of one sub-chunk, of a few sub-chunks starting and ending inside segments, and
+    of a whole tile."""
     rng = np.random.default_rng(77)
     sizes = np.array([333, 1, 129, 700, 64, 2, 515])
     rho = np.array([0.95, 0.5, 0.3, 0.75, 1.0, 1.0, 0.55])
