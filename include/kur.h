@@ -96,11 +96,11 @@ const char *kur_last_error(const kur_ctx *ctx);
  *                 list entry. Needs a chunk of at least 512 columns. The same sums in another
  *                 order. Takes effect at the next graph set. Default 2 (off).
  *   "mask_sub"    columns of one set of those tables (a multiple of 128 in [128, 1024], at most
- *                 the chunk). Default 512.
+ *                 the chunk). Default 1024.
  *   "mask_item"   the bitmask work is cut into items of consecutive tables' worth of one tile's
  *                 bitmask rows, each of at most this many cells (rows x columns; at least one
  *                 set of tables), summed by one workgroup each, largest first, into partial
- *                 sums that the tile adds in segment order (1..1e12). Default 524288. Both take
+ *                 sums that the tile adds in segment order (1..1e12). Default 32768. Both take
  *                 effect at the next graph set or re-tiling.
  *   "transpose"   1: kur_set_graph_csr / kur_set_graph_csr_w on a device context also build and
  *                 keep the layout of A^T when A is asymmetric (same block order; about the

@@ -333,7 +333,7 @@ extern "C" kur_status kur_autotune_csr(kur_ctx *c, int64_t n, const int64_t *row
     // bitmask segments (needs a chunk of at least kMaskMinW): off, or from a list density
     std::vector<double> mask_mins;
     if (best.l.chunk >= kMaskMinW) {
-        if (effort == 1) mask_mins = {0.3};
+        if (effort == 1) mask_mins = {0.2, 0.3};
         if (effort >= 2) mask_mins = {0.2, 0.3, 0.4};
         if (best.l.mask_min <= 1.0) mask_mins.push_back(2.0);
     }

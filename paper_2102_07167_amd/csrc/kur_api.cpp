@@ -73,7 +73,7 @@ struct kur_ctx {
     DevBuf d_blk, d_segd, d_grp, d_tiles, d_order, d_seg, d_list, d_iptr, d_icol, d_mask;
     DevBuf d_msum;              // bitmask item partial sums (k_mask), when a layout has any
     DevBuf d_mitem, d_mtile, d_mitemT, d_mtileT;  // bitmask items and per-tile item runs (A, A^T)
-    int32_t nmitem = 0, nmitemT = 0, mask_sub = 512, mask_subT = 512;
+    int32_t nmitem = 0, nmitemT = 0, mask_sub = 1024, mask_subT = 1024;
     bool masks = false, masksT = false;  // the layout (of A, of A^T) has bitmask segments
     // layout of A^T for the adjoint of an asymmetric A (option "transpose")
     int transpose = 0;

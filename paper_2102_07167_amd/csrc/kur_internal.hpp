@@ -105,9 +105,9 @@ struct BuildOptions {
     int32_t pair_min = 32;      // least rows and columns of such a block
     double mask_min = 2.0;      // a segment holding at least this many list entries per cell is
                                 // stored as a bitmask (needs W >= kMaskMinW); above 1: never
-    int32_t mask_sub = 512;     // columns of a bitmask sub-chunk (a multiple of kMaskUnitCols,
+    int32_t mask_sub = 1024;    // columns of a bitmask sub-chunk (a multiple of kMaskUnitCols,
                                 // at most kMaskSubMax)
-    int64_t mask_item = 1 << 19;  // cells (rows x columns) of a bitmask work item, at most (an
+    int64_t mask_item = 1 << 15;  // cells (rows x columns) of a bitmask work item, at most (an
                                   // item holds at least one sub-chunk)
 };
 
@@ -131,8 +131,8 @@ struct BlockGraph {
     std::vector<int32_t> inter_col;   // block-order columns
     std::vector<Tile> tiles;
     std::vector<int32_t> order;       // launch order of tiles; -1 marks an empty slot (see order_tiles)
-    int32_t mask_sub = 512;           // columns of a bitmask sub-chunk (see MaskItem)
-    int64_t mask_item = 1 << 19;      // most cells of a bitmask item beyond its first sub-chunk
+    int32_t mask_sub = 1024;          // columns of a bitmask sub-chunk (see MaskItem)
+    int64_t mask_item = 1 << 15;      // most cells of a bitmask item beyond its first sub-chunk
     std::vector<MaskItem> mitems;     // bitmask items in launch order (largest first)
     std::vector<MaskTile> mtiles;     // per tile its items' partial sums (empty without bitmasks)
     int64_t mask_part_rows = 0;       // rows of the item buffer
