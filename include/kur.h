@@ -96,7 +96,7 @@ const char *kur_last_error(const kur_ctx *ctx);
  *                 list entry. Needs a chunk of at least 512 columns. The same sums in another
  *                 order. Takes effect at the next graph set. Default 2 (off).
  *   "mask_sub"    columns of one set of those tables (a multiple of 128 in [128, 1024], at most
- *                 the chunk). Default 1024.
+ *                 the chunk; in FP64 at most 512). Default 1024.
  *   "mask_item"   the bitmask work is cut into items of consecutive tables' worth of one tile's
  *                 bitmask rows, each of at most this many cells (rows x columns; at least one
  *                 set of tables), summed by one workgroup each, largest first, into partial

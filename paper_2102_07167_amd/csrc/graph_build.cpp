@@ -357,10 +357,13 @@ std::string to_masks(BlockGraph &g, const BuildOptions &opt)
 
 namespace {
 
-// The bitmask sub-chunk width (the option, at most the chunk, in whole units) and item size.
+// The bitmask sub-chunk width (the option, at most the chunk, in whole units; for 16-byte value
+// pairs at most 4 units, so that a table read's constant offset stays below 64 KiB) and item
+// size.
 void mask_params(BlockGraph &g, const BuildOptions &opt)
 {
-    g.mask_sub = std::max(kMaskUnitCols, std::min(opt.mask_sub, g.W) / kMaskUnitCols * kMaskUnitCols);
+    const int32_t cap = g.esz2 > 8 ? kMaskSubMax / 2 : kMaskSubMax;
+    g.mask_sub = std::max(kMaskUnitCols, std::min({opt.mask_sub, g.W, cap}) / kMaskUnitCols * kMaskUnitCols);
     g.mask_item = opt.mask_item;
 }
 

@@ -214,23 +214,37 @@ __device__ __forceinline__ void subset_sums4(VT *t, int P, const VT x0, const VT
     t[15 * P] = add(v14, x0);
 }
 
-// Add to acc the row sums of one 128-column bitmask unit: per nibble (4 columns, in column
-// order) one read of the subset-sum table of that column group. tb points at the unit's first
-// group; entry m of group j sits at tb[m * P + j]. With an odd pitch, the lanes of a wave (rows,
-// all at the same group) read distinct banks for distinct entries. The address is formed in bytes
-// as one 24-bit multiply-add (m < 16, P < 2^16); the group offset is a constant of the read.
-template <typename VT>
-__device__ __forceinline__ void mask_unit(const VT *tb, int P, const u32x4 u, VT &acc)
+// Pitch of the subset-sum tables of a bitmask sub-chunk: entry m of column group j at
+// xs[j * kTabPitch + m]. The lanes of a wave (rows, all at the same group) read distinct
+// consecutive entries (distinct banks); the threads that build consecutive groups write at a
+// pitch of 17 entries, which spreads them over the banks.
+constexpr int kTabPitch = 17;
+
+// Add to acc the row sums of one 128-column bitmask unit, unit SLOT of the sub-chunk: per nibble
+// (4 columns, in column order) one read of the subset-sum table of that column group. The
+// nibbles of a word are taken times the entry bytes from two masked copies of it (even and odd
+// nibbles, one per byte), so that a table read costs one byte extraction; the group's offset
+// is a constant of the read.
+template <int SLOT, typename VT>
+__device__ __forceinline__ void mask_unit(const VT *xs, const u32x4 u, VT &acc)
 {
+    constexpr int SH = sizeof(VT) == 8 ? 3 : 4;  // log2 of the entry bytes
+    constexpr uint32_t M = 0x0F0F0F0Fu << SH;
     const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-    const uint32_t pb = (uint32_t)P * (uint32_t)sizeof(VT);  // bytes between entries of a group
-    const char *base = reinterpret_cast<const char *>(tb);
+    const char *base = reinterpret_cast<const char *>(xs);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
+        uint32_t we = (w[k] << SH) & M;        // nibbles 0, 2, 4, 6 of the word
+        uint32_t wo = (w[k] >> (4 - SH)) & M;  // nibbles 1, 3, 5, 7
+        // opaque to the compiler, which would otherwise shift and mask every nibble of the word
+        asm volatile("" : "+v"(we), "+v"(wo));
 #pragma unroll
-        for (int n = 0; n < 8; ++n) {
-            const uint32_t m = (w[k] >> (4 * n)) & 15u;
-            vacc(acc, *reinterpret_cast<const VT *>(base + __umul24(m, pb) + (8 * k + n) * sizeof(VT)));
+        for (int b = 0; b < 4; ++b) {
+            constexpr int G0 = SLOT * (kMaskUnitCols / 4);
+            const int j = G0 + 8 * k + 2 * b;  // group of nibble 2b of word k
+            const uint32_t e = (we >> (8 * b)) & 0xFFu, o = (wo >> (8 * b)) & 0xFFu;
+            vacc(acc, *reinterpret_cast<const VT *>(base + e + (size_t)j * kTabPitch * sizeof(VT)));
+            vacc(acc, *reinterpret_cast<const VT *>(base + o + (size_t)(j + 1) * kTabPitch * sizeof(VT)));
         }
         // an empty statement that no memory access may cross, after every word (measured with it)
         asm volatile("" ::: "memory");
@@ -252,10 +266,14 @@ __global__ __launch_bounds__(NT) void k_mask(
     DevGraph g, const typename V2<T>::type *__restrict__ x_in)
 {
     using VT = typename V2<T>::type;
+    // columns per sub-chunk: a multiple of the unit, at most kMaskSubMax <= 4 NT (one column group
+    // per thread, at most 8 units; 4 for 16-byte pairs)
+    const int S = g.mask_sub;
+    // the tables at a fixed LDS address (a table read's offset is then a constant of the read)
+    constexpr int kGroups = (sizeof(VT) == 8 ? kMaskSubMax : kMaskSubMax / 2) / 4;
+    __shared__ VT xs[kTabPitch * kGroups];
     extern __shared__ __align__(16) unsigned char smem[];
-    const int S = g.mask_sub;  // a multiple of the unit, at most 4 NT (one column group per thread)
-    VT *xs = reinterpret_cast<VT *>(smem);  // 16 (S/4 + 1) table slots
-    VT *macc = xs + 16 * (S / 4 + 1);       // tile rows partial sums
+    VT *macc = reinterpret_cast<VT *>(smem);  // tile rows partial sums
     const MaskItem it = g.mitem[blockIdx.x];
     const Tile tl = g.tiles[it.tile];
     const BlkInfo bi = g.blk[tl.block];
@@ -295,11 +313,10 @@ __global__ __launch_bounds__(NT) void k_mask(
         const __amdgpu_buffer_rsrc_t Mt = uniform_rsrc(g.mask + 4 * sd.mbase, (int64_t)bi.size * nq * 16);
         const int ncol = min(S, cw - s0);
         // tables for every group of the units touched (a unit's bits past the segment are zero
-        // and read entry 0 of their group, which must exist and be zero); an odd pitch, and
-        // 16 P <= 16 (S/4 + 1) slots since ng <= S / 4
+        // and read entry 0 of their group, which must exist and be zero)
         const int ng = (ncol + kMaskUnitCols - 1) / kMaskUnitCols * (kMaskUnitCols / 4);
-        const int P = ng | 1;
         const int qa = s0 / kMaskUnitCols, qb = (s0 + ncol + kMaskUnitCols - 1) / kMaskUnitCols;
+        const int nqs = qb - qa;  // 1 .. 8
         // unit q of row r, or (q past the sub-chunk, or r past the tile) an offset past the end of
         // the buffer, which reads as zero without a memory access: every load is issued
         // unconditionally, so the wave's in-order wait counts stay exact
@@ -311,7 +328,7 @@ __global__ __launch_bounds__(NT) void k_mask(
         u32x4 u0 = unit(qa, threadIdx.x), u1 = unit(qa + 1, threadIdx.x), u2 = unit(qa + 2, threadIdx.x),
               u3 = unit(qa + 3, threadIdx.x);
         __syncthreads();  // the previous sub-chunk's readers of the tables are done
-        if ((int)threadIdx.x < ng) subset_sums4(xs + threadIdx.x, P, f0, f1, f2, f3);
+        if ((int)threadIdx.x < ng) subset_sums4(xs + kTabPitch * threadIdx.x, 1, f0, f1, f2, f3);
         // the item's next sub-chunk (of this segment or the next bitmask one), whose values are
         // fetched now
         int cn = c, sn = s0 + S;
@@ -321,26 +338,26 @@ __global__ __launch_bounds__(NT) void k_mask(
         }
         if (k + 1 < it.nsub) fetch(cn, sn);
         __syncthreads();
+        // units in column order, four in flight: units 4..7 load into the registers of units
+        // 0..3 once read, then units 0..3 of the thread's next row
         for (int r = threadIdx.x; r < nrows; r += NT) {
-            if (r != (int)threadIdx.x) {  // a later row of this thread
-                u0 = unit(qa, r);
-                u1 = unit(qa + 1, r);
-                u2 = unit(qa + 2, r);
-                u3 = unit(qa + 3, r);
-            }
             VT acc = vzero<VT>();
-            // units in column order; the one four ahead loads into the registers of the one just
-            // read (unrolled by four: no register copy of a load in flight)
-            for (int q = qa; q < qb; q += 4) {
-                mask_unit(xs + 32 * (q - qa), P, u0, acc);
-                u0 = unit(q + 4, r);
-                if (q + 1 < qb) mask_unit(xs + 32 * (q + 1 - qa), P, u1, acc);
-                u1 = unit(q + 5, r);
-                if (q + 2 < qb) mask_unit(xs + 32 * (q + 2 - qa), P, u2, acc);
-                u2 = unit(q + 6, r);
-                if (q + 3 < qb) mask_unit(xs + 32 * (q + 3 - qa), P, u3, acc);
-                u3 = unit(q + 7, r);
-            }
+            mask_unit<0>(xs, u0, acc);
+            u0 = unit(qa + 4, r);
+            if (nqs > 1) mask_unit<1>(xs, u1, acc);
+            u1 = unit(qa + 5, r);
+            if (nqs > 2) mask_unit<2>(xs, u2, acc);
+            u2 = unit(qa + 6, r);
+            if (nqs > 3) mask_unit<3>(xs, u3, acc);
+            u3 = unit(qa + 7, r);
+            if (nqs > 4) mask_unit<4>(xs, u0, acc);
+            u0 = unit(qa, r + NT);
+            if (nqs > 5) mask_unit<5>(xs, u1, acc);
+            u1 = unit(qa + 1, r + NT);
+            if (nqs > 6) mask_unit<6>(xs, u2, acc);
+            u2 = unit(qa + 2, r + NT);
+            if (nqs > 7) mask_unit<7>(xs, u3, acc);
+            u3 = unit(qa + 3, r + NT);
             vacc(macc[r], vscale(acc, sign));  // row r's own thread, in segment order
         }
         c = cn;
@@ -1023,12 +1040,13 @@ hipError_t with_nt(int threads, F &&f)
 // dynamic LDS limit requested for the tile kernels (the rest of the 160 KiB stays for static use)
 constexpr int kMaxDynLds = 156 * 1024;
 
-// Raise the dynamic LDS limit of the tile kernel Fn, once per process (one static per kernel).
-template <auto Fn>
+// Raise the dynamic LDS limit of the kernel Fn to Limit bytes (its static LDS plus Limit must fit
+// the LDS of a workgroup), once per process (one static per kernel).
+template <auto Fn, int Limit = kMaxDynLds>
 hipError_t dyn_lds_attr()
 {
     static const hipError_t e =
-        hipFuncSetAttribute(reinterpret_cast<const void *>(Fn), hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+        hipFuncSetAttribute(reinterpret_cast<const void *>(Fn), hipFuncAttributeMaxDynamicSharedMemorySize, Limit);
     return e;
 }
 
@@ -1053,9 +1071,14 @@ hipError_t launch_mask(const DevGraph &g, const void *x_in, hipStream_t st)
 {
     if (!g.msum || g.nmitem <= 0) return hipSuccess;
     constexpr int NT = 256;
-    static_assert(kMaskSubMax <= 4 * NT, "one column group per thread");
-    const size_t lds = ((size_t)16 * (g.mask_sub / 4 + 1) + (size_t)g.tile_rows) * 2 * sizeof(T);
-    hipError_t e = dyn_lds_attr<&k_mask<T, NT>>();
+    static_assert(kMaskSubMax <= 4 * NT && kMaskSubMax <= 8 * kMaskUnitCols, "one column group per thread, 8 units");
+    if (g.mask_sub < kMaskUnitCols || g.mask_sub > (sizeof(T) == 4 ? kMaskSubMax : kMaskSubMax / 2) ||
+        g.mask_sub % kMaskUnitCols)
+        return hipErrorInvalidValue;
+    // the rows' sums beyond the tables' static LDS: at most 4096 rows of 16 bytes
+    const size_t lds = (size_t)g.tile_rows * 2 * sizeof(T);
+    if (lds > 65536) return hipErrorInvalidValue;
+    hipError_t e = dyn_lds_attr<&k_mask<T, NT>, 65536>();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_mask<T, NT>), dim3(g.nmitem), dim3(NT), lds, st, g,
                        reinterpret_cast<const typename V2<T>::type *>(x_in));
