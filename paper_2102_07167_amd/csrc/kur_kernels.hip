@@ -536,20 +536,31 @@ __device__ __forceinline__ void tile_gather(const DevGraph &g, int tile_id, cons
                 }
             }
         } else {
-            for (int r = grp; r < nrows; r += ngrp) {
-                const int v0 = L.bnd[r];
+            // G lanes per row; the group's first two vectors of its next row load while it sums
+            // the current one. Loads past the row are not gathered (past the tile's vectors they
+            // read zero without a memory access).
+            int r = grp;
+            int v0 = r < nrows ? L.bnd[r] : 0;
+            u32x4 qa = list_load(Lt, (uint32_t)(v0 + lane)), qb = list_load(Lt, (uint32_t)(v0 + lane + G));
+            for (; r < nrows; r += ngrp) {
                 const int nv = L.bnd[r + 1] - v0;
+                const int rn = r + ngrp;
+                const int v0n = rn < nrows ? L.bnd[rn] : v0 + nv;
+                const u32x4 na = list_load(Lt, (uint32_t)(v0n + lane)), nb = list_load(Lt, (uint32_t)(v0n + lane + G));
                 VT acc = vzero<VT>();
-                int v = lane;
-                for (; v + G < nv; v += 2 * G) {
-                    const u32x4 qa = list_load(Lt, (uint32_t)(v0 + v));
-                    const u32x4 qb = list_load(Lt, (uint32_t)(v0 + v + G));
-                    gather8(L.xs, qa, acc);
-                    gather8(L.xs, qb, acc);
+                if (lane < nv) gather8(L.xs, qa, acc);
+                if (lane + G < nv) gather8(L.xs, qb, acc);
+                for (int v = lane + 2 * G; v < nv; v += 2 * G) {  // rows longer than 2 G vectors
+                    const u32x4 ra = list_load(Lt, (uint32_t)(v0 + v));
+                    const u32x4 rb2 = list_load(Lt, (uint32_t)(v0 + v + G));
+                    gather8(L.xs, ra, acc);
+                    if (v + G < nv) gather8(L.xs, rb2, acc);
                 }
-                if (v < nv) gather8(L.xs, list_load(Lt, (uint32_t)(v0 + v)), acc);
                 acc = vgroup_sum_dpp(acc, G);
                 if (lane == G - 1) vacc(L.acc[r], vscale(acc, sign));
+                qa = na;
+                qb = nb;
+                v0 = v0n;
             }
         }
     }
