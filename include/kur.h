@@ -251,6 +251,14 @@ kur_status kur_graph_info(const kur_ctx *ctx, int64_t out[10]);
  * bitmasks, out[1] = their bytes. KUR_ESTATE without a graph. */
 kur_status kur_graph_masks(const kur_ctx *ctx, int64_t out[2]);
 
+/* Bitmask work items of a host-only context's layout (options "mask_sub" and "mask_item"):
+ * *count receives their number. If items is not NULL it receives 9 values per item, in launch
+ * order: tile, block, first segment (block-local index), first sub-chunk of that segment,
+ * sub-chunks, tile rows, 128-column units per row, cells (rows x columns) and the first row of
+ * its partial sums in the item buffer. Caller-owned, 9 * count entries. KUR_ESTATE without a
+ * graph or on a device context. For the tests of the item cut. */
+kur_status kur_graph_mask_items(const kur_ctx *ctx, int64_t *count, int64_t *items);
+
 /* Permutation in use: perm[u] = block-order index of user node u (n entries). */
 kur_status kur_get_perm(const kur_ctx *ctx, int32_t *perm);
 

@@ -944,6 +944,48 @@ kur_status kur_graph_masks(const kur_ctx *c, int64_t out[2])
     return KUR_OK;
 }
 
+kur_status kur_graph_mask_items(const kur_ctx *c, int64_t *count, int64_t *items)
+{
+    if (!c || !count) return KUR_EINVAL;
+    if (!c->has_graph || !c->host_only) return KUR_ESTATE;
+    const BlockGraph &g = c->host_graph;
+    *count = (int64_t)g.mitems.size();
+    if (!items) return KUR_OK;
+    const int64_t S = g.mask_sub;
+    for (size_t i = 0; i < g.mitems.size(); ++i) {
+        const MaskItem &it = g.mitems[i];
+        const Tile &tl = g.tiles[it.tile];
+        const BlkInfo &b = g.blk[tl.block];
+        const int64_t h = tl.r1 - tl.r0;
+        // the item's sub-chunks, in the order the kernel visits them
+        int64_t units = 0, cells = 0;
+        int32_t ch = it.seg;
+        int64_t s0 = (int64_t)it.sub * S;
+        for (int32_t k = 0; k < it.nsub && ch < b.nchunk; ++k) {
+            const int64_t w = std::min<int64_t>(S, g.segd[b.sd0 + ch].cw - s0);
+            units += (w + kMaskUnitCols - 1) / kMaskUnitCols;
+            cells += h * w;
+            s0 += S;
+            if (s0 >= g.segd[b.sd0 + ch].cw) {
+                s0 = 0;
+                do ++ch;
+                while (ch < b.nchunk && !g.segd[b.sd0 + ch].mask);
+            }
+        }
+        int64_t *o = items + 9 * i;
+        o[0] = it.tile;
+        o[1] = tl.block;
+        o[2] = it.seg;
+        o[3] = it.sub;
+        o[4] = it.nsub;
+        o[5] = h;
+        o[6] = units;
+        o[7] = cells;
+        o[8] = it.out;
+    }
+    return KUR_OK;
+}
+
 kur_status kur_get_perm(const kur_ctx *c, int32_t *perm)
 {
     if (!c || !perm) return KUR_EINVAL;

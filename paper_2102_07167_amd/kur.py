@@ -41,6 +41,7 @@ SIGNATURES = {
     "kur_graph_pairs": (ST, [P, P]),
     "kur_graph_info": (ST, [P, P]),
     "kur_graph_masks": (ST, [P, P]),
+    "kur_graph_mask_items": (ST, [P, P, P]),
     "kur_get_perm": (ST, [P, P]),
     "kur_get_blocks": (ST, [P, P, P]),
     "kur_get_row_lists": (ST, [P, I64, P, P, P, P]),
@@ -227,6 +228,16 @@ class Kuramoto:
         out = np.zeros(2, dtype=np.int64)
         self._chk(self._L.kur_graph_masks(self._h, _ptr(out)))
         return {"mask_segments": int(out[0]), "mask_bytes": int(out[1])}
+
+    def graph_mask_items(self) -> np.ndarray:
+        """Bitmask work items of a host-only context's layout, one row per item in launch order:
+        tile, block, segment, first sub-chunk, sub-chunks, rows, units per row, cells, first
+        partial-sum row."""
+        cnt = I64(0)
+        self._chk(self._L.kur_graph_mask_items(self._h, ctypes.byref(cnt), None))
+        out = np.zeros((max(cnt.value, 1), 9), dtype=np.int64)
+        self._chk(self._L.kur_graph_mask_items(self._h, ctypes.byref(cnt), _ptr(out)))
+        return out[: cnt.value]
 
     def graph_pairs(self) -> int:
         """Number of dense off-diagonal blocks of the installed graph."""

@@ -517,3 +517,39 @@ def test_mask_segments_in_batch():
                 _same_rows(k1, k, g.n, off)
             off += g.n
         assert total["mask_segments"] == segs > 0
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(mask_sub=128, mask_item=1), dict(mask_sub=256, mask_item=20000),
+                                  dict(mask_sub=1024, mask_item=10**9, tile_rows=512, chunk=1024)])
+def test_mask_items_cover_every_bitmask_unit(opts):
+    """The bitmask work items (one workgroup each) hold every 128-column unit of every row of
+    every bitmask segment exactly once: rows x units x 16 bytes summed over the items equals the
+    layout's bitmask bytes. An item of more than one sub-chunk stays within mask_item cells;
+    items launch largest first; their partial-sum rows are disjoint runs of their tile's rows
+    covering the item buffer; a tile's items follow its segments in order."""
+    rng = np.random.default_rng(81)
+    sizes = np.array([700, 1, 64, 1300, 7, 530])
+    rho = np.array([0.9, 0.5, 0.3, 0.6, 1.0, 0.97])
+    g = gen.sbm(sizes, rho, 0.004, key=777, uperm=rng.permutation(sizes.sum()).astype(np.int32))
+    base = dict(chunk=512, tile_rows=64, mask_min=0.0)
+    base.update(opts)
+    with host_ctx(**base) as k:
+        k.set_graph(g)
+        ms = k.graph_masks()
+        it = k.graph_mask_items()
+    assert ms["mask_segments"] > 0 and len(it) > 0
+    tile, block, seg, sub, nsub, rows, units, cells, out = it.T
+    assert np.all(nsub >= 1) and np.all(rows >= 1)
+    assert int(np.sum(rows * units)) * 16 == ms["mask_bytes"]
+    budget = opts.get("mask_item", 32768)
+    assert np.all((nsub == 1) | (cells <= budget))
+    assert np.all(np.diff(cells) <= 0)
+    o = np.argsort(out, kind="stable")
+    assert out[o][0] == 0 and np.array_equal(out[o][1:], (out + rows)[o][:-1])
+    for t in np.unique(tile):
+        m = np.flatnonzero(tile == t)
+        m = m[np.argsort(out[m])]
+        assert len(set(block[m])) == 1 and len(set(rows[m])) == 1
+        assert list(zip(seg[m], sub[m])) == sorted(zip(seg[m], sub[m]))
+    with host_ctx() as k:
+        _expect(K.KUR_ESTATE, k.graph_mask_items)
