@@ -324,9 +324,10 @@ __global__ __launch_bounds__(NT) void k_mask(
             const bool in = q < qb && r < nrows;
             return list_load(Mt, in ? (uint32_t)q * ustride + (uint32_t)(tl.r0 + r) : kUnitPastEnd);
         };
-        // the first four units of the thread's first row load while the tables are built
+        // every unit of the thread's first row loads while the tables are built
         u32x4 u0 = unit(qa, threadIdx.x), u1 = unit(qa + 1, threadIdx.x), u2 = unit(qa + 2, threadIdx.x),
-              u3 = unit(qa + 3, threadIdx.x);
+              u3 = unit(qa + 3, threadIdx.x), u4 = unit(qa + 4, threadIdx.x), u5 = unit(qa + 5, threadIdx.x),
+              u6 = unit(qa + 6, threadIdx.x), u7 = unit(qa + 7, threadIdx.x);
         __syncthreads();  // the previous sub-chunk's readers of the tables are done
         if ((int)threadIdx.x < ng) subset_sums4(xs + kTabPitch * threadIdx.x, 1, f0, f1, f2, f3);
         // the item's next sub-chunk (of this segment or the next bitmask one), whose values are
@@ -338,26 +339,26 @@ __global__ __launch_bounds__(NT) void k_mask(
         }
         if (k + 1 < it.nsub) fetch(cn, sn);
         __syncthreads();
-        // units in column order, four in flight: units 4..7 load into the registers of units
-        // 0..3 once read, then units 0..3 of the thread's next row
+        // units in column order, the sub-chunk's eight in flight: once read, each unit's registers
+        // receive the same unit of the thread's next row
         for (int r = threadIdx.x; r < nrows; r += NT) {
             VT acc = vzero<VT>();
             mask_unit<0>(xs, u0, acc);
-            u0 = unit(qa + 4, r);
-            if (nqs > 1) mask_unit<1>(xs, u1, acc);
-            u1 = unit(qa + 5, r);
-            if (nqs > 2) mask_unit<2>(xs, u2, acc);
-            u2 = unit(qa + 6, r);
-            if (nqs > 3) mask_unit<3>(xs, u3, acc);
-            u3 = unit(qa + 7, r);
-            if (nqs > 4) mask_unit<4>(xs, u0, acc);
             u0 = unit(qa, r + NT);
-            if (nqs > 5) mask_unit<5>(xs, u1, acc);
+            if (nqs > 1) mask_unit<1>(xs, u1, acc);
             u1 = unit(qa + 1, r + NT);
-            if (nqs > 6) mask_unit<6>(xs, u2, acc);
+            if (nqs > 2) mask_unit<2>(xs, u2, acc);
             u2 = unit(qa + 2, r + NT);
-            if (nqs > 7) mask_unit<7>(xs, u3, acc);
+            if (nqs > 3) mask_unit<3>(xs, u3, acc);
             u3 = unit(qa + 3, r + NT);
+            if (nqs > 4) mask_unit<4>(xs, u4, acc);
+            u4 = unit(qa + 4, r + NT);
+            if (nqs > 5) mask_unit<5>(xs, u5, acc);
+            u5 = unit(qa + 5, r + NT);
+            if (nqs > 6) mask_unit<6>(xs, u6, acc);
+            u6 = unit(qa + 6, r + NT);
+            if (nqs > 7) mask_unit<7>(xs, u7, acc);
+            u7 = unit(qa + 7, r + NT);
             vacc(macc[r], vscale(acc, sign));  // row r's own thread, in segment order
         }
         c = cn;
