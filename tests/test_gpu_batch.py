@@ -62,13 +62,19 @@ def test_batch_matches_oracle_per_instance(need_gpu, dtype, graph):
         assert np.abs(r[:, i] - ro).max() < tol, i
 
 
-def test_graph_replay_is_bitwise_equal_to_plain_launches(need_gpu):
+@pytest.mark.parametrize("masks", [False, True])
+def test_graph_replay_is_bitwise_equal_to_plain_launches(need_gpu, masks):
     """Regression: a cached step graph once kept the order-parameter buffers of an earlier call
-    after they had been reallocated for more samples."""
+    after they had been reallocated for more samples. With bitmask segments the captured graph
+    also holds the bitmask kernel's launches before every tile-kernel launch."""
     w = gen.sbm_equal(n_comm=8, comm_size=300, rho_in=0.9, p_out=0.01, steps=10, seed=9)
     out = {}
     for graph in (0, 1):
         with Kuramoto("f32", device=0) as k:
+            if masks:
+                k.set_option("mask_min", 0.0)
+                k.set_option("chunk", 512)
+                k.set_option("mask_sub", 128)
             k.set_option("graph", graph)
             k.set_option("graph_steps", 4)
             k.set_graph(w.graph)
@@ -82,6 +88,8 @@ def test_graph_replay_is_bitwise_equal_to_plain_launches(need_gpu):
                 r, _ = k.step_rk4(w.dt, nsteps, r_every=r_every)
                 rs.append(r)
                 rs.append(np.array([k.order_parameter()[0]]))
+            if masks:
+                assert k.graph_masks()["mask_segments"] > 0
             out[graph] = (k.get_state(), rs)
     assert out[0][0] == out[1][0]
     for a, b in zip(out[0][1], out[1][1]):

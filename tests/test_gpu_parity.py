@@ -212,16 +212,19 @@ def test_empty_graph_and_single_node(need_gpu):
         assert abs(r - 1.0) < 1e-6
 
 
-def test_state_roundtrip_bitwise_and_determinism(need_gpu):
+@pytest.mark.parametrize("opts", [dict(), dict(mask_min=0.0, chunk=512, mask_sub=128, mask_item=20000)])
+def test_state_roundtrip_bitwise_and_determinism(need_gpu, opts):
+    """A run resumed from a saved state repeats an uninterrupted run bit for bit (lists only,
+    and with bitmask segments summed in items of a few sub-chunks)."""
     w = small_sbm(n_comm=4, comm_size=300, steps=40)
     for dtype in ("f32", "f64"):
-        with make(w, dtype) as k1:
+        with make(w, dtype, **opts) as k1:
             k1.step_rk4(w.dt, 40)
             a = k1.get_state()
-        with make(w, dtype) as k2:
+        with make(w, dtype, **opts) as k2:
             k2.step_rk4(w.dt, 20)
             blob = k2.get_state()
-        with make(w, dtype) as k3:
+        with make(w, dtype, **opts) as k3:
             k3.set_state(blob)
             k3.step_rk4(w.dt, 20)
             b = k3.get_state()
