@@ -22,10 +22,17 @@ def wrap(x):
     return np.remainder(x + np.pi, TWO_PI) - np.pi
 
 
-def test_tune_tiles_keeps_state_and_parity(need_gpu):
+@pytest.mark.parametrize("opts", [dict(), dict(mask_min=0.0, chunk=512, mask_sub=128, mask_item=20000)])
+def test_tune_tiles_keeps_state_and_parity(need_gpu, opts):
+    """Re-tiling (which also re-cuts the bitmask items of a layout with bitmask segments) keeps
+    the state bit for bit, and the RHS, the trajectory and the adjoint stay within parity."""
     w = ragged_sbm(13)
     with Kuramoto("f64", device=0) as k:
+        for key, v in opts.items():
+            k.set_option(key, v)
         k.set_graph(w.graph)
+        if opts:
+            assert k.graph_masks()["mask_segments"] > 0
         k.set_params(w.omega, w.K)
         k.set_phases(w.theta0)
         k.step_rk4(w.dt, 5)
